@@ -1,0 +1,29 @@
+"""FP64 CPU oracle for the CppFlow refinement path (arXiv 2309.09102).
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
+benchmark's CPU-baseline leg may import this package.  It shares no code with
+the HIP path and imports nothing from it.
+
+The arithmetic lives in ``cpf_oracle.c`` (plain C, IEEE double,
+``-ffp-contract=off``); this module builds it with gcc and wraps it with
+ctypes.  Robots are duck-typed objects with float64 arrays ``a, d, alpha,
+theta_off, q_lo, q_hi``.
+
+Parity status per function (what pins it, in tests/test_oracle_pins.py):
+  fk / jacobian   closed forms at q = 0, single-axis and planar chains;
+                  orthonormality; central finite differences
+  log_so3         Exp(Log R) = R, known angles, branch continuity
+  cost / gradient central finite differences of the cost
+  dp              brute-force enumeration on tiny K, T; special cases
+  btd_solve       dense numpy solve; DCT closed form of the smoothness system
+  lm_step         push-through identity for T = 1; block-diagonal w_s = 0 case
+  lm              monotone cost, rejected steps keep xi, fixed point, pose
+                  convergence with w_s -> 0.  The exact iterate path (the
+                  sequence of accept / reject decisions) is parity unpinned:
+                  the paper prints no worked example of it.
+"""
+from .oracle import (build, lib_path, fk, log_so3, cost, dp, mjac, btd_solve,
+                     lm_step, lm, plan, pose_compare, DEFAULT_LM)
+
+__all__ = ["build", "lib_path", "fk", "log_so3", "cost", "dp", "mjac",
+           "btd_solve", "lm_step", "lm", "plan", "pose_compare", "DEFAULT_LM"]

@@ -1,0 +1,623 @@
+/*
+ * cpf_oracle.c -- plain, slow, FP64 CPU oracle for the CppFlow refinement
+ * path (arXiv 2309.09102).  TEST INFRASTRUCTURE ONLY: the product path never
+ * calls, links or includes this file; only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg do.
+ *
+ * Everything is IEEE double, built with -O2 -ffp-contract=off (no fused
+ * multiply-add, no fast-math) so every operation rounds exactly as written.
+ * The notation follows the paper with the build's names: T waypoints, n
+ * joints, K candidate plans per waypoint.
+ *
+ * Contents and the passages they follow:
+ *   or_fk          forward kinematics FK(q) : R^n -> SE(3)          Sec. II
+ *                  (standard distal Denavit-Hartenberg chain)
+ *                  and the geometric (kinematic) Jacobian J_fk      Sec. III-C
+ *   or_log_so3     rotation vector of a rotation matrix; its norm is the
+ *                  geodesic rotation error used as the validity metric Sec. II
+ *   or_cost        pose residual + differencing residual, squared   Sec. III-C,
+ *                  and weighted                                      Fig. (residual)
+ *   or_dp          layered-graph search minimising the maximum joint angle
+ *                  change (mjac) with the joint-limit penalty        Sec. III-B
+ *   or_btd_solve   the LM normal equations (J^T J + lambda I) step   Sec. III-C
+ *                  for the block-tridiagonal system that the pose and
+ *                  differencing residuals give (their Jacobians are
+ *                  per-waypoint blocks and +-I)
+ *   or_lm          Levenberg-Marquardt with clamping to joint limits Sec. III-C
+ *   or_plan        search, then LM from the searched seed            Sec. III
+ *
+ * Readings where the paper is silent or garbled (each listed with its reason
+ * in the design notes):
+ *   - rotation residual = Log(R(q) R*^T) (world frame) rather than a roll /
+ *     pitch / yaw difference; its norm is the paper's geodesic error;
+ *   - LM step (J^T W J + lambda I) delta = -J^T W r (transpose and sign of the
+ *     printed update restored), pure Levenberg damping lambda*I;
+ *   - weights multiply squared norms: C = w_p/2 sum|r_t|^2 + w_s/2 sum|dq|^2;
+ *   - lambda schedule: Nielsen's gain-ratio rule (H.B. Nielsen, IMM-REP-1999-05;
+ *     Madsen, Nielsen & Tingleff 2004, Sec. 3.2);
+ *   - penalties enter the search on the edge into the penalised node; ties
+ *     are broken by the key (value, edge change, predecessor index).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_MAXN 16
+#define OR_PI 3.14159265358979323846
+
+/* ------------------------------------------------------------------------ */
+/* Small dense helpers (row-major)                                           */
+/* ------------------------------------------------------------------------ */
+
+/* 4x4 homogeneous transform as a 3x4 row-major block [R | p]. */
+static void tf_identity(double M[12]) {
+    memset(M, 0, 12 * sizeof(double));
+    M[0] = 1.0; M[5] = 1.0; M[10] = 1.0;
+}
+
+/* Standard DH link transform Rz(theta) Tz(d) Tx(a) Rx(alpha). */
+static void dh_link(double theta, double d, double a, double alpha, double A[12]) {
+    double ct = cos(theta), st = sin(theta);
+    double ca = cos(alpha), sa = sin(alpha);
+    A[0] = ct;  A[1] = -st * ca; A[2]  = st * sa;  A[3]  = a * ct;
+    A[4] = st;  A[5] = ct * ca;  A[6]  = -ct * sa; A[7]  = a * st;
+    A[8] = 0.0; A[9] = sa;       A[10] = ca;       A[11] = d;
+}
+
+/* C = A * B for 3x4 homogeneous blocks. */
+static void tf_mul(const double A[12], const double B[12], double C[12]) {
+    double out[12];
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 4; ++c) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) s += A[r * 4 + k] * B[k * 4 + c];
+            if (c == 3) s += A[r * 4 + 3];
+            out[r * 4 + c] = s;
+        }
+    }
+    memcpy(C, out, sizeof(out));
+}
+
+/* ------------------------------------------------------------------------ */
+/* Forward kinematics and geometric Jacobian (Sec. II, Sec. III-C)           */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * pose[12] = (x, y, z, R00, R01, R02, R10, ..., R22) of the end effector.
+ * J (optional) is 6 x n row-major: rows vx, vy, vz, wx, wy, wz; column i is
+ * z_{i-1} x (p - o_{i-1}) over z_{i-1}, the axis and origin of joint i.
+ */
+void or_fk(int n, const double *a, const double *d, const double *alpha,
+           const double *theta_off, const double *q, double *pose, double *J) {
+    double M[12], A[12];
+    double z[OR_MAXN][3], o[OR_MAXN][3];
+    tf_identity(M);
+    for (int i = 0; i < n; ++i) {
+        z[i][0] = M[2]; z[i][1] = M[6]; z[i][2] = M[10];
+        o[i][0] = M[3]; o[i][1] = M[7]; o[i][2] = M[11];
+        double th = q[i] + (theta_off ? theta_off[i] : 0.0);
+        dh_link(th, d[i], a[i], alpha[i], A);
+        tf_mul(M, A, M);
+    }
+    pose[0] = M[3]; pose[1] = M[7]; pose[2] = M[11];
+    pose[3] = M[0]; pose[4] = M[1]; pose[5] = M[2];
+    pose[6] = M[4]; pose[7] = M[5]; pose[8] = M[6];
+    pose[9] = M[8]; pose[10] = M[9]; pose[11] = M[10];
+    if (J) {
+        for (int i = 0; i < n; ++i) {
+            double dx = pose[0] - o[i][0], dy = pose[1] - o[i][1], dz = pose[2] - o[i][2];
+            J[0 * n + i] = z[i][1] * dz - z[i][2] * dy;
+            J[1 * n + i] = z[i][2] * dx - z[i][0] * dz;
+            J[2 * n + i] = z[i][0] * dy - z[i][1] * dx;
+            J[3 * n + i] = z[i][0];
+            J[4 * n + i] = z[i][1];
+            J[5 * n + i] = z[i][2];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Rotation vector (log map of SO(3))                                        */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * phi = theta * u with R = exp([phi]x).  theta = atan2(|v|, (tr R - 1)/2),
+ * v = vee(R - R^T)/2.  Near theta = 0 the factor theta/sin(theta) is its
+ * Taylor series; near theta = pi the axis comes from the symmetric part
+ * (R + R^T)/2 - cos(theta) I = (1 - cos theta) u u^T.
+ */
+void or_log_so3(const double *R, double *phi) {
+    double v0 = 0.5 * (R[7] - R[5]);
+    double v1 = 0.5 * (R[2] - R[6]);
+    double v2 = 0.5 * (R[3] - R[1]);
+    double s = sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+    double c = 0.5 * (R[0] + R[4] + R[8] - 1.0);
+    double th = atan2(s, c);
+    if (th < 1e-4) {
+        double k = 1.0 + th * th / 6.0;
+        phi[0] = k * v0; phi[1] = k * v1; phi[2] = k * v2;
+        return;
+    }
+    if (th > OR_PI - 1e-6) {
+        double B[9];
+        for (int r = 0; r < 3; ++r)
+            for (int cc = 0; cc < 3; ++cc)
+                B[r * 3 + cc] = 0.5 * (R[r * 3 + cc] + R[cc * 3 + r]) - (r == cc ? c : 0.0);
+        int i = 0;
+        if (B[4] > B[i * 4]) i = 1;
+        if (B[8] > B[i * 4]) i = 2;
+        double omc = 1.0 - c;
+        double ui = sqrt(B[i * 4] / omc);
+        double u[3];
+        for (int j = 0; j < 3; ++j) u[j] = B[i * 3 + j] / (omc * ui);
+        u[i] = ui;
+        double dotv = u[0] * v0 + u[1] * v1 + u[2] * v2;
+        if (dotv < 0.0) { u[0] = -u[0]; u[1] = -u[1]; u[2] = -u[2]; }
+        phi[0] = th * u[0]; phi[1] = th * u[1]; phi[2] = th * u[2];
+        return;
+    }
+    double k = th / s;
+    phi[0] = k * v0; phi[1] = k * v1; phi[2] = k * v2;
+}
+
+/* Geodesic angle between two rotations: angle of A B^T. */
+static double rot_angle(const double *A, const double *B) {
+    double M[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            M[r * 3 + c] = A[r * 3 + 0] * B[c * 3 + 0] + A[r * 3 + 1] * B[c * 3 + 1] +
+                           A[r * 3 + 2] * B[c * 3 + 2];
+    double v0 = 0.5 * (M[7] - M[5]), v1 = 0.5 * (M[2] - M[6]), v2 = 0.5 * (M[3] - M[1]);
+    double s = sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+    double c = 0.5 * (M[0] + M[4] + M[8] - 1.0);
+    return atan2(s, c);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Residual and cost (Sec. III-C, residual figure)                           */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int n;
+    const double *a, *d, *alpha, *theta_off, *lo, *hi;
+} or_robot;
+
+/* r[6] = [p(q) - p*; Log(R(q) R*^T)] for one waypoint; J6 optional (6 x n). */
+static void pose_residual(const or_robot *rb, const double *q, const double *target,
+                          double *r, double *J6) {
+    double pose[12];
+    or_fk(rb->n, rb->a, rb->d, rb->alpha, rb->theta_off, q, pose, J6);
+    r[0] = pose[0] - target[0];
+    r[1] = pose[1] - target[1];
+    r[2] = pose[2] - target[2];
+    const double *R = pose + 3, *Rt = target + 3;
+    double E[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            E[i * 3 + j] = R[i * 3 + 0] * Rt[j * 3 + 0] + R[i * 3 + 1] * Rt[j * 3 + 1] +
+                           R[i * 3 + 2] * Rt[j * 3 + 2];
+    or_log_so3(E, r + 3);
+}
+
+/* C(xi) = w_p/2 sum_t |r_t|^2 + w_s/2 sum_{t<T-1} |xi_{t+1} - xi_t|^2 (xi is [T][n]). */
+static double cost_of(const or_robot *rb, int T, const double *xi, const double *targets,
+                      double w_p, double w_s) {
+    int n = rb->n;
+    double pose_sum = 0.0, diff_sum = 0.0;
+    for (int t = 0; t < T; ++t) {
+        double r[6];
+        pose_residual(rb, xi + (size_t)t * n, targets + (size_t)t * 12, r, NULL);
+        for (int i = 0; i < 6; ++i) pose_sum += r[i] * r[i];
+    }
+    for (int t = 0; t + 1 < T; ++t)
+        for (int j = 0; j < n; ++j) {
+            double dq = xi[(size_t)(t + 1) * n + j] - xi[(size_t)t * n + j];
+            diff_sum += dq * dq;
+        }
+    return 0.5 * w_p * pose_sum + 0.5 * w_s * diff_sum;
+}
+
+double or_cost(int n, const double *a, const double *d, const double *alpha,
+               const double *theta_off, int T, const double *xi, const double *targets,
+               double w_p, double w_s) {
+    or_robot rb = {n, a, d, alpha, theta_off, NULL, NULL};
+    return cost_of(&rb, T, xi, targets, w_p, w_s);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Global discrete search (Sec. III-B)                                       */
+/* ------------------------------------------------------------------------ */
+
+/* Penalty of candidate k at waypoint t: joint-limit margin plus caller extra. */
+static double node_penalty(int n, const double *q, const double *lo, const double *hi,
+                           double margin, double penalty, double extra) {
+    int near = 0;
+    for (int j = 0; j < n; ++j)
+        if (q[j] <= lo[j] + margin || q[j] >= hi[j] - margin) near = 1;
+    return (near ? penalty : 0.0) + extra;
+}
+
+/*
+ * cand is [K][T][n].  B_0(k) = pen_0(k);
+ * B_t(k) = min over k' of max(B_{t-1}(k'), e_t(k',k) + pen_t(k)),
+ * e_t(k',k) = max_j |q_t^k[j] - q_{t-1}^{k'}[j]|; the minimising k' is the
+ * smallest under the key (value, e_t(k',k), k').  The end node is the
+ * smallest under (B_{T-1}(k), k); backtracking gives path[T].
+ * Optional outputs: B_all[T][K], bp_all[T][K] (bp_all[0][*] = -1).
+ * Returns 0, or -1 on bad arguments / allocation failure.
+ */
+int or_dp(int T, int K, int n, const double *cand, const double *lo, const double *hi,
+          double margin, double penalty, const double *extra, int32_t *path,
+          double *best_out, double *B_all, int32_t *bp_all) {
+    if (T < 1 || K < 1 || n < 1 || n > OR_MAXN) return -1;
+    double *Bp = (double *)malloc(sizeof(double) * K);
+    double *Bc = (double *)malloc(sizeof(double) * K);
+    int32_t *bp = (int32_t *)malloc(sizeof(int32_t) * (size_t)T * K);
+    if (!Bp || !Bc || !bp) { free(Bp); free(Bc); free(bp); return -1; }
+#define CAND(k, t) (cand + ((size_t)(k) * T + (t)) * n)
+    for (int k = 0; k < K; ++k) {
+        Bp[k] = node_penalty(n, CAND(k, 0), lo, hi, margin, penalty, extra ? extra[k] : 0.0);
+        bp[k] = -1;
+    }
+    if (B_all) memcpy(B_all, Bp, sizeof(double) * K);
+    for (int t = 1; t < T; ++t) {
+        for (int k = 0; k < K; ++k) {
+            const double *qk = CAND(k, t);
+            double pen = node_penalty(n, qk, lo, hi, margin, penalty,
+                                      extra ? extra[(size_t)t * K + k] : 0.0);
+            double bv = INFINITY, be = INFINITY;
+            int bk = -1;
+            for (int kp = 0; kp < K; ++kp) {
+                const double *qp = CAND(kp, t - 1);
+                double e = 0.0;
+                for (int j = 0; j < n; ++j) {
+                    double dq = fabs(qk[j] - qp[j]);
+                    if (dq > e) e = dq;
+                }
+                double v = e + pen;
+                if (Bp[kp] > v) v = Bp[kp];
+                if (v < bv || (v == bv && e < be)) { bv = v; be = e; bk = kp; }
+            }
+            Bc[k] = bv;
+            bp[(size_t)t * K + k] = bk;
+        }
+        if (B_all) memcpy(B_all + (size_t)t * K, Bc, sizeof(double) * K);
+        double *tmp = Bp; Bp = Bc; Bc = tmp;
+    }
+    int kend = 0;
+    for (int k = 1; k < K; ++k)
+        if (Bp[k] < Bp[kend]) kend = k;
+    if (best_out) *best_out = Bp[kend];
+    path[T - 1] = kend;
+    for (int t = T - 1; t > 0; --t) path[t - 1] = bp[(size_t)t * K + path[t]];
+    if (bp_all) memcpy(bp_all, bp, sizeof(int32_t) * (size_t)T * K);
+#undef CAND
+    free(Bp); free(Bc); free(bp);
+    return 0;
+}
+
+/* Maximum joint-angle change along xi ([T][n]); 0 when T < 2. */
+double or_mjac(int T, int n, const double *xi) {
+    double m = 0.0;
+    for (int t = 0; t + 1 < T; ++t)
+        for (int j = 0; j < n; ++j) {
+            double dq = fabs(xi[(size_t)(t + 1) * n + j] - xi[(size_t)t * n + j]);
+            if (dq > m) m = dq;
+        }
+    return m;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Block-tridiagonal symmetric positive definite solve                       */
+/* ------------------------------------------------------------------------ */
+
+/* In-place lower Cholesky of an n x n row-major SPD matrix; -1 if not SPD. */
+static int chol(int n, double *A) {
+    for (int j = 0; j < n; ++j) {
+        double s = A[j * n + j];
+        for (int k = 0; k < j; ++k) s -= A[j * n + k] * A[j * n + k];
+        if (!(s > 0.0)) return -1;
+        double ljj = sqrt(s);
+        A[j * n + j] = ljj;
+        for (int i = j + 1; i < n; ++i) {
+            double u = A[i * n + j];
+            for (int k = 0; k < j; ++k) u -= A[i * n + k] * A[j * n + k];
+            A[i * n + j] = u / ljj;
+        }
+        for (int i = 0; i < j; ++i) A[i * n + j] = 0.0;
+    }
+    return 0;
+}
+
+/* x = L^{-1} b (forward substitution). */
+static void lsolve(int n, const double *L, const double *b, double *x) {
+    for (int i = 0; i < n; ++i) {
+        double s = b[i];
+        for (int k = 0; k < i; ++k) s -= L[i * n + k] * x[k];
+        x[i] = s / L[i * n + i];
+    }
+}
+
+/* x = L^{-T} b (backward substitution). */
+static void ltsolve(int n, const double *L, const double *b, double *x) {
+    for (int i = n - 1; i >= 0; --i) {
+        double s = b[i];
+        for (int k = i + 1; k < n; ++k) s -= L[k * n + i] * x[k];
+        x[i] = s / L[i * n + i];
+    }
+}
+
+/*
+ * Solve H x = b for H with diagonal blocks D_t ([T][n][n], symmetric) and
+ * off-diagonal blocks -w I, by block Cholesky H = L L^T with L block lower
+ * bidiagonal: diagonal blocks L_t with L_t L_t^T = S_t,
+ * S_0 = D_0, S_t = D_t - w^2 S_{t-1}^{-1}; sub-diagonal blocks -w L_{t-1}^{-T}.
+ * Returns 0, or -1 (a pivot was not positive), -2 (allocation).
+ */
+int or_btd_solve(int T, int n, const double *D, double w, const double *b, double *x) {
+    if (T < 1 || n < 1 || n > OR_MAXN) return -2;
+    size_t nn = (size_t)n * n;
+    double *L = (double *)malloc(sizeof(double) * nn * T);
+    double *z = (double *)malloc(sizeof(double) * (size_t)n * T);
+    if (!L || !z) { free(L); free(z); return -2; }
+    double col[OR_MAXN], tmp[OR_MAXN], inv[OR_MAXN * OR_MAXN];
+    int rc = 0;
+    for (int t = 0; t < T; ++t) {
+        double *Lt = L + nn * t;
+        memcpy(Lt, D + nn * t, sizeof(double) * nn);
+        if (t > 0) {
+            const double *Lp = L + nn * (t - 1);
+            /* inv = S_{t-1}^{-1}, column by column. */
+            for (int c = 0; c < n; ++c) {
+                for (int i = 0; i < n; ++i) col[i] = (i == c) ? 1.0 : 0.0;
+                lsolve(n, Lp, col, tmp);
+                ltsolve(n, Lp, tmp, col);
+                for (int i = 0; i < n; ++i) inv[i * n + c] = col[i];
+            }
+            for (size_t e = 0; e < nn; ++e) Lt[e] -= w * w * inv[e];
+        }
+        if (chol(n, Lt) != 0) { rc = -1; break; }
+    }
+    if (rc == 0) {
+        /* Forward: L_t z_t = b_t + w L_{t-1}^{-T} z_{t-1}. */
+        for (int t = 0; t < T; ++t) {
+            double rhs[OR_MAXN];
+            for (int i = 0; i < n; ++i) rhs[i] = b[(size_t)t * n + i];
+            if (t > 0) {
+                ltsolve(n, L + nn * (t - 1), z + (size_t)(t - 1) * n, tmp);
+                for (int i = 0; i < n; ++i) rhs[i] += w * tmp[i];
+            }
+            lsolve(n, L + nn * t, rhs, z + (size_t)t * n);
+        }
+        /* Backward: L_t^T x_t = z_t + w L_t^{-1} x_{t+1}. */
+        for (int t = T - 1; t >= 0; --t) {
+            double rhs[OR_MAXN];
+            for (int i = 0; i < n; ++i) rhs[i] = z[(size_t)t * n + i];
+            if (t < T - 1) {
+                lsolve(n, L + nn * t, x + (size_t)(t + 1) * n, tmp);
+                for (int i = 0; i < n; ++i) rhs[i] += w * tmp[i];
+            }
+            ltsolve(n, L + nn * t, rhs, x + (size_t)t * n);
+        }
+    }
+    free(L); free(z);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Levenberg-Marquardt (Sec. III-C)                                          */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Linearise at xi ([T][n]): per waypoint A_t = w_p J_t^T J_t ([T][n][n]) and
+ * gradient g_t = w_p J_t^T r_t + w_s (c_t xi_t - xi_{t-1} - xi_{t+1}), with
+ * c_t the number of neighbours of t (the differencing residual's Jacobian is
+ * +I on q_{t+1} and -I on q_t).
+ */
+static void linearise(const or_robot *rb, int T, const double *xi, const double *targets,
+                      double w_p, double w_s, double *A, double *g) {
+    int n = rb->n;
+    double J6[6 * OR_MAXN], r[6];
+    for (int t = 0; t < T; ++t) {
+        const double *q = xi + (size_t)t * n;
+        pose_residual(rb, q, targets + (size_t)t * 12, r, J6);
+        double *At = A + (size_t)t * n * n;
+        double *gt = g + (size_t)t * n;
+        for (int i = 0; i < n; ++i) {
+            for (int j = 0; j < n; ++j) {
+                double s = 0.0;
+                for (int k = 0; k < 6; ++k) s += J6[k * n + i] * J6[k * n + j];
+                At[i * n + j] = w_p * s;
+            }
+            double s = 0.0;
+            for (int k = 0; k < 6; ++k) s += J6[k * n + i] * r[k];
+            gt[i] = w_p * s;
+        }
+        for (int j = 0; j < n; ++j) {
+            double sm = 0.0;
+            if (t > 0) sm += q[j] - xi[(size_t)(t - 1) * n + j];
+            if (t + 1 < T) sm += q[j] - xi[(size_t)(t + 1) * n + j];
+            gt[j] += w_s * sm;
+        }
+    }
+}
+
+/* Solve (A + w_s L (x) I + lambda I) delta = -g; returns or_btd_solve's code. */
+static int lm_solve(int T, int n, const double *A, const double *g, double w_s,
+                    double lambda, double *delta, double *Dbuf, double *rhs) {
+    size_t nn = (size_t)n * n;
+    for (int t = 0; t < T; ++t) {
+        int ct = (t > 0) + (t + 1 < T);
+        memcpy(Dbuf + nn * t, A + nn * t, sizeof(double) * nn);
+        for (int i = 0; i < n; ++i) Dbuf[nn * t + (size_t)i * n + i] += w_s * ct + lambda;
+        for (int i = 0; i < n; ++i) rhs[(size_t)t * n + i] = -g[(size_t)t * n + i];
+    }
+    return or_btd_solve(T, n, Dbuf, w_s, rhs, delta);
+}
+
+/*
+ * One damped Gauss-Newton step at xi without accepting it: writes the step
+ * delta ([T][n]) and optionally the gradient g ([T][n]).  Returns 0 or the
+ * solve's error code.
+ */
+int or_lm_step(int n, const double *a, const double *d, const double *alpha,
+               const double *theta_off, int T, const double *xi, const double *targets,
+               double w_p, double w_s, double lambda, double *delta, double *g_out) {
+    or_robot rb = {n, a, d, alpha, theta_off, NULL, NULL};
+    size_t nn = (size_t)n * n;
+    double *A = (double *)malloc(sizeof(double) * nn * T);
+    double *g = (double *)malloc(sizeof(double) * (size_t)n * T);
+    double *Db = (double *)malloc(sizeof(double) * nn * T);
+    double *rhs = (double *)malloc(sizeof(double) * (size_t)n * T);
+    int rc = -2;
+    if (A && g && Db && rhs) {
+        linearise(&rb, T, xi, targets, w_p, w_s, A, g);
+        rc = lm_solve(T, n, A, g, w_s, lambda, delta, Db, rhs);
+        if (g_out) memcpy(g_out, g, sizeof(double) * (size_t)n * T);
+    }
+    free(A); free(g); free(Db); free(rhs);
+    return rc;
+}
+
+typedef struct {
+    double w_pose, w_smooth, lambda0, lambda_min, lambda_max;
+} or_lm_opts;
+
+/*
+ * Levenberg-Marquardt from xi ([T][n], overwritten with the result).
+ * Start: xi <- clamp(xi), lambda <- lambda0, nu <- 2.  Each of `iters`
+ * iterations: linearise at xi (reused after a rejected trial), solve for
+ * delta, trial xi' = clamp(xi + delta), C' = C(xi'); predicted reduction
+ * pred = delta^T (lambda delta - g) / 2 (unclamped delta), gain rho =
+ * (C - C')/pred.  Accept iff C' < C: xi <- xi', lambda *= max(1/3,
+ * 1 - (2 rho - 1)^3), nu <- 2; else lambda *= nu, nu *= 2.  lambda is kept in
+ * [lambda_min, lambda_max].  No early exit.
+ * Histories (optional, length iters): cost after the iteration, lambda used
+ * by the iteration, accept flag.  Returns 0, -1 (non-positive pivot: xi left
+ * at the last accepted iterate), -2 (allocation).
+ */
+int or_lm(int n, const double *a, const double *d, const double *alpha,
+          const double *theta_off, const double *lo, const double *hi, int T,
+          double *xi, const double *targets, const double *opts5, int iters,
+          double *cost_hist, double *lambda_hist, int32_t *acc_hist, double *cost0_out) {
+    or_robot rb = {n, a, d, alpha, theta_off, lo, hi};
+    or_lm_opts o = {opts5[0], opts5[1], opts5[2], opts5[3], opts5[4]};
+    size_t nn = (size_t)n * n, nT = (size_t)n * T;
+    double *A = (double *)malloc(sizeof(double) * nn * T);
+    double *g = (double *)malloc(sizeof(double) * nT);
+    double *Db = (double *)malloc(sizeof(double) * nn * T);
+    double *rhs = (double *)malloc(sizeof(double) * nT);
+    double *delta = (double *)malloc(sizeof(double) * nT);
+    double *trial = (double *)malloc(sizeof(double) * nT);
+    int rc = 0;
+    if (!A || !g || !Db || !rhs || !delta || !trial) { rc = -2; goto done; }
+    for (int t = 0; t < T; ++t)
+        for (int j = 0; j < n; ++j) {
+            double v = xi[(size_t)t * n + j];
+            if (v < lo[j]) v = lo[j];
+            if (v > hi[j]) v = hi[j];
+            xi[(size_t)t * n + j] = v;
+        }
+    double lambda = o.lambda0, nu = 2.0;
+    double C = cost_of(&rb, T, xi, targets, o.w_pose, o.w_smooth);
+    if (cost0_out) *cost0_out = C;
+    int need_lin = 1;
+    for (int it = 0; it < iters; ++it) {
+        if (need_lin) linearise(&rb, T, xi, targets, o.w_pose, o.w_smooth, A, g);
+        if (lambda_hist) lambda_hist[it] = lambda;
+        if (lm_solve(T, n, A, g, o.w_smooth, lambda, delta, Db, rhs) != 0) { rc = -1; break; }
+        for (int t = 0; t < T; ++t)
+            for (int j = 0; j < n; ++j) {
+                size_t e = (size_t)t * n + j;
+                double v = xi[e] + delta[e];
+                if (v < lo[j]) v = lo[j];
+                if (v > hi[j]) v = hi[j];
+                trial[e] = v;
+            }
+        double Cn = cost_of(&rb, T, trial, targets, o.w_pose, o.w_smooth);
+        double pred = 0.0;
+        for (size_t e = 0; e < nT; ++e) pred += delta[e] * (lambda * delta[e] - g[e]);
+        pred *= 0.5;
+        int acc = Cn < C;
+        if (acc) {
+            double rho = (C - Cn) / pred;
+            double u = 2.0 * rho - 1.0;
+            double f = 1.0 - u * u * u;
+            if (f < 1.0 / 3.0) f = 1.0 / 3.0;
+            lambda *= f;
+            nu = 2.0;
+            memcpy(xi, trial, sizeof(double) * nT);
+            C = Cn;
+            need_lin = 1;
+        } else {
+            lambda *= nu;
+            nu *= 2.0;
+            need_lin = 0;
+        }
+        if (lambda < o.lambda_min) lambda = o.lambda_min;
+        if (lambda > o.lambda_max) lambda = o.lambda_max;
+        if (cost_hist) cost_hist[it] = C;
+        if (acc_hist) acc_hist[it] = acc;
+    }
+done:
+    free(A); free(g); free(Db); free(rhs); free(delta); free(trial);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Whole plan and evaluator                                                  */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Search (or_dp) over cand [K][T][n], seed xi_out[T][n] with the chosen
+ * candidates, then `iters` LM iterations.  Returns 0 or a negative code.
+ */
+int or_plan(int n, const double *a, const double *d, const double *alpha,
+            const double *theta_off, const double *lo, const double *hi, int T, int K,
+            const double *cand, const double *targets, const double *extra, double margin,
+            double penalty, const double *opts5, int iters, int32_t *path, double *best,
+            double *xi_out, double *cost_out) {
+    int rc = or_dp(T, K, n, cand, lo, hi, margin, penalty, extra, path, best, NULL, NULL);
+    if (rc) return rc;
+    for (int t = 0; t < T; ++t)
+        memcpy(xi_out + (size_t)t * n, cand + ((size_t)path[t] * T + t) * n, sizeof(double) * n);
+    double *hist = (double *)malloc(sizeof(double) * (iters > 0 ? iters : 1));
+    if (!hist) return -2;
+    double c0 = 0.0;
+    rc = or_lm(n, a, d, alpha, theta_off, lo, hi, T, xi_out, targets, opts5, iters, hist, NULL,
+               NULL, &c0);
+    if (cost_out) *cost_out = iters > 0 ? hist[iters - 1] : c0;
+    free(hist);
+    return rc;
+}
+
+/*
+ * Pose agreement of two trajectories under this oracle's FK:
+ * out[0] = max_t |p_a - p_b| (m), out[1] = max_t angle(R_a R_b^T) (rad).
+ * With xi_b == NULL the second pose comes from targets[T][12] instead.
+ */
+void or_pose_compare(int n, const double *a, const double *d, const double *alpha,
+                     const double *theta_off, int T, const double *xi_a, const double *xi_b,
+                     const double *targets, double *out) {
+    double pa[12], pb[12], mp = 0.0, mr = 0.0;
+    for (int t = 0; t < T; ++t) {
+        or_fk(n, a, d, alpha, theta_off, xi_a + (size_t)t * n, pa, NULL);
+        if (xi_b) or_fk(n, a, d, alpha, theta_off, xi_b + (size_t)t * n, pb, NULL);
+        else memcpy(pb, targets + (size_t)t * 12, sizeof(pb));
+        double dx = pa[0] - pb[0], dy = pa[1] - pb[1], dz = pa[2] - pb[2];
+        double ep = sqrt(dx * dx + dy * dy + dz * dz);
+        double er = rot_angle(pa + 3, pb + 3);
+        if (ep > mp) mp = ep;
+        if (er > mr) mr = er;
+    }
+    out[0] = mp; out[1] = mr;
+}
+
+/* FK of M configurations q[M][n] -> pose[M][12] (and J[M][6][n] if non-NULL). */
+void or_fk_many(int n, const double *a, const double *d, const double *alpha,
+                const double *theta_off, long M, const double *q, double *pose, double *J) {
+    for (long m = 0; m < M; ++m)
+        or_fk(n, a, d, alpha, theta_off, q + (size_t)m * n, pose + (size_t)m * 12,
+              J ? J + (size_t)m * 6 * n : NULL);
+}

@@ -1,0 +1,197 @@
+"""Seeded synthetic workloads for the CppFlow refinement path (arXiv 2309.09102).
+
+This module draws random numbers and nothing else: it holds none of the
+method's arithmetic (no kinematics, no search, no optimisation). Target poses
+are FK(q*), so they are produced by the caller with whichever forward
+kinematics it owns and passed back in through ``Problem.with_targets``.
+
+Workload shapes follow the paper: candidate plans come from a generative IK
+model as K joint-space trajectories over T waypoints (Sec. III-A), the robot is
+a redundant 7-DOF serial chain (Sec. II), and the default K sits in the range
+of the paper's K=175 (Sec. III-A).  The paper's robots and target paths are
+not available, so a random standard-DH chain and a sum-of-sinusoids joint path
+stand in for them.
+
+Draw order (fixed; changing it changes every workload):
+  robot   rng = default_rng([seed, 0]):  a ~ U[0, 0.1] (n), d ~ U[0, 0.4] (n),
+          alpha sign bit ~ U{0, 1} (n)  -> alpha = -pi/2 or +pi/2
+  problem rng = default_rng([seed, 1]):  centre c ~ U[-1, 1] (n),
+          amplitude A ~ U[0, 0.5/3] (n, 3), frequency f ~ U[0.25, 1.5] (n, 3)
+          cycles per path, phase ~ U[0, 2 pi) (n, 3); then the candidate noise
+          N(0, sigma) (K, T, n); then a permutation of K (the first nb get a
+          branch offset); then one sign per (offset candidate, joint 2/4/6).
+Every value handed to either implementation is rounded to the nearest float32
+and stored as float64, so both sides see bit-identical inputs.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+N_JOINTS = 7
+Q_LIMIT = float(np.float32(2.8))
+# 1-based joints 2, 4 and 6 of the chain get the branch offset.
+BRANCH_JOINTS = (1, 3, 5)
+
+
+def _f32(x):
+    return np.asarray(x, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+@dataclasses.dataclass
+class Robot:
+    """Standard (distal) DH chain: one revolute joint per row."""
+    a: np.ndarray
+    d: np.ndarray
+    alpha: np.ndarray
+    theta_off: np.ndarray
+    q_lo: np.ndarray
+    q_hi: np.ndarray
+
+    @property
+    def dof(self) -> int:
+        return int(self.a.shape[0])
+
+
+@dataclasses.dataclass
+class Problem:
+    """One planning request: T target poses and K candidate plans."""
+    robot: Robot
+    q_star: np.ndarray          # [T][n] ground-truth joint path
+    cand: np.ndarray            # [K][T][n] candidate plans
+    targets: np.ndarray | None  # [T][12] (x, y, z, R row-major); None until set
+    seed: int
+    sigma: float
+    branch_frac: float
+
+    @property
+    def T(self) -> int:
+        return int(self.q_star.shape[0])
+
+    @property
+    def K(self) -> int:
+        return int(self.cand.shape[0])
+
+    def with_targets(self, fk_poses: np.ndarray) -> "Problem":
+        """Attach target poses FK(q*) computed by the caller ([T][12])."""
+        fk_poses = np.asarray(fk_poses, dtype=np.float64).reshape(self.T, 12)
+        return dataclasses.replace(self, targets=_f32(fk_poses))
+
+
+def make_robot(seed: int, n: int = N_JOINTS) -> Robot:
+    rng = np.random.default_rng([seed, 0])
+    a = rng.uniform(0.0, 0.1, n)
+    d = rng.uniform(0.0, 0.4, n)
+    bit = rng.integers(0, 2, n)
+    alpha = np.where(bit == 0, -math.pi / 2, math.pi / 2)
+    return Robot(a=_f32(a), d=_f32(d), alpha=_f32(alpha),
+                 theta_off=np.zeros(n), q_lo=np.full(n, -Q_LIMIT),
+                 q_hi=np.full(n, Q_LIMIT))
+
+
+def make_problem(robot: Robot, seed: int, T: int, K: int, sigma: float,
+                 branch_frac: float = 0.0, n_branch: int | None = None,
+                 mode: str = "iid") -> Problem:
+    """Ground-truth path q* and K noisy candidate plans around it.
+
+    mode="iid": noise independent per (candidate, waypoint, joint).
+    mode="smooth": noise drawn per (candidate, joint) and held along the path,
+    closer to the slowly varying plans a generative IK model returns.
+    """
+    if T < 1 or K < 1:
+        raise ValueError("T and K must be >= 1")
+    n = robot.dof
+    rng = np.random.default_rng([seed, 1])
+    c = rng.uniform(-1.0, 1.0, n)
+    A = rng.uniform(0.0, 0.5 / 3.0, (n, 3))
+    f = rng.uniform(0.25, 1.5, (n, 3))
+    ph = rng.uniform(0.0, 2 * math.pi, (n, 3))
+    s = np.arange(T, dtype=np.float64) / max(T - 1, 1)
+    arg = 2 * math.pi * f[None, :, :] * s[:, None, None] + ph[None, :, :]
+    q_star = c[None, :] + np.sum(A[None, :, :] * np.sin(arg), axis=2)
+    q_star = np.clip(_f32(q_star), robot.q_lo, robot.q_hi)
+
+    if mode == "iid":
+        noise = rng.normal(0.0, sigma, (K, T, n))
+    elif mode == "smooth":
+        noise = np.broadcast_to(rng.normal(0.0, sigma, (K, 1, n)), (K, T, n))
+    else:
+        raise ValueError(f"unknown candidate mode {mode!r}")
+    cand = q_star[None, :, :] + noise
+    nb = int(round(branch_frac * K)) if n_branch is None else int(n_branch)
+    nb = max(0, min(nb, K))
+    perm = rng.permutation(K)
+    sel = perm[:nb]
+    signs = rng.choice(np.array([-1.0, 1.0]), (nb, len(BRANCH_JOINTS)))
+    joints = [j for j in BRANCH_JOINTS if j < n]
+    for r, k in enumerate(sel):
+        for c_i, j in enumerate(joints):
+            cand[k, :, j] += signs[r, c_i] * (math.pi / 2)
+    cand = np.clip(_f32(cand), robot.q_lo[None, None, :], robot.q_hi[None, None, :])
+    return Problem(robot=robot, q_star=q_star, cand=np.ascontiguousarray(cand),
+                   targets=None, seed=seed, sigma=float(sigma),
+                   branch_frac=float(nb) / K)
+
+
+# ---- the five measured configurations ---------------------------------------
+
+def config1() -> Problem:
+    """T=50, K=16, sigma=0.05, 4 branch-offset candidates; seed-0 robot."""
+    return make_problem(make_robot(0), seed=0, T=50, K=16, sigma=0.05, n_branch=4)
+
+
+def config2() -> Problem:
+    """T=300, K=256, sigma=0.1, 25% branch-offset candidates."""
+    return make_problem(make_robot(0), seed=2, T=300, K=256, sigma=0.1,
+                        branch_frac=0.25)
+
+
+def config3() -> Problem:
+    """T=1000, K=512, sigma=0.1, 25% branch-offset candidates."""
+    return make_problem(make_robot(0), seed=3, T=1000, K=512, sigma=0.1,
+                        branch_frac=0.25)
+
+
+def config4_problem(i: int, T_range=(100, 1000), K_range=(64, 512)) -> Problem:
+    """Problem i of the 64-problem ragged batch: fresh robot per problem."""
+    seed = 4000 + i
+    rng = np.random.default_rng([seed, 2])
+    T = int(rng.integers(T_range[0], T_range[1] + 1))
+    K = int(rng.integers(K_range[0], K_range[1] + 1))
+    return make_problem(make_robot(seed), seed=seed, T=T, K=K, sigma=0.1,
+                        branch_frac=0.25)
+
+
+def config5_request(i: int, T_range=(50, 2000), K_choices=(128, 256, 512)) -> Problem:
+    """Request i of the serving stream: seed-0 robot, per-request shape."""
+    seed = 5000 + i
+    rng = np.random.default_rng([seed, 2])
+    T = int(rng.integers(T_range[0], T_range[1] + 1))
+    K = int(rng.choice(np.array(K_choices)))
+    sigma = float(rng.uniform(0.02, 0.15))
+    frac = float(rng.uniform(0.0, 0.3))
+    return make_problem(make_robot(0), seed=seed, T=T, K=K, sigma=sigma,
+                        branch_frac=frac)
+
+
+def config5_arrivals(rate_hz: float = 200.0, duration_s: float = 60.0,
+                     seed: int = 5) -> np.ndarray:
+    """Poisson arrival times (s) of the serving stream."""
+    rng = np.random.default_rng([seed, 3])
+    out = []
+    t = 0.0
+    while True:
+        t += rng.exponential(1.0 / rate_hz)
+        if t >= duration_s:
+            break
+        out.append(t)
+    return np.asarray(out)
+
+
+def random_configs(seed: int, M: int, robot: Robot, spread: float = math.pi) -> np.ndarray:
+    """M joint configurations ([M][n]) uniform in [-spread, spread], float32-exact."""
+    rng = np.random.default_rng([seed, 4])
+    q = rng.uniform(-spread, spread, (M, robot.dof))
+    return _f32(q)

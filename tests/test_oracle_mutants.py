@@ -1,0 +1,90 @@
+"""Each plausible mistake planted in a copy of the oracle must fail a pin.
+
+The copies are compiled on the CPU into a temporary directory; the real
+oracle library is restored afterwards.  This checks that the pins in
+test_oracle_pins.py constrain every part of the oracle (a dropped term, a
+wrong sign or index, a transposed operand, a wrong tie-break).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import oracle as _w
+from tests import test_oracle_pins as P
+
+SRC = os.path.join(os.path.dirname(_w.__file__), "cpf_oracle.c")
+
+MUTANTS = {
+    "fk_sign": ("A[1] = -st * ca;", "A[1] = st * ca;"),
+    "fk_param": ("A[11] = d;", "A[11] = a;"),
+    "fk_translation_dropped": ("if (c == 3) s += A[r * 4 + 3];", "if (c == 3) s += 0.0;"),
+    "jac_cross_sign": ("J[0 * n + i] = z[i][1] * dz - z[i][2] * dy;",
+                       "J[0 * n + i] = z[i][2] * dy - z[i][1] * dz;"),
+    "log_vee_sign": ("double v0 = 0.5 * (R[7] - R[5]);", "double v0 = 0.5 * (R[5] - R[7]);"),
+    "residual_sign": ("r[0] = pose[0] - target[0];", "r[0] = target[0] - pose[0];"),
+    "cost_weight": ("return 0.5 * w_p * pose_sum + 0.5 * w_s * diff_sum;",
+                    "return 0.5 * w_p * pose_sum + w_s * diff_sum;"),
+    "grad_term_dropped": ("if (t > 0) sm += q[j] - xi[(size_t)(t - 1) * n + j];",
+                          "if (t > 0) sm += 0.0;"),
+    "jtj_index": ("s += J6[k * n + i] * J6[k * n + j];", "s += J6[k * n + i] * J6[k * n + i];"),
+    "dp_tiebreak": ("if (v < bv || (v == bv && e < be))", "if (v < bv || (v == bv && e > be))"),
+    "dp_penalty_dropped": ("double v = e + pen;", "double v = e;"),
+    "dp_end_tie": ("if (Bp[k] < Bp[kend]) kend = k;", "if (Bp[k] <= Bp[kend]) kend = k;"),
+    "btd_forward_sign": ("for (int i = 0; i < n; ++i) rhs[i] += w * tmp[i];\n            }\n            lsolve",
+                         "for (int i = 0; i < n; ++i) rhs[i] -= w * tmp[i];\n            }\n            lsolve"),
+    "btd_schur_power": ("Lt[e] -= w * w * inv[e];", "Lt[e] -= w * inv[e];"),
+    "lm_diag_dropped": ("Dbuf[nn * t + (size_t)i * n + i] += w_s * ct + lambda;",
+                        "Dbuf[nn * t + (size_t)i * n + i] += lambda;"),
+    "lm_always_accept": ("int acc = Cn < C;", "int acc = 1;"),
+    "lm_no_clamp": ("if (v > hi[j]) v = hi[j];\n                trial[e] = v;",
+                    "trial[e] = v;"),
+}
+
+
+def battery():
+    """Fast calls of the pin tests; each raises if its pin is violated."""
+    return [
+        lambda: P.test_p1_fk_zero_configuration(0),
+        lambda: P.test_p2_fk_single_axis(0, 1.0),
+        lambda: P.test_p5_jacobian_finite_differences(0),
+        lambda: P.test_p5_jacobian_planar_closed_form(),
+        lambda: P.test_p6_gradient_matches_cost_fd(0.1),
+        lambda: P.test_p6_cost_definition_small_case(),
+        lambda: P.test_p7_log_branches_match_library(0.5),
+        lambda: P.test_p8_dp_matches_brute_force(),
+        lambda: P.test_p9_single_waypoint_is_argmin_penalty(),
+        lambda: P.test_p9_exact_tie_breaks_on_edge_then_index(),
+        lambda: P.test_p9_penalised_node_avoided_when_possible(),
+        lambda: P.test_p10_block_solve_matches_dense(7, 0.1),
+        lambda: P.test_p11_smoothness_only_step_dct_closed_form(9, 1e-3),
+        lambda: P.test_p12_dls_push_through_identity(1e-2),
+        lambda: P.test_p13_lm_cost_monotone_and_rejects_keep_xi(0),
+        lambda: P.test_p13_lm_clamps_to_limits(),
+    ]
+
+
+def test_unmutated_battery_passes():
+    for check in battery():
+        check()
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) >= 1, f"mutation anchor for {name} not found"
+    lib = _w.build_copy(src.replace(old, new, 1), str(tmp_path / f"lib_{name}.so"))
+    prev = _w.use_library(lib)
+    caught = []
+    try:
+        for i, check in enumerate(battery()):
+            try:
+                check()
+            except Exception as exc:   # AssertionError, LinAlgError, hypothesis errors
+                caught.append((i, type(exc).__name__))
+    finally:
+        _w.restore_library(prev)
+    assert caught, f"mutant {name} passed every pin"
