@@ -1,0 +1,175 @@
+"""Benchmark of the CppFlow refinement path on one MI355X.
+
+A step is one pass of the whole path over one request: batched FK over the
+K x T candidates, the layered-graph search with its back-tracking and seed
+gather, the LM iterations (linearise, FP64 block solve with refinement,
+trial, accept) and the pose-error report.  Inputs are resident in HBM before
+the timed region starts (the plan is uploaded once; every step restarts from
+the search).
+
+Default workload: T=300 waypoints, K=256 candidates (sigma 0.1 rad, 25%
+branch-offset candidates), 50 LM iterations, seed-0 7-DOF DH robot.
+
+Prints one JSON line.  `value` is waypoint-LM-iterations per second of the
+mixed-precision path (FP32 kinematics, FP64 solve); the all-FP64 path on the
+same GPU is reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_ALU_TFLOPS = 78.6      # 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz, FP32 unpacked and FP64
+PEAK_HBM_GBS = 8000.0
+
+# Algorithmic flops of one LM waypoint-iteration (derivation in the design notes):
+# linearise 964 (FK + J + residual + J^T J + J^T r), trial 436 (FK + residual),
+# FP64 solve 1160, FP64 refinement 330, FP64 clamp / predicted reduction 42.
+LM_FLOPS_PER_WAYPOINT_ITER = 964 + 436 + 1160 + 330 + 42
+# One search pair (t, k', k): 7 sub + 7 abs-max + add + max + 2 compares.
+DP_OPS_PER_PAIR = 18
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--iters", type=int, default=50)
+    ap.add_argument("--workload", default="T300_K256", choices=["T300_K256", "T1000_K512"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); plans are "
+              "independent, so several GPUs would shard whole requests with no collective.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2309_09102_amd import cpf, synth
+
+    dev = torch.device("cuda:0")
+    prob = synth.config2() if args.workload == "T300_K256" else synth.config3()
+    T, K, iters = prob.T, prob.K, args.iters
+    ctx = cpf.Context(0)
+
+    # Targets FK(q*) by the library's FP64 FK on the device (input preparation).
+    q_star = torch.tensor(prob.q_star.T.copy(), dtype=torch.float64, device=dev)
+    pose, _ = ctx.fk_batch(prob.robot, q_star)
+    torch.cuda.synchronize()
+    prob = prob.with_targets(pose.cpu().numpy().T)
+
+    cand_soa = torch.tensor(prob.cand.reshape(-1, 7).T.copy(), dtype=torch.float32, device=dev)
+
+    def run_arm(prec):
+        opts = cpf.make_opts(prec=prec, iters=iters)
+        plan = ctx.plan(prob.robot, prob.targets, prob.cand, opts=opts)
+
+        def step():
+            ctx.fk_batch(prob.robot, cand_soa)          # batched FK over the K x T candidates
+            plan.dp_search()                             # search, back-track, seed
+            return plan.lm_refine(iters, want_xi=False)  # LM iterations + report
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, rep = step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        stats = {k: ctx.kernel_stats(k) for k in ("fk", "dp", "lm", "eval")}
+        ctx.profile(False)
+        xi, _ = plan.lm_refine(0)
+        plan.free()
+        return (t1 - t0) / args.steps, stats, rep, xi
+
+    sec_mixed, st_mixed, rep_mixed, xi_mixed = run_arm("mixed")
+    sec_fp64, st_fp64, rep_fp64, xi_fp64 = run_arm("fp64")
+
+    work = T * iters
+    value = work / sec_mixed
+
+    def avg_ms(stats, k):
+        ms, n = stats[k]
+        return ms / max(n, 1)
+
+    lm_ms = avg_ms(st_mixed, "lm")
+    dp_ms = avg_ms(st_mixed, "dp")
+    lm_flops = LM_FLOPS_PER_WAYPOINT_ITER * T * iters
+    dp_flops = DP_OPS_PER_PAIR * (T - 1) * K * K
+    if lm_ms >= dp_ms:
+        dom, dom_ms, dom_flops = "lm_kernel<float>", lm_ms, lm_flops
+    else:
+        dom, dom_ms, dom_flops = "dp_kernel", dp_ms, dp_flops
+    achieved = dom_flops / (dom_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_ALU_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS, "traffic": None,
+                "avg_launch_ms": dom_ms}
+
+    out = {
+        "metric": "waypoint-LM-iters/sec",
+        "value": value,
+        "unit": "waypoint-LM-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec_mixed * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 kinematics + f64 solve",
+        "data": "synthetic (seeded DH robot, sum-of-sinusoid path, noisy candidate plans)",
+        "config": {"workload": f"single request T={T} K={K}, {iters} LM iterations",
+                   "T": T, "K": K, "lm_iters": iters, "parallelism": "single GPU"},
+        "fp64_path": {"value": work / sec_fp64, "ms_per_step": sec_fp64 * 1e3,
+                      "speedup_mixed_over_fp64": sec_fp64 / sec_mixed},
+        "kernels_ms": {"mixed": {k: avg_ms(st_mixed, k) for k in st_mixed},
+                       "fp64": {k: avg_ms(st_fp64, k) for k in st_fp64}},
+        "report": {"mixed": rep_mixed, "fp64": rep_fp64},
+        "roofline": roofline,
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = 1
+        t0 = time.perf_counter()
+        n = 0
+        ref = None
+        while True:
+            ref = oracle.plan(prob.robot, prob.cand, prob.targets, iters)
+            n += 1
+            if time.perf_counter() - t0 >= args.cpu_seconds:
+                break
+        dt = (time.perf_counter() - t0) / n
+        out["cpu_baseline"] = {"value": work / dt, "unit": "waypoint-LM-iters/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"{n} full runs of the same request (search + {iters} LM "
+                                         f"iterations), FP64 C oracle, 1 thread, "
+                                         f"{platform.processor() or platform.machine()}"}
+        ep_m, er_m = oracle.pose_compare(prob.robot, xi_mixed, ref["xi"])
+        ep_d, er_d = oracle.pose_compare(prob.robot, xi_fp64, ref["xi"])
+        out["pose_err_vs_oracle"] = {"mixed": [ep_m, er_m], "fp64": [ep_d, er_d],
+                                     "unit": ["m", "rad"]}
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

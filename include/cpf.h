@@ -1,0 +1,211 @@
+/*
+ * cpf.h -- C ABI of the MI355X (gfx950) refinement path of CppFlow
+ * (arXiv 2309.09102): batched forward kinematics, the layered-graph search
+ * over candidate plans, and Levenberg-Marquardt trajectory optimisation,
+ * plus a continuously batched request server.
+ *
+ * Problem (Sec. II): given a redundant serial robot with forward kinematics
+ * FK : R^n -> SE(3) and a target path Y = [y_0 .. y_{T-1}] of T poses, find
+ * a joint trajectory xi = [q_0 .. q_{T-1}] whose end effector follows Y.
+ * The caller supplies K approximate candidate plans (the role of the
+ * generative IK model in Sec. III-A); the library picks one candidate per
+ * waypoint minimising the maximum joint-angle change (Sec. III-B) and then
+ * refines the result with damped least squares on pose and differencing
+ * residuals, clamped to the joint limits (Sec. III-C).
+ *
+ * Conventions
+ *   - n = dof = 7 revolute joints, standard (distal) Denavit-Hartenberg:
+ *     A_i = Rz(q_i + theta_off_i) Tz(d_i) Tx(a_i) Rx(alpha_i), no base or
+ *     tool transform.  Other dof values return CPF_E_UNSUPPORTED.
+ *   - A pose is 12 doubles: x, y, z, then the 3x3 rotation row-major.
+ *   - Host arrays are C-contiguous float64 unless stated otherwise.
+ *   - Every function is exception-free; a non-OK status leaves outputs
+ *     untouched and sets a per-thread message readable by cpf_last_error().
+ *   - Candidate and target values are used as given; the library does not
+ *     round them.  (Float32-representable inputs make the search decisions
+ *     independent of the precision the candidates are stored in on device.)
+ *
+ * Status codes
+ *   CPF_OK           success
+ *   CPF_PENDING      (cpf_poll) the request is not finished yet
+ *   CPF_E_ARG        null pointer, bad size, non-finite input
+ *   CPF_E_NOMEM      device allocation failed or the request exceeds the
+ *                    context's whole memory budget
+ *   CPF_E_DEVICE     a HIP runtime error
+ *   CPF_E_STATE      call out of order (e.g. lm_refine before dp_search)
+ *   CPF_E_NOTFOUND   unknown ticket
+ *   CPF_E_NUMERIC    non-finite cost or a non-positive pivot in the solve
+ *   CPF_E_UNSUPPORTED a shape the kernels are not built for (dof != 7,
+ *                    K > 1024)
+ */
+#ifndef CPF_H
+#define CPF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum cpf_status {
+    CPF_OK = 0,
+    CPF_PENDING = 1,
+    CPF_E_ARG = -1,
+    CPF_E_NOMEM = -2,
+    CPF_E_DEVICE = -3,
+    CPF_E_STATE = -4,
+    CPF_E_NOTFOUND = -5,
+    CPF_E_NUMERIC = -6,
+    CPF_E_UNSUPPORTED = -7
+} cpf_status;
+
+/* Arithmetic of FK, Jacobians and residuals.  The linear solve is FP64 in
+ * both: CPF_MIXED computes kinematics in FP32 and refines the FP64 solve;
+ * CPF_F64 computes everything in FP64. */
+enum { CPF_F32 = 0, CPF_F64 = 1 };
+enum { CPF_MIXED = 0, CPF_FP64 = 1 };
+
+typedef struct cpf_ctx cpf_ctx;
+typedef struct cpf_plan cpf_plan;
+
+/* Robot: dof rows of standard DH parameters and joint limits (host, copied). */
+typedef struct cpf_robot {
+    int32_t dof;
+    const double *a, *d, *alpha, *theta_off; /* theta_off may be NULL (zeros) */
+    const double *q_lo, *q_hi;
+} cpf_robot;
+
+/* One problem (host, copied by every call that takes it).
+ *   targets  [T][12]   target poses Y (Sec. II)
+ *   cand     [K][T][dof] candidate plans (Sec. III-A)
+ *   node_pen [T][K] or NULL: extra per-node search cost added to the
+ *            joint-limit penalty (the paper's collision cost, Sec. III-B) */
+typedef struct cpf_problem {
+    int32_t T, K;
+    const double *targets;
+    const double *cand;
+    const double *node_pen;
+} cpf_problem;
+
+/* Options (cpf_opts_default fills the defaults shown).
+ *   w_pose 1, w_smooth 0.1: cost C = w_pose/2 sum_t |r_pose,t|^2
+ *                           + w_smooth/2 sum_t |q_{t+1} - q_t|^2 (Sec. III-C)
+ *   lambda0 1e-3, lambda_min 1e-10, lambda_max 1e10: Levenberg damping and
+ *     its bounds; updated by Nielsen's gain-ratio rule
+ *   limit_margin 1.5 deg, limit_penalty 10: joint-limit search penalty
+ *     (Sec. III-B)
+ *   iters: LM iterations run by cpf_submit / cpf_plan_solve
+ *   prec: CPF_MIXED or CPF_FP64
+ *   refine_steps 1: FP64 iterative-refinement steps after each solve */
+typedef struct cpf_opts {
+    double w_pose, w_smooth;
+    double lambda0, lambda_min, lambda_max;
+    double limit_margin, limit_penalty;
+    int32_t iters, prec, refine_steps;
+} cpf_opts;
+
+typedef struct cpf_lm_report {
+    double cost0;            /* cost of the clamped seed */
+    double cost;             /* cost after the last iteration */
+    double lambda;           /* current damping */
+    double grad_inf;         /* max |g| at the last linearisation */
+    int32_t n_accepted;      /* accepted iterations so far */
+    int32_t iters_done;      /* iterations so far (resumable) */
+    double max_pos_err_m;    /* max_t |p(q_t) - p*_t| (FP64 FK) */
+    double max_rot_err_rad;  /* max_t angle(R(q_t) R*_t^T) (FP64 FK) */
+    double mjac;             /* max joint change along the result */
+} cpf_lm_report;
+
+typedef struct cpf_result {
+    double *xi;              /* [T][dof] caller buffer, or NULL */
+    int32_t *path;           /* [T] caller buffer, or NULL */
+    cpf_lm_report report;
+    double search_best;      /* optimal search value B* */
+    double search_mjac;      /* mjac of the searched seed */
+    int32_t status;          /* per-request cpf_status */
+    int64_t t_submit_ns, t_admit_ns, t_search_done_ns, t_done_ns; /* steady clock */
+} cpf_result;
+
+void cpf_opts_default(cpf_opts *o);
+
+/* Per-thread message of the last failed call on this thread. */
+const char *cpf_last_error(void);
+
+/* Context on HIP device `device` with a device-memory budget in bytes for
+ * plans and requests (0 = 64 GiB).  Owns its streams and server thread. */
+cpf_status cpf_ctx_create(int device, uint64_t mem_budget_bytes, cpf_ctx **out);
+/* Finishes in-flight requests (their tickets resolve), then frees all. */
+void cpf_ctx_destroy(cpf_ctx *ctx);
+/* Budget bytes currently reserved by live plans and admitted requests. */
+uint64_t cpf_ctx_bytes_in_use(const cpf_ctx *ctx);
+
+/* Copy one problem to the device (candidates as float32, SoA).  Inputs are
+ * copied before return.  Sec. II (problem), Sec. III-A (candidates). */
+cpf_status cpf_plan_init(cpf_ctx *ctx, const cpf_robot *robot, const cpf_problem *prob,
+                         const cpf_opts *opts, cpf_plan **out);
+void cpf_plan_free(cpf_plan *plan);
+
+/* Batched forward kinematics and geometric Jacobian (Sec. II; the kinematic
+ * Jacobian of Sec. III-C).  Device pointers owned by the caller, SoA:
+ *   q_dev    [dof][M]      joint values
+ *   pose_dev [12][M]       x, y, z, R row-major
+ *   jac_dev  [6*dof][M] or NULL; element (row, j) of the 6 x dof Jacobian
+ *            (rows vx, vy, vz, wx, wy, wz) at index (row*dof + j)*M + m
+ * prec selects float (CPF_F32) or double (CPF_F64) for all three arrays.
+ * Asynchronous on hip_stream (a hipStream_t, NULL = default stream); only
+ * argument errors are reported synchronously. */
+cpf_status cpf_fk_batch(cpf_ctx *ctx, const cpf_robot *robot, int64_t M, int32_t prec,
+                        const void *q_dev, void *pose_dev, void *jac_dev, void *hip_stream);
+
+/* Layered-graph search (Sec. III-B): node (t, k) is candidate k at waypoint
+ * t; B_0(k) = pen_0(k), B_t(k) = min_k' max(B_{t-1}(k'), e_t(k',k) +
+ * pen_t(k)) with e_t = max_j |q_t^k[j] - q_{t-1}^k'[j]| and pen the
+ * joint-limit penalty plus node_pen.  Ties go to the smallest (value, e,
+ * k'); the end node is the smallest (B_{T-1}(k), k).  Writes path[T], B*
+ * and the mjac of the chosen seed; stores the seed in the plan.
+ * Synchronous. */
+cpf_status cpf_dp_search(cpf_plan *plan, int32_t *path_out, double *best_out,
+                         double *mjac_out);
+
+/* Run `iters` LM iterations from the plan's current trajectory (the clamped
+ * search seed the first time; resumable).  xi_out [T][dof] or NULL.
+ * Sec. III-C.  Synchronous. */
+cpf_status cpf_lm_refine(cpf_plan *plan, int32_t iters, double *xi_out, cpf_lm_report *rep);
+
+/* Search + opts->iters LM iterations for nplans independent problems in one
+ * launch of each kernel (one workgroup per plan).  results[i].xi / .path may
+ * be NULL.  Per-plan errors land in results[i].status; the call returns the
+ * first argument / device error. */
+cpf_status cpf_solve_batch(cpf_ctx *ctx, int32_t nplans, const cpf_robot *robots,
+                           const cpf_problem *probs, const cpf_opts *opts,
+                           cpf_result *results);
+
+/* Serving: copy the request, queue it, return a ticket at once.  The server
+ * thread admits queued requests while their device bytes fit the budget,
+ * runs their searches, and advances every admitted request by LM iterations
+ * in shared launches until it reaches opts->iters.  A request larger than
+ * the whole budget gives CPF_E_NOMEM. */
+cpf_status cpf_submit(cpf_ctx *ctx, const cpf_robot *robot, const cpf_problem *prob,
+                      const cpf_opts *opts, uint64_t *ticket);
+
+/* Wait up to timeout_ms (0 = do not wait, <0 = forever) for a ticket.
+ * CPF_PENDING while running; on completion copies xi / path into the
+ * caller's buffers in *out (if non-NULL), fills the report and timestamps,
+ * releases the ticket and returns CPF_OK (the request's own failure is in
+ * out->status).  Unknown or already released ticket: CPF_E_NOTFOUND. */
+cpf_status cpf_poll(cpf_ctx *ctx, uint64_t ticket, int32_t timeout_ms, cpf_result *out);
+
+/* Kernel timing (tracing aid for the benchmark): with profiling enabled the
+ * context brackets each of its kernel launches with HIP events on the
+ * stream the kernel runs on.  cpf_ctx_kernel_stats returns the summed
+ * duration (ms) and launch count for kernel "fk", "dp", "lm" or "eval" since
+ * profiling was enabled (it synchronises the context's streams). */
+cpf_status cpf_ctx_profile(cpf_ctx *ctx, int32_t enable);
+cpf_status cpf_ctx_kernel_stats(cpf_ctx *ctx, const char *kernel, double *total_ms,
+                                int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPF_H */

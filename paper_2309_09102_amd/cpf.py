@@ -1,0 +1,356 @@
+"""Python binding of libcpf.so (the C ABI declared in include/cpf.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  PyTorch is imported first so that the process has a single HIP
+runtime (torch's), which the library then shares; torch tensors serve as
+caller-owned device buffers for ``fk_batch``.  If the library has not been
+built this module raises at import; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcpf.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() "
+                      "(or python paper_2309_09102_amd/build.py) first")
+_lib = C.CDLL(LIB_PATH)
+
+OK, PENDING = 0, 1
+E_ARG, E_NOMEM, E_DEVICE, E_STATE, E_NOTFOUND, E_NUMERIC, E_UNSUPPORTED = -1, -2, -3, -4, -5, -6, -7
+F32, F64 = 0, 1
+MIXED, FP64 = 0, 1
+_NAMES = {0: "OK", 1: "PENDING", -1: "E_ARG", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_STATE",
+          -5: "E_NOTFOUND", -6: "E_NUMERIC", -7: "E_UNSUPPORTED"}
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class CpfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class cpf_robot(C.Structure):
+    _fields_ = [("dof", C.c_int32), ("a", _dp), ("d", _dp), ("alpha", _dp),
+                ("theta_off", _dp), ("q_lo", _dp), ("q_hi", _dp)]
+
+
+class cpf_problem(C.Structure):
+    _fields_ = [("T", C.c_int32), ("K", C.c_int32), ("targets", _dp), ("cand", _dp),
+                ("node_pen", _dp)]
+
+
+class cpf_opts(C.Structure):
+    _fields_ = [("w_pose", C.c_double), ("w_smooth", C.c_double), ("lambda0", C.c_double),
+                ("lambda_min", C.c_double), ("lambda_max", C.c_double),
+                ("limit_margin", C.c_double), ("limit_penalty", C.c_double),
+                ("iters", C.c_int32), ("prec", C.c_int32), ("refine_steps", C.c_int32)]
+
+
+class cpf_lm_report(C.Structure):
+    _fields_ = [("cost0", C.c_double), ("cost", C.c_double), ("lambda_", C.c_double),
+                ("grad_inf", C.c_double), ("n_accepted", C.c_int32), ("iters_done", C.c_int32),
+                ("max_pos_err_m", C.c_double), ("max_rot_err_rad", C.c_double),
+                ("mjac", C.c_double)]
+
+
+class cpf_result(C.Structure):
+    _fields_ = [("xi", _dp), ("path", _ip), ("report", cpf_lm_report),
+                ("search_best", C.c_double), ("search_mjac", C.c_double),
+                ("status", C.c_int32), ("t_submit_ns", C.c_int64), ("t_admit_ns", C.c_int64),
+                ("t_search_done_ns", C.c_int64), ("t_done_ns", C.c_int64)]
+
+
+_vp = C.c_void_p
+_lib.cpf_opts_default.argtypes = [C.POINTER(cpf_opts)]
+_lib.cpf_last_error.restype = C.c_char_p
+_lib.cpf_ctx_create.argtypes = [C.c_int, C.c_uint64, C.POINTER(_vp)]
+_lib.cpf_ctx_destroy.argtypes = [_vp]
+_lib.cpf_ctx_bytes_in_use.argtypes = [_vp]
+_lib.cpf_ctx_bytes_in_use.restype = C.c_uint64
+_lib.cpf_plan_init.argtypes = [_vp, C.POINTER(cpf_robot), C.POINTER(cpf_problem),
+                               C.POINTER(cpf_opts), C.POINTER(_vp)]
+_lib.cpf_plan_free.argtypes = [_vp]
+_lib.cpf_fk_batch.argtypes = [_vp, C.POINTER(cpf_robot), C.c_int64, C.c_int32, _vp, _vp, _vp, _vp]
+_lib.cpf_dp_search.argtypes = [_vp, _ip, _dp, _dp]
+_lib.cpf_lm_refine.argtypes = [_vp, C.c_int32, _dp, C.POINTER(cpf_lm_report)]
+_lib.cpf_solve_batch.argtypes = [_vp, C.c_int32, C.POINTER(cpf_robot), C.POINTER(cpf_problem),
+                                 C.POINTER(cpf_opts), C.POINTER(cpf_result)]
+_lib.cpf_submit.argtypes = [_vp, C.POINTER(cpf_robot), C.POINTER(cpf_problem),
+                            C.POINTER(cpf_opts), C.POINTER(C.c_uint64)]
+_lib.cpf_poll.argtypes = [_vp, C.c_uint64, C.c_int32, C.POINTER(cpf_result)]
+_lib.cpf_ctx_profile.argtypes = [_vp, C.c_int32]
+_lib.cpf_ctx_kernel_stats.argtypes = [_vp, C.c_char_p, C.POINTER(C.c_double),
+                                      C.POINTER(C.c_int64)]
+for _f in ("cpf_ctx_create", "cpf_plan_init", "cpf_fk_batch", "cpf_dp_search", "cpf_lm_refine",
+           "cpf_solve_batch", "cpf_submit", "cpf_poll", "cpf_ctx_profile",
+           "cpf_ctx_kernel_stats"):
+    getattr(_lib, _f).restype = C.c_int
+
+EXPORTS = ("cpf_opts_default", "cpf_last_error", "cpf_ctx_create", "cpf_ctx_destroy",
+           "cpf_ctx_bytes_in_use", "cpf_plan_init", "cpf_plan_free", "cpf_fk_batch",
+           "cpf_dp_search", "cpf_lm_refine", "cpf_solve_batch", "cpf_submit", "cpf_poll",
+           "cpf_ctx_profile", "cpf_ctx_kernel_stats")
+
+
+def last_error() -> str:
+    return (_lib.cpf_last_error() or b"").decode()
+
+
+def _check(st):
+    if st not in (OK, PENDING):
+        raise CpfError(st, last_error())
+    return st
+
+
+def _f64(x):
+    return np.ascontiguousarray(x, dtype=np.float64)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+class _Keep:
+    """ctypes struct plus the numpy arrays its pointers refer to."""
+
+    def __init__(self, struct, arrays):
+        self.struct = struct
+        self.arrays = arrays
+
+
+def make_robot(robot) -> _Keep:
+    arrs = [_f64(robot.a), _f64(robot.d), _f64(robot.alpha), _f64(robot.theta_off),
+            _f64(robot.q_lo), _f64(robot.q_hi)]
+    s = cpf_robot(int(arrs[0].shape[0]), *[_ptr(a) for a in arrs])
+    return _Keep(s, arrs)
+
+
+def make_problem(targets, cand, node_pen=None) -> _Keep:
+    tg = _f64(targets)
+    cd = _f64(cand)
+    K, T = int(cd.shape[0]), int(cd.shape[1])
+    npen = None if node_pen is None else _f64(node_pen)
+    s = cpf_problem(T, K, _ptr(tg), _ptr(cd), _ptr(npen))
+    return _Keep(s, [tg, cd, npen])
+
+
+def opts_default() -> cpf_opts:
+    o = cpf_opts()
+    _lib.cpf_opts_default(C.byref(o))
+    return o
+
+
+def make_opts(**kw) -> cpf_opts:
+    o = opts_default()
+    for k, v in kw.items():
+        if k == "prec" and isinstance(v, str):
+            v = {"mixed": MIXED, "fp64": FP64}[v]
+        setattr(o, k, v)
+    return o
+
+
+def _report(r: cpf_lm_report) -> dict:
+    return dict(cost0=r.cost0, cost=r.cost, lam=r.lambda_, grad_inf=r.grad_inf,
+                n_accepted=r.n_accepted, iters_done=r.iters_done,
+                max_pos_err_m=r.max_pos_err_m, max_rot_err_rad=r.max_rot_err_rad, mjac=r.mjac)
+
+
+# ---- functions with the C ABI's names ---------------------------------------
+
+def ctx_create(device: int = 0, budget_bytes: int = 0):
+    h = _vp()
+    _check(_lib.cpf_ctx_create(device, budget_bytes, C.byref(h)))
+    return h
+
+
+def ctx_destroy(ctx):
+    _lib.cpf_ctx_destroy(ctx)
+
+
+def ctx_bytes_in_use(ctx) -> int:
+    return int(_lib.cpf_ctx_bytes_in_use(ctx))
+
+
+def ctx_profile(ctx, enable: bool):
+    _check(_lib.cpf_ctx_profile(ctx, 1 if enable else 0))
+
+
+def ctx_kernel_stats(ctx, kernel: str):
+    """(total ms, launches) of kernel 'fk' | 'dp' | 'lm' | 'eval' since profiling began."""
+    ms = C.c_double()
+    n = C.c_int64()
+    _check(_lib.cpf_ctx_kernel_stats(ctx, kernel.encode(), C.byref(ms), C.byref(n)))
+    return ms.value, int(n.value)
+
+
+def plan_init(ctx, robot, targets, cand, node_pen=None, opts=None):
+    rb = make_robot(robot)
+    pb = make_problem(targets, cand, node_pen)
+    o = opts if opts is not None else opts_default()
+    h = _vp()
+    _check(_lib.cpf_plan_init(ctx, C.byref(rb.struct), C.byref(pb.struct), C.byref(o), C.byref(h)))
+    return h
+
+
+def plan_free(plan):
+    _lib.cpf_plan_free(plan)
+
+
+def fk_batch(ctx, robot, M, prec, q_ptr, pose_ptr, jac_ptr=None, stream=None):
+    """Device pointers (ints) in the SoA layout of include/cpf.h."""
+    rb = make_robot(robot)
+    _check(_lib.cpf_fk_batch(ctx, C.byref(rb.struct), int(M), int(prec), _vp(q_ptr),
+                             _vp(pose_ptr), _vp(jac_ptr) if jac_ptr else None,
+                             _vp(stream) if stream else None))
+
+
+def dp_search(plan, T: int):
+    path = np.empty(T, dtype=np.int32)
+    best = C.c_double()
+    mj = C.c_double()
+    _check(_lib.cpf_dp_search(plan, path.ctypes.data_as(_ip), C.byref(best), C.byref(mj)))
+    return path, best.value, mj.value
+
+
+def lm_refine(plan, iters: int, T: int, want_xi: bool = True):
+    xi = np.empty((T, 7)) if want_xi else None
+    rep = cpf_lm_report()
+    st = _lib.cpf_lm_refine(plan, int(iters), _ptr(xi), C.byref(rep))
+    if st != OK:
+        raise CpfError(st, last_error())
+    return xi, _report(rep)
+
+
+def solve_batch(ctx, problems, opts=None):
+    """problems: list of (robot, targets, cand[, node_pen]).  Returns list of dicts."""
+    n = len(problems)
+    keeps, robots, probs = [], (cpf_robot * n)(), (cpf_problem * n)()
+    results = (cpf_result * n)()
+    outs = []
+    for i, pr in enumerate(problems):
+        rb = make_robot(pr[0])
+        pb = make_problem(pr[1], pr[2], pr[3] if len(pr) > 3 else None)
+        keeps += [rb, pb]
+        robots[i] = rb.struct
+        probs[i] = pb.struct
+        T = pb.struct.T
+        xi = np.empty((T, 7))
+        path = np.empty(T, dtype=np.int32)
+        outs.append((xi, path))
+        results[i].xi = _ptr(xi)
+        results[i].path = path.ctypes.data_as(_ip)
+    o = opts if opts is not None else opts_default()
+    _check(_lib.cpf_solve_batch(ctx, n, robots, probs, C.byref(o), results))
+    return [_result(results[i], *outs[i]) for i in range(n)]
+
+
+def _result(r: cpf_result, xi, path) -> dict:
+    return dict(xi=xi, path=path, report=_report(r.report), search_best=r.search_best,
+                search_mjac=r.search_mjac, status=r.status,
+                t_submit_ns=r.t_submit_ns, t_admit_ns=r.t_admit_ns,
+                t_search_done_ns=r.t_search_done_ns, t_done_ns=r.t_done_ns)
+
+
+def submit(ctx, robot, targets, cand, opts=None, node_pen=None) -> int:
+    rb = make_robot(robot)
+    pb = make_problem(targets, cand, node_pen)
+    o = opts if opts is not None else opts_default()
+    t = C.c_uint64()
+    _check(_lib.cpf_submit(ctx, C.byref(rb.struct), C.byref(pb.struct), C.byref(o), C.byref(t)))
+    return int(t.value)
+
+
+def poll(ctx, ticket: int, T: int, timeout_ms: int = -1):
+    """Result dict, or None while the request is pending."""
+    xi = np.empty((T, 7))
+    path = np.empty(T, dtype=np.int32)
+    r = cpf_result()
+    r.xi = _ptr(xi)
+    r.path = path.ctypes.data_as(_ip)
+    st = _check(_lib.cpf_poll(ctx, int(ticket), int(timeout_ms), C.byref(r)))
+    if st == PENDING:
+        return None
+    return _result(r, xi, path)
+
+
+# ---- small object layer -------------------------------------------------------
+
+class Context:
+    def __init__(self, device: int = 0, budget_bytes: int = 0):
+        self.h = ctx_create(device, budget_bytes)
+
+    def close(self):
+        if self.h:
+            ctx_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def bytes_in_use(self) -> int:
+        return ctx_bytes_in_use(self.h)
+
+    def profile(self, enable: bool = True):
+        ctx_profile(self.h, enable)
+
+    def kernel_stats(self, kernel: str):
+        return ctx_kernel_stats(self.h, kernel)
+
+    def plan(self, robot, targets, cand, node_pen=None, opts=None) -> "Plan":
+        return Plan(self, plan_init(self.h, robot, targets, cand, node_pen, opts),
+                    int(np.shape(cand)[1]))
+
+    def fk_batch(self, robot, q: "torch.Tensor", want_jac: bool = False, stream=None):
+        """q: device tensor [7][M] (float32 or float64) -> (pose [12][M], J [42][M] | None)."""
+        assert q.is_cuda and q.dim() == 2 and q.shape[0] == 7 and q.is_contiguous()
+        prec = F64 if q.dtype == torch.float64 else F32
+        M = q.shape[1]
+        pose = torch.empty((12, M), dtype=q.dtype, device=q.device)
+        jac = torch.empty((42, M), dtype=q.dtype, device=q.device) if want_jac else None
+        s = stream if stream is not None else torch.cuda.current_stream(q.device).cuda_stream
+        fk_batch(self.h, robot, M, prec, q.data_ptr(), pose.data_ptr(),
+                 jac.data_ptr() if jac is not None else None, s)
+        return pose, jac
+
+    def solve_batch(self, problems, opts=None):
+        return solve_batch(self.h, problems, opts)
+
+    def submit(self, robot, targets, cand, opts=None, node_pen=None) -> int:
+        return submit(self.h, robot, targets, cand, opts, node_pen)
+
+    def poll(self, ticket: int, T: int, timeout_ms: int = -1):
+        return poll(self.h, ticket, T, timeout_ms)
+
+
+class Plan:
+    def __init__(self, ctx: Context, h, T: int):
+        self.ctx, self.h, self.T = ctx, h, T
+
+    def dp_search(self):
+        return dp_search(self.h, self.T)
+
+    def lm_refine(self, iters: int, want_xi: bool = True):
+        return lm_refine(self.h, iters, self.T, want_xi)
+
+    def free(self):
+        if self.h:
+            plan_free(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.free()

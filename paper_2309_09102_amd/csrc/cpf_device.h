@@ -1,0 +1,186 @@
+// cpf_device.h -- device-side data layout and per-lane math of the CppFlow
+// refinement path (arXiv 2309.09102) on gfx950.
+//
+// Layout of one plan in HBM (all SoA so that consecutive lanes touch
+// consecutive addresses):
+//   cand     float  [T][7][K]   candidate joint values (Sec. III-A), lane = k
+//   extra    double [T][K]      optional caller search cost (Sec. III-B)
+//   bp       uint16 [T][K]      search back-pointers
+//   path     int32  [T]
+//   targets  double [12][T]     target poses (Sec. II): x y z, R row-major
+//   xi, xt   double [7][T]      trajectory master copy and LM trial point
+//   A        double [28][T]     w_p J_t^T J_t, packed lower triangle
+//   g        double [7][T]      gradient of the cost
+//   P        double [49][T]     inverse Schur blocks of the block LDL^T
+//   y, dx, rb double [7][T]     forward sweep, step, refinement residual
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cpf {
+
+constexpr int NJ = 7;         // joints
+constexpr int NTRI = 28;      // packed lower triangle of a 7x7 block
+constexpr int NBLK = 49;      // full 7x7 block
+constexpr int MAX_K = 1024;   // search kernel limit (one lane per destination)
+constexpr int CPF_STATUS_NUMERIC = -6;
+
+struct LMState {
+    double lambda, nu, cost, cost0, grad_inf;
+    double pad0, pad1, pad2;
+    int32_t n_acc, iters_done, status, need_lin;
+    int32_t iters_target, seeded, pad3, pad4;
+};
+
+struct DevPlan {
+    int32_t T, K, has_extra, prec;
+    int32_t refine_steps, pad0, pad1, pad2;
+    double w_p, w_s, lam0, lam_min, lam_max, margin, penalty;
+    // robot in double and float (cos/sin of the twist precomputed on host)
+    double a[8], d[8], ca[8], sa[8], off[8], lo[8], hi[8];
+    float af[8], df[8], caf[8], saf[8], offf[8];
+    const float *cand;
+    const double *extra;
+    uint16_t *bp;
+    int32_t *path;
+    double *dp_out;    // [0] = B*, [1] = mjac of the seed, [2] = end node
+    double *targets;
+    double *xi, *xt, *A, *g, *P, *y, *dx, *rb;
+    LMState *st;
+    double *report;    // [0] max pos err, [1] max rot err, [2] mjac
+};
+
+template <typename S>
+struct RobotT {
+    S a[NJ], d[NJ], ca[NJ], sa[NJ], off[NJ];
+};
+
+template <typename S>
+__device__ __forceinline__ RobotT<S> load_robot(const DevPlan &P);
+
+template <>
+__device__ __forceinline__ RobotT<double> load_robot<double>(const DevPlan &P) {
+    RobotT<double> r;
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+        r.a[i] = P.a[i]; r.d[i] = P.d[i]; r.ca[i] = P.ca[i]; r.sa[i] = P.sa[i]; r.off[i] = P.off[i];
+    }
+    return r;
+}
+
+template <>
+__device__ __forceinline__ RobotT<float> load_robot<float>(const DevPlan &P) {
+    RobotT<float> r;
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+        r.a[i] = P.af[i]; r.d[i] = P.df[i]; r.ca[i] = P.caf[i]; r.sa[i] = P.saf[i]; r.off[i] = P.offf[i];
+    }
+    return r;
+}
+
+__device__ __forceinline__ void dev_sincos(float x, float *s, float *c) { sincosf(x, s, c); }
+__device__ __forceinline__ void dev_sincos(double x, double *s, double *c) { sincos(x, s, c); }
+
+// Kinematic chain of the standard DH convention, kept in registers.
+// Frame columns X, Y, Z and origin p start at the identity; link i maps
+//   X' = c X + s Y,  W = c Y - s X,  Y' = ca W + sa Z,  Z' = ca Z - sa W,
+//   p' = p + a X' + d Z,
+// which is the product with Rz(q) Tz(d) Tx(a) Rx(alpha) written per column.
+// With FRAMES the axis Z and origin p of joint i (before link i) are kept
+// for the geometric Jacobian.
+template <typename S, bool FRAMES>
+__device__ __forceinline__ void chain(const RobotT<S> &rb, const S *q, S X[3], S Y[3], S Z[3],
+                                      S p[3], S Zs[NJ][3], S Os[NJ][3]) {
+    X[0] = 1; X[1] = 0; X[2] = 0;
+    Y[0] = 0; Y[1] = 1; Y[2] = 0;
+    Z[0] = 0; Z[1] = 0; Z[2] = 1;
+    p[0] = 0; p[1] = 0; p[2] = 0;
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+        if (FRAMES) {
+#pragma unroll
+            for (int r = 0; r < 3; ++r) { Zs[i][r] = Z[r]; Os[i][r] = p[r]; }
+        }
+        S s, c;
+        dev_sincos(q[i] + rb.off[i], &s, &c);
+        S nx[3], w[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            nx[r] = c * X[r] + s * Y[r];
+            w[r] = c * Y[r] - s * X[r];
+        }
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            p[r] = p[r] + rb.a[i] * nx[r] + rb.d[i] * Z[r];
+            Y[r] = rb.ca[i] * w[r] + rb.sa[i] * Z[r];
+            Z[r] = rb.ca[i] * Z[r] - rb.sa[i] * w[r];
+            X[r] = nx[r];
+        }
+    }
+}
+
+template <typename S> __device__ __forceinline__ S dev_atan2(S y, S x);
+template <> __device__ __forceinline__ float dev_atan2<float>(float y, float x) { return atan2f(y, x); }
+template <> __device__ __forceinline__ double dev_atan2<double>(double y, double x) { return atan2(y, x); }
+
+// Rotation vector of E (row-major 3x3): angle atan2(|v|, (tr E - 1)/2) with
+// v = vee(E - E^T)/2; series for the small-angle factor, and the axis of the
+// symmetric part near pi.
+template <typename S>
+__device__ __forceinline__ void log_rot(const S E[9], S phi[3]) {
+    const S v0 = S(0.5) * (E[7] - E[5]);
+    const S v1 = S(0.5) * (E[2] - E[6]);
+    const S v2 = S(0.5) * (E[3] - E[1]);
+    const S sn = sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+    const S cs = S(0.5) * (E[0] + E[4] + E[8] - S(1));
+    const S th = dev_atan2<S>(sn, cs);
+    if (th < S(1e-4)) {
+        const S k = S(1) + th * th / S(6);
+        phi[0] = k * v0; phi[1] = k * v1; phi[2] = k * v2;
+        return;
+    }
+    if (th > S(3.14159265358979323846) - S(1e-6)) {
+        S B[3][3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                B[r][c] = S(0.5) * (E[r * 3 + c] + E[c * 3 + r]) - (r == c ? cs : S(0));
+        int i = 0;
+        if (B[1][1] > B[i][i]) i = 1;
+        if (B[2][2] > B[i][i]) i = 2;
+        const S omc = S(1) - cs;
+        const S ui = sqrt(B[i][i] / omc);
+        S u[3];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) u[j] = B[i][j] / (omc * ui);
+        u[i] = ui;
+        if (u[0] * v0 + u[1] * v1 + u[2] * v2 < S(0)) { u[0] = -u[0]; u[1] = -u[1]; u[2] = -u[2]; }
+        phi[0] = th * u[0]; phi[1] = th * u[1]; phi[2] = th * u[2];
+        return;
+    }
+    const S k = th / sn;
+    phi[0] = k * v0; phi[1] = k * v1; phi[2] = k * v2;
+}
+
+// Pose residual r = [p - p*; Log(R R*^T)] of one waypoint; R has columns
+// X, Y, Z.  tgt is x y z then R* row-major (already in S).
+template <typename S>
+__device__ __forceinline__ void pose_residual(const S X[3], const S Y[3], const S Z[3], const S p[3],
+                                              const S tgt[12], S r[6]) {
+    r[0] = p[0] - tgt[0];
+    r[1] = p[1] - tgt[1];
+    r[2] = p[2] - tgt[2];
+    S E[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)   // (R R*^T)_ij = sum_k R_ik R*_jk, R_ik = column k row i
+            E[i * 3 + j] = X[i] * tgt[3 + j * 3 + 0] + Y[i] * tgt[3 + j * 3 + 1] + Z[i] * tgt[3 + j * 3 + 2];
+    log_rot<S>(E, r + 3);
+}
+
+__host__ __device__ constexpr int tri_index(int i, int j) { return i * (i + 1) / 2 + j; }  // i >= j
+
+}  // namespace cpf

@@ -1,0 +1,29 @@
+// cpf_internal.h -- host-side declarations shared by the library's sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cpf_device.h"
+
+namespace cpf {
+
+// Robot as the host keeps it: DH rows plus cos/sin of the twist computed
+// once in double.
+struct HostRobot {
+    double a[NJ], d[NJ], alpha[NJ], ca[NJ], sa[NJ], off[NJ], lo[NJ], hi[NJ];
+};
+
+// Kernel launchers (asynchronous on stream s).
+hipError_t fk_batch_launch(const HostRobot &hr, int64_t M, int prec, const void *q, void *pose,
+                           void *J, hipStream_t s);
+// Search + seed gather for nplans plans (one workgroup each).
+hipError_t dp_launch(const DevPlan *d_plans, int nplans, int maxK, hipStream_t s);
+// `iters` LM iterations for each active plan.  prec: 0 = mixed, 1 = FP64.
+hipError_t lm_launch(const DevPlan *d_plans, int nplans, int prec, int iters, hipStream_t s);
+// Pose error vs targets and mjac of the current trajectory (FP64 FK).
+hipError_t eval_launch(const DevPlan *d_plans, int nplans, hipStream_t s);
+// Initialise LM state of freshly searched plans.
+hipError_t lm_seed_launch(const DevPlan *d_plans, int nplans, int prec, hipStream_t s);
+
+}  // namespace cpf

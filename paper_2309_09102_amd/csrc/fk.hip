@@ -1,0 +1,69 @@
+// fk.hip -- batched forward kinematics and geometric Jacobian (Sec. II; the
+// kinematic Jacobian of Sec. III-C).  One lane per configuration; the chain
+// lives in registers; q, pose and J are SoA so every load and store of a
+// wavefront is one contiguous 256-byte (float) or 512-byte (double) run.
+#include "cpf_device.h"
+#include "cpf_internal.h"
+
+namespace cpf {
+
+template <typename S, bool WANT_J>
+__global__ __launch_bounds__(256) void fk_batch_kernel(RobotT<S> rb, int64_t M,
+                                                       const S *__restrict__ q,
+                                                       S *__restrict__ pose,
+                                                       S *__restrict__ J) {
+    const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (m >= M) return;
+    S qq[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) qq[j] = q[(int64_t)j * M + m];
+    S X[3], Y[3], Z[3], p[3], Zs[NJ][3], Os[NJ][3];
+    chain<S, WANT_J>(rb, qq, X, Y, Z, p, Zs, Os);
+    const S out[12] = {p[0], p[1], p[2], X[0], Y[0], Z[0], X[1], Y[1], Z[1], X[2], Y[2], Z[2]};
+#pragma unroll
+    for (int e = 0; e < 12; ++e) pose[(int64_t)e * M + m] = out[e];
+    if (WANT_J) {
+#pragma unroll
+        for (int i = 0; i < NJ; ++i) {
+            const S dx = p[0] - Os[i][0], dy = p[1] - Os[i][1], dz = p[2] - Os[i][2];
+            const S col[6] = {Zs[i][1] * dz - Zs[i][2] * dy, Zs[i][2] * dx - Zs[i][0] * dz,
+                              Zs[i][0] * dy - Zs[i][1] * dx, Zs[i][0], Zs[i][1], Zs[i][2]};
+#pragma unroll
+            for (int r = 0; r < 6; ++r) J[((int64_t)r * NJ + i) * M + m] = col[r];
+        }
+    }
+}
+
+template <typename S>
+static hipError_t launch_fk(const RobotT<S> &rb, int64_t M, const void *q, void *pose, void *J,
+                            hipStream_t s) {
+    if (M == 0) return hipSuccess;
+    const dim3 grid((unsigned)((M + 255) / 256));
+    if (J)
+        hipLaunchKernelGGL((fk_batch_kernel<S, true>), grid, dim3(256), 0, s, rb, M,
+                           (const S *)q, (S *)pose, (S *)J);
+    else
+        hipLaunchKernelGGL((fk_batch_kernel<S, false>), grid, dim3(256), 0, s, rb, M,
+                           (const S *)q, (S *)pose, (S *)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t fk_batch_launch(const HostRobot &hr, int64_t M, int prec, const void *q, void *pose,
+                           void *J, hipStream_t s) {
+    if (prec == 1) {
+        RobotT<double> rb;
+        for (int i = 0; i < NJ; ++i) {
+            rb.a[i] = hr.a[i]; rb.d[i] = hr.d[i]; rb.ca[i] = hr.ca[i]; rb.sa[i] = hr.sa[i];
+            rb.off[i] = hr.off[i];
+        }
+        return launch_fk<double>(rb, M, q, pose, J, s);
+    }
+    RobotT<float> rb;
+    for (int i = 0; i < NJ; ++i) {
+        rb.a[i] = (float)hr.a[i]; rb.d[i] = (float)hr.d[i]; rb.ca[i] = (float)hr.ca[i];
+        rb.sa[i] = (float)hr.sa[i]; rb.off[i] = (float)hr.off[i];
+    }
+    return launch_fk<float>(rb, M, q, pose, J, s);
+}
+
+}  // namespace cpf

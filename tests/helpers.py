@@ -1,0 +1,31 @@
+"""Shared test helpers: seeded problems with oracle-computed targets."""
+import numpy as np
+
+import oracle
+from paper_2309_09102_amd import synth
+
+
+def with_targets(prob):
+    """Targets FK(q*) from the oracle (float32-rounded by the generator)."""
+    return prob.with_targets(oracle.fk(prob.robot, prob.q_star))
+
+
+def small_problem(seed=11, T=40, K=24, sigma=0.08, frac=0.25, robot_seed=0):
+    return with_targets(synth.make_problem(synth.make_robot(robot_seed), seed=seed, T=T, K=K,
+                                           sigma=sigma, branch_frac=frac))
+
+
+def seed_of(prob, path):
+    return prob.cand[path, np.arange(prob.T)]
+
+
+def parity_metrics(prob, xi_gpu, xi_ref, opts=None):
+    """(max position diff m, max rotation diff rad, relative cost gap) under
+    the oracle's FP64 FK and cost."""
+    o = dict(oracle.DEFAULT_LM)
+    if opts:
+        o.update(opts)
+    ep, er = oracle.pose_compare(prob.robot, xi_gpu, xi_ref)
+    c_gpu = oracle.cost(prob.robot, xi_gpu, prob.targets, o["w_pose"], o["w_smooth"])
+    c_ref = oracle.cost(prob.robot, xi_ref, prob.targets, o["w_pose"], o["w_smooth"])
+    return ep, er, abs(c_gpu - c_ref) / c_ref

@@ -1,0 +1,235 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances (stated for the refinement path): final trajectories agree with
+the oracle's to <= 1e-5 m in position and <= 1e-5 rad in rotation (both
+under the oracle's FP64 FK) and to <= 1e-6 relative cost; the search path
+is index-identical (the search is exact FP64 on both sides, so ties resolve
+identically).  FK: FP64 to 1e-12, FP32 to 2e-6 per component (a 7-link chain
+of unit-scale float operations).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2309_09102_amd import synth
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2309_09102_amd import cpf  # noqa: E402
+
+POS_TOL, ROT_TOL, COST_TOL = 1e-5, 1e-5, 1e-6
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = cpf.Context(0, 8 << 30)
+    yield c
+    c.close()
+
+
+def _fk_ref(robot, qT):
+    pose, J = oracle.fk(robot, qT, jacobian=True)
+    return pose, J
+
+
+@pytest.mark.parametrize("M", [1, 255, 256, 1000, 4097])
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 2e-6)])
+def test_fk_batch_matches_oracle(ctx, M, dtype, tol):
+    rb = synth.make_robot(3)
+    q = synth.random_configs(M, M, rb)
+    qd = torch.tensor(q.T.copy(), dtype=dtype, device="cuda")
+    pose, jac = ctx.fk_batch(rb, qd, want_jac=True)
+    torch.cuda.synchronize()
+    pose = pose.double().cpu().numpy().T
+    jac = jac.double().cpu().numpy().T.reshape(M, 6, 7)
+    pr, Jr = _fk_ref(rb, q)
+    np.testing.assert_allclose(pose, pr, atol=tol, rtol=0)
+    np.testing.assert_allclose(jac, Jr, atol=tol, rtol=0)
+
+
+def test_fk_batch_candidates_full_size(ctx):
+    """K*T = 76,800 configurations of the T=300, K=256 workload."""
+    p = synth.config2()
+    q = p.cand.reshape(-1, 7)
+    qd = torch.tensor(q.T.copy(), dtype=torch.float32, device="cuda")
+    pose, _ = ctx.fk_batch(p.robot, qd)
+    torch.cuda.synchronize()
+    pose = pose.double().cpu().numpy().T
+    idx = np.random.default_rng(0).choice(q.shape[0], 2000, replace=False)
+    np.testing.assert_allclose(pose[idx], oracle.fk(p.robot, q[idx]), atol=2e-6, rtol=0)
+
+
+def test_fk_batch_empty_and_errors(ctx):
+    rb = synth.make_robot(0)
+    q = torch.zeros((7, 0), dtype=torch.float32, device="cuda")
+    pose, _ = ctx.fk_batch(rb, q)
+    assert pose.shape == (12, 0)
+    bad = synth.Robot(a=np.zeros(6), d=np.zeros(6), alpha=np.zeros(6), theta_off=np.zeros(6),
+                      q_lo=-np.ones(6), q_hi=np.ones(6))
+    with pytest.raises(cpf.CpfError) as ei:
+        cpf.fk_batch(ctx.h, bad, 1, cpf.F32, 1, 1)
+    assert ei.value.status == cpf.E_UNSUPPORTED
+
+
+# ---- search --------------------------------------------------------------------
+
+SEARCH_CASES = [
+    dict(seed=1, T=1, K=5),
+    dict(seed=2, T=7, K=1),
+    dict(seed=3, T=2, K=3),
+    dict(seed=4, T=33, K=65),       # ragged K
+    dict(seed=5, T=50, K=16),
+    dict(seed=6, T=120, K=300),     # K above 256: two lanes per part, ragged
+    dict(seed=7, T=64, K=1024),     # maximum K
+]
+
+
+@pytest.mark.parametrize("case", SEARCH_CASES, ids=lambda c: f"T{c['T']}K{c['K']}")
+def test_dp_search_index_identical(ctx, case):
+    p = H.small_problem(seed=case["seed"], T=case["T"], K=case["K"])
+    path_ref, best_ref, _, _ = oracle.dp(p.cand, p.robot)
+    with ctx.plan(p.robot, p.targets, p.cand) as plan:
+        path, best, mj = plan.dp_search()
+    assert np.array_equal(path, path_ref)
+    assert best == best_ref
+    assert mj == oracle.mjac(H.seed_of(p, path_ref))
+
+
+def test_dp_search_with_node_penalty_and_ties(ctx):
+    p = H.small_problem(seed=9, T=30, K=40, sigma=0.0)     # identical candidates: all ties
+    extra = np.zeros((p.T, p.K))
+    extra[:, :3] = 0.25
+    extra[10, 5] = 100.0
+    path_ref, best_ref, _, _ = oracle.dp(p.cand, p.robot, extra=extra)
+    with ctx.plan(p.robot, p.targets, p.cand, node_pen=extra) as plan:
+        path, best, _ = plan.dp_search()
+    assert np.array_equal(path, path_ref) and best == best_ref
+
+
+def test_dp_search_config2_full_size(ctx):
+    p = H.with_targets(synth.config2())
+    path_ref, best_ref, _, _ = oracle.dp(p.cand, p.robot)
+    with ctx.plan(p.robot, p.targets, p.cand) as plan:
+        path, best, _ = plan.dp_search()
+    assert np.array_equal(path, path_ref) and best == best_ref
+
+
+# ---- LM ------------------------------------------------------------------------
+
+def _lm_case(ctx, p, iters, prec, opts=None):
+    o = dict(opts or {})
+    copts = cpf.make_opts(prec=prec, **o)
+    path_ref, _, _, _ = oracle.dp(p.cand, p.robot)
+    ref = oracle.lm(p.robot, H.seed_of(p, path_ref), p.targets, iters, opts=o)
+    with ctx.plan(p.robot, p.targets, p.cand, opts=copts) as plan:
+        path, _, _ = plan.dp_search()
+        xi, rep = plan.lm_refine(iters)
+    assert np.array_equal(path, path_ref)
+    return xi, rep, ref
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_lm_small_matches_oracle(ctx, prec):
+    p = H.small_problem(seed=21, T=150, K=32)
+    xi, rep, ref = _lm_case(ctx, p, 50, prec)
+    ep, er, ec = H.parity_metrics(p, xi, ref["xi"])
+    assert ep <= POS_TOL and er <= ROT_TOL and ec <= COST_TOL, (ep, er, ec)
+    assert rep["iters_done"] == 50
+    assert rep["cost"] <= rep["cost0"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_lm_config2_full_size(ctx, prec):
+    p = H.with_targets(synth.config2())
+    xi, rep, ref = _lm_case(ctx, p, 50, prec)
+    ep, er, ec = H.parity_metrics(p, xi, ref["xi"])
+    print(f"config2 {prec}: pos {ep:.3e} m rot {er:.3e} rad cost {ec:.3e}")
+    assert ep <= POS_TOL and er <= ROT_TOL and ec <= COST_TOL, (ep, er, ec)
+
+
+@pytest.mark.parametrize("T", [1, 2, 3])
+def test_lm_tiny_paths(ctx, T):
+    p = H.small_problem(seed=30 + T, T=T, K=4)
+    xi, rep, ref = _lm_case(ctx, p, 10, "fp64")
+    ep, er, ec = H.parity_metrics(p, xi, ref["xi"])
+    assert ep <= POS_TOL and er <= ROT_TOL and ec <= COST_TOL, (ep, er, ec)
+
+
+def test_lm_without_smoothness_is_per_waypoint(ctx):
+    p = H.small_problem(seed=40, T=20, K=8)
+    xi, rep, ref = _lm_case(ctx, p, 15, "fp64", opts=dict(w_smooth=0.0))
+    ep, er, _ = H.parity_metrics(p, xi, ref["xi"], opts=dict(w_smooth=0.0))
+    assert ep <= POS_TOL and er <= ROT_TOL
+
+
+def test_lm_resumable_bitwise(ctx):
+    p = H.small_problem(seed=50, T=90, K=16)
+    with ctx.plan(p.robot, p.targets, p.cand) as a, ctx.plan(p.robot, p.targets, p.cand) as b:
+        a.dp_search()
+        b.dp_search()
+        xa, ra = a.lm_refine(30)
+        b.lm_refine(12)
+        xb, rb = b.lm_refine(18)
+    assert np.array_equal(xa, xb) and ra["cost"] == rb["cost"] and rb["iters_done"] == 30
+
+
+def test_lm_before_search_is_state_error(ctx):
+    p = H.small_problem(seed=51, T=10, K=4)
+    with ctx.plan(p.robot, p.targets, p.cand) as plan:
+        with pytest.raises(cpf.CpfError) as ei:
+            plan.lm_refine(1)
+    assert ei.value.status == cpf.E_STATE
+
+
+def test_bad_inputs_rejected(ctx):
+    p = H.small_problem(seed=52, T=10, K=4)
+    cand = p.cand.copy()
+    cand[0, 0, 0] = np.nan
+    with pytest.raises(cpf.CpfError) as ei:
+        ctx.plan(p.robot, p.targets, cand)
+    assert ei.value.status == cpf.E_ARG
+    small = cpf.Context(0, 1024)
+    try:
+        with pytest.raises(cpf.CpfError) as ei:
+            small.plan(p.robot, p.targets, p.cand)
+        assert ei.value.status == cpf.E_NOMEM
+    finally:
+        small.close()
+
+
+# ---- batching invariance -------------------------------------------------------
+
+def test_solve_batch_equals_single(ctx):
+    probs = [H.small_problem(seed=60 + i, T=40 + 17 * i, K=16 + 9 * i, robot_seed=i)
+             for i in range(5)]
+    opts = cpf.make_opts(iters=20)
+    res = ctx.solve_batch([(p.robot, p.targets, p.cand) for p in probs], opts)
+    for p, r in zip(probs, res):
+        with ctx.plan(p.robot, p.targets, p.cand, opts=opts) as plan:
+            path, best, _ = plan.dp_search()
+            xi, rep = plan.lm_refine(20)
+        assert r["status"] == 0
+        assert np.array_equal(r["path"], path) and r["search_best"] == best
+        assert np.array_equal(r["xi"], xi) and r["report"]["cost"] == rep["cost"]
+
+
+def test_serving_results_equal_alone(ctx):
+    probs = [H.small_problem(seed=70 + i, T=30 + 11 * i, K=12 + 5 * i) for i in range(6)]
+    opts = cpf.make_opts(iters=12)
+    tickets = [ctx.submit(p.robot, p.targets, p.cand, opts) for p in probs]
+    outs = [ctx.poll(t, p.T, timeout_ms=60000) for t, p in zip(tickets, probs)]
+    for p, r in zip(probs, outs):
+        assert r is not None and r["status"] == 0
+        with ctx.plan(p.robot, p.targets, p.cand, opts=opts) as plan:
+            plan.dp_search()
+            xi, rep = plan.lm_refine(12)
+        assert np.array_equal(r["xi"], xi)
+        assert r["t_done_ns"] >= r["t_search_done_ns"] >= r["t_admit_ns"] >= r["t_submit_ns"]
+    with pytest.raises(cpf.CpfError) as ei:
+        ctx.poll(tickets[0], probs[0].T, timeout_ms=0)
+    assert ei.value.status == cpf.E_NOTFOUND
