@@ -180,6 +180,11 @@ cpf_status cpf_solve_batch(cpf_ctx *ctx, int32_t nplans, const cpf_robot *robots
                            const cpf_problem *probs, const cpf_opts *opts,
                            cpf_result *results);
 
+/* Server shape, before the first cpf_submit: `slots` requests resident on the
+ * device at once (default 256) and LM iterations per tick (default 10).
+ * CPF_E_STATE once the server runs. */
+cpf_status cpf_ctx_config(cpf_ctx *ctx, int32_t slots, int32_t iters_per_tick);
+
 /* Serving: copy the request, queue it, return a ticket at once.  The server
  * thread admits queued requests while their device bytes fit the budget,
  * runs their searches, and advances every admitted request by LM iterations

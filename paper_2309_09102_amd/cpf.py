@@ -87,18 +87,19 @@ _lib.cpf_solve_batch.argtypes = [_vp, C.c_int32, C.POINTER(cpf_robot), C.POINTER
 _lib.cpf_submit.argtypes = [_vp, C.POINTER(cpf_robot), C.POINTER(cpf_problem),
                             C.POINTER(cpf_opts), C.POINTER(C.c_uint64)]
 _lib.cpf_poll.argtypes = [_vp, C.c_uint64, C.c_int32, C.POINTER(cpf_result)]
+_lib.cpf_ctx_config.argtypes = [_vp, C.c_int32, C.c_int32]
 _lib.cpf_ctx_profile.argtypes = [_vp, C.c_int32]
 _lib.cpf_ctx_kernel_stats.argtypes = [_vp, C.c_char_p, C.POINTER(C.c_double),
                                       C.POINTER(C.c_int64)]
 for _f in ("cpf_ctx_create", "cpf_plan_init", "cpf_fk_batch", "cpf_dp_search", "cpf_lm_refine",
            "cpf_solve_batch", "cpf_submit", "cpf_poll", "cpf_ctx_profile",
-           "cpf_ctx_kernel_stats"):
+           "cpf_ctx_kernel_stats", "cpf_ctx_config"):
     getattr(_lib, _f).restype = C.c_int
 
 EXPORTS = ("cpf_opts_default", "cpf_last_error", "cpf_ctx_create", "cpf_ctx_destroy",
            "cpf_ctx_bytes_in_use", "cpf_plan_init", "cpf_plan_free", "cpf_fk_batch",
            "cpf_dp_search", "cpf_lm_refine", "cpf_solve_batch", "cpf_submit", "cpf_poll",
-           "cpf_ctx_profile", "cpf_ctx_kernel_stats")
+           "cpf_ctx_profile", "cpf_ctx_kernel_stats", "cpf_ctx_config")
 
 
 def last_error() -> str:
@@ -178,6 +179,10 @@ def ctx_destroy(ctx):
 
 def ctx_bytes_in_use(ctx) -> int:
     return int(_lib.cpf_ctx_bytes_in_use(ctx))
+
+
+def ctx_config(ctx, slots: int, iters_per_tick: int):
+    _check(_lib.cpf_ctx_config(ctx, int(slots), int(iters_per_tick)))
 
 
 def ctx_profile(ctx, enable: bool):
@@ -301,6 +306,9 @@ class Context:
 
     def bytes_in_use(self) -> int:
         return ctx_bytes_in_use(self.h)
+
+    def config(self, slots: int = 256, iters_per_tick: int = 10):
+        ctx_config(self.h, slots, iters_per_tick)
 
     def profile(self, enable: bool = True):
         ctx_profile(self.h, enable)

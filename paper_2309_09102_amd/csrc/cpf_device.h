@@ -12,6 +12,7 @@
 //   A        double [28][T]     w_p J_t^T J_t, packed lower triangle
 //   g        double [7][T]      gradient of the cost
 //   P        double [49][T]     inverse Schur blocks of the block LDL^T
+//   F        double [49][T]     coupling of each block to the previous chunk's end
 //   y, dx, rb double [7][T]     forward sweep, step, refinement residual
 #pragma once
 
@@ -30,7 +31,7 @@ struct LMState {
     double lambda, nu, cost, cost0, grad_inf;
     double pad0, pad1, pad2;
     int32_t n_acc, iters_done, status, need_lin;
-    int32_t iters_target, seeded, pad3, pad4;
+    int32_t iters_target, seeded, reported, pad4;
 };
 
 struct DevPlan {
@@ -46,7 +47,7 @@ struct DevPlan {
     int32_t *path;
     double *dp_out;    // [0] = B*, [1] = mjac of the seed, [2] = end node
     double *targets;
-    double *xi, *xt, *A, *g, *P, *y, *dx, *rb;
+    double *xi, *xt, *A, *g, *P, *F, *y, *dx, *rb;
     LMState *st;
     double *report;    // [0] max pos err, [1] max rot err, [2] mjac
 };

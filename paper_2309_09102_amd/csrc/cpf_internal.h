@@ -19,11 +19,12 @@ hipError_t fk_batch_launch(const HostRobot &hr, int64_t M, int prec, const void 
                            void *J, hipStream_t s);
 // Search + seed gather for nplans plans (one workgroup each).
 hipError_t dp_launch(const DevPlan *d_plans, int nplans, int maxK, hipStream_t s);
-// `iters` LM iterations for each active plan.  prec: 0 = mixed, 1 = FP64.
+// Up to `iters` LM iterations for each plan of precision prec (0 = mixed,
+// 1 = FP64); empty slots (T = 0) and plans of the other precision are skipped.
 hipError_t lm_launch(const DevPlan *d_plans, int nplans, int prec, int iters, hipStream_t s);
-// Pose error vs targets and mjac of the current trajectory (FP64 FK).
-hipError_t eval_launch(const DevPlan *d_plans, int nplans, hipStream_t s);
-// Initialise LM state of freshly searched plans.
-hipError_t lm_seed_launch(const DevPlan *d_plans, int nplans, int prec, hipStream_t s);
+// Pose error vs targets and mjac of the current trajectory (FP64 FK).  With
+// only_finished, only plans that reached their iteration target (or failed)
+// and have not been reported yet.
+hipError_t eval_launch(const DevPlan *d_plans, int nplans, int only_finished, hipStream_t s);
 
 }  // namespace cpf

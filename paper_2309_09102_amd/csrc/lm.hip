@@ -23,7 +23,7 @@
 
 namespace cpf {
 
-constexpr int LM_BS = 256;
+constexpr int LM_BS = 512;
 
 __device__ __forceinline__ double block_sum(double v, double *red) {
     const int tid = threadIdx.x;
@@ -246,6 +246,187 @@ __device__ bool factor_and_solve(const DevPlan &P, int T, double lam, int lane) 
     return ok;
 }
 
+// ---------------------------------------------------------------------------
+// Partitioned solve.  The waypoints are split into C contiguous chunks
+// [s_c, e_c], one per wavefront.  Within a chunk, block Gaussian elimination
+// from s_c onwards treats the previous chunk's last block z_{c-1} = x_{e_{c-1}}
+// as an external unknown:
+//   S_t x_t - w x_{t+1} = y_t + F_t z_{c-1},  S_t = D_t - w^2 P_{t-1},
+//   P_t = S_t^{-1},  y_t = b_t + w P_{t-1} y_{t-1},  F_t = w P_{t-1} F_{t-1},
+//   F_{s_c} = w I (zero for the first chunk).
+// Back-substituting from the chunk's last block z_c gives, at its first block,
+//   x_{s_c} = a_c + G_c z_{c-1} + (F_{e_c}^T / w) z_c,
+//   a: a_t = P_t (y_t + w a_{t+1}),  G: G_t = P_t (F_t + w G_{t+1}),  a_e = G_e = 0.
+// The last rows of the chunks then form a symmetric block-tridiagonal system
+// in z_0 .. z_{C-1} (the Schur complement on the chunk ends):
+//   M_c = S_{e_c} - w G_{c+1},  sub-diagonal -F_{e_c},  r_c = y_{e_c} + w a_{c+1},
+// solved by one wavefront with the same LDL^T sweep, after which every chunk
+// recovers its interior: x_t = P_t (y_t + F_t z_{c-1} + w x_{t+1}).
+// ---------------------------------------------------------------------------
+
+constexpr int MAX_CHUNKS = LM_BS / 64;
+
+struct ChunkShared {
+    double S[MAX_CHUNKS][NBLK];    // S_{e_c}, then M_c, then Pi_c = Sigma_c^{-1}
+    double G[MAX_CHUNKS][NBLK];    // G_c at the chunk's first block
+    double y[MAX_CHUNKS][8];       // y_{e_c}, then r_c, then rho_c
+    double a[MAX_CHUNKS][8];       // a_c at the chunk's first block
+    double z[MAX_CHUNKS][8];       // chunk-end solution z_c
+    int bad;
+};
+
+__device__ __forceinline__ double matmul7(double A, double B, int i, int j) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < NJ; ++k) s += __shfl(A, i * NJ + k) * __shfl(B, k * NJ + j);
+    return s;
+}
+
+__device__ __forceinline__ void chunk_bounds(int T, int C, int c, int &s, int &e) {
+    s = (int)(((long long)c * T) / C);
+    e = (int)(((long long)(c + 1) * T) / C) - 1;
+}
+
+// Factorisation of the partitioned system (all waves; wave c owns chunk c).
+// Stores P_t (t < e_c) and F_t for every t, and Pi_c for the chunk ends.
+// Returns false on a non-positive pivot (flag in sh.bad).
+__device__ bool chunk_factor(const DevPlan &P, int T, int C, double lam, ChunkShared &sh) {
+    const int lane = threadIdx.x & 63, c = threadIdx.x >> 6;
+    const int i = lane < NBLK ? lane / NJ : 0, j = lane < NBLK ? lane % NJ : 0;
+    const int l = lane < NBLK ? lane : 0;
+    const double w = P.w_s, w2 = w * w;
+    if (threadIdx.x == 0) sh.bad = 0;
+    __syncthreads();
+    bool ok = true;
+    if (c < C) {
+        int s, e;
+        chunk_bounds(T, C, c, s, e);
+        double pprev = 0.0, fprev = 0.0;
+        for (int t = s; t <= e; ++t) {
+            const double d = d_elem(P, T, t, i, j, lam);
+            const double S = (t > s) ? d - w2 * pprev : d;
+            double F;
+            if (t == s) F = (c > 0 && i == j) ? w : 0.0;
+            else F = w * matmul7(pprev, fprev, i, j);
+            if (lane < NBLK) P.F[(size_t)lane * T + t] = F;
+            if (t == e) {
+                if (lane < NBLK) sh.S[c][lane] = S;
+            } else {
+                const double pinv = gj_inverse7(S, i, j, ok);
+                if (lane < NBLK) P.P[(size_t)lane * T + t] = pinv;
+                pprev = pinv;
+            }
+            fprev = F;
+        }
+        // G at the first block: G_t = P_t (F_t + w G_{t+1}), G_e = 0.
+        double G = 0.0;
+        for (int t = e - 1; t >= s; --t) {
+            const double pm = P.P[(size_t)l * T + t];
+            const double f = P.F[(size_t)l * T + t];
+            G = matmul7(pm, f + w * G, i, j);
+        }
+        if (lane < NBLK) sh.G[c][lane] = G;
+        if (!ok) sh.bad = 1;
+    }
+    __syncthreads();
+    // Reduced system on the chunk ends (wave 0).
+    if (c == 0) {
+        double pi_prev = 0.0;
+        for (int cc = 0; cc < C; ++cc) {
+            int s, e;
+            chunk_bounds(T, C, cc, s, e);
+            double M = sh.S[cc][l];
+            if (cc + 1 < C) M -= w * sh.G[cc + 1][l];
+            if (cc > 0) {
+                const double Fe = P.F[(size_t)l * T + e];
+                const double FePi = matmul7(Fe, pi_prev, i, j);
+                M -= matmul7(FePi, __shfl(Fe, j * NJ + i), i, j);   // F Pi F^T
+            }
+            const double pi = gj_inverse7(M, i, j, ok);
+            if (lane < NBLK) sh.S[cc][lane] = pi;
+            pi_prev = pi;
+        }
+        if (!ok) sh.bad = 1;
+    }
+    __syncthreads();
+    return sh.bad == 0;
+}
+
+// Solve with the partitioned factors for right-hand side sign*rhs ([7][T]);
+// writes out ([7][T], may alias rhs).  All waves.
+__device__ void chunk_substitute(const DevPlan &P, int T, int C, const double *rhs, double sign,
+                                 double *out, ChunkShared &sh) {
+    const int lane = threadIdx.x & 63, c = threadIdx.x >> 6;
+    const int j = lane < NBLK ? lane % NJ : 0;
+    const int l = lane < NBLK ? lane : 0;
+    const double w = P.w_s;
+    if (c < C) {
+        int s, e;
+        chunk_bounds(T, C, c, s, e);
+        // forward: y_t = b_t + w P_{t-1} y_{t-1} within the chunk
+        double yprev = 0.0;
+        for (int t = s; t <= e; ++t) {
+            double y = lane < NJ ? sign * rhs[(size_t)lane * T + t] : 0.0;
+            if (t > s) y += w * matvec7(P.P[(size_t)l * T + t - 1], yprev, lane, j);
+            if (lane < NJ) P.y[(size_t)lane * T + t] = y;
+            yprev = y;
+        }
+        if (lane < NJ) sh.y[c][lane] = yprev;
+        // backward: a_t = P_t (y_t + w a_{t+1}), a_e = 0
+        double a = 0.0;
+        for (int t = e - 1; t >= s; --t) {
+            const double v = (lane < NJ ? P.y[(size_t)lane * T + t] : 0.0) + w * a;
+            a = matvec7(P.P[(size_t)l * T + t], v, lane, j);
+        }
+        if (lane < NJ) sh.a[c][lane] = a;
+    }
+    __syncthreads();
+    if (c == 0) {
+        // rho_c = r_c + F_{e_c} Pi_{c-1} rho_{c-1};  z_c = Pi_c (rho_c + F_{e_{c+1}}^T z_{c+1})
+        double rho_prev = 0.0;
+        for (int cc = 0; cc < C; ++cc) {
+            int s, e;
+            chunk_bounds(T, C, cc, s, e);
+            double r = lane < NJ ? sh.y[cc][lane] : 0.0;
+            if (cc + 1 < C && lane < NJ) r += w * sh.a[cc + 1][lane];
+            if (cc > 0) {
+                const double v = matvec7(sh.S[cc - 1][l], rho_prev, lane, j);
+                r += matvec7(P.F[(size_t)l * T + e], v, lane, j);
+            }
+            if (lane < NJ) sh.y[cc][lane] = r;
+            rho_prev = r;
+        }
+        double znext = 0.0;
+        for (int cc = C - 1; cc >= 0; --cc) {
+            double v = lane < NJ ? sh.y[cc][lane] : 0.0;
+            if (cc + 1 < C) {
+                int s1, e1;
+                chunk_bounds(T, C, cc + 1, s1, e1);
+                const double Fe = P.F[(size_t)l * T + e1];
+                v += matvec7(__shfl(Fe, j * NJ + (lane < NBLK ? lane / NJ : 0)), znext, lane, j);
+            }
+            const double z = matvec7(sh.S[cc][l], v, lane, j);
+            if (lane < NJ) sh.z[cc][lane] = z;
+            znext = z;
+        }
+    }
+    __syncthreads();
+    if (c < C) {
+        int s, e;
+        chunk_bounds(T, C, c, s, e);
+        const double zl = (c > 0 && lane < NJ) ? sh.z[c - 1][lane] : 0.0;
+        double x = lane < NJ ? sh.z[c][lane] : 0.0;
+        if (lane < NJ) out[(size_t)lane * T + e] = x;
+        for (int t = e - 1; t >= s; --t) {
+            double v = (lane < NJ ? P.y[(size_t)lane * T + t] : 0.0) + w * x;
+            if (c > 0) v += matvec7(P.F[(size_t)l * T + t], zl, lane, j);
+            x = matvec7(P.P[(size_t)l * T + t], v, lane, j);
+            if (lane < NJ) out[(size_t)lane * T + t] = x;
+        }
+    }
+    __syncthreads();
+}
+
 // rb_t = -g_t - (H dx)_t  for every waypoint (all lanes).
 __device__ void refine_residual(const DevPlan &P, int T, double lam) {
     const double w = P.w_s;
@@ -267,9 +448,14 @@ __device__ void refine_residual(const DevPlan &P, int T, double lam) {
 
 template <typename S>
 __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ plans, int iters) {
+    constexpr int PREC = sizeof(S) == sizeof(double) ? 1 : 0;
     const DevPlan &P = plans[blockIdx.x];
     const int T = P.T;
-    if (T <= 0) return;
+    if (T <= 0 || P.prec != PREC) return;   // empty slot or the other precision's plan
+    {
+        const LMState *s0 = P.st;
+        if (s0->seeded && s0->iters_target > 0 && s0->iters_done >= s0->iters_target) return;
+    }
     __shared__ double red[LM_BS];
     __shared__ double sh_lam, sh_nu, sh_cost;
     __shared__ int sh_flags[4];   // 0 need_lin, 1 status, 2 accept, 3 pivot failure
@@ -318,6 +504,10 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
 
     const int lane = tid & 63;
     const bool wave0 = tid < 64;
+    __shared__ ChunkShared chs;
+    // Chunks of at least 8 waypoints, one per wavefront; short paths use the
+    // single-wavefront sweep.
+    const int C = min(MAX_CHUNKS, T / 8) >= 2 ? min(MAX_CHUNKS, T / 8) : 1;
     for (int it = 0; it < n_it; ++it) {
         if (sh_flags[1] != 0) break;
         const double lam = sh_lam;
@@ -327,7 +517,11 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
             if (tid == 0) st->grad_inf = gmax;
         }
         __syncthreads();
-        if (wave0) {
+        if (C > 1) {
+            const bool ok = chunk_factor(P, T, C, lam, chs);
+            if (tid == 0) sh_flags[3] = ok ? 0 : 1;
+            if (ok) chunk_substitute(P, T, C, P.g, -1.0, P.dx, chs);   // right-hand side -g
+        } else if (wave0) {
             const bool ok = factor_and_solve(P, T, lam, lane);
             if (lane == 0) sh_flags[3] = ok ? 0 : 1;
         }
@@ -340,8 +534,10 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
         for (int rs = 0; rs < P.refine_steps; ++rs) {
             refine_residual(P, T, lam);
             __syncthreads();
-            if (wave0) {
-                substitute(P, T, P.rb, 1.0, P.rb, lane);   // correction in place
+            if (C > 1) {
+                chunk_substitute(P, T, C, P.rb, 1.0, P.rb, chs);   // correction in place
+            } else if (wave0) {
+                substitute(P, T, P.rb, 1.0, P.rb, lane);
             }
             __syncthreads();
             for (int t = tid; t < T; t += LM_BS)
@@ -408,10 +604,17 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
 }
 
 // Report: FP64 pose error of xi vs the targets and mjac (Sec. II metrics).
-__global__ __launch_bounds__(LM_BS) void eval_kernel(const DevPlan *__restrict__ plans) {
+__global__ __launch_bounds__(LM_BS) void eval_kernel(const DevPlan *__restrict__ plans,
+                                                     int only_finished) {
     const DevPlan &P = plans[blockIdx.x];
     const int T = P.T;
     if (T <= 0) return;
+    if (only_finished) {
+        const LMState *s0 = P.st;
+        const bool finished = s0->status != 0 ||
+                              (s0->iters_target > 0 && s0->iters_done >= s0->iters_target);
+        if (!finished || s0->reported) return;
+    }
     __shared__ double red[LM_BS];
     const RobotT<double> rb = load_robot<double>(P);
     double ep = 0.0, er = 0.0, mj = 0.0;
@@ -445,6 +648,7 @@ __global__ __launch_bounds__(LM_BS) void eval_kernel(const DevPlan *__restrict__
         P.report[0] = ep;
         P.report[1] = er;
         P.report[2] = mj;
+        if (only_finished) P.st->reported = 1;
     }
 }
 
@@ -457,9 +661,9 @@ hipError_t lm_launch(const DevPlan *d_plans, int nplans, int prec, int iters, hi
     return hipGetLastError();
 }
 
-hipError_t eval_launch(const DevPlan *d_plans, int nplans, hipStream_t s) {
+hipError_t eval_launch(const DevPlan *d_plans, int nplans, int only_finished, hipStream_t s) {
     if (nplans <= 0) return hipSuccess;
-    hipLaunchKernelGGL(eval_kernel, dim3(nplans), dim3(LM_BS), 0, s, d_plans);
+    hipLaunchKernelGGL(eval_kernel, dim3(nplans), dim3(LM_BS), 0, s, d_plans, only_finished);
     return hipGetLastError();
 }
 

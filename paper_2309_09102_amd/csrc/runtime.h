@@ -1,0 +1,145 @@
+// runtime.h -- host-side runtime objects shared by capi.cpp and serve.cpp:
+// the context (device, budget, streams, server state), plans and their
+// device arenas, error reporting and kernel timing.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/cpf.h"
+#include "cpf_device.h"
+#include "cpf_internal.h"
+
+// Best-effort cleanup calls whose status cannot be reported.
+#define HIP_IGNORE(expr) ((void)(expr))
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return cpf::fail(CPF_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)
+
+namespace cpf {
+
+cpf_status fail(cpf_status st, const char *fmt, ...);
+int64_t now_ns();
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Byte offsets of one plan's buffers inside its arena.
+struct Layout {
+    size_t cand, extra, bp, path, dp_out, targets, xi, xt, A, g, P, F, y, dx, rb, st, report, total;
+};
+Layout make_layout(int T, int K, bool extra);
+uint64_t plan_bytes(int T, int K, bool extra);
+
+cpf_status check_robot(const cpf_robot *r, HostRobot *out);
+cpf_status check_problem(const cpf_problem *p);
+cpf_status check_opts(const cpf_opts *o);
+
+enum { KIND_FK = 0, KIND_DP = 1, KIND_LM = 2, KIND_EVAL = 3 };
+
+struct Request;
+struct Server;
+
+}  // namespace cpf
+
+struct cpf_ctx {
+    int device = 0;
+    uint64_t budget = 0;
+    std::atomic<uint64_t> used{0};
+    hipStream_t stream = nullptr;   // synchronous plan calls
+    // serving
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<cpf::Request *> pending;
+    std::map<uint64_t, cpf::Request *> tickets;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    cpf::Server *server = nullptr;
+    std::thread server_thread;
+    int32_t slots = 256;           // concurrent requests on the device
+    int32_t iters_per_tick = 10;   // LM iterations per graph replay
+    // kernel timing
+    std::mutex prof_mu;
+    std::atomic<bool> prof{false};
+    struct Ev {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Ev> events;
+    double prof_ms[4] = {0, 0, 0, 0};
+    int64_t prof_n[4] = {0, 0, 0, 0};
+
+    bool reserve(uint64_t b) {
+        uint64_t cur = used.load();
+        while (true) {
+            if (cur + b > budget) return false;
+            if (used.compare_exchange_weak(cur, cur + b)) return true;
+        }
+    }
+    void release(uint64_t b) { used.fetch_sub(b); }
+};
+
+struct cpf_plan {
+    cpf_ctx *ctx = nullptr;
+    int T = 0, K = 0;
+    cpf::HostRobot robot{};
+    cpf_opts opts{};
+    cpf::Layout L{};
+    char *arena = nullptr;
+    uint64_t bytes = 0;
+    cpf::DevPlan desc{};
+    cpf::DevPlan *d_desc = nullptr;
+    bool searched = false;
+};
+
+namespace cpf {
+
+// Launch through `launch`; with profiling on, bracket it with events on s.
+template <class F>
+hipError_t timed(cpf_ctx *ctx, int kind, hipStream_t s, F &&launch) {
+    if (!ctx->prof.load()) return launch();
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e == hipSuccess) e = hipEventRecord(a, s);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, s);
+    std::lock_guard<std::mutex> lk(ctx->prof_mu);
+    ctx->events.push_back({kind, a, b});
+    return e;
+}
+
+// Allocate and upload one plan on stream s (asynchronous; `staging` must stay
+// alive until s is synchronised).  iters_target = 0 lets each lm_refine call
+// run the iterations it asks for.
+cpf_status plan_create(cpf_ctx *ctx, const HostRobot &hr, const cpf_problem *prob,
+                       const cpf_opts *opts, int32_t iters_target, hipStream_t s,
+                       std::vector<char> &staging, cpf_plan **out);
+void plan_destroy(cpf_plan *p);
+
+struct PlanReadback {
+    LMState st;
+    double report[8];
+    double dp_out[8];
+};
+// Read state / report / search output and optionally xi ([T][7]) and path.
+cpf_status read_plan(cpf_plan *p, hipStream_t s, const LMState *state_dev, PlanReadback *rb,
+                     double *xi_out, int32_t *path_out);
+void fill_report(const PlanReadback &rb, cpf_lm_report *rep);
+
+// Server lifetime (serve.cpp).
+void server_stop_and_join(cpf_ctx *ctx);
+
+}  // namespace cpf
