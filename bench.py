@@ -46,7 +46,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--iters", type=int, default=50)
-    ap.add_argument("--workload", default="T300_K256", choices=["T300_K256", "T1000_K512"])
+    ap.add_argument("--workload", default="T300_K256",
+                    choices=["T300_K256", "T1000_K512", "batch64", "serve"],
+                    help="T300_K256: the headline single-request line; the others are the "
+                         "additional measured workloads in paper_2309_09102_amd/workloads.py")
+    ap.add_argument("--duration", type=float, default=10.0, help="serve: stream length (s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     return ap.parse_args()
@@ -60,11 +64,22 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.workload != "T300_K256":
+        from paper_2309_09102_amd import workloads
+        if args.workload == "T1000_K512":
+            out = workloads.run_precision(iters=args.iters)
+        elif args.workload == "batch64":
+            out = workloads.run_batch64(iters=30)
+        else:
+            out = workloads.run_serve(duration_s=args.duration)
+        print(json.dumps(out))
+        return
+
     import torch
     from paper_2309_09102_amd import cpf, synth
 
     dev = torch.device("cuda:0")
-    prob = synth.config2() if args.workload == "T300_K256" else synth.config3()
+    prob = synth.config2()
     T, K, iters = prob.T, prob.K, args.iters
     ctx = cpf.Context(0)
 

@@ -50,6 +50,7 @@ Layout make_layout(int T, int K, bool extra) {
     L.cand = take(t * NJ * k * sizeof(float));
     L.extra = take(extra ? t * k * sizeof(double) : 0);
     L.bp = take(t * k * sizeof(uint16_t));
+    L.topk = take(t * TOPM * k * sizeof(uint16_t));
     L.path = take(t * sizeof(int32_t));
     L.dp_out = take(8 * sizeof(double));
     L.targets = take(12 * t * sizeof(double));
@@ -57,8 +58,8 @@ Layout make_layout(int T, int K, bool extra) {
     L.xt = take(NJ * t * sizeof(double));
     L.A = take(NTRI * t * sizeof(double));
     L.g = take(NJ * t * sizeof(double));
-    L.P = take(NBLK * t * sizeof(double));
-    L.F = take(NBLK * t * sizeof(double));
+    L.P = take(56 * t * sizeof(double));   // [T][7][8]
+    L.F = take(56 * t * sizeof(double));
     L.y = take(NJ * t * sizeof(double));
     L.dx = take(NJ * t * sizeof(double));
     L.rb = take(NJ * t * sizeof(double));
@@ -157,23 +158,24 @@ static void fill_desc(cpf_plan *p, bool has_extra) {
     }
     char *b = p->arena;
     const Layout &L = p->L;
-    D.cand = (const float *)(b + L.cand);
-    D.extra = has_extra ? (const double *)(b + L.extra) : nullptr;
-    D.bp = (uint16_t *)(b + L.bp);
-    D.path = (int32_t *)(b + L.path);
-    D.dp_out = (double *)(b + L.dp_out);
-    D.targets = (double *)(b + L.targets);
-    D.xi = (double *)(b + L.xi);
-    D.xt = (double *)(b + L.xt);
-    D.A = (double *)(b + L.A);
-    D.g = (double *)(b + L.g);
-    D.P = (double *)(b + L.P);
-    D.F = (double *)(b + L.F);
-    D.y = (double *)(b + L.y);
-    D.dx = (double *)(b + L.dx);
-    D.rb = (double *)(b + L.rb);
-    D.st = (LMState *)(b + L.st);
-    D.report = (double *)(b + L.report);
+    set_dev_ptr(D.cand, b + L.cand);
+    set_dev_ptr(D.extra, has_extra ? b + L.extra : nullptr);
+    set_dev_ptr(D.bp, b + L.bp);
+    set_dev_ptr(D.topk, b + L.topk);
+    set_dev_ptr(D.path, b + L.path);
+    set_dev_ptr(D.dp_out, b + L.dp_out);
+    set_dev_ptr(D.targets, b + L.targets);
+    set_dev_ptr(D.xi, b + L.xi);
+    set_dev_ptr(D.xt, b + L.xt);
+    set_dev_ptr(D.A, b + L.A);
+    set_dev_ptr(D.g, b + L.g);
+    set_dev_ptr(D.P, b + L.P);
+    set_dev_ptr(D.F, b + L.F);
+    set_dev_ptr(D.y, b + L.y);
+    set_dev_ptr(D.dx, b + L.dx);
+    set_dev_ptr(D.rb, b + L.rb);
+    set_dev_ptr(D.st, b + L.st);
+    set_dev_ptr(D.report, b + L.report);
 }
 
 cpf_status plan_create(cpf_ctx *ctx, const HostRobot &hr, const cpf_problem *prob,
@@ -397,7 +399,7 @@ cpf_status cpf_dp_search(cpf_plan *plan, int32_t *path_out, double *best_out, do
     cpf_ctx *ctx = plan->ctx;
     HIP_TRY(hipSetDevice(ctx->device));
     HIP_TRY(timed(ctx, KIND_DP, ctx->stream,
-                  [&] { return dp_launch(plan->d_desc, 1, plan->K, ctx->stream); }));
+                  [&] { return dp_launch(plan->d_desc, 1, plan->K, plan->T, ctx->stream); }));
     PlanReadback rb;
     cpf_status st = read_plan(plan, ctx->stream, nullptr, &rb, nullptr, path_out);
     if (st != CPF_OK) return st;
@@ -449,7 +451,7 @@ cpf_status cpf_solve_batch(cpf_ctx *ctx, int32_t nplans, const cpf_robot *robots
         if (d_descs) HIP_IGNORE(hipFree(d_descs));
         for (auto *p : plans) plan_destroy(p);
     };
-    int maxK = 0;
+    int maxK = 0, maxT = 0;
     for (int i = 0; i < nplans; ++i) {
         cpf_plan *p = nullptr;
         if ((st = plan_create(ctx, hrs[i], &probs[i], &o, 0, ctx->stream, staging[i], &p)) != CPF_OK) {
@@ -458,6 +460,7 @@ cpf_status cpf_solve_batch(cpf_ctx *ctx, int32_t nplans, const cpf_robot *robots
         }
         plans.push_back(p);
         maxK = std::max(maxK, probs[i].K);
+        maxT = std::max(maxT, probs[i].T);
     }
     std::vector<DevPlan> host(nplans);
     for (int i = 0; i < nplans; ++i) host[i] = plans[i]->desc;
@@ -469,7 +472,7 @@ cpf_status cpf_solve_batch(cpf_ctx *ctx, int32_t nplans, const cpf_robot *robots
     const int64_t t0 = now_ns();
     if (e == hipSuccess)
         e = timed(ctx, KIND_DP, ctx->stream,
-                  [&] { return dp_launch(d_descs, nplans, maxK, ctx->stream); });
+                  [&] { return dp_launch(d_descs, nplans, maxK, maxT, ctx->stream); });
     if (e == hipSuccess)
         e = timed(ctx, KIND_LM, ctx->stream,
                   [&] { return lm_launch(d_descs, nplans, o.prec, o.iters, ctx->stream); });

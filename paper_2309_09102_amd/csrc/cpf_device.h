@@ -6,18 +6,37 @@
 //   cand     float  [T][7][K]   candidate joint values (Sec. III-A), lane = k
 //   extra    double [T][K]      optional caller search cost (Sec. III-B)
 //   bp       uint16 [T][K]      search back-pointers
+//   topk     uint16 [T][16][K]  nearest predecessors of each search node
 //   path     int32  [T]
 //   targets  double [12][T]     target poses (Sec. II): x y z, R row-major
 //   xi, xt   double [7][T]      trajectory master copy and LM trial point
 //   A        double [28][T]     w_p J_t^T J_t, packed lower triangle
 //   g        double [7][T]      gradient of the cost
-//   P        double [49][T]     inverse Schur blocks of the block LDL^T
-//   F        double [49][T]     coupling of each block to the previous chunk's end
+//   P        double [T][7][8]   inverse Schur blocks of the block LDL^T (row = 64 B)
+//   F        double [T][7][8]   coupling of each block to the previous chunk's end
 //   y, dx, rb double [7][T]     forward sweep, step, refinement residual
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+// Device code reaches the per-plan arrays through pointers stored in the plan
+// descriptor.  Marking them as global-address-space pointers lets the
+// compiler emit global (not flat) memory instructions, whose completion is
+// counted separately from LDS traffic, so loads issued ahead stay in flight
+// across LDS waits.  Host code sees plain pointers (same size and layout).
+#ifdef __HIP_DEVICE_COMPILE__
+#define CPF_GLOBAL __attribute__((address_space(1)))
+#else
+#define CPF_GLOBAL
+#endif
+
+// Host-side store of a device address into a descriptor field (an integer
+// round trip, valid whichever address space the field carries).
+template <class Field, class Ptr>
+inline void set_dev_ptr(Field &field, Ptr *p) {
+    field = (Field)(uintptr_t)p;
+}
 
 namespace cpf {
 
@@ -26,6 +45,7 @@ constexpr int NTRI = 28;      // packed lower triangle of a 7x7 block
 constexpr int NBLK = 49;      // full 7x7 block
 constexpr int MAX_K = 1024;   // search kernel limit (one lane per destination)
 constexpr int CPF_STATUS_NUMERIC = -6;
+constexpr int TOPM = 16;      // nearest predecessors kept per search node
 
 struct LMState {
     double lambda, nu, cost, cost0, grad_inf;
@@ -41,15 +61,16 @@ struct DevPlan {
     // robot in double and float (cos/sin of the twist precomputed on host)
     double a[8], d[8], ca[8], sa[8], off[8], lo[8], hi[8];
     float af[8], df[8], caf[8], saf[8], offf[8];
-    const float *cand;
-    const double *extra;
-    uint16_t *bp;
-    int32_t *path;
-    double *dp_out;    // [0] = B*, [1] = mjac of the seed, [2] = end node
-    double *targets;
-    double *xi, *xt, *A, *g, *P, *F, *y, *dx, *rb;
-    LMState *st;
-    double *report;    // [0] max pos err, [1] max rot err, [2] mjac
+    CPF_GLOBAL const float *cand;
+    CPF_GLOBAL const double *extra;
+    CPF_GLOBAL uint16_t *bp;
+    CPF_GLOBAL uint16_t *topk;    // [T][TOPM][K] nearest predecessors of each node
+    CPF_GLOBAL int32_t *path;
+    CPF_GLOBAL double *dp_out;    // [0] = B*, [1] = mjac of the seed, [2] = end node
+    CPF_GLOBAL double *targets;
+    CPF_GLOBAL double *xi, *xt, *A, *g, *P, *F, *y, *dx, *rb;
+    CPF_GLOBAL LMState *st;
+    CPF_GLOBAL double *report;    // [0] max pos err, [1] max rot err, [2] mjac
 };
 
 template <typename S>

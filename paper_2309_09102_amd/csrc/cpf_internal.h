@@ -17,8 +17,9 @@ struct HostRobot {
 // Kernel launchers (asynchronous on stream s).
 hipError_t fk_batch_launch(const HostRobot &hr, int64_t M, int prec, const void *q, void *pose,
                            void *J, hipStream_t s);
-// Search + seed gather for nplans plans (one workgroup each).
-hipError_t dp_launch(const DevPlan *d_plans, int nplans, int maxK, hipStream_t s);
+// Search + seed gather for nplans plans: the predecessor lists over the
+// whole GPU, then one workgroup per plan for the stages.
+hipError_t dp_launch(const DevPlan *d_plans, int nplans, int maxK, int maxT, hipStream_t s);
 // Up to `iters` LM iterations for each plan of precision prec (0 = mixed,
 // 1 = FP64); empty slots (T = 0) and plans of the other precision are skipped.
 hipError_t lm_launch(const DevPlan *d_plans, int nplans, int prec, int iters, hipStream_t s);

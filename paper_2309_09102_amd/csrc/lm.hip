@@ -13,9 +13,9 @@
 // One workgroup per plan runs all iterations without returning to the host.
 // Kinematics (FK, J, residuals, J^T J) run in S = float or double; the
 // assembly, the solve and every cross-waypoint sum are FP64.  The solve is a
-// block LDL^T sweep  S_t = D_t - w^2 S_{t-1}^{-1}  on one wavefront (lane
-// i*7+j holds element (i, j); 7x7 inverses by Gauss-Jordan), then forward /
-// backward substitution, then FP64 iterative refinement against the same H.
+// block LDL^T sweep  S_t = D_t - w^2 S_{t-1}^{-1}, partitioned over the
+// wavefronts of the workgroup (7x7 blocks one element per lane, inverses by
+// Gauss-Jordan), then FP64 iterative refinement against the same H.
 #include <float.h>
 
 #include "cpf_device.h"
@@ -61,7 +61,7 @@ __device__ __forceinline__ void load_target(const DevPlan &P, int T, int t, S tg
 
 // Squared pose residual of trajectory X ([7][T]) at waypoint t.
 template <typename S>
-__device__ __forceinline__ double pose_sq(const DevPlan &P, const RobotT<S> &rb, const double *X,
+__device__ __forceinline__ double pose_sq(const DevPlan &P, const RobotT<S> &rb, const CPF_GLOBAL double *X,
                                           int T, int t) {
     S q[NJ];
 #pragma unroll
@@ -79,7 +79,7 @@ __device__ __forceinline__ double pose_sq(const DevPlan &P, const RobotT<S> &rb,
 
 // Cost of trajectory X: pose part and smoothness part, block-reduced.
 template <typename S>
-__device__ __forceinline__ double plan_cost(const DevPlan &P, const RobotT<S> &rb, const double *X,
+__device__ __forceinline__ double plan_cost(const DevPlan &P, const RobotT<S> &rb, const CPF_GLOBAL double *X,
                                             int T, double *red) {
     double ps = 0.0, ss = 0.0;
     for (int t = threadIdx.x; t < T; t += LM_BS) {
@@ -164,86 +164,127 @@ __device__ __forceinline__ double d_elem(const DevPlan &P, int T, int t, int i, 
     return v;
 }
 
-// In-place Gauss-Jordan inverse of a symmetric positive definite 7x7 matrix
-// spread over a wavefront (lane i*7+j holds element (i, j); lanes >= 49
-// carry copies and are ignored).  ok becomes false on a non-positive pivot.
-__device__ __forceinline__ double gj_inverse7(double a, int i, int j, bool &ok) {
+// ---------------------------------------------------------------------------
+// 7x7 blocks on a wavefront: lane l < 49 holds element (l / 7, l % 7); lanes
+// 49..63 hold nothing and never write.  A vector is held in lanes 0..6.
+// Block products exchange operands through a per-wavefront LDS scratch (one
+// write of the block, then each lane reads its row and column); LDS
+// instructions of one wavefront execute in program order, so no barrier is
+// needed.  Blocks live in HBM as [T][7][8] doubles.
+// ---------------------------------------------------------------------------
+
+struct Lane {
+    int l, i, j, r;   // lane, element row / column, vector index
+    bool el;          // lane holds an element
+};
+
+__device__ __forceinline__ Lane lane_info() {
+    Lane L;
+    L.l = threadIdx.x & 63;
+    L.el = L.l < NBLK;
+    L.i = L.el ? L.l / NJ : NJ - 1;
+    L.j = L.el ? L.l % NJ : NJ - 1;
+    L.r = L.l < NJ ? L.l : NJ - 1;
+    return L;
+}
+
+struct WaveScratch {
+    double m0[64], m1[64], v[8];
+};
+
+// The wave barriers keep the compiler from moving scratch reads of the
+// previous product past this write, or this product's reads before it.
+__device__ __forceinline__ void put(double *buf, const Lane &L, double x) {
+    __builtin_amdgcn_wave_barrier();
+    if (L.el) buf[L.i * 8 + L.j] = x;
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ void put_vec(double *buf, const Lane &L, double x) {
+    __builtin_amdgcn_wave_barrier();
+    if (L.l < NJ) buf[L.l] = x;
+    __builtin_amdgcn_wave_barrier();
+}
+
+// element (i, j) of A B
+__device__ __forceinline__ double mm(double A, double B, const Lane &L, WaveScratch &ws) {
+    put(ws.m0, L, A);
+    put(ws.m1, L, B);
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < NJ; ++k) s += ws.m0[L.i * 8 + k] * ws.m1[k * 8 + L.j];
+    return s;
+}
+
+// element (i, j) of A B^T
+__device__ __forceinline__ double mm_bt(double A, double B, const Lane &L, WaveScratch &ws) {
+    put(ws.m0, L, A);
+    put(ws.m1, L, B);
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < NJ; ++k) s += ws.m0[L.i * 8 + k] * ws.m1[L.j * 8 + k];
+    return s;
+}
+
+// (M v)_r in lane r < 7
+__device__ __forceinline__ double mv(double M, double v, const Lane &L, WaveScratch &ws) {
+    put(ws.m0, L, M);
+    put_vec(ws.v, L, v);
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < NJ; ++k) s += ws.m0[L.r * 8 + k] * ws.v[k];
+    return s;
+}
+
+// (M^T v)_r in lane r < 7
+__device__ __forceinline__ double mtv(double M, double v, const Lane &L, WaveScratch &ws) {
+    put(ws.m0, L, M);
+    put_vec(ws.v, L, v);
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < NJ; ++k) s += ws.m0[k * 8 + L.r] * ws.v[k];
+    return s;
+}
+
+// In-place Gauss-Jordan inverse of a symmetric positive definite block.
+// Pivot k: a_kk, the lane's a_ik and a_kj are read back from the scratch.
+// ok becomes false on a non-positive pivot.
+__device__ __forceinline__ double gj_inverse(double a, const Lane &L, WaveScratch &ws, bool &ok) {
 #pragma unroll
     for (int k = 0; k < NJ; ++k) {
-        const double akk = __shfl(a, k * NJ + k);
-        const double aik = __shfl(a, i * NJ + k);
-        const double akj = __shfl(a, k * NJ + j);
+        put(ws.m0, L, a);
+        const double akk = ws.m0[k * 9];
+        const double aik = ws.m0[L.i * 8 + k];
+        const double akj = ws.m0[k * 8 + L.j];
         ok = ok && (akk > 0.0);
-        const double r = 1.0 / akk;
+        // reciprocal: hardware estimate refined by one Newton step
+        double rc = __builtin_amdgcn_rcp(akk);
+        rc = fma(rc, fma(-akk, rc, 1.0), rc);
         double na;
-        if (i == k) na = (j == k) ? r : akj * r;
-        else if (j == k) na = -aik * r;
-        else na = a - aik * (akj * r);
+        if (L.i == k) na = (L.j == k) ? rc : akj * rc;
+        else if (L.j == k) na = -aik * rc;
+        else na = a - aik * (akj * rc);
         a = na;
     }
     return a;
 }
 
-// Product of a lane-distributed 7x7 block (lane r*7+c holds M(r, c)) with a
-// vector held in lanes 0..6: lane r < 7 returns (M v)_r.  `col` is the
-// lane's column index c; the row sum gathered by lane r is over lanes
-// r*7 .. r*7+6.
-__device__ __forceinline__ double matvec7(double m, double v, int lane, int col) {
-    const double prod = m * __shfl(v, col);
-    const int r = lane < NJ ? lane : 0;
-    double s = 0.0;
-#pragma unroll
-    for (int c = 0; c < NJ; ++c) s += __shfl(prod, r * NJ + c);
-    return s;
+__device__ __forceinline__ double blk_ld(const CPF_GLOBAL double *base, int t, const Lane &L, int lo, int hi) {
+    return (t >= lo && t <= hi && L.el) ? base[(size_t)t * 56 + L.i * 8 + L.j] : 0.0;
 }
 
-// Solve H x = rhs with the stored inverse Schur blocks P[49][T]:
-// forward y_t = sign*rhs_t + w P_{t-1} y_{t-1}; backward x_t = P_t (y_t + w x_{t+1}).
-// Wave 0 only.  rhs, out are [7][T] (may alias); y is scratch.
-__device__ void substitute(const DevPlan &P, int T, const double *rhs, double sign, double *out,
-                           int lane) {
-    const int j = lane < NBLK ? lane % NJ : 0;
-    const int l = lane < NBLK ? lane : 0;
-    const double w = P.w_s;
-    double yprev = 0.0;
-    for (int t = 0; t < T; ++t) {
-        double y = lane < NJ ? sign * rhs[(size_t)lane * T + t] : 0.0;
-        if (t > 0) {
-            const double pm = P.P[(size_t)l * T + t - 1];
-            y += w * matvec7(pm, yprev, lane, j);
-        }
-        if (lane < NJ) P.y[(size_t)lane * T + t] = y;
-        yprev = y;
-    }
-    double xnext = 0.0;
-    for (int t = T - 1; t >= 0; --t) {
-        const double pm = P.P[(size_t)l * T + t];
-        double v = lane < NJ ? P.y[(size_t)lane * T + t] : 0.0;
-        if (t + 1 < T) v += w * xnext;
-        const double x = matvec7(pm, v, lane, j);
-        if (lane < NJ) out[(size_t)lane * T + t] = x;
-        xnext = x;
-    }
+__device__ __forceinline__ void blk_st(CPF_GLOBAL double *base, int t, const Lane &L, double x) {
+    if (L.el) base[(size_t)t * 56 + L.i * 8 + L.j] = x;
 }
 
-// Factor sweep: P_t = (D_t - w^2 P_{t-1})^{-1}, then substitution for -g.
-// Wave 0 only.  Returns false on a non-positive pivot.
-__device__ bool factor_and_solve(const DevPlan &P, int T, double lam, int lane) {
-    const int i = lane < NBLK ? lane / NJ : 0, j = lane < NBLK ? lane % NJ : 0;
-    const double w = P.w_s, w2 = w * w;
-    bool ok = true;
-    double pprev = 0.0;
-    double dnext = d_elem(P, T, 0, i, j, lam);
-    for (int t = 0; t < T; ++t) {
-        const double dcur = dnext;
-        if (t + 1 < T) dnext = d_elem(P, T, t + 1, i, j, lam);
-        const double s = (t > 0) ? dcur - w2 * pprev : dcur;
-        const double pinv = gj_inverse7(s, i, j, ok);
-        if (lane < NBLK) P.P[(size_t)lane * T + t] = pinv;
-        pprev = pinv;
-    }
-    substitute(P, T, P.g, -1.0, P.dx, lane);   // right-hand side -g
-    return ok;
+__device__ __forceinline__ double vec_ld(const CPF_GLOBAL double *base, int T, const Lane &L, int t, int lo,
+                                         int hi) {
+    return (t >= lo && t <= hi) ? base[(size_t)L.r * T + t] : 0.0;
+}
+
+__device__ __forceinline__ double d_ld(const DevPlan &P, int T, int t, const Lane &L, int lo, int hi,
+                                       double lam) {
+    return (t >= lo && t <= hi) ? d_elem(P, T, t, L.i, L.j, lam) : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -256,179 +297,234 @@ __device__ bool factor_and_solve(const DevPlan &P, int T, double lam, int lane) 
 //   F_{s_c} = w I (zero for the first chunk).
 // Back-substituting from the chunk's last block z_c gives, at its first block,
 //   x_{s_c} = a_c + G_c z_{c-1} + (F_{e_c}^T / w) z_c,
-//   a: a_t = P_t (y_t + w a_{t+1}),  G: G_t = P_t (F_t + w G_{t+1}),  a_e = G_e = 0.
+//   a_t = P_t (y_t + w a_{t+1}),  G_t = P_t (F_t + w G_{t+1}),  a_e = G_e = 0.
 // The last rows of the chunks then form a symmetric block-tridiagonal system
 // in z_0 .. z_{C-1} (the Schur complement on the chunk ends):
 //   M_c = S_{e_c} - w G_{c+1},  sub-diagonal -F_{e_c},  r_c = y_{e_c} + w a_{c+1},
 // solved by one wavefront with the same LDL^T sweep, after which every chunk
 // recovers its interior: x_t = P_t (y_t + F_t z_{c-1} + w x_{t+1}).
+// With C = 1 this is the plain block LDL^T sweep over the whole path.
 // ---------------------------------------------------------------------------
 
 constexpr int MAX_CHUNKS = LM_BS / 64;
 
 struct ChunkShared {
-    double S[MAX_CHUNKS][NBLK];    // S_{e_c}, then M_c, then Pi_c = Sigma_c^{-1}
-    double G[MAX_CHUNKS][NBLK];    // G_c at the chunk's first block
-    double y[MAX_CHUNKS][8];       // y_{e_c}, then r_c, then rho_c
-    double a[MAX_CHUNKS][8];       // a_c at the chunk's first block
-    double z[MAX_CHUNKS][8];       // chunk-end solution z_c
+    double Pi[MAX_CHUNKS][64];   // S_{e_c}, then Pi_c = Sigma_c^{-1}
+    double G[MAX_CHUNKS][64];    // G_c at the chunk's first block
+    double y[MAX_CHUNKS][8];     // y_{e_c}, then rho_c
+    double a[MAX_CHUNKS][8];     // a_c at the chunk's first block
+    double z[MAX_CHUNKS][8];     // chunk-end solution z_c
+    WaveScratch ws[MAX_CHUNKS];
     int bad;
 };
-
-__device__ __forceinline__ double matmul7(double A, double B, int i, int j) {
-    double s = 0.0;
-#pragma unroll
-    for (int k = 0; k < NJ; ++k) s += __shfl(A, i * NJ + k) * __shfl(B, k * NJ + j);
-    return s;
-}
 
 __device__ __forceinline__ void chunk_bounds(int T, int C, int c, int &s, int &e) {
     s = (int)(((long long)c * T) / C);
     e = (int)(((long long)(c + 1) * T) / C) - 1;
 }
 
-// Factorisation of the partitioned system (all waves; wave c owns chunk c).
-// Stores P_t (t < e_c) and F_t for every t, and Pi_c for the chunk ends.
-// Returns false on a non-positive pivot (flag in sh.bad).
-__device__ bool chunk_factor(const DevPlan &P, int T, int C, double lam, ChunkShared &sh) {
-    const int lane = threadIdx.x & 63, c = threadIdx.x >> 6;
-    const int i = lane < NBLK ? lane / NJ : 0, j = lane < NBLK ? lane % NJ : 0;
-    const int l = lane < NBLK ? lane : 0;
+// Reduced system on the chunk ends (wave 0).  With `factor`, Sigma_c =
+// M_c - F_{e_c} Pi_{c-1} F_{e_c}^T is factored (Pi_c kept in sh.Pi); then
+// rho / z are solved from sh.y (y_{e_c}) and sh.a (a_c).
+__device__ __forceinline__ void reduced_solve(const DevPlan &P, int T, int C, bool factor, ChunkShared &sh,
+                              bool &ok) {
+    const Lane L = lane_info();
+    WaveScratch &ws = sh.ws[0];
+    const double w = P.w_s;
+    const int ij = L.i * 8 + L.j;
+    double pi_prev = 0.0, rho_prev = 0.0;
+    for (int cc = 0; cc < C; ++cc) {
+        int s, e;
+        chunk_bounds(T, C, cc, s, e);
+        const double Fe = cc > 0 ? blk_ld(P.F, e, L, 0, T - 1) : 0.0;   // F_{e_c}
+        double pi;
+        if (factor) {
+            double M = sh.Pi[cc][ij];
+            if (cc + 1 < C) M -= w * sh.G[cc + 1][ij];
+            if (cc > 0) M -= mm_bt(mm(Fe, pi_prev, L, ws), Fe, L, ws);   // F Pi F^T
+            pi = gj_inverse(M, L, ws, ok);
+            if (L.el) sh.Pi[cc][ij] = pi;
+        } else {
+            pi = sh.Pi[cc][ij];
+        }
+        double r = sh.y[cc][L.r];
+        if (cc + 1 < C) r += w * sh.a[cc + 1][L.r];
+        if (cc > 0) r += mv(Fe, mv(pi_prev, rho_prev, L, ws), L, ws);
+        if (L.l < NJ) sh.y[cc][L.r] = r;
+        rho_prev = r;
+        pi_prev = pi;
+    }
+    double znext = 0.0;
+    for (int cc = C - 1; cc >= 0; --cc) {
+        double v = sh.y[cc][L.r];
+        if (cc + 1 < C) {
+            int s1, e1;
+            chunk_bounds(T, C, cc + 1, s1, e1);
+            v += mtv(blk_ld(P.F, e1, L, 0, T - 1), znext, L, ws);   // F_{e_{c+1}}^T z_{c+1}
+        }
+        const double z = mv(sh.Pi[cc][ij], v, L, ws);
+        if (L.l < NJ) sh.z[cc][L.r] = z;
+        znext = z;
+    }
+}
+
+// Interior of chunk c: x_t = P_t (y_t + F_t z_{c-1} + w x_{t+1}), x_e = z_c.
+__device__ __forceinline__ void chunk_interior(const DevPlan &P, int T, int c, int s, int e,
+                                               CPF_GLOBAL double *out, ChunkShared &sh) {
+    const Lane L = lane_info();
+    WaveScratch &ws = sh.ws[c];
+    const double w = P.w_s;
+    const double zl = c > 0 ? sh.z[c - 1][L.r] : 0.0;
+    double x = sh.z[c][L.r];
+    if (L.l < NJ) out[(size_t)L.r * T + e] = x;
+    double p0 = blk_ld(P.P, e - 1, L, s, e - 1), p1 = blk_ld(P.P, e - 2, L, s, e - 1);
+    double f0 = blk_ld(P.F, e - 1, L, s, e - 1), f1 = blk_ld(P.F, e - 2, L, s, e - 1);
+    double y0 = vec_ld(P.y, T, L, e - 1, s, e - 1), y1 = vec_ld(P.y, T, L, e - 2, s, e - 1);
+    for (int t = e - 1; t >= s; --t) {
+        const double pm = p0, fm = f0, ym = y0;
+        p0 = p1; f0 = f1; y0 = y1;
+        p1 = blk_ld(P.P, t - 2, L, s, e - 1);
+        f1 = blk_ld(P.F, t - 2, L, s, e - 1);
+        y1 = vec_ld(P.y, T, L, t - 2, s, e - 1);
+        double v = ym + w * x;
+        if (c > 0) v += mv(fm, zl, L, ws);
+        x = mv(pm, v, L, ws);
+        if (L.l < NJ) out[(size_t)L.r * T + t] = x;
+    }
+}
+
+// Factorisation of the partitioned system fused with the solve for the
+// right-hand side -g (all waves; wave c owns chunk c).  Stores P_t (t < e_c),
+// F_t and y_t, Pi_c for the chunk ends, and the step in P.dx.  Returns false
+// on a non-positive pivot.
+__device__ __forceinline__ bool chunk_factor_solve(const DevPlan &P, int T, int C, double lam,
+                                                   ChunkShared &sh) {
+    const int c = threadIdx.x >> 6;
+    const Lane L = lane_info();
     const double w = P.w_s, w2 = w * w;
     if (threadIdx.x == 0) sh.bad = 0;
     __syncthreads();
     bool ok = true;
+    int s = 0, e = -1;
     if (c < C) {
-        int s, e;
+        WaveScratch &ws = sh.ws[c];
         chunk_bounds(T, C, c, s, e);
-        double pprev = 0.0, fprev = 0.0;
+        double d0 = d_ld(P, T, s, L, s, e, lam), d1 = d_ld(P, T, s + 1, L, s, e, lam);
+        double b0 = -vec_ld(P.g, T, L, s, s, e), b1 = -vec_ld(P.g, T, L, s + 1, s, e);
+        double pprev = 0.0, fprev = 0.0, yprev = 0.0;
         for (int t = s; t <= e; ++t) {
-            const double d = d_elem(P, T, t, i, j, lam);
-            const double S = (t > s) ? d - w2 * pprev : d;
-            double F;
-            if (t == s) F = (c > 0 && i == j) ? w : 0.0;
-            else F = w * matmul7(pprev, fprev, i, j);
-            if (lane < NBLK) P.F[(size_t)lane * T + t] = F;
-            if (t == e) {
-                if (lane < NBLK) sh.S[c][lane] = S;
+            const double d = d0, b = b0;
+            d0 = d1;
+            b0 = b1;
+            d1 = d_ld(P, T, t + 2, L, s, e, lam);
+            b1 = -vec_ld(P.g, T, L, t + 2, s, e);
+            double S = d, F, y = b;
+            if (t == s) {
+                F = (c > 0 && L.el && L.i == L.j) ? w : 0.0;
             } else {
-                const double pinv = gj_inverse7(S, i, j, ok);
-                if (lane < NBLK) P.P[(size_t)lane * T + t] = pinv;
-                pprev = pinv;
+                S -= w2 * pprev;
+                F = w * mm(pprev, fprev, L, ws);
+                y += w * mv(pprev, yprev, L, ws);
+            }
+            if (C > 1) blk_st(P.F, t, L, F);
+            if (L.l < NJ) P.y[(size_t)L.r * T + t] = y;
+            if (t == e) {
+                if (L.el) sh.Pi[c][L.i * 8 + L.j] = S;
+                if (L.l < NJ) sh.y[c][L.r] = y;
+            } else {
+                pprev = gj_inverse(S, L, ws, ok);
+                blk_st(P.P, t, L, pprev);
             }
             fprev = F;
+            yprev = y;
         }
-        // G at the first block: G_t = P_t (F_t + w G_{t+1}), G_e = 0.
-        double G = 0.0;
-        for (int t = e - 1; t >= s; --t) {
-            const double pm = P.P[(size_t)l * T + t];
-            const double f = P.F[(size_t)l * T + t];
-            G = matmul7(pm, f + w * G, i, j);
-        }
-        if (lane < NBLK) sh.G[c][lane] = G;
-        if (!ok) sh.bad = 1;
-    }
-    __syncthreads();
-    // Reduced system on the chunk ends (wave 0).
-    if (c == 0) {
-        double pi_prev = 0.0;
-        for (int cc = 0; cc < C; ++cc) {
-            int s, e;
-            chunk_bounds(T, C, cc, s, e);
-            double M = sh.S[cc][l];
-            if (cc + 1 < C) M -= w * sh.G[cc + 1][l];
-            if (cc > 0) {
-                const double Fe = P.F[(size_t)l * T + e];
-                const double FePi = matmul7(Fe, pi_prev, i, j);
-                M -= matmul7(FePi, __shfl(Fe, j * NJ + i), i, j);   // F Pi F^T
+        // backward (chunks that have a predecessor): G and a at the first block
+        double G = 0.0, a = 0.0;
+        if (c > 0) {
+            double p0 = blk_ld(P.P, e - 1, L, s, e - 1), p1 = blk_ld(P.P, e - 2, L, s, e - 1);
+            double f0 = blk_ld(P.F, e - 1, L, s, e - 1), f1 = blk_ld(P.F, e - 2, L, s, e - 1);
+            double y0 = vec_ld(P.y, T, L, e - 1, s, e - 1), y1 = vec_ld(P.y, T, L, e - 2, s, e - 1);
+            for (int t = e - 1; t >= s; --t) {
+                const double pm = p0, fm = f0, ym = y0;
+                p0 = p1; f0 = f1; y0 = y1;
+                p1 = blk_ld(P.P, t - 2, L, s, e - 1);
+                f1 = blk_ld(P.F, t - 2, L, s, e - 1);
+                y1 = vec_ld(P.y, T, L, t - 2, s, e - 1);
+                G = mm(pm, fm + w * G, L, ws);
+                a = mv(pm, ym + w * a, L, ws);
             }
-            const double pi = gj_inverse7(M, i, j, ok);
-            if (lane < NBLK) sh.S[cc][lane] = pi;
-            pi_prev = pi;
         }
+        if (L.el) sh.G[c][L.i * 8 + L.j] = G;
+        if (L.l < NJ) sh.a[c][L.r] = a;
         if (!ok) sh.bad = 1;
     }
     __syncthreads();
-    return sh.bad == 0;
+    if (c == 0) {
+        reduced_solve(P, T, C, true, sh, ok);
+        if (!ok) sh.bad = 1;
+    }
+    __syncthreads();
+    if (sh.bad) return false;
+    if (c < C) chunk_interior(P, T, c, s, e, P.dx, sh);
+    __syncthreads();
+    return true;
 }
 
 // Solve with the partitioned factors for right-hand side sign*rhs ([7][T]);
 // writes out ([7][T], may alias rhs).  All waves.
-__device__ void chunk_substitute(const DevPlan &P, int T, int C, const double *rhs, double sign,
-                                 double *out, ChunkShared &sh) {
-    const int lane = threadIdx.x & 63, c = threadIdx.x >> 6;
-    const int j = lane < NBLK ? lane % NJ : 0;
-    const int l = lane < NBLK ? lane : 0;
+__device__ __forceinline__ void chunk_substitute(const DevPlan &P, int T, int C,
+                                                 const CPF_GLOBAL double *rhs,
+                                 double sign, CPF_GLOBAL double *out, ChunkShared &sh) {
+    const int c = threadIdx.x >> 6;
+    const Lane L = lane_info();
     const double w = P.w_s;
+    int s = 0, e = -1;
     if (c < C) {
-        int s, e;
+        WaveScratch &ws = sh.ws[c];
         chunk_bounds(T, C, c, s, e);
         // forward: y_t = b_t + w P_{t-1} y_{t-1} within the chunk
-        double yprev = 0.0;
+        double yprev = 0.0, pprev = 0.0;
+        double p0 = blk_ld(P.P, s, L, s, e - 1), p1 = blk_ld(P.P, s + 1, L, s, e - 1);
+        double r0 = vec_ld(rhs, T, L, s, s, e), r1 = vec_ld(rhs, T, L, s + 1, s, e);
         for (int t = s; t <= e; ++t) {
-            double y = lane < NJ ? sign * rhs[(size_t)lane * T + t] : 0.0;
-            if (t > s) y += w * matvec7(P.P[(size_t)l * T + t - 1], yprev, lane, j);
-            if (lane < NJ) P.y[(size_t)lane * T + t] = y;
+            const double pm = p0, rm = r0;
+            p0 = p1; r0 = r1;
+            p1 = blk_ld(P.P, t + 2, L, s, e - 1);
+            r1 = vec_ld(rhs, T, L, t + 2, s, e);
+            double y = sign * rm;
+            if (t > s) y += w * mv(pprev, yprev, L, ws);
+            if (L.l < NJ) P.y[(size_t)L.r * T + t] = y;
             yprev = y;
+            pprev = pm;
         }
-        if (lane < NJ) sh.y[c][lane] = yprev;
+        if (L.l < NJ) sh.y[c][L.r] = yprev;
         // backward: a_t = P_t (y_t + w a_{t+1}), a_e = 0
         double a = 0.0;
-        for (int t = e - 1; t >= s; --t) {
-            const double v = (lane < NJ ? P.y[(size_t)lane * T + t] : 0.0) + w * a;
-            a = matvec7(P.P[(size_t)l * T + t], v, lane, j);
+        if (c > 0) {
+            double q0 = blk_ld(P.P, e - 1, L, s, e - 1), q1 = blk_ld(P.P, e - 2, L, s, e - 1);
+            double y0 = vec_ld(P.y, T, L, e - 1, s, e - 1), y1 = vec_ld(P.y, T, L, e - 2, s, e - 1);
+            for (int t = e - 1; t >= s; --t) {
+                const double pm = q0, ym = y0;
+                q0 = q1; y0 = y1;
+                q1 = blk_ld(P.P, t - 2, L, s, e - 1);
+                y1 = vec_ld(P.y, T, L, t - 2, s, e - 1);
+                a = mv(pm, ym + w * a, L, ws);
+            }
         }
-        if (lane < NJ) sh.a[c][lane] = a;
+        if (L.l < NJ) sh.a[c][L.r] = a;
     }
     __syncthreads();
     if (c == 0) {
-        // rho_c = r_c + F_{e_c} Pi_{c-1} rho_{c-1};  z_c = Pi_c (rho_c + F_{e_{c+1}}^T z_{c+1})
-        double rho_prev = 0.0;
-        for (int cc = 0; cc < C; ++cc) {
-            int s, e;
-            chunk_bounds(T, C, cc, s, e);
-            double r = lane < NJ ? sh.y[cc][lane] : 0.0;
-            if (cc + 1 < C && lane < NJ) r += w * sh.a[cc + 1][lane];
-            if (cc > 0) {
-                const double v = matvec7(sh.S[cc - 1][l], rho_prev, lane, j);
-                r += matvec7(P.F[(size_t)l * T + e], v, lane, j);
-            }
-            if (lane < NJ) sh.y[cc][lane] = r;
-            rho_prev = r;
-        }
-        double znext = 0.0;
-        for (int cc = C - 1; cc >= 0; --cc) {
-            double v = lane < NJ ? sh.y[cc][lane] : 0.0;
-            if (cc + 1 < C) {
-                int s1, e1;
-                chunk_bounds(T, C, cc + 1, s1, e1);
-                const double Fe = P.F[(size_t)l * T + e1];
-                v += matvec7(__shfl(Fe, j * NJ + (lane < NBLK ? lane / NJ : 0)), znext, lane, j);
-            }
-            const double z = matvec7(sh.S[cc][l], v, lane, j);
-            if (lane < NJ) sh.z[cc][lane] = z;
-            znext = z;
-        }
+        bool ok = true;
+        reduced_solve(P, T, C, false, sh, ok);
     }
     __syncthreads();
-    if (c < C) {
-        int s, e;
-        chunk_bounds(T, C, c, s, e);
-        const double zl = (c > 0 && lane < NJ) ? sh.z[c - 1][lane] : 0.0;
-        double x = lane < NJ ? sh.z[c][lane] : 0.0;
-        if (lane < NJ) out[(size_t)lane * T + e] = x;
-        for (int t = e - 1; t >= s; --t) {
-            double v = (lane < NJ ? P.y[(size_t)lane * T + t] : 0.0) + w * x;
-            if (c > 0) v += matvec7(P.F[(size_t)l * T + t], zl, lane, j);
-            x = matvec7(P.P[(size_t)l * T + t], v, lane, j);
-            if (lane < NJ) out[(size_t)lane * T + t] = x;
-        }
-    }
+    if (c < C) chunk_interior(P, T, c, s, e, out, sh);
     __syncthreads();
 }
 
 // rb_t = -g_t - (H dx)_t  for every waypoint (all lanes).
-__device__ void refine_residual(const DevPlan &P, int T, double lam) {
+__device__ __forceinline__ void refine_residual(const DevPlan &P, int T, double lam) {
     const double w = P.w_s;
     for (int t = threadIdx.x; t < T; t += LM_BS) {
         double d[NJ];
@@ -502,12 +598,26 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
     __syncthreads();
     const int n_it = sh_flags[2];
 
-    const int lane = tid & 63;
-    const bool wave0 = tid < 64;
     __shared__ ChunkShared chs;
-    // Chunks of at least 8 waypoints, one per wavefront; short paths use the
-    // single-wavefront sweep.
-    const int C = min(MAX_CHUNKS, T / 8) >= 2 ? min(MAX_CHUNKS, T / 8) : 1;
+    // Chunks of at least 8 waypoints, one per wavefront (C = 1: plain sweep).
+    const int C = max(1, min(MAX_CHUNKS, T / 8));
+#ifdef CPF_PHASE_CYCLES
+    // Diagnostic build only: per-phase shader-clock totals printed by thread 0.
+    uint64_t ph[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint64_t ph_last = clock64();
+#define PHASE_MARK(k)                                  \
+    do {                                               \
+        if (tid == 0) {                                \
+            const uint64_t now_ = clock64();           \
+            ph[k] += now_ - ph_last;                   \
+            ph_last = now_;                            \
+        }                                              \
+    } while (0)
+#else
+#define PHASE_MARK(k) \
+    do {              \
+    } while (0)
+#endif
     for (int it = 0; it < n_it; ++it) {
         if (sh_flags[1] != 0) break;
         const double lam = sh_lam;
@@ -517,13 +627,11 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
             if (tid == 0) st->grad_inf = gmax;
         }
         __syncthreads();
-        if (C > 1) {
-            const bool ok = chunk_factor(P, T, C, lam, chs);
+        PHASE_MARK(0);
+        {
+            const bool ok = chunk_factor_solve(P, T, C, lam, chs);   // right-hand side -g
             if (tid == 0) sh_flags[3] = ok ? 0 : 1;
-            if (ok) chunk_substitute(P, T, C, P.g, -1.0, P.dx, chs);   // right-hand side -g
-        } else if (wave0) {
-            const bool ok = factor_and_solve(P, T, lam, lane);
-            if (lane == 0) sh_flags[3] = ok ? 0 : 1;
+            PHASE_MARK(1);
         }
         __syncthreads();
         if (sh_flags[3]) {
@@ -534,16 +642,14 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
         for (int rs = 0; rs < P.refine_steps; ++rs) {
             refine_residual(P, T, lam);
             __syncthreads();
-            if (C > 1) {
-                chunk_substitute(P, T, C, P.rb, 1.0, P.rb, chs);   // correction in place
-            } else if (wave0) {
-                substitute(P, T, P.rb, 1.0, P.rb, lane);
-            }
+            PHASE_MARK(3);
+            chunk_substitute(P, T, C, P.rb, 1.0, P.rb, chs);   // correction in place
             __syncthreads();
             for (int t = tid; t < T; t += LM_BS)
 #pragma unroll
                 for (int j = 0; j < NJ; ++j) P.dx[(size_t)j * T + t] += P.rb[(size_t)j * T + t];
             __syncthreads();
+            PHASE_MARK(4);
         }
         // Trial point, its cost and the predicted reduction.
         double pr = 0.0;
@@ -561,6 +667,7 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
         __syncthreads();
         const double cn = plan_cost<S>(P, rb, P.xt, T, red);
         const double pred = 0.5 * block_sum(pr, red);
+        PHASE_MARK(5);
         if (tid == 0) {
             const double c = sh_cost;
             double l = sh_lam, nu = sh_nu;
@@ -593,7 +700,17 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
                 for (int j = 0; j < NJ; ++j) P.xi[(size_t)j * T + t] = P.xt[(size_t)j * T + t];
         }
         __syncthreads();
+        PHASE_MARK(6);
     }
+#ifdef CPF_PHASE_CYCLES
+    if (tid == 0 && blockIdx.x == 0)
+        printf("lm phase cycles T=%d C=%d iters=%d: lin %llu factor %llu solve %llu refres %llu "
+               "refsub %llu trial %llu accept %llu\n",
+               T, C, n_it, (unsigned long long)ph[0], (unsigned long long)ph[1],
+               (unsigned long long)ph[2], (unsigned long long)ph[3], (unsigned long long)ph[4],
+               (unsigned long long)ph[5], (unsigned long long)ph[6]);
+#endif
+#undef PHASE_MARK
     if (tid == 0) {
         st->lambda = sh_lam;
         st->nu = sh_nu;

@@ -172,7 +172,7 @@ void server_main(cpf_ctx *ctx) {
         }
         // 1. upload and place the admitted requests
         std::vector<DevPlan> fresh;
-        int maxK = 0;
+        int maxK = 0, maxT = 0;
         for (Request *r : admitted) {
             cpf_problem pb{r->T, r->K, r->targets.data(), r->cand.data(),
                            r->node_pen.empty() ? nullptr : r->node_pen.data()};
@@ -189,7 +189,7 @@ void server_main(cpf_ctx *ctx) {
             r->slot = slot;
             sv->slot_req[slot] = r;
             DevPlan d = r->plan->desc;
-            d.st = sv->d_states + slot;
+            set_dev_ptr(d.st, sv->d_states + slot);
             sv->h_work[slot] = d;
             LMState &ls = sv->h_states[slot];
             memset(&ls, 0, sizeof(ls));
@@ -202,6 +202,7 @@ void server_main(cpf_ctx *ctx) {
                                       hipMemcpyHostToDevice, sv->s));
             fresh.push_back(d);
             maxK = std::max(maxK, r->K);
+            maxT = std::max(maxT, r->T);
             active.push_back(r);
         }
         cpf_status dev = CPF_OK;
@@ -211,7 +212,7 @@ void server_main(cpf_ctx *ctx) {
                                           hipMemcpyHostToDevice, sv->s);
             if (e == hipSuccess)
                 e = timed(ctx, KIND_DP, sv->s,
-                          [&] { return dp_launch(sv->d_new, (int)fresh.size(), maxK, sv->s); });
+                          [&] { return dp_launch(sv->d_new, (int)fresh.size(), maxK, maxT, sv->s); });
             if (e == hipSuccess) e = hipStreamSynchronize(sv->s);
             if (e != hipSuccess) dev = fail(CPF_E_DEVICE, "search launch: %s", hipGetErrorString(e));
             const int64_t ts = now_ns();

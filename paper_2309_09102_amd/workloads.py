@@ -1,0 +1,184 @@
+"""Additional measured workloads of the refinement path (bench.py --workload).
+
+  batch64    64 independent problems of uneven size (T ~ U{100..1000},
+             K ~ U{64..512}, a fresh robot each), search + 30 LM iterations,
+             FP32 kinematics with FP64 solve, one launch of each kernel.
+  T1000_K512 one request with T=1000, K=512, 50 LM iterations; the mixed arm
+             (FP32 kinematics + FP64 solve + one FP64 refinement step) and the
+             all-FP64 arm (their agreement with the oracle is a GPU test).
+  serve      Poisson arrivals (200 requests/s) of requests with T ~ U{50..2000},
+             K in {128, 256, 512}, sigma ~ U[0.02, 0.15], offset fraction
+             ~ U[0, 0.3] and 30 LM iterations, served by cpf_submit/cpf_poll
+             (continuous batching, mixed precision), and the same arrival
+             schedule served one request at a time by the all-FP64 path.
+             Requests are drawn from a pool of distinct seeded problems that
+             the stream cycles through (the pool keeps host memory bounded).
+
+Every mode prints one JSON object; inputs are synthetic and seeded.
+"""
+from __future__ import annotations
+
+import json
+import threading
+import time
+
+import numpy as np
+
+
+def _targets(ctx, prob, torch, dev):
+    q = torch.tensor(prob.q_star.T.copy(), dtype=torch.float64, device=dev)
+    pose, _ = ctx.fk_batch(prob.robot, q)
+    torch.cuda.synchronize()
+    return prob.with_targets(pose.cpu().numpy().T)
+
+
+def run_batch64(n=64, iters=30):
+    import torch
+    from paper_2309_09102_amd import cpf, synth
+    dev = torch.device("cuda:0")
+    ctx = cpf.Context(0)
+    probs = [_targets(ctx, synth.config4_problem(i), torch, dev) for i in range(n)]
+    opts = cpf.make_opts(iters=iters, prec="mixed")
+    items = [(p.robot, p.targets, p.cand) for p in probs]
+    ctx.solve_batch(items[:2], opts)                  # warm-up (code objects)
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    res = ctx.solve_batch(items, opts)
+    t1 = time.perf_counter()
+    st = {k: ctx.kernel_stats(k) for k in ("dp", "lm", "eval")}
+    ctx.profile(False)
+    work = sum(p.T for p in probs) * iters
+    dev_ms = sum(v[0] for v in st.values())
+    out = {"mode": "batch64", "problems": n, "lm_iters": iters,
+           "waypoint_lm_iters": work,
+           "value_end_to_end": work / (t1 - t0), "value_device": work / (dev_ms * 1e-3),
+           "unit": "waypoint-LM-iters/s", "wall_s": t1 - t0,
+           "kernels_ms": {k: v[0] for k, v in st.items()},
+           "statuses": sorted(set(int(r["status"]) for r in res))}
+    ctx.close()
+    return out
+
+
+def run_precision(iters=50):
+    import torch
+    from paper_2309_09102_amd import cpf, synth
+    dev = torch.device("cuda:0")
+    ctx = cpf.Context(0)
+    p = _targets(ctx, synth.config3(), torch, dev)
+    out = {"mode": "T1000_K512", "T": p.T, "K": p.K, "lm_iters": iters, "arms": {}}
+    for arm, prec in (("A_mixed", "mixed"), ("B_fp64", "fp64")):
+        plan = ctx.plan(p.robot, p.targets, p.cand, opts=cpf.make_opts(prec=prec))
+        plan.dp_search()
+        plan.lm_refine(1)                              # warm-up
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        plan.dp_search()
+        _, rep = plan.lm_refine(iters, want_xi=False)
+        t1 = time.perf_counter()
+        st = {k: ctx.kernel_stats(k) for k in ("dp", "lm")}
+        ctx.profile(False)
+        plan.free()
+        out["arms"][arm] = {"latency_ms": (t1 - t0) * 1e3,
+                            "waypoint_lm_iters_per_s": p.T * iters / (t1 - t0),
+                            "kernels_ms": {k: v[0] for k, v in st.items()},
+                            "pose_err_vs_targets": [rep["max_pos_err_m"], rep["max_rot_err_rad"]]}
+    ctx.close()
+    return out
+
+
+def _pct(xs, q):
+    return float(np.percentile(np.asarray(xs), q)) if xs else None
+
+
+def run_serve(duration_s=10.0, rate_hz=200.0, pool=48, iters=30, slots=256, ipt=10,
+              fp64_budget_s=None):
+    import torch
+    from paper_2309_09102_amd import cpf, synth
+    dev = torch.device("cuda:0")
+    arrivals = synth.config5_arrivals(rate_hz, duration_s)
+    gen_ctx = cpf.Context(0)
+    reqs = [_targets(gen_ctx, synth.config5_request(i), torch, dev) for i in range(pool)]
+    gen_ctx.close()
+
+    def stream_items():
+        return [(float(a), reqs[i % pool]) for i, a in enumerate(arrivals)]
+
+    # --- mixed precision, continuous batching ---------------------------------
+    ctx = cpf.Context(0, 64 << 30)
+    ctx.config(slots=slots, iters_per_tick=ipt)
+    opts = cpf.make_opts(iters=iters, prec="mixed")
+    w = ctx.submit(reqs[0].robot, reqs[0].targets, reqs[0].cand, opts)   # warm-up
+    ctx.poll(w, reqs[0].T)
+    items = stream_items()
+    tickets = [None] * len(items)
+    t_start = time.perf_counter()
+
+    def submitter():
+        for n, (at, p) in enumerate(items):
+            d = t_start + at - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            tickets[n] = ctx.submit(p.robot, p.targets, p.cand, opts)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    lat, done_work, statuses = [], 0, set()
+    for n, (at, p) in enumerate(items):
+        while tickets[n] is None:
+            time.sleep(0.0005)
+        r = ctx.poll(tickets[n], p.T, timeout_ms=-1)
+        lat.append((r["t_done_ns"] - r["t_submit_ns"]) * 1e-6)
+        done_work += p.T * iters
+        statuses.add(int(r["status"]))
+    th.join()
+    t_end = time.perf_counter()
+    ctx.close()
+    mixed = {"requests": len(items), "throughput": done_work / (t_end - t_start),
+             "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99), "max_ms": max(lat),
+             "wall_s": t_end - t_start, "statuses": sorted(statuses)}
+
+    # --- all FP64, one request at a time (same arrival schedule) --------------
+    ctx = cpf.Context(0, 64 << 30)
+    o64 = cpf.make_opts(iters=iters, prec="fp64")
+    budget = fp64_budget_s if fp64_budget_s is not None else duration_s * 3
+    lat64, work64 = [], 0
+    t0 = time.perf_counter()
+    served = 0
+    for at, p in items:
+        now = time.perf_counter() - t0
+        if now < at:
+            time.sleep(at - now)
+        if time.perf_counter() - t0 > budget:
+            break
+        plan = ctx.plan(p.robot, p.targets, p.cand, opts=o64)
+        plan.dp_search()
+        plan.lm_refine(iters, want_xi=True)
+        plan.free()
+        lat64.append((time.perf_counter() - t0 - at) * 1e3)
+        work64 += p.T * iters
+        served += 1
+    t1 = time.perf_counter()
+    ctx.close()
+    fp64 = {"requests_served": served, "requests_offered": len(items),
+            "throughput": work64 / (t1 - t0), "p50_ms": _pct(lat64, 50),
+            "p99_ms": _pct(lat64, 99), "wall_s": t1 - t0,
+            "note": "stops after the time budget; unserved requests are not counted"}
+    return {"mode": "serve", "rate_hz": rate_hz, "duration_s": duration_s, "pool": pool,
+            "lm_iters": iters, "slots": slots, "iters_per_tick": ipt,
+            "unit": "waypoint-LM-iters/s", "mixed_continuous_batching": mixed,
+            "fp64_one_at_a_time": fp64,
+            "speedup": mixed["throughput"] / max(fp64["throughput"], 1e-9)}
+
+
+if __name__ == "__main__":
+    import argparse
+    ap = argparse.ArgumentParser()
+    ap.add_argument("mode", choices=["batch64", "T1000_K512", "serve"])
+    ap.add_argument("--duration", type=float, default=10.0)
+    a = ap.parse_args()
+    if a.mode == "batch64":
+        print(json.dumps(run_batch64()))
+    elif a.mode == "T1000_K512":
+        print(json.dumps(run_precision()))
+    else:
+        print(json.dumps(run_serve(duration_s=a.duration)))

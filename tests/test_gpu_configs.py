@@ -1,0 +1,74 @@
+"""GPU parity at the measured workload sizes, through the C ABI.
+
+- T=1000, K=512, 50 LM iterations: the mixed arm (FP32 kinematics, FP64
+  solve + refinement) and the all-FP64 arm against the FP64 oracle.
+- The 64-problem ragged batch (T ~ U{100..1000}, K ~ U{64..512}, fresh robot
+  each, 30 iterations): sampled problems against the oracle, and every
+  sampled result identical to the same problem solved alone.
+Tolerances as in test_gpu_parity: <= 1e-5 m, <= 1e-5 rad, <= 1e-6 relative
+cost, identical search path.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2309_09102_amd import synth
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2309_09102_amd import cpf  # noqa: E402
+
+POS_TOL, ROT_TOL, COST_TOL = 1e-5, 1e-5, 1e-6
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = cpf.Context(0, 16 << 30)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def config3():
+    p = H.with_targets(synth.config3())
+    ref = oracle.plan(p.robot, p.cand, p.targets, 50)
+    return p, ref
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_precision_study_T1000_K512(ctx, config3, prec):
+    p, ref = config3
+    with ctx.plan(p.robot, p.targets, p.cand, opts=cpf.make_opts(prec=prec)) as plan:
+        path, best, _ = plan.dp_search()
+        xi, rep = plan.lm_refine(50)
+    assert np.array_equal(path, ref["path"]) and best == ref["best"]
+    ep, er, ec = H.parity_metrics(p, xi, ref["xi"])
+    print(f"T1000 K512 {prec}: pos {ep:.3e} m  rot {er:.3e} rad  cost {ec:.3e}  "
+          f"pose vs targets {rep['max_pos_err_m']:.3e} m")
+    assert ep <= POS_TOL and er <= ROT_TOL and ec <= COST_TOL, (ep, er, ec)
+
+
+def test_batch64_sampled_vs_oracle_and_alone(ctx):
+    probs = [H.with_targets(synth.config4_problem(i)) for i in range(64)]
+    opts = cpf.make_opts(iters=30)
+    res = ctx.solve_batch([(p.robot, p.targets, p.cand) for p in probs], opts)
+    assert all(r["status"] == 0 for r in res)
+    # the four cheapest searches, plus the largest path
+    order = sorted(range(64), key=lambda i: probs[i].T * probs[i].K ** 2)
+    sample = order[:4] + [max(range(64), key=lambda i: probs[i].T)]
+    for i in sample:
+        p = probs[i]
+        ref = oracle.plan(p.robot, p.cand, p.targets, 30)
+        assert np.array_equal(res[i]["path"], ref["path"])
+        ep, er, ec = H.parity_metrics(p, res[i]["xi"], ref["xi"])
+        print(f"batch64[{i}] T={p.T} K={p.K}: pos {ep:.3e} rot {er:.3e} cost {ec:.3e}")
+        assert ep <= POS_TOL and er <= ROT_TOL and ec <= COST_TOL, (i, ep, er, ec)
+        with ctx.plan(p.robot, p.targets, p.cand, opts=opts) as plan:
+            plan.dp_search()
+            xi, _ = plan.lm_refine(30)
+        assert np.array_equal(xi, res[i]["xi"])

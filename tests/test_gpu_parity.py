@@ -111,6 +111,23 @@ def test_dp_search_with_node_penalty_and_ties(ctx):
     assert np.array_equal(path, path_ref) and best == best_ref
 
 
+def test_dp_search_list_fallback(ctx):
+    """The 20 'hub' candidates equal the ground truth, so they are the nearest
+    predecessors of every node, but carry a node cost of 50: each node's
+    16-entry nearest list holds only hubs and cannot prove the minimum, which
+    forces the exhaustive scan."""
+    p = H.small_problem(seed=12, T=24, K=64, sigma=0.3, frac=0.0)
+    cand = p.cand.copy()
+    cand[:20] = p.q_star[None]
+    extra = np.zeros((p.T, p.K))
+    extra[:, :20] = 50.0
+    path_ref, best_ref, _, _ = oracle.dp(cand, p.robot, extra=extra)
+    with ctx.plan(p.robot, p.targets, cand, node_pen=extra) as plan:
+        path, best, _ = plan.dp_search()
+    assert np.array_equal(path, path_ref) and best == best_ref
+    assert best < 50.0 and not np.any(path < 20)
+
+
 def test_dp_search_config2_full_size(ctx):
     p = H.with_targets(synth.config2())
     path_ref, best_ref, _, _ = oracle.dp(p.cand, p.robot)
