@@ -53,11 +53,55 @@ def parse():
     ap.add_argument("--duration", type=float, default=10.0, help="serve: stream length (s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain 1 GiB device copy three times: the known-size "
+                         "reference that scales the FETCH_SIZE / WRITE_SIZE counters")
     return ap.parse_args()
+
+
+def calibrate_copy():
+    import torch
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "device copy", "bytes_read": a.numel() * 8,
+                      "bytes_written": a.numel() * 8, "repeats": 3}))
+
+
+def kernel_sources_sha(files):
+    """Hash of the sources a kernel is built from; counter figures taken from a
+    different build of the kernel are not reported."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2309_09102_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when the kernel's sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_T300_K256.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except OSError:
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if not k or k.get("sources_sha") != kernel_sources_sha(k["sources"]):
+        return None
+    return k["bytes_per_launch"]
 
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); plans are "
               "independent, so several GPUs would shard whole requests with no collective.",
@@ -135,7 +179,7 @@ def main():
         dom, dom_ms, dom_flops = "dp_kernel", dp_ms, dp_flops
     achieved = dom_flops / (dom_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_ALU_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS, "traffic": measured_traffic(dom),
                 "avg_launch_ms": dom_ms}
 
     out = {
