@@ -49,8 +49,10 @@ Layout make_layout(int T, int K, bool extra) {
     const size_t t = (size_t)T, k = (size_t)K;
     L.cand = take(t * NJ * k * sizeof(float));
     L.extra = take(extra ? t * k * sizeof(double) : 0);
+    L.pen = take(t * k * sizeof(double));
     L.bp = take(t * k * sizeof(uint16_t));
-    L.topk = take(t * TOPM * k * sizeof(uint16_t));
+    L.topk = take(t * k * TOPM * sizeof(uint16_t));
+    L.topc = take(t * k * TOPM * sizeof(double));
     L.path = take(t * sizeof(int32_t));
     L.dp_out = take(8 * sizeof(double));
     L.targets = take(12 * t * sizeof(double));
@@ -161,7 +163,9 @@ static void fill_desc(cpf_plan *p, bool has_extra) {
     set_dev_ptr(D.cand, b + L.cand);
     set_dev_ptr(D.extra, has_extra ? b + L.extra : nullptr);
     set_dev_ptr(D.bp, b + L.bp);
+    set_dev_ptr(D.pen, b + L.pen);
     set_dev_ptr(D.topk, b + L.topk);
+    set_dev_ptr(D.topc, b + L.topc);
     set_dev_ptr(D.path, b + L.path);
     set_dev_ptr(D.dp_out, b + L.dp_out);
     set_dev_ptr(D.targets, b + L.targets);

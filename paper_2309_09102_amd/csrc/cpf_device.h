@@ -6,7 +6,9 @@
 //   cand     float  [T][7][K]   candidate joint values (Sec. III-A), lane = k
 //   extra    double [T][K]      optional caller search cost (Sec. III-B)
 //   bp       uint16 [T][K]      search back-pointers
-//   topk     uint16 [T][16][K]  nearest predecessors of each search node
+//   pen      double [T][K]      search node penalties
+//   topk     uint16 [T][K][16]  nearest predecessors of each search node
+//   topc     double [T][K][16]  their edges plus the node's penalty
 //   path     int32  [T]
 //   targets  double [12][T]     target poses (Sec. II): x y z, R row-major
 //   xi, xt   double [7][T]      trajectory master copy and LM trial point
@@ -64,7 +66,9 @@ struct DevPlan {
     CPF_GLOBAL const float *cand;
     CPF_GLOBAL const double *extra;
     CPF_GLOBAL uint16_t *bp;
-    CPF_GLOBAL uint16_t *topk;    // [T][TOPM][K] nearest predecessors of each node
+    CPF_GLOBAL double *pen;       // [T][K] node penalties
+    CPF_GLOBAL uint16_t *topk;    // [T][K][TOPM] nearest predecessors of each node
+    CPF_GLOBAL double *topc;      // [T][K][TOPM] their edges plus the node penalty
     CPF_GLOBAL int32_t *path;
     CPF_GLOBAL double *dp_out;    // [0] = B*, [1] = mjac of the seed, [2] = end node
     CPF_GLOBAL double *targets;

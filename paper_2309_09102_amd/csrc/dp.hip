@@ -12,17 +12,26 @@
 // e + pen, so the result does not depend on the order of evaluation.
 //
 // Two kernels:
-//  1. dp_topm_kernel (whole GPU, no stage dependency): for every node (t, k),
-//     the TOPM predecessors with the smallest (e_t(k',k), k'), in order.
+//  1. dp_topm_kernel (whole GPU, no stage dependency): the penalty of every
+//     node, and for every node (t, k) with t >= 1 the TOPM predecessors with
+//     the smallest (e_t(k',k), k'), in that order, with c = e + pen_t(k).
+//     The rounding of e + pen is monotone in e, so c ascends along the list.
 //  2. dp_kernel (one workgroup per plan, stages in sequence): node (t, k)
-//     first scans its TOPM list.  Every predecessor not in the list has
-//     e >= e_M (the list's last edge) and B >= beta = min_k' B_{t-1}(k'), so
-//     its value is at least max(beta, e_M + pen) (e + pen is monotone in e
-//     under rounding).  If that bound exceeds the best value found, or equals
-//     it with e_M >= the best edge (the list then also wins every tie), the
-//     list result is the exact minimum; otherwise the lane falls back to the
-//     full scan over all K predecessors.  Either way the answer equals the
-//     exhaustive minimum, bit for bit.
+//     takes the best of its list under the key (value, e, k'), where
+//     value = max(B_{t-1}(k'), c).  In list order (e, k') ascends, so the
+//     first entry of smallest value is the key minimum.  Every predecessor
+//     outside the list has e >= e_M (the list's last edge) and
+//     B >= beta = min_k' B_{t-1}(k'), so its value is at least
+//     lb = max(beta, c_M).  If lb > the list's best value, no outside
+//     predecessor reaches it; if lb equals it, an outside predecessor can
+//     only tie on value, and then loses on (e, k') because its e >= e_M >=
+//     the best entry's edge (an equal e comes with a larger k', since the
+//     list keeps the earliest k' of equal edges).  So lb >= best value proves
+//     the list result exact; otherwise the lane falls back to the full scan
+//     over all K predecessors.  Either way the answer equals the exhaustive
+//     minimum, bit for bit.  A stage costs one LDS gather of TOPM values per
+//     lane and one workgroup barrier; the lists of later stages are loaded
+//     ahead.
 #include <float.h>
 
 #include "cpf_device.h"
@@ -30,40 +39,51 @@
 
 namespace cpf {
 
-constexpr int DP_BS = 1024;        // serial kernel: one lane per destination (K <= 1024)
 constexpr int TOPM_BS = 256;       // list kernel: one lane per node of a stage tile
-
-__device__ __forceinline__ bool key_less(double v, double e, int k, double bv, double be, int bk) {
-    return v < bv || (v == bv && (e < be || (e == be && k < bk)));
-}
 
 // Edge change between a destination (registers) and a predecessor (7 values).
 template <typename Q>
-__device__ __forceinline__ double edge(const double qk[NJ], const Q *pq, int stride) {
+__device__ __forceinline__ double edge(const double qk[NJ], const Q *pq, long stride) {
     double e = fabs(qk[0] - (double)pq[0]);
 #pragma unroll
     for (int j = 1; j < NJ; ++j) e = fmax(e, fabs(qk[j] - (double)pq[j * stride]));
     return e;
 }
 
-// Grid: x = tile (stage t >= 1, block of TOPM_BS destinations), y = plan.
+// Node penalty: limit_penalty if any joint is within the margin of a limit,
+// plus the caller's cost of the node.
+__device__ __forceinline__ double node_penalty(const DevPlan &P, const double q[NJ], int t, int k) {
+    bool near = false;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+        near = near || (q[j] <= P.lo[j] + P.margin) || (q[j] >= P.hi[j] - P.margin);
+    const double ex = P.has_extra ? P.extra[(size_t)t * P.K + k] : 0.0;
+    return (near ? P.penalty : 0.0) + ex;
+}
+
+// Grid: x = tile (stage t, block of TOPM_BS destinations), y = plan.
 __global__ __launch_bounds__(TOPM_BS) void dp_topm_kernel(const DevPlan *__restrict__ plans) {
     const DevPlan &P = plans[blockIdx.y];
     const int T = P.T, K = P.K;
-    if (T <= 1 || K <= 0) return;
+    if (T <= 0 || K <= 0) return;
     const int nkb = (K + TOPM_BS - 1) / TOPM_BS;
-    const int t = 1 + blockIdx.x / nkb, kb = blockIdx.x % nkb;
+    const int t = blockIdx.x / nkb, kb = blockIdx.x % nkb;
     if (t >= T) return;
     extern __shared__ float qprev[];   // [7][K]: candidates of stage t-1
     const CPF_GLOBAL float *__restrict__ cand = P.cand;
-    for (int x = threadIdx.x; x < NJ * K; x += TOPM_BS)
-        qprev[x] = cand[(size_t)(t - 1) * NJ * K + x];
+    if (t > 0) {
+        for (int x = threadIdx.x; x < NJ * K; x += TOPM_BS)
+            qprev[x] = cand[(size_t)(t - 1) * NJ * K + x];
+    }
     __syncthreads();
     const int k = kb * TOPM_BS + threadIdx.x;
     if (k >= K) return;
     double qk[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) qk[j] = (double)cand[((size_t)t * NJ + j) * K + k];
+    const double pen = node_penalty(P, qk, t, k);
+    P.pen[(size_t)t * K + k] = pen;
+    if (t == 0) return;
     double le[TOPM];
     int li[TOPM];
 #pragma unroll
@@ -87,141 +107,183 @@ __global__ __launch_bounds__(TOPM_BS) void dp_topm_kernel(const DevPlan *__restr
             }
         }
     }
-    const int meff = K < TOPM ? K : TOPM;
+    // With K < TOPM the entries past K keep index 0 and an infinite edge;
+    // the serial pass reads only the first min(K, TOPM).
+    const size_t node = (size_t)t * K + k;
+    CPF_GLOBAL uint4 *ix = (CPF_GLOBAL uint4 *)(P.topk + node * TOPM);
+    uint32_t pk[TOPM / 2];
 #pragma unroll
-    for (int m = 0; m < TOPM; ++m)
-        if (m < meff) P.topk[((size_t)t * TOPM + m) * K + k] = (uint16_t)li[m];
+    for (int m = 0; m < TOPM / 2; ++m) pk[m] = (uint32_t)li[2 * m] | ((uint32_t)li[2 * m + 1] << 16);
+    ix[0] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+    ix[1] = make_uint4(pk[4], pk[5], pk[6], pk[7]);
+    CPF_GLOBAL double2 *cv = (CPF_GLOBAL double2 *)(P.topc + node * TOPM);
+#pragma unroll
+    for (int m = 0; m < TOPM / 2; ++m) cv[m] = make_double2(le[2 * m] + pen, le[2 * m + 1] + pen);
 }
 
-__global__ __launch_bounds__(DP_BS) void dp_kernel(const DevPlan *__restrict__ plans) {
+// One stage's list of a destination, in registers.
+// The destination's own candidate and penalty ride along for the rare full
+// scan, so that scan issues no per-lane memory loads of its own.
+struct StageList {
+    uint4 ix0, ix1;       // TOPM packed 16-bit predecessor indices
+    double c[TOPM];       // their edges plus the destination's penalty
+    float q[NJ];          // the destination's candidate
+    double pen;           // its penalty
+};
+
+__device__ __forceinline__ void load_list(const DevPlan &P, int t, int k, StageList &L) {
+    const int K = P.K;
+    const size_t node = (size_t)t * K + k;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) L.q[j] = P.cand[((size_t)t * NJ + j) * K + k];
+    L.pen = P.pen[node];
+    const CPF_GLOBAL uint4 *ix = (const CPF_GLOBAL uint4 *)(P.topk + node * TOPM);
+    L.ix0 = ix[0];
+    L.ix1 = ix[1];
+    const CPF_GLOBAL double2 *cv = (const CPF_GLOBAL double2 *)(P.topc + node * TOPM);
+#pragma unroll
+    for (int m = 0; m < TOPM / 2; ++m) {
+        const double2 v = cv[m];
+        L.c[2 * m] = v.x;
+        L.c[2 * m + 1] = v.y;
+    }
+}
+
+// Lane-to-lane move of a double by a DPP control (ALU only, no LDS); rows
+// outside row_mask keep their own value.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const int plo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROW_MASK, 0xf, false);
+    const int phi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROW_MASK, 0xf, false);
+    return __hiloint2double(phi, plo);
+}
+
+// Minimum over the 64 lanes of a wavefront (every lane active): within
+// quads, half rows and rows of 16 lanes, then row 0 into row 1 and row 2
+// into row 3 (lane 15's broadcast), then rows 0-1 into row 3 (lane 31's);
+// lane 63 ends up holding the minimum of all 64 lanes.
+__device__ __forceinline__ double wave_min(double v) {
+    auto mn = [](double a, double b) { return b < a ? b : a; };
+    v = mn(v, dpp_f64<0xb1, 0xf>(v));    // quad_perm [1,0,3,2]
+    v = mn(v, dpp_f64<0x4e, 0xf>(v));    // quad_perm [2,3,0,1]
+    v = mn(v, dpp_f64<0x141, 0xf>(v));   // row_half_mirror
+    v = mn(v, dpp_f64<0x140, 0xf>(v));   // row_mirror
+    v = mn(v, dpp_f64<0x142, 0xa>(v));   // row_bcast:15 into rows 1 and 3
+    v = mn(v, dpp_f64<0x143, 0xc>(v));   // row_bcast:31 into rows 2 and 3
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ int list_index(const StageList &L, int m) {
+    const uint4 &v = m < 8 ? L.ix0 : L.ix1;
+    const int w = (m & 7) >> 1;
+    const uint32_t word = w == 0 ? v.x : (w == 1 ? v.y : (w == 2 ? v.z : v.w));
+    return (int)((word >> ((m & 1) * 16)) & 0xffffu);
+}
+
+// One lane per destination; BS >= K threads.  AHEAD stages of lists are in
+// flight ahead of use (fewer with 1024 lanes, where registers are scarcer).
+template <int BS, int AHEAD>
+__global__ __launch_bounds__(BS) void dp_kernel(const DevPlan *__restrict__ plans) {
     const DevPlan &P = plans[blockIdx.x];
     const int T = P.T, K = P.K;
     if (T <= 0 || K <= 0) return;
-    extern __shared__ double prev[];   // [K][8]: q_{t-1}^k' (7) and B_{t-1}(k')
-    __shared__ double wmin[DP_BS / 64];
-    __shared__ double red[DP_BS];
+    __shared__ double Bb[2][MAX_K];          // B_{t-1} and B_t (ping-pong)
+    __shared__ double wmin[2][BS / 64];   // per-wave minima of each buffer
+    __shared__ double red[BS];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nwave = (int)(blockDim.x >> 6);
     const int k = tid;
     const bool owner = k < K;
     const int meff = K < TOPM ? K : TOPM;
-
-    double lom[NJ], him[NJ];
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-        lom[j] = P.lo[j] + P.margin;
-        him[j] = P.hi[j] - P.margin;
-    }
     const CPF_GLOBAL float *__restrict__ cand = P.cand;
+    CPF_GLOBAL uint16_t *__restrict__ bp = P.bp;
 
-    auto penalty = [&](const double *q, int t) -> double {
-        bool near = false;
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) near = near || (q[j] <= lom[j]) || (q[j] >= him[j]);
-        const double ex = (P.has_extra && owner) ? P.extra[(size_t)t * K + k] : 0.0;
-        return (near ? P.penalty : 0.0) + ex;
-    };
-    // beta = min over the values just written to prev (all waves call this)
-    auto stage_min = [&](double b) -> double {
-        double m = owner ? b : __builtin_inf();
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) m = fmin(m, __shfl_xor(m, off));
-        if (lane == 0) wmin[wave] = m;
+    // publish a stage's values and its minimum (one barrier)
+    auto publish = [&](int buf, double b) -> double {
+        if (owner) Bb[buf][k] = b;
+        const double m = wave_min(owner ? b : __builtin_inf());
+        if (lane == 0) wmin[buf][wave] = m;
         __syncthreads();
-        double r = wmin[0];
-#pragma unroll
-        for (int w = 1; w < DP_BS / 64; ++w) r = fmin(r, wmin[w]);
+        double r = wmin[buf][0];
+        for (int w = 1; w < nwave; ++w) r = fmin(r, wmin[buf][w]);
         return r;
     };
 
-    double qk[NJ];
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) qk[j] = owner ? (double)cand[(size_t)j * K + k] : 0.0;
-    double b0 = 0.0;
-    if (owner) {
-        b0 = penalty(qk, 0);
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) prev[k * 8 + j] = qk[j];
-        prev[k * 8 + 7] = b0;
-    }
-    double beta = stage_min(b0);   // includes the barrier that publishes prev
+    double beta = publish(0, owner ? P.pen[k] : 0.0);   // B_0 = pen_0
 
-    // candidates and predecessor lists of the next stage, loaded one stage ahead
-    float qn[NJ];
-    int ln[TOPM];
+    // One stage: the best of the list in `L`, the exactness check and, when
+    // it fails, the full scan; then `L` is refilled with the list AHEAD
+    // stages on (clamped to a valid node, so every lane loads and no branch
+    // separates the loads from their use).
+    const int kc = owner ? k : K - 1;
+    auto stage = [&](int t, StageList &L) {
+        const int cur = t & 1, prv = cur ^ 1;
+        double b[TOPM];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) qn[j] = (owner && T > 1) ? cand[((size_t)1 * NJ + j) * K + k] : 0.f;
-#pragma unroll
-    for (int m = 0; m < TOPM; ++m)
-        ln[m] = (owner && T > 1 && m < meff) ? P.topk[((size_t)1 * TOPM + m) * K + k] : 0;
-
-    for (int t = 1; t < T; ++t) {
-        double bv = __builtin_inf(), be = __builtin_inf();
+        for (int m = 0; m < TOPM; ++m) b[m] = Bb[prv][list_index(L, m)];
+        double bv = __builtin_inf();
         int bk = -1;
-        if (owner) {
-            int lc[TOPM];
 #pragma unroll
-            for (int j = 0; j < NJ; ++j) qk[j] = (double)qn[j];
-#pragma unroll
-            for (int m = 0; m < TOPM; ++m) lc[m] = ln[m];
-            if (t + 1 < T) {
-#pragma unroll
-                for (int j = 0; j < NJ; ++j) qn[j] = cand[((size_t)(t + 1) * NJ + j) * K + k];
-#pragma unroll
-                for (int m = 0; m < TOPM; ++m)
-                    if (m < meff) ln[m] = P.topk[((size_t)(t + 1) * TOPM + m) * K + k];
-            }
-            const double pen = penalty(qk, t);
-            double eM = 0.0;
-#pragma unroll
-            for (int m = 0; m < TOPM; ++m) {
-                if (m < meff) {
-                    const int kp = lc[m];
-                    const double *pq = prev + kp * 8;
-                    const double e = edge(qk, pq, 1);
-                    const double v = fmax(pq[7], e + pen);   // finite operands: exact max
-                    if (key_less(v, e, kp, bv, be, bk)) {
-                        bv = v;
-                        be = e;
-                        bk = kp;
-                    }
-                    eM = e;
-                }
-            }
-            const double lb = fmax(beta, eM + pen);
-            const bool exact = (meff == K) || (lb > bv) || (lb == bv && eM >= be);
-            if (!exact) {   // full scan over every predecessor
-                bv = __builtin_inf();
-                be = __builtin_inf();
-                bk = -1;
-                for (int kp = 0; kp < K; ++kp) {
-                    const double *pq = prev + kp * 8;
-                    const double e = edge(qk, pq, 1);
-                    const double v = fmax(pq[7], e + pen);
-                    const bool upd = (v < bv) | ((v == bv) & (e < be));
-                    bv = upd ? v : bv;
-                    be = upd ? e : be;
-                    bk = upd ? kp : bk;
-                }
-            }
-            P.bp[(size_t)t * K + k] = (uint16_t)(bk >= 0 ? bk : 0);
+        for (int m = 0; m < TOPM; ++m) {
+            const double v = fmax(b[m], L.c[m]);
+            const bool take = (m < meff) && (v < bv);
+            bv = take ? v : bv;
+            bk = take ? list_index(L, m) : bk;
         }
-        __syncthreads();   // every lane has finished reading prev
-        if (owner) {
+        double cM = L.c[0];
 #pragma unroll
-            for (int j = 0; j < NJ; ++j) prev[k * 8 + j] = qk[j];
-            prev[k * 8 + 7] = bv;
+        for (int m = 1; m < TOPM; ++m) cM = m < meff ? L.c[m] : cM;
+        const bool exact = (meff == K) || (fmax(beta, cM) >= bv);
+        if (owner && !exact) {   // full scan over every predecessor
+            const double pen = L.pen;
+            double qk[NJ];
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) qk[j] = (double)L.q[j];
+            const CPF_GLOBAL float *qp = cand + (size_t)(t - 1) * NJ * K;
+            bv = __builtin_inf();
+            double be = __builtin_inf();
+            bk = -1;
+            for (int kp = 0; kp < K; ++kp) {
+                const double e = edge(qk, qp + kp, K);
+                const double vv = fmax(Bb[prv][kp], e + pen);
+                const bool upd = (vv < bv) | ((vv == bv) & (e < be));
+                bv = upd ? vv : bv;
+                be = upd ? e : be;
+                bk = upd ? kp : bk;
+            }
         }
-        beta = stage_min(bv);
-        __syncthreads();   // wmin is rewritten by the next stage
+        if (owner) bp[(size_t)t * K + k] = (uint16_t)(bk >= 0 ? bk : 0);
+        load_list(P, min(t + AHEAD, T - 1), kc, L);
+        beta = publish(cur, bv);
+    };
+
+    // lists of the next AHEAD stages, in flight; buffer a serves the stages
+    // t with (t - 1) % AHEAD == a, so no list is ever copied
+    StageList buf[AHEAD];
+#pragma unroll
+    for (int a = 0; a < AHEAD; ++a) load_list(P, min(1 + a, T - 1), kc, buf[a]);
+    // whole rounds of AHEAD stages keep the loop body free of branches
+    // around the loads; the remaining stages follow
+    int t0 = 1;
+    for (; t0 + AHEAD <= T; t0 += AHEAD) {
+#pragma unroll
+        for (int a = 0; a < AHEAD; ++a) stage(t0 + a, buf[a]);
     }
+#pragma unroll
+    for (int a = 0; a < AHEAD; ++a)
+        if (t0 + a < T) stage(t0 + a, buf[a]);
 
     // End node: smallest (B_{T-1}(k), k); then follow the back-pointers.
+    const int last = (T - 1) & 1;
     if (tid < 64) {
         double bb = __builtin_inf();
         int bkk = 0x7fffffff;
         for (int kk = tid; kk < K; kk += 64) {
-            const double b = prev[kk * 8 + 7];
+            const double b = Bb[last][kk];
             if (b < bb) { bb = b; bkk = kk; }
         }
 #pragma unroll
@@ -238,7 +300,7 @@ __global__ __launch_bounds__(DP_BS) void dp_kernel(const DevPlan *__restrict__ p
             int cur = (bkk >= 0 && bkk < K) ? bkk : 0;
             P.path[T - 1] = cur;
             for (int t = T - 1; t > 0; --t) {
-                cur = P.bp[(size_t)t * K + cur];
+                cur = bp[(size_t)t * K + cur];
                 cur = cur < K ? cur : 0;
                 P.path[t - 1] = cur;
             }
@@ -248,7 +310,7 @@ __global__ __launch_bounds__(DP_BS) void dp_kernel(const DevPlan *__restrict__ p
 
     // Seed gather xi[j][t] = q_t^{path[t]}[j] and its mjac.
     double m = 0.0;
-    for (int t = tid; t < T; t += DP_BS) {
+    for (int t = tid; t < T; t += (int)blockDim.x) {
         const int kk = P.path[t];
 #pragma unroll
         for (int j = 0; j < NJ; ++j) P.xi[(size_t)j * T + t] = (double)cand[((size_t)t * NJ + j) * K + kk];
@@ -262,7 +324,7 @@ __global__ __launch_bounds__(DP_BS) void dp_kernel(const DevPlan *__restrict__ p
     }
     red[tid] = m;
     __syncthreads();
-    for (int s = DP_BS / 2; s > 0; s >>= 1) {
+    for (int s = (int)blockDim.x / 2; s > 0; s >>= 1) {
         if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
         __syncthreads();
     }
@@ -274,17 +336,20 @@ __global__ __launch_bounds__(DP_BS) void dp_kernel(const DevPlan *__restrict__ p
 }
 
 hipError_t dp_launch(const DevPlan *d_plans, int nplans, int maxK, int maxT, hipStream_t s) {
-    if (nplans <= 0) return hipSuccess;
-    if (maxT > 1) {
-        const int nkb = (maxK + TOPM_BS - 1) / TOPM_BS;
-        const dim3 grid((unsigned)((maxT - 1) * nkb), (unsigned)nplans);
-        hipLaunchKernelGGL(dp_topm_kernel, grid, dim3(TOPM_BS), (size_t)maxK * NJ * sizeof(float),
-                           s, d_plans);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    const size_t lds = (size_t)maxK * 8 * sizeof(double);
-    hipLaunchKernelGGL(dp_kernel, dim3(nplans), dim3(DP_BS), lds, s, d_plans);
+    if (nplans <= 0 || maxT <= 0 || maxK <= 0) return hipSuccess;
+    if (maxK > MAX_K) return hipErrorInvalidValue;
+    const int nkb = (maxK + TOPM_BS - 1) / TOPM_BS;
+    const dim3 grid((unsigned)(maxT * nkb), (unsigned)nplans);
+    hipLaunchKernelGGL(dp_topm_kernel, grid, dim3(TOPM_BS), (size_t)maxK * NJ * sizeof(float), s, d_plans);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // one lane per destination, whole wavefronts (the seed reduction needs a power of two)
+    int bs = 64;
+    while (bs < maxK) bs <<= 1;
+    if (bs <= 512)
+        hipLaunchKernelGGL((dp_kernel<512, 2>), dim3(nplans), dim3(bs), 0, s, d_plans);
+    else
+        hipLaunchKernelGGL((dp_kernel<1024, 1>), dim3(nplans), dim3(bs), 0, s, d_plans);
     return hipGetLastError();
 }
 
