@@ -58,11 +58,9 @@ Layout make_layout(int T, int K, bool extra) {
     L.targets = take(12 * t * sizeof(double));
     L.xi = take(NJ * t * sizeof(double));
     L.xt = take(NJ * t * sizeof(double));
-    L.A = take(NTRI * t * sizeof(double));
+    L.A = take(NBLK * t * sizeof(double));
     L.g = take(NJ * t * sizeof(double));
-    L.P = take(56 * t * sizeof(double));   // [T][7][8]
-    L.F = take(56 * t * sizeof(double));
-    L.y = take(NJ * t * sizeof(double));
+    L.cr = take(cr_doubles(T) * sizeof(double));
     L.dx = take(NJ * t * sizeof(double));
     L.rb = take(NJ * t * sizeof(double));
     L.st = take(sizeof(LMState));
@@ -173,9 +171,7 @@ static void fill_desc(cpf_plan *p, bool has_extra) {
     set_dev_ptr(D.xt, b + L.xt);
     set_dev_ptr(D.A, b + L.A);
     set_dev_ptr(D.g, b + L.g);
-    set_dev_ptr(D.P, b + L.P);
-    set_dev_ptr(D.F, b + L.F);
-    set_dev_ptr(D.y, b + L.y);
+    set_dev_ptr(D.cr, b + L.cr);
     set_dev_ptr(D.dx, b + L.dx);
     set_dev_ptr(D.rb, b + L.rb);
     set_dev_ptr(D.st, b + L.st);

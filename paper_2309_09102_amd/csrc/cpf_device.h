@@ -12,11 +12,10 @@
 //   path     int32  [T]
 //   targets  double [12][T]     target poses (Sec. II): x y z, R row-major
 //   xi, xt   double [7][T]      trajectory master copy and LM trial point
-//   A        double [28][T]     w_p J_t^T J_t, packed lower triangle
+//   A        double [T][49]     w_p J_t^T J_t, whole 7x7 blocks
 //   g        double [7][T]      gradient of the cost
-//   P        double [T][7][8]   inverse Schur blocks of the block LDL^T (row = 64 B)
-//   F        double [T][7][8]   coupling of each block to the previous chunk's end
-//   y, dx, rb double [7][T]     forward sweep, step, refinement residual
+//   cr       double             cyclic-reduction levels of the LM system (cr_doubles(T))
+//   dx, rb   double [7][T]      step, refinement residual
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -72,7 +71,7 @@ struct DevPlan {
     CPF_GLOBAL int32_t *path;
     CPF_GLOBAL double *dp_out;    // [0] = B*, [1] = mjac of the seed, [2] = end node
     CPF_GLOBAL double *targets;
-    CPF_GLOBAL double *xi, *xt, *A, *g, *P, *F, *y, *dx, *rb;
+    CPF_GLOBAL double *xi, *xt, *A, *g, *cr, *dx, *rb;
     CPF_GLOBAL LMState *st;
     CPF_GLOBAL double *report;    // [0] max pos err, [1] max rot err, [2] mjac
 };
@@ -208,5 +207,30 @@ __device__ __forceinline__ void pose_residual(const S X[3], const S Y[3], const 
 }
 
 __host__ __device__ constexpr int tri_index(int i, int j) { return i * (i + 1) / 2 + j; }  // i >= j
+
+// Storage of one cyclic-reduction level with n blocks (no = n / 2 odd
+// blocks, ne = n - no even ones), in doubles, every block whole (49) or a
+// whole vector (7): the sub-diagonal blocks E (49 n), the even blocks'
+// diagonal block and right-hand side (49 ne + 7 ne), the solution (7 n), and
+// per odd block the inverse Cholesky factor, the two coupling products, the
+// two Schur contributions (5 x 49), the transformed right-hand side and its
+// two contributions (3 x 7); the last level (n = 1) keeps its factor in the
+// first odd slot.
+__host__ __device__ inline size_t cr_level_doubles(int n) {
+    const size_t no = (size_t)(n / 2), ne = (size_t)n - no, nod = no > 0 ? no : 1;
+    return 56 * (size_t)n + 56 * ne + 266 * nod;
+}
+
+// All levels of a path of T waypoints (n halves, rounding up, down to 1).
+__host__ __device__ inline size_t cr_doubles(int T) {
+    size_t total = 0;
+    int n = T;
+    while (true) {
+        total += cr_level_doubles(n);
+        if (n <= 1) break;
+        n = (n + 1) / 2;
+    }
+    return total;
+}
 
 }  // namespace cpf

@@ -12,10 +12,10 @@
 //
 // One workgroup per plan runs all iterations without returning to the host.
 // Kinematics (FK, J, residuals, J^T J) run in S = float or double; the
-// assembly, the solve and every cross-waypoint sum are FP64.  The solve is a
-// block LDL^T sweep  S_t = D_t - w^2 S_{t-1}^{-1}, partitioned over the
-// wavefronts of the workgroup (7x7 blocks one element per lane, inverses by
-// Gauss-Jordan), then FP64 iterative refinement against the same H.
+// assembly, the solve and every cross-waypoint sum are FP64.  The solve is
+// block cyclic reduction (a Cholesky factor per eliminated block, one lane
+// per 7x7 block, log2 T levels), then FP64 iterative refinement against the
+// same H reusing the stored factors.
 #include <float.h>
 
 #include "cpf_device.h"
@@ -133,7 +133,9 @@ __device__ __forceinline__ double linearise(const DevPlan &P, const RobotT<S> &r
                 S s = J[0][i] * J[0][j];
 #pragma unroll
                 for (int k = 1; k < 6; ++k) s += J[k][i] * J[k][j];
-                P.A[(size_t)tri_index(i, j) * T + t] = w_p * (double)s;
+                const double v = w_p * (double)s;
+                P.A[(size_t)t * NBLK + i * NJ + j] = v;
+                if (i != j) P.A[(size_t)t * NBLK + j * NJ + i] = v;
             }
         }
 #pragma unroll
@@ -155,8 +157,7 @@ __device__ __forceinline__ double linearise(const DevPlan &P, const RobotT<S> &r
 
 // Element (i, j) of D_t = A_t + (w_s c_t + lambda) I.
 __device__ __forceinline__ double d_elem(const DevPlan &P, int T, int t, int i, int j, double lam) {
-    const int hi = i > j ? i : j, lo = i > j ? j : i;
-    double v = P.A[(size_t)tri_index(hi, lo) * T + t];
+    double v = P.A[(size_t)t * NBLK + i * NJ + j];
     if (i == j) {
         const int ct = (t > 0) + (t + 1 < T);
         v += P.w_s * ct + lam;
@@ -165,362 +166,581 @@ __device__ __forceinline__ double d_elem(const DevPlan &P, int T, int t, int i, 
 }
 
 // ---------------------------------------------------------------------------
-// 7x7 blocks on a wavefront: lane l < 49 holds element (l / 7, l % 7); lanes
-// 49..63 hold nothing and never write.  A vector is held in lanes 0..6.
-// Block products exchange operands through a per-wavefront LDS scratch (one
-// write of the block, then each lane reads its row and column); LDS
-// instructions of one wavefront execute in program order, so no barrier is
-// needed.  Blocks live in HBM as [T][7][8] doubles.
+// Block-tridiagonal solve by cyclic reduction.
+//
+// Level 0 is the LM system: diagonal blocks D_t, sub-diagonal blocks
+// E_t = -w_s I.  A level with n blocks eliminates its odd blocks i:
+//   L_i L_i^T = D_i (Cholesky), Li = L_i^{-1},
+//   W_i = Li E_i,  V_i = Li E_{i+1}^T,
+//   D'_{i-1} -= W_i^T W_i,  D'_{i+1} -= V_i^T V_i,
+//   E'_{(i+1)/2} = -V_i^T W_i        (new coupling of blocks i+1 and i-1),
+//   s_i = Li r_i,  r'_{i-1} -= W_i^T s_i,  r'_{i+1} -= V_i^T s_i,
+// and its even blocks j form level l+1 as block j/2.  At the single block of
+// the last level x = Li^T Li r; going back down, every odd block recovers
+//   x_i = Li^T (s_i - W_i x_{i-1} - V_i x_{i+1}).
+// At level 0 (E = -w I) this is W_i = V_i = -w Li, the Schur contribution
+// w^2 Li^T Li on both neighbours and E' = -w^2 Li^T Li.  The factors of all
+// levels stay in the plan's `cr` storage, so a further right-hand side (the
+// refinement) costs only the right-hand-side and back-substitution rounds.
+//
+// Each round is one pass over a level followed by one workgroup barrier.
+// Level 0 runs one lane per block.  Above it, 7 lanes share an odd block
+// (lane c owns column c of W, V and of the products) and exchange columns
+// through a per-group LDS area; LDS instructions of one wavefront complete
+// in order, so a wave barrier is the only synchronisation the exchange
+// needs.  Blocks are stored whole (7 x 7 row-major, 49 doubles, symmetric
+// ones in full and factors with zeros above the diagonal) one after another,
+// so a lane reaches every element of its block, row or column from one
+// per-lane address plus an instruction immediate.
 // ---------------------------------------------------------------------------
 
-struct Lane {
-    int l, i, j, r;   // lane, element row / column, vector index
-    bool el;          // lane holds an element
+constexpr int CR_GPW = 9;                          // 7-lane groups per wavefront (lane 63 idles)
+constexpr int CR_GROUPS = (LM_BS / 64) * CR_GPW;   // groups per workgroup
+constexpr int CR_EX = 2 * NBLK;                    // LDS doubles per group
+
+struct CRLevel {
+    CPF_GLOBAL double *p;
+    int n, no, ne, nod;
+    __device__ CPF_GLOBAL double *E() const { return p; }
+    __device__ CPF_GLOBAL double *DE() const { return p + 49 * (size_t)n; }
+    __device__ CPF_GLOBAL double *rE() const { return DE() + 49 * (size_t)ne; }
+    __device__ CPF_GLOBAL double *X() const { return rE() + 7 * (size_t)ne; }
+    __device__ CPF_GLOBAL double *Li() const { return X() + 7 * (size_t)n; }
+    __device__ CPF_GLOBAL double *W() const { return Li() + 49 * (size_t)nod; }
+    __device__ CPF_GLOBAL double *V() const { return W() + 49 * (size_t)nod; }
+    __device__ CPF_GLOBAL double *Z1() const { return V() + 49 * (size_t)nod; }
+    __device__ CPF_GLOBAL double *Z2() const { return Z1() + 49 * (size_t)nod; }
+    __device__ CPF_GLOBAL double *s() const { return Z2() + 49 * (size_t)nod; }
+    __device__ CPF_GLOBAL double *c1() const { return s() + 7 * (size_t)nod; }
+    __device__ CPF_GLOBAL double *c2() const { return c1() + 7 * (size_t)nod; }
 };
 
-__device__ __forceinline__ Lane lane_info() {
-    Lane L;
-    L.l = threadIdx.x & 63;
-    L.el = L.l < NBLK;
-    L.i = L.el ? L.l / NJ : NJ - 1;
-    L.j = L.el ? L.l % NJ : NJ - 1;
-    L.r = L.l < NJ ? L.l : NJ - 1;
+__device__ __forceinline__ CRLevel cr_level(CPF_GLOBAL double *base, int T, int lev) {
+    int n = T;
+    size_t off = 0;
+    for (int l = 0; l < lev; ++l) {
+        off += cr_level_doubles(n);
+        n = (n + 1) / 2;
+    }
+    CRLevel L;
+    L.p = base + off;
+    L.n = n;
+    L.no = n / 2;
+    L.ne = n - L.no;
+    L.nod = L.no > 0 ? L.no : 1;
     return L;
 }
 
-struct WaveScratch {
-    double m0[64], m1[64], v[8];
+__device__ __forceinline__ int cr_top(int T) {
+    int lev = 0;
+    for (int n = T; n > 1; n = (n + 1) / 2) ++lev;
+    return lev;
+}
+
+// Block `idx` of an array of whole blocks of `sz` doubles.
+__device__ __forceinline__ CPF_GLOBAL double *blk(CPF_GLOBAL double *a, int idx, int sz) {
+    return a + (size_t)idx * sz;
+}
+__device__ __forceinline__ const CPF_GLOBAL double *blk(const CPF_GLOBAL double *a, int idx, int sz) {
+    return a + (size_t)idx * sz;
+}
+
+// In place: the packed lower triangle of an SPD block becomes the inverse of
+// its Cholesky factor.  Reciprocal square roots: hardware estimate and two
+// Newton steps.  ok becomes false on a pivot that is not positive.
+__device__ __forceinline__ void chol_inverse(double a[NTRI], bool &ok) {
+    double rd[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        double d = a[tri_index(j, j)];
+#pragma unroll
+        for (int k = 0; k < j; ++k) d = fma(-a[tri_index(j, k)], a[tri_index(j, k)], d);
+        ok = ok && (d > 0.0);
+        const double dd = d > 0.0 ? d : 1.0;
+        double r = __builtin_amdgcn_rsq(dd);
+        r = r * fma(-0.5 * dd, r * r, 1.5);
+        r = r * fma(-0.5 * dd, r * r, 1.5);
+        rd[j] = r;
+#pragma unroll
+        for (int i = j + 1; i < NJ; ++i) {
+            double s = a[tri_index(i, j)];
+#pragma unroll
+            for (int k = 0; k < j; ++k) s = fma(-a[tri_index(i, k)], a[tri_index(j, k)], s);
+            a[tri_index(i, j)] = s * r;
+        }
+    }
+    // L^{-1}, column by column: M_jj = 1 / L_jj, M_ij = -(sum_{k=j}^{i-1} L_ik M_kj) / L_ii.
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        a[tri_index(j, j)] = rd[j];
+#pragma unroll
+        for (int i = j + 1; i < NJ; ++i) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = j; k < i; ++k) s = fma(a[tri_index(i, k)], a[tri_index(k, j)], s);
+            a[tri_index(i, j)] = -s * rd[i];
+        }
+    }
+}
+
+// y = M x and y = M^T x for a packed lower-triangular M.
+__device__ __forceinline__ void tri_mv(const double M[NTRI], const double x[NJ], double y[NJ]) {
+#pragma unroll
+    for (int a = 0; a < NJ; ++a) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k <= a; ++k) s = fma(M[tri_index(a, k)], x[k], s);
+        y[a] = s;
+    }
+}
+__device__ __forceinline__ void tri_tmv(const double M[NTRI], const double x[NJ], double y[NJ]) {
+#pragma unroll
+    for (int a = 0; a < NJ; ++a) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = a; k < NJ; ++k) s = fma(M[tri_index(k, a)], x[k], s);
+        y[a] = s;
+    }
+}
+
+// Lower triangle of a whole block / a whole block from a lower triangle
+// (zeros above the diagonal, or mirrored when sym).
+__device__ __forceinline__ void ld_lower(const CPF_GLOBAL double *b, double m[NTRI]) {
+#pragma unroll
+    for (int a = 0; a < NJ; ++a)
+#pragma unroll
+        for (int k = 0; k <= a; ++k) m[tri_index(a, k)] = b[a * NJ + k];
+}
+__device__ __forceinline__ void st_full(CPF_GLOBAL double *b, const double m[NTRI], bool sym, double scale) {
+#pragma unroll
+    for (int a = 0; a < NJ; ++a)
+#pragma unroll
+        for (int k = 0; k < NJ; ++k)
+            b[a * NJ + k] = k <= a ? scale * m[tri_index(a, k)] : (sym ? scale * m[tri_index(k, a)] : 0.0);
+}
+
+// Level-0 diagonal block t (lower triangle): w_p J^T J + (w_s c_t + lambda) I.
+__device__ __forceinline__ void level0_D(const DevPlan &P, int T, double lam, int t, double D[NTRI]) {
+    ld_lower(blk(P.A, t, NBLK), D);
+    const double dg = P.w_s * ((t > 0) + (t + 1 < T)) + lam;
+#pragma unroll
+    for (int a = 0; a < NJ; ++a) D[tri_index(a, a)] += dg;
+}
+
+// Neighbour slots on level lev-1 of block j of level lev: the odd blocks
+// 2j+1 (slot j) and 2j-1 (slot j-1); a missing one is read at a valid slot
+// and masked, so that all loads of a block are issued together.
+struct CRNbr {
+    bool has_r, has_l;
+    int jr, jl;
 };
-
-// The wave barriers keep the compiler from moving scratch reads of the
-// previous product past this write, or this product's reads before it.
-__device__ __forceinline__ void put(double *buf, const Lane &L, double x) {
-    __builtin_amdgcn_wave_barrier();
-    if (L.el) buf[L.i * 8 + L.j] = x;
-    __builtin_amdgcn_wave_barrier();
+__device__ __forceinline__ CRNbr cr_nbr(const CRLevel &Lp, int j) {
+    CRNbr q;
+    q.has_r = 2 * j + 1 < Lp.n;
+    q.has_l = j >= 1;
+    q.jr = q.has_r ? j : 0;
+    q.jl = q.has_l ? j - 1 : 0;
+    return q;
 }
 
-__device__ __forceinline__ void put_vec(double *buf, const Lane &L, double x) {
-    __builtin_amdgcn_wave_barrier();
-    if (L.l < NJ) buf[L.l] = x;
-    __builtin_amdgcn_wave_barrier();
-}
-
-// element (i, j) of A B
-__device__ __forceinline__ double mm(double A, double B, const Lane &L, WaveScratch &ws) {
-    put(ws.m0, L, A);
-    put(ws.m1, L, B);
-    double s = 0.0;
+// Block j of level lev >= 1 (one lane): lower triangle of its diagonal
+// block and its right-hand side, formed from level lev-1.
+__device__ __forceinline__ void cr_form_lane(const DevPlan &P, int T, double lam, const CRLevel &Lp, int lev, int j,
+                                             bool factor, const CPF_GLOBAL double *rhs, double sgn, double D[NTRI],
+                                             double r[NJ]) {
+    const CRNbr q = cr_nbr(Lp, j);
+    const CPF_GLOBAL double *Z2 = lev == 1 ? Lp.Z1() : Lp.Z2();   // level 0: Z1 = Z2
+    const CPF_GLOBAL double *c2 = lev == 1 ? Lp.c1() : Lp.c2();
+    if (factor) {
+        if (lev == 1) level0_D(P, T, lam, 2 * j, D);
+        else ld_lower(blk(Lp.DE(), j, NBLK), D);
+        const CPF_GLOBAL double *zr = blk(Lp.Z1(), q.jr, NBLK), *zl = blk(Z2, q.jl, NBLK);
 #pragma unroll
-    for (int k = 0; k < NJ; ++k) s += ws.m0[L.i * 8 + k] * ws.m1[k * 8 + L.j];
-    return s;
-}
-
-// element (i, j) of A B^T
-__device__ __forceinline__ double mm_bt(double A, double B, const Lane &L, WaveScratch &ws) {
-    put(ws.m0, L, A);
-    put(ws.m1, L, B);
-    double s = 0.0;
+        for (int a = 0; a < NJ; ++a)
 #pragma unroll
-    for (int k = 0; k < NJ; ++k) s += ws.m0[L.i * 8 + k] * ws.m1[L.j * 8 + k];
-    return s;
-}
-
-// (M v)_r in lane r < 7
-__device__ __forceinline__ double mv(double M, double v, const Lane &L, WaveScratch &ws) {
-    put(ws.m0, L, M);
-    put_vec(ws.v, L, v);
-    double s = 0.0;
+            for (int k = 0; k <= a; ++k) {
+                const double vr = zr[a * NJ + k], vl = zl[a * NJ + k];
+                D[tri_index(a, k)] = D[tri_index(a, k)] - (q.has_r ? vr : 0.0) - (q.has_l ? vl : 0.0);
+            }
+    }
+    const CPF_GLOBAL double *cr_ = blk(Lp.c1(), q.jr, NJ), *cl = blk(c2, q.jl, NJ);
+    const CPF_GLOBAL double *rb = lev == 1 ? nullptr : blk(Lp.rE(), j, NJ);
 #pragma unroll
-    for (int k = 0; k < NJ; ++k) s += ws.m0[L.r * 8 + k] * ws.v[k];
-    return s;
+    for (int e = 0; e < NJ; ++e) {
+        const double r0 = lev == 1 ? sgn * rhs[(size_t)e * T + 2 * j] : rb[e];
+        const double vr = cr_[e], vl = cl[e];
+        r[e] = r0 - (q.has_r ? vr : 0.0) - (q.has_l ? vl : 0.0);
+    }
 }
 
-// (M^T v)_r in lane r < 7
-__device__ __forceinline__ double mtv(double M, double v, const Lane &L, WaveScratch &ws) {
-    put(ws.m0, L, M);
-    put_vec(ws.v, L, v);
-    double s = 0.0;
+// Column c of the diagonal block j of level lev >= 1 and entry c of its
+// right-hand side (the share of lane c of a group).
+__device__ __forceinline__ void cr_form_col(const DevPlan &P, int T, double lam, const CRLevel &Lp, int lev, int j,
+                                            int c, bool factor, const CPF_GLOBAL double *rhs, double sgn,
+                                            double d[NJ], double &rc) {
+    const CRNbr q = cr_nbr(Lp, j);
+    const CPF_GLOBAL double *Z2 = lev == 1 ? Lp.Z1() : Lp.Z2();
+    const CPF_GLOBAL double *c2 = lev == 1 ? Lp.c1() : Lp.c2();
+    if (factor) {
+        const int t = 2 * j;
+        const CPF_GLOBAL double *b0 = lev == 1 ? blk(P.A, t, NBLK) : blk(Lp.DE(), j, NBLK);
+        const double dg = lev == 1 ? P.w_s * ((t > 0) + (t + 1 < T)) + lam : 0.0;
+        const CPF_GLOBAL double *zr = blk(Lp.Z1(), q.jr, NBLK) + c, *zl = blk(Z2, q.jl, NBLK) + c;
+        b0 += c;
 #pragma unroll
-    for (int k = 0; k < NJ; ++k) s += ws.m0[k * 8 + L.r] * ws.v[k];
-    return s;
+        for (int a = 0; a < NJ; ++a) {
+            const double v = b0[a * NJ] + (a == c ? dg : 0.0);
+            const double vr = zr[a * NJ], vl = zl[a * NJ];
+            d[a] = v - (q.has_r ? vr : 0.0) - (q.has_l ? vl : 0.0);
+        }
+    }
+    const double r0 = lev == 1 ? sgn * rhs[(size_t)c * T + 2 * j] : blk(Lp.rE(), j, NJ)[c];
+    const double vr = blk(Lp.c1(), q.jr, NJ)[c], vl = blk(c2, q.jl, NJ)[c];
+    rc = r0 - (q.has_r ? vr : 0.0) - (q.has_l ? vl : 0.0);
 }
 
-// In-place Gauss-Jordan inverse of a symmetric positive definite block.
-// Pivot k: a_kk, the lane's a_ik and a_kj are read back from the scratch.
-// ok becomes false on a non-positive pivot.
-__device__ __forceinline__ double gj_inverse(double a, const Lane &L, WaveScratch &ws, bool &ok) {
+// Odd block i = 2h+1 of level 0 (one lane): factor, Schur contribution and
+// coupling of level 1 (factor only), s and its contribution.
+__device__ __forceinline__ void cr_odd_level0(const DevPlan &P, int T, double lam, const CRLevel &L0,
+                                              const CRLevel &L1, int h, bool factor, const CPF_GLOBAL double *rhs,
+                                              double sgn, bool &ok) {
+    const int i = 2 * h + 1;
+    const double w = P.w_s;
+    double Li[NTRI];
+    if (factor) {
+        level0_D(P, T, lam, i, Li);
+        chol_inverse(Li, ok);
+        st_full(blk(L0.Li(), h, NBLK), Li, false, 1.0);
+        double Pm[NTRI];   // Li^T Li
+#pragma unroll
+        for (int a = 0; a < NJ; ++a)
+#pragma unroll
+            for (int b = 0; b <= a; ++b) {
+                double s = 0.0;
+#pragma unroll
+                for (int k = a; k < NJ; ++k) s = fma(Li[tri_index(k, a)], Li[tri_index(k, b)], s);
+                Pm[tri_index(a, b)] = s;
+            }
+        const double w2 = w * w;
+        st_full(blk(L0.Z1(), h, NBLK), Pm, true, w2);
+        if (i + 1 < L0.n) st_full(blk(L1.E(), (i + 1) / 2, NBLK), Pm, true, -w2);
+    } else {
+        ld_lower(blk(L0.Li(), h, NBLK), Li);
+    }
+    double r[NJ], s[NJ], c[NJ];
+#pragma unroll
+    for (int e = 0; e < NJ; ++e) r[e] = sgn * rhs[(size_t)e * T + i];
+    tri_mv(Li, r, s);
+    tri_tmv(Li, s, c);
+    CPF_GLOBAL double *so = blk(L0.s(), h, NJ), *co = blk(L0.c1(), h, NJ);
+#pragma unroll
+    for (int e = 0; e < NJ; ++e) {
+        so[e] = s[e];
+        co[e] = -w * c[e];   // W^T s with W = -w Li
+    }
+}
+
+// Even block j = 2 jj of level lev >= 1 (one lane): its diagonal block and
+// right-hand side, kept for level lev+1 (as block jj).
+__device__ __forceinline__ void cr_even(const DevPlan &P, int T, double lam, const CRLevel &Lp, const CRLevel &L,
+                                        int lev, int jj, bool factor, const CPF_GLOBAL double *rhs, double sgn) {
+    double D[NTRI], r[NJ];
+    cr_form_lane(P, T, lam, Lp, lev, 2 * jj, factor, rhs, sgn, D, r);
+    if (factor) st_full(blk(L.DE(), jj, NBLK), D, true, 1.0);
+    CPF_GLOBAL double *ro = blk(L.rE(), jj, NJ);
+#pragma unroll
+    for (int e = 0; e < NJ; ++e) ro[e] = r[e];
+}
+
+// Last level (one block, one lane): factor (or reuse) and x = Li^T Li r.
+__device__ __forceinline__ void cr_top_solve(const DevPlan &P, int T, double lam, const CRLevel &Lp,
+                                             const CRLevel &L, int lev, bool factor, const CPF_GLOBAL double *rhs,
+                                             double sgn, CPF_GLOBAL double *out, bool &ok) {
+    double Li[NTRI], r[NJ], s[NJ], x[NJ];
+    if (lev == 0) {   // a single waypoint
+        if (factor) level0_D(P, T, lam, 0, Li);
+#pragma unroll
+        for (int e = 0; e < NJ; ++e) r[e] = sgn * rhs[(size_t)e * T];
+    } else {
+        cr_form_lane(P, T, lam, Lp, lev, 0, factor, rhs, sgn, Li, r);
+    }
+    if (factor) {
+        chol_inverse(Li, ok);
+        st_full(blk(L.Li(), 0, NBLK), Li, false, 1.0);
+    } else {
+        ld_lower(blk(L.Li(), 0, NBLK), Li);
+    }
+    tri_mv(Li, r, s);
+    tri_tmv(Li, s, x);
+#pragma unroll
+    for (int e = 0; e < NJ; ++e) {
+        if (lev == 0) out[(size_t)e * T] = x[e];
+        else blk(L.X(), 0, NJ)[e] = x[e];
+    }
+}
+
+__device__ __forceinline__ void group_sync() { __builtin_amdgcn_wave_barrier(); }
+
+// Odd block i = 2h+1 of level lev >= 1, factor round (group, lane c).
+__device__ __forceinline__ void cr_odd_factor(const DevPlan &P, int T, double lam, const CRLevel &Lp,
+                                              const CRLevel &L, const CRLevel &Ln, int lev, int h, int c,
+                                              const CPF_GLOBAL double *rhs, double sgn, double *ex, bool &ok) {
+    const int i = 2 * h + 1;
+    const bool right = i + 1 < L.n;
+    // column c of E_i and row c of E_{i+1}, loaded first (used after the factor)
+    const CPF_GLOBAL double *Ei = blk(L.E(), i, NBLK) + c;
+    const CPF_GLOBAL double *Er = blk(L.E(), right ? i + 1 : i, NBLK) + c * NJ;
+    double e[NJ], f[NJ];
 #pragma unroll
     for (int k = 0; k < NJ; ++k) {
-        put(ws.m0, L, a);
-        const double akk = ws.m0[k * 9];
-        const double aik = ws.m0[L.i * 8 + k];
-        const double akj = ws.m0[k * 8 + L.j];
-        ok = ok && (akk > 0.0);
-        // reciprocal: hardware estimate refined by one Newton step
-        double rc = __builtin_amdgcn_rcp(akk);
-        rc = fma(rc, fma(-akk, rc, 1.0), rc);
-        double na;
-        if (L.i == k) na = (L.j == k) ? rc : akj * rc;
-        else if (L.j == k) na = -aik * rc;
-        else na = a - aik * (akj * rc);
-        a = na;
+        e[k] = Ei[k * NJ];
+        const double fk = Er[k];
+        f[k] = right ? fk : 0.0;
     }
-    return a;
-}
-
-__device__ __forceinline__ double blk_ld(const CPF_GLOBAL double *base, int t, const Lane &L, int lo, int hi) {
-    return (t >= lo && t <= hi && L.el) ? base[(size_t)t * 56 + L.i * 8 + L.j] : 0.0;
-}
-
-__device__ __forceinline__ void blk_st(CPF_GLOBAL double *base, int t, const Lane &L, double x) {
-    if (L.el) base[(size_t)t * 56 + L.i * 8 + L.j] = x;
-}
-
-__device__ __forceinline__ double vec_ld(const CPF_GLOBAL double *base, int T, const Lane &L, int t, int lo,
-                                         int hi) {
-    return (t >= lo && t <= hi) ? base[(size_t)L.r * T + t] : 0.0;
-}
-
-__device__ __forceinline__ double d_ld(const DevPlan &P, int T, int t, const Lane &L, int lo, int hi,
-                                       double lam) {
-    return (t >= lo && t <= hi) ? d_elem(P, T, t, L.i, L.j, lam) : 0.0;
-}
-
-// ---------------------------------------------------------------------------
-// Partitioned solve.  The waypoints are split into C contiguous chunks
-// [s_c, e_c], one per wavefront.  Within a chunk, block Gaussian elimination
-// from s_c onwards treats the previous chunk's last block z_{c-1} = x_{e_{c-1}}
-// as an external unknown:
-//   S_t x_t - w x_{t+1} = y_t + F_t z_{c-1},  S_t = D_t - w^2 P_{t-1},
-//   P_t = S_t^{-1},  y_t = b_t + w P_{t-1} y_{t-1},  F_t = w P_{t-1} F_{t-1},
-//   F_{s_c} = w I (zero for the first chunk).
-// Back-substituting from the chunk's last block z_c gives, at its first block,
-//   x_{s_c} = a_c + G_c z_{c-1} + (F_{e_c}^T / w) z_c,
-//   a_t = P_t (y_t + w a_{t+1}),  G_t = P_t (F_t + w G_{t+1}),  a_e = G_e = 0.
-// The last rows of the chunks then form a symmetric block-tridiagonal system
-// in z_0 .. z_{C-1} (the Schur complement on the chunk ends):
-//   M_c = S_{e_c} - w G_{c+1},  sub-diagonal -F_{e_c},  r_c = y_{e_c} + w a_{c+1},
-// solved by one wavefront with the same LDL^T sweep, after which every chunk
-// recovers its interior: x_t = P_t (y_t + F_t z_{c-1} + w x_{t+1}).
-// With C = 1 this is the plain block LDL^T sweep over the whole path.
-// ---------------------------------------------------------------------------
-
-constexpr int MAX_CHUNKS = LM_BS / 64;
-
-struct ChunkShared {
-    double Pi[MAX_CHUNKS][64];   // S_{e_c}, then Pi_c = Sigma_c^{-1}
-    double G[MAX_CHUNKS][64];    // G_c at the chunk's first block
-    double y[MAX_CHUNKS][8];     // y_{e_c}, then rho_c
-    double a[MAX_CHUNKS][8];     // a_c at the chunk's first block
-    double z[MAX_CHUNKS][8];     // chunk-end solution z_c
-    WaveScratch ws[MAX_CHUNKS];
-    int bad;
-};
-
-__device__ __forceinline__ void chunk_bounds(int T, int C, int c, int &s, int &e) {
-    s = (int)(((long long)c * T) / C);
-    e = (int)(((long long)(c + 1) * T) / C) - 1;
-}
-
-// Reduced system on the chunk ends (wave 0).  With `factor`, Sigma_c =
-// M_c - F_{e_c} Pi_{c-1} F_{e_c}^T is factored (Pi_c kept in sh.Pi); then
-// rho / z are solved from sh.y (y_{e_c}) and sh.a (a_c).
-__device__ __forceinline__ void reduced_solve(const DevPlan &P, int T, int C, bool factor, ChunkShared &sh,
-                              bool &ok) {
-    const Lane L = lane_info();
-    WaveScratch &ws = sh.ws[0];
-    const double w = P.w_s;
-    const int ij = L.i * 8 + L.j;
-    double pi_prev = 0.0, rho_prev = 0.0;
-    for (int cc = 0; cc < C; ++cc) {
-        int s, e;
-        chunk_bounds(T, C, cc, s, e);
-        const double Fe = cc > 0 ? blk_ld(P.F, e, L, 0, T - 1) : 0.0;   // F_{e_c}
-        double pi;
-        if (factor) {
-            double M = sh.Pi[cc][ij];
-            if (cc + 1 < C) M -= w * sh.G[cc + 1][ij];
-            if (cc > 0) M -= mm_bt(mm(Fe, pi_prev, L, ws), Fe, L, ws);   // F Pi F^T
-            pi = gj_inverse(M, L, ws, ok);
-            if (L.el) sh.Pi[cc][ij] = pi;
-        } else {
-            pi = sh.Pi[cc][ij];
+    // the group forms D_i and r_i column by column and shares them
+    {
+        double d[NJ], rc;
+        cr_form_col(P, T, lam, Lp, lev, i, c, true, rhs, sgn, d, rc);
+#pragma unroll
+        for (int a = 0; a < NJ; ++a) ex[a * NJ + c] = d[a];
+        ex[NBLK + c] = rc;
+    }
+    group_sync();
+    double Li[NTRI], r[NJ], s[NJ];
+#pragma unroll
+    for (int a = 0; a < NJ; ++a) {
+#pragma unroll
+        for (int b = 0; b <= a; ++b) Li[tri_index(a, b)] = ex[a * NJ + b];
+        r[a] = ex[NBLK + a];
+    }
+    group_sync();   // ex is rewritten below
+    chol_inverse(Li, ok);
+    tri_mv(Li, r, s);
+    // column c of W = Li E_i and of V = Li E_{i+1}^T (row c of E_{i+1})
+    double w[NJ], v[NJ];
+    tri_mv(Li, e, w);
+    tri_mv(Li, f, v);
+    CPF_GLOBAL double *Wc = blk(L.W(), h, NBLK) + c, *Vc = blk(L.V(), h, NBLK) + c;
+    double c1 = 0.0, c2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < NJ; ++k) {
+        c1 = fma(w[k], s[k], c1);
+        c2 = fma(v[k], s[k], c2);
+        Wc[k * NJ] = w[k];
+        Vc[k * NJ] = v[k];
+        ex[k * NJ + c] = w[k];
+        ex[NBLK + k * NJ + c] = v[k];
+    }
+    blk(L.c1(), h, NJ)[c] = c1;
+    blk(L.c2(), h, NJ)[c] = c2;
+    // Li (whole block, zeros above the diagonal) and s: element q by lane q % 7
+    CPF_GLOBAL double *Lo = blk(L.Li(), h, NBLK);
+#pragma unroll
+    for (int a = 0; a < NJ; ++a)
+#pragma unroll
+        for (int b = 0; b < NJ; ++b)
+            if (b == c) Lo[a * NJ + b] = b <= a ? Li[tri_index(a, b)] : 0.0;
+#pragma unroll
+    for (int a = 0; a < NJ; ++a)
+        if (a == c) blk(L.s(), h, NJ)[a] = s[a];
+    group_sync();
+    // column c of W^T W, V^T V and -V^T W (the coupling of level lev+1)
+    CPF_GLOBAL double *Z1c = blk(L.Z1(), h, NBLK) + c, *Z2c = blk(L.Z2(), h, NBLK) + c;
+    CPF_GLOBAL double *Enc = blk(Ln.E(), right ? (i + 1) / 2 : 0, NBLK) + c;
+#pragma unroll
+    for (int a = 0; a < NJ; ++a) {
+        double z1 = 0.0, z2 = 0.0, en = 0.0;
+#pragma unroll
+        for (int k = 0; k < NJ; ++k) {
+            const double wa = ex[k * NJ + a], va = ex[NBLK + k * NJ + a];
+            z1 = fma(wa, w[k], z1);
+            z2 = fma(va, v[k], z2);
+            en = fma(va, w[k], en);
         }
-        double r = sh.y[cc][L.r];
-        if (cc + 1 < C) r += w * sh.a[cc + 1][L.r];
-        if (cc > 0) r += mv(Fe, mv(pi_prev, rho_prev, L, ws), L, ws);
-        if (L.l < NJ) sh.y[cc][L.r] = r;
-        rho_prev = r;
-        pi_prev = pi;
+        Z1c[a * NJ] = z1;
+        Z2c[a * NJ] = z2;
+        if (right) Enc[a * NJ] = -en;
     }
-    double znext = 0.0;
-    for (int cc = C - 1; cc >= 0; --cc) {
-        double v = sh.y[cc][L.r];
-        if (cc + 1 < C) {
-            int s1, e1;
-            chunk_bounds(T, C, cc + 1, s1, e1);
-            v += mtv(blk_ld(P.F, e1, L, 0, T - 1), znext, L, ws);   // F_{e_{c+1}}^T z_{c+1}
+    group_sync();   // ex is rewritten by the group's next block
+}
+
+// Odd block i = 2h+1 of level lev >= 1 for a further right-hand side
+// (group, lane c): s = Li r and its contributions through W and V.
+__device__ __forceinline__ void cr_odd_rhs(const DevPlan &P, int T, const CRLevel &Lp, const CRLevel &L, int lev,
+                                           int h, int c, const CPF_GLOBAL double *rhs, double sgn, double *ex) {
+    const int i = 2 * h + 1;
+    // row c of Li and column c of W and V, loaded with the right-hand side
+    const CPF_GLOBAL double *Lr = blk(L.Li(), h, NBLK) + c * NJ;
+    const CPF_GLOBAL double *Wc = blk(L.W(), h, NBLK) + c, *Vc = blk(L.V(), h, NBLK) + c;
+    double lr[NJ], wc[NJ], vc[NJ];
+#pragma unroll
+    for (int k = 0; k < NJ; ++k) {
+        lr[k] = Lr[k];
+        wc[k] = Wc[k * NJ];
+        vc[k] = Vc[k * NJ];
+    }
+    double d[NJ], rc;
+    cr_form_col(P, T, 0.0, Lp, lev, i, c, false, rhs, sgn, d, rc);
+    ex[c] = rc;
+    group_sync();
+    double sc = 0.0;
+#pragma unroll
+    for (int k = 0; k < NJ; ++k) sc = fma(lr[k], ex[k], sc);
+    group_sync();
+    ex[c] = sc;
+    blk(L.s(), h, NJ)[c] = sc;
+    group_sync();
+    double c1 = 0.0, c2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < NJ; ++k) {
+        const double sk = ex[k];
+        c1 = fma(wc[k], sk, c1);
+        c2 = fma(vc[k], sk, c2);
+    }
+    blk(L.c1(), h, NJ)[c] = c1;
+    blk(L.c2(), h, NJ)[c] = c2;
+    group_sync();
+}
+
+// Back-substitution of odd block i = 2h+1 of level lev >= 1 (group, lane c):
+// y_c = s_c - (W x_{i-1})_c - (V x_{i+1})_c, then x_c = (Li^T y)_c.
+__device__ __forceinline__ void cr_back_group(const CRLevel &L, const CRLevel &Ln, int h, int c, double *ex) {
+    const int i = 2 * h + 1;
+    const bool right = i + 1 < L.n;
+    const CPF_GLOBAL double *xl = blk(Ln.X(), (i - 1) / 2, NJ), *xr = blk(Ln.X(), right ? (i + 1) / 2 : 0, NJ);
+    const CPF_GLOBAL double *Wr = blk(L.W(), h, NBLK) + c * NJ, *Vr = blk(L.V(), h, NBLK) + c * NJ;
+    const CPF_GLOBAL double *Lc = blk(L.Li(), h, NBLK) + c;   // column c of Li (zeros above)
+    double lc[NJ];
+#pragma unroll
+    for (int a = 0; a < NJ; ++a) lc[a] = Lc[a * NJ];
+    double acc = blk(L.s(), h, NJ)[c];
+#pragma unroll
+    for (int k = 0; k < NJ; ++k) {
+        const double vr = xr[k];
+        acc = fma(-Wr[k], xl[k], acc);
+        acc = fma(-Vr[k], right ? vr : 0.0, acc);
+    }
+    ex[c] = acc;
+    group_sync();
+    double x = 0.0;
+#pragma unroll
+    for (int a = 0; a < NJ; ++a) x = fma(lc[a], ex[a], x);
+    blk(L.X(), i, NJ)[c] = x;
+    group_sync();
+}
+
+// Back-substitution, one lane per block: odd blocks of level 0,
+// x_i = Li^T (s_i + w Li (x_{i-1} + x_{i+1})), and the even blocks of any
+// level (copied from the level above).
+__device__ __forceinline__ void cr_back_lane(const DevPlan &P, int T, const CRLevel &L, const CRLevel &Ln, int lev,
+                                             int x, CPF_GLOBAL double *out) {
+    double xv[NJ];
+    if (lev == 0 && (x & 1)) {
+        const int i = x, h = (i - 1) / 2;
+        const bool right = i + 1 < L.n;
+        const CPF_GLOBAL double *xl = blk(Ln.X(), (i - 1) / 2, NJ), *xr = blk(Ln.X(), right ? (i + 1) / 2 : 0, NJ);
+        const CPF_GLOBAL double *so = blk(L.s(), h, NJ);
+        double u[NJ], v[NJ], y[NJ], Li[NTRI];
+#pragma unroll
+        for (int e = 0; e < NJ; ++e) {
+            const double vr = xr[e];
+            u[e] = xl[e] + (right ? vr : 0.0);
         }
-        const double z = mv(sh.Pi[cc][ij], v, L, ws);
-        if (L.l < NJ) sh.z[cc][L.r] = z;
-        znext = z;
+        ld_lower(blk(L.Li(), h, NBLK), Li);
+        tri_mv(Li, u, v);
+#pragma unroll
+        for (int e = 0; e < NJ; ++e) y[e] = fma(P.w_s, v[e], so[e]);
+        tri_tmv(Li, y, xv);
+    } else {
+        const CPF_GLOBAL double *xs = blk(Ln.X(), x / 2, NJ);
+#pragma unroll
+        for (int e = 0; e < NJ; ++e) xv[e] = xs[e];
+    }
+#pragma unroll
+    for (int e = 0; e < NJ; ++e) {
+        if (lev == 0) out[(size_t)e * T + x] = xv[e];
+        else blk(L.X(), x, NJ)[e] = xv[e];
     }
 }
 
-// Interior of chunk c: x_t = P_t (y_t + F_t z_{c-1} + w x_{t+1}), x_e = z_c.
-__device__ __forceinline__ void chunk_interior(const DevPlan &P, int T, int c, int s, int e,
-                                               CPF_GLOBAL double *out, ChunkShared &sh) {
-    const Lane L = lane_info();
-    WaveScratch &ws = sh.ws[c];
-    const double w = P.w_s;
-    const double zl = c > 0 ? sh.z[c - 1][L.r] : 0.0;
-    double x = sh.z[c][L.r];
-    if (L.l < NJ) out[(size_t)L.r * T + e] = x;
-    double p0 = blk_ld(P.P, e - 1, L, s, e - 1), p1 = blk_ld(P.P, e - 2, L, s, e - 1);
-    double f0 = blk_ld(P.F, e - 1, L, s, e - 1), f1 = blk_ld(P.F, e - 2, L, s, e - 1);
-    double y0 = vec_ld(P.y, T, L, e - 1, s, e - 1), y1 = vec_ld(P.y, T, L, e - 2, s, e - 1);
-    for (int t = e - 1; t >= s; --t) {
-        const double pm = p0, fm = f0, ym = y0;
-        p0 = p1; f0 = f1; y0 = y1;
-        p1 = blk_ld(P.P, t - 2, L, s, e - 1);
-        f1 = blk_ld(P.F, t - 2, L, s, e - 1);
-        y1 = vec_ld(P.y, T, L, t - 2, s, e - 1);
-        double v = ym + w * x;
-        if (c > 0) v += mv(fm, zl, L, ws);
-        x = mv(pm, v, L, ws);
-        if (L.l < NJ) out[(size_t)L.r * T + t] = x;
-    }
-}
+#ifdef CPF_PHASE_CYCLES
+// Diagnostic build only: shader-clock totals per solve round (block 0).
+__device__ unsigned long long cr_round_cycles[2][64];
+#define CR_ROUND_MARK(kind, r)                                                     \
+    do {                                                                           \
+        if (threadIdx.x == 0 && blockIdx.x == 0) {                                 \
+            const unsigned long long now_ = clock64();                             \
+            cr_round_cycles[kind][(r) & 63] += now_ - cr_last_;                     \
+            cr_last_ = now_;                                                       \
+        }                                                                          \
+    } while (0)
+#else
+#define CR_ROUND_MARK(kind, r) \
+    do {                       \
+    } while (0)
+#endif
 
-// Factorisation of the partitioned system fused with the solve for the
-// right-hand side -g (all waves; wave c owns chunk c).  Stores P_t (t < e_c),
-// F_t and y_t, Pi_c for the chunk ends, and the step in P.dx.  Returns false
-// on a non-positive pivot.
-__device__ __forceinline__ bool chunk_factor_solve(const DevPlan &P, int T, int C, double lam,
-                                                   ChunkShared &sh) {
-    const int c = threadIdx.x >> 6;
-    const Lane L = lane_info();
-    const double w = P.w_s, w2 = w * w;
-    if (threadIdx.x == 0) sh.bad = 0;
-    __syncthreads();
+// Solve H x = sgn * rhs ([7][T]), factoring H first (factor = true) or
+// reusing the stored factors; x goes to out ([7][T], may alias rhs: the
+// right-hand side is read only in the first two forward rounds).  Returns
+// false on a pivot that is not positive.  All threads of the workgroup;
+// exch: CR_GROUPS x CR_EX doubles of LDS.
+__device__ __forceinline__ bool cr_solve(const DevPlan &P, int T, double lam, bool factor,
+                                         const CPF_GLOBAL double *rhs, double sgn, CPF_GLOBAL double *out,
+                                         int *bad, double *exch) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int gid = lane < 63 ? (tid >> 6) * CR_GPW + lane / NJ : -1;
+    const int gc = lane < 63 ? lane % NJ : 0;
+    double *ex = exch + (size_t)(gid >= 0 ? gid : 0) * CR_EX;
+    const int top = cr_top(T);
+    CPF_GLOBAL double *base = P.cr;
     bool ok = true;
-    int s = 0, e = -1;
-    if (c < C) {
-        WaveScratch &ws = sh.ws[c];
-        chunk_bounds(T, C, c, s, e);
-        double d0 = d_ld(P, T, s, L, s, e, lam), d1 = d_ld(P, T, s + 1, L, s, e, lam);
-        double b0 = -vec_ld(P.g, T, L, s, s, e), b1 = -vec_ld(P.g, T, L, s + 1, s, e);
-        double pprev = 0.0, fprev = 0.0, yprev = 0.0;
-        for (int t = s; t <= e; ++t) {
-            const double d = d0, b = b0;
-            d0 = d1;
-            b0 = b1;
-            d1 = d_ld(P, T, t + 2, L, s, e, lam);
-            b1 = -vec_ld(P.g, T, L, t + 2, s, e);
-            double S = d, F, y = b;
-            if (t == s) {
-                F = (c > 0 && L.el && L.i == L.j) ? w : 0.0;
-            } else {
-                S -= w2 * pprev;
-                F = w * mm(pprev, fprev, L, ws);
-                y += w * mv(pprev, yprev, L, ws);
+    if (tid == 0) *bad = 0;
+#ifdef CPF_PHASE_CYCLES
+    unsigned long long cr_last_ = clock64();
+#endif
+    // forward rounds
+    for (int lev = 0; lev <= top; ++lev) {
+        const CRLevel L = cr_level(base, T, lev);
+        const CRLevel Lp = cr_level(base, T, lev > 0 ? lev - 1 : 0);
+        if (lev == top) {
+            if (tid == 0) cr_top_solve(P, T, lam, Lp, L, lev, factor, rhs, sgn, out, ok);
+        } else if (lev == 0) {
+            const CRLevel L1 = cr_level(base, T, 1);
+            for (int h = tid; h < L.no; h += LM_BS) cr_odd_level0(P, T, lam, L, L1, h, factor, rhs, sgn, ok);
+        } else {
+            const CRLevel Ln = cr_level(base, T, lev + 1);
+            if (gid >= 0) {
+                for (int h = gid; h < L.no; h += CR_GROUPS) {
+                    if (factor) cr_odd_factor(P, T, lam, Lp, L, Ln, lev, h, gc, rhs, sgn, ex, ok);
+                    else cr_odd_rhs(P, T, Lp, L, lev, h, gc, rhs, sgn, ex);
+                }
             }
-            if (C > 1) blk_st(P.F, t, L, F);
-            if (L.l < NJ) P.y[(size_t)L.r * T + t] = y;
-            if (t == e) {
-                if (L.el) sh.Pi[c][L.i * 8 + L.j] = S;
-                if (L.l < NJ) sh.y[c][L.r] = y;
-            } else {
-                pprev = gj_inverse(S, L, ws, ok);
-                blk_st(P.P, t, L, pprev);
-            }
-            fprev = F;
-            yprev = y;
+            // even blocks from the last wavefronts down, so that on small levels
+            // they run beside the groups (which start at the first wavefront)
+            for (int x = LM_BS - 1 - tid; x < L.ne; x += LM_BS) cr_even(P, T, lam, Lp, L, lev, x, factor, rhs, sgn);
         }
-        // backward (chunks that have a predecessor): G and a at the first block
-        double G = 0.0, a = 0.0;
-        if (c > 0) {
-            double p0 = blk_ld(P.P, e - 1, L, s, e - 1), p1 = blk_ld(P.P, e - 2, L, s, e - 1);
-            double f0 = blk_ld(P.F, e - 1, L, s, e - 1), f1 = blk_ld(P.F, e - 2, L, s, e - 1);
-            double y0 = vec_ld(P.y, T, L, e - 1, s, e - 1), y1 = vec_ld(P.y, T, L, e - 2, s, e - 1);
-            for (int t = e - 1; t >= s; --t) {
-                const double pm = p0, fm = f0, ym = y0;
-                p0 = p1; f0 = f1; y0 = y1;
-                p1 = blk_ld(P.P, t - 2, L, s, e - 1);
-                f1 = blk_ld(P.F, t - 2, L, s, e - 1);
-                y1 = vec_ld(P.y, T, L, t - 2, s, e - 1);
-                G = mm(pm, fm + w * G, L, ws);
-                a = mv(pm, ym + w * a, L, ws);
-            }
+        __syncthreads();
+        CR_ROUND_MARK(factor ? 0 : 1, lev);
+    }
+    if (!ok) *bad = 1;
+    // back-substitution rounds
+    for (int lev = top - 1; lev >= 0; --lev) {
+        const CRLevel L = cr_level(base, T, lev);
+        const CRLevel Ln = cr_level(base, T, lev + 1);
+        if (lev == 0) {
+            for (int x = tid; x < L.n; x += LM_BS) cr_back_lane(P, T, L, Ln, 0, x, out);
+        } else {
+            if (gid >= 0)
+                for (int h = gid; h < L.no; h += CR_GROUPS) cr_back_group(L, Ln, h, gc, ex);
+            for (int x = 2 * (LM_BS - 1 - tid); x < L.n; x += 2 * LM_BS) cr_back_lane(P, T, L, Ln, lev, x, out);
         }
-        if (L.el) sh.G[c][L.i * 8 + L.j] = G;
-        if (L.l < NJ) sh.a[c][L.r] = a;
-        if (!ok) sh.bad = 1;
+        __syncthreads();
+        CR_ROUND_MARK(factor ? 0 : 1, 32 + lev);
     }
     __syncthreads();
-    if (c == 0) {
-        reduced_solve(P, T, C, true, sh, ok);
-        if (!ok) sh.bad = 1;
-    }
-    __syncthreads();
-    if (sh.bad) return false;
-    if (c < C) chunk_interior(P, T, c, s, e, P.dx, sh);
-    __syncthreads();
-    return true;
-}
-
-// Solve with the partitioned factors for right-hand side sign*rhs ([7][T]);
-// writes out ([7][T], may alias rhs).  All waves.
-__device__ __forceinline__ void chunk_substitute(const DevPlan &P, int T, int C,
-                                                 const CPF_GLOBAL double *rhs,
-                                 double sign, CPF_GLOBAL double *out, ChunkShared &sh) {
-    const int c = threadIdx.x >> 6;
-    const Lane L = lane_info();
-    const double w = P.w_s;
-    int s = 0, e = -1;
-    if (c < C) {
-        WaveScratch &ws = sh.ws[c];
-        chunk_bounds(T, C, c, s, e);
-        // forward: y_t = b_t + w P_{t-1} y_{t-1} within the chunk
-        double yprev = 0.0, pprev = 0.0;
-        double p0 = blk_ld(P.P, s, L, s, e - 1), p1 = blk_ld(P.P, s + 1, L, s, e - 1);
-        double r0 = vec_ld(rhs, T, L, s, s, e), r1 = vec_ld(rhs, T, L, s + 1, s, e);
-        for (int t = s; t <= e; ++t) {
-            const double pm = p0, rm = r0;
-            p0 = p1; r0 = r1;
-            p1 = blk_ld(P.P, t + 2, L, s, e - 1);
-            r1 = vec_ld(rhs, T, L, t + 2, s, e);
-            double y = sign * rm;
-            if (t > s) y += w * mv(pprev, yprev, L, ws);
-            if (L.l < NJ) P.y[(size_t)L.r * T + t] = y;
-            yprev = y;
-            pprev = pm;
-        }
-        if (L.l < NJ) sh.y[c][L.r] = yprev;
-        // backward: a_t = P_t (y_t + w a_{t+1}), a_e = 0
-        double a = 0.0;
-        if (c > 0) {
-            double q0 = blk_ld(P.P, e - 1, L, s, e - 1), q1 = blk_ld(P.P, e - 2, L, s, e - 1);
-            double y0 = vec_ld(P.y, T, L, e - 1, s, e - 1), y1 = vec_ld(P.y, T, L, e - 2, s, e - 1);
-            for (int t = e - 1; t >= s; --t) {
-                const double pm = q0, ym = y0;
-                q0 = q1; y0 = y1;
-                q1 = blk_ld(P.P, t - 2, L, s, e - 1);
-                y1 = vec_ld(P.y, T, L, t - 2, s, e - 1);
-                a = mv(pm, ym + w * a, L, ws);
-            }
-        }
-        if (L.l < NJ) sh.a[c][L.r] = a;
-    }
-    __syncthreads();
-    if (c == 0) {
-        bool ok = true;
-        reduced_solve(P, T, C, false, sh, ok);
-    }
-    __syncthreads();
-    if (c < C) chunk_interior(P, T, c, s, e, out, sh);
-    __syncthreads();
+    return *bad == 0;
 }
 
 // rb_t = -g_t - (H dx)_t  for every waypoint (all lanes).
@@ -556,7 +776,6 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
     __shared__ double sh_lam, sh_nu, sh_cost;
     __shared__ int sh_flags[4];   // 0 need_lin, 1 status, 2 accept, 3 pivot failure
     const int tid = threadIdx.x;
-    const RobotT<S> rb = load_robot<S>(P);
     LMState *st = P.st;
 
     if (tid == 0) sh_flags[2] = st->seeded;
@@ -571,7 +790,7 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
                 P.xi[(size_t)j * T + t] = v;
             }
         __syncthreads();
-        const double c0 = plan_cost<S>(P, rb, P.xi, T, red);
+        const double c0 = plan_cost<S>(P, load_robot<S>(P), P.xi, T, red);
         if (tid == 0) {
             st->nu = 2.0;
             st->cost = c0;
@@ -598,9 +817,8 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
     __syncthreads();
     const int n_it = sh_flags[2];
 
-    __shared__ ChunkShared chs;
-    // Chunks of at least 8 waypoints, one per wavefront (C = 1: plain sweep).
-    const int C = max(1, min(MAX_CHUNKS, T / 8));
+    __shared__ int sh_bad;
+    __shared__ double exch[CR_GROUPS * CR_EX];
 #ifdef CPF_PHASE_CYCLES
     // Diagnostic build only: per-phase shader-clock totals printed by thread 0.
     uint64_t ph[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -622,34 +840,41 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
         if (sh_flags[1] != 0) break;
         const double lam = sh_lam;
         if (sh_flags[0]) {
-            const double gm = linearise<S>(P, rb, T);
+            const double gm = linearise<S>(P, load_robot<S>(P), T);
             const double gmax = block_max(gm, red);
             if (tid == 0) st->grad_inf = gmax;
         }
         __syncthreads();
         PHASE_MARK(0);
-        {
-            const bool ok = chunk_factor_solve(P, T, C, lam, chs);   // right-hand side -g
-            if (tid == 0) sh_flags[3] = ok ? 0 : 1;
-            PHASE_MARK(1);
+        // Solve 0 factors H and solves H dx = -g; each further solve takes
+        // the FP64 residual rb = -g - H dx and adds the correction H^-1 rb
+        // (one call site, so the solver is inlined once).
+        for (int rs = 0; rs <= P.refine_steps; ++rs) {
+            const bool first = rs == 0;
+            if (!first) {
+                refine_residual(P, T, lam);
+                __syncthreads();
+                PHASE_MARK(3);
+            }
+            const bool ok = cr_solve(P, T, lam, first, first ? P.g : P.rb, first ? -1.0 : 1.0,
+                                     first ? P.dx : P.rb, &sh_bad, exch);
+            if (first) {
+                if (tid == 0) sh_flags[3] = ok ? 0 : 1;
+                PHASE_MARK(1);
+                __syncthreads();
+                if (sh_flags[3]) break;
+            } else {
+                for (int t = tid; t < T; t += LM_BS)
+#pragma unroll
+                    for (int j = 0; j < NJ; ++j) P.dx[(size_t)j * T + t] += P.rb[(size_t)j * T + t];
+                __syncthreads();
+                PHASE_MARK(4);
+            }
         }
-        __syncthreads();
         if (sh_flags[3]) {
             if (tid == 0) sh_flags[1] = CPF_STATUS_NUMERIC;
             __syncthreads();
             break;
-        }
-        for (int rs = 0; rs < P.refine_steps; ++rs) {
-            refine_residual(P, T, lam);
-            __syncthreads();
-            PHASE_MARK(3);
-            chunk_substitute(P, T, C, P.rb, 1.0, P.rb, chs);   // correction in place
-            __syncthreads();
-            for (int t = tid; t < T; t += LM_BS)
-#pragma unroll
-                for (int j = 0; j < NJ; ++j) P.dx[(size_t)j * T + t] += P.rb[(size_t)j * T + t];
-            __syncthreads();
-            PHASE_MARK(4);
         }
         // Trial point, its cost and the predicted reduction.
         double pr = 0.0;
@@ -665,7 +890,7 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
                 pr += dl * (lam * dl - P.g[e]);
             }
         __syncthreads();
-        const double cn = plan_cost<S>(P, rb, P.xt, T, red);
+        const double cn = plan_cost<S>(P, load_robot<S>(P), P.xt, T, red);
         const double pred = 0.5 * block_sum(pr, red);
         PHASE_MARK(5);
         if (tid == 0) {
@@ -704,11 +929,22 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
     }
 #ifdef CPF_PHASE_CYCLES
     if (tid == 0 && blockIdx.x == 0)
-        printf("lm phase cycles T=%d C=%d iters=%d: lin %llu factor %llu solve %llu refres %llu "
+        printf("lm phase cycles T=%d iters=%d: lin %llu factor %llu solve %llu refres %llu "
                "refsub %llu trial %llu accept %llu\n",
-               T, C, n_it, (unsigned long long)ph[0], (unsigned long long)ph[1],
+               T, n_it, (unsigned long long)ph[0], (unsigned long long)ph[1],
                (unsigned long long)ph[2], (unsigned long long)ph[3], (unsigned long long)ph[4],
                (unsigned long long)ph[5], (unsigned long long)ph[6]);
+#endif
+#ifdef CPF_PHASE_CYCLES
+    if (tid == 0 && blockIdx.x == 0) {
+        for (int k = 0; k < 2; ++k) {
+            printf("cr rounds %s:", k ? "rhs" : "factor");
+            for (int r = 0; r < 64; ++r)
+                if (cr_round_cycles[k][r]) printf(" %s%d=%llu", r >= 32 ? "b" : "f", r & 31, cr_round_cycles[k][r]);
+            printf("\n");
+            for (int r = 0; r < 64; ++r) cr_round_cycles[k][r] = 0;
+        }
+    }
 #endif
 #undef PHASE_MARK
     if (tid == 0) {

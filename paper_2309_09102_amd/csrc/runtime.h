@@ -36,7 +36,7 @@ inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Byte offsets of one plan's buffers inside its arena.
 struct Layout {
-    size_t cand, extra, pen, bp, topk, topc, path, dp_out, targets, xi, xt, A, g, P, F, y, dx, rb, st, report,
+    size_t cand, extra, pen, bp, topk, topc, path, dp_out, targets, xi, xt, A, g, cr, dx, rb, st, report,
         total;
 };
 Layout make_layout(int T, int K, bool extra);
