@@ -52,7 +52,8 @@ Layout make_layout(int T, int K, bool extra) {
     L.pen = take(t * k * sizeof(double));
     L.bp = take(t * k * sizeof(uint16_t));
     L.topk = take(t * k * TOPM * sizeof(uint16_t));
-    L.topc = take(t * k * TOPM * sizeof(double));
+    L.topc = take(std::max(t * k * TOPM * sizeof(double), (t * k * NJ + 12 * t) * sizeof(double)));
+    L.raw = L.topc;
     L.path = take(t * sizeof(int32_t));
     L.dp_out = take(8 * sizeof(double));
     L.targets = take(12 * t * sizeof(double));
@@ -71,6 +72,63 @@ Layout make_layout(int T, int K, bool extra) {
 
 uint64_t plan_bytes(int T, int K, bool extra) {
     return make_layout(T, K, extra).total + align256(sizeof(DevPlan));
+}
+
+uint64_t plan_class_bytes(int T, int K, bool extra) {
+    const uint64_t b = plan_bytes(T, K, extra);
+    uint64_t c = (uint64_t)1 << 20;
+    while (c < b) c <<= 1;
+    return c;
+}
+
+cpf_status arena_get(cpf_ctx *ctx, uint64_t cls, void **out) {
+    std::vector<void *> evict;
+    {
+        std::lock_guard<std::mutex> lk(ctx->pool_mu);
+        if (ctx->used.load() + cls > ctx->budget)
+            return fail(CPF_E_NOMEM, "plan needs %llu bytes; budget %llu, in use %llu",
+                        (unsigned long long)cls, (unsigned long long)ctx->budget,
+                        (unsigned long long)ctx->used.load());
+        auto it = ctx->pool.find(cls);
+        if (it != ctx->pool.end() && !it->second.empty()) {
+            *out = it->second.back();
+            it->second.pop_back();
+            ctx->pooled -= cls;
+            ctx->used += cls;
+            return CPF_OK;
+        }
+        // make room among the cached arenas of other sizes
+        for (auto &kv : ctx->pool) {
+            while (!kv.second.empty() && ctx->used.load() + ctx->pooled + cls > ctx->budget) {
+                evict.push_back(kv.second.back());
+                kv.second.pop_back();
+                ctx->pooled -= kv.first;
+            }
+        }
+        ctx->used += cls;
+    }
+    for (void *p : evict) HIP_IGNORE(hipFree(p));
+    hipError_t e = hipMalloc(out, cls);
+    if (e != hipSuccess) {
+        ctx->used -= cls;
+        return fail(CPF_E_NOMEM, "hipMalloc(%llu): %s", (unsigned long long)cls, hipGetErrorString(e));
+    }
+    return CPF_OK;
+}
+
+void arena_put(cpf_ctx *ctx, void *p, uint64_t cls) {
+    std::lock_guard<std::mutex> lk(ctx->pool_mu);
+    ctx->used -= cls;
+    ctx->pool[cls].push_back(p);
+    ctx->pooled += cls;
+}
+
+void pool_clear(cpf_ctx *ctx) {
+    std::lock_guard<std::mutex> lk(ctx->pool_mu);
+    for (auto &kv : ctx->pool)
+        for (void *p : kv.second) HIP_IGNORE(hipFree(p));
+    ctx->pool.clear();
+    ctx->pooled = 0;
 }
 
 static bool all_finite(const double *p, size_t n) {
@@ -179,71 +237,48 @@ static void fill_desc(cpf_plan *p, bool has_extra) {
 }
 
 cpf_status plan_create(cpf_ctx *ctx, const HostRobot &hr, const cpf_problem *prob,
-                       const cpf_opts *opts, int32_t iters_target, hipStream_t s,
-                       std::vector<char> &staging, cpf_plan **out) {
+                       const cpf_opts *opts, int32_t iters_target, hipStream_t s, cpf_plan **out) {
     const bool has_extra = prob->node_pen != nullptr;
-    const uint64_t bytes = plan_bytes(prob->T, prob->K, has_extra);
-    if (!ctx->reserve(bytes))
-        return fail(CPF_E_NOMEM, "plan needs %llu bytes; budget %llu, in use %llu",
-                    (unsigned long long)bytes, (unsigned long long)ctx->budget,
-                    (unsigned long long)ctx->used.load());
+    const uint64_t cls = plan_class_bytes(prob->T, prob->K, has_extra);
+    void *mem = nullptr;
+    cpf_status st = arena_get(ctx, cls, &mem);
+    if (st != CPF_OK) return st;
     std::unique_ptr<cpf_plan> p(new cpf_plan());
     p->ctx = ctx;
     p->T = prob->T;
     p->K = prob->K;
     p->robot = hr;
     p->opts = *opts;
-    p->bytes = bytes;
+    p->bytes = cls;
     p->L = make_layout(p->T, p->K, has_extra);
-    void *mem = nullptr;
-    hipError_t e = hipMalloc(&mem, bytes);
-    if (e != hipSuccess) {
-        ctx->release(bytes);
-        return fail(CPF_E_NOMEM, "hipMalloc(%llu): %s", (unsigned long long)bytes,
-                    hipGetErrorString(e));
-    }
     p->arena = (char *)mem;
     p->d_desc = (DevPlan *)(p->arena + p->L.total);
     fill_desc(p.get(), has_extra);
+    p->init.lambda = opts->lambda0;
+    p->init.nu = 2.0;
+    p->init.iters_target = iters_target;
 
-    // Host staging: SoA candidates (float), SoA targets, LM state, descriptor.
+    // The caller's arrays go up as they are; a kernel converts them into the
+    // device layout (candidates to float, joint-major; targets component-major).
     const int T = p->T, K = p->K;
-    const size_t n_cand = (size_t)T * NJ * K;
-    const size_t stage_bytes = n_cand * sizeof(float) + (size_t)12 * T * sizeof(double) +
-                               sizeof(LMState) + sizeof(DevPlan);
-    staging.resize(stage_bytes);
-    float *cs = (float *)staging.data();
-    double *ts = (double *)(staging.data() + n_cand * sizeof(float));
-    LMState *ss = (LMState *)(ts + (size_t)12 * T);
-    DevPlan *ds = (DevPlan *)(ss + 1);
-    for (int k = 0; k < K; ++k)
-        for (int t = 0; t < T; ++t) {
-            const double *src = prob->cand + ((size_t)k * T + t) * NJ;
-            for (int j = 0; j < NJ; ++j) cs[((size_t)t * NJ + j) * K + k] = (float)src[j];
-        }
-    for (int t = 0; t < T; ++t)
-        for (int c = 0; c < 12; ++c) ts[(size_t)c * T + t] = prob->targets[(size_t)t * 12 + c];
-    memset(ss, 0, sizeof(LMState));
-    ss->lambda = opts->lambda0;
-    ss->nu = 2.0;
-    ss->iters_target = iters_target;
-    *ds = p->desc;
-
-    e = hipMemcpyAsync(p->arena + p->L.cand, cs, n_cand * sizeof(float), hipMemcpyHostToDevice, s);
+    const size_t n_cand = (size_t)T * K * NJ;
+    double *raw = (double *)(p->arena + p->L.raw);
+    hipError_t e = hipMemcpyAsync(raw, prob->cand, n_cand * sizeof(double), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(p->arena + p->L.targets, ts, (size_t)12 * T * sizeof(double),
+        e = hipMemcpyAsync(raw + n_cand, prob->targets, (size_t)12 * T * sizeof(double),
                            hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = stage_launch(raw, T, K, (float *)(p->arena + p->L.cand), (double *)(p->arena + p->L.targets), s);
     if (e == hipSuccess && has_extra)
         e = hipMemcpyAsync(p->arena + p->L.extra, prob->node_pen, (size_t)T * K * sizeof(double),
                            hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(p->arena + p->L.st, ss, sizeof(LMState), hipMemcpyHostToDevice, s);
+        e = hipMemcpyAsync(p->arena + p->L.st, &p->init, sizeof(LMState), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(p->d_desc, ds, sizeof(DevPlan), hipMemcpyHostToDevice, s);
+        e = hipMemcpyAsync(p->d_desc, &p->desc, sizeof(DevPlan), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) {
         HIP_IGNORE(hipStreamSynchronize(s));
-        HIP_IGNORE(hipFree(mem));
-        ctx->release(bytes);
+        arena_put(ctx, mem, cls);
         return fail(CPF_E_DEVICE, "upload failed: %s", hipGetErrorString(e));
     }
     *out = p.release();
@@ -252,10 +287,7 @@ cpf_status plan_create(cpf_ctx *ctx, const HostRobot &hr, const cpf_problem *pro
 
 void plan_destroy(cpf_plan *p) {
     if (!p) return;
-    if (p->arena) {
-        HIP_IGNORE(hipFree(p->arena));
-        p->ctx->release(p->bytes);
-    }
+    if (p->arena) arena_put(p->ctx, p->arena, p->bytes);
     delete p;
 }
 
@@ -340,6 +372,8 @@ void cpf_ctx_destroy(cpf_ctx *ctx) {
     server_stop_and_join(ctx);
     HIP_IGNORE(hipSetDevice(ctx->device));
     cpf_ctx_profile(ctx, 0);
+    if (ctx->stream) HIP_IGNORE(hipStreamSynchronize(ctx->stream));
+    pool_clear(ctx);
     if (ctx->stream) HIP_IGNORE(hipStreamDestroy(ctx->stream));
     delete ctx;
 }
@@ -358,9 +392,8 @@ cpf_status cpf_plan_init(cpf_ctx *ctx, const cpf_robot *robot, const cpf_problem
     if (opts) o = *opts;
     if ((st = check_opts(&o)) != CPF_OK) return st;
     HIP_TRY(hipSetDevice(ctx->device));
-    std::vector<char> staging;
     cpf_plan *p = nullptr;
-    if ((st = plan_create(ctx, hr, prob, &o, 0, ctx->stream, staging, &p)) != CPF_OK) return st;
+    if ((st = plan_create(ctx, hr, prob, &o, 0, ctx->stream, &p)) != CPF_OK) return st;
     hipError_t e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
         plan_destroy(p);
@@ -444,7 +477,6 @@ cpf_status cpf_solve_batch(cpf_ctx *ctx, int32_t nplans, const cpf_robot *robots
     if (nplans == 0) return CPF_OK;
     HIP_TRY(hipSetDevice(ctx->device));
     std::vector<cpf_plan *> plans;
-    std::vector<std::vector<char>> staging(nplans);
     DevPlan *d_descs = nullptr;
     auto cleanup = [&]() {
         HIP_IGNORE(hipStreamSynchronize(ctx->stream));
@@ -454,7 +486,7 @@ cpf_status cpf_solve_batch(cpf_ctx *ctx, int32_t nplans, const cpf_robot *robots
     int maxK = 0, maxT = 0;
     for (int i = 0; i < nplans; ++i) {
         cpf_plan *p = nullptr;
-        if ((st = plan_create(ctx, hrs[i], &probs[i], &o, 0, ctx->stream, staging[i], &p)) != CPF_OK) {
+        if ((st = plan_create(ctx, hrs[i], &probs[i], &o, 0, ctx->stream, &p)) != CPF_OK) {
             cleanup();
             return st;
         }

@@ -17,6 +17,10 @@ struct HostRobot {
 // Kernel launchers (asynchronous on stream s).
 hipError_t fk_batch_launch(const HostRobot &hr, int64_t M, int prec, const void *q, void *pose,
                            void *J, hipStream_t s);
+// Convert the uploaded caller arrays of one plan (candidates [K][T][7] and
+// targets [T][12], doubles) into the device layout (cand float [T][7][K],
+// targets [12][T]).
+hipError_t stage_launch(const double *raw, int T, int K, float *cand, double *targets, hipStream_t s);
 // Search + seed gather for nplans plans: the predecessor lists over the
 // whole GPU, then one workgroup per plan for the stages.
 hipError_t dp_launch(const DevPlan *d_plans, int nplans, int maxK, int maxT, hipStream_t s);

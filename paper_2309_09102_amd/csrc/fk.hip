@@ -66,4 +66,32 @@ hipError_t fk_batch_launch(const HostRobot &hr, int64_t M, int prec, const void 
     return launch_fk<float>(rb, M, q, pose, J, s);
 }
 
+// One thread per (waypoint, candidate) pair, candidates fastest, so the
+// float stores of a joint row are contiguous; the last T threads transpose
+// the targets.
+__global__ __launch_bounds__(256) void stage_kernel(const double *__restrict__ raw, int T, int K,
+                                                    float *__restrict__ cand, double *__restrict__ targets) {
+    const long long n = (long long)T * K;
+    const long long x = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (x < n) {
+        const int t = (int)(x / K), k = (int)(x % K);
+        const double *q = raw + ((size_t)k * T + t) * NJ;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) cand[((size_t)t * NJ + j) * K + k] = (float)q[j];
+    } else if (x < n + T) {
+        const int t = (int)(x - n);
+        const double *tg = raw + (size_t)n * NJ + (size_t)t * 12;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) targets[(size_t)c * T + t] = tg[c];
+    }
+}
+
+hipError_t stage_launch(const double *raw, int T, int K, float *cand, double *targets, hipStream_t s) {
+    const long long n = (long long)T * K + T;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(stage_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, raw, T, K, cand,
+                       targets);
+    return hipGetLastError();
+}
+
 }  // namespace cpf

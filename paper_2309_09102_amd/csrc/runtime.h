@@ -34,13 +34,19 @@ cpf_status fail(cpf_status st, const char *fmt, ...);
 int64_t now_ns();
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
-// Byte offsets of one plan's buffers inside its arena.
+// Byte offsets of one plan's buffers inside its arena.  `raw` receives the
+// caller's candidates ([K][T][7] doubles) and targets ([T][12]) as uploaded;
+// a kernel converts them into the device layout before the search, so the
+// region is shared with the search lists (topc), which are written later.
 struct Layout {
-    size_t cand, extra, pen, bp, topk, topc, path, dp_out, targets, xi, xt, A, g, cr, dx, rb, st, report,
-        total;
+    size_t cand, extra, pen, bp, topk, topc, raw, path, dp_out, targets, xi, xt, A, g, cr, dx, rb, st,
+        report, total;
 };
 Layout make_layout(int T, int K, bool extra);
 uint64_t plan_bytes(int T, int K, bool extra);
+// Device bytes a plan takes from the budget: its arena rounded up to a
+// power of two (at least 1 MiB), the unit the arena pool recycles.
+uint64_t plan_class_bytes(int T, int K, bool extra);
 
 cpf_status check_robot(const cpf_robot *r, HostRobot *out);
 cpf_status check_problem(const cpf_problem *p);
@@ -56,8 +62,14 @@ struct Server;
 struct cpf_ctx {
     int device = 0;
     uint64_t budget = 0;
-    std::atomic<uint64_t> used{0};
-    hipStream_t stream = nullptr;   // synchronous plan calls
+    std::atomic<uint64_t> used{0};   // arenas held by live plans
+    hipStream_t stream = nullptr;    // synchronous plan calls
+    // Arena pool: freed arenas are kept by size class and handed out again,
+    // so steady serving makes no device allocation or free; cached bytes
+    // count against the budget together with `used`.
+    std::mutex pool_mu;
+    std::map<uint64_t, std::vector<void *>> pool;
+    uint64_t pooled = 0;
     // serving
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -80,14 +92,6 @@ struct cpf_ctx {
     double prof_ms[4] = {0, 0, 0, 0};
     int64_t prof_n[4] = {0, 0, 0, 0};
 
-    bool reserve(uint64_t b) {
-        uint64_t cur = used.load();
-        while (true) {
-            if (cur + b > budget) return false;
-            if (used.compare_exchange_weak(cur, cur + b)) return true;
-        }
-    }
-    void release(uint64_t b) { used.fetch_sub(b); }
 };
 
 struct cpf_plan {
@@ -97,9 +101,10 @@ struct cpf_plan {
     cpf_opts opts{};
     cpf::Layout L{};
     char *arena = nullptr;
-    uint64_t bytes = 0;
+    uint64_t bytes = 0;   // size class taken from the pool
     cpf::DevPlan desc{};
     cpf::DevPlan *d_desc = nullptr;
+    cpf::LMState init{};  // host source of the initial LM state upload
     bool searched = false;
 };
 
@@ -122,12 +127,17 @@ hipError_t timed(cpf_ctx *ctx, int kind, hipStream_t s, F &&launch) {
     return e;
 }
 
-// Allocate and upload one plan on stream s (asynchronous; `staging` must stay
-// alive until s is synchronised).  iters_target = 0 lets each lm_refine call
-// run the iterations it asks for.
+// Arena of `cls` bytes from the pool (or a new allocation within the
+// budget); E_NOMEM when the budget does not allow it.
+cpf_status arena_get(cpf_ctx *ctx, uint64_t cls, void **out);
+void arena_put(cpf_ctx *ctx, void *p, uint64_t cls);
+void pool_clear(cpf_ctx *ctx);
+
+// Take an arena and upload one plan on stream s (asynchronous: the caller's
+// arrays in `prob` must stay alive until s is synchronised).  iters_target =
+// 0 lets each lm_refine call run the iterations it asks for.
 cpf_status plan_create(cpf_ctx *ctx, const HostRobot &hr, const cpf_problem *prob,
-                       const cpf_opts *opts, int32_t iters_target, hipStream_t s,
-                       std::vector<char> &staging, cpf_plan **out);
+                       const cpf_opts *opts, int32_t iters_target, hipStream_t s, cpf_plan **out);
 void plan_destroy(cpf_plan *p);
 
 struct PlanReadback {

@@ -2,20 +2,26 @@
 // cpf_poll.
 //
 // The device holds a fixed table of `slots` plan descriptors (the work list)
-// and their LM states in one contiguous array.  One server thread runs ticks:
-//   1. admit queued requests while a slot is free and their arena fits the
-//      memory budget (upload on the server stream);
-//   2. search the newly admitted requests in one launch (one workgroup each);
-//   3. replay the LM tick graph: lm_kernel<float> and lm_kernel<double> over
-//      every slot (each skips empty slots and the other precision), each
-//      plan advancing up to `iters_per_tick` iterations, then the report
-//      kernel for plans that just finished;
-//   4. read all slot states back in one copy and retire finished requests.
-// Requests submitted while a tick runs join at the next tick, so their work
-// overlaps on the device with the requests already in flight.  The graph is
-// captured once per context: its kernels read the work list from device
-// memory, so admissions and retirements only rewrite descriptor slots
-// between replays.
+// and their LM states in one contiguous array.  One server thread loops:
+//   1. admission: while a slot is free and the request's arena fits the
+//      memory budget, take an arena from the pool and upload the request on
+//      the upload stream; the admitted requests are searched in one launch
+//      there (one workgroup per request), while
+//   2. the LM stream replays the tick graph over the work list:
+//      lm_kernel<float> and lm_kernel<double> over every slot (each skips
+//      empty slots and the other precision), every plan advancing up to
+//      `iters_per_tick` iterations, then the report kernel for plans that
+//      just finished;
+//   3. a searched batch joins the work list at the next tick (its
+//      descriptors are written into their slots on the LM stream);
+//   4. after each tick all slot states come back in one copy, and the
+//      finished requests are read back together and retired (their arenas
+//      go back to the pool).
+// Requests submitted while the GPU is busy join at the next tick, so their
+// search and iterations overlap on the device with the requests in flight.
+// The graph is captured once per context: its kernels read the work list
+// from device memory, so admissions and retirements only rewrite descriptor
+// slots between replays.
 #include <algorithm>
 #include <cstring>
 #include <memory>
@@ -32,13 +38,13 @@ struct Request {
     std::vector<double> targets, cand, node_pen;
     uint64_t bytes = 0;
     cpf_plan *plan = nullptr;
-    std::vector<char> staging;
     int slot = -1;
     bool done = false;
     cpf_status status = CPF_OK;
-    std::vector<double> xi;
+    std::vector<double> xi, xi_soa;
     std::vector<int32_t> path;
-    cpf_lm_report report{};
+    double report[8] = {0}, dp_out[8] = {0};
+    cpf_lm_report rep{};
     double best = 0, smjac = 0;
     int64_t t_submit = 0, t_admit = 0, t_search = 0, t_done = 0;
 };
@@ -46,13 +52,16 @@ struct Request {
 struct Server {
     int cap = 0;
     int ipt = 0;
-    hipStream_t s = nullptr;
+    hipStream_t s_lm = nullptr;    // tick graph, work-list updates, read-back
+    hipStream_t s_up = nullptr;    // uploads and searches
+    hipEvent_t searched = nullptr;
     DevPlan *d_work = nullptr;     // [cap]
     LMState *d_states = nullptr;   // [cap]
-    DevPlan *d_new = nullptr;      // [cap] descriptors of the tick's admissions
-    std::vector<DevPlan> h_work;
-    std::vector<LMState> h_states;
+    DevPlan *d_new = nullptr;      // [cap] descriptors of the batch being searched
+    std::vector<DevPlan> h_work, h_new;
+    std::vector<LMState> h_states, h_init;
     std::vector<Request *> slot_req;
+    std::vector<Request *> searching;   // the batch in flight on s_up
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -63,25 +72,29 @@ cpf_status server_init(cpf_ctx *ctx, Server *sv) {
     sv->cap = ctx->slots;
     sv->ipt = ctx->iters_per_tick;
     HIP_TRY(hipSetDevice(ctx->device));
-    HIP_TRY(hipStreamCreateWithFlags(&sv->s, hipStreamNonBlocking));
+    HIP_TRY(hipStreamCreateWithFlags(&sv->s_lm, hipStreamNonBlocking));
+    HIP_TRY(hipStreamCreateWithFlags(&sv->s_up, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&sv->searched, hipEventDisableTiming));
     HIP_TRY(hipMalloc((void **)&sv->d_work, sizeof(DevPlan) * sv->cap));
     HIP_TRY(hipMalloc((void **)&sv->d_states, sizeof(LMState) * sv->cap));
     HIP_TRY(hipMalloc((void **)&sv->d_new, sizeof(DevPlan) * sv->cap));
     sv->h_work.assign(sv->cap, DevPlan{});     // T = 0: empty slot
+    sv->h_new.assign(sv->cap, DevPlan{});
     sv->h_states.assign(sv->cap, LMState{});
+    sv->h_init.assign(sv->cap, LMState{});
     sv->slot_req.assign(sv->cap, nullptr);
     HIP_TRY(hipMemcpyAsync(sv->d_work, sv->h_work.data(), sizeof(DevPlan) * sv->cap,
-                           hipMemcpyHostToDevice, sv->s));
+                           hipMemcpyHostToDevice, sv->s_lm));
     HIP_TRY(hipMemcpyAsync(sv->d_states, sv->h_states.data(), sizeof(LMState) * sv->cap,
-                           hipMemcpyHostToDevice, sv->s));
-    HIP_TRY(hipStreamSynchronize(sv->s));
+                           hipMemcpyHostToDevice, sv->s_lm));
+    HIP_TRY(hipStreamSynchronize(sv->s_lm));
     // Capture the LM tick: both precisions over every slot, then the report
     // for plans that finished in this tick.
-    HIP_TRY(hipStreamBeginCapture(sv->s, hipStreamCaptureModeThreadLocal));
-    hipError_t e = lm_launch(sv->d_work, sv->cap, 0, sv->ipt, sv->s);
-    if (e == hipSuccess) e = lm_launch(sv->d_work, sv->cap, 1, sv->ipt, sv->s);
-    if (e == hipSuccess) e = eval_launch(sv->d_work, sv->cap, 1, sv->s);
-    hipError_t e2 = hipStreamEndCapture(sv->s, &sv->graph);
+    HIP_TRY(hipStreamBeginCapture(sv->s_lm, hipStreamCaptureModeThreadLocal));
+    hipError_t e = lm_launch(sv->d_work, sv->cap, 0, sv->ipt, sv->s_lm);
+    if (e == hipSuccess) e = lm_launch(sv->d_work, sv->cap, 1, sv->ipt, sv->s_lm);
+    if (e == hipSuccess) e = eval_launch(sv->d_work, sv->cap, 1, sv->s_lm);
+    hipError_t e2 = hipStreamEndCapture(sv->s_lm, &sv->graph);
     if (e != hipSuccess) return fail(CPF_E_DEVICE, "tick capture: %s", hipGetErrorString(e));
     if (e2 != hipSuccess) return fail(CPF_E_DEVICE, "tick capture end: %s", hipGetErrorString(e2));
     HIP_TRY(hipGraphInstantiate(&sv->exec, sv->graph, nullptr, nullptr, 0));
@@ -89,39 +102,25 @@ cpf_status server_init(cpf_ctx *ctx, Server *sv) {
 }
 
 void server_free(Server *sv) {
-    if (sv->s) HIP_IGNORE(hipStreamSynchronize(sv->s));
+    if (sv->s_up) HIP_IGNORE(hipStreamSynchronize(sv->s_up));
+    if (sv->s_lm) HIP_IGNORE(hipStreamSynchronize(sv->s_lm));
     if (sv->exec) HIP_IGNORE(hipGraphExecDestroy(sv->exec));
     if (sv->graph) HIP_IGNORE(hipGraphDestroy(sv->graph));
+    if (sv->searched) HIP_IGNORE(hipEventDestroy(sv->searched));
     if (sv->d_work) HIP_IGNORE(hipFree(sv->d_work));
     if (sv->d_states) HIP_IGNORE(hipFree(sv->d_states));
     if (sv->d_new) HIP_IGNORE(hipFree(sv->d_new));
-    if (sv->s) HIP_IGNORE(hipStreamDestroy(sv->s));
+    if (sv->s_up) HIP_IGNORE(hipStreamDestroy(sv->s_up));
+    if (sv->s_lm) HIP_IGNORE(hipStreamDestroy(sv->s_lm));
 }
 
-// Finish a request: read its results, free its plan and slot, wake pollers.
-void retire(cpf_ctx *ctx, Server *sv, Request *r, cpf_status dev_status) {
-    if (r->plan && dev_status == CPF_OK) {
-        PlanReadback rb;
-        r->xi.resize((size_t)r->T * NJ);
-        r->path.resize(r->T);
-        cpf_status st = read_plan(r->plan, sv->s, sv->d_states + r->slot, &rb, r->xi.data(),
-                                  r->path.data());
-        if (st == CPF_OK) {
-            fill_report(rb, &r->report);
-            r->best = rb.dp_out[0];
-            r->smjac = rb.dp_out[1];
-            r->status = rb.st.status != 0 ? CPF_E_NUMERIC : CPF_OK;
-        } else {
-            r->status = st;
-        }
-    } else if (dev_status != CPF_OK) {
-        r->status = dev_status;
-    }
+// Release a request's slot, plan and inputs and wake its pollers.  The slot's
+// descriptor is cleared on the LM stream, ahead of the next tick.
+void finish(cpf_ctx *ctx, Server *sv, Request *r) {
     if (r->slot >= 0) {
         sv->h_work[r->slot] = DevPlan{};
         HIP_IGNORE(hipMemcpyAsync(sv->d_work + r->slot, &sv->h_work[r->slot], sizeof(DevPlan),
-                                  hipMemcpyHostToDevice, sv->s));
-        HIP_IGNORE(hipStreamSynchronize(sv->s));
+                                  hipMemcpyHostToDevice, sv->s_lm));
         sv->slot_req[r->slot] = nullptr;
         r->slot = -1;
     }
@@ -129,116 +128,211 @@ void retire(cpf_ctx *ctx, Server *sv, Request *r, cpf_status dev_status) {
         plan_destroy(r->plan);
         r->plan = nullptr;
     }
-    r->cand.clear();
-    r->cand.shrink_to_fit();
-    r->staging.clear();
-    r->staging.shrink_to_fit();
+    std::vector<double>().swap(r->cand);
+    std::vector<double>().swap(r->node_pen);
+    std::vector<double>().swap(r->xi_soa);
     r->t_done = now_ns();
     std::lock_guard<std::mutex> lk(ctx->mu);
     r->done = true;
     ctx->cv_done.notify_all();
 }
 
-void server_main(cpf_ctx *ctx) {
-    std::unique_ptr<Server> sv(new Server());
-    cpf_status init = server_init(ctx, sv.get());
-    std::vector<Request *> active;
-    while (true) {
-        std::vector<Request *> admitted;
-        {
-            std::unique_lock<std::mutex> lk(ctx->mu);
-            ctx->cv_work.wait(lk, [&] { return ctx->stop || !ctx->pending.empty() || !active.empty(); });
-            if (ctx->stop && ctx->pending.empty() && active.empty()) break;
-            int free_slots = sv->cap - (int)active.size();
-            uint64_t planned = 0;
-            while (!ctx->pending.empty() && free_slots > 0 && init == CPF_OK) {
-                Request *r = ctx->pending.front();
-                if (ctx->used.load() + planned + r->bytes > ctx->budget) break;   // wait for budget
-                ctx->pending.pop_front();
-                admitted.push_back(r);
-                planned += r->bytes;
-                --free_slots;
-            }
-            if (init != CPF_OK) {   // no device server: fail everything queued
-                while (!ctx->pending.empty()) {
-                    admitted.push_back(ctx->pending.front());
-                    ctx->pending.pop_front();
-                }
-            }
+// Read back the finished requests together (one synchronisation), then
+// release them.
+void retire(cpf_ctx *ctx, Server *sv, const std::vector<Request *> &fin, cpf_status dev) {
+    if (fin.empty()) return;
+    hipError_t e = hipSuccess;
+    if (dev == CPF_OK) {
+        for (Request *r : fin) {
+            if (!r->plan) continue;
+            const Layout &L = r->plan->L;
+            const char *a = r->plan->arena;
+            r->xi_soa.resize((size_t)NJ * r->T);
+            r->path.resize(r->T);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(r->xi_soa.data(), a + L.xi, r->xi_soa.size() * sizeof(double),
+                                   hipMemcpyDeviceToHost, sv->s_lm);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(r->path.data(), a + L.path, (size_t)r->T * sizeof(int32_t),
+                                   hipMemcpyDeviceToHost, sv->s_lm);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(r->report, a + L.report, sizeof(r->report), hipMemcpyDeviceToHost, sv->s_lm);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(r->dp_out, a + L.dp_out, sizeof(r->dp_out), hipMemcpyDeviceToHost, sv->s_lm);
         }
-        if (init != CPF_OK) {
-            for (Request *r : admitted) retire(ctx, sv.get(), r, init);
+        if (e == hipSuccess) e = hipStreamSynchronize(sv->s_lm);
+        if (e != hipSuccess) dev = fail(CPF_E_DEVICE, "read-back: %s", hipGetErrorString(e));
+    }
+    for (Request *r : fin) {
+        if (dev != CPF_OK || !r->plan) {
+            if (r->status == CPF_OK) r->status = dev;
+        } else {
+            const LMState &ls = sv->h_states[r->slot];
+            r->xi.resize((size_t)r->T * NJ);
+            for (int t = 0; t < r->T; ++t)
+                for (int j = 0; j < NJ; ++j) r->xi[(size_t)t * NJ + j] = r->xi_soa[(size_t)j * r->T + t];
+            r->rep.cost0 = ls.cost0;
+            r->rep.cost = ls.cost;
+            r->rep.lambda = ls.lambda;
+            r->rep.grad_inf = ls.grad_inf;
+            r->rep.n_accepted = ls.n_acc;
+            r->rep.iters_done = ls.iters_done;
+            r->rep.max_pos_err_m = r->report[0];
+            r->rep.max_rot_err_rad = r->report[1];
+            r->rep.mjac = r->report[2];
+            r->best = r->dp_out[0];
+            r->smjac = r->dp_out[1];
+            r->status = ls.status != 0 ? CPF_E_NUMERIC : CPF_OK;
+        }
+        finish(ctx, sv, r);
+    }
+}
+
+// Admit queued requests into free slots while their arenas fit the budget,
+// upload them on s_up and launch their search there.  Returns the number
+// admitted; requests that fail to upload are retired with their status.
+int admit(cpf_ctx *ctx, Server *sv, int free_slots) {
+    std::vector<Request *> batch;
+    int maxK = 0, maxT = 0;
+    while (free_slots > 0) {
+        Request *r = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            if (ctx->pending.empty()) break;
+            r = ctx->pending.front();
+            ctx->pending.pop_front();
+        }
+        cpf_problem pb{r->T, r->K, r->targets.data(), r->cand.data(),
+                       r->node_pen.empty() ? nullptr : r->node_pen.data()};
+        r->t_admit = now_ns();
+        cpf_status st = plan_create(ctx, r->robot, &pb, &r->opts, r->opts.iters, sv->s_up, &r->plan);
+        if (st == CPF_E_NOMEM) {   // wait for arenas to come back
+            std::lock_guard<std::mutex> lk(ctx->mu);
+            ctx->pending.push_front(r);
+            break;
+        }
+        if (st != CPF_OK) {
+            r->plan = nullptr;
+            r->status = st;
+            finish(ctx, sv, r);
             continue;
         }
-        // 1. upload and place the admitted requests
-        std::vector<DevPlan> fresh;
-        int maxK = 0, maxT = 0;
-        for (Request *r : admitted) {
-            cpf_problem pb{r->T, r->K, r->targets.data(), r->cand.data(),
-                           r->node_pen.empty() ? nullptr : r->node_pen.data()};
-            r->t_admit = now_ns();
-            cpf_status st = plan_create(ctx, r->robot, &pb, &r->opts, r->opts.iters, sv->s,
-                                        r->staging, &r->plan);
-            if (st != CPF_OK) {
-                r->plan = nullptr;
-                retire(ctx, sv.get(), r, st);
-                continue;
+        int slot = 0;
+        while (sv->slot_req[slot]) ++slot;
+        r->slot = slot;
+        sv->slot_req[slot] = r;
+        LMState &ls = sv->h_init[slot];
+        memset(&ls, 0, sizeof(ls));
+        ls.lambda = r->opts.lambda0;
+        ls.nu = 2.0;
+        ls.iters_target = r->opts.iters;
+        HIP_IGNORE(hipMemcpyAsync(sv->d_states + slot, &ls, sizeof(LMState), hipMemcpyHostToDevice, sv->s_up));
+        DevPlan d = r->plan->desc;
+        set_dev_ptr(d.st, sv->d_states + slot);
+        sv->h_new[batch.size()] = d;
+        batch.push_back(r);
+        maxK = std::max(maxK, r->K);
+        maxT = std::max(maxT, r->T);
+        --free_slots;
+    }
+    if (batch.empty()) return 0;
+    hipError_t e = hipMemcpyAsync(sv->d_new, sv->h_new.data(), sizeof(DevPlan) * batch.size(),
+                                  hipMemcpyHostToDevice, sv->s_up);
+    if (e == hipSuccess)
+        e = timed(ctx, KIND_DP, sv->s_up, [&] { return dp_launch(sv->d_new, (int)batch.size(), maxK, maxT, sv->s_up); });
+    if (e == hipSuccess) e = hipEventRecord(sv->searched, sv->s_up);
+    if (e != hipSuccess) {
+        HIP_IGNORE(hipStreamSynchronize(sv->s_up));
+        const cpf_status dev = fail(CPF_E_DEVICE, "search launch: %s", hipGetErrorString(e));
+        for (Request *r : batch) r->status = dev;
+        retire(ctx, sv, batch, dev);
+        return 0;
+    }
+    sv->searching = batch;
+    return (int)batch.size();
+}
+
+// A searched batch joins the work list (descriptors written on s_lm, so the
+// next tick sees them).
+void activate(Server *sv) {
+    const int64_t ts = now_ns();
+    for (Request *r : sv->searching) {
+        DevPlan d = r->plan->desc;
+        set_dev_ptr(d.st, sv->d_states + r->slot);
+        sv->h_work[r->slot] = d;
+        HIP_IGNORE(hipMemcpyAsync(sv->d_work + r->slot, &sv->h_work[r->slot], sizeof(DevPlan),
+                                  hipMemcpyHostToDevice, sv->s_lm));
+        r->t_search = ts;
+        // inputs are on the device now
+        std::vector<double>().swap(r->cand);
+    }
+    sv->searching.clear();
+}
+
+void server_main(cpf_ctx *ctx) {
+    std::unique_ptr<Server> sv(new Server());
+    const cpf_status init = server_init(ctx, sv.get());
+    std::vector<Request *> active;   // in the work list
+    while (true) {
+        const bool busy = !active.empty() || !sv->searching.empty();
+        {
+            std::unique_lock<std::mutex> lk(ctx->mu);
+            if (!busy)
+                ctx->cv_work.wait(lk, [&] { return ctx->stop || !ctx->pending.empty(); });
+            if (ctx->stop && ctx->pending.empty() && !busy) break;
+        }
+        if (init != CPF_OK) {   // no device server: fail everything queued
+            std::vector<Request *> q;
+            {
+                std::lock_guard<std::mutex> lk(ctx->mu);
+                q.assign(ctx->pending.begin(), ctx->pending.end());
+                ctx->pending.clear();
             }
-            int slot = 0;
-            while (sv->slot_req[slot]) ++slot;
-            r->slot = slot;
-            sv->slot_req[slot] = r;
-            DevPlan d = r->plan->desc;
-            set_dev_ptr(d.st, sv->d_states + slot);
-            sv->h_work[slot] = d;
-            LMState &ls = sv->h_states[slot];
-            memset(&ls, 0, sizeof(ls));
-            ls.lambda = r->opts.lambda0;
-            ls.nu = 2.0;
-            ls.iters_target = r->opts.iters;
-            HIP_IGNORE(hipMemcpyAsync(sv->d_states + slot, &ls, sizeof(LMState),
-                                      hipMemcpyHostToDevice, sv->s));
-            HIP_IGNORE(hipMemcpyAsync(sv->d_work + slot, &sv->h_work[slot], sizeof(DevPlan),
-                                      hipMemcpyHostToDevice, sv->s));
-            fresh.push_back(d);
-            maxK = std::max(maxK, r->K);
-            maxT = std::max(maxT, r->T);
-            active.push_back(r);
+            for (Request *r : q) {
+                r->status = init;
+                finish(ctx, sv.get(), r);
+            }
+            continue;
         }
+        // 1. admit and search a new batch when none is in flight
+        if (sv->searching.empty()) {
+            int used = 0;
+            for (Request *r : sv->slot_req) used += r != nullptr;
+            admit(ctx, sv.get(), sv->cap - used);
+        }
+        // 2. a finished search joins the work list before the next tick
+        if (!sv->searching.empty()) {
+            const hipError_t q = active.empty() ? hipEventSynchronize(sv->searched) : hipEventQuery(sv->searched);
+            if (q == hipSuccess) {
+                for (Request *r : sv->searching) active.push_back(r);
+                activate(sv.get());
+            } else if (q != hipErrorNotReady) {
+                const cpf_status dev = fail(CPF_E_DEVICE, "search: %s", hipGetErrorString(q));
+                std::vector<Request *> b = sv->searching;
+                sv->searching.clear();
+                retire(ctx, sv.get(), b, dev);
+            }
+        }
+        if (active.empty()) continue;
+        // 3. one LM tick over every slot, then all slot states in one copy
         cpf_status dev = CPF_OK;
-        // 2. search the admitted requests
-        if (!fresh.empty()) {
-            hipError_t e = hipMemcpyAsync(sv->d_new, fresh.data(), sizeof(DevPlan) * fresh.size(),
-                                          hipMemcpyHostToDevice, sv->s);
-            if (e == hipSuccess)
-                e = timed(ctx, KIND_DP, sv->s,
-                          [&] { return dp_launch(sv->d_new, (int)fresh.size(), maxK, maxT, sv->s); });
-            if (e == hipSuccess) e = hipStreamSynchronize(sv->s);
-            if (e != hipSuccess) dev = fail(CPF_E_DEVICE, "search launch: %s", hipGetErrorString(e));
-            const int64_t ts = now_ns();
-            for (Request *r : admitted)
-                if (r->plan) r->t_search = ts;
-        }
-        // 3. one LM tick over every slot
-        if (dev == CPF_OK && !active.empty()) {
-            hipError_t e = timed(ctx, KIND_LM, sv->s, [&] { return hipGraphLaunch(sv->exec, sv->s); });
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(sv->h_states.data(), sv->d_states, sizeof(LMState) * sv->cap,
-                                   hipMemcpyDeviceToHost, sv->s);
-            if (e == hipSuccess) e = hipStreamSynchronize(sv->s);
-            if (e != hipSuccess) dev = fail(CPF_E_DEVICE, "LM tick: %s", hipGetErrorString(e));
-        }
-        // 4. retire finished (or failed) requests
-        std::vector<Request *> still;
+        hipError_t e = timed(ctx, KIND_LM, sv->s_lm, [&] { return hipGraphLaunch(sv->exec, sv->s_lm); });
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(sv->h_states.data(), sv->d_states, sizeof(LMState) * sv->cap,
+                               hipMemcpyDeviceToHost, sv->s_lm);
+        if (e == hipSuccess) e = hipStreamSynchronize(sv->s_lm);
+        if (e != hipSuccess) dev = fail(CPF_E_DEVICE, "LM tick: %s", hipGetErrorString(e));
+        // 4. retire finished (or failed) requests together
+        std::vector<Request *> still, fin;
         for (Request *r : active) {
             bool finished = dev != CPF_OK;
             if (!finished) {
                 const LMState &ls = sv->h_states[r->slot];
                 finished = ls.status != 0 || (ls.iters_done >= r->opts.iters && ls.reported);
             }
-            if (finished) retire(ctx, sv.get(), r, dev);
-            else still.push_back(r);
+            (finished ? fin : still).push_back(r);
         }
+        retire(ctx, sv.get(), fin, dev);
         active.swap(still);
     }
     server_free(sv.get());
@@ -284,7 +378,7 @@ extern "C" cpf_status cpf_submit(cpf_ctx *ctx, const cpf_robot *robot, const cpf
     cpf_opts_default(&o);
     if (opts) o = *opts;
     if ((st = check_opts(&o)) != CPF_OK) return st;
-    const uint64_t bytes = plan_bytes(prob->T, prob->K, prob->node_pen != nullptr);
+    const uint64_t bytes = plan_class_bytes(prob->T, prob->K, prob->node_pen != nullptr);
     if (bytes > ctx->budget)
         return fail(CPF_E_NOMEM, "request needs %llu bytes, budget is %llu",
                     (unsigned long long)bytes, (unsigned long long)ctx->budget);
@@ -329,7 +423,7 @@ extern "C" cpf_status cpf_poll(cpf_ctx *ctx, uint64_t ticket, int32_t timeout_ms
         if (out->xi && !r->xi.empty()) memcpy(out->xi, r->xi.data(), r->xi.size() * sizeof(double));
         if (out->path && !r->path.empty())
             memcpy(out->path, r->path.data(), r->path.size() * sizeof(int32_t));
-        out->report = r->report;
+        out->report = r->rep;
         out->search_best = r->best;
         out->search_mjac = r->smjac;
         out->status = r->status;

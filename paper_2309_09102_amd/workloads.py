@@ -10,9 +10,10 @@
              K in {128, 256, 512}, sigma ~ U[0.02, 0.15], offset fraction
              ~ U[0, 0.3] and 30 LM iterations, served by cpf_submit/cpf_poll
              (continuous batching, mixed precision), and the same arrival
-             schedule served one request at a time by the all-FP64 path.
-             Requests are drawn from a pool of distinct seeded problems that
-             the stream cycles through (the pool keeps host memory bounded).
+             schedule served one request at a time by the all-FP64 path;
+             then a closed-loop burst (saturation) both ways.  Requests are
+             drawn from a pool of distinct seeded problems that the stream
+             cycles through (the pool keeps host memory bounded).
 
 Every mode prints one JSON object; inputs are synthetic and seeded.
 """
@@ -90,28 +91,11 @@ def _pct(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if xs else None
 
 
-def run_serve(duration_s=10.0, rate_hz=200.0, pool=48, iters=30, slots=256, ipt=10,
-              fp64_budget_s=None):
-    import torch
-    from paper_2309_09102_amd import cpf, synth
-    dev = torch.device("cuda:0")
-    arrivals = synth.config5_arrivals(rate_hz, duration_s)
-    gen_ctx = cpf.Context(0)
-    reqs = [_targets(gen_ctx, synth.config5_request(i), torch, dev) for i in range(pool)]
-    gen_ctx.close()
-
-    def stream_items():
-        return [(float(a), reqs[i % pool]) for i, a in enumerate(arrivals)]
-
-    # --- mixed precision, continuous batching ---------------------------------
-    ctx = cpf.Context(0, 64 << 30)
-    ctx.config(slots=slots, iters_per_tick=ipt)
-    opts = cpf.make_opts(iters=iters, prec="mixed")
-    w = ctx.submit(reqs[0].robot, reqs[0].targets, reqs[0].cand, opts)   # warm-up
-    ctx.poll(w, reqs[0].T)
-    items = stream_items()
+def _serve_stream(ctx, items, opts, iters, t_start):
+    """Submit items [(arrival_s, problem)] at their arrival times (a
+    submitter thread) and poll them in order; returns latencies (ms), the
+    waypoint-iterations done, statuses and the wall time."""
     tickets = [None] * len(items)
-    t_start = time.perf_counter()
 
     def submitter():
         for n, (at, p) in enumerate(items):
@@ -122,52 +106,90 @@ def run_serve(duration_s=10.0, rate_hz=200.0, pool=48, iters=30, slots=256, ipt=
 
     th = threading.Thread(target=submitter)
     th.start()
-    lat, done_work, statuses = [], 0, set()
+    lat, work, statuses = [], 0, set()
     for n, (at, p) in enumerate(items):
         while tickets[n] is None:
             time.sleep(0.0005)
         r = ctx.poll(tickets[n], p.T, timeout_ms=-1)
         lat.append((r["t_done_ns"] - r["t_submit_ns"]) * 1e-6)
-        done_work += p.T * iters
+        work += p.T * iters
         statuses.add(int(r["status"]))
     th.join()
-    t_end = time.perf_counter()
-    ctx.close()
-    mixed = {"requests": len(items), "throughput": done_work / (t_end - t_start),
-             "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99), "max_ms": max(lat),
-             "wall_s": t_end - t_start, "statuses": sorted(statuses)}
+    return lat, work, statuses, time.perf_counter() - t_start
 
-    # --- all FP64, one request at a time (same arrival schedule) --------------
-    ctx = cpf.Context(0, 64 << 30)
-    o64 = cpf.make_opts(iters=iters, prec="fp64")
-    budget = fp64_budget_s if fp64_budget_s is not None else duration_s * 3
-    lat64, work64 = [], 0
+
+def _one_at_a_time(ctx, items, opts, iters, budget_s):
+    """The plain path: each request searched and refined alone, in arrival
+    order, by the synchronous calls; stops after budget_s."""
+    lat, work, served = [], 0, 0
     t0 = time.perf_counter()
-    served = 0
     for at, p in items:
         now = time.perf_counter() - t0
         if now < at:
             time.sleep(at - now)
-        if time.perf_counter() - t0 > budget:
+        if time.perf_counter() - t0 > budget_s:
             break
-        plan = ctx.plan(p.robot, p.targets, p.cand, opts=o64)
+        plan = ctx.plan(p.robot, p.targets, p.cand, opts=opts)
         plan.dp_search()
         plan.lm_refine(iters, want_xi=True)
         plan.free()
-        lat64.append((time.perf_counter() - t0 - at) * 1e3)
-        work64 += p.T * iters
+        lat.append((time.perf_counter() - t0 - at) * 1e3)
+        work += p.T * iters
         served += 1
-    t1 = time.perf_counter()
+    return lat, work, served, time.perf_counter() - t0
+
+
+def run_serve(duration_s=10.0, rate_hz=200.0, pool=48, iters=30, slots=256, ipt=10,
+              burst=240, fp64_budget_s=None):
+    """Open loop: Poisson arrivals at rate_hz for duration_s, served by
+    continuous batching (mixed precision) and, on the same schedule, one
+    request at a time by the all-FP64 path.  Closed loop (saturation): a
+    burst of `burst` requests submitted at once, both ways."""
+    import torch
+    from paper_2309_09102_amd import cpf, synth
+    dev = torch.device("cuda:0")
+    arrivals = synth.config5_arrivals(rate_hz, duration_s)
+    gen_ctx = cpf.Context(0)
+    reqs = [_targets(gen_ctx, synth.config5_request(i), torch, dev) for i in range(pool)]
+    gen_ctx.close()
+    items = [(float(a), reqs[i % pool]) for i, a in enumerate(arrivals)]
+    burst_items = [(0.0, reqs[i % pool]) for i in range(burst)]
+    o_mix = cpf.make_opts(iters=iters, prec="mixed")
+    o_64 = cpf.make_opts(iters=iters, prec="fp64")
+    out = {"mode": "serve", "rate_hz": rate_hz, "duration_s": duration_s, "pool": pool,
+           "lm_iters": iters, "slots": slots, "iters_per_tick": ipt, "burst": burst,
+           "unit": "waypoint-LM-iters/s"}
+
+    # --- mixed precision, continuous batching -----------------------------------
+    ctx = cpf.Context(0, 64 << 30)
+    ctx.config(slots=slots, iters_per_tick=ipt)
+    w = ctx.submit(reqs[0].robot, reqs[0].targets, reqs[0].cand, o_mix)   # warm-up
+    ctx.poll(w, reqs[0].T)
+    lat, work, st, wall = _serve_stream(ctx, items, o_mix, iters, time.perf_counter())
+    out["mixed_open"] = {"requests": len(items), "throughput": work / wall, "p50_ms": _pct(lat, 50),
+                         "p99_ms": _pct(lat, 99), "max_ms": max(lat), "wall_s": wall,
+                         "statuses": sorted(st)}
+    lat, work, st, wall = _serve_stream(ctx, burst_items, o_mix, iters, time.perf_counter())
+    out["mixed_closed"] = {"requests": burst, "throughput": work / wall, "p50_ms": _pct(lat, 50),
+                           "p99_ms": _pct(lat, 99), "wall_s": wall, "statuses": sorted(st)}
     ctx.close()
-    fp64 = {"requests_served": served, "requests_offered": len(items),
-            "throughput": work64 / (t1 - t0), "p50_ms": _pct(lat64, 50),
-            "p99_ms": _pct(lat64, 99), "wall_s": t1 - t0,
-            "note": "stops after the time budget; unserved requests are not counted"}
-    return {"mode": "serve", "rate_hz": rate_hz, "duration_s": duration_s, "pool": pool,
-            "lm_iters": iters, "slots": slots, "iters_per_tick": ipt,
-            "unit": "waypoint-LM-iters/s", "mixed_continuous_batching": mixed,
-            "fp64_one_at_a_time": fp64,
-            "speedup": mixed["throughput"] / max(fp64["throughput"], 1e-9)}
+
+    # --- all FP64, one request at a time ----------------------------------------
+    ctx = cpf.Context(0, 64 << 30)
+    budget = fp64_budget_s if fp64_budget_s is not None else duration_s * 3
+    lat, work, served, wall = _one_at_a_time(ctx, items, o_64, iters, budget)
+    out["fp64_one_at_a_time_open"] = {
+        "requests_served": served, "requests_offered": len(items), "throughput": work / wall,
+        "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99), "wall_s": wall,
+        "note": "stops after the time budget; unserved requests are not counted"}
+    lat, work, served, wall = _one_at_a_time(ctx, burst_items, o_64, iters, budget)
+    out["fp64_one_at_a_time_closed"] = {"requests_served": served, "throughput": work / wall,
+                                        "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99), "wall_s": wall}
+    ctx.close()
+    out["speedup_open"] = out["mixed_open"]["throughput"] / max(out["fp64_one_at_a_time_open"]["throughput"], 1e-9)
+    out["speedup_closed"] = (out["mixed_closed"]["throughput"] /
+                             max(out["fp64_one_at_a_time_closed"]["throughput"], 1e-9))
+    return out
 
 
 if __name__ == "__main__":
