@@ -12,7 +12,12 @@ branch-offset candidates), 50 LM iterations, seed-0 7-DOF DH robot.
 
 Prints one JSON line.  `value` is waypoint-LM-iterations per second of the
 mixed-precision path (FP32 kinematics, FP64 solve); the all-FP64 path on the
-same GPU is reported beside it.
+same GPU is reported beside it.  The `serving` object is the other half of
+the metric: a short seeded request stream (Poisson arrivals at 200/s,
+T ~ U{50..2000}, K in {128, 256, 512}, 30 LM iterations) served by
+cpf_submit/cpf_poll (continuous batching, mixed precision) and by the
+all-FP64 path one request at a time, with p50/p99 latency, open loop and as
+a closed-loop burst.
 """
 from __future__ import annotations
 
@@ -52,6 +57,10 @@ def parse():
                          "additional measured workloads in paper_2309_09102_amd/workloads.py")
     ap.add_argument("--duration", type=float, default=10.0, help="serve: stream length (s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the short serving comparison (continuous batching, mixed precision, "
+                         "vs all-FP64 one request at a time) that the default line carries")
+    ap.add_argument("--serving-seconds", type=float, default=5.0)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy three times: the known-size "
@@ -204,6 +213,20 @@ def main():
         "report": {"mixed": rep_mixed, "fp64": rep_fp64},
         "roofline": roofline,
     }
+
+    if not args.no_serving:
+        # The serving half of the metric: the same seeded request stream
+        # (Poisson 200/s, T ~ U{50..2000}, K in {128, 256, 512}, 30 LM
+        # iterations) served by continuous batching in mixed precision and
+        # one request at a time by the all-FP64 path, open loop and as a
+        # closed-loop burst; latencies are submit -> result.
+        from paper_2309_09102_amd import workloads
+        sv = workloads.run_serve(duration_s=args.serving_seconds, burst=240,
+                                 fp64_budget_s=args.serving_seconds)
+        keep = ("throughput", "p50_ms", "p99_ms", "wall_s", "requests", "requests_served",
+                "requests_offered", "statuses")
+        out["serving"] = {k: ({kk: vv for kk, vv in v.items() if kk in keep} if isinstance(v, dict) else v)
+                          for k, v in sv.items()}
 
     if not args.no_cpu_baseline:
         import oracle

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <thread>
 
 #include "runtime.h"
 
@@ -129,6 +130,56 @@ void pool_clear(cpf_ctx *ctx) {
         for (void *p : kv.second) HIP_IGNORE(hipFree(p));
     ctx->pool.clear();
     ctx->pooled = 0;
+    for (auto &kv : ctx->pinned)
+        for (void *p : kv.second) HIP_IGNORE(hipHostFree(p));
+    ctx->pinned.clear();
+    ctx->pinned_total = 0;
+}
+
+void *pinned_get(cpf_ctx *ctx, uint64_t bytes, uint64_t *cls) {
+    uint64_t c = (uint64_t)1 << 20;
+    while (c < bytes) c <<= 1;
+    *cls = c;
+    {
+        std::lock_guard<std::mutex> lk(ctx->pool_mu);
+        auto it = ctx->pinned.find(c);
+        if (it != ctx->pinned.end() && !it->second.empty()) {
+            void *p = it->second.back();
+            it->second.pop_back();
+            return p;
+        }
+        if (ctx->pinned_total + c > ctx->pinned_cap) return nullptr;
+        ctx->pinned_total += c;
+    }
+    void *p = nullptr;
+    if (hipHostMalloc(&p, c, hipHostMallocDefault) != hipSuccess) {
+        std::lock_guard<std::mutex> lk(ctx->pool_mu);
+        ctx->pinned_total -= c;
+        return nullptr;
+    }
+    return p;
+}
+
+void pinned_put(cpf_ctx *ctx, void *p, uint64_t cls) {
+    std::lock_guard<std::mutex> lk(ctx->pool_mu);
+    ctx->pinned[cls].push_back(p);
+}
+
+void copy_parallel(void *dst, const void *src, size_t bytes) {
+    const size_t chunk = (size_t)4 << 20;
+    const int nt = (int)std::min<size_t>(4, (bytes + chunk - 1) / chunk);
+    if (nt <= 1) {
+        memcpy(dst, src, bytes);
+        return;
+    }
+    const size_t per = (bytes + nt - 1) / nt;
+    std::vector<std::thread> th;
+    for (int i = 1; i < nt; ++i) {
+        const size_t off = per * i, n = std::min(per, bytes - std::min(bytes, off));
+        if (n) th.emplace_back([=] { memcpy((char *)dst + off, (const char *)src + off, n); });
+    }
+    memcpy(dst, src, std::min(per, bytes));
+    for (auto &t : th) t.join();
 }
 
 static bool all_finite(const double *p, size_t n) {

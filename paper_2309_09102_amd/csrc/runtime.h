@@ -70,6 +70,11 @@ struct cpf_ctx {
     std::mutex pool_mu;
     std::map<uint64_t, std::vector<void *>> pool;
     uint64_t pooled = 0;
+    // Pinned host staging for submitted requests (same scheme, capped), so
+    // their uploads are asynchronous DMA.
+    std::map<uint64_t, std::vector<void *>> pinned;
+    uint64_t pinned_total = 0;
+    uint64_t pinned_cap = (uint64_t)4 << 30;
     // serving
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -132,6 +137,13 @@ hipError_t timed(cpf_ctx *ctx, int kind, hipStream_t s, F &&launch) {
 cpf_status arena_get(cpf_ctx *ctx, uint64_t cls, void **out);
 void arena_put(cpf_ctx *ctx, void *p, uint64_t cls);
 void pool_clear(cpf_ctx *ctx);
+// Pinned host buffer of at least `bytes` (class written to *cls), or
+// nullptr when the pinned cap is reached (the caller then uses pageable
+// memory).
+void *pinned_get(cpf_ctx *ctx, uint64_t bytes, uint64_t *cls);
+void pinned_put(cpf_ctx *ctx, void *p, uint64_t cls);
+// memcpy split over a few threads for large copies.
+void copy_parallel(void *dst, const void *src, size_t bytes);
 
 // Take an arena and upload one plan on stream s (asynchronous: the caller's
 // arrays in `prob` must stay alive until s is synchronised).  iters_target =

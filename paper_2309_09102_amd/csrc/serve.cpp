@@ -35,7 +35,12 @@ struct Request {
     HostRobot robot{};
     cpf_opts opts{};
     int T = 0, K = 0;
-    std::vector<double> targets, cand, node_pen;
+    // copies of the caller's arrays: candidates, targets, node costs, one
+    // buffer (pinned when the pinned pool allows, else pageable)
+    double *cand = nullptr, *targets = nullptr, *node_pen = nullptr;
+    void *stage = nullptr;
+    uint64_t stage_cls = 0;
+    std::vector<double> stage_vec;
     uint64_t bytes = 0;
     cpf_plan *plan = nullptr;
     int slot = -1;
@@ -114,6 +119,13 @@ void server_free(Server *sv) {
     if (sv->s_lm) HIP_IGNORE(hipStreamDestroy(sv->s_lm));
 }
 
+void release_stage(cpf_ctx *ctx, Request *r) {
+    if (r->stage) pinned_put(ctx, r->stage, r->stage_cls);
+    r->stage = nullptr;
+    std::vector<double>().swap(r->stage_vec);
+    r->cand = r->targets = r->node_pen = nullptr;
+}
+
 // Release a request's slot, plan and inputs and wake its pollers.  The slot's
 // descriptor is cleared on the LM stream, ahead of the next tick.
 void finish(cpf_ctx *ctx, Server *sv, Request *r) {
@@ -128,8 +140,7 @@ void finish(cpf_ctx *ctx, Server *sv, Request *r) {
         plan_destroy(r->plan);
         r->plan = nullptr;
     }
-    std::vector<double>().swap(r->cand);
-    std::vector<double>().swap(r->node_pen);
+    release_stage(ctx, r);
     std::vector<double>().swap(r->xi_soa);
     r->t_done = now_ns();
     std::lock_guard<std::mutex> lk(ctx->mu);
@@ -202,8 +213,7 @@ int admit(cpf_ctx *ctx, Server *sv, int free_slots) {
             r = ctx->pending.front();
             ctx->pending.pop_front();
         }
-        cpf_problem pb{r->T, r->K, r->targets.data(), r->cand.data(),
-                       r->node_pen.empty() ? nullptr : r->node_pen.data()};
+        cpf_problem pb{r->T, r->K, r->targets, r->cand, r->node_pen};
         r->t_admit = now_ns();
         cpf_status st = plan_create(ctx, r->robot, &pb, &r->opts, r->opts.iters, sv->s_up, &r->plan);
         if (st == CPF_E_NOMEM) {   // wait for arenas to come back
@@ -254,7 +264,7 @@ int admit(cpf_ctx *ctx, Server *sv, int free_slots) {
 
 // A searched batch joins the work list (descriptors written on s_lm, so the
 // next tick sees them).
-void activate(Server *sv) {
+void activate(cpf_ctx *ctx, Server *sv) {
     const int64_t ts = now_ns();
     for (Request *r : sv->searching) {
         DevPlan d = r->plan->desc;
@@ -263,8 +273,7 @@ void activate(Server *sv) {
         HIP_IGNORE(hipMemcpyAsync(sv->d_work + r->slot, &sv->h_work[r->slot], sizeof(DevPlan),
                                   hipMemcpyHostToDevice, sv->s_lm));
         r->t_search = ts;
-        // inputs are on the device now
-        std::vector<double>().swap(r->cand);
+        release_stage(ctx, r);   // the inputs are on the device now
     }
     sv->searching.clear();
 }
@@ -305,7 +314,7 @@ void server_main(cpf_ctx *ctx) {
             const hipError_t q = active.empty() ? hipEventSynchronize(sv->searched) : hipEventQuery(sv->searched);
             if (q == hipSuccess) {
                 for (Request *r : sv->searching) active.push_back(r);
-                activate(sv.get());
+                activate(ctx, sv.get());
             } else if (q != hipErrorNotReady) {
                 const cpf_status dev = fail(CPF_E_DEVICE, "search: %s", hipGetErrorString(q));
                 std::vector<Request *> b = sv->searching;
@@ -387,14 +396,29 @@ extern "C" cpf_status cpf_submit(cpf_ctx *ctx, const cpf_robot *robot, const cpf
     r->opts = o;
     r->T = prob->T;
     r->K = prob->K;
-    r->targets.assign(prob->targets, prob->targets + (size_t)prob->T * 12);
-    r->cand.assign(prob->cand, prob->cand + (size_t)prob->K * prob->T * NJ);
-    if (prob->node_pen) r->node_pen.assign(prob->node_pen, prob->node_pen + (size_t)prob->T * prob->K);
+    const size_t n_cand = (size_t)prob->K * prob->T * NJ, n_tg = (size_t)prob->T * 12;
+    const size_t n_pen = prob->node_pen ? (size_t)prob->T * prob->K : 0;
+    const size_t n_all = n_cand + n_tg + n_pen;
+    r->stage = pinned_get(ctx, n_all * sizeof(double), &r->stage_cls);
+    double *buf = (double *)r->stage;
+    if (!buf) {
+        r->stage_vec.resize(n_all);
+        buf = r->stage_vec.data();
+    }
+    r->cand = buf;
+    r->targets = buf + n_cand;
+    r->node_pen = n_pen ? buf + n_cand + n_tg : nullptr;
+    copy_parallel(r->cand, prob->cand, n_cand * sizeof(double));
+    memcpy(r->targets, prob->targets, n_tg * sizeof(double));
+    if (n_pen) copy_parallel(r->node_pen, prob->node_pen, n_pen * sizeof(double));
     r->bytes = bytes;
     r->t_submit = now_ns();
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
-        if (ctx->stop) return fail(CPF_E_STATE, "context is shutting down");
+        if (ctx->stop) {
+            release_stage(ctx, r.get());
+            return fail(CPF_E_STATE, "context is shutting down");
+        }
         if (!ctx->server_thread.joinable()) ctx->server_thread = std::thread(server_main, ctx);
         r->ticket = ctx->next_ticket++;
         *ticket = r->ticket;
