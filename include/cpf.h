@@ -180,6 +180,18 @@ cpf_status cpf_solve_batch(cpf_ctx *ctx, int32_t nplans, const cpf_robot *robots
                            const cpf_problem *probs, const cpf_opts *opts,
                            cpf_result *results);
 
+/* Optimise the M smoothest of the problem's K candidate plans directly,
+ * without the search (the "BatchOpt" planner of the paper, Sec. III and its
+ * planner list): the M candidates with the least mjac (largest joint change
+ * between consecutive waypoints, Sec. III-B), ties to the lower index, each
+ * clamped to the limits and refined by opts->iters LM iterations as an
+ * independent plan (one workgroup each).  Writes the chosen candidate
+ * indices to idx_out[M] (ascending mjac) and one result per candidate to
+ * results[M] (xi / path may be NULL; path is all zeros: the seed is the
+ * candidate itself).  1 <= M <= K, else CPF_E_ARG.  Synchronous. */
+cpf_status cpf_batchopt(cpf_ctx *ctx, const cpf_robot *robot, const cpf_problem *prob,
+                        const cpf_opts *opts, int32_t M, int32_t *idx_out, cpf_result *results);
+
 /* Server shape, before the first cpf_submit: `slots` requests resident on the
  * device at once (default 256) and LM iterations per tick (default 10).
  * CPF_E_STATE once the server runs. */

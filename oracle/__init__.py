@@ -21,9 +21,11 @@ Parity status per function (what pins it, in tests/test_oracle_pins.py):
                   convergence with w_s -> 0.  The exact iterate path (the
                   sequence of accept / reject decisions) is parity unpinned:
                   the paper prints no worked example of it.
+  batchopt        selection pinned against numpy's own mjac ordering; each
+                  result is plan() on one candidate (pinned above)
 """
 from .oracle import (build, lib_path, fk, log_so3, cost, dp, mjac, btd_solve,
-                     lm_step, lm, plan, pose_compare, DEFAULT_LM)
+                     lm_step, lm, plan, batchopt, pose_compare, DEFAULT_LM)
 
 __all__ = ["build", "lib_path", "fk", "log_so3", "cost", "dp", "mjac",
-           "btd_solve", "lm_step", "lm", "plan", "pose_compare", "DEFAULT_LM"]
+           "btd_solve", "lm_step", "lm", "plan", "batchopt", "pose_compare", "DEFAULT_LM"]

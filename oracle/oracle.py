@@ -257,6 +257,20 @@ def plan(robot, cand, targets, iters, opts=None, extra=None, margin=LIMIT_MARGIN
     return dict(path=path, best=float(best[0]), xi=xi, cost=float(cst[0]), rc=int(rc))
 
 
+def batchopt(robot, cand, targets, M, iters, opts=None):
+    """Optimise the M smoothest candidate plans directly, without the search
+    (the paper's "BatchOpt" planner, described in a comment next to its list
+    of planners): the candidates with the least mjac (Sec. III-B's maximum
+    joint change between consecutive waypoints), ties to the lower index,
+    each clamped and refined by `iters` LM iterations on its own.  Returns
+    (indices [M], list of plan() results)."""
+    cand = _d(cand)
+    K = cand.shape[0]
+    m = [mjac(cand[k]) for k in range(K)]
+    order = sorted(range(K), key=lambda k: (m[k], k))[:M]
+    return order, [plan(robot, cand[k:k + 1], targets, iters, opts) for k in order]
+
+
 def pose_compare(robot, xi_a, xi_b=None, targets=None):
     """(max position difference m, max rotation angle rad) under oracle FK."""
     lib = _load()

@@ -84,6 +84,8 @@ _lib.cpf_dp_search.argtypes = [_vp, _ip, _dp, _dp]
 _lib.cpf_lm_refine.argtypes = [_vp, C.c_int32, _dp, C.POINTER(cpf_lm_report)]
 _lib.cpf_solve_batch.argtypes = [_vp, C.c_int32, C.POINTER(cpf_robot), C.POINTER(cpf_problem),
                                  C.POINTER(cpf_opts), C.POINTER(cpf_result)]
+_lib.cpf_batchopt.argtypes = [_vp, C.POINTER(cpf_robot), C.POINTER(cpf_problem), C.POINTER(cpf_opts),
+                              C.c_int32, _ip, C.POINTER(cpf_result)]
 _lib.cpf_submit.argtypes = [_vp, C.POINTER(cpf_robot), C.POINTER(cpf_problem),
                             C.POINTER(cpf_opts), C.POINTER(C.c_uint64)]
 _lib.cpf_poll.argtypes = [_vp, C.c_uint64, C.c_int32, C.POINTER(cpf_result)]
@@ -92,14 +94,14 @@ _lib.cpf_ctx_profile.argtypes = [_vp, C.c_int32]
 _lib.cpf_ctx_kernel_stats.argtypes = [_vp, C.c_char_p, C.POINTER(C.c_double),
                                       C.POINTER(C.c_int64)]
 for _f in ("cpf_ctx_create", "cpf_plan_init", "cpf_fk_batch", "cpf_dp_search", "cpf_lm_refine",
-           "cpf_solve_batch", "cpf_submit", "cpf_poll", "cpf_ctx_profile",
+           "cpf_solve_batch", "cpf_batchopt", "cpf_submit", "cpf_poll", "cpf_ctx_profile",
            "cpf_ctx_kernel_stats", "cpf_ctx_config"):
     getattr(_lib, _f).restype = C.c_int
 
 EXPORTS = ("cpf_opts_default", "cpf_last_error", "cpf_ctx_create", "cpf_ctx_destroy",
            "cpf_ctx_bytes_in_use", "cpf_plan_init", "cpf_plan_free", "cpf_fk_batch",
-           "cpf_dp_search", "cpf_lm_refine", "cpf_solve_batch", "cpf_submit", "cpf_poll",
-           "cpf_ctx_profile", "cpf_ctx_kernel_stats", "cpf_ctx_config")
+           "cpf_dp_search", "cpf_lm_refine", "cpf_solve_batch", "cpf_batchopt", "cpf_submit",
+           "cpf_poll", "cpf_ctx_profile", "cpf_ctx_kernel_stats", "cpf_ctx_config")
 
 
 def last_error() -> str:
@@ -258,6 +260,27 @@ def solve_batch(ctx, problems, opts=None):
     return [_result(results[i], *outs[i]) for i in range(n)]
 
 
+def batchopt(ctx, robot, targets, cand, M: int, opts=None, node_pen=None):
+    """The M smoothest candidates optimised directly.  Returns (indices,
+    list of result dicts), in ascending candidate mjac."""
+    rb = make_robot(robot)
+    pb = make_problem(targets, cand, node_pen)
+    T = pb.struct.T
+    idx = np.empty(max(M, 0), dtype=np.int32)
+    results = (cpf_result * max(M, 1))()
+    outs = []
+    for i in range(M):
+        xi = np.empty((T, 7))
+        path = np.empty(T, dtype=np.int32)
+        outs.append((xi, path))
+        results[i].xi = _ptr(xi)
+        results[i].path = path.ctypes.data_as(_ip)
+    o = opts if opts is not None else opts_default()
+    _check(_lib.cpf_batchopt(ctx, C.byref(rb.struct), C.byref(pb.struct), C.byref(o), M,
+                             idx.ctypes.data_as(_ip), results))
+    return [int(k) for k in idx], [_result(results[i], *outs[i]) for i in range(M)]
+
+
 def _result(r: cpf_result, xi, path) -> dict:
     return dict(xi=xi, path=path, report=_report(r.report), search_best=r.search_best,
                 search_mjac=r.search_mjac, status=r.status,
@@ -334,6 +357,9 @@ class Context:
 
     def solve_batch(self, problems, opts=None):
         return solve_batch(self.h, problems, opts)
+
+    def batchopt(self, robot, targets, cand, M: int, opts=None, node_pen=None):
+        return batchopt(self.h, robot, targets, cand, M, opts, node_pen)
 
     def submit(self, robot, targets, cand, opts=None, node_pen=None) -> int:
         return submit(self.h, robot, targets, cand, opts, node_pen)

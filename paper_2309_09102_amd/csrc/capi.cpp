@@ -588,6 +588,55 @@ cpf_status cpf_solve_batch(cpf_ctx *ctx, int32_t nplans, const cpf_robot *robots
     return CPF_OK;
 }
 
+cpf_status cpf_batchopt(cpf_ctx *ctx, const cpf_robot *robot, const cpf_problem *prob,
+                        const cpf_opts *opts, int32_t M, int32_t *idx_out, cpf_result *results) {
+    if (!ctx || !idx_out || !results) return fail(CPF_E_ARG, "ctx / idx_out / results is NULL");
+    HostRobot hr;
+    cpf_status st;
+    if ((st = check_robot(robot, &hr)) != CPF_OK) return st;
+    if ((st = check_problem(prob)) != CPF_OK) return st;
+    if (M < 1 || M > prob->K) return fail(CPF_E_ARG, "M=%d with K=%d", M, prob->K);
+    cpf_opts o;
+    cpf_opts_default(&o);
+    if (opts) o = *opts;
+    if ((st = check_opts(&o)) != CPF_OK) return st;
+    HIP_TRY(hipSetDevice(ctx->device));
+    // 1. the candidates' mjac on the device (the uploaded plan's penalty
+    //    array is free until a search runs)
+    const int T = prob->T, K = prob->K;
+    cpf_plan *p = nullptr;
+    if ((st = plan_create(ctx, hr, prob, &o, 0, ctx->stream, &p)) != CPF_OK) return st;
+    std::vector<double> m(K);
+    hipError_t e = cand_mjac_launch((const float *)(p->arena + p->L.cand), T, K, (double *)(p->arena + p->L.pen),
+                                    ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(m.data(), p->arena + p->L.pen, (size_t)K * sizeof(double), hipMemcpyDeviceToHost,
+                           ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    plan_destroy(p);
+    if (e != hipSuccess) return fail(CPF_E_DEVICE, "candidate mjac: %s", hipGetErrorString(e));
+    // 2. the M smallest (mjac, index)
+    std::vector<int> order(K);
+    for (int k = 0; k < K; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return m[a] < m[b]; });
+    // 3. one single-candidate problem each (views into the caller's arrays;
+    //    a caller node cost is gathered per candidate)
+    std::vector<cpf_robot> robots(M, *robot);
+    std::vector<cpf_problem> probs(M);
+    std::vector<std::vector<double>> pens(M);
+    for (int i = 0; i < M; ++i) {
+        const int k = order[i];
+        idx_out[i] = k;
+        probs[i] = cpf_problem{T, 1, prob->targets, prob->cand + (size_t)k * T * NJ, nullptr};
+        if (prob->node_pen) {
+            pens[i].resize(T);
+            for (int t = 0; t < T; ++t) pens[i][t] = prob->node_pen[(size_t)t * K + k];
+            probs[i].node_pen = pens[i].data();
+        }
+    }
+    return cpf_solve_batch(ctx, M, robots.data(), probs.data(), &o, results);
+}
+
 cpf_status cpf_ctx_profile(cpf_ctx *ctx, int32_t enable) {
     if (!ctx) return fail(CPF_E_ARG, "ctx is NULL");
     std::lock_guard<std::mutex> lk(ctx->prof_mu);

@@ -21,6 +21,9 @@ hipError_t fk_batch_launch(const HostRobot &hr, int64_t M, int prec, const void 
 // targets [T][12], doubles) into the device layout (cand float [T][7][K],
 // targets [12][T]).
 hipError_t stage_launch(const double *raw, int T, int K, float *cand, double *targets, hipStream_t s);
+// mjac of every candidate plan (max over steps and joints of the change
+// between consecutive waypoints), cand float [T][7][K] -> out double [K].
+hipError_t cand_mjac_launch(const float *cand, int T, int K, double *out, hipStream_t s);
 // Search + seed gather for nplans plans: the predecessor lists over the
 // whole GPU, then one workgroup per plan for the stages.
 hipError_t dp_launch(const DevPlan *d_plans, int nplans, int maxK, int maxT, hipStream_t s);

@@ -353,4 +353,25 @@ hipError_t dp_launch(const DevPlan *d_plans, int nplans, int maxK, int maxT, hip
     return hipGetLastError();
 }
 
+// One lane per candidate plan: its mjac, computed like the search computes
+// edges (exact FP64 differences of the float32 values).
+__global__ __launch_bounds__(256) void cand_mjac_kernel(const float *__restrict__ cand, int T, int K,
+                                                        double *__restrict__ out) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= K) return;
+    double m = 0.0;
+    for (int t = 0; t + 1 < T; ++t)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+            m = fmax(m, fabs((double)cand[((size_t)(t + 1) * NJ + j) * K + k] -
+                             (double)cand[((size_t)t * NJ + j) * K + k]));
+    out[k] = m;
+}
+
+hipError_t cand_mjac_launch(const float *cand, int T, int K, double *out, hipStream_t s) {
+    if (K <= 0) return hipSuccess;
+    hipLaunchKernelGGL(cand_mjac_kernel, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, cand, T, K, out);
+    return hipGetLastError();
+}
+
 }  // namespace cpf

@@ -6,6 +6,8 @@
   T1000_K512 one request with T=1000, K=512, 50 LM iterations; the mixed arm
              (FP32 kinematics + FP64 solve + one FP64 refinement step) and the
              all-FP64 arm (their agreement with the oracle is a GPU test).
+  batchopt   the 5 smoothest candidates of the T=300, K=256 request optimised
+             directly without the search, 50 LM iterations each.
   serve      Poisson arrivals (200 requests/s) of requests with T ~ U{50..2000},
              K in {128, 256, 512}, sigma ~ U[0.02, 0.15], offset fraction
              ~ U[0, 0.3] and 30 LM iterations, served by cpf_submit/cpf_poll
@@ -83,6 +85,34 @@ def run_precision(iters=50):
                             "waypoint_lm_iters_per_s": p.T * iters / (t1 - t0),
                             "kernels_ms": {k: v[0] for k, v in st.items()},
                             "pose_err_vs_targets": [rep["max_pos_err_m"], rep["max_rot_err_rad"]]}
+    ctx.close()
+    return out
+
+
+def run_batchopt(M=5, iters=50):
+    """The M smoothest of the T=300, K=256 request's candidates optimised
+    directly (no search), both precisions."""
+    import torch
+    from paper_2309_09102_amd import cpf, synth
+    dev = torch.device("cuda:0")
+    ctx = cpf.Context(0)
+    p = _targets(ctx, synth.config2(), torch, dev)
+    out = {"mode": "batchopt", "T": p.T, "K": p.K, "M": M, "lm_iters": iters, "arms": {}}
+    for arm, prec in (("mixed", "mixed"), ("fp64", "fp64")):
+        o = cpf.make_opts(iters=iters, prec=prec)
+        ctx.batchopt(p.robot, p.targets, p.cand, M, opts=o)           # warm-up
+        reps = []
+        t0 = time.perf_counter()
+        for _ in range(3):
+            idx, res = ctx.batchopt(p.robot, p.targets, p.cand, M, opts=o)
+        dt = (time.perf_counter() - t0) / 3
+        costs = [r["report"]["cost"] for r in res]
+        out["arms"][arm] = {"latency_ms": dt * 1e3,
+                            "waypoint_lm_iters_per_s": M * p.T * iters / dt,
+                            "candidates": idx, "final_cost": costs,
+                            "best": idx[int(np.argmin(costs))],
+                            "pose_err_vs_targets_best": [res[int(np.argmin(costs))]["report"]["max_pos_err_m"],
+                                                         res[int(np.argmin(costs))]["report"]["max_rot_err_rad"]]}
     ctx.close()
     return out
 
@@ -195,12 +225,14 @@ def run_serve(duration_s=10.0, rate_hz=200.0, pool=48, iters=30, slots=256, ipt=
 if __name__ == "__main__":
     import argparse
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["batch64", "T1000_K512", "serve"])
+    ap.add_argument("mode", choices=["batch64", "T1000_K512", "batchopt", "serve"])
     ap.add_argument("--duration", type=float, default=10.0)
     a = ap.parse_args()
     if a.mode == "batch64":
         print(json.dumps(run_batch64()))
     elif a.mode == "T1000_K512":
         print(json.dumps(run_precision()))
+    elif a.mode == "batchopt":
+        print(json.dumps(run_batchopt()))
     else:
         print(json.dumps(run_serve(duration_s=a.duration)))

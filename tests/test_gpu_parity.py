@@ -219,6 +219,32 @@ def test_bad_inputs_rejected(ctx):
         small.close()
 
 
+# ---- BatchOpt: the M smoothest candidates, optimised directly --------------------
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batchopt_matches_oracle(ctx, prec):
+    p = H.small_problem(seed=81, T=60, K=24)
+    cand = p.cand.copy()
+    cand[7] = cand[3]                    # a tie in mjac: the lower index first
+    # 50 iterations: both arms converged, so the comparison is not of two
+    # mid-descent iterates from a raw (noisy) candidate
+    idx, res = ctx.batchopt(p.robot, p.targets, cand, 6, opts=cpf.make_opts(iters=50, prec=prec))
+    idx_ref, ref = oracle.batchopt(p.robot, cand, p.targets, 6, 50)
+    assert idx == idx_ref
+    for r, rr in zip(res, ref):
+        assert r["status"] == 0 and np.all(r["path"] == 0)
+        ep, er, ec = H.parity_metrics(p, r["xi"], rr["xi"])
+        assert ep <= POS_TOL and er <= ROT_TOL and ec <= COST_TOL, (ep, er, ec)
+
+
+def test_batchopt_rejects_bad_m(ctx):
+    p = H.small_problem(seed=82, T=10, K=4)
+    for M in (0, 5):
+        with pytest.raises(cpf.CpfError) as ei:
+            ctx.batchopt(p.robot, p.targets, p.cand, M)
+        assert ei.value.status == cpf.E_ARG
+
+
 # ---- batching invariance -------------------------------------------------------
 
 def test_solve_batch_equals_single(ctx):

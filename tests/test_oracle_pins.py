@@ -459,3 +459,23 @@ def test_paper_constants():
     assert oracle.oracle.LIMIT_MARGIN == pytest.approx(math.radians(c["limit_margin_deg"]["value"]))
     # the penalty exceeds any possible joint change of a revolute joint (pi)
     assert c["limit_penalty"]["value"] > math.pi
+
+
+# ---- BatchOpt: the M smoothest candidates, optimised directly -------------------
+
+def test_p14_batchopt_selects_least_mjac_candidates():
+    rb = synth.make_robot(3)
+    prob = synth.make_problem(rb, seed=9, T=12, K=9, sigma=0.1, n_branch=3)
+    cand = prob.cand.copy()
+    cand[4] = cand[2]                    # an exact tie: the lower index goes first
+    targets = oracle.fk(rb, prob.q_star)
+    idx, res = oracle.batchopt(rb, cand, targets, 5, 3)
+    # numpy's own mjac: max |q_{t+1} - q_t| over steps and joints
+    m = np.abs(np.diff(cand, axis=1)).max(axis=(1, 2))
+    expect = sorted(range(len(cand)), key=lambda k: (m[k], k))[:5]
+    assert idx == expect
+    assert idx.index(2) < idx.index(4) if 4 in idx else True
+    for k, r in zip(idx, res):
+        assert np.all(r["path"] == 0)   # one candidate: the search keeps it
+        ref = oracle.plan(rb, cand[k:k + 1], targets, 3)
+        assert np.array_equal(r["xi"], ref["xi"])
