@@ -23,9 +23,14 @@ Parity status per function (what pins it, in tests/test_oracle_pins.py):
                   the paper prints no worked example of it.
   batchopt        selection pinned against numpy's own mjac ordering; each
                   result is plan() on one candidate (pinned above)
+  lm_schedule     single steps equal lm() with the other weight zero; the
+                  latest valid trajectory meets the thresholds under FK; its
+                  length vs numpy; the first check on a valid seed passes
 """
 from .oracle import (build, lib_path, fk, log_so3, cost, dp, mjac, btd_solve,
-                     lm_step, lm, plan, batchopt, pose_compare, DEFAULT_LM)
+                     lm_step, lm, lm_schedule, plan, batchopt, pose_compare,
+                     DEFAULT_LM, VALID_TOL)
 
 __all__ = ["build", "lib_path", "fk", "log_so3", "cost", "dp", "mjac",
-           "btd_solve", "lm_step", "lm", "plan", "batchopt", "pose_compare", "DEFAULT_LM"]
+           "btd_solve", "lm_step", "lm", "lm_schedule", "plan", "batchopt", "pose_compare",
+           "DEFAULT_LM", "VALID_TOL"]

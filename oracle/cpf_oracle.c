@@ -614,6 +614,98 @@ void or_pose_compare(int n, const double *a, const double *d, const double *alph
     out[0] = mp; out[1] = mr;
 }
 
+/*
+ * Non-stationary objective with anytime validity (Sec. III-C: the optimiser
+ * alternates between the pose residual alone and the differencing residual,
+ * and keeps the latest valid solution; validity thresholds of Sec. II).
+ * Before every iteration, and once after the last, the current trajectory is
+ * checked: position error <= tol[0] (m) and geodesic rotation error <=
+ * tol[1] (rad) at every waypoint, and no joint changing by more than tol[2]
+ * (rad) between consecutive waypoints (joint limits hold by clamping).  A
+ * trajectory that passes is kept in xi_valid.  A trajectory whose pose
+ * errors are within the thresholds then takes one LM step on the
+ * differencing residual alone (w_pose = 0); any other takes one LM step on
+ * the pose residual alone (w_smooth = 0).  Each objective keeps its own
+ * damping (lambda, nu), updated by the same Nielsen rule as or_lm.
+ * info[0] = checks passed, info[1] = iteration of the first pass (-1: none;
+ * iters: only after the last iteration), info[2] = trajectory length of the
+ * latest valid trajectory (sum over steps and joints of |change|), info[3] =
+ * pose steps taken, info[4] = differencing steps taken.
+ */
+int or_lm_schedule(int n, const double *a, const double *d, const double *alpha,
+                   const double *theta_off, const double *lo, const double *hi, int T, double *xi,
+                   const double *targets, const double *opts5, const double *tol, int iters,
+                   double *xi_valid, double *info) {
+    or_robot rb = {n, a, d, alpha, theta_off, lo, hi};
+    or_lm_opts o = {opts5[0], opts5[1], opts5[2], opts5[3], opts5[4]};
+    size_t nn = (size_t)n * n, nT = (size_t)n * T;
+    double *A = (double *)malloc(sizeof(double) * nn * T);
+    double *g = (double *)malloc(sizeof(double) * nT);
+    double *Db = (double *)malloc(sizeof(double) * nn * T);
+    double *rhs = (double *)malloc(sizeof(double) * nT);
+    double *delta = (double *)malloc(sizeof(double) * nT);
+    double *trial = (double *)malloc(sizeof(double) * nT);
+    int rc = 0;
+    info[0] = 0; info[1] = -1; info[2] = 0; info[3] = 0; info[4] = 0;
+    if (!A || !g || !Db || !rhs || !delta || !trial) { rc = -2; goto done; }
+    for (size_t e = 0; e < nT; ++e) {
+        int j = (int)(e % (size_t)n);
+        if (xi[e] < lo[j]) xi[e] = lo[j];
+        if (xi[e] > hi[j]) xi[e] = hi[j];
+    }
+    double lam[2] = {o.lambda0, o.lambda0}, nu[2] = {2.0, 2.0};
+    for (int it = 0; it <= iters; ++it) {
+        double err[2];
+        or_pose_compare(n, a, d, alpha, theta_off, T, xi, NULL, targets, err);
+        int pose_ok = err[0] <= tol[0] && err[1] <= tol[1];
+        int steps_ok = or_mjac(T, n, xi) <= tol[2];
+        if (pose_ok && steps_ok) {
+            memcpy(xi_valid, xi, sizeof(double) * nT);
+            info[0] += 1;
+            if (info[1] < 0) info[1] = it;
+            double len = 0.0;
+            for (int t = 0; t + 1 < T; ++t)
+                for (int j = 0; j < n; ++j) len += fabs(xi[(size_t)(t + 1) * n + j] - xi[(size_t)t * n + j]);
+            info[2] = len;
+        }
+        if (it == iters) break;
+        const int m = pose_ok ? 1 : 0;   /* 0: pose step, 1: differencing step */
+        const double wp = m ? 0.0 : o.w_pose, ws = m ? o.w_smooth : 0.0;
+        info[3 + m] += 1;
+        const double C = cost_of(&rb, T, xi, targets, wp, ws);
+        linearise(&rb, T, xi, targets, wp, ws, A, g);
+        if (lm_solve(T, n, A, g, ws, lam[m], delta, Db, rhs) != 0) { rc = -1; break; }
+        for (size_t e = 0; e < nT; ++e) {
+            int j = (int)(e % (size_t)n);
+            double v = xi[e] + delta[e];
+            if (v < lo[j]) v = lo[j];
+            if (v > hi[j]) v = hi[j];
+            trial[e] = v;
+        }
+        const double Cn = cost_of(&rb, T, trial, targets, wp, ws);
+        double pred = 0.0;
+        for (size_t e = 0; e < nT; ++e) pred += delta[e] * (lam[m] * delta[e] - g[e]);
+        pred *= 0.5;
+        if (Cn < C) {
+            double rho = (C - Cn) / pred;
+            double u = 2.0 * rho - 1.0;
+            double f = 1.0 - u * u * u;
+            if (f < 1.0 / 3.0) f = 1.0 / 3.0;
+            lam[m] *= f;
+            nu[m] = 2.0;
+            memcpy(xi, trial, sizeof(double) * nT);
+        } else {
+            lam[m] *= nu[m];
+            nu[m] *= 2.0;
+        }
+        if (lam[m] < o.lambda_min) lam[m] = o.lambda_min;
+        if (lam[m] > o.lambda_max) lam[m] = o.lambda_max;
+    }
+done:
+    free(A); free(g); free(Db); free(rhs); free(delta); free(trial);
+    return rc;
+}
+
 /* FK of M configurations q[M][n] -> pose[M][12] (and J[M][6][n] if non-NULL). */
 void or_fk_many(int n, const double *a, const double *d, const double *alpha,
                 const double *theta_off, long M, const double *q, double *pose, double *J) {

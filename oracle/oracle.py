@@ -75,6 +75,9 @@ def _load():
         lib.or_pose_compare.argtypes = [C.c_int, _dp, _dp, _dp, _dp, C.c_int, _dp, _dp,
                                         _dp, _dp]
         lib.or_pose_compare.restype = None
+        lib.or_lm_schedule.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, C.c_int, _dp, _dp, _dp,
+                                       _dp, C.c_int, _dp, _dp]
+        lib.or_lm_schedule.restype = C.c_int
         _lib = lib
         return lib
 
@@ -255,6 +258,29 @@ def plan(robot, cand, targets, iters, opts=None, extra=None, margin=LIMIT_MARGIN
                      _p(tg), _p(ex), margin, penalty, _p(o5), int(iters), _ipp(path),
                      _p(best), _p(xi), _p(cst))
     return dict(path=path, best=float(best[0]), xi=xi, cost=float(cst[0]), rc=int(rc))
+
+
+# Validity thresholds of Sec. II: 0.1 mm position, 0.1 degree rotation, and
+# at most 7 degrees of change of a revolute joint between waypoints.
+VALID_TOL = (1e-4, np.deg2rad(0.1), np.deg2rad(7.0))
+
+
+def lm_schedule(robot, xi0, targets, iters, opts=None, tol=VALID_TOL):
+    """Pose-first alternating LM with the latest-valid store (see
+    or_lm_schedule).  Returns dict(xi, xi_valid | None, n_valid, first_valid,
+    valid_length, pose_steps, diff_steps, rc)."""
+    lib = _load()
+    xi = _d(xi0).copy()
+    T, n = xi.shape
+    tg = _d(targets)
+    a, d, al, th, lo, hi = _robot(robot)
+    xv = np.zeros((T, n))
+    info = np.zeros(5)
+    rc = lib.or_lm_schedule(n, _p(a), _p(d), _p(al), _p(th), _p(lo), _p(hi), T, _p(xi), _p(tg),
+                            _p(_opts5(opts)), _p(_d(tol)), int(iters), _p(xv), _p(info))
+    return dict(xi=xi, xi_valid=xv if info[0] > 0 else None, n_valid=int(info[0]),
+                first_valid=int(info[1]), valid_length=float(info[2]), pose_steps=int(info[3]),
+                diff_steps=int(info[4]), rc=int(rc))
 
 
 def batchopt(robot, cand, targets, M, iters, opts=None):

@@ -41,6 +41,10 @@ MUTANTS = {
     "lm_always_accept": ("int acc = Cn < C;", "int acc = 1;"),
     "lm_no_clamp": ("if (v > hi[j]) v = hi[j];\n                trial[e] = v;",
                     "trial[e] = v;"),
+    "sched_modes_swapped": ("const int m = pose_ok ? 1 : 0;", "const int m = pose_ok ? 0 : 1;"),
+    "sched_step_check_dropped": ("int steps_ok = or_mjac(T, n, xi) <= tol[2];", "int steps_ok = 1;"),
+    "sched_length_signed": ("len += fabs(xi[(size_t)(t + 1) * n + j] - xi[(size_t)t * n + j]);",
+                            "len += xi[(size_t)(t + 1) * n + j] - xi[(size_t)t * n + j];"),
 }
 
 
@@ -63,6 +67,10 @@ def battery():
         lambda: P.test_p12_dls_push_through_identity(1e-2),
         lambda: P.test_p13_lm_cost_monotone_and_rejects_keep_xi(0),
         lambda: P.test_p13_lm_clamps_to_limits(),
+        lambda: P.test_p15_schedule_pose_step_is_lm_without_smoothness(),
+        lambda: P.test_p15_schedule_valid_seed_takes_a_differencing_step(),
+        lambda: P.test_p15_schedule_latest_valid_meets_the_thresholds(),
+        lambda: P.test_p15_schedule_rejects_a_discontinuous_pose_valid_trajectory(),
     ]
 
 

@@ -479,3 +479,63 @@ def test_p14_batchopt_selects_least_mjac_candidates():
         assert np.all(r["path"] == 0)   # one candidate: the search keeps it
         ref = oracle.plan(rb, cand[k:k + 1], targets, 3)
         assert np.array_equal(r["xi"], ref["xi"])
+
+
+# ---- pose-first alternating schedule with the latest-valid store --------------
+
+def _sched_case(seed=1, T=30, sigma=0.02):
+    rb = synth.make_robot(seed)
+    prob = synth.make_problem(rb, seed=seed, T=T, K=1, sigma=sigma)
+    return rb, prob, oracle.fk(rb, prob.q_star)
+
+
+def test_p15_schedule_pose_step_is_lm_without_smoothness():
+    rb, prob, tg = _sched_case()
+    r = oracle.lm_schedule(rb, prob.cand[0], tg, 1)
+    ref = oracle.lm(rb, prob.cand[0], tg, 1, opts=dict(w_smooth=0.0))
+    assert r["pose_steps"] == 1 and r["diff_steps"] == 0 and r["first_valid"] == -1
+    assert np.array_equal(r["xi"], ref["xi"])
+
+
+def test_p15_schedule_valid_seed_takes_a_differencing_step():
+    rb, prob, tg = _sched_case()
+    xi0 = prob.q_star.copy()             # exact targets: pose error 0, smooth path
+    r = oracle.lm_schedule(rb, xi0, tg, 1)
+    ref = oracle.lm(rb, xi0, tg, 1, opts=dict(w_pose=0.0))
+    assert r["first_valid"] == 0 and r["diff_steps"] == 1 and r["pose_steps"] == 0
+    assert np.array_equal(r["xi"], ref["xi"])
+    assert np.array_equal(r["xi_valid"], np.clip(xi0, rb.q_lo, rb.q_hi))
+
+
+def test_p15_schedule_latest_valid_meets_the_thresholds():
+    rb, prob, tg = _sched_case(seed=2, T=40, sigma=0.03)
+    r = oracle.lm_schedule(rb, prob.cand[0], tg, 40)
+    assert r["rc"] == 0 and r["n_valid"] >= 1 and r["pose_steps"] + r["diff_steps"] == 40
+    xv = r["xi_valid"]
+    ep, er = oracle.pose_compare(rb, xv, targets=tg)
+    assert ep <= 1e-4 and er <= np.deg2rad(0.1)
+    steps = np.abs(np.diff(xv, axis=0))
+    assert steps.max() <= np.deg2rad(7.0)
+    assert r["valid_length"] == pytest.approx(steps.sum(), rel=1e-12)
+
+
+def test_p15_schedule_unreachable_targets_stay_invalid():
+    rb, prob, tg = _sched_case(seed=3, T=10)
+    far = tg.copy()
+    far[:, :3] += 10.0                   # 10 m away: beyond any 7-link reach here
+    r = oracle.lm_schedule(rb, prob.cand[0], far, 5)
+    assert r["n_valid"] == 0 and r["first_valid"] == -1 and r["xi_valid"] is None
+    assert r["pose_steps"] == 5
+
+
+def test_p15_schedule_rejects_a_discontinuous_pose_valid_trajectory():
+    rb, prob, tg = _sched_case(seed=4, T=20)
+    q = prob.q_star.copy()
+    q[10:, 0] += np.deg2rad(10.0)        # a 10 degree step of joint 1 between waypoints 9 and 10
+    q = np.clip(q, rb.q_lo, rb.q_hi)
+    tgj = oracle.fk(rb, q)
+    r = oracle.lm_schedule(rb, q, tgj, 1)
+    # the seed reaches its targets exactly (a differencing step follows) but
+    # is not valid: one joint changes by more than 7 degrees
+    assert r["diff_steps"] == 1 and r["pose_steps"] == 0
+    assert r["first_valid"] == -1 and r["n_valid"] == 0
