@@ -60,8 +60,10 @@ typedef enum cpf_status {
 } cpf_status;
 
 /* Arithmetic of FK, Jacobians and residuals.  The linear solve is FP64 in
- * both: CPF_MIXED computes kinematics in FP32 and refines the FP64 solve;
- * CPF_F64 computes everything in FP64. */
+ * both: CPF_MIXED computes kinematics (FK, Jacobian, residuals, the cost's
+ * pose terms) in FP32 and refines the FP64 solve, with the Gram J^T J, the
+ * cross-waypoint sums and the validity checks in FP64; CPF_FP64 computes
+ * everything in FP64.  (CPF_F32 / CPF_F64 select cpf_fk_batch's precision.) */
 enum { CPF_F32 = 0, CPF_F64 = 1 };
 enum { CPF_MIXED = 0, CPF_FP64 = 1 };
 
@@ -96,12 +98,23 @@ typedef struct cpf_problem {
  *     (Sec. III-B)
  *   iters: LM iterations run by cpf_submit / cpf_plan_solve
  *   prec: CPF_MIXED or CPF_FP64
- *   refine_steps 1: FP64 iterative-refinement steps after each solve */
+ *   refine_steps 1: FP64 iterative-refinement steps after each solve
+ *   schedule 0: 1 runs the alternating objective with anytime validity
+ *     (Sec. III-C): before every iteration, and once after the last one of a
+ *     call, the trajectory is checked in FP64 against the validity thresholds
+ *     valid_pos_m 1e-4 (m), valid_rot_rad 0.1 deg and valid_step_rad 7 deg
+ *     (largest joint change between consecutive waypoints; Sec. II); one that
+ *     passes is kept as the latest valid trajectory.  A trajectory within the
+ *     pose thresholds then takes an LM step on the differencing term alone
+ *     (weight w_smooth), any other a step on the pose term alone (weight
+ *     w_pose); each objective keeps its own damping. */
 typedef struct cpf_opts {
     double w_pose, w_smooth;
     double lambda0, lambda_min, lambda_max;
     double limit_margin, limit_penalty;
     int32_t iters, prec, refine_steps;
+    int32_t schedule;
+    double valid_pos_m, valid_rot_rad, valid_step_rad;
 } cpf_opts;
 
 typedef struct cpf_lm_report {
@@ -114,6 +127,15 @@ typedef struct cpf_lm_report {
     double max_pos_err_m;    /* max_t |p(q_t) - p*_t| (FP64 FK) */
     double max_rot_err_rad;  /* max_t angle(R(q_t) R*_t^T) (FP64 FK) */
     double mjac;             /* max joint change along the result */
+    /* schedule mode only (zero / -1 otherwise): */
+    int32_t n_valid;         /* validity checks passed */
+    int32_t first_valid;     /* iteration before which the first check passed
+                                (iters_done: after the last), -1 if none */
+    int32_t pose_steps;      /* steps taken on the pose objective */
+    int32_t diff_steps;      /* steps taken on the differencing objective */
+    double valid_length;     /* sum over steps and joints of |change| along the
+                                latest valid trajectory */
+    double lambda_diff;      /* damping of the differencing objective */
 } cpf_lm_report;
 
 typedef struct cpf_result {
@@ -124,6 +146,9 @@ typedef struct cpf_result {
     double search_mjac;      /* mjac of the searched seed */
     int32_t status;          /* per-request cpf_status */
     int64_t t_submit_ns, t_admit_ns, t_search_done_ns, t_done_ns; /* steady clock */
+    double *xi_valid;        /* [T][dof] caller buffer, or NULL: schedule mode's
+                                latest valid trajectory, written when
+                                report.n_valid > 0 (left untouched otherwise) */
 } cpf_result;
 
 void cpf_opts_default(cpf_opts *o);
@@ -171,6 +196,12 @@ cpf_status cpf_dp_search(cpf_plan *plan, int32_t *path_out, double *best_out,
  * search seed the first time; resumable).  xi_out [T][dof] or NULL.
  * Sec. III-C.  Synchronous. */
 cpf_status cpf_lm_refine(cpf_plan *plan, int32_t iters, double *xi_out, cpf_lm_report *rep);
+
+/* Latest valid trajectory of a plan refined with opts.schedule = 1 (the
+ * anytime result of Sec. III-C's alternating objective), written to xi_out
+ * [T][dof] (caller-owned, not NULL).  CPF_E_STATE if the plan does not use
+ * the schedule or no check has passed yet.  Synchronous. */
+cpf_status cpf_lm_latest_valid(cpf_plan *plan, double *xi_out);
 
 /* Search + opts->iters LM iterations for nplans independent problems in one
  * launch of each kernel (one workgroup per plan).  results[i].xi / .path may

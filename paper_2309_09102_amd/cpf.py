@@ -52,21 +52,25 @@ class cpf_opts(C.Structure):
     _fields_ = [("w_pose", C.c_double), ("w_smooth", C.c_double), ("lambda0", C.c_double),
                 ("lambda_min", C.c_double), ("lambda_max", C.c_double),
                 ("limit_margin", C.c_double), ("limit_penalty", C.c_double),
-                ("iters", C.c_int32), ("prec", C.c_int32), ("refine_steps", C.c_int32)]
+                ("iters", C.c_int32), ("prec", C.c_int32), ("refine_steps", C.c_int32),
+                ("schedule", C.c_int32), ("valid_pos_m", C.c_double),
+                ("valid_rot_rad", C.c_double), ("valid_step_rad", C.c_double)]
 
 
 class cpf_lm_report(C.Structure):
     _fields_ = [("cost0", C.c_double), ("cost", C.c_double), ("lambda_", C.c_double),
                 ("grad_inf", C.c_double), ("n_accepted", C.c_int32), ("iters_done", C.c_int32),
                 ("max_pos_err_m", C.c_double), ("max_rot_err_rad", C.c_double),
-                ("mjac", C.c_double)]
+                ("mjac", C.c_double), ("n_valid", C.c_int32), ("first_valid", C.c_int32),
+                ("pose_steps", C.c_int32), ("diff_steps", C.c_int32),
+                ("valid_length", C.c_double), ("lambda_diff", C.c_double)]
 
 
 class cpf_result(C.Structure):
     _fields_ = [("xi", _dp), ("path", _ip), ("report", cpf_lm_report),
                 ("search_best", C.c_double), ("search_mjac", C.c_double),
                 ("status", C.c_int32), ("t_submit_ns", C.c_int64), ("t_admit_ns", C.c_int64),
-                ("t_search_done_ns", C.c_int64), ("t_done_ns", C.c_int64)]
+                ("t_search_done_ns", C.c_int64), ("t_done_ns", C.c_int64), ("xi_valid", _dp)]
 
 
 _vp = C.c_void_p
@@ -82,6 +86,7 @@ _lib.cpf_plan_free.argtypes = [_vp]
 _lib.cpf_fk_batch.argtypes = [_vp, C.POINTER(cpf_robot), C.c_int64, C.c_int32, _vp, _vp, _vp, _vp]
 _lib.cpf_dp_search.argtypes = [_vp, _ip, _dp, _dp]
 _lib.cpf_lm_refine.argtypes = [_vp, C.c_int32, _dp, C.POINTER(cpf_lm_report)]
+_lib.cpf_lm_latest_valid.argtypes = [_vp, _dp]
 _lib.cpf_solve_batch.argtypes = [_vp, C.c_int32, C.POINTER(cpf_robot), C.POINTER(cpf_problem),
                                  C.POINTER(cpf_opts), C.POINTER(cpf_result)]
 _lib.cpf_batchopt.argtypes = [_vp, C.POINTER(cpf_robot), C.POINTER(cpf_problem), C.POINTER(cpf_opts),
@@ -94,13 +99,15 @@ _lib.cpf_ctx_profile.argtypes = [_vp, C.c_int32]
 _lib.cpf_ctx_kernel_stats.argtypes = [_vp, C.c_char_p, C.POINTER(C.c_double),
                                       C.POINTER(C.c_int64)]
 for _f in ("cpf_ctx_create", "cpf_plan_init", "cpf_fk_batch", "cpf_dp_search", "cpf_lm_refine",
+           "cpf_lm_latest_valid",
            "cpf_solve_batch", "cpf_batchopt", "cpf_submit", "cpf_poll", "cpf_ctx_profile",
            "cpf_ctx_kernel_stats", "cpf_ctx_config"):
     getattr(_lib, _f).restype = C.c_int
 
 EXPORTS = ("cpf_opts_default", "cpf_last_error", "cpf_ctx_create", "cpf_ctx_destroy",
            "cpf_ctx_bytes_in_use", "cpf_plan_init", "cpf_plan_free", "cpf_fk_batch",
-           "cpf_dp_search", "cpf_lm_refine", "cpf_solve_batch", "cpf_batchopt", "cpf_submit",
+           "cpf_dp_search", "cpf_lm_refine", "cpf_lm_latest_valid", "cpf_solve_batch",
+           "cpf_batchopt", "cpf_submit",
            "cpf_poll", "cpf_ctx_profile", "cpf_ctx_kernel_stats", "cpf_ctx_config")
 
 
@@ -164,7 +171,9 @@ def make_opts(**kw) -> cpf_opts:
 def _report(r: cpf_lm_report) -> dict:
     return dict(cost0=r.cost0, cost=r.cost, lam=r.lambda_, grad_inf=r.grad_inf,
                 n_accepted=r.n_accepted, iters_done=r.iters_done,
-                max_pos_err_m=r.max_pos_err_m, max_rot_err_rad=r.max_rot_err_rad, mjac=r.mjac)
+                max_pos_err_m=r.max_pos_err_m, max_rot_err_rad=r.max_rot_err_rad, mjac=r.mjac,
+                n_valid=r.n_valid, first_valid=r.first_valid, pose_steps=r.pose_steps,
+                diff_steps=r.diff_steps, valid_length=r.valid_length, lam_diff=r.lambda_diff)
 
 
 # ---- functions with the C ABI's names ---------------------------------------
@@ -237,6 +246,14 @@ def lm_refine(plan, iters: int, T: int, want_xi: bool = True):
     return xi, _report(rep)
 
 
+def lm_latest_valid(plan, T: int):
+    """Latest valid trajectory [T][7] of a plan refined under the schedule
+    (raises CpfError E_STATE when there is none yet or no schedule)."""
+    xi = np.empty((T, 7))
+    _check(_lib.cpf_lm_latest_valid(plan, _ptr(xi)))
+    return xi
+
+
 def solve_batch(ctx, problems, opts=None):
     """problems: list of (robot, targets, cand[, node_pen]).  Returns list of dicts."""
     n = len(problems)
@@ -252,9 +269,11 @@ def solve_batch(ctx, problems, opts=None):
         T = pb.struct.T
         xi = np.empty((T, 7))
         path = np.empty(T, dtype=np.int32)
-        outs.append((xi, path))
+        xv = np.empty((T, 7))
+        outs.append((xi, path, xv))
         results[i].xi = _ptr(xi)
         results[i].path = path.ctypes.data_as(_ip)
+        results[i].xi_valid = _ptr(xv)
     o = opts if opts is not None else opts_default()
     _check(_lib.cpf_solve_batch(ctx, n, robots, probs, C.byref(o), results))
     return [_result(results[i], *outs[i]) for i in range(n)]
@@ -272,17 +291,21 @@ def batchopt(ctx, robot, targets, cand, M: int, opts=None, node_pen=None):
     for i in range(M):
         xi = np.empty((T, 7))
         path = np.empty(T, dtype=np.int32)
-        outs.append((xi, path))
+        xv = np.empty((T, 7))
+        outs.append((xi, path, xv))
         results[i].xi = _ptr(xi)
         results[i].path = path.ctypes.data_as(_ip)
+        results[i].xi_valid = _ptr(xv)
     o = opts if opts is not None else opts_default()
     _check(_lib.cpf_batchopt(ctx, C.byref(rb.struct), C.byref(pb.struct), C.byref(o), M,
                              idx.ctypes.data_as(_ip), results))
     return [int(k) for k in idx], [_result(results[i], *outs[i]) for i in range(M)]
 
 
-def _result(r: cpf_result, xi, path) -> dict:
-    return dict(xi=xi, path=path, report=_report(r.report), search_best=r.search_best,
+def _result(r: cpf_result, xi, path, xv=None) -> dict:
+    rep = _report(r.report)
+    return dict(xi=xi, path=path, report=rep, xi_valid=xv if rep["n_valid"] > 0 else None,
+                search_best=r.search_best,
                 search_mjac=r.search_mjac, status=r.status,
                 t_submit_ns=r.t_submit_ns, t_admit_ns=r.t_admit_ns,
                 t_search_done_ns=r.t_search_done_ns, t_done_ns=r.t_done_ns)
@@ -301,13 +324,15 @@ def poll(ctx, ticket: int, T: int, timeout_ms: int = -1):
     """Result dict, or None while the request is pending."""
     xi = np.empty((T, 7))
     path = np.empty(T, dtype=np.int32)
+    xv = np.empty((T, 7))
     r = cpf_result()
     r.xi = _ptr(xi)
     r.path = path.ctypes.data_as(_ip)
+    r.xi_valid = _ptr(xv)
     st = _check(_lib.cpf_poll(ctx, int(ticket), int(timeout_ms), C.byref(r)))
     if st == PENDING:
         return None
-    return _result(r, xi, path)
+    return _result(r, xi, path, xv)
 
 
 # ---- small object layer -------------------------------------------------------
@@ -377,6 +402,9 @@ class Plan:
 
     def lm_refine(self, iters: int, want_xi: bool = True):
         return lm_refine(self.h, iters, self.T, want_xi)
+
+    def latest_valid(self):
+        return lm_latest_valid(self.h, self.T)
 
     def free(self):
         if self.h:

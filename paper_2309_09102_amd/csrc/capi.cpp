@@ -67,6 +67,7 @@ Layout make_layout(int T, int K, bool extra) {
     L.rb = take(NJ * t * sizeof(double));
     L.st = take(sizeof(LMState));
     L.report = take(8 * sizeof(double));
+    L.xv = take(NJ * t * sizeof(double));
     L.total = off;
     return L;
 }
@@ -239,6 +240,10 @@ cpf_status check_opts(const cpf_opts *o) {
     if (o->prec != CPF_MIXED && o->prec != CPF_FP64) return fail(CPF_E_ARG, "prec %d", o->prec);
     if (o->iters < 0 || o->refine_steps < 0 || o->refine_steps > 8)
         return fail(CPF_E_ARG, "iters / refine_steps out of range");
+    if (o->schedule != 0 && o->schedule != 1) return fail(CPF_E_ARG, "schedule %d", o->schedule);
+    const double tv[3] = {o->valid_pos_m, o->valid_rot_rad, o->valid_step_rad};
+    if (!all_finite(tv, 3) || tv[0] < 0 || tv[1] < 0 || tv[2] < 0)
+        return fail(CPF_E_ARG, "validity thresholds must be finite and >= 0");
     return CPF_OK;
 }
 
@@ -258,6 +263,10 @@ static void fill_desc(cpf_plan *p, bool has_extra) {
     D.lam_max = p->opts.lambda_max;
     D.margin = p->opts.limit_margin;
     D.penalty = p->opts.limit_penalty;
+    D.schedule = p->opts.schedule;
+    D.vtol[0] = p->opts.valid_pos_m;
+    D.vtol[1] = p->opts.valid_rot_rad;
+    D.vtol[2] = p->opts.valid_step_rad;
     const HostRobot &r = p->robot;
     for (int i = 0; i < NJ; ++i) {
         D.a[i] = r.a[i]; D.d[i] = r.d[i]; D.ca[i] = r.ca[i]; D.sa[i] = r.sa[i]; D.off[i] = r.off[i];
@@ -285,6 +294,7 @@ static void fill_desc(cpf_plan *p, bool has_extra) {
     set_dev_ptr(D.rb, b + L.rb);
     set_dev_ptr(D.st, b + L.st);
     set_dev_ptr(D.report, b + L.report);
+    set_dev_ptr(D.xv, b + L.xv);
 }
 
 cpf_status plan_create(cpf_ctx *ctx, const HostRobot &hr, const cpf_problem *prob,
@@ -343,8 +353,8 @@ void plan_destroy(cpf_plan *p) {
 }
 
 cpf_status read_plan(cpf_plan *p, hipStream_t s, const LMState *state_dev, PlanReadback *rb,
-                     double *xi_out, int32_t *path_out) {
-    std::vector<double> xs;
+                     double *xi_out, int32_t *path_out, double *xv_out) {
+    std::vector<double> xs, vs;
     const void *st_src = state_dev ? (const void *)state_dev : (const void *)(p->arena + p->L.st);
     HIP_TRY(hipMemcpyAsync(&rb->st, st_src, sizeof(LMState), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(rb->report, p->arena + p->L.report, 8 * sizeof(double),
@@ -359,24 +369,41 @@ cpf_status read_plan(cpf_plan *p, hipStream_t s, const LMState *state_dev, PlanR
     if (path_out)
         HIP_TRY(hipMemcpyAsync(path_out, p->arena + p->L.path, (size_t)p->T * sizeof(int32_t),
                                hipMemcpyDeviceToHost, s));
+    if (xv_out) {
+        vs.resize((size_t)NJ * p->T);
+        HIP_TRY(hipMemcpyAsync(vs.data(), p->arena + p->L.xv, vs.size() * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+    }
     HIP_TRY(hipStreamSynchronize(s));
-    if (xi_out)
-        for (int t = 0; t < p->T; ++t)
-            for (int j = 0; j < NJ; ++j) xi_out[(size_t)t * NJ + j] = xs[(size_t)j * p->T + t];
+    if (xi_out) soa_to_rows(xs.data(), p->T, xi_out);
+    if (xv_out && rb->st.n_valid > 0) soa_to_rows(vs.data(), p->T, xv_out);
     return CPF_OK;
 }
 
-void fill_report(const PlanReadback &rb, cpf_lm_report *rep) {
-    rep->cost0 = rb.st.cost0;
-    rep->cost = rb.st.cost;
-    rep->lambda = rb.st.lambda;
-    rep->grad_inf = rb.st.grad_inf;
-    rep->n_accepted = rb.st.n_acc;
-    rep->iters_done = rb.st.iters_done;
-    rep->max_pos_err_m = rb.report[0];
-    rep->max_rot_err_rad = rb.report[1];
-    rep->mjac = rb.report[2];
+void soa_to_rows(const double *soa, int T, double *rows) {
+    for (int t = 0; t < T; ++t)
+        for (int j = 0; j < NJ; ++j) rows[(size_t)t * NJ + j] = soa[(size_t)j * T + t];
 }
+
+void report_from(const LMState &ls, const double *report, cpf_lm_report *rep) {
+    rep->cost0 = ls.cost0;
+    rep->cost = ls.cost;
+    rep->lambda = ls.lambda;
+    rep->grad_inf = ls.grad_inf;
+    rep->n_accepted = ls.n_acc;
+    rep->iters_done = ls.iters_done;
+    rep->max_pos_err_m = report[0];
+    rep->max_rot_err_rad = report[1];
+    rep->mjac = report[2];
+    rep->n_valid = ls.n_valid;
+    rep->first_valid = ls.first_valid;
+    rep->pose_steps = ls.pose_steps;
+    rep->diff_steps = ls.diff_steps;
+    rep->valid_length = ls.valid_length;
+    rep->lambda_diff = ls.lambda_d;
+}
+
+void fill_report(const PlanReadback &rb, cpf_lm_report *rep) { report_from(rb.st, rb.report, rep); }
 
 }  // namespace cpf
 
@@ -400,6 +427,10 @@ void cpf_opts_default(cpf_opts *o) {
     o->iters = 50;
     o->prec = CPF_MIXED;
     o->refine_steps = 1;
+    o->schedule = 0;
+    o->valid_pos_m = 1e-4;
+    o->valid_rot_rad = 0.1 * 3.14159265358979323846 / 180.0;
+    o->valid_step_rad = 7.0 * 3.14159265358979323846 / 180.0;
 }
 
 const char *cpf_last_error(void) { return cpf::g_err.c_str(); }
@@ -485,7 +516,7 @@ cpf_status cpf_dp_search(cpf_plan *plan, int32_t *path_out, double *best_out, do
     HIP_TRY(timed(ctx, KIND_DP, ctx->stream,
                   [&] { return dp_launch(plan->d_desc, 1, plan->K, plan->T, ctx->stream); }));
     PlanReadback rb;
-    cpf_status st = read_plan(plan, ctx->stream, nullptr, &rb, nullptr, path_out);
+    cpf_status st = read_plan(plan, ctx->stream, nullptr, &rb, nullptr, path_out, nullptr);
     if (st != CPF_OK) return st;
     plan->searched = true;
     if (best_out) *best_out = rb.dp_out[0];
@@ -500,14 +531,27 @@ cpf_status cpf_lm_refine(cpf_plan *plan, int32_t iters, double *xi_out, cpf_lm_r
     cpf_ctx *ctx = plan->ctx;
     HIP_TRY(hipSetDevice(ctx->device));
     HIP_TRY(timed(ctx, KIND_LM, ctx->stream,
-                  [&] { return lm_launch(plan->d_desc, 1, plan->opts.prec, iters, ctx->stream); }));
+                  [&] { return lm_launch(plan->d_desc, 1, plan->opts.prec, plan->opts.schedule, iters, ctx->stream); }));
     HIP_TRY(timed(ctx, KIND_EVAL, ctx->stream,
                   [&] { return eval_launch(plan->d_desc, 1, 0, ctx->stream); }));
     PlanReadback rb;
-    cpf_status st = read_plan(plan, ctx->stream, nullptr, &rb, xi_out, nullptr);
+    cpf_status st = read_plan(plan, ctx->stream, nullptr, &rb, xi_out, nullptr, nullptr);
     if (st != CPF_OK) return st;
     if (rep) fill_report(rb, rep);
     if (rb.st.status != 0) return fail(CPF_E_NUMERIC, "non-positive pivot in the block solve");
+    return CPF_OK;
+}
+
+cpf_status cpf_lm_latest_valid(cpf_plan *plan, double *xi_out) {
+    if (!plan || !xi_out) return fail(CPF_E_ARG, "plan / xi_out is NULL");
+    if (!plan->opts.schedule) return fail(CPF_E_STATE, "plan was not created with opts.schedule = 1");
+    cpf_ctx *ctx = plan->ctx;
+    HIP_TRY(hipSetDevice(ctx->device));
+    PlanReadback rb;
+    cpf_status st = read_plan(plan, ctx->stream, nullptr, &rb, nullptr, nullptr, xi_out);
+    if (st != CPF_OK) return st;
+    if (!plan->searched || rb.st.seeded == 0 || rb.st.n_valid == 0)
+        return fail(CPF_E_STATE, "no valid trajectory yet");
     return CPF_OK;
 }
 
@@ -558,7 +602,7 @@ cpf_status cpf_solve_batch(cpf_ctx *ctx, int32_t nplans, const cpf_robot *robots
                   [&] { return dp_launch(d_descs, nplans, maxK, maxT, ctx->stream); });
     if (e == hipSuccess)
         e = timed(ctx, KIND_LM, ctx->stream,
-                  [&] { return lm_launch(d_descs, nplans, o.prec, o.iters, ctx->stream); });
+                  [&] { return lm_launch(d_descs, nplans, o.prec, o.schedule, o.iters, ctx->stream); });
     if (e == hipSuccess)
         e = timed(ctx, KIND_EVAL, ctx->stream,
                   [&] { return eval_launch(d_descs, nplans, 0, ctx->stream); });
@@ -570,7 +614,8 @@ cpf_status cpf_solve_batch(cpf_ctx *ctx, int32_t nplans, const cpf_robot *robots
     }
     for (int i = 0; i < nplans; ++i) {
         PlanReadback rb;
-        if ((st = read_plan(plans[i], ctx->stream, nullptr, &rb, results[i].xi, results[i].path)) !=
+        if ((st = read_plan(plans[i], ctx->stream, nullptr, &rb, results[i].xi, results[i].path,
+                            results[i].xi_valid)) !=
             CPF_OK) {
             cleanup();
             return st;

@@ -50,14 +50,23 @@ constexpr int TOPM = 16;      // nearest predecessors kept per search node
 
 struct LMState {
     double lambda, nu, cost, cost0, grad_inf;
-    double pad0, pad1, pad2;
+    // schedule mode: damping of the differencing objective (lambda, nu above
+    // belong to the pose objective) and the length of the latest valid
+    // trajectory
+    double lambda_d, nu_d, valid_length;
     int32_t n_acc, iters_done, status, need_lin;
-    int32_t iters_target, seeded, reported, pad4;
+    int32_t iters_target, seeded, reported, checked;
+    // schedule mode: objective of the next step (0 pose, 1 differencing) as
+    // the last validity check decided, objective of the previous step (-1:
+    // none), checks passed, iteration of the first pass (-1: none), steps
+    // taken on each objective
+    int32_t mode, last_mode, n_valid, first_valid;
+    int32_t pose_steps, diff_steps, pad0, pad1;
 };
 
 struct DevPlan {
     int32_t T, K, has_extra, prec;
-    int32_t refine_steps, pad0, pad1, pad2;
+    int32_t refine_steps, schedule, pad1, pad2;
     double w_p, w_s, lam0, lam_min, lam_max, margin, penalty;
     // robot in double and float (cos/sin of the twist precomputed on host)
     double a[8], d[8], ca[8], sa[8], off[8], lo[8], hi[8];
@@ -74,6 +83,10 @@ struct DevPlan {
     CPF_GLOBAL double *xi, *xt, *A, *g, *cr, *dx, *rb;
     CPF_GLOBAL LMState *st;
     CPF_GLOBAL double *report;    // [0] max pos err, [1] max rot err, [2] mjac
+    // schedule mode: validity thresholds (position m, rotation rad, joint
+    // step rad) and the latest valid trajectory [dof][T]
+    double vtol[3], pad3;
+    CPF_GLOBAL double *xv;
 };
 
 template <typename S>

@@ -29,7 +29,7 @@ hipError_t cand_mjac_launch(const float *cand, int T, int K, double *out, hipStr
 hipError_t dp_launch(const DevPlan *d_plans, int nplans, int maxK, int maxT, hipStream_t s);
 // Up to `iters` LM iterations for each plan of precision prec (0 = mixed,
 // 1 = FP64); empty slots (T = 0) and plans of the other precision are skipped.
-hipError_t lm_launch(const DevPlan *d_plans, int nplans, int prec, int iters, hipStream_t s);
+hipError_t lm_launch(const DevPlan *d_plans, int nplans, int prec, int sched, int iters, hipStream_t s);
 // Pose error vs targets and mjac of the current trajectory (FP64 FK).  With
 // only_finished, only plans that reached their iteration target (or failed)
 // and have not been reported yet.

@@ -11,8 +11,9 @@
 // the joint limits; lambda follows Nielsen's gain-ratio rule.
 //
 // One workgroup per plan runs all iterations without returning to the host.
-// Kinematics (FK, J, residuals, J^T J) run in S = float or double; the
-// assembly, the solve and every cross-waypoint sum are FP64.  The solve is
+// Kinematics (FK, J, residuals, and the cost's pose terms) run in S = float
+// or double; the Gram J^T J, the assembly, the solve and every
+// cross-waypoint sum are FP64.  The solve is
 // block cyclic reduction (a Cholesky factor per eliminated block, one lane
 // per 7x7 block, log2 T levels), then FP64 iterative refinement against the
 // same H reusing the stored factors.
@@ -80,7 +81,7 @@ __device__ __forceinline__ double pose_sq(const DevPlan &P, const RobotT<S> &rb,
 // Cost of trajectory X: pose part and smoothness part, block-reduced.
 template <typename S>
 __device__ __forceinline__ double plan_cost(const DevPlan &P, const RobotT<S> &rb, const CPF_GLOBAL double *X,
-                                            int T, double *red) {
+                                            int T, double *red, double wp, double ws) {
     double ps = 0.0, ss = 0.0;
     for (int t = threadIdx.x; t < T; t += LM_BS) {
         ps += pose_sq<S>(P, rb, X, T, t);
@@ -94,14 +95,13 @@ __device__ __forceinline__ double plan_cost(const DevPlan &P, const RobotT<S> &r
     }
     const double pose_sum = block_sum(ps, red);
     const double diff_sum = block_sum(ss, red);
-    return 0.5 * P.w_p * pose_sum + 0.5 * P.w_s * diff_sum;
+    return 0.5 * wp * pose_sum + 0.5 * ws * diff_sum;
 }
 
 // Linearise at xi: A_t = w_p J^T J (packed lower), g_t; returns max |g|.
 template <typename S>
-__device__ __forceinline__ double linearise(const DevPlan &P, const RobotT<S> &rb, int T) {
+__device__ __forceinline__ double linearise(const DevPlan &P, const RobotT<S> &rb, int T, double w_p, double w_s) {
     double gmax = 0.0;
-    const double w_p = P.w_p, w_s = P.w_s;
     for (int t = threadIdx.x; t < T; t += LM_BS) {
         double xq[NJ];
         S q[NJ];
@@ -126,14 +126,18 @@ __device__ __forceinline__ double linearise(const DevPlan &P, const RobotT<S> &r
             J[4][i] = Zs[i][1];
             J[5][i] = Zs[i][2];
         }
+        // The Gram matrix of the (FP32 or FP64) Jacobian is accumulated in
+        // FP64: then it is positive semi-definite to FP64 rounding, and the
+        // damped block stays positive definite for every lambda >= lambda_min
+        // also when no smoothness term is added (the schedule's pose step).
 #pragma unroll
         for (int i = 0; i < NJ; ++i) {
 #pragma unroll
             for (int j = 0; j <= i; ++j) {
-                S s = J[0][i] * J[0][j];
+                double s = (double)J[0][i] * (double)J[0][j];
 #pragma unroll
-                for (int k = 1; k < 6; ++k) s += J[k][i] * J[k][j];
-                const double v = w_p * (double)s;
+                for (int k = 1; k < 6; ++k) s += (double)J[k][i] * (double)J[k][j];
+                const double v = w_p * s;
                 P.A[(size_t)t * NBLK + i * NJ + j] = v;
                 if (i != j) P.A[(size_t)t * NBLK + j * NJ + i] = v;
             }
@@ -156,11 +160,11 @@ __device__ __forceinline__ double linearise(const DevPlan &P, const RobotT<S> &r
 }
 
 // Element (i, j) of D_t = A_t + (w_s c_t + lambda) I.
-__device__ __forceinline__ double d_elem(const DevPlan &P, int T, int t, int i, int j, double lam) {
+__device__ __forceinline__ double d_elem(const DevPlan &P, int T, int t, int i, int j, double lam, double ws) {
     double v = P.A[(size_t)t * NBLK + i * NJ + j];
     if (i == j) {
         const int ct = (t > 0) + (t + 1 < T);
-        v += P.w_s * ct + lam;
+        v += ws * ct + lam;
     }
     return v;
 }
@@ -320,9 +324,9 @@ __device__ __forceinline__ void st_full(CPF_GLOBAL double *b, const double m[NTR
 }
 
 // Level-0 diagonal block t (lower triangle): w_p J^T J + (w_s c_t + lambda) I.
-__device__ __forceinline__ void level0_D(const DevPlan &P, int T, double lam, int t, double D[NTRI]) {
+__device__ __forceinline__ void level0_D(const DevPlan &P, int T, double lam, double ws, int t, double D[NTRI]) {
     ld_lower(blk(P.A, t, NBLK), D);
-    const double dg = P.w_s * ((t > 0) + (t + 1 < T)) + lam;
+    const double dg = ws * ((t > 0) + (t + 1 < T)) + lam;
 #pragma unroll
     for (int a = 0; a < NJ; ++a) D[tri_index(a, a)] += dg;
 }
@@ -345,14 +349,14 @@ __device__ __forceinline__ CRNbr cr_nbr(const CRLevel &Lp, int j) {
 
 // Block j of level lev >= 1 (one lane): lower triangle of its diagonal
 // block and its right-hand side, formed from level lev-1.
-__device__ __forceinline__ void cr_form_lane(const DevPlan &P, int T, double lam, const CRLevel &Lp, int lev, int j,
+__device__ __forceinline__ void cr_form_lane(const DevPlan &P, int T, double lam, double ws, const CRLevel &Lp, int lev, int j,
                                              bool factor, const CPF_GLOBAL double *rhs, double sgn, double D[NTRI],
                                              double r[NJ]) {
     const CRNbr q = cr_nbr(Lp, j);
     const CPF_GLOBAL double *Z2 = lev == 1 ? Lp.Z1() : Lp.Z2();   // level 0: Z1 = Z2
     const CPF_GLOBAL double *c2 = lev == 1 ? Lp.c1() : Lp.c2();
     if (factor) {
-        if (lev == 1) level0_D(P, T, lam, 2 * j, D);
+        if (lev == 1) level0_D(P, T, lam, ws, 2 * j, D);
         else ld_lower(blk(Lp.DE(), j, NBLK), D);
         const CPF_GLOBAL double *zr = blk(Lp.Z1(), q.jr, NBLK), *zl = blk(Z2, q.jl, NBLK);
 #pragma unroll
@@ -375,7 +379,7 @@ __device__ __forceinline__ void cr_form_lane(const DevPlan &P, int T, double lam
 
 // Column c of the diagonal block j of level lev >= 1 and entry c of its
 // right-hand side (the share of lane c of a group).
-__device__ __forceinline__ void cr_form_col(const DevPlan &P, int T, double lam, const CRLevel &Lp, int lev, int j,
+__device__ __forceinline__ void cr_form_col(const DevPlan &P, int T, double lam, double ws, const CRLevel &Lp, int lev, int j,
                                             int c, bool factor, const CPF_GLOBAL double *rhs, double sgn,
                                             double d[NJ], double &rc) {
     const CRNbr q = cr_nbr(Lp, j);
@@ -384,7 +388,7 @@ __device__ __forceinline__ void cr_form_col(const DevPlan &P, int T, double lam,
     if (factor) {
         const int t = 2 * j;
         const CPF_GLOBAL double *b0 = lev == 1 ? blk(P.A, t, NBLK) : blk(Lp.DE(), j, NBLK);
-        const double dg = lev == 1 ? P.w_s * ((t > 0) + (t + 1 < T)) + lam : 0.0;
+        const double dg = lev == 1 ? ws * ((t > 0) + (t + 1 < T)) + lam : 0.0;
         const CPF_GLOBAL double *zr = blk(Lp.Z1(), q.jr, NBLK) + c, *zl = blk(Z2, q.jl, NBLK) + c;
         b0 += c;
 #pragma unroll
@@ -401,14 +405,14 @@ __device__ __forceinline__ void cr_form_col(const DevPlan &P, int T, double lam,
 
 // Odd block i = 2h+1 of level 0 (one lane): factor, Schur contribution and
 // coupling of level 1 (factor only), s and its contribution.
-__device__ __forceinline__ void cr_odd_level0(const DevPlan &P, int T, double lam, const CRLevel &L0,
+__device__ __forceinline__ void cr_odd_level0(const DevPlan &P, int T, double lam, double ws, const CRLevel &L0,
                                               const CRLevel &L1, int h, bool factor, const CPF_GLOBAL double *rhs,
                                               double sgn, bool &ok) {
     const int i = 2 * h + 1;
-    const double w = P.w_s;
+    const double w = ws;
     double Li[NTRI];
     if (factor) {
-        level0_D(P, T, lam, i, Li);
+        level0_D(P, T, lam, ws, i, Li);
         chol_inverse(Li, ok);
         st_full(blk(L0.Li(), h, NBLK), Li, false, 1.0);
         double Pm[NTRI];   // Li^T Li
@@ -442,10 +446,10 @@ __device__ __forceinline__ void cr_odd_level0(const DevPlan &P, int T, double la
 
 // Even block j = 2 jj of level lev >= 1 (one lane): its diagonal block and
 // right-hand side, kept for level lev+1 (as block jj).
-__device__ __forceinline__ void cr_even(const DevPlan &P, int T, double lam, const CRLevel &Lp, const CRLevel &L,
+__device__ __forceinline__ void cr_even(const DevPlan &P, int T, double lam, double ws, const CRLevel &Lp, const CRLevel &L,
                                         int lev, int jj, bool factor, const CPF_GLOBAL double *rhs, double sgn) {
     double D[NTRI], r[NJ];
-    cr_form_lane(P, T, lam, Lp, lev, 2 * jj, factor, rhs, sgn, D, r);
+    cr_form_lane(P, T, lam, ws, Lp, lev, 2 * jj, factor, rhs, sgn, D, r);
     if (factor) st_full(blk(L.DE(), jj, NBLK), D, true, 1.0);
     CPF_GLOBAL double *ro = blk(L.rE(), jj, NJ);
 #pragma unroll
@@ -453,16 +457,16 @@ __device__ __forceinline__ void cr_even(const DevPlan &P, int T, double lam, con
 }
 
 // Last level (one block, one lane): factor (or reuse) and x = Li^T Li r.
-__device__ __forceinline__ void cr_top_solve(const DevPlan &P, int T, double lam, const CRLevel &Lp,
+__device__ __forceinline__ void cr_top_solve(const DevPlan &P, int T, double lam, double ws, const CRLevel &Lp,
                                              const CRLevel &L, int lev, bool factor, const CPF_GLOBAL double *rhs,
                                              double sgn, CPF_GLOBAL double *out, bool &ok) {
     double Li[NTRI], r[NJ], s[NJ], x[NJ];
     if (lev == 0) {   // a single waypoint
-        if (factor) level0_D(P, T, lam, 0, Li);
+        if (factor) level0_D(P, T, lam, ws, 0, Li);
 #pragma unroll
         for (int e = 0; e < NJ; ++e) r[e] = sgn * rhs[(size_t)e * T];
     } else {
-        cr_form_lane(P, T, lam, Lp, lev, 0, factor, rhs, sgn, Li, r);
+        cr_form_lane(P, T, lam, ws, Lp, lev, 0, factor, rhs, sgn, Li, r);
     }
     if (factor) {
         chol_inverse(Li, ok);
@@ -482,7 +486,7 @@ __device__ __forceinline__ void cr_top_solve(const DevPlan &P, int T, double lam
 __device__ __forceinline__ void group_sync() { __builtin_amdgcn_wave_barrier(); }
 
 // Odd block i = 2h+1 of level lev >= 1, factor round (group, lane c).
-__device__ __forceinline__ void cr_odd_factor(const DevPlan &P, int T, double lam, const CRLevel &Lp,
+__device__ __forceinline__ void cr_odd_factor(const DevPlan &P, int T, double lam, double ws, const CRLevel &Lp,
                                               const CRLevel &L, const CRLevel &Ln, int lev, int h, int c,
                                               const CPF_GLOBAL double *rhs, double sgn, double *ex, bool &ok) {
     const int i = 2 * h + 1;
@@ -500,7 +504,7 @@ __device__ __forceinline__ void cr_odd_factor(const DevPlan &P, int T, double la
     // the group forms D_i and r_i column by column and shares them
     {
         double d[NJ], rc;
-        cr_form_col(P, T, lam, Lp, lev, i, c, true, rhs, sgn, d, rc);
+        cr_form_col(P, T, lam, ws, Lp, lev, i, c, true, rhs, sgn, d, rc);
 #pragma unroll
         for (int a = 0; a < NJ; ++a) ex[a * NJ + c] = d[a];
         ex[NBLK + c] = rc;
@@ -580,7 +584,7 @@ __device__ __forceinline__ void cr_odd_rhs(const DevPlan &P, int T, const CRLeve
         vc[k] = Vc[k * NJ];
     }
     double d[NJ], rc;
-    cr_form_col(P, T, 0.0, Lp, lev, i, c, false, rhs, sgn, d, rc);
+    cr_form_col(P, T, 0.0, 0.0, Lp, lev, i, c, false, rhs, sgn, d, rc);
     ex[c] = rc;
     group_sync();
     double sc = 0.0;
@@ -632,7 +636,7 @@ __device__ __forceinline__ void cr_back_group(const CRLevel &L, const CRLevel &L
 // Back-substitution, one lane per block: odd blocks of level 0,
 // x_i = Li^T (s_i + w Li (x_{i-1} + x_{i+1})), and the even blocks of any
 // level (copied from the level above).
-__device__ __forceinline__ void cr_back_lane(const DevPlan &P, int T, const CRLevel &L, const CRLevel &Ln, int lev,
+__device__ __forceinline__ void cr_back_lane(const DevPlan &P, int T, double ws, const CRLevel &L, const CRLevel &Ln, int lev,
                                              int x, CPF_GLOBAL double *out) {
     double xv[NJ];
     if (lev == 0 && (x & 1)) {
@@ -649,7 +653,7 @@ __device__ __forceinline__ void cr_back_lane(const DevPlan &P, int T, const CRLe
         ld_lower(blk(L.Li(), h, NBLK), Li);
         tri_mv(Li, u, v);
 #pragma unroll
-        for (int e = 0; e < NJ; ++e) y[e] = fma(P.w_s, v[e], so[e]);
+        for (int e = 0; e < NJ; ++e) y[e] = fma(ws, v[e], so[e]);
         tri_tmv(Li, y, xv);
     } else {
         const CPF_GLOBAL double *xs = blk(Ln.X(), x / 2, NJ);
@@ -685,7 +689,7 @@ __device__ unsigned long long cr_round_cycles[2][64];
 // right-hand side is read only in the first two forward rounds).  Returns
 // false on a pivot that is not positive.  All threads of the workgroup;
 // exch: CR_GROUPS x CR_EX doubles of LDS.
-__device__ __forceinline__ bool cr_solve(const DevPlan &P, int T, double lam, bool factor,
+__device__ __forceinline__ bool cr_solve(const DevPlan &P, int T, double lam, double ws, bool factor,
                                          const CPF_GLOBAL double *rhs, double sgn, CPF_GLOBAL double *out,
                                          int *bad, double *exch) {
     const int tid = threadIdx.x;
@@ -705,21 +709,21 @@ __device__ __forceinline__ bool cr_solve(const DevPlan &P, int T, double lam, bo
         const CRLevel L = cr_level(base, T, lev);
         const CRLevel Lp = cr_level(base, T, lev > 0 ? lev - 1 : 0);
         if (lev == top) {
-            if (tid == 0) cr_top_solve(P, T, lam, Lp, L, lev, factor, rhs, sgn, out, ok);
+            if (tid == 0) cr_top_solve(P, T, lam, ws, Lp, L, lev, factor, rhs, sgn, out, ok);
         } else if (lev == 0) {
             const CRLevel L1 = cr_level(base, T, 1);
-            for (int h = tid; h < L.no; h += LM_BS) cr_odd_level0(P, T, lam, L, L1, h, factor, rhs, sgn, ok);
+            for (int h = tid; h < L.no; h += LM_BS) cr_odd_level0(P, T, lam, ws, L, L1, h, factor, rhs, sgn, ok);
         } else {
             const CRLevel Ln = cr_level(base, T, lev + 1);
             if (gid >= 0) {
                 for (int h = gid; h < L.no; h += CR_GROUPS) {
-                    if (factor) cr_odd_factor(P, T, lam, Lp, L, Ln, lev, h, gc, rhs, sgn, ex, ok);
+                    if (factor) cr_odd_factor(P, T, lam, ws, Lp, L, Ln, lev, h, gc, rhs, sgn, ex, ok);
                     else cr_odd_rhs(P, T, Lp, L, lev, h, gc, rhs, sgn, ex);
                 }
             }
             // even blocks from the last wavefronts down, so that on small levels
             // they run beside the groups (which start at the first wavefront)
-            for (int x = LM_BS - 1 - tid; x < L.ne; x += LM_BS) cr_even(P, T, lam, Lp, L, lev, x, factor, rhs, sgn);
+            for (int x = LM_BS - 1 - tid; x < L.ne; x += LM_BS) cr_even(P, T, lam, ws, Lp, L, lev, x, factor, rhs, sgn);
         }
         __syncthreads();
         CR_ROUND_MARK(factor ? 0 : 1, lev);
@@ -730,11 +734,11 @@ __device__ __forceinline__ bool cr_solve(const DevPlan &P, int T, double lam, bo
         const CRLevel L = cr_level(base, T, lev);
         const CRLevel Ln = cr_level(base, T, lev + 1);
         if (lev == 0) {
-            for (int x = tid; x < L.n; x += LM_BS) cr_back_lane(P, T, L, Ln, 0, x, out);
+            for (int x = tid; x < L.n; x += LM_BS) cr_back_lane(P, T, ws, L, Ln, 0, x, out);
         } else {
             if (gid >= 0)
                 for (int h = gid; h < L.no; h += CR_GROUPS) cr_back_group(L, Ln, h, gc, ex);
-            for (int x = 2 * (LM_BS - 1 - tid); x < L.n; x += 2 * LM_BS) cr_back_lane(P, T, L, Ln, lev, x, out);
+            for (int x = 2 * (LM_BS - 1 - tid); x < L.n; x += 2 * LM_BS) cr_back_lane(P, T, ws, L, Ln, lev, x, out);
         }
         __syncthreads();
         CR_ROUND_MARK(factor ? 0 : 1, 32 + lev);
@@ -744,8 +748,8 @@ __device__ __forceinline__ bool cr_solve(const DevPlan &P, int T, double lam, bo
 }
 
 // rb_t = -g_t - (H dx)_t  for every waypoint (all lanes).
-__device__ __forceinline__ void refine_residual(const DevPlan &P, int T, double lam) {
-    const double w = P.w_s;
+__device__ __forceinline__ void refine_residual(const DevPlan &P, int T, double lam, double ws) {
+    const double w = ws;
     for (int t = threadIdx.x; t < T; t += LM_BS) {
         double d[NJ];
 #pragma unroll
@@ -754,7 +758,7 @@ __device__ __forceinline__ void refine_residual(const DevPlan &P, int T, double 
         for (int r = 0; r < NJ; ++r) {
             double h = 0.0;
 #pragma unroll
-            for (int c = 0; c < NJ; ++c) h += d_elem(P, T, t, r, c, lam) * d[c];
+            for (int c = 0; c < NJ; ++c) h += d_elem(P, T, t, r, c, lam, ws) * d[c];
             if (t > 0) h -= w * P.dx[(size_t)r * T + t - 1];
             if (t + 1 < T) h -= w * P.dx[(size_t)r * T + t + 1];
             P.rb[(size_t)r * T + t] = -P.g[(size_t)r * T + t] - h;
@@ -762,20 +766,91 @@ __device__ __forceinline__ void refine_residual(const DevPlan &P, int T, double 
     }
 }
 
-template <typename S>
+// FP64 pose errors of waypoint t of X against its target (the Sec. II
+// metrics): position distance and geodesic rotation angle.
+__device__ __forceinline__ void pose_err_fp64(const DevPlan &P, const RobotT<double> &rb,
+                                              const CPF_GLOBAL double *X, int T, int t, double *ep,
+                                              double *er) {
+    double q[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) q[j] = X[(size_t)j * T + t];
+    double Xc[3], Yc[3], Zc[3], p[3], Zs[NJ][3], Os[NJ][3];
+    chain<double, false>(rb, q, Xc, Yc, Zc, p, Zs, Os);
+    double tg[12];
+    load_target<double>(P, T, t, tg);
+    const double dx = p[0] - tg[0], dy = p[1] - tg[1], dz = p[2] - tg[2];
+    *ep = sqrt(dx * dx + dy * dy + dz * dz);
+    // E = R R*^T; angle from its skew part and trace
+    double E[9];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            E[a * 3 + b] = Xc[a] * tg[3 + b * 3 + 0] + Yc[a] * tg[3 + b * 3 + 1] + Zc[a] * tg[3 + b * 3 + 2];
+    const double v0 = 0.5 * (E[7] - E[5]), v1 = 0.5 * (E[2] - E[6]), v2 = 0.5 * (E[3] - E[1]);
+    *er = atan2(sqrt(v0 * v0 + v1 * v1 + v2 * v2), 0.5 * (E[0] + E[4] + E[8] - 1.0));
+}
+
+// Validity check of the alternating schedule (Sec. III-C's anytime result
+// under the Sec. II thresholds), FP64 kinematics: every waypoint within the
+// position and rotation thresholds and no joint step above the step
+// threshold.  A trajectory that passes is copied to xv and counted.  Returns
+// the next step's objective to all lanes: 1 (differencing) when the pose
+// thresholds hold, else 0 (pose).
+__device__ int schedule_check(const DevPlan &P, LMState *st, int T, double *red) {
+    const RobotT<double> rb = load_robot<double>(P);
+    double ep = 0.0, er = 0.0, mj = 0.0, len = 0.0;
+    for (int t = threadIdx.x; t < T; t += LM_BS) {
+        double a, b;
+        pose_err_fp64(P, rb, P.xi, T, t, &a, &b);
+        ep = fmax(ep, a);
+        er = fmax(er, b);
+        if (t + 1 < T)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const double d = fabs(P.xi[(size_t)j * T + t + 1] - P.xi[(size_t)j * T + t]);
+                mj = fmax(mj, d);
+                len += d;
+            }
+    }
+    ep = block_max(ep, red);
+    er = block_max(er, red);
+    mj = block_max(mj, red);
+    len = block_sum(len, red);
+    const bool pose_ok = ep <= P.vtol[0] && er <= P.vtol[1];
+    if (pose_ok && mj <= P.vtol[2]) {
+        for (int e = threadIdx.x; e < NJ * T; e += LM_BS) P.xv[e] = P.xi[e];
+        if (threadIdx.x == 0) {
+            st->n_valid += 1;
+            if (st->first_valid < 0) st->first_valid = st->iters_done;
+            st->valid_length = len;
+        }
+    }
+    return pose_ok ? 1 : 0;
+}
+
+// One instance per precision and objective kind (the weighted sum, or the
+// alternating schedule), so that the schedule's extra state does not add
+// register pressure to the plain iteration.
+template <typename S, bool SCHED>
 __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ plans, int iters) {
     constexpr int PREC = sizeof(S) == sizeof(double) ? 1 : 0;
     const DevPlan &P = plans[blockIdx.x];
     const int T = P.T;
-    if (T <= 0 || P.prec != PREC) return;   // empty slot or the other precision's plan
+    // empty slot, or a plan of the other precision or objective kind
+    if (T <= 0 || P.prec != PREC || (P.schedule != 0) != SCHED) return;
     {
         const LMState *s0 = P.st;
         if (s0->seeded && s0->iters_target > 0 && s0->iters_done >= s0->iters_target) return;
     }
     __shared__ double red[LM_BS];
-    __shared__ double sh_lam, sh_nu, sh_cost;
+    // damping per objective: [0] the weighted sum (or the pose objective of
+    // the schedule), [1] the schedule's differencing objective
+    __shared__ double sh_lam[2], sh_nu[2], sh_cost;
     __shared__ int sh_flags[4];   // 0 need_lin, 1 status, 2 accept, 3 pivot failure
+    __shared__ int sh_sched[3];   // 0 checked, 1 next objective, 2 objective of the last step
     const int tid = threadIdx.x;
+    constexpr bool sched = SCHED;
     LMState *st = P.st;
 
     if (tid == 0) sh_flags[2] = st->seeded;
@@ -790,7 +865,7 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
                 P.xi[(size_t)j * T + t] = v;
             }
         __syncthreads();
-        const double c0 = plan_cost<S>(P, load_robot<S>(P), P.xi, T, red);
+        const double c0 = plan_cost<S>(P, load_robot<S>(P), P.xi, T, red, P.w_p, P.w_s);
         if (tid == 0) {
             st->nu = 2.0;
             st->cost = c0;
@@ -801,13 +876,28 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
             st->need_lin = 1;
             st->seeded = 1;
             st->grad_inf = 0.0;
+            st->lambda_d = P.lam0;
+            st->nu_d = 2.0;
+            st->valid_length = 0.0;
+            st->checked = 0;
+            st->mode = 0;
+            st->last_mode = -1;
+            st->n_valid = 0;
+            st->first_valid = -1;
+            st->pose_steps = 0;
+            st->diff_steps = 0;
         }
         __syncthreads();
     }
     if (tid == 0) {
-        sh_lam = st->lambda;
-        sh_nu = st->nu;
+        sh_lam[0] = st->lambda;
+        sh_nu[0] = st->nu;
+        sh_lam[1] = st->lambda_d;
+        sh_nu[1] = st->nu_d;
         sh_cost = st->cost;
+        sh_sched[0] = st->checked;
+        sh_sched[1] = st->mode;
+        sh_sched[2] = st->last_mode;
         sh_flags[0] = st->need_lin;
         sh_flags[1] = st->status;
         // iterations this launch: at most what the plan still has to do
@@ -838,9 +928,38 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
 #endif
     for (int it = 0; it < n_it; ++it) {
         if (sh_flags[1] != 0) break;
-        const double lam = sh_lam;
+        // Objective of this step: the weighted sum, or under the schedule the
+        // pose term alone until the pose thresholds hold, then the
+        // differencing term alone (re-decided by a check before every step).
+        int m = 0;
+        double wp = P.w_p, ws = P.w_s;
+        if (sched) {
+            if (!sh_sched[0]) {
+                const int nm = schedule_check(P, st, T, red);
+                if (tid == 0) {
+                    sh_sched[0] = 1;
+                    sh_sched[1] = nm;
+                }
+                __syncthreads();
+            }
+            m = sh_sched[1];
+            wp = m ? 0.0 : P.w_p;
+            ws = m ? P.w_s : 0.0;
+            if (m != sh_sched[2]) {   // new objective: its cost and linearisation
+                // (the barriers inside plan_cost order every lane's read of
+                // sh_sched[2] before lane 0 rewrites it)
+                const double c = plan_cost<S>(P, load_robot<S>(P), P.xi, T, red, wp, ws);
+                if (tid == 0) {
+                    sh_cost = c;
+                    sh_flags[0] = 1;
+                    sh_sched[2] = m;
+                }
+                __syncthreads();
+            }
+        }
+        const double lam = sh_lam[m];
         if (sh_flags[0]) {
-            const double gm = linearise<S>(P, load_robot<S>(P), T);
+            const double gm = linearise<S>(P, load_robot<S>(P), T, wp, ws);
             const double gmax = block_max(gm, red);
             if (tid == 0) st->grad_inf = gmax;
         }
@@ -852,11 +971,11 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
         for (int rs = 0; rs <= P.refine_steps; ++rs) {
             const bool first = rs == 0;
             if (!first) {
-                refine_residual(P, T, lam);
+                refine_residual(P, T, lam, ws);
                 __syncthreads();
                 PHASE_MARK(3);
             }
-            const bool ok = cr_solve(P, T, lam, first, first ? P.g : P.rb, first ? -1.0 : 1.0,
+            const bool ok = cr_solve(P, T, lam, ws, first, first ? P.g : P.rb, first ? -1.0 : 1.0,
                                      first ? P.dx : P.rb, &sh_bad, exch);
             if (first) {
                 if (tid == 0) sh_flags[3] = ok ? 0 : 1;
@@ -890,12 +1009,12 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
                 pr += dl * (lam * dl - P.g[e]);
             }
         __syncthreads();
-        const double cn = plan_cost<S>(P, load_robot<S>(P), P.xt, T, red);
+        const double cn = plan_cost<S>(P, load_robot<S>(P), P.xt, T, red, wp, ws);
         const double pred = 0.5 * block_sum(pr, red);
         PHASE_MARK(5);
         if (tid == 0) {
             const double c = sh_cost;
-            double l = sh_lam, nu = sh_nu;
+            double l = sh_lam[m], nu = sh_nu[m];
             const int acc = cn < c;
             if (acc) {
                 const double rho = (c - cn) / pred;
@@ -912,11 +1031,16 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
             }
             if (l < P.lam_min) l = P.lam_min;
             if (l > P.lam_max) l = P.lam_max;
-            sh_lam = l;
-            sh_nu = nu;
+            sh_lam[m] = l;
+            sh_nu[m] = nu;
             sh_flags[0] = acc;
             sh_flags[2] = acc;
             st->iters_done += 1;
+            if (sched) {
+                sh_sched[0] = 0;
+                if (m) st->diff_steps += 1;
+                else st->pose_steps += 1;
+            }
         }
         __syncthreads();
         if (sh_flags[2]) {
@@ -947,12 +1071,27 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
     }
 #endif
 #undef PHASE_MARK
+    // The check after the last step of the call (the next call's first step
+    // then reuses its decision).
+    if (sched && sh_flags[1] == 0 && !sh_sched[0]) {
+        const int nm = schedule_check(P, st, T, red);
+        if (tid == 0) {
+            sh_sched[0] = 1;
+            sh_sched[1] = nm;
+        }
+    }
+    __syncthreads();
     if (tid == 0) {
-        st->lambda = sh_lam;
-        st->nu = sh_nu;
+        st->lambda = sh_lam[0];
+        st->nu = sh_nu[0];
+        st->lambda_d = sh_lam[1];
+        st->nu_d = sh_nu[1];
         st->cost = sh_cost;
         st->need_lin = sh_flags[0];
         st->status = sh_flags[1];
+        st->checked = sh_sched[0];
+        st->mode = sh_sched[1];
+        st->last_mode = sh_sched[2];
     }
 }
 
@@ -972,27 +1111,14 @@ __global__ __launch_bounds__(LM_BS) void eval_kernel(const DevPlan *__restrict__
     const RobotT<double> rb = load_robot<double>(P);
     double ep = 0.0, er = 0.0, mj = 0.0;
     for (int t = threadIdx.x; t < T; t += LM_BS) {
-        double q[NJ];
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) q[j] = P.xi[(size_t)j * T + t];
-        double X[3], Y[3], Z[3], p[3], Zs[NJ][3], Os[NJ][3];
-        chain<double, false>(rb, q, X, Y, Z, p, Zs, Os);
-        double tg[12];
-        load_target<double>(P, T, t, tg);
-        const double dx = p[0] - tg[0], dy = p[1] - tg[1], dz = p[2] - tg[2];
-        ep = fmax(ep, sqrt(dx * dx + dy * dy + dz * dz));
-        double E[9];
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b)
-                E[a * 3 + b] = X[a] * tg[3 + b * 3 + 0] + Y[a] * tg[3 + b * 3 + 1] + Z[a] * tg[3 + b * 3 + 2];
-        const double v0 = 0.5 * (E[7] - E[5]), v1 = 0.5 * (E[2] - E[6]), v2 = 0.5 * (E[3] - E[1]);
-        er = fmax(er, atan2(sqrt(v0 * v0 + v1 * v1 + v2 * v2), 0.5 * (E[0] + E[4] + E[8] - 1.0)));
+        double a, b;
+        pose_err_fp64(P, rb, P.xi, T, t, &a, &b);
+        ep = fmax(ep, a);
+        er = fmax(er, b);
         if (t + 1 < T)
 #pragma unroll
             for (int j = 0; j < NJ; ++j)
-                mj = fmax(mj, fabs(P.xi[(size_t)j * T + t + 1] - q[j]));
+                mj = fmax(mj, fabs(P.xi[(size_t)j * T + t + 1] - P.xi[(size_t)j * T + t]));
     }
     ep = block_max(ep, red);
     er = block_max(er, red);
@@ -1005,12 +1131,17 @@ __global__ __launch_bounds__(LM_BS) void eval_kernel(const DevPlan *__restrict__
     }
 }
 
-hipError_t lm_launch(const DevPlan *d_plans, int nplans, int prec, int iters, hipStream_t s) {
+hipError_t lm_launch(const DevPlan *d_plans, int nplans, int prec, int sched, int iters, hipStream_t s) {
     if (nplans <= 0) return hipSuccess;
-    if (prec == 1)
-        hipLaunchKernelGGL((lm_kernel<double>), dim3(nplans), dim3(LM_BS), 0, s, d_plans, iters);
+    const dim3 g(nplans), b(LM_BS);
+    if (prec == 1 && sched)
+        hipLaunchKernelGGL((lm_kernel<double, true>), g, b, 0, s, d_plans, iters);
+    else if (prec == 1)
+        hipLaunchKernelGGL((lm_kernel<double, false>), g, b, 0, s, d_plans, iters);
+    else if (sched)
+        hipLaunchKernelGGL((lm_kernel<float, true>), g, b, 0, s, d_plans, iters);
     else
-        hipLaunchKernelGGL((lm_kernel<float>), dim3(nplans), dim3(LM_BS), 0, s, d_plans, iters);
+        hipLaunchKernelGGL((lm_kernel<float, false>), g, b, 0, s, d_plans, iters);
     return hipGetLastError();
 }
 

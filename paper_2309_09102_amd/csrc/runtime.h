@@ -40,7 +40,7 @@ inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 // region is shared with the search lists (topc), which are written later.
 struct Layout {
     size_t cand, extra, pen, bp, topk, topc, raw, path, dp_out, targets, xi, xt, A, g, cr, dx, rb, st,
-        report, total;
+        report, xv, total;
 };
 Layout make_layout(int T, int K, bool extra);
 uint64_t plan_bytes(int T, int K, bool extra);
@@ -157,9 +157,13 @@ struct PlanReadback {
     double report[8];
     double dp_out[8];
 };
-// Read state / report / search output and optionally xi ([T][7]) and path.
+// Read state / report / search output and optionally xi ([T][7]), path and
+// the latest valid trajectory ([T][7], written only when one exists).
 cpf_status read_plan(cpf_plan *p, hipStream_t s, const LMState *state_dev, PlanReadback *rb,
-                     double *xi_out, int32_t *path_out);
+                     double *xi_out, int32_t *path_out, double *xv_out);
+// Device [7][T] to caller [T][7].
+void soa_to_rows(const double *soa, int T, double *rows);
+void report_from(const LMState &ls, const double *report, cpf_lm_report *rep);
 void fill_report(const PlanReadback &rb, cpf_lm_report *rep);
 
 // Server lifetime (serve.cpp).

@@ -46,7 +46,7 @@ struct Request {
     int slot = -1;
     bool done = false;
     cpf_status status = CPF_OK;
-    std::vector<double> xi, xi_soa;
+    std::vector<double> xi, xi_soa, xv, xv_soa;
     std::vector<int32_t> path;
     double report[8] = {0}, dp_out[8] = {0};
     cpf_lm_report rep{};
@@ -93,11 +93,13 @@ cpf_status server_init(cpf_ctx *ctx, Server *sv) {
     HIP_TRY(hipMemcpyAsync(sv->d_states, sv->h_states.data(), sizeof(LMState) * sv->cap,
                            hipMemcpyHostToDevice, sv->s_lm));
     HIP_TRY(hipStreamSynchronize(sv->s_lm));
-    // Capture the LM tick: both precisions over every slot, then the report
-    // for plans that finished in this tick.
+    // Capture the LM tick: both precisions and both objective kinds over
+    // every slot (each instance skips the slots of the others), then the
+    // report for plans that finished in this tick.
     HIP_TRY(hipStreamBeginCapture(sv->s_lm, hipStreamCaptureModeThreadLocal));
-    hipError_t e = lm_launch(sv->d_work, sv->cap, 0, sv->ipt, sv->s_lm);
-    if (e == hipSuccess) e = lm_launch(sv->d_work, sv->cap, 1, sv->ipt, sv->s_lm);
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 4 && e == hipSuccess; ++k)
+        e = lm_launch(sv->d_work, sv->cap, k & 1, k >> 1, sv->ipt, sv->s_lm);
     if (e == hipSuccess) e = eval_launch(sv->d_work, sv->cap, 1, sv->s_lm);
     hipError_t e2 = hipStreamEndCapture(sv->s_lm, &sv->graph);
     if (e != hipSuccess) return fail(CPF_E_DEVICE, "tick capture: %s", hipGetErrorString(e));
@@ -142,6 +144,7 @@ void finish(cpf_ctx *ctx, Server *sv, Request *r) {
     }
     release_stage(ctx, r);
     std::vector<double>().swap(r->xi_soa);
+    std::vector<double>().swap(r->xv_soa);
     r->t_done = now_ns();
     std::lock_guard<std::mutex> lk(ctx->mu);
     r->done = true;
@@ -170,6 +173,12 @@ void retire(cpf_ctx *ctx, Server *sv, const std::vector<Request *> &fin, cpf_sta
                 e = hipMemcpyAsync(r->report, a + L.report, sizeof(r->report), hipMemcpyDeviceToHost, sv->s_lm);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(r->dp_out, a + L.dp_out, sizeof(r->dp_out), hipMemcpyDeviceToHost, sv->s_lm);
+            if (r->opts.schedule && sv->h_states[r->slot].n_valid > 0) {
+                r->xv_soa.resize((size_t)NJ * r->T);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(r->xv_soa.data(), a + L.xv, r->xv_soa.size() * sizeof(double),
+                                       hipMemcpyDeviceToHost, sv->s_lm);
+            }
         }
         if (e == hipSuccess) e = hipStreamSynchronize(sv->s_lm);
         if (e != hipSuccess) dev = fail(CPF_E_DEVICE, "read-back: %s", hipGetErrorString(e));
@@ -180,17 +189,12 @@ void retire(cpf_ctx *ctx, Server *sv, const std::vector<Request *> &fin, cpf_sta
         } else {
             const LMState &ls = sv->h_states[r->slot];
             r->xi.resize((size_t)r->T * NJ);
-            for (int t = 0; t < r->T; ++t)
-                for (int j = 0; j < NJ; ++j) r->xi[(size_t)t * NJ + j] = r->xi_soa[(size_t)j * r->T + t];
-            r->rep.cost0 = ls.cost0;
-            r->rep.cost = ls.cost;
-            r->rep.lambda = ls.lambda;
-            r->rep.grad_inf = ls.grad_inf;
-            r->rep.n_accepted = ls.n_acc;
-            r->rep.iters_done = ls.iters_done;
-            r->rep.max_pos_err_m = r->report[0];
-            r->rep.max_rot_err_rad = r->report[1];
-            r->rep.mjac = r->report[2];
+            soa_to_rows(r->xi_soa.data(), r->T, r->xi.data());
+            if (!r->xv_soa.empty()) {
+                r->xv.resize((size_t)r->T * NJ);
+                soa_to_rows(r->xv_soa.data(), r->T, r->xv.data());
+            }
+            report_from(ls, r->report, &r->rep);
             r->best = r->dp_out[0];
             r->smjac = r->dp_out[1];
             r->status = ls.status != 0 ? CPF_E_NUMERIC : CPF_OK;
@@ -447,6 +451,8 @@ extern "C" cpf_status cpf_poll(cpf_ctx *ctx, uint64_t ticket, int32_t timeout_ms
         if (out->xi && !r->xi.empty()) memcpy(out->xi, r->xi.data(), r->xi.size() * sizeof(double));
         if (out->path && !r->path.empty())
             memcpy(out->path, r->path.data(), r->path.size() * sizeof(int32_t));
+        if (out->xi_valid && !r->xv.empty())
+            memcpy(out->xi_valid, r->xv.data(), r->xv.size() * sizeof(double));
         out->report = r->rep;
         out->search_best = r->best;
         out->search_mjac = r->smjac;

@@ -1,0 +1,205 @@
+"""GPU parity of the alternating schedule with anytime validity (Sec. III-C;
+validity thresholds of Sec. II) against oracle.lm_schedule.
+
+All-FP64 arm: the same decisions as the oracle (which objective each step
+takes, which checks pass: counts compared exactly), the final and the latest
+valid trajectories within the refinement path's tolerances (1e-5 m, 1e-5
+rad under the oracle's FP64 FK), the valid trajectory's length to 1e-9
+relative.  Mixed arm (FP32 kinematics): its FP32 residuals move the path by
+far less than the thresholds, so the first pass comes at the same iteration
+and the stored trajectory must itself pass the thresholds under the
+oracle's FK.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2309_09102_amd import synth
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2309_09102_amd import cpf  # noqa: E402
+
+POS_TOL, ROT_TOL = 1e-5, 1e-5
+VALID = oracle.VALID_TOL
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = cpf.Context(0, 8 << 30)
+    yield c
+    c.close()
+
+
+def _opts(prec, **kw):
+    return cpf.make_opts(prec=prec, schedule=1, **kw)
+
+
+def _gpu(ctx, p, iters, prec, chunks=None):
+    with ctx.plan(p.robot, p.targets, p.cand, opts=_opts(prec)) as plan:
+        path, _, _ = plan.dp_search()
+        for n in chunks or [iters]:
+            xi, rep = plan.lm_refine(n)
+        xv = plan.latest_valid() if rep["n_valid"] > 0 else None
+    return path, xi, rep, xv
+
+
+def _ref(p, iters):
+    path, _, _, _ = oracle.dp(p.cand, p.robot)
+    return path, oracle.lm_schedule(p.robot, H.seed_of(p, path), p.targets, iters)
+
+
+def _assert_valid(p, xv):
+    ep, er = oracle.pose_compare(p.robot, xv, targets=p.targets)
+    assert ep <= VALID[0] and er <= VALID[1], (ep, er)
+    assert np.abs(np.diff(xv, axis=0)).max() <= VALID[2]
+
+
+def _close(p, a, b):
+    ep, er = oracle.pose_compare(p.robot, a, b)
+    assert ep <= POS_TOL and er <= ROT_TOL, (ep, er)
+
+
+COUNTS = ("n_valid", "first_valid", "pose_steps", "diff_steps")
+
+
+def _assert_length(rep, xv, ref=None):
+    """The reported length is that of the stored trajectory (sum of |joint
+    change|, to summation-order rounding); against the oracle's it can differ
+    by at most 2 sum_t,j |xv - xv_ref| (each term of the sum moves by at
+    most the change of its two endpoints)."""
+    own = np.abs(np.diff(xv, axis=0)).sum()
+    assert rep["valid_length"] == pytest.approx(own, rel=1e-12)
+    if ref is not None:
+        bound = 2.0 * np.abs(xv - ref["xi_valid"]).sum() + 1e-12
+        assert abs(rep["valid_length"] - ref["valid_length"]) <= bound
+
+
+@pytest.mark.parametrize("seed,T,K,iters", [(21, 60, 16, 40), (22, 150, 32, 25), (24, 40, 8, 12)])
+def test_schedule_fp64_matches_oracle(ctx, seed, T, K, iters):
+    p = H.small_problem(seed=seed, T=T, K=K)
+    path_ref, ref = _ref(p, iters)
+    path, xi, rep, xv = _gpu(ctx, p, iters, "fp64")
+    assert np.array_equal(path, path_ref)
+    assert {k: rep[k] for k in COUNTS} == {k: ref[k] for k in COUNTS}
+    assert rep["iters_done"] == iters and rep["pose_steps"] + rep["diff_steps"] == iters
+    _close(p, xi, ref["xi"])
+    assert ref["n_valid"] > 0
+    _close(p, xv, ref["xi_valid"])
+    _assert_valid(p, xv)
+    _assert_length(rep, xv, ref)
+
+
+def test_schedule_mixed_first_pass_and_validity(ctx):
+    p = H.small_problem(seed=21, T=60, K=16)
+    _, ref = _ref(p, 40)
+    _, xi, rep, xv = _gpu(ctx, p, 40, "mixed")
+    assert rep["first_valid"] == ref["first_valid"]
+    assert rep["n_valid"] >= 1 and rep["pose_steps"] + rep["diff_steps"] == 40
+    _assert_valid(p, xv)
+    _assert_length(rep, xv)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_schedule_config2_full_size(ctx, prec):
+    """T=300, K=256 with 30 iterations."""
+    p = H.with_targets(synth.config2())
+    _, ref = _ref(p, 30)
+    _, xi, rep, xv = _gpu(ctx, p, 30, prec)
+    print(f"config2 schedule {prec}: " + " ".join(f"{k}={rep[k]}" for k in COUNTS)
+          + " | oracle " + " ".join(f"{k}={ref[k]}" for k in COUNTS))
+    assert rep["first_valid"] == ref["first_valid"] >= 0
+    _assert_valid(p, xv)
+    if prec == "fp64":
+        assert {k: rep[k] for k in COUNTS} == {k: ref[k] for k in COUNTS}
+        _close(p, xi, ref["xi"])
+        _close(p, xv, ref["xi_valid"])
+
+
+def test_schedule_resumable_bitwise(ctx):
+    p = H.small_problem(seed=23, T=100, K=24)
+    _, xa, ra, va = _gpu(ctx, p, 30, "mixed")
+    _, xb, rb, vb = _gpu(ctx, p, 30, "mixed", chunks=[7, 0, 11, 12])
+    assert np.array_equal(xa, xb) and np.array_equal(va, vb)
+    assert {k: ra[k] for k in COUNTS} == {k: rb[k] for k in COUNTS}
+    assert ra["cost"] == rb["cost"] and ra["lam_diff"] == rb["lam_diff"]
+
+
+@pytest.mark.parametrize("T", [1, 2, 3])
+def test_schedule_tiny_paths(ctx, T):
+    p = H.small_problem(seed=30 + T, T=T, K=4)
+    _, ref = _ref(p, 8)
+    _, xi, rep, xv = _gpu(ctx, p, 8, "fp64")
+    assert {k: rep[k] for k in COUNTS} == {k: ref[k] for k in COUNTS}
+    _close(p, xi, ref["xi"])
+
+
+def test_schedule_discontinuous_seed_takes_a_differencing_step(ctx):
+    """A seed on its targets with one 10 degree joint jump: pose-valid, so a
+    differencing step follows, but not valid (step threshold 7 degrees)."""
+    rb = synth.make_robot(4)
+    prob = synth.make_problem(rb, seed=4, T=20, K=1, sigma=0.02)
+    q = prob.q_star.copy()
+    q[10:, 0] += np.deg2rad(10.0)
+    q = np.clip(q, rb.q_lo, rb.q_hi)
+    p = prob.with_targets(oracle.fk(rb, q))
+    cand = q[None]
+    ref = oracle.lm_schedule(rb, q, p.targets, 1)
+    with ctx.plan(rb, p.targets, cand, opts=_opts("fp64")) as plan:
+        plan.dp_search()
+        xi, rep = plan.lm_refine(1)
+        with pytest.raises(cpf.CpfError) as ei:
+            plan.latest_valid()
+    assert ei.value.status == cpf.E_STATE
+    assert {k: rep[k] for k in COUNTS} == {k: ref[k] for k in COUNTS}
+    assert rep["diff_steps"] == 1 and rep["n_valid"] == 0
+    _close(p, xi, ref["xi"])
+
+
+def test_schedule_unreachable_targets_stay_invalid(ctx):
+    p = H.small_problem(seed=25, T=10, K=4)
+    far = p.targets.copy()
+    far[:, :3] += 10.0
+    with ctx.plan(p.robot, far, p.cand, opts=_opts("mixed")) as plan:
+        plan.dp_search()
+        _, rep = plan.lm_refine(5)
+        with pytest.raises(cpf.CpfError) as ei:
+            plan.latest_valid()
+    assert ei.value.status == cpf.E_STATE
+    assert rep["n_valid"] == 0 and rep["first_valid"] == -1 and rep["pose_steps"] == 5
+
+
+def test_latest_valid_needs_the_schedule(ctx):
+    p = H.small_problem(seed=26, T=10, K=4)
+    with ctx.plan(p.robot, p.targets, p.cand) as plan:
+        plan.dp_search()
+        plan.lm_refine(3)
+        with pytest.raises(cpf.CpfError) as ei:
+            plan.latest_valid()
+    assert ei.value.status == cpf.E_STATE
+    with pytest.raises(cpf.CpfError) as ei:
+        ctx.plan(p.robot, p.targets, p.cand, opts=cpf.make_opts(schedule=2))
+    assert ei.value.status == cpf.E_ARG
+
+
+def test_schedule_batch_and_serving_equal_alone(ctx):
+    probs = [H.small_problem(seed=90 + i, T=40 + 13 * i, K=12 + 4 * i) for i in range(4)]
+    opts = _opts("mixed", iters=16)
+    batch = ctx.solve_batch([(p.robot, p.targets, p.cand) for p in probs], opts)
+    tickets = [ctx.submit(p.robot, p.targets, p.cand, opts) for p in probs]
+    served = [ctx.poll(t, p.T, timeout_ms=60000) for t, p in zip(tickets, probs)]
+    for p, b, s in zip(probs, batch, served):
+        _, xi, rep, xv = _gpu(ctx, p, 16, "mixed")
+        for r in (b, s):
+            assert r is not None and r["status"] == 0
+            assert np.array_equal(r["xi"], xi)
+            assert {k: r["report"][k] for k in COUNTS} == {k: rep[k] for k in COUNTS}
+            if rep["n_valid"] > 0:
+                assert np.array_equal(r["xi_valid"], xv)
+            else:
+                assert r["xi_valid"] is None
