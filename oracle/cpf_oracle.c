@@ -625,8 +625,13 @@ void or_pose_compare(int n, const double *a, const double *d, const double *alph
  * trajectory that passes is kept in xi_valid.  A trajectory whose pose
  * errors are within the thresholds then takes one LM step on the
  * differencing residual alone (w_pose = 0); any other takes one LM step on
- * the pose residual alone (w_smooth = 0).  Each objective keeps its own
- * damping (lambda, nu), updated by the same Nielsen rule as or_lm.
+ * the pose residual alone (w_smooth = 0).  The pose objective's damping
+ * (lambda, nu) follows the same Nielsen rule as or_lm.  The differencing
+ * step keeps the fixed damping lambda0: its objective is quadratic, so its
+ * gain ratio is 1 up to clamping and the rule would only shrink lambda
+ * towards its floor, after which one step would collapse the whole path
+ * onto a constant configuration.  A step is accepted iff it lowers its own
+ * objective.
  * info[0] = checks passed, info[1] = iteration of the first pass (-1: none;
  * iters: only after the last iteration), info[2] = trajectory length of the
  * latest valid trajectory (sum over steps and joints of |change|), info[3] =
@@ -653,7 +658,7 @@ int or_lm_schedule(int n, const double *a, const double *d, const double *alpha,
         if (xi[e] < lo[j]) xi[e] = lo[j];
         if (xi[e] > hi[j]) xi[e] = hi[j];
     }
-    double lam[2] = {o.lambda0, o.lambda0}, nu[2] = {2.0, 2.0};
+    double lam = o.lambda0, nu = 2.0;   /* pose objective */
     for (int it = 0; it <= iters; ++it) {
         double err[2];
         or_pose_compare(n, a, d, alpha, theta_off, T, xi, NULL, targets, err);
@@ -671,10 +676,11 @@ int or_lm_schedule(int n, const double *a, const double *d, const double *alpha,
         if (it == iters) break;
         const int m = pose_ok ? 1 : 0;   /* 0: pose step, 1: differencing step */
         const double wp = m ? 0.0 : o.w_pose, ws = m ? o.w_smooth : 0.0;
+        const double l = m ? o.lambda0 : lam;
         info[3 + m] += 1;
         const double C = cost_of(&rb, T, xi, targets, wp, ws);
         linearise(&rb, T, xi, targets, wp, ws, A, g);
-        if (lm_solve(T, n, A, g, ws, lam[m], delta, Db, rhs) != 0) { rc = -1; break; }
+        if (lm_solve(T, n, A, g, ws, l, delta, Db, rhs) != 0) { rc = -1; break; }
         for (size_t e = 0; e < nT; ++e) {
             int j = (int)(e % (size_t)n);
             double v = xi[e] + delta[e];
@@ -683,23 +689,26 @@ int or_lm_schedule(int n, const double *a, const double *d, const double *alpha,
             trial[e] = v;
         }
         const double Cn = cost_of(&rb, T, trial, targets, wp, ws);
-        double pred = 0.0;
-        for (size_t e = 0; e < nT; ++e) pred += delta[e] * (lam[m] * delta[e] - g[e]);
-        pred *= 0.5;
-        if (Cn < C) {
-            double rho = (C - Cn) / pred;
-            double u = 2.0 * rho - 1.0;
-            double f = 1.0 - u * u * u;
-            if (f < 1.0 / 3.0) f = 1.0 / 3.0;
-            lam[m] *= f;
-            nu[m] = 2.0;
-            memcpy(xi, trial, sizeof(double) * nT);
-        } else {
-            lam[m] *= nu[m];
-            nu[m] *= 2.0;
+        const int acc = Cn < C;
+        if (acc) memcpy(xi, trial, sizeof(double) * nT);
+        if (m == 0) {
+            double pred = 0.0;
+            for (size_t e = 0; e < nT; ++e) pred += delta[e] * (lam * delta[e] - g[e]);
+            pred *= 0.5;
+            if (acc) {
+                double rho = (C - Cn) / pred;
+                double u = 2.0 * rho - 1.0;
+                double f = 1.0 - u * u * u;
+                if (f < 1.0 / 3.0) f = 1.0 / 3.0;
+                lam *= f;
+                nu = 2.0;
+            } else {
+                lam *= nu;
+                nu *= 2.0;
+            }
+            if (lam < o.lambda_min) lam = o.lambda_min;
+            if (lam > o.lambda_max) lam = o.lambda_max;
         }
-        if (lam[m] < o.lambda_min) lam[m] = o.lambda_min;
-        if (lam[m] > o.lambda_max) lam[m] = o.lambda_max;
     }
 done:
     free(A); free(g); free(Db); free(rhs); free(delta); free(trial);

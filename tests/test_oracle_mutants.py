@@ -43,6 +43,9 @@ MUTANTS = {
                     "trial[e] = v;"),
     "sched_modes_swapped": ("const int m = pose_ok ? 1 : 0;", "const int m = pose_ok ? 0 : 1;"),
     "sched_step_check_dropped": ("int steps_ok = or_mjac(T, n, xi) <= tol[2];", "int steps_ok = 1;"),
+    "sched_diff_damping_adapts": ("const double l = m ? o.lambda0 : lam;", "const double l = lam;"),
+    "sched_reject_keeps_damping": ("lam *= nu;\n                nu *= 2.0;\n            }\n            if (lam < o.lambda_min)",
+                                   "nu *= 2.0;\n            }\n            if (lam < o.lambda_min)"),
     "sched_length_signed": ("len += fabs(xi[(size_t)(t + 1) * n + j] - xi[(size_t)t * n + j]);",
                             "len += xi[(size_t)(t + 1) * n + j] - xi[(size_t)t * n + j];"),
 }
@@ -71,6 +74,7 @@ def battery():
         lambda: P.test_p15_schedule_valid_seed_takes_a_differencing_step(),
         lambda: P.test_p15_schedule_latest_valid_meets_the_thresholds(),
         lambda: P.test_p15_schedule_rejects_a_discontinuous_pose_valid_trajectory(),
+        lambda: P.test_p15_schedule_steps_are_single_objective_lm_steps(),
     ]
 
 

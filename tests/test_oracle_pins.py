@@ -539,3 +539,51 @@ def test_p15_schedule_rejects_a_discontinuous_pose_valid_trajectory():
     # is not valid: one joint changes by more than 7 degrees
     assert r["diff_steps"] == 1 and r["pose_steps"] == 0
     assert r["first_valid"] == -1 and r["n_valid"] == 0
+
+
+def _replay_schedule(rb, x0, tg, kmax):
+    """Replays a schedule run step by step from the oracle's own LM step:
+    returns (differencing steps, rejected steps, longest run of rejects)."""
+    lam0 = oracle.DEFAULT_LM["lambda0"]
+    prev = oracle.lm_schedule(rb, x0, tg, 0)
+    lam_pose, nu_pose = lam0, 2.0
+    n_diff = n_rej = run = longest = 0
+    for k in range(1, kmax + 1):
+        cur = oracle.lm_schedule(rb, x0, tg, k)
+        x = prev["xi"]
+        diff = cur["diff_steps"] > prev["diff_steps"]
+        wp, ws = (0.0, 0.1) if diff else (1.0, 0.0)
+        lam = lam0 if diff else lam_pose
+        d, g = oracle.lm_step(rb, x, tg, wp, ws, lam)
+        trial = np.clip(x + d, rb.q_lo, rb.q_hi)
+        c, cn = oracle.cost(rb, x, tg, wp, ws), oracle.cost(rb, trial, tg, wp, ws)
+        np.testing.assert_allclose(cur["xi"], trial if cn < c else x, rtol=0, atol=1e-12)
+        if not diff:   # the Nielsen rule on the pose objective
+            if cn < c:
+                u = 2.0 * (c - cn) / (0.5 * np.sum(d * (lam * d - g))) - 1.0
+                lam_pose, nu_pose = lam * max(1.0 / 3.0, 1.0 - u * u * u), 2.0
+            else:
+                lam_pose, nu_pose = lam * nu_pose, 2.0 * nu_pose
+            lam_pose = min(max(lam_pose, 1e-10), 1e10)
+        n_diff += diff
+        run = run + 1 if cn >= c else 0
+        n_rej += cn >= c
+        longest = max(longest, run)
+        prev = cur
+    return n_diff, n_rej, longest
+
+
+def test_p15_schedule_steps_are_single_objective_lm_steps():
+    """Each step of a run is one damped step of its own objective from the
+    previous iterate (runs of k and k+1 iterations share their first k): a
+    differencing step with the fixed damping lambda0 (w_pose = 0), a pose
+    step with the damping the pose steps before it left by the Nielsen rule
+    (w_smooth = 0), accepted iff it lowers that objective.  One smooth case
+    alternates; one rough case (1.5 rad noise) has rejected pose steps, two
+    in a row."""
+    rb, prob, tg = _sched_case(seed=2, T=40, sigma=0.03)
+    n_diff, _, _ = _replay_schedule(rb, prob.cand[0], tg, 15)
+    assert n_diff >= 2
+    rb, prob, tg = _sched_case(seed=8, T=20, sigma=1.5)
+    _, n_rej, longest = _replay_schedule(rb, prob.cand[0], tg, 12)
+    assert n_rej >= 3 and longest >= 2
