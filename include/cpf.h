@@ -107,7 +107,8 @@ typedef struct cpf_problem {
  *     passes is kept as the latest valid trajectory.  A trajectory within the
  *     pose thresholds then takes an LM step on the differencing term alone
  *     (weight w_smooth), any other a step on the pose term alone (weight
- *     w_pose); each objective keeps its own damping. */
+ *     w_pose).  The pose steps' damping follows the gain-ratio rule; the
+ *     differencing steps keep lambda0. */
 typedef struct cpf_opts {
     double w_pose, w_smooth;
     double lambda0, lambda_min, lambda_max;
@@ -135,7 +136,6 @@ typedef struct cpf_lm_report {
     int32_t diff_steps;      /* steps taken on the differencing objective */
     double valid_length;     /* sum over steps and joints of |change| along the
                                 latest valid trajectory */
-    double lambda_diff;      /* damping of the differencing objective */
 } cpf_lm_report;
 
 typedef struct cpf_result {

@@ -63,7 +63,7 @@ class cpf_lm_report(C.Structure):
                 ("max_pos_err_m", C.c_double), ("max_rot_err_rad", C.c_double),
                 ("mjac", C.c_double), ("n_valid", C.c_int32), ("first_valid", C.c_int32),
                 ("pose_steps", C.c_int32), ("diff_steps", C.c_int32),
-                ("valid_length", C.c_double), ("lambda_diff", C.c_double)]
+                ("valid_length", C.c_double)]
 
 
 class cpf_result(C.Structure):
@@ -173,7 +173,7 @@ def _report(r: cpf_lm_report) -> dict:
                 n_accepted=r.n_accepted, iters_done=r.iters_done,
                 max_pos_err_m=r.max_pos_err_m, max_rot_err_rad=r.max_rot_err_rad, mjac=r.mjac,
                 n_valid=r.n_valid, first_valid=r.first_valid, pose_steps=r.pose_steps,
-                diff_steps=r.diff_steps, valid_length=r.valid_length, lam_diff=r.lambda_diff)
+                diff_steps=r.diff_steps, valid_length=r.valid_length)
 
 
 # ---- functions with the C ABI's names ---------------------------------------

@@ -400,7 +400,6 @@ void report_from(const LMState &ls, const double *report, cpf_lm_report *rep) {
     rep->pose_steps = ls.pose_steps;
     rep->diff_steps = ls.diff_steps;
     rep->valid_length = ls.valid_length;
-    rep->lambda_diff = ls.lambda_d;
 }
 
 void fill_report(const PlanReadback &rb, cpf_lm_report *rep) { report_from(rb.st, rb.report, rep); }

@@ -50,10 +50,9 @@ constexpr int TOPM = 16;      // nearest predecessors kept per search node
 
 struct LMState {
     double lambda, nu, cost, cost0, grad_inf;
-    // schedule mode: damping of the differencing objective (lambda, nu above
-    // belong to the pose objective) and the length of the latest valid
-    // trajectory
-    double lambda_d, nu_d, valid_length;
+    // schedule mode: the length of the latest valid trajectory (lambda, nu
+    // above belong to the pose objective)
+    double valid_length, pad2, pad3;
     int32_t n_acc, iters_done, status, need_lin;
     int32_t iters_target, seeded, reported, checked;
     // schedule mode: objective of the next step (0 pose, 1 differencing) as

@@ -126,10 +126,14 @@ __device__ __forceinline__ double linearise(const DevPlan &P, const RobotT<S> &r
             J[4][i] = Zs[i][1];
             J[5][i] = Zs[i][2];
         }
-        // The Gram matrix of the (FP32 or FP64) Jacobian is accumulated in
-        // FP64: then it is positive semi-definite to FP64 rounding, and the
-        // damped block stays positive definite for every lambda >= lambda_min
-        // also when no smoothness term is added (the schedule's pose step).
+        // The Gram matrix and the gradient J^T r of the (FP32 or FP64)
+        // Jacobian and residual are accumulated in FP64.  Then the Gram is
+        // positive semi-definite to FP64 rounding, so the damped block stays
+        // positive definite for every lambda >= lambda_min also without a
+        // smoothness term (the schedule's pose step), and the gradient lies
+        // in J's row space to FP64 rounding: FP32 accumulation would leave a
+        // component along J's null space (the self-motion direction) that a
+        // pose-only step amplifies by 1 / lambda.
 #pragma unroll
         for (int i = 0; i < NJ; ++i) {
 #pragma unroll
@@ -144,10 +148,10 @@ __device__ __forceinline__ double linearise(const DevPlan &P, const RobotT<S> &r
         }
 #pragma unroll
         for (int i = 0; i < NJ; ++i) {
-            S s = J[0][i] * r[0];
+            double s = (double)J[0][i] * (double)r[0];
 #pragma unroll
-            for (int k = 1; k < 6; ++k) s += J[k][i] * r[k];
-            double gi = w_p * (double)s;
+            for (int k = 1; k < 6; ++k) s += (double)J[k][i] * (double)r[k];
+            double gi = w_p * s;
             double sm = 0.0;
             if (t > 0) sm += xq[i] - P.xi[(size_t)i * T + t - 1];
             if (t + 1 < T) sm += xq[i] - P.xi[(size_t)i * T + t + 1];
@@ -747,6 +751,32 @@ __device__ __forceinline__ bool cr_solve(const DevPlan &P, int T, double lam, do
     return *bad == 0;
 }
 
+// Block-diagonal case (no differencing term, w_s = 0: the schedule's pose
+// step, Sec. III-C): each waypoint solves D_t x_t = sgn rhs_t on its own,
+// one lane per waypoint, refactoring for every right-hand side (a 7 x 7
+// Cholesky is cheaper than storing and reloading it).  out may alias rhs.
+// Returns false on a pivot that is not positive.  All threads.
+__device__ __forceinline__ bool diag_solve(const DevPlan &P, int T, double lam, const CPF_GLOBAL double *rhs,
+                                           double sgn, CPF_GLOBAL double *out, int *bad) {
+    if (threadIdx.x == 0) *bad = 0;
+    __syncthreads();
+    bool ok = true;
+    for (int t = threadIdx.x; t < T; t += LM_BS) {
+        double D[NTRI], b[NJ], y[NJ], x[NJ];
+        level0_D(P, T, lam, 0.0, t, D);
+        chol_inverse(D, ok);
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) b[j] = sgn * rhs[(size_t)j * T + t];
+        tri_mv(D, b, y);
+        tri_tmv(D, y, x);
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) out[(size_t)j * T + t] = x[j];
+    }
+    if (!ok) *bad = 1;
+    __syncthreads();
+    return *bad == 0;
+}
+
 // rb_t = -g_t - (H dx)_t  for every waypoint (all lanes).
 __device__ __forceinline__ void refine_residual(const DevPlan &P, int T, double lam, double ws) {
     const double w = ws;
@@ -844,9 +874,7 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
         if (s0->seeded && s0->iters_target > 0 && s0->iters_done >= s0->iters_target) return;
     }
     __shared__ double red[LM_BS];
-    // damping per objective: [0] the weighted sum (or the pose objective of
-    // the schedule), [1] the schedule's differencing objective
-    __shared__ double sh_lam[2], sh_nu[2], sh_cost;
+    __shared__ double sh_lam, sh_nu, sh_cost;
     __shared__ int sh_flags[4];   // 0 need_lin, 1 status, 2 accept, 3 pivot failure
     __shared__ int sh_sched[3];   // 0 checked, 1 next objective, 2 objective of the last step
     const int tid = threadIdx.x;
@@ -876,8 +904,6 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
             st->need_lin = 1;
             st->seeded = 1;
             st->grad_inf = 0.0;
-            st->lambda_d = P.lam0;
-            st->nu_d = 2.0;
             st->valid_length = 0.0;
             st->checked = 0;
             st->mode = 0;
@@ -890,10 +916,8 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
         __syncthreads();
     }
     if (tid == 0) {
-        sh_lam[0] = st->lambda;
-        sh_nu[0] = st->nu;
-        sh_lam[1] = st->lambda_d;
-        sh_nu[1] = st->nu_d;
+        sh_lam = st->lambda;
+        sh_nu = st->nu;
         sh_cost = st->cost;
         sh_sched[0] = st->checked;
         sh_sched[1] = st->mode;
@@ -931,6 +955,9 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
         // Objective of this step: the weighted sum, or under the schedule the
         // pose term alone until the pose thresholds hold, then the
         // differencing term alone (re-decided by a check before every step).
+        // The differencing step keeps the fixed damping lambda0: its
+        // objective is quadratic, so the gain-ratio rule would only drive
+        // lambda to its floor and one step would then flatten the path.
         int m = 0;
         double wp = P.w_p, ws = P.w_s;
         if (sched) {
@@ -957,7 +984,7 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
                 __syncthreads();
             }
         }
-        const double lam = sh_lam[m];
+        const double lam = m ? P.lam0 : sh_lam;
         if (sh_flags[0]) {
             const double gm = linearise<S>(P, load_robot<S>(P), T, wp, ws);
             const double gmax = block_max(gm, red);
@@ -975,8 +1002,11 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
                 __syncthreads();
                 PHASE_MARK(3);
             }
-            const bool ok = cr_solve(P, T, lam, ws, first, first ? P.g : P.rb, first ? -1.0 : 1.0,
-                                     first ? P.dx : P.rb, &sh_bad, exch);
+            const bool ok = (SCHED && ws == 0.0)
+                                ? diag_solve(P, T, lam, first ? P.g : P.rb, first ? -1.0 : 1.0,
+                                             first ? P.dx : P.rb, &sh_bad)
+                                : cr_solve(P, T, lam, ws, first, first ? P.g : P.rb, first ? -1.0 : 1.0,
+                                           first ? P.dx : P.rb, &sh_bad, exch);
             if (first) {
                 if (tid == 0) sh_flags[3] = ok ? 0 : 1;
                 PHASE_MARK(1);
@@ -1014,9 +1044,16 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
         PHASE_MARK(5);
         if (tid == 0) {
             const double c = sh_cost;
-            double l = sh_lam[m], nu = sh_nu[m];
+            double l = sh_lam, nu = sh_nu;
             const int acc = cn < c;
-            if (acc) {
+            if (m) {
+                // differencing step: accept iff it lowers its objective; the
+                // pose objective's damping is left as it is
+                if (acc) {
+                    sh_cost = cn;
+                    st->n_acc += 1;
+                }
+            } else if (acc) {
                 const double rho = (c - cn) / pred;
                 const double u = 2.0 * rho - 1.0;
                 double f = 1.0 - u * u * u;
@@ -1031,8 +1068,10 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
             }
             if (l < P.lam_min) l = P.lam_min;
             if (l > P.lam_max) l = P.lam_max;
-            sh_lam[m] = l;
-            sh_nu[m] = nu;
+            if (!m) {
+                sh_lam = l;
+                sh_nu = nu;
+            }
             sh_flags[0] = acc;
             sh_flags[2] = acc;
             st->iters_done += 1;
@@ -1082,10 +1121,8 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
     }
     __syncthreads();
     if (tid == 0) {
-        st->lambda = sh_lam[0];
-        st->nu = sh_nu[0];
-        st->lambda_d = sh_lam[1];
-        st->nu_d = sh_nu[1];
+        st->lambda = sh_lam;
+        st->nu = sh_nu;
         st->cost = sh_cost;
         st->need_lin = sh_flags[0];
         st->status = sh_flags[1];

@@ -8,6 +8,9 @@
              all-FP64 arm (their agreement with the oracle is a GPU test).
   batchopt   the 5 smoothest candidates of the T=300, K=256 request optimised
              directly without the search, 50 LM iterations each.
+  schedule   the T=300, K=256 request refined for 50 iterations by the
+             alternating schedule with anytime validity (both precisions),
+             beside the weighted objective.
   serve      Poisson arrivals (200 requests/s) of requests with T ~ U{50..2000},
              K in {128, 256, 512}, sigma ~ U[0.02, 0.15], offset fraction
              ~ U[0, 0.3] and 30 LM iterations, served by cpf_submit/cpf_poll
@@ -113,6 +116,41 @@ def run_batchopt(M=5, iters=50):
                             "best": idx[int(np.argmin(costs))],
                             "pose_err_vs_targets_best": [res[int(np.argmin(costs))]["report"]["max_pos_err_m"],
                                                          res[int(np.argmin(costs))]["report"]["max_rot_err_rad"]]}
+    ctx.close()
+    return out
+
+
+def run_schedule(iters=50):
+    """The T=300, K=256 request refined by the alternating schedule with
+    anytime validity, both precisions, beside the weighted objective."""
+    import torch
+    from paper_2309_09102_amd import cpf, synth
+    dev = torch.device("cuda:0")
+    ctx = cpf.Context(0)
+    p = _targets(ctx, synth.config2(), torch, dev)
+    out = {"mode": "schedule", "T": p.T, "K": p.K, "lm_iters": iters, "arms": {}}
+    for arm, prec, sched in (("schedule_mixed", "mixed", 1), ("schedule_fp64", "fp64", 1),
+                             ("weighted_mixed", "mixed", 0)):
+        o = cpf.make_opts(prec=prec, schedule=sched)
+        with ctx.plan(p.robot, p.targets, p.cand, opts=o) as plan:
+            plan.dp_search()
+            plan.lm_refine(1)                          # warm-up
+        with ctx.plan(p.robot, p.targets, p.cand, opts=o) as plan:
+            plan.dp_search()
+            ctx.profile(True)
+            t0 = time.perf_counter()
+            _, rep = plan.lm_refine(iters, want_xi=False)
+            t1 = time.perf_counter()
+            lm_ms = ctx.kernel_stats("lm")[0]
+            ctx.profile(False)
+        a = {"latency_ms": (t1 - t0) * 1e3, "lm_kernel_ms": lm_ms,
+             "waypoint_lm_iters_per_s": p.T * iters / (lm_ms * 1e-3),
+             "final_pose_err": [rep["max_pos_err_m"], rep["max_rot_err_rad"]],
+             "final_mjac": rep["mjac"]}
+        if sched:
+            a.update({k: rep[k] for k in ("n_valid", "first_valid", "pose_steps", "diff_steps",
+                                          "valid_length")})
+        out["arms"][arm] = a
     ctx.close()
     return out
 
@@ -225,7 +263,7 @@ def run_serve(duration_s=10.0, rate_hz=200.0, pool=48, iters=30, slots=256, ipt=
 if __name__ == "__main__":
     import argparse
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["batch64", "T1000_K512", "batchopt", "serve"])
+    ap.add_argument("mode", choices=["batch64", "T1000_K512", "batchopt", "schedule", "serve"])
     ap.add_argument("--duration", type=float, default=10.0)
     a = ap.parse_args()
     if a.mode == "batch64":
@@ -234,5 +272,7 @@ if __name__ == "__main__":
         print(json.dumps(run_precision()))
     elif a.mode == "batchopt":
         print(json.dumps(run_batchopt()))
+    elif a.mode == "schedule":
+        print(json.dumps(run_schedule()))
     else:
         print(json.dumps(run_serve(duration_s=a.duration)))

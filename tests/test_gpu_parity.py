@@ -231,17 +231,10 @@ def test_batchopt_matches_oracle(ctx, prec):
     idx, res = ctx.batchopt(p.robot, p.targets, cand, 6, opts=cpf.make_opts(iters=50, prec=prec))
     idx_ref, ref = oracle.batchopt(p.robot, cand, p.targets, 6, 50)
     assert idx == idx_ref
-    # Raw candidates (not searched; some are branch-offset, cost 0.2 - 3.6
-    # after the iterations) descend slowly along the weakly determined
-    # self-motion direction, which FP32 residual rounding steers: the mixed
-    # arm settles about 9e-6 m / 4.2e-6 relative cost from the FP64 optimum
-    # on this case and stays there at 200 iterations, while the FP64 arm
-    # agrees to 1e-11.  The mixed arm is held to that floor with a 2x margin.
-    pos_tol, cost_tol = (POS_TOL, COST_TOL) if prec == "fp64" else (2e-5, 1e-5)
     for r, rr in zip(res, ref):
         assert r["status"] == 0 and np.all(r["path"] == 0)
         ep, er, ec = H.parity_metrics(p, r["xi"], rr["xi"])
-        assert ep <= pos_tol and er <= ROT_TOL and ec <= cost_tol, (ep, er, ec)
+        assert ep <= POS_TOL and er <= ROT_TOL and ec <= COST_TOL, (ep, er, ec)
 
 
 def test_batchopt_rejects_bad_m(ctx):

@@ -127,7 +127,7 @@ def test_schedule_resumable_bitwise(ctx):
     _, xb, rb, vb = _gpu(ctx, p, 30, "mixed", chunks=[7, 0, 11, 12])
     assert np.array_equal(xa, xb) and np.array_equal(va, vb)
     assert {k: ra[k] for k in COUNTS} == {k: rb[k] for k in COUNTS}
-    assert ra["cost"] == rb["cost"] and ra["lam_diff"] == rb["lam_diff"]
+    assert ra["cost"] == rb["cost"] and ra["lam"] == rb["lam"]
 
 
 @pytest.mark.parametrize("T", [1, 2, 3])
