@@ -192,6 +192,27 @@ cpf_status cpf_fk_batch(cpf_ctx *ctx, const cpf_robot *robot, int64_t M, int32_t
 cpf_status cpf_dp_search(cpf_plan *plan, int32_t *path_out, double *best_out,
                          double *mjac_out);
 
+/* Seed mjac above which the paper generates more candidate plans and
+ * searches again (12 degrees, Sec. III-B); compare with cpf_dp_search's
+ * mjac_out. */
+#define CPF_RESEARCH_MJAC_RAD 0.20943951023931953
+
+/* Append K_add candidate plans to a plan, for a repeated search over K +
+ * K_add candidates (Sec. III-B: more plans when the seed's mjac exceeds 12
+ * degrees; Sec. III-C: when refinement finds no valid trajectory).
+ * cand_add [K_add][T][dof] FP64 as in cpf_plan_init; node_pen_add [T][K_add]
+ * or NULL (zero cost for the new nodes; nodes of a plan created without
+ * node_pen cost zero).  Kept on the device, not uploaded again: the earlier
+ * candidates and node costs and, once the plan has been searched, their
+ * penalties and search lists, which are merged with the new predecessors
+ * only; the following cpf_dp_search then runs the stage recursion alone.  The plan must be searched again before
+ * cpf_lm_refine (CPF_E_STATE otherwise); its LM state restarts from the new
+ * search.  CPF_E_UNSUPPORTED if K + K_add exceeds 1024, CPF_E_NOMEM if the
+ * larger arena does not fit the budget (the plan is then unchanged).
+ * Synchronous. */
+cpf_status cpf_plan_append(cpf_plan *plan, int32_t K_add, const double *cand_add,
+                           const double *node_pen_add);
+
 /* Run `iters` LM iterations from the plan's current trajectory (the clamped
  * search seed the first time; resumable).  xi_out [T][dof] or NULL.
  * Sec. III-C.  Synchronous. */

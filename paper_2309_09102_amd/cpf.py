@@ -25,6 +25,7 @@ OK, PENDING = 0, 1
 E_ARG, E_NOMEM, E_DEVICE, E_STATE, E_NOTFOUND, E_NUMERIC, E_UNSUPPORTED = -1, -2, -3, -4, -5, -6, -7
 F32, F64 = 0, 1
 MIXED, FP64 = 0, 1
+RESEARCH_MJAC_RAD = 0.20943951023931953   # CPF_RESEARCH_MJAC_RAD: 12 degrees
 _NAMES = {0: "OK", 1: "PENDING", -1: "E_ARG", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_STATE",
           -5: "E_NOTFOUND", -6: "E_NUMERIC", -7: "E_UNSUPPORTED"}
 
@@ -87,6 +88,7 @@ _lib.cpf_fk_batch.argtypes = [_vp, C.POINTER(cpf_robot), C.c_int64, C.c_int32, _
 _lib.cpf_dp_search.argtypes = [_vp, _ip, _dp, _dp]
 _lib.cpf_lm_refine.argtypes = [_vp, C.c_int32, _dp, C.POINTER(cpf_lm_report)]
 _lib.cpf_lm_latest_valid.argtypes = [_vp, _dp]
+_lib.cpf_plan_append.argtypes = [_vp, C.c_int32, _dp, _dp]
 _lib.cpf_solve_batch.argtypes = [_vp, C.c_int32, C.POINTER(cpf_robot), C.POINTER(cpf_problem),
                                  C.POINTER(cpf_opts), C.POINTER(cpf_result)]
 _lib.cpf_batchopt.argtypes = [_vp, C.POINTER(cpf_robot), C.POINTER(cpf_problem), C.POINTER(cpf_opts),
@@ -99,14 +101,14 @@ _lib.cpf_ctx_profile.argtypes = [_vp, C.c_int32]
 _lib.cpf_ctx_kernel_stats.argtypes = [_vp, C.c_char_p, C.POINTER(C.c_double),
                                       C.POINTER(C.c_int64)]
 for _f in ("cpf_ctx_create", "cpf_plan_init", "cpf_fk_batch", "cpf_dp_search", "cpf_lm_refine",
-           "cpf_lm_latest_valid",
+           "cpf_lm_latest_valid", "cpf_plan_append",
            "cpf_solve_batch", "cpf_batchopt", "cpf_submit", "cpf_poll", "cpf_ctx_profile",
            "cpf_ctx_kernel_stats", "cpf_ctx_config"):
     getattr(_lib, _f).restype = C.c_int
 
 EXPORTS = ("cpf_opts_default", "cpf_last_error", "cpf_ctx_create", "cpf_ctx_destroy",
            "cpf_ctx_bytes_in_use", "cpf_plan_init", "cpf_plan_free", "cpf_fk_batch",
-           "cpf_dp_search", "cpf_lm_refine", "cpf_lm_latest_valid", "cpf_solve_batch",
+           "cpf_dp_search", "cpf_plan_append", "cpf_lm_refine", "cpf_lm_latest_valid", "cpf_solve_batch",
            "cpf_batchopt", "cpf_submit",
            "cpf_poll", "cpf_ctx_profile", "cpf_ctx_kernel_stats", "cpf_ctx_config")
 
@@ -244,6 +246,17 @@ def lm_refine(plan, iters: int, T: int, want_xi: bool = True):
     if st != OK:
         raise CpfError(st, last_error())
     return xi, _report(rep)
+
+
+def plan_append(plan, T: int, cand_add, node_pen_add=None):
+    """Append candidates [K_add][T][7] (and their node costs [T][K_add])."""
+    cd = _f64(cand_add)
+    if cd.ndim != 3 or cd.shape[1] != T or cd.shape[2] != 7:
+        raise ValueError(f"cand_add must be [K_add][{T}][7], got {cd.shape}")
+    npen = None if node_pen_add is None else _f64(node_pen_add)
+    if npen is not None and npen.shape != (T, cd.shape[0]):
+        raise ValueError(f"node_pen_add must be [{T}][{cd.shape[0]}], got {npen.shape}")
+    _check(_lib.cpf_plan_append(plan, int(cd.shape[0]), _ptr(cd), _ptr(npen)))
 
 
 def lm_latest_valid(plan, T: int):
@@ -405,6 +418,9 @@ class Plan:
 
     def latest_valid(self):
         return lm_latest_valid(self.h, self.T)
+
+    def append(self, cand_add, node_pen_add=None):
+        plan_append(self.h, self.T, cand_add, node_pen_add)
 
     def free(self):
         if self.h:

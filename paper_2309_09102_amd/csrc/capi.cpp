@@ -297,27 +297,45 @@ static void fill_desc(cpf_plan *p, bool has_extra) {
     set_dev_ptr(D.xv, b + L.xv);
 }
 
-cpf_status plan_create(cpf_ctx *ctx, const HostRobot &hr, const cpf_problem *prob,
-                       const cpf_opts *opts, int32_t iters_target, hipStream_t s, cpf_plan **out) {
-    const bool has_extra = prob->node_pen != nullptr;
-    const uint64_t cls = plan_class_bytes(prob->T, prob->K, has_extra);
+// A plan of T waypoints and K candidates with an arena from the pool, its
+// descriptor and initial LM state uploaded on s; no problem data yet.
+cpf_status plan_alloc(cpf_ctx *ctx, const HostRobot &hr, int T, int K, bool has_extra, const cpf_opts *opts,
+                      int32_t iters_target, hipStream_t s, cpf_plan **out) {
+    const uint64_t cls = plan_class_bytes(T, K, has_extra);
     void *mem = nullptr;
     cpf_status st = arena_get(ctx, cls, &mem);
     if (st != CPF_OK) return st;
     std::unique_ptr<cpf_plan> p(new cpf_plan());
     p->ctx = ctx;
-    p->T = prob->T;
-    p->K = prob->K;
+    p->T = T;
+    p->K = K;
     p->robot = hr;
     p->opts = *opts;
     p->bytes = cls;
-    p->L = make_layout(p->T, p->K, has_extra);
+    p->L = make_layout(T, K, has_extra);
     p->arena = (char *)mem;
     p->d_desc = (DevPlan *)(p->arena + p->L.total);
     fill_desc(p.get(), has_extra);
     p->init.lambda = opts->lambda0;
     p->init.nu = 2.0;
     p->init.iters_target = iters_target;
+    hipError_t e = hipMemcpyAsync(p->arena + p->L.st, &p->init, sizeof(LMState), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->d_desc, &p->desc, sizeof(DevPlan), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) {
+        HIP_IGNORE(hipStreamSynchronize(s));
+        arena_put(ctx, mem, cls);
+        return fail(CPF_E_DEVICE, "upload failed: %s", hipGetErrorString(e));
+    }
+    *out = p.release();
+    return CPF_OK;
+}
+
+cpf_status plan_create(cpf_ctx *ctx, const HostRobot &hr, const cpf_problem *prob,
+                       const cpf_opts *opts, int32_t iters_target, hipStream_t s, cpf_plan **out) {
+    const bool has_extra = prob->node_pen != nullptr;
+    cpf_plan *p = nullptr;
+    cpf_status st = plan_alloc(ctx, hr, prob->T, prob->K, has_extra, opts, iters_target, s, &p);
+    if (st != CPF_OK) return st;
 
     // The caller's arrays go up as they are; a kernel converts them into the
     // device layout (candidates to float, joint-major; targets component-major).
@@ -333,16 +351,12 @@ cpf_status plan_create(cpf_ctx *ctx, const HostRobot &hr, const cpf_problem *pro
     if (e == hipSuccess && has_extra)
         e = hipMemcpyAsync(p->arena + p->L.extra, prob->node_pen, (size_t)T * K * sizeof(double),
                            hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(p->arena + p->L.st, &p->init, sizeof(LMState), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(p->d_desc, &p->desc, sizeof(DevPlan), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) {
         HIP_IGNORE(hipStreamSynchronize(s));
-        arena_put(ctx, mem, cls);
+        plan_destroy(p);
         return fail(CPF_E_DEVICE, "upload failed: %s", hipGetErrorString(e));
     }
-    *out = p.release();
+    *out = p;
     return CPF_OK;
 }
 
@@ -513,13 +527,93 @@ cpf_status cpf_dp_search(cpf_plan *plan, int32_t *path_out, double *best_out, do
     cpf_ctx *ctx = plan->ctx;
     HIP_TRY(hipSetDevice(ctx->device));
     HIP_TRY(timed(ctx, KIND_DP, ctx->stream,
-                  [&] { return dp_launch(plan->d_desc, 1, plan->K, plan->T, ctx->stream); }));
+                  [&] { return dp_launch(plan->d_desc, 1, plan->K, plan->T, plan->lists_valid, ctx->stream); }));
     PlanReadback rb;
     cpf_status st = read_plan(plan, ctx->stream, nullptr, &rb, nullptr, path_out, nullptr);
     if (st != CPF_OK) return st;
     plan->searched = true;
+    plan->lists_valid = true;
     if (best_out) *best_out = rb.dp_out[0];
     if (mjac_out) *mjac_out = rb.dp_out[1];
+    return CPF_OK;
+}
+
+cpf_status cpf_plan_append(cpf_plan *plan, int32_t K_add, const double *cand_add, const double *node_pen_add) {
+    if (!plan || !cand_add) return fail(CPF_E_ARG, "plan / cand_add is NULL");
+    if (K_add < 1) return fail(CPF_E_ARG, "K_add=%d must be >= 1", K_add);
+    const int T = plan->T, K0 = plan->K, K2 = K0 + K_add;
+    if (K2 > MAX_K) return fail(CPF_E_UNSUPPORTED, "K=%d + %d exceeds %d", K0, K_add, MAX_K);
+    if (!all_finite(cand_add, (size_t)K_add * T * NJ)) return fail(CPF_E_ARG, "cand_add not finite");
+    if (node_pen_add)
+        for (size_t i = 0; i < (size_t)T * K_add; ++i)
+            if (!(std::fabs(node_pen_add[i]) <= 1e30))
+                return fail(CPF_E_ARG, "node_pen_add must be finite with |value| <= 1e30");
+    cpf_ctx *ctx = plan->ctx;
+    hipStream_t s = ctx->stream;
+    HIP_TRY(hipSetDevice(ctx->device));
+    const bool old_extra = plan->desc.has_extra != 0;
+    const bool has_extra = old_extra || node_pen_add != nullptr;
+    // A plan searched before has current penalties and lists to merge into;
+    // otherwise the next search computes them for all candidates.
+    const bool merge = plan->lists_valid;
+    cpf_plan *np = nullptr;
+    cpf_status st = plan_alloc(ctx, plan->robot, T, K2, has_extra, &plan->opts, plan->init.iters_target, s, &np);
+    if (st != CPF_OK) return st;
+    char *a2 = np->arena;
+    const char *a1 = plan->arena;
+    const Layout &L1 = plan->L, &L2 = np->L;
+    // 1. the new candidates go up through the raw region and are converted
+    //    into columns K0.. of the new candidate array
+    hipError_t e = hipMemcpyAsync(a2 + L2.raw, cand_add, (size_t)K_add * T * NJ * sizeof(double),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = stage_append_launch((const double *)(a2 + L2.raw), T, K_add, K2, K0, (float *)(a2 + L2.cand), s);
+    // 2. kept on the device: candidates, node costs, penalties, predecessor
+    //    lists and targets (the lists overwrite the raw region, in stream order)
+    auto cols = [&](size_t off2, size_t off1, size_t elem, int rows) {
+        if (e == hipSuccess)
+            e = hipMemcpy2DAsync(a2 + off2, (size_t)K2 * elem, a1 + off1, (size_t)K0 * elem, (size_t)K0 * elem,
+                                 (size_t)rows, hipMemcpyDeviceToDevice, s);
+    };
+    cols(L2.cand, L1.cand, sizeof(float), T * NJ);
+    if (merge) {
+        cols(L2.pen, L1.pen, sizeof(double), T);
+        cols(L2.topk, L1.topk, TOPM * sizeof(uint16_t), T);
+        cols(L2.topc, L1.topc, TOPM * sizeof(double), T);
+    }
+    if (has_extra) {
+        if (old_extra) cols(L2.extra, L1.extra, sizeof(double), T);
+        else if (e == hipSuccess)
+            e = hipMemset2DAsync(a2 + L2.extra, (size_t)K2 * sizeof(double), 0, (size_t)K0 * sizeof(double), T, s);
+        if (e == hipSuccess && node_pen_add)
+            e = hipMemcpy2DAsync(a2 + L2.extra + (size_t)K0 * sizeof(double), (size_t)K2 * sizeof(double),
+                                 node_pen_add, (size_t)K_add * sizeof(double), (size_t)K_add * sizeof(double),
+                                 (size_t)T, hipMemcpyHostToDevice, s);
+        else if (e == hipSuccess)
+            e = hipMemset2DAsync(a2 + L2.extra + (size_t)K0 * sizeof(double), (size_t)K2 * sizeof(double), 0,
+                                 (size_t)K_add * sizeof(double), T, s);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(a2 + L2.targets, a1 + L1.targets, (size_t)12 * T * sizeof(double),
+                           hipMemcpyDeviceToDevice, s);
+    // 3. penalties and lists of the new nodes; the old nodes' lists merged
+    if (e == hipSuccess && merge) e = dp_append_launch(np->d_desc, K0, K2, T, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        HIP_IGNORE(hipStreamSynchronize(s));
+        plan_destroy(np);
+        return fail(CPF_E_DEVICE, "append: %s", hipGetErrorString(e));
+    }
+    // The caller's handle takes the new arena; the old one returns to the pool.
+    std::swap(plan->arena, np->arena);
+    std::swap(plan->L, np->L);
+    std::swap(plan->bytes, np->bytes);
+    std::swap(plan->desc, np->desc);
+    std::swap(plan->d_desc, np->d_desc);
+    std::swap(plan->K, np->K);
+    plan_destroy(np);
+    plan->searched = false;
+    plan->lists_valid = merge;
     return CPF_OK;
 }
 
@@ -598,7 +692,7 @@ cpf_status cpf_solve_batch(cpf_ctx *ctx, int32_t nplans, const cpf_robot *robots
     const int64_t t0 = now_ns();
     if (e == hipSuccess)
         e = timed(ctx, KIND_DP, ctx->stream,
-                  [&] { return dp_launch(d_descs, nplans, maxK, maxT, ctx->stream); });
+                  [&] { return dp_launch(d_descs, nplans, maxK, maxT, false, ctx->stream); });
     if (e == hipSuccess)
         e = timed(ctx, KIND_LM, ctx->stream,
                   [&] { return lm_launch(d_descs, nplans, o.prec, o.schedule, o.iters, ctx->stream); });

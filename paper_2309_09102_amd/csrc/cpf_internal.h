@@ -21,12 +21,20 @@ hipError_t fk_batch_launch(const HostRobot &hr, int64_t M, int prec, const void 
 // targets [T][12], doubles) into the device layout (cand float [T][7][K],
 // targets [12][T]).
 hipError_t stage_launch(const double *raw, int T, int K, float *cand, double *targets, hipStream_t s);
+// Appended candidates raw [K_add][T][7] doubles into columns k_off .. of the
+// float [T][7][K] candidate array.
+hipError_t stage_append_launch(const double *raw, int T, int K_add, int K, int k_off, float *cand,
+                               hipStream_t s);
 // mjac of every candidate plan (max over steps and joints of the change
 // between consecutive waypoints), cand float [T][7][K] -> out double [K].
 hipError_t cand_mjac_launch(const float *cand, int T, int K, double *out, hipStream_t s);
 // Search + seed gather for nplans plans: the predecessor lists over the
-// whole GPU, then one workgroup per plan for the stages.
-hipError_t dp_launch(const DevPlan *d_plans, int nplans, int maxK, int maxT, hipStream_t s);
+// whole GPU (unless lists_ready: the plans' lists are current), then one
+// workgroup per plan for the stages.
+hipError_t dp_launch(const DevPlan *d_plans, int nplans, int maxK, int maxT, bool lists_ready, hipStream_t s);
+// Penalties and predecessor lists of one plan after candidates K_old..K-1
+// were appended (the old nodes' penalties and lists already copied in).
+hipError_t dp_append_launch(const DevPlan *d_plan, int K_old, int K, int T, hipStream_t s);
 // Up to `iters` LM iterations for each plan of precision prec (0 = mixed,
 // 1 = FP64); empty slots (T = 0) and plans of the other precision are skipped.
 hipError_t lm_launch(const DevPlan *d_plans, int nplans, int prec, int sched, int iters, hipStream_t s);

@@ -61,6 +61,37 @@ __device__ __forceinline__ double node_penalty(const DevPlan &P, const double q[
     return (near ? P.penalty : 0.0) + ex;
 }
 
+// Sorted insertion into a TOPM list ordered by (e, k').  Callers offer k' in
+// ascending order among equal e, so a tie on e never displaces an earlier k'.
+__device__ __forceinline__ void list_insert(double le[TOPM], int li[TOPM], double e, int kp) {
+    if (e < le[TOPM - 1]) {
+#pragma unroll
+        for (int m = TOPM - 1; m > 0; --m) {
+            const bool shift = e < le[m - 1];
+            const bool here = !shift && e < le[m];
+            le[m] = shift ? le[m - 1] : (here ? e : le[m]);
+            li[m] = shift ? li[m - 1] : (here ? kp : li[m]);
+        }
+        if (e < le[0]) {
+            le[0] = e;
+            li[0] = kp;
+        }
+    }
+}
+
+__device__ __forceinline__ void store_list(const DevPlan &P, size_t node, const double le[TOPM],
+                                           const int li[TOPM], double pen) {
+    CPF_GLOBAL uint4 *ix = (CPF_GLOBAL uint4 *)(P.topk + node * TOPM);
+    uint32_t pk[TOPM / 2];
+#pragma unroll
+    for (int m = 0; m < TOPM / 2; ++m) pk[m] = (uint32_t)li[2 * m] | ((uint32_t)li[2 * m + 1] << 16);
+    ix[0] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+    ix[1] = make_uint4(pk[4], pk[5], pk[6], pk[7]);
+    CPF_GLOBAL double2 *cv = (CPF_GLOBAL double2 *)(P.topc + node * TOPM);
+#pragma unroll
+    for (int m = 0; m < TOPM / 2; ++m) cv[m] = make_double2(le[2 * m] + pen, le[2 * m + 1] + pen);
+}
+
 // Grid: x = tile (stage t, block of TOPM_BS destinations), y = plan.
 __global__ __launch_bounds__(TOPM_BS) void dp_topm_kernel(const DevPlan *__restrict__ plans) {
     const DevPlan &P = plans[blockIdx.y];
@@ -91,34 +122,68 @@ __global__ __launch_bounds__(TOPM_BS) void dp_topm_kernel(const DevPlan *__restr
         le[m] = __builtin_inf();
         li[m] = 0;
     }
-    for (int kp = 0; kp < K; ++kp) {
-        const double e = edge(qk, qprev + kp, K);
-        if (e < le[TOPM - 1]) {   // ascending k': a tie on e never displaces an earlier k'
-#pragma unroll
-            for (int m = TOPM - 1; m > 0; --m) {
-                const bool shift = e < le[m - 1];
-                const bool here = !shift && e < le[m];
-                le[m] = shift ? le[m - 1] : (here ? e : le[m]);
-                li[m] = shift ? li[m - 1] : (here ? kp : li[m]);
-            }
-            if (e < le[0]) {
-                le[0] = e;
-                li[0] = kp;
-            }
-        }
-    }
+    for (int kp = 0; kp < K; ++kp) list_insert(le, li, edge(qk, qprev + kp, K), kp);
     // With K < TOPM the entries past K keep index 0 and an infinite edge;
     // the serial pass reads only the first min(K, TOPM).
+    store_list(P, (size_t)t * K + k, le, li, pen);
+}
+
+// After candidates K_old..K-1 were appended to a plan (Sec. III-B's
+// re-search with more candidate plans), with the first K_old candidates'
+// penalties and lists already copied into the plan's layout: penalties and
+// full lists for the new nodes; for an old node, its list merged with the
+// new predecessors only.  The TOPM smallest (e, k') over all K predecessors
+// are among the old list and the new predecessors, and offering the old
+// list in its order and then the new k' ascending keeps the (e, k') order of
+// equal edges, so the merged list equals the list computed from scratch.
+// The old entries' edges are recomputed (the stored c = e + pen is rounded).
+__global__ __launch_bounds__(TOPM_BS) void dp_topm_append_kernel(const DevPlan *__restrict__ plans, int K_old) {
+    const DevPlan &P = plans[blockIdx.y];
+    const int T = P.T, K = P.K;
+    if (T <= 0 || K <= 0) return;
+    const int nkb = (K + TOPM_BS - 1) / TOPM_BS;
+    const int t = blockIdx.x / nkb, kb = blockIdx.x % nkb;
+    if (t >= T) return;
+    extern __shared__ float qprev[];   // [7][K]: candidates of stage t-1
+    const CPF_GLOBAL float *__restrict__ cand = P.cand;
+    if (t > 0) {
+        for (int x = threadIdx.x; x < NJ * K; x += TOPM_BS)
+            qprev[x] = cand[(size_t)(t - 1) * NJ * K + x];
+    }
+    __syncthreads();
+    const int k = kb * TOPM_BS + threadIdx.x;
+    if (k >= K) return;
+    double qk[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) qk[j] = (double)cand[((size_t)t * NJ + j) * K + k];
     const size_t node = (size_t)t * K + k;
-    CPF_GLOBAL uint4 *ix = (CPF_GLOBAL uint4 *)(P.topk + node * TOPM);
-    uint32_t pk[TOPM / 2];
+    const bool old = k < K_old;
+    double pen;
+    if (old) {
+        pen = P.pen[node];   // kept from the first search
+    } else {
+        pen = node_penalty(P, qk, t, k);
+        P.pen[node] = pen;
+    }
+    if (t == 0) return;
+    double le[TOPM];
+    int li[TOPM];
 #pragma unroll
-    for (int m = 0; m < TOPM / 2; ++m) pk[m] = (uint32_t)li[2 * m] | ((uint32_t)li[2 * m + 1] << 16);
-    ix[0] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
-    ix[1] = make_uint4(pk[4], pk[5], pk[6], pk[7]);
-    CPF_GLOBAL double2 *cv = (CPF_GLOBAL double2 *)(P.topc + node * TOPM);
-#pragma unroll
-    for (int m = 0; m < TOPM / 2; ++m) cv[m] = make_double2(le[2 * m] + pen, le[2 * m + 1] + pen);
+    for (int m = 0; m < TOPM; ++m) {
+        le[m] = __builtin_inf();
+        li[m] = 0;
+    }
+    int kp0 = 0;
+    if (old) {
+        const int n_old = K_old < TOPM ? K_old : TOPM;
+        for (int m = 0; m < n_old; ++m) {
+            const int kp = P.topk[node * TOPM + m];
+            list_insert(le, li, edge(qk, qprev + kp, K), kp);
+        }
+        kp0 = K_old;
+    }
+    for (int kp = kp0; kp < K; ++kp) list_insert(le, li, edge(qk, qprev + kp, K), kp);
+    store_list(P, node, le, li, pen);
 }
 
 // One stage's list of a destination, in registers.
@@ -335,14 +400,16 @@ __global__ __launch_bounds__(BS) void dp_kernel(const DevPlan *__restrict__ plan
     }
 }
 
-hipError_t dp_launch(const DevPlan *d_plans, int nplans, int maxK, int maxT, hipStream_t s) {
+hipError_t dp_launch(const DevPlan *d_plans, int nplans, int maxK, int maxT, bool lists_ready, hipStream_t s) {
     if (nplans <= 0 || maxT <= 0 || maxK <= 0) return hipSuccess;
     if (maxK > MAX_K) return hipErrorInvalidValue;
-    const int nkb = (maxK + TOPM_BS - 1) / TOPM_BS;
-    const dim3 grid((unsigned)(maxT * nkb), (unsigned)nplans);
-    hipLaunchKernelGGL(dp_topm_kernel, grid, dim3(TOPM_BS), (size_t)maxK * NJ * sizeof(float), s, d_plans);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (!lists_ready) {
+        const int nkb = (maxK + TOPM_BS - 1) / TOPM_BS;
+        const dim3 grid((unsigned)(maxT * nkb), (unsigned)nplans);
+        hipLaunchKernelGGL(dp_topm_kernel, grid, dim3(TOPM_BS), (size_t)maxK * NJ * sizeof(float), s, d_plans);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     // one lane per destination, whole wavefronts (the seed reduction needs a power of two)
     int bs = 64;
     while (bs < maxK) bs <<= 1;
@@ -350,6 +417,15 @@ hipError_t dp_launch(const DevPlan *d_plans, int nplans, int maxK, int maxT, hip
         hipLaunchKernelGGL((dp_kernel<512, 2>), dim3(nplans), dim3(bs), 0, s, d_plans);
     else
         hipLaunchKernelGGL((dp_kernel<1024, 1>), dim3(nplans), dim3(bs), 0, s, d_plans);
+    return hipGetLastError();
+}
+
+hipError_t dp_append_launch(const DevPlan *d_plan, int K_old, int K, int T, hipStream_t s) {
+    if (T <= 0 || K <= 0) return hipSuccess;
+    if (K > MAX_K || K_old < 0 || K_old > K) return hipErrorInvalidValue;
+    const int nkb = (K + TOPM_BS - 1) / TOPM_BS;
+    hipLaunchKernelGGL(dp_topm_append_kernel, dim3((unsigned)(T * nkb), 1), dim3(TOPM_BS),
+                       (size_t)K * NJ * sizeof(float), s, d_plan, K_old);
     return hipGetLastError();
 }
 

@@ -86,6 +86,28 @@ __global__ __launch_bounds__(256) void stage_kernel(const double *__restrict__ r
     }
 }
 
+// Appended candidates: raw [K_add][T][7] doubles into columns
+// k_off .. k_off + K_add - 1 of the float [T][7][K] candidate array.
+__global__ __launch_bounds__(256) void stage_append_kernel(const double *__restrict__ raw, int T, int K_add,
+                                                           int K, int k_off, float *__restrict__ cand) {
+    const long long x = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (x >= (long long)T * K_add) return;
+    const int t = (int)(x / K_add), k = (int)(x % K_add);
+    const double *q = raw + ((size_t)k * T + t) * NJ;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) cand[((size_t)t * NJ + j) * K + k_off + k] = (float)q[j];
+}
+
+hipError_t stage_append_launch(const double *raw, int T, int K_add, int K, int k_off, float *cand,
+                               hipStream_t s) {
+    const long long n = (long long)T * K_add;
+    if (n <= 0) return hipSuccess;
+    if (k_off < 0 || k_off + K_add > K) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(stage_append_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, raw, T, K_add,
+                       K, k_off, cand);
+    return hipGetLastError();
+}
+
 hipError_t stage_launch(const double *raw, int T, int K, float *cand, double *targets, hipStream_t s) {
     const long long n = (long long)T * K + T;
     if (n <= 0) return hipSuccess;

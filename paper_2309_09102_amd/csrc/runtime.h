@@ -111,6 +111,7 @@ struct cpf_plan {
     cpf::DevPlan *d_desc = nullptr;
     cpf::LMState init{};  // host source of the initial LM state upload
     bool searched = false;
+    bool lists_valid = false;   // the search's predecessor lists are current
 };
 
 namespace cpf {
@@ -148,6 +149,8 @@ void copy_parallel(void *dst, const void *src, size_t bytes);
 // Take an arena and upload one plan on stream s (asynchronous: the caller's
 // arrays in `prob` must stay alive until s is synchronised).  iters_target =
 // 0 lets each lm_refine call run the iterations it asks for.
+cpf_status plan_alloc(cpf_ctx *ctx, const HostRobot &hr, int T, int K, bool has_extra, const cpf_opts *opts,
+                      int32_t iters_target, hipStream_t s, cpf_plan **out);
 cpf_status plan_create(cpf_ctx *ctx, const HostRobot &hr, const cpf_problem *prob,
                        const cpf_opts *opts, int32_t iters_target, hipStream_t s, cpf_plan **out);
 void plan_destroy(cpf_plan *p);

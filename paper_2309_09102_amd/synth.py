@@ -135,6 +135,27 @@ def make_problem(robot: Robot, seed: int, T: int, K: int, sigma: float,
                    branch_frac=float(nb) / K)
 
 
+def more_candidates(prob: Problem, K_add: int, batch: int = 1) -> np.ndarray:
+    """K_add further candidate plans [K_add][T][n] around the same path q*,
+    drawn like the problem's own (same sigma and branch-offset fraction) from
+    an independent stream per batch (the stand-in for asking the candidate
+    generator for more plans)."""
+    if K_add < 1:
+        raise ValueError("K_add must be >= 1")
+    rb = prob.robot
+    n = rb.dof
+    rng = np.random.default_rng([prob.seed, 2, batch])
+    cand = prob.q_star[None, :, :] + rng.normal(0.0, prob.sigma, (K_add, prob.T, n))
+    nb = int(round(prob.branch_frac * K_add))
+    sel = rng.permutation(K_add)[:nb]
+    signs = rng.choice(np.array([-1.0, 1.0]), (nb, len(BRANCH_JOINTS)))
+    joints = [j for j in BRANCH_JOINTS if j < n]
+    for r, k in enumerate(sel):
+        for c_i, j in enumerate(joints):
+            cand[k, :, j] += signs[r, c_i] * (math.pi / 2)
+    return np.ascontiguousarray(np.clip(_f32(cand), rb.q_lo[None, None, :], rb.q_hi[None, None, :]))
+
+
 # ---- the five measured configurations ---------------------------------------
 
 def config1() -> Problem:
