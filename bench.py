@@ -52,7 +52,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--iters", type=int, default=50)
     ap.add_argument("--workload", default="T300_K256",
-                    choices=["T300_K256", "T1000_K512", "batch64", "batchopt", "schedule", "serve"],
+                    choices=["T300_K256", "T1000_K512", "batch64", "batchopt", "schedule", "research",
+                             "serve"],
                     help="T300_K256: the headline single-request line; the others are the "
                          "additional measured workloads in paper_2309_09102_amd/workloads.py")
     ap.add_argument("--duration", type=float, default=10.0, help="serve: stream length (s)")
@@ -127,6 +128,8 @@ def main():
             out = workloads.run_batchopt()
         elif args.workload == "schedule":
             out = workloads.run_schedule()
+        elif args.workload == "research":
+            out = workloads.run_research()
         else:
             out = workloads.run_serve(duration_s=args.duration)
         print(json.dumps(out))

@@ -597,7 +597,8 @@ cpf_status cpf_plan_append(cpf_plan *plan, int32_t K_add, const double *cand_add
         e = hipMemcpyAsync(a2 + L2.targets, a1 + L1.targets, (size_t)12 * T * sizeof(double),
                            hipMemcpyDeviceToDevice, s);
     // 3. penalties and lists of the new nodes; the old nodes' lists merged
-    if (e == hipSuccess && merge) e = dp_append_launch(np->d_desc, K0, K2, T, s);
+    if (e == hipSuccess && merge)
+        e = timed(ctx, KIND_DP, s, [&] { return dp_append_launch(np->d_desc, K0, K2, T, s); });
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         HIP_IGNORE(hipStreamSynchronize(s));

@@ -27,11 +27,13 @@
 //     only tie on value, and then loses on (e, k') because its e >= e_M >=
 //     the best entry's edge (an equal e comes with a larger k', since the
 //     list keeps the earliest k' of equal edges).  So lb >= best value proves
-//     the list result exact; otherwise the lane falls back to the full scan
-//     over all K predecessors.  Either way the answer equals the exhaustive
-//     minimum, bit for bit.  A stage costs one LDS gather of TOPM values per
-//     lane and one workgroup barrier; the lists of later stages are loaded
-//     ahead.
+//     the list result exact; otherwise the node gets the full scan over all
+//     K predecessors, done by a whole wavefront (the nodes needing one are
+//     shared out among the wavefronts after the stage's barrier).  Either
+//     way the answer equals the exhaustive minimum, bit for bit.  A stage
+//     costs one LDS gather of TOPM values per lane and one workgroup barrier
+//     (two more when a full scan is needed); the lists of later stages are
+//     loaded ahead.
 #include <float.h>
 
 #include "cpf_device.h"
@@ -187,21 +189,14 @@ __global__ __launch_bounds__(TOPM_BS) void dp_topm_append_kernel(const DevPlan *
 }
 
 // One stage's list of a destination, in registers.
-// The destination's own candidate and penalty ride along for the rare full
-// scan, so that scan issues no per-lane memory loads of its own.
 struct StageList {
     uint4 ix0, ix1;       // TOPM packed 16-bit predecessor indices
     double c[TOPM];       // their edges plus the destination's penalty
-    float q[NJ];          // the destination's candidate
-    double pen;           // its penalty
 };
 
 __device__ __forceinline__ void load_list(const DevPlan &P, int t, int k, StageList &L) {
     const int K = P.K;
     const size_t node = (size_t)t * K + k;
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) L.q[j] = P.cand[((size_t)t * NJ + j) * K + k];
-    L.pen = P.pen[node];
     const CPF_GLOBAL uint4 *ix = (const CPF_GLOBAL uint4 *)(P.topk + node * TOPM);
     L.ix0 = ix[0];
     L.ix1 = ix[1];
@@ -257,6 +252,8 @@ __global__ __launch_bounds__(BS) void dp_kernel(const DevPlan *__restrict__ plan
     if (T <= 0 || K <= 0) return;
     __shared__ double Bb[2][MAX_K];          // B_{t-1} and B_t (ping-pong)
     __shared__ double wmin[2][BS / 64];   // per-wave minima of each buffer
+    __shared__ unsigned long long fmask[2][BS / 64];   // lanes whose list proved nothing
+    __shared__ int ftag[2];   // = t when a lane of stage t needs a full scan (never cleared)
     __shared__ double red[BS];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -278,12 +275,60 @@ __global__ __launch_bounds__(BS) void dp_kernel(const DevPlan *__restrict__ plan
         return r;
     };
 
-    double beta = publish(0, owner ? P.pen[k] : 0.0);   // B_0 = pen_0
+    if (tid < 2) ftag[tid] = -1;
+    double beta = publish(0, owner ? P.pen[k] : 0.0);   // B_0 = pen_0 (the barrier orders ftag too)
+
+    // Full scans of stage t for the nodes whose list could not prove their
+    // minimum (fmask[cur]), one wavefront per node: lane l takes the
+    // predecessors l, l + 64, ..., keeping the smallest (value, e, k') in
+    // ascending k', then the wavefront reduces under the same key, which is
+    // the serial scan's result.  Returns the new stage minimum.
+    auto full_scans = [&](int t, int cur, int prv) -> double {
+        const CPF_GLOBAL float *qp = cand + (size_t)(t - 1) * NJ * K;
+        int i = 0;
+        for (int w = 0; w < nwave; ++w) {
+            unsigned long long m = fmask[cur][w];
+            while (m) {
+                const int node = w * 64 + __builtin_ctzll(m);
+                m &= m - 1;
+                if (i++ % nwave != wave) continue;
+                double qk[NJ];
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) qk[j] = (double)cand[((size_t)t * NJ + j) * K + node];
+                const double pen = P.pen[(size_t)t * K + node];
+                double bv = __builtin_inf(), be = __builtin_inf();
+                int bk = 0x7fffffff;
+                for (int kp = lane; kp < K; kp += 64) {
+                    const double e = edge(qk, qp + kp, K);
+                    const double vv = fmax(Bb[prv][kp], e + pen);
+                    const bool upd = (vv < bv) | ((vv == bv) & (e < be));
+                    bv = upd ? vv : bv;
+                    be = upd ? e : be;
+                    bk = upd ? kp : bk;
+                }
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+                    const double ov = __shfl_xor(bv, off), oe = __shfl_xor(be, off);
+                    const int ok = __shfl_xor(bk, off);
+                    const bool take = (ov < bv) | ((ov == bv) & ((oe < be) | ((oe == be) & (ok < bk))));
+                    bv = take ? ov : bv;
+                    be = take ? oe : be;
+                    bk = take ? ok : bk;
+                }
+                if (lane == 0) {
+                    Bb[cur][node] = bv;
+                    bp[(size_t)t * K + node] = (uint16_t)(bk < K ? bk : 0);
+                }
+            }
+        }
+        __syncthreads();
+        return publish(cur, owner ? Bb[cur][k] : 0.0);
+    };
 
     // One stage: the best of the list in `L`, the exactness check and, when
-    // it fails, the full scan; then `L` is refilled with the list AHEAD
-    // stages on (clamped to a valid node, so every lane loads and no branch
-    // separates the loads from their use).
+    // it fails anywhere, the cooperative full scans; `L` is refilled with the
+    // list AHEAD stages on (clamped to a valid node, so every lane loads and
+    // no branch separates the loads from their use).
     const int kc = owner ? k : K - 1;
     auto stage = [&](int t, StageList &L) {
         const int cur = t & 1, prv = cur ^ 1;
@@ -303,27 +348,15 @@ __global__ __launch_bounds__(BS) void dp_kernel(const DevPlan *__restrict__ plan
 #pragma unroll
         for (int m = 1; m < TOPM; ++m) cM = m < meff ? L.c[m] : cM;
         const bool exact = (meff == K) || (fmax(beta, cM) >= bv);
-        if (owner && !exact) {   // full scan over every predecessor
-            const double pen = L.pen;
-            double qk[NJ];
-#pragma unroll
-            for (int j = 0; j < NJ; ++j) qk[j] = (double)L.q[j];
-            const CPF_GLOBAL float *qp = cand + (size_t)(t - 1) * NJ * K;
-            bv = __builtin_inf();
-            double be = __builtin_inf();
-            bk = -1;
-            for (int kp = 0; kp < K; ++kp) {
-                const double e = edge(qk, qp + kp, K);
-                const double vv = fmax(Bb[prv][kp], e + pen);
-                const bool upd = (vv < bv) | ((vv == bv) & (e < be));
-                bv = upd ? vv : bv;
-                be = upd ? e : be;
-                bk = upd ? kp : bk;
-            }
+        const unsigned long long need = __ballot(owner && !exact);
+        if (lane == 0) {
+            fmask[cur][wave] = need;
+            if (need) ftag[cur] = t;
         }
-        if (owner) bp[(size_t)t * K + k] = (uint16_t)(bk >= 0 ? bk : 0);
+        if (owner && exact) bp[(size_t)t * K + k] = (uint16_t)(bk >= 0 ? bk : 0);
         load_list(P, min(t + AHEAD, T - 1), kc, L);
-        beta = publish(cur, bv);
+        beta = publish(cur, bv);   // its barrier also publishes fmask[cur] and ftag[cur]
+        if (ftag[cur] == t) beta = full_scans(t, cur, prv);
     };
 
     // lists of the next AHEAD stages, in flight; buffer a serves the stages

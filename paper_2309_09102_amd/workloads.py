@@ -11,6 +11,8 @@
   schedule   the T=300, K=256 request refined for 50 iterations by the
              alternating schedule with anytime validity (both precisions),
              beside the weighted objective.
+  research   the T=300, K=256 request searched, 256 more candidates appended
+             and the search repeated, against a fresh plan over all 512.
   serve      Poisson arrivals (200 requests/s) of requests with T ~ U{50..2000},
              K in {128, 256, 512}, sigma ~ U[0.02, 0.15], offset fraction
              ~ U[0, 0.3] and 30 LM iterations, served by cpf_submit/cpf_poll
@@ -155,6 +157,55 @@ def run_schedule(iters=50):
     return out
 
 
+def run_research(K_add=256, reps=5):
+    """The T=300, K=256 request searched, then K_add more candidates
+    appended and the search repeated (Sec. III-B), against a fresh plan over
+    all K + K_add candidates searched from scratch."""
+    import torch
+    from paper_2309_09102_amd import cpf, synth
+    dev = torch.device("cuda:0")
+    ctx = cpf.Context(0)
+    p = _targets(ctx, synth.config2(), torch, dev)
+    extra = synth.more_candidates(p, K_add)
+    allc = np.concatenate([p.cand, extra])
+    out = {"mode": "research", "T": p.T, "K": p.K, "K_add": K_add, "reps": reps}
+    app, fresh, app_dev, fresh_dev, mj = [], [], [], [], []
+    for r in range(reps + 1):
+        with ctx.plan(p.robot, p.targets, p.cand) as plan:
+            plan.dp_search()
+            ctx.profile(True)
+            t0 = time.perf_counter()
+            plan.append(extra)
+            _, best_a, mj_a = plan.dp_search()
+            t1 = time.perf_counter()
+            dev_a = ctx.kernel_stats("dp")[0]
+            ctx.profile(False)
+        ctx.profile(True)
+        t2 = time.perf_counter()
+        with ctx.plan(p.robot, p.targets, allc) as plan:
+            _, best_f, _ = plan.dp_search()
+        t3 = time.perf_counter()
+        dev_f = ctx.kernel_stats("dp")[0]
+        ctx.profile(False)
+        assert best_a == best_f
+        if r:   # the first round warms up
+            app.append(t1 - t0)
+            fresh.append(t3 - t2)
+            app_dev.append(dev_a)
+            fresh_dev.append(dev_f)
+            mj.append(mj_a)
+    out.update({"append_and_research_ms": 1e3 * float(np.median(app)),
+                "fresh_plan_and_search_ms": 1e3 * float(np.median(fresh)),
+                "append_device_ms": float(np.median(app_dev)),
+                "fresh_search_device_ms": float(np.median(fresh_dev)),
+                "seed_mjac_before_after": [None, float(mj[0])]})
+    with ctx.plan(p.robot, p.targets, p.cand) as plan:
+        _, _, mj0 = plan.dp_search()
+    out["seed_mjac_before_after"][0] = float(mj0)
+    ctx.close()
+    return out
+
+
 def _pct(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if xs else None
 
@@ -263,7 +314,7 @@ def run_serve(duration_s=10.0, rate_hz=200.0, pool=48, iters=30, slots=256, ipt=
 if __name__ == "__main__":
     import argparse
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["batch64", "T1000_K512", "batchopt", "schedule", "serve"])
+    ap.add_argument("mode", choices=["batch64", "T1000_K512", "batchopt", "schedule", "research", "serve"])
     ap.add_argument("--duration", type=float, default=10.0)
     a = ap.parse_args()
     if a.mode == "batch64":
@@ -274,5 +325,7 @@ if __name__ == "__main__":
         print(json.dumps(run_batchopt()))
     elif a.mode == "schedule":
         print(json.dumps(run_schedule()))
+    elif a.mode == "research":
+        print(json.dumps(run_research()))
     else:
         print(json.dumps(run_serve(duration_s=a.duration)))
