@@ -26,11 +26,18 @@ Parity status per function (what pins it, in tests/test_oracle_pins.py):
   lm_schedule     single steps equal lm() with the other weight zero; the
                   latest valid trajectory meets the thresholds under FK; its
                   length vs numpy; the first check on a valid seed passes
+  seg_seg,        the two distance QPs vs closed forms (parallel, crossing,
+  seg_box         skew, touching) and vs scipy's bounded minimiser
+  coll_eval       capsule endpoints vs FK of the truncated chains, distances vs
+                  scipy, gradients vs central differences; adjacent links
+                  never checked; the search penalty vs brute force
 """
 from .oracle import (build, lib_path, fk, log_so3, cost, dp, mjac, btd_solve,
                      lm_step, lm, lm_schedule, plan, batchopt, pose_compare,
-                     DEFAULT_LM, VALID_TOL)
+                     seg_seg, seg_box, coll_eval, coll_spec,
+                     DEFAULT_LM, VALID_TOL, COLL_MARGIN, COLL_WEIGHT, COLL_PENALTY)
 
 __all__ = ["build", "lib_path", "fk", "log_so3", "cost", "dp", "mjac",
            "btd_solve", "lm_step", "lm", "lm_schedule", "plan", "batchopt", "pose_compare",
-           "DEFAULT_LM", "VALID_TOL"]
+           "seg_seg", "seg_box", "coll_eval", "coll_spec",
+           "DEFAULT_LM", "VALID_TOL", "COLL_MARGIN", "COLL_WEIGHT", "COLL_PENALTY"]

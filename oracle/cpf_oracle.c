@@ -178,9 +178,41 @@ static double rot_angle(const double *A, const double *B) {
 /* Residual and cost (Sec. III-C, residual figure)                           */
 /* ------------------------------------------------------------------------ */
 
+/* ------------------------------------------------------------------------ */
+/* Collision geometry (Sec. II collision avoidance; Sec. III-C robot-robot   */
+/* and robot-environment distances)                                          */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * A capsule on every link: a segment between two points fixed in the frame
+ * after link i, and a radius.  Obstacles are cuboids: a frame (origin, then
+ * the rotation row-major, its columns the cuboid's axes) and the corners
+ * p_min, p_max in that frame.  Flat description (NULL: no geometry):
+ *   spec[0] margin m of the residual max(0, m - d), spec[1] weight w_c of the
+ *   collision residuals, spec[2] search penalty of a colliding configuration,
+ *   spec[3] number of obstacles n_obs, then n x 7 capsule values
+ *   (p0 xyz, p1 xyz, radius), then n_obs x 18 obstacle values
+ *   (origin xyz, R row-major, p_min xyz, p_max xyz).
+ */
+typedef struct {
+    double margin, w_c, penalty;
+    int nobs;
+    const double *caps, *obs;
+} or_coll;
+
+static void coll_parse(int n, const double *spec, or_coll *c) {
+    c->margin = spec[0];
+    c->w_c = spec[1];
+    c->penalty = spec[2];
+    c->nobs = (int)spec[3];
+    c->caps = spec + 4;
+    c->obs = spec + 4 + 7 * n;
+}
+
 typedef struct {
     int n;
     const double *a, *d, *alpha, *theta_off, *lo, *hi;
+    const or_coll *coll;   /* NULL: no collision geometry */
 } or_robot;
 
 /* r[6] = [p(q) - p*; Log(R(q) R*^T)] for one waypoint; J6 optional (6 x n). */
@@ -200,11 +232,270 @@ static void pose_residual(const or_robot *rb, const double *q, const double *tar
     or_log_so3(E, r + 3);
 }
 
-/* C(xi) = w_p/2 sum_t |r_t|^2 + w_s/2 sum_{t<T-1} |xi_{t+1} - xi_t|^2 (xi is [T][n]). */
+/*
+ * Squared distance of the segments p(s) = P0 + s (P1 - P0) and
+ * q(t) = Q0 + t (Q1 - Q0), s, t in [0, 1] (the robot-robot QP of Sec.
+ * III-C).  f(s, t) = |r + s d1 - t d2|^2 is convex, so its minimum over the
+ * square is the interior stationary point (when it exists and lies inside)
+ * or the smallest of the four edge minima, each a clamped 1-D quadratic.
+ * Candidates are compared in the order interior, s = 0, s = 1, t = 0, t = 1;
+ * the first of equal values wins.
+ */
+static double seg_seg(const double P0[3], const double P1[3], const double Q0[3], const double Q1[3],
+                      double *s_out, double *t_out) {
+    double d1[3], d2[3], r[3];
+    for (int k = 0; k < 3; ++k) {
+        d1[k] = P1[k] - P0[k];
+        d2[k] = Q1[k] - Q0[k];
+        r[k] = P0[k] - Q0[k];
+    }
+    double a = 0, b = 0, e = 0, c = 0, f = 0;
+    for (int k = 0; k < 3; ++k) {
+        a += d1[k] * d1[k];
+        b += d1[k] * d2[k];
+        e += d2[k] * d2[k];
+        c += d1[k] * r[k];
+        f += d2[k] * r[k];
+    }
+    double cs[5], ct[5];
+    int nc = 0;
+    double det = a * e - b * b;
+    if (det > 1e-12 * a * e && det > 0.0) {
+        double s = (b * f - c * e) / det, t = (a * f - b * c) / det;
+        if (s >= 0.0 && s <= 1.0 && t >= 0.0 && t <= 1.0) { cs[nc] = s; ct[nc] = t; ++nc; }
+    }
+    for (int side = 0; side < 2; ++side) {          /* s fixed */
+        double s = side, t = e > 0.0 ? (b * s + f) / e : 0.0;
+        t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+        cs[nc] = s; ct[nc] = t; ++nc;
+    }
+    for (int side = 0; side < 2; ++side) {          /* t fixed */
+        double t = side, s = a > 0.0 ? (b * t - c) / a : 0.0;
+        s = s < 0.0 ? 0.0 : (s > 1.0 ? 1.0 : s);
+        cs[nc] = s; ct[nc] = t; ++nc;
+    }
+    double best = INFINITY;
+    for (int i = 0; i < nc; ++i) {
+        double v = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            double w = r[k] + cs[i] * d1[k] - ct[i] * d2[k];
+            v += w * w;
+        }
+        if (v < best) { best = v; *s_out = cs[i]; *t_out = ct[i]; }
+    }
+    return best;
+}
+
+/* Squared distance from x to the interval [lo, hi] (one axis of a cuboid). */
+static double axis_gap2(double x, double lo, double hi) {
+    if (x < lo) return (lo - x) * (lo - x);
+    if (x > hi) return (x - hi) * (x - hi);
+    return 0.0;
+}
+
+/*
+ * Squared distance of the segment x(s) = A + s D (cuboid frame) to the box
+ * [pmin, pmax] (the robot-environment QP of Sec. III-C, minimised over the
+ * box point in closed form).  f(s) = sum_k gap_k(x_k(s))^2 is convex and
+ * quadratic between the points where some x_k crosses pmin_k or pmax_k, so
+ * its minimum is at an end of such a piece or at the vertex of the piece's
+ * quadratic.  All those candidates are evaluated; the first smallest wins.
+ */
+static double seg_box(const double A[3], const double D[3], const double pmin[3], const double pmax[3],
+                      double *s_out) {
+    double br[8];
+    int nb = 0;
+    br[nb++] = 0.0;
+    br[nb++] = 1.0;
+    for (int k = 0; k < 3; ++k) {
+        if (D[k] == 0.0) continue;
+        double sa = (pmin[k] - A[k]) / D[k], sb = (pmax[k] - A[k]) / D[k];
+        if (sa > 0.0 && sa < 1.0 && nb < 8) br[nb++] = sa;
+        if (sb > 0.0 && sb < 1.0 && nb < 8) br[nb++] = sb;
+    }
+    for (int i = 1; i < nb; ++i)   /* insertion sort */
+        for (int j = i; j > 0 && br[j] < br[j - 1]; --j) { double tmp = br[j]; br[j] = br[j - 1]; br[j - 1] = tmp; }
+    double cand[16];
+    int nc = 0;
+    for (int i = 0; i < nb; ++i) cand[nc++] = br[i];
+    for (int i = 0; i + 1 < nb; ++i) {
+        double mid = 0.5 * (br[i] + br[i + 1]);
+        /* the piece's quadratic: sum over axes outside the box at mid */
+        double qa = 0.0, qb = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            double x = A[k] + mid * D[k];
+            double edge = x < pmin[k] ? pmin[k] : (x > pmax[k] ? pmax[k] : x);
+            if (x < pmin[k] || x > pmax[k]) {   /* (A + s D - edge)^2 */
+                qa += D[k] * D[k];
+                qb += 2.0 * D[k] * (A[k] - edge);
+            }
+        }
+        if (qa > 0.0) {
+            double v = -qb / (2.0 * qa);
+            if (v > br[i] && v < br[i + 1]) cand[nc++] = v;
+        }
+    }
+    double best = INFINITY;
+    for (int i = 0; i < nc; ++i) {
+        double v = 0.0;
+        for (int k = 0; k < 3; ++k) v += axis_gap2(A[k] + cand[i] * D[k], pmin[k], pmax[k]);
+        if (v < best) { best = v; *s_out = cand[i]; }
+    }
+    return best;
+}
+
+/* Test entry points of the two distance QPs: out = {squared distance, s, t}
+ * (t = 0 for the box; the box is given in its own frame). */
+void or_seg_seg(const double *P0, const double *P1, const double *Q0, const double *Q1, double *out) {
+    out[0] = seg_seg(P0, P1, Q0, Q1, &out[1], &out[2]);
+}
+void or_seg_box(const double *A, const double *D, const double *pmin, const double *pmax, double *out) {
+    out[0] = seg_box(A, D, pmin, pmax, &out[1]);
+    out[2] = 0.0;
+}
+
+/* Joint axes z[i], origins o[i] (before link i) and the frame F[i] after
+ * link i (3x4), for i = 0..n-1. */
+static void link_frames(const or_robot *rb, const double *q, double z[][3], double o[][3], double F[][12]) {
+    double M[12], A[12];
+    tf_identity(M);
+    for (int i = 0; i < rb->n; ++i) {
+        z[i][0] = M[2]; z[i][1] = M[6]; z[i][2] = M[10];
+        o[i][0] = M[3]; o[i][1] = M[7]; o[i][2] = M[11];
+        double th = q[i] + (rb->theta_off ? rb->theta_off[i] : 0.0);
+        dh_link(th, rb->d[i], rb->a[i], rb->alpha[i], A);
+        tf_mul(M, A, M);
+        memcpy(F[i], M, sizeof(M));
+    }
+}
+
+/* World point of a point fixed in frame F. */
+static void frame_point(const double F[12], const double p[3], double w[3]) {
+    for (int r = 0; r < 3; ++r) w[r] = F[r * 4 + 0] * p[0] + F[r * 4 + 1] * p[1] + F[r * 4 + 2] * p[2] + F[r * 4 + 3];
+}
+
+/* Gradient contribution of moving the point w, carried by link `lnk`:
+ * g[k] += sgn * u . (z_k x (w - o_k)) for the joints k <= lnk. */
+static void point_grad(const double z[][3], const double o[][3], int lnk, const double w[3], const double u[3],
+                       double sgn, double *g) {
+    for (int k = 0; k <= lnk; ++k) {
+        double v[3] = {w[0] - o[k][0], w[1] - o[k][1], w[2] - o[k][2]};
+        double c0 = z[k][1] * v[2] - z[k][2] * v[1];
+        double c1 = z[k][2] * v[0] - z[k][0] * v[2];
+        double c2 = z[k][0] * v[1] - z[k][1] * v[0];
+        g[k] += sgn * (u[0] * c0 + u[1] * c1 + u[2] * c2);
+    }
+}
+
+/*
+ * Collision distances of configuration q: dmin[0] = min over capsule pairs
+ * of links at least three apart in the chain (i, j >= i + 3; nearer links
+ * meet at the joints between them, so their checks are left out, as the
+ * paper leaves out pairs that cannot collide) of |p_i - p_j| - r_i - r_j,
+ * dmin[1] =
+ * min over capsules and cuboids of |p - box| - r, with the closest points of
+ * the QPs (the distance is the square root of the QP's optimum less the
+ * radii); +inf where nothing is checked.  grad (optional, [2][n]): the
+ * gradient of each minimum with respect to q through its closest points
+ * (the points move with their links; derivative of a minimum over the QP's
+ * variables taken at the optimum), zero where the closest points coincide.
+ */
+static void coll_eval(const or_robot *rb, const double *q, double dmin[2], double *grad) {
+    const int n = rb->n;
+    const or_coll *c = rb->coll;
+    double z[OR_MAXN][3], o[OR_MAXN][3], F[OR_MAXN][12];
+    double P0[OR_MAXN][3], P1[OR_MAXN][3];
+    link_frames(rb, q, z, o, F);
+    for (int i = 0; i < n; ++i) {
+        frame_point(F[i], c->caps + 7 * i, P0[i]);
+        frame_point(F[i], c->caps + 7 * i + 3, P1[i]);
+    }
+    dmin[0] = INFINITY;
+    dmin[1] = INFINITY;
+    if (grad) memset(grad, 0, sizeof(double) * 2 * n);
+    int bi = -1, bj = -1;
+    double bs = 0, bt = 0;
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 3; j < n; ++j) {
+            double s, t;
+            double d2 = seg_seg(P0[i], P1[i], P0[j], P1[j], &s, &t);
+            double d = sqrt(d2) - c->caps[7 * i + 6] - c->caps[7 * j + 6];
+            if (d < dmin[0]) { dmin[0] = d; bi = i; bj = j; bs = s; bt = t; }
+        }
+    if (grad && bi >= 0) {
+        double pa[3], pb[3], u[3], nrm = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            pa[k] = P0[bi][k] + bs * (P1[bi][k] - P0[bi][k]);
+            pb[k] = P0[bj][k] + bt * (P1[bj][k] - P0[bj][k]);
+            u[k] = pa[k] - pb[k];
+            nrm += u[k] * u[k];
+        }
+        nrm = sqrt(nrm);
+        if (nrm > 0.0) {
+            for (int k = 0; k < 3; ++k) u[k] /= nrm;
+            point_grad(z, o, bi, pa, u, 1.0, grad);
+            point_grad(z, o, bj, pb, u, -1.0, grad);
+        }
+    }
+    int li = -1, ob = -1;
+    double ls = 0;
+    for (int i = 0; i < n; ++i)
+        for (int m = 0; m < c->nobs; ++m) {
+            const double *B = c->obs + 18 * m, *R = B + 3;
+            double A[3], D[3];
+            for (int r = 0; r < 3; ++r) {   /* R^T (P0 - origin), R^T (P1 - P0) */
+                A[r] = R[0 * 3 + r] * (P0[i][0] - B[0]) + R[1 * 3 + r] * (P0[i][1] - B[1]) +
+                       R[2 * 3 + r] * (P0[i][2] - B[2]);
+                D[r] = R[0 * 3 + r] * (P1[i][0] - P0[i][0]) + R[1 * 3 + r] * (P1[i][1] - P0[i][1]) +
+                       R[2 * 3 + r] * (P1[i][2] - P0[i][2]);
+            }
+            double s;
+            double d2 = seg_box(A, D, B + 12, B + 15, &s);
+            double d = sqrt(d2) - c->caps[7 * i + 6];
+            if (d < dmin[1]) { dmin[1] = d; li = i; ob = m; ls = s; }
+        }
+    if (grad && li >= 0) {
+        const double *B = c->obs + 18 * ob, *R = B + 3;
+        double pa[3], x[3], pb[3], u[3], nrm = 0.0;
+        for (int k = 0; k < 3; ++k) pa[k] = P0[li][k] + ls * (P1[li][k] - P0[li][k]);
+        for (int r = 0; r < 3; ++r) {
+            double v = R[0 * 3 + r] * (pa[0] - B[0]) + R[1 * 3 + r] * (pa[1] - B[1]) + R[2 * 3 + r] * (pa[2] - B[2]);
+            x[r] = v < B[12 + r] ? B[12 + r] : (v > B[15 + r] ? B[15 + r] : v);
+        }
+        for (int k = 0; k < 3; ++k) {
+            pb[k] = B[k] + R[k * 3 + 0] * x[0] + R[k * 3 + 1] * x[1] + R[k * 3 + 2] * x[2];
+            u[k] = pa[k] - pb[k];
+            nrm += u[k] * u[k];
+        }
+        nrm = sqrt(nrm);
+        if (nrm > 0.0) {
+            for (int k = 0; k < 3; ++k) u[k] /= nrm;
+            point_grad(z, o, li, pa, u, 1.0, grad + n);
+        }
+    }
+}
+
+/* The two collision residuals of a waypoint, max(0, m - dmin), and (J
+ * optional, [2][n]) their Jacobians (minus the distance gradients where the
+ * residual is positive). */
+static void coll_residual(const or_robot *rb, const double *q, double rc[2], double *J) {
+    double dmin[2], g[2 * OR_MAXN];
+    coll_eval(rb, q, dmin, J ? g : NULL);
+    for (int h = 0; h < 2; ++h) {
+        double r = rb->coll->margin - dmin[h];
+        rc[h] = r > 0.0 ? r : 0.0;
+        if (J)
+            for (int k = 0; k < rb->n; ++k) J[h * rb->n + k] = r > 0.0 ? -g[h * rb->n + k] : 0.0;
+    }
+}
+
+/* C(xi) = w_p/2 sum_t |r_t|^2 + w_s/2 sum_{t<T-1} |xi_{t+1} - xi_t|^2
+ * + w_c/2 sum_t (r_self,t^2 + r_env,t^2) (xi is [T][n]; the collision terms
+ * only with collision geometry). */
 static double cost_of(const or_robot *rb, int T, const double *xi, const double *targets,
-                      double w_p, double w_s) {
+                      double w_p, double w_s, double w_c) {
     int n = rb->n;
-    double pose_sum = 0.0, diff_sum = 0.0;
+    double pose_sum = 0.0, diff_sum = 0.0, coll_sum = 0.0;
     for (int t = 0; t < T; ++t) {
         double r[6];
         pose_residual(rb, xi + (size_t)t * n, targets + (size_t)t * 12, r, NULL);
@@ -215,14 +506,34 @@ static double cost_of(const or_robot *rb, int T, const double *xi, const double 
             double dq = xi[(size_t)(t + 1) * n + j] - xi[(size_t)t * n + j];
             diff_sum += dq * dq;
         }
-    return 0.5 * w_p * pose_sum + 0.5 * w_s * diff_sum;
+    if (rb->coll && w_c != 0.0)
+        for (int t = 0; t < T; ++t) {
+            double rc[2];
+            coll_residual(rb, xi + (size_t)t * n, rc, NULL);
+            coll_sum += rc[0] * rc[0] + rc[1] * rc[1];
+        }
+    return 0.5 * w_p * pose_sum + 0.5 * w_s * diff_sum + 0.5 * w_c * coll_sum;
 }
 
 double or_cost(int n, const double *a, const double *d, const double *alpha,
                const double *theta_off, int T, const double *xi, const double *targets,
-               double w_p, double w_s) {
-    or_robot rb = {n, a, d, alpha, theta_off, NULL, NULL};
-    return cost_of(&rb, T, xi, targets, w_p, w_s);
+               double w_p, double w_s, const double *coll) {
+    or_coll cg;
+    or_robot rb = {n, a, d, alpha, theta_off, NULL, NULL, NULL};
+    if (coll) { coll_parse(n, coll, &cg); rb.coll = &cg; }
+    return cost_of(&rb, T, xi, targets, w_p, w_s, rb.coll ? cg.w_c : 0.0);
+}
+
+/* Collision distances of M configurations q[M][n]: out[M][2] (self, env)
+ * and optionally their gradients grad[M][2][n] (see coll_eval). */
+void or_coll_eval(int n, const double *a, const double *d, const double *alpha,
+                  const double *theta_off, const double *coll, long M, const double *q, double *out,
+                  double *grad) {
+    or_coll cg;
+    coll_parse(n, coll, &cg);
+    or_robot rb = {n, a, d, alpha, theta_off, NULL, NULL, &cg};
+    for (long m = 0; m < M; ++m)
+        coll_eval(&rb, q + (size_t)m * n, out + 2 * m, grad ? grad + (size_t)2 * n * m : NULL);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -238,6 +549,12 @@ static double node_penalty(int n, const double *q, const double *lo, const doubl
     return (near ? penalty : 0.0) + extra;
 }
 
+static double coll_pen(const or_robot *rb, const double *q) {
+    double dmin[2];
+    coll_eval(rb, q, dmin, NULL);
+    return (dmin[0] < 0.0 || dmin[1] < 0.0) ? rb->coll->penalty : 0.0;
+}
+
 /*
  * cand is [K][T][n].  B_0(k) = pen_0(k);
  * B_t(k) = min over k' of max(B_{t-1}(k'), e_t(k',k) + pen_t(k)),
@@ -249,15 +566,23 @@ static double node_penalty(int n, const double *q, const double *lo, const doubl
  */
 int or_dp(int T, int K, int n, const double *cand, const double *lo, const double *hi,
           double margin, double penalty, const double *extra, int32_t *path,
-          double *best_out, double *B_all, int32_t *bp_all) {
+          double *best_out, double *B_all, int32_t *bp_all, const double *a, const double *d,
+          const double *alpha, const double *theta_off, const double *coll) {
     if (T < 1 || K < 1 || n < 1 || n > OR_MAXN) return -1;
+    or_coll cg;
+    or_robot rb = {n, a, d, alpha, theta_off, lo, hi, NULL};
+    if (coll) { coll_parse(n, coll, &cg); rb.coll = &cg; }
+    /* a configuration in collision (some distance below zero) costs the
+     * collision penalty on top (Sec. III-B) */
+#define COLL_PEN(q) (rb.coll ? coll_pen(&rb, (q)) : 0.0)
     double *Bp = (double *)malloc(sizeof(double) * K);
     double *Bc = (double *)malloc(sizeof(double) * K);
     int32_t *bp = (int32_t *)malloc(sizeof(int32_t) * (size_t)T * K);
     if (!Bp || !Bc || !bp) { free(Bp); free(Bc); free(bp); return -1; }
 #define CAND(k, t) (cand + ((size_t)(k) * T + (t)) * n)
     for (int k = 0; k < K; ++k) {
-        Bp[k] = node_penalty(n, CAND(k, 0), lo, hi, margin, penalty, extra ? extra[k] : 0.0);
+        Bp[k] = node_penalty(n, CAND(k, 0), lo, hi, margin, penalty, extra ? extra[k] : 0.0) +
+                COLL_PEN(CAND(k, 0));
         bp[k] = -1;
     }
     if (B_all) memcpy(B_all, Bp, sizeof(double) * K);
@@ -265,7 +590,8 @@ int or_dp(int T, int K, int n, const double *cand, const double *lo, const doubl
         for (int k = 0; k < K; ++k) {
             const double *qk = CAND(k, t);
             double pen = node_penalty(n, qk, lo, hi, margin, penalty,
-                                      extra ? extra[(size_t)t * K + k] : 0.0);
+                                      extra ? extra[(size_t)t * K + k] : 0.0) +
+                         COLL_PEN(qk);
             double bv = INFINITY, be = INFINITY;
             int bk = -1;
             for (int kp = 0; kp < K; ++kp) {
@@ -293,6 +619,7 @@ int or_dp(int T, int K, int n, const double *cand, const double *lo, const doubl
     for (int t = T - 1; t > 0; --t) path[t - 1] = bp[(size_t)t * K + path[t]];
     if (bp_all) memcpy(bp_all, bp, sizeof(int32_t) * (size_t)T * K);
 #undef CAND
+#undef COLL_PEN
     free(Bp); free(Bc); free(bp);
     return 0;
 }
@@ -413,10 +740,11 @@ int or_btd_solve(int T, int n, const double *D, double w, const double *b, doubl
  * Linearise at xi ([T][n]): per waypoint A_t = w_p J_t^T J_t ([T][n][n]) and
  * gradient g_t = w_p J_t^T r_t + w_s (c_t xi_t - xi_{t-1} - xi_{t+1}), with
  * c_t the number of neighbours of t (the differencing residual's Jacobian is
- * +I on q_{t+1} and -I on q_t).
+ * +I on q_{t+1} and -I on q_t); with collision geometry also
+ * w_c sum_h (J_h^T J_h, J_h^T r_h) of the two collision residuals.
  */
 static void linearise(const or_robot *rb, int T, const double *xi, const double *targets,
-                      double w_p, double w_s, double *A, double *g) {
+                      double w_p, double w_s, double w_c, double *A, double *g) {
     int n = rb->n;
     double J6[6 * OR_MAXN], r[6];
     for (int t = 0; t < T; ++t) {
@@ -439,6 +767,15 @@ static void linearise(const or_robot *rb, int T, const double *xi, const double 
             if (t > 0) sm += q[j] - xi[(size_t)(t - 1) * n + j];
             if (t + 1 < T) sm += q[j] - xi[(size_t)(t + 1) * n + j];
             gt[j] += w_s * sm;
+        }
+        if (rb->coll && w_c != 0.0) {
+            double rc[2], Jc[2 * OR_MAXN];
+            coll_residual(rb, q, rc, Jc);
+            for (int h = 0; h < 2; ++h)
+                for (int i = 0; i < n; ++i) {
+                    for (int j = 0; j < n; ++j) At[i * n + j] += w_c * Jc[h * n + i] * Jc[h * n + j];
+                    gt[i] += w_c * Jc[h * n + i] * rc[h];
+                }
         }
     }
 }
@@ -463,8 +800,11 @@ static int lm_solve(int T, int n, const double *A, const double *g, double w_s,
  */
 int or_lm_step(int n, const double *a, const double *d, const double *alpha,
                const double *theta_off, int T, const double *xi, const double *targets,
-               double w_p, double w_s, double lambda, double *delta, double *g_out) {
-    or_robot rb = {n, a, d, alpha, theta_off, NULL, NULL};
+               double w_p, double w_s, double lambda, double *delta, double *g_out,
+               const double *coll, double w_c) {
+    or_coll cg;
+    or_robot rb = {n, a, d, alpha, theta_off, NULL, NULL, NULL};
+    if (coll) { coll_parse(n, coll, &cg); rb.coll = &cg; }
     size_t nn = (size_t)n * n;
     double *A = (double *)malloc(sizeof(double) * nn * T);
     double *g = (double *)malloc(sizeof(double) * (size_t)n * T);
@@ -472,7 +812,7 @@ int or_lm_step(int n, const double *a, const double *d, const double *alpha,
     double *rhs = (double *)malloc(sizeof(double) * (size_t)n * T);
     int rc = -2;
     if (A && g && Db && rhs) {
-        linearise(&rb, T, xi, targets, w_p, w_s, A, g);
+        linearise(&rb, T, xi, targets, w_p, w_s, w_c, A, g);
         rc = lm_solve(T, n, A, g, w_s, lambda, delta, Db, rhs);
         if (g_out) memcpy(g_out, g, sizeof(double) * (size_t)n * T);
     }
@@ -500,8 +840,12 @@ typedef struct {
 int or_lm(int n, const double *a, const double *d, const double *alpha,
           const double *theta_off, const double *lo, const double *hi, int T,
           double *xi, const double *targets, const double *opts5, int iters,
-          double *cost_hist, double *lambda_hist, int32_t *acc_hist, double *cost0_out) {
-    or_robot rb = {n, a, d, alpha, theta_off, lo, hi};
+          double *cost_hist, double *lambda_hist, int32_t *acc_hist, double *cost0_out,
+          const double *coll) {
+    or_coll cg;
+    or_robot rb = {n, a, d, alpha, theta_off, lo, hi, NULL};
+    if (coll) { coll_parse(n, coll, &cg); rb.coll = &cg; }
+    const double w_c = rb.coll ? cg.w_c : 0.0;
     or_lm_opts o = {opts5[0], opts5[1], opts5[2], opts5[3], opts5[4]};
     size_t nn = (size_t)n * n, nT = (size_t)n * T;
     double *A = (double *)malloc(sizeof(double) * nn * T);
@@ -520,11 +864,11 @@ int or_lm(int n, const double *a, const double *d, const double *alpha,
             xi[(size_t)t * n + j] = v;
         }
     double lambda = o.lambda0, nu = 2.0;
-    double C = cost_of(&rb, T, xi, targets, o.w_pose, o.w_smooth);
+    double C = cost_of(&rb, T, xi, targets, o.w_pose, o.w_smooth, w_c);
     if (cost0_out) *cost0_out = C;
     int need_lin = 1;
     for (int it = 0; it < iters; ++it) {
-        if (need_lin) linearise(&rb, T, xi, targets, o.w_pose, o.w_smooth, A, g);
+        if (need_lin) linearise(&rb, T, xi, targets, o.w_pose, o.w_smooth, w_c, A, g);
         if (lambda_hist) lambda_hist[it] = lambda;
         if (lm_solve(T, n, A, g, o.w_smooth, lambda, delta, Db, rhs) != 0) { rc = -1; break; }
         for (int t = 0; t < T; ++t)
@@ -535,7 +879,7 @@ int or_lm(int n, const double *a, const double *d, const double *alpha,
                 if (v > hi[j]) v = hi[j];
                 trial[e] = v;
             }
-        double Cn = cost_of(&rb, T, trial, targets, o.w_pose, o.w_smooth);
+        double Cn = cost_of(&rb, T, trial, targets, o.w_pose, o.w_smooth, w_c);
         double pred = 0.0;
         for (size_t e = 0; e < nT; ++e) pred += delta[e] * (lambda * delta[e] - g[e]);
         pred *= 0.5;
@@ -577,8 +921,9 @@ int or_plan(int n, const double *a, const double *d, const double *alpha,
             const double *theta_off, const double *lo, const double *hi, int T, int K,
             const double *cand, const double *targets, const double *extra, double margin,
             double penalty, const double *opts5, int iters, int32_t *path, double *best,
-            double *xi_out, double *cost_out) {
-    int rc = or_dp(T, K, n, cand, lo, hi, margin, penalty, extra, path, best, NULL, NULL);
+            double *xi_out, double *cost_out, const double *coll) {
+    int rc = or_dp(T, K, n, cand, lo, hi, margin, penalty, extra, path, best, NULL, NULL, a, d, alpha,
+                   theta_off, coll);
     if (rc) return rc;
     for (int t = 0; t < T; ++t)
         memcpy(xi_out + (size_t)t * n, cand + ((size_t)path[t] * T + t) * n, sizeof(double) * n);
@@ -586,7 +931,7 @@ int or_plan(int n, const double *a, const double *d, const double *alpha,
     if (!hist) return -2;
     double c0 = 0.0;
     rc = or_lm(n, a, d, alpha, theta_off, lo, hi, T, xi_out, targets, opts5, iters, hist, NULL,
-               NULL, &c0);
+               NULL, &c0, coll);
     if (cost_out) *cost_out = iters > 0 ? hist[iters - 1] : c0;
     free(hist);
     return rc;
@@ -621,11 +966,12 @@ void or_pose_compare(int n, const double *a, const double *d, const double *alph
  * Before every iteration, and once after the last, the current trajectory is
  * checked: position error <= tol[0] (m) and geodesic rotation error <=
  * tol[1] (rad) at every waypoint, and no joint changing by more than tol[2]
- * (rad) between consecutive waypoints (joint limits hold by clamping).  A
- * trajectory that passes is kept in xi_valid.  A trajectory whose pose
- * errors are within the thresholds then takes one LM step on the
- * differencing residual alone (w_pose = 0); any other takes one LM step on
- * the pose residual alone (w_smooth = 0).  The pose objective's damping
+ * (rad) between consecutive waypoints (joint limits hold by clamping), and
+ * with collision geometry no capsule distance below zero (Sec. II collision
+ * avoidance).  A trajectory that passes is kept in xi_valid.  A trajectory
+ * whose pose errors are within the thresholds then takes one LM step on the
+ * differencing residual, with the collision residuals (w_pose = 0); any
+ * other takes one LM step on the pose residual alone (w_smooth = w_c = 0).  The pose objective's damping
  * (lambda, nu) follows the same Nielsen rule as or_lm.  The differencing
  * step keeps the fixed damping lambda0: its objective is quadratic, so its
  * gain ratio is 1 up to clamping and the rule would only shrink lambda
@@ -640,8 +986,10 @@ void or_pose_compare(int n, const double *a, const double *d, const double *alph
 int or_lm_schedule(int n, const double *a, const double *d, const double *alpha,
                    const double *theta_off, const double *lo, const double *hi, int T, double *xi,
                    const double *targets, const double *opts5, const double *tol, int iters,
-                   double *xi_valid, double *info) {
-    or_robot rb = {n, a, d, alpha, theta_off, lo, hi};
+                   double *xi_valid, double *info, const double *coll) {
+    or_coll cg;
+    or_robot rb = {n, a, d, alpha, theta_off, lo, hi, NULL};
+    if (coll) { coll_parse(n, coll, &cg); rb.coll = &cg; }
     or_lm_opts o = {opts5[0], opts5[1], opts5[2], opts5[3], opts5[4]};
     size_t nn = (size_t)n * n, nT = (size_t)n * T;
     double *A = (double *)malloc(sizeof(double) * nn * T);
@@ -664,7 +1012,14 @@ int or_lm_schedule(int n, const double *a, const double *d, const double *alpha,
         or_pose_compare(n, a, d, alpha, theta_off, T, xi, NULL, targets, err);
         int pose_ok = err[0] <= tol[0] && err[1] <= tol[1];
         int steps_ok = or_mjac(T, n, xi) <= tol[2];
-        if (pose_ok && steps_ok) {
+        int coll_ok = 1;
+        if (rb.coll)
+            for (int t = 0; t < T; ++t) {
+                double dmin[2];
+                coll_eval(&rb, xi + (size_t)t * n, dmin, NULL);
+                if (dmin[0] < 0.0 || dmin[1] < 0.0) coll_ok = 0;
+            }
+        if (pose_ok && steps_ok && coll_ok) {
             memcpy(xi_valid, xi, sizeof(double) * nT);
             info[0] += 1;
             if (info[1] < 0) info[1] = it;
@@ -676,10 +1031,11 @@ int or_lm_schedule(int n, const double *a, const double *d, const double *alpha,
         if (it == iters) break;
         const int m = pose_ok ? 1 : 0;   /* 0: pose step, 1: differencing step */
         const double wp = m ? 0.0 : o.w_pose, ws = m ? o.w_smooth : 0.0;
+        const double wc = (m && rb.coll) ? cg.w_c : 0.0;
         const double l = m ? o.lambda0 : lam;
         info[3 + m] += 1;
-        const double C = cost_of(&rb, T, xi, targets, wp, ws);
-        linearise(&rb, T, xi, targets, wp, ws, A, g);
+        const double C = cost_of(&rb, T, xi, targets, wp, ws, wc);
+        linearise(&rb, T, xi, targets, wp, ws, wc, A, g);
         if (lm_solve(T, n, A, g, ws, l, delta, Db, rhs) != 0) { rc = -1; break; }
         for (size_t e = 0; e < nT; ++e) {
             int j = (int)(e % (size_t)n);
@@ -688,7 +1044,7 @@ int or_lm_schedule(int n, const double *a, const double *d, const double *alpha,
             if (v > hi[j]) v = hi[j];
             trial[e] = v;
         }
-        const double Cn = cost_of(&rb, T, trial, targets, wp, ws);
+        const double Cn = cost_of(&rb, T, trial, targets, wp, ws, wc);
         const int acc = Cn < C;
         if (acc) memcpy(xi, trial, sizeof(double) * nT);
         if (m == 0) {

@@ -19,6 +19,10 @@ DEFAULT_LM = dict(w_pose=1.0, w_smooth=0.1, lambda0=1e-3, lambda_min=1e-10,
                   lambda_max=1e10)
 LIMIT_MARGIN = 1.5 * np.pi / 180.0
 LIMIT_PENALTY = 10.0
+# Collision residual margin (m), weight and search penalty (Sec. III-B: 100)
+COLL_MARGIN = 0.02
+COLL_WEIGHT = 1.0
+COLL_PENALTY = 100.0
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -53,30 +57,36 @@ def _load():
         lib.or_log_so3.argtypes = [_dp, _dp]
         lib.or_log_so3.restype = None
         lib.or_cost.argtypes = [C.c_int, _dp, _dp, _dp, _dp, C.c_int, _dp, _dp,
-                                C.c_double, C.c_double]
+                                C.c_double, C.c_double, _dp]
         lib.or_cost.restype = C.c_double
         lib.or_dp.argtypes = [C.c_int, C.c_int, C.c_int, _dp, _dp, _dp, C.c_double,
-                              C.c_double, _dp, _ip, _dp, _dp, _ip]
+                              C.c_double, _dp, _ip, _dp, _dp, _ip, _dp, _dp, _dp, _dp, _dp]
         lib.or_dp.restype = C.c_int
         lib.or_mjac.argtypes = [C.c_int, C.c_int, _dp]
         lib.or_mjac.restype = C.c_double
         lib.or_btd_solve.argtypes = [C.c_int, C.c_int, _dp, C.c_double, _dp, _dp]
         lib.or_btd_solve.restype = C.c_int
         lib.or_lm_step.argtypes = [C.c_int, _dp, _dp, _dp, _dp, C.c_int, _dp, _dp,
-                                   C.c_double, C.c_double, C.c_double, _dp, _dp]
+                                   C.c_double, C.c_double, C.c_double, _dp, _dp, _dp, C.c_double]
         lib.or_lm_step.restype = C.c_int
         lib.or_lm.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, C.c_int, _dp, _dp,
-                              _dp, C.c_int, _dp, _dp, _ip, _dp]
+                              _dp, C.c_int, _dp, _dp, _ip, _dp, _dp]
         lib.or_lm.restype = C.c_int
         lib.or_plan.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, C.c_int, C.c_int,
                                 _dp, _dp, _dp, C.c_double, C.c_double, _dp, C.c_int, _ip,
-                                _dp, _dp, _dp]
+                                _dp, _dp, _dp, _dp]
         lib.or_plan.restype = C.c_int
         lib.or_pose_compare.argtypes = [C.c_int, _dp, _dp, _dp, _dp, C.c_int, _dp, _dp,
                                         _dp, _dp]
         lib.or_pose_compare.restype = None
         lib.or_lm_schedule.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, C.c_int, _dp, _dp, _dp,
-                                       _dp, C.c_int, _dp, _dp]
+                                       _dp, C.c_int, _dp, _dp, _dp]
+        lib.or_coll_eval.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _dp, C.c_long, _dp, _dp, _dp]
+        lib.or_coll_eval.restype = None
+        lib.or_seg_seg.argtypes = [_dp, _dp, _dp, _dp, _dp]
+        lib.or_seg_seg.restype = None
+        lib.or_seg_box.argtypes = [_dp, _dp, _dp, _dp, _dp]
+        lib.or_seg_box.restype = None
         lib.or_lm_schedule.restype = C.c_int
         _lib = lib
         return lib
@@ -150,18 +160,67 @@ def log_so3(R):
     return out
 
 
-def cost(robot, xi, targets, w_pose=1.0, w_smooth=0.1) -> float:
+def coll_spec(n, coll):
+    """Flat collision description for the C oracle, or None.  coll: dict with
+    capsules [n][7] (p0 xyz, p1 xyz in the frame after the link, radius),
+    obstacles [m][18] (frame origin xyz, rotation row-major, p_min xyz, p_max
+    xyz), margin, w_coll, penalty."""
+    if coll is None:
+        return None
+    caps = _d(coll["capsules"]).reshape(n, 7)
+    obs = _d(coll.get("obstacles", np.zeros((0, 18)))).reshape(-1, 18)
+    head = [coll.get("margin", COLL_MARGIN), coll.get("w_coll", COLL_WEIGHT),
+            coll.get("penalty", COLL_PENALTY), float(obs.shape[0])]
+    return _d(np.concatenate([head, caps.ravel(), obs.ravel()]))
+
+
+def seg_seg(P0, P1, Q0, Q1):
+    """Robot-robot QP: (squared distance, s, t) of two segments."""
+    lib = _load()
+    out = np.empty(3)
+    lib.or_seg_seg(_p(_d(P0)), _p(_d(P1)), _p(_d(Q0)), _p(_d(Q1)), _p(out))
+    return float(out[0]), float(out[1]), float(out[2])
+
+
+def seg_box(A, D, pmin, pmax):
+    """Robot-environment QP in the cuboid frame: (squared distance, s) of
+    the segment A + s D to the box [pmin, pmax]."""
+    lib = _load()
+    out = np.empty(3)
+    lib.or_seg_box(_p(_d(A)), _p(_d(D)), _p(_d(pmin)), _p(_d(pmax)), _p(out))
+    return float(out[0]), float(out[1])
+
+
+def coll_eval(robot, coll, q, gradient: bool = False):
+    """q [..., n] -> distances [..., 2] (self, environment) and optionally
+    their gradients [..., 2, n]."""
+    lib = _load()
+    n = robot.a.shape[0]
+    q = _d(q)
+    shape = q.shape[:-1]
+    M = int(np.prod(shape)) if shape else 1
+    a, d, al, th, _, _ = _robot(robot)
+    spec = coll_spec(n, coll)
+    out = np.empty((M, 2))
+    g = np.empty((M, 2, n)) if gradient else None
+    lib.or_coll_eval(n, _p(a), _p(d), _p(al), _p(th), _p(spec), M, _p(q), _p(out), _p(g))
+    out = out.reshape(shape + (2,))
+    return (out, g.reshape(shape + (2, n))) if gradient else out
+
+
+def cost(robot, xi, targets, w_pose=1.0, w_smooth=0.1, coll=None) -> float:
     lib = _load()
     xi = _d(xi)
     tg = _d(targets)
     T, n = xi.shape
     a, d, al, th, _, _ = _robot(robot)
+    spec = coll_spec(n, coll)
     return float(lib.or_cost(n, _p(a), _p(d), _p(al), _p(th), T, _p(xi), _p(tg),
-                             w_pose, w_smooth))
+                             w_pose, w_smooth, _p(spec)))
 
 
 def dp(cand, robot, margin=LIMIT_MARGIN, penalty=LIMIT_PENALTY, extra=None,
-       want_tables: bool = False):
+       want_tables: bool = False, coll=None):
     """cand [K][T][n] -> (path[T] int32, B*, B_all[T][K] | None, bp_all | None)."""
     lib = _load()
     cand = _d(cand)
@@ -172,8 +231,11 @@ def dp(cand, robot, margin=LIMIT_MARGIN, penalty=LIMIT_PENALTY, extra=None,
     best = np.empty(1)
     B_all = np.empty((T, K)) if want_tables else None
     bp_all = np.empty((T, K), dtype=np.int32) if want_tables else None
+    a, d, al, th, _, _ = _robot(robot)
+    spec = coll_spec(n, coll)
     rc = lib.or_dp(T, K, n, _p(cand), _p(lo), _p(hi), margin, penalty, _p(ex),
-                   _ipp(path), _p(best), _p(B_all), _ipp(bp_all))
+                   _ipp(path), _p(best), _p(B_all), _ipp(bp_all), _p(a), _p(d), _p(al), _p(th),
+                   _p(spec))
     if rc != 0:
         raise RuntimeError(f"or_dp failed ({rc})")
     return path, float(best[0]), B_all, bp_all
@@ -199,8 +261,9 @@ def btd_solve(D, w, b):
     return x
 
 
-def lm_step(robot, xi, targets, w_pose, w_smooth, lam):
-    """One damped Gauss-Newton step at xi -> (delta [T][n], g [T][n])."""
+def lm_step(robot, xi, targets, w_pose, w_smooth, lam, coll=None, w_coll=0.0):
+    """One damped Gauss-Newton step at xi -> (delta [T][n], g [T][n]); with
+    collision geometry the collision residuals enter with weight w_coll."""
     lib = _load()
     xi = _d(xi)
     tg = _d(targets)
@@ -208,8 +271,9 @@ def lm_step(robot, xi, targets, w_pose, w_smooth, lam):
     a, d, al, th, _, _ = _robot(robot)
     delta = np.empty((T, n))
     g = np.empty((T, n))
+    spec = coll_spec(n, coll)
     rc = lib.or_lm_step(n, _p(a), _p(d), _p(al), _p(th), T, _p(xi), _p(tg),
-                        w_pose, w_smooth, lam, _p(delta), _p(g))
+                        w_pose, w_smooth, lam, _p(delta), _p(g), _p(spec), float(w_coll))
     if rc != 0:
         raise np.linalg.LinAlgError(f"or_lm_step failed ({rc})")
     return delta, g
@@ -222,7 +286,7 @@ def _opts5(opts):
     return _d([o["w_pose"], o["w_smooth"], o["lambda0"], o["lambda_min"], o["lambda_max"]])
 
 
-def lm(robot, xi0, targets, iters, opts=None):
+def lm(robot, xi0, targets, iters, opts=None, coll=None):
     """LM from xi0 -> dict(xi, cost_hist, lambda_hist, accepted, cost0, rc)."""
     lib = _load()
     xi = _d(xi0).copy()
@@ -234,14 +298,15 @@ def lm(robot, xi0, targets, iters, opts=None):
     lh = np.empty(max(iters, 1))
     ah = np.empty(max(iters, 1), dtype=np.int32)
     c0 = np.empty(1)
+    spec = coll_spec(n, coll)
     rc = lib.or_lm(n, _p(a), _p(d), _p(al), _p(th), _p(lo), _p(hi), T, _p(xi), _p(tg),
-                   _p(o5), int(iters), _p(ch), _p(lh), _ipp(ah), _p(c0))
+                   _p(o5), int(iters), _p(ch), _p(lh), _ipp(ah), _p(c0), _p(spec))
     return dict(xi=xi, cost_hist=ch[:iters], lambda_hist=lh[:iters],
                 accepted=ah[:iters].astype(bool), cost0=float(c0[0]), rc=int(rc))
 
 
 def plan(robot, cand, targets, iters, opts=None, extra=None, margin=LIMIT_MARGIN,
-         penalty=LIMIT_PENALTY):
+         penalty=LIMIT_PENALTY, coll=None):
     """Search then LM -> dict(path, best, xi, cost, rc).  Releases the GIL."""
     lib = _load()
     cand = _d(cand)
@@ -254,9 +319,10 @@ def plan(robot, cand, targets, iters, opts=None, extra=None, margin=LIMIT_MARGIN
     best = np.empty(1)
     xi = np.empty((T, n))
     cst = np.empty(1)
+    spec = coll_spec(n, coll)
     rc = lib.or_plan(n, _p(a), _p(d), _p(al), _p(th), _p(lo), _p(hi), T, K, _p(cand),
                      _p(tg), _p(ex), margin, penalty, _p(o5), int(iters), _ipp(path),
-                     _p(best), _p(xi), _p(cst))
+                     _p(best), _p(xi), _p(cst), _p(spec))
     return dict(path=path, best=float(best[0]), xi=xi, cost=float(cst[0]), rc=int(rc))
 
 
@@ -265,7 +331,7 @@ def plan(robot, cand, targets, iters, opts=None, extra=None, margin=LIMIT_MARGIN
 VALID_TOL = (1e-4, np.deg2rad(0.1), np.deg2rad(7.0))
 
 
-def lm_schedule(robot, xi0, targets, iters, opts=None, tol=VALID_TOL):
+def lm_schedule(robot, xi0, targets, iters, opts=None, tol=VALID_TOL, coll=None):
     """Pose-first alternating LM with the latest-valid store (see
     or_lm_schedule).  Returns dict(xi, xi_valid | None, n_valid, first_valid,
     valid_length, pose_steps, diff_steps, rc)."""
@@ -276,8 +342,9 @@ def lm_schedule(robot, xi0, targets, iters, opts=None, tol=VALID_TOL):
     a, d, al, th, lo, hi = _robot(robot)
     xv = np.zeros((T, n))
     info = np.zeros(5)
+    spec = coll_spec(n, coll)
     rc = lib.or_lm_schedule(n, _p(a), _p(d), _p(al), _p(th), _p(lo), _p(hi), T, _p(xi), _p(tg),
-                            _p(_opts5(opts)), _p(_d(tol)), int(iters), _p(xv), _p(info))
+                            _p(_opts5(opts)), _p(_d(tol)), int(iters), _p(xv), _p(info), _p(spec))
     return dict(xi=xi, xi_valid=xv if info[0] > 0 else None, n_valid=int(info[0]),
                 first_valid=int(info[1]), valid_length=float(info[2]), pose_steps=int(info[3]),
                 diff_steps=int(info[4]), rc=int(rc))

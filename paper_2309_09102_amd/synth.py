@@ -156,6 +156,56 @@ def more_candidates(prob: Problem, K_add: int, batch: int = 1) -> np.ndarray:
     return np.ascontiguousarray(np.clip(_f32(cand), rb.q_lo[None, None, :], rb.q_hi[None, None, :]))
 
 
+def make_capsules(robot: Robot, trim: float = 0.15, radius_frac: float = 0.2,
+                  r_max: float = 0.03) -> np.ndarray:
+    """One capsule per link [n][7] (p0 xyz, p1 xyz in the frame after the
+    link, radius): the part of the segment from the link's joint to the next
+    joint that remains after cutting `trim` of its length off both ends, with
+    radius min(r_max, radius_frac x length).  In the frame after link i of a
+    standard DH chain the joint of link i sits at (-a_i, -d_i sin alpha_i,
+    -d_i cos alpha_i) and the next joint at the origin."""
+    a, d, al = robot.a, robot.d, robot.alpha
+    out = np.zeros((robot.dof, 7))
+    for i in range(robot.dof):
+        j0 = np.array([-a[i], -d[i] * math.sin(al[i]), -d[i] * math.cos(al[i])])
+        j1 = np.zeros(3)
+        L = float(np.linalg.norm(j1 - j0))
+        out[i, 0:3] = j0 + trim * (j1 - j0)
+        out[i, 3:6] = j1 - trim * (j1 - j0)
+        out[i, 6] = min(r_max, radius_frac * L)
+    return out
+
+
+def make_obstacles(seed: int, n_obs: int, r_lo: float = 0.3, r_hi: float = 0.9,
+                   ext_lo: float = 0.03, ext_hi: float = 0.12) -> np.ndarray:
+    """n_obs cuboids [n_obs][18] (frame origin xyz, rotation row-major, p_min
+    xyz, p_max xyz): origins uniform in direction at a distance U[r_lo, r_hi]
+    from the base, rotations from uniform unit quaternions, half extents
+    U[ext_lo, ext_hi] per axis, centred in their frame."""
+    rng = np.random.default_rng([seed, 3])
+    out = np.zeros((n_obs, 18))
+    for m in range(n_obs):
+        v = rng.normal(size=3)
+        out[m, 0:3] = v / np.linalg.norm(v) * rng.uniform(r_lo, r_hi)
+        w, x, y, z = (lambda u: u / np.linalg.norm(u))(rng.normal(size=4))
+        R = np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                      [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                      [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+        out[m, 3:12] = R.ravel()
+        h = rng.uniform(ext_lo, ext_hi, 3)
+        out[m, 12:15] = -h
+        out[m, 15:18] = h
+    return out
+
+
+def collision_model(robot: Robot, obstacles: np.ndarray | None = None, margin: float = 0.02,
+                    w_coll: float = 1.0, penalty: float = 100.0) -> dict:
+    """Collision description shared by the oracle and the library binding."""
+    return dict(capsules=make_capsules(robot),
+                obstacles=np.zeros((0, 18)) if obstacles is None else np.asarray(obstacles, float),
+                margin=float(margin), w_coll=float(w_coll), penalty=float(penalty))
+
+
 # ---- the five measured configurations ---------------------------------------
 
 def config1() -> Problem:

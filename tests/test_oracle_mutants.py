@@ -25,8 +25,8 @@ MUTANTS = {
                        "J[0 * n + i] = z[i][2] * dy - z[i][1] * dz;"),
     "log_vee_sign": ("double v0 = 0.5 * (R[7] - R[5]);", "double v0 = 0.5 * (R[5] - R[7]);"),
     "residual_sign": ("r[0] = pose[0] - target[0];", "r[0] = target[0] - pose[0];"),
-    "cost_weight": ("return 0.5 * w_p * pose_sum + 0.5 * w_s * diff_sum;",
-                    "return 0.5 * w_p * pose_sum + w_s * diff_sum;"),
+    "cost_weight": ("return 0.5 * w_p * pose_sum + 0.5 * w_s * diff_sum + 0.5 * w_c * coll_sum;",
+                    "return 0.5 * w_p * pose_sum + w_s * diff_sum + 0.5 * w_c * coll_sum;"),
     "grad_term_dropped": ("if (t > 0) sm += q[j] - xi[(size_t)(t - 1) * n + j];",
                           "if (t > 0) sm += 0.0;"),
     "jtj_index": ("s += J6[k * n + i] * J6[k * n + j];", "s += J6[k * n + i] * J6[k * n + i];"),
@@ -46,6 +46,19 @@ MUTANTS = {
     "sched_diff_damping_adapts": ("const double l = m ? o.lambda0 : lam;", "const double l = lam;"),
     "sched_reject_keeps_damping": ("lam *= nu;\n                nu *= 2.0;\n            }\n            if (lam < o.lambda_min)",
                                    "nu *= 2.0;\n            }\n            if (lam < o.lambda_min)"),
+    "coll_radius_dropped": ("double d = sqrt(d2) - c->caps[7 * i + 6] - c->caps[7 * j + 6];",
+                            "double d = sqrt(d2) - c->caps[7 * i + 6];"),
+    "coll_grad_sign": ("point_grad(z, o, bj, pb, u, -1.0, grad);", "point_grad(z, o, bj, pb, u, 1.0, grad);"),
+    "seg_seg_edge_sign": ("double s = side, t = e > 0.0 ? (b * s + f) / e : 0.0;",
+                          "double s = side, t = e > 0.0 ? (b * s - f) / e : 0.0;"),
+    "seg_box_upper_gap": ("if (x > hi) return (x - hi) * (x - hi);", "if (x > hi) return (x - lo) * (x - lo);"),
+    "coll_adjacent_checked": ("for (int j = i + 3; j < n; ++j) {", "for (int j = i + 2; j < n; ++j) {"),
+    "coll_penalty_dropped": ("return (dmin[0] < 0.0 || dmin[1] < 0.0) ? rb->coll->penalty : 0.0;", "return 0.0;"),
+    "coll_residual_sign": ("J[h * rb->n + k] = r > 0.0 ? -g[h * rb->n + k] : 0.0;",
+                           "J[h * rb->n + k] = r > 0.0 ? g[h * rb->n + k] : 0.0;"),
+    "box_frame_transposed": ("A[r] = R[0 * 3 + r] * (P0[i][0] - B[0]) + R[1 * 3 + r] * (P0[i][1] - B[1]) +",
+                             "A[r] = R[r * 3 + 0] * (P0[i][0] - B[0]) + R[r * 3 + 1] * (P0[i][1] - B[1]) +"),
+    "sched_collision_ignored": ("if (dmin[0] < 0.0 || dmin[1] < 0.0) coll_ok = 0;", "if (0) coll_ok = 0;"),
     "sched_length_signed": ("len += fabs(xi[(size_t)(t + 1) * n + j] - xi[(size_t)t * n + j]);",
                             "len += xi[(size_t)(t + 1) * n + j] - xi[(size_t)t * n + j];"),
 }
@@ -75,6 +88,16 @@ def battery():
         lambda: P.test_p15_schedule_latest_valid_meets_the_thresholds(),
         lambda: P.test_p15_schedule_rejects_a_discontinuous_pose_valid_trajectory(),
         lambda: P.test_p15_schedule_steps_are_single_objective_lm_steps(),
+        lambda: P.test_p16_seg_seg_closed_forms(),
+        lambda: P.test_p16_seg_seg_matches_bounded_minimiser(0),
+        lambda: P.test_p16_seg_box_closed_forms(),
+        lambda: P.test_p16_seg_box_matches_dense_sampling(0),
+        lambda: P.test_p16_distances_match_independent_evaluation(0),
+        lambda: P.test_p16_distance_gradients_match_central_differences(0),
+        lambda: P.test_p16_adjacent_links_never_checked(),
+        lambda: P.test_p16_search_penalises_colliding_nodes_brute_force(),
+        lambda: P.test_p16_lm_gradient_with_collision_matches_cost_differences(),
+        lambda: P.test_p16_schedule_rejects_a_colliding_pose_valid_trajectory(),
     ]
 
 

@@ -587,3 +587,229 @@ def test_p15_schedule_steps_are_single_objective_lm_steps():
     rb, prob, tg = _sched_case(seed=8, T=20, sigma=1.5)
     _, n_rej, longest = _replay_schedule(rb, prob.cand[0], tg, 12)
     assert n_rej >= 3 and longest >= 2
+
+
+# ---- collision distances, residuals and penalty (Sec. II, III-B, III-C) --------
+
+def test_p16_seg_seg_closed_forms():
+    # parallel segments 0.3 apart, overlapping in x: distance 0.3
+    d2, s, t = oracle.seg_seg([0, 0, 0], [1, 0, 0], [0.5, 0.3, 0], [2, 0.3, 0])
+    assert d2 == pytest.approx(0.09, abs=1e-15)
+    # crossing segments: distance 0 at the midpoints
+    d2, s, t = oracle.seg_seg([-1, 0, 0], [1, 0, 0], [0, -1, 0], [0, 1, 0])
+    assert d2 == 0.0 and s == pytest.approx(0.5) and t == pytest.approx(0.5)
+    # skew perpendicular lines 0.2 apart in z, closest points interior
+    d2, s, t = oracle.seg_seg([-1, 0, 0], [1, 0, 0], [0.25, -1, 0.2], [0.25, 1, 0.2])
+    assert d2 == pytest.approx(0.04, abs=1e-15) and s == pytest.approx(0.625) and t == pytest.approx(0.5)
+    # closest points at the ends: collinear, gap 0.5
+    d2, s, t = oracle.seg_seg([0, 0, 0], [1, 0, 0], [1.5, 0, 0], [3, 0, 0])
+    assert d2 == pytest.approx(0.25, abs=1e-15) and s == 1.0 and t == 0.0
+    # a point (zero-length segment) against a segment
+    d2, s, t = oracle.seg_seg([0.5, 0.4, 0], [0.5, 0.4, 0], [0, 0, 0], [1, 0, 0])
+    assert d2 == pytest.approx(0.16, abs=1e-15) and t == pytest.approx(0.5)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_p16_seg_seg_matches_bounded_minimiser(seed):
+    from scipy.optimize import minimize
+    rng = np.random.default_rng(seed)
+    P0, P1, Q0, Q1 = rng.uniform(-1, 1, (4, 3))
+    f = lambda x: np.sum((P0 + x[0] * (P1 - P0) - Q0 - x[1] * (Q1 - Q0)) ** 2)
+    best = min(minimize(f, x0, bounds=[(0, 1), (0, 1)], method="L-BFGS-B", tol=1e-14).fun
+               for x0 in ([0.5, 0.5], [0, 0], [1, 1], [0, 1], [1, 0]))
+    d2, s, t = oracle.seg_seg(P0, P1, Q0, Q1)
+    assert d2 == pytest.approx(best, abs=1e-10)
+    assert d2 == pytest.approx(f([s, t]), abs=1e-14) and 0 <= s <= 1 and 0 <= t <= 1
+
+
+def test_p16_seg_box_closed_forms():
+    lo, hi = np.array([-0.1, -0.2, -0.3]), np.array([0.1, 0.2, 0.3])
+    # parallel to the +x face, 0.25 outside it, spanning the face: distance 0.25
+    d2, s = oracle.seg_box([0.35, -1, 0], [0, 2, 0], lo, hi)
+    assert d2 == pytest.approx(0.0625, abs=1e-15)
+    # through the box: 0
+    d2, s = oracle.seg_box([-1, 0, 0], [2, 0, 0], lo, hi)
+    assert d2 == 0.0
+    # towards a corner, stopping short: the end point's distance to the corner
+    d2, s = oracle.seg_box([1, 1, 1], [-0.5, -0.5, -0.5], lo, hi)
+    assert s == 1.0 and d2 == pytest.approx(0.4 ** 2 + 0.3 ** 2 + 0.2 ** 2, abs=1e-15)
+    # passing an edge diagonally: closest approach at the edge x=0.1, y=0.2
+    d2, s = oracle.seg_box([0.3, -0.5, 0], [0, 2, 0], lo, hi)
+    assert d2 == pytest.approx(0.04, abs=1e-15)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_p16_seg_box_matches_dense_sampling(seed):
+    rng = np.random.default_rng(100 + seed)
+    A, D = rng.uniform(-0.6, 0.6, 3), rng.uniform(-1, 1, 3)
+    h = rng.uniform(0.05, 0.3, 3)
+    lo, hi = -h + rng.uniform(-0.1, 0.1, 3), h
+    s = np.linspace(0, 1, 200001)
+    x = A[None, :] + s[:, None] * D[None, :]
+    gap = np.maximum(lo - x, 0) + np.maximum(x - hi, 0)
+    sampled = (gap ** 2).sum(axis=1)
+    d2, sm = oracle.seg_box(A, D, lo, hi)
+    assert d2 <= sampled.min() + 1e-15                     # the QP is the true minimum
+    assert sampled.min() - d2 <= 2e-10 * (1 + np.abs(D).sum())  # and the samples approach it
+    xm = A + sm * D
+    assert d2 == pytest.approx(float(((np.maximum(lo - xm, 0) + np.maximum(xm - hi, 0)) ** 2).sum()), abs=1e-15)
+
+
+def _coll_case(robot_seed=0, n_obs=4):
+    rb = synth.make_robot(robot_seed)
+    return rb, synth.collision_model(rb, synth.make_obstacles(robot_seed, n_obs))
+
+
+def _link_frame(rb, q, i):
+    """Frame after link i from FK of the chain cut after link i."""
+    cut = synth.Robot(a=rb.a[:i + 1], d=rb.d[:i + 1], alpha=rb.alpha[:i + 1],
+                      theta_off=rb.theta_off[:i + 1], q_lo=rb.q_lo[:i + 1], q_hi=rb.q_hi[:i + 1])
+    pose = oracle.fk(cut, q[:i + 1])
+    return pose[3:12].reshape(3, 3), pose[:3]
+
+
+def test_p16_capsules_span_consecutive_joints():
+    """Untrimmed synthetic capsules run from the joint of link i (origin of
+    the frame before it) to the next joint (origin of the frame after it)."""
+    rb = synth.make_robot(1)
+    caps = synth.make_capsules(rb, trim=0.0)
+    q = np.random.default_rng(3).uniform(-1, 1, 7)
+    prev = np.zeros(3)
+    for i in range(7):
+        R, p = _link_frame(rb, q, i)
+        np.testing.assert_allclose(R @ caps[i, 0:3] + p, prev, atol=1e-12)
+        np.testing.assert_allclose(R @ caps[i, 3:6] + p, p, atol=1e-12)
+        prev = p
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_p16_distances_match_independent_evaluation(seed):
+    """Self and environment distances against capsules placed by FK of the
+    truncated chains and scipy's bounded minimiser over the QP variables."""
+    from scipy.optimize import minimize
+    rb, cm = _coll_case(seed % 2)
+    q = np.random.default_rng(seed).uniform(-2, 2, 7)
+    caps = cm["capsules"]
+    ends = []
+    for i in range(7):
+        R, p = _link_frame(rb, q, i)
+        ends.append((R @ caps[i, 0:3] + p, R @ caps[i, 3:6] + p, caps[i, 6]))
+    self_d = np.inf
+    for i in range(7):
+        for j in range(i + 3, 7):
+            (a0, a1, ra), (b0, b1, rb_) = ends[i], ends[j]
+            f = lambda x: np.sum((a0 + x[0] * (a1 - a0) - b0 - x[1] * (b1 - b0)) ** 2)
+            m = min(minimize(f, x0, bounds=[(0, 1), (0, 1)], method="L-BFGS-B", tol=1e-14).fun
+                    for x0 in ([0.5, 0.5], [0, 0], [1, 1], [0, 1], [1, 0]))
+            self_d = min(self_d, np.sqrt(max(m, 0)) - ra - rb_)
+    env_d = np.inf
+    for i in range(7):
+        a0, a1, ra = ends[i]
+        for B in cm["obstacles"]:
+            R, o = B[3:12].reshape(3, 3), B[0:3]
+            lo, hi = B[12:15], B[15:18]
+            def f(x):
+                pw = a0 + x[0] * (a1 - a0)
+                return np.sum((R @ x[1:4] + o - pw) ** 2)
+            x0s = [np.r_[s0, np.clip(R.T @ (a0 + s0 * (a1 - a0) - o), lo, hi)] for s0 in (0, 0.5, 1)]
+            m = min(minimize(f, x0, bounds=[(0, 1)] + list(zip(lo, hi)), method="L-BFGS-B",
+                             tol=1e-15).fun for x0 in x0s)
+            env_d = min(env_d, np.sqrt(max(m, 0)) - ra)
+    d = oracle.coll_eval(rb, cm, q)
+    assert d[0] == pytest.approx(self_d, abs=1e-6)
+    assert d[1] == pytest.approx(env_d, abs=1e-6)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_p16_distance_gradients_match_central_differences(seed):
+    rb, cm = _coll_case(1)
+    q = np.random.default_rng(50 + seed).uniform(-2, 2, 7)
+    d, g = oracle.coll_eval(rb, cm, q, gradient=True)
+    h = 1e-6
+    for k in range(7):
+        e = np.zeros(7)
+        e[k] = h
+        fd = (oracle.coll_eval(rb, cm, q + e) - oracle.coll_eval(rb, cm, q - e)) / (2 * h)
+        np.testing.assert_allclose(g[:, k], fd, atol=2e-6)
+
+
+def test_p16_adjacent_links_never_checked():
+    """Capsules of links fewer than three apart may overlap freely: a robot
+    whose capsules are huge spheres around each joint reports only the pairs
+    three or more apart."""
+    rb, cm = _coll_case(0, n_obs=0)
+    caps = cm["capsules"].copy()
+    caps[:, 0:6] = 0.0                 # every capsule a sphere at its frame's origin
+    caps[:, 6] = 0.01
+    caps[2, 6] = caps[3, 6] = caps[4, 6] = 5.0   # links 2, 3, 4 overlap each other hugely
+    cm2 = dict(cm, capsules=caps)
+    q = np.zeros(7)
+    d = oracle.coll_eval(rb, cm2, q)
+    frames = [_link_frame(rb, q, i)[1] for i in range(7)]
+    expect = min(np.linalg.norm(frames[i] - frames[j]) - caps[i, 6] - caps[j, 6]
+                 for i in range(7) for j in range(i + 3, 7))
+    assert d[0] == pytest.approx(expect, abs=1e-12)
+    assert np.isinf(d[1])
+
+
+def test_p16_search_penalises_colliding_nodes_brute_force():
+    """Tiny search (K=3, T=4) with collision geometry against enumeration of
+    all 81 paths, node penalty = joint-limit term + 100 if in collision."""
+    rb, cm = _coll_case(3)
+    rng = np.random.default_rng(9)
+    cand = rng.uniform(-2.0, 2.0, (3, 4, 7))
+    dist = oracle.coll_eval(rb, cm, cand)
+    coll = (dist < 0).any(axis=-1)
+    assert coll.any() and not coll.all()
+    lo, hi = rb.q_lo, rb.q_hi
+    near = ((cand <= lo + oracle.oracle.LIMIT_MARGIN) | (cand >= hi - oracle.oracle.LIMIT_MARGIN)).any(-1)
+    pen = 10.0 * near + 100.0 * coll                       # [K][T]
+    best = np.inf
+    for path in itertools.product(range(3), repeat=4):
+        v = pen[path[0], 0]
+        for t in range(1, 4):
+            e = np.abs(cand[path[t], t] - cand[path[t - 1], t - 1]).max()
+            v = max(v, e + pen[path[t], t])
+        best = min(best, v)
+    path, B, _, _ = oracle.dp(cand, rb, coll=cm)
+    assert B == best
+    _, B0, _, _ = oracle.dp(cand, rb)
+    assert B0 < B or not coll.any()
+
+
+def test_p16_lm_gradient_with_collision_matches_cost_differences():
+    rb, cm = _coll_case(3)
+    prob = synth.make_problem(rb, seed=7, T=12, K=1, sigma=0.3)
+    tg = oracle.fk(rb, prob.q_star)
+    xi = prob.cand[0]
+    cm = dict(cm, margin=0.3)                  # wide margin: residuals active
+    assert (oracle.coll_eval(rb, cm, xi) < 0.3).any()
+    _, g = oracle.lm_step(rb, xi, tg, 1.0, 0.1, 1e-3, coll=cm, w_coll=1.0)
+    h = 1e-6
+    for t, j in [(0, 0), (3, 2), (6, 4), (11, 6), (5, 1)]:
+        e = np.zeros_like(xi)
+        e[t, j] = h
+        fd = (oracle.cost(rb, xi + e, tg, coll=cm) - oracle.cost(rb, xi - e, tg, coll=cm)) / (2 * h)
+        assert g[t, j] == pytest.approx(fd, abs=1e-5, rel=1e-5)
+    # no geometry: the collision terms vanish
+    assert oracle.cost(rb, xi, tg, coll=dict(cm, w_coll=0.0)) == oracle.cost(rb, xi, tg)
+
+
+def test_p16_schedule_rejects_a_colliding_pose_valid_trajectory():
+    rb, cm = _coll_case(1)
+    prob = synth.make_problem(rb, seed=7, T=80, K=1, sigma=0.02)
+    q = prob.q_star.copy()
+    tg = oracle.fk(rb, q)
+    d = oracle.coll_eval(rb, cm, q)
+    assert (d >= 0).all() and oracle.mjac(q) <= oracle.VALID_TOL[2]
+    # a cuboid around the end effector's second waypoint makes q collide
+    box = np.zeros(18)
+    box[0:3] = tg[1, :3]
+    box[3:12] = np.eye(3).ravel()
+    box[12:15], box[15:18] = -0.02, 0.02
+    cm_hit = dict(cm, obstacles=np.vstack([cm["obstacles"], box]))
+    assert oracle.coll_eval(rb, cm_hit, q)[1, 1] < 0
+    r = oracle.lm_schedule(rb, q, tg, 0, coll=cm_hit)
+    assert r["n_valid"] == 0
+    r = oracle.lm_schedule(rb, q, tg, 0, coll=cm)
+    assert r["n_valid"] == 1
