@@ -70,11 +70,18 @@ enum { CPF_MIXED = 0, CPF_FP64 = 1 };
 typedef struct cpf_ctx cpf_ctx;
 typedef struct cpf_plan cpf_plan;
 
-/* Robot: dof rows of standard DH parameters and joint limits (host, copied). */
+/* Robot: dof rows of standard DH parameters and joint limits (host, copied).
+ * capsules [dof][7] or NULL: the collision capsule of each link (Sec. II
+ * collision avoidance): segment end points p0, p1 (xyz, metres) in the frame
+ * after the link, then the radius.  With capsules the search adds
+ * opts.coll_penalty to a configuration in collision (Sec. III-B) and the LM
+ * adds the collision residuals (Sec. III-C); pairs of links fewer than three
+ * apart in the chain are not checked. */
 typedef struct cpf_robot {
     int32_t dof;
     const double *a, *d, *alpha, *theta_off; /* theta_off may be NULL (zeros) */
     const double *q_lo, *q_hi;
+    const double *capsules;
 } cpf_robot;
 
 /* One problem (host, copied by every call that takes it).
@@ -87,6 +94,11 @@ typedef struct cpf_problem {
     const double *targets;
     const double *cand;
     const double *node_pen;
+    /* cuboid obstacles [n_obstacles][18] (used with robot capsules): frame
+     * origin xyz, rotation row-major (columns = the cuboid's axes), p_min xyz,
+     * p_max xyz in that frame (Sec. III-C); n_obstacles <= 64 */
+    int32_t n_obstacles;
+    const double *obstacles;
 } cpf_problem;
 
 /* Options (cpf_opts_default fills the defaults shown).
@@ -108,7 +120,12 @@ typedef struct cpf_problem {
  *     pose thresholds then takes an LM step on the differencing term alone
  *     (weight w_smooth), any other a step on the pose term alone (weight
  *     w_pose).  The pose steps' damping follows the gain-ratio rule; the
- *     differencing steps keep lambda0. */
+ *     differencing steps keep lambda0.
+ *   coll_margin 0.02 m, w_coll 1, coll_penalty 100 (robots with capsules):
+ *     collision residuals max(0, coll_margin - d) of the smallest self and
+ *     environment distances d of every waypoint, weight w_coll in the cost
+ *     (w_coll/2 sum r^2; in the schedule they belong to the differencing
+ *     step), and the search penalty of a configuration with d < 0. */
 typedef struct cpf_opts {
     double w_pose, w_smooth;
     double lambda0, lambda_min, lambda_max;
@@ -116,6 +133,7 @@ typedef struct cpf_opts {
     int32_t iters, prec, refine_steps;
     int32_t schedule;
     double valid_pos_m, valid_rot_rad, valid_step_rad;
+    double coll_margin, w_coll, coll_penalty;
 } cpf_opts;
 
 typedef struct cpf_lm_report {
@@ -136,6 +154,10 @@ typedef struct cpf_lm_report {
     int32_t diff_steps;      /* steps taken on the differencing objective */
     double valid_length;     /* sum over steps and joints of |change| along the
                                 latest valid trajectory */
+    double min_self_dist_m;  /* smallest capsule self distance along the result
+                                (+inf without capsules) */
+    double min_env_dist_m;   /* smallest capsule-obstacle distance (+inf
+                                without capsules or obstacles) */
 } cpf_lm_report;
 
 typedef struct cpf_result {
@@ -181,6 +203,23 @@ void cpf_plan_free(cpf_plan *plan);
  * argument errors are reported synchronously. */
 cpf_status cpf_fk_batch(cpf_ctx *ctx, const cpf_robot *robot, int64_t M, int32_t prec,
                         const void *q_dev, void *pose_dev, void *jac_dev, void *hip_stream);
+
+/* Batched collision distances (the collision checker of Sec. III-B; the
+ * distance QPs of Sec. III-C) of M configurations of a robot with capsules.
+ * Device pointers owned by the caller, SoA:
+ *   obstacles_dev [n_obstacles][18] double (layout of cpf_problem), or NULL
+ *                 when n_obstacles is 0
+ *   q_dev         [dof][M]   joint values
+ *   dist_dev      [2][M]     smallest self distance, smallest capsule-obstacle
+ *                            distance (metres; < 0 in collision; +inf when
+ *                            nothing is checked)
+ *   grad_dev      [2*dof][M] or NULL: their gradients, row h*dof + j
+ * prec selects float or double for q, dist and grad.  Asynchronous on
+ * hip_stream; only argument errors are reported synchronously
+ * (CPF_E_ARG without capsules). */
+cpf_status cpf_coll_batch(cpf_ctx *ctx, const cpf_robot *robot, int32_t n_obstacles,
+                          const double *obstacles_dev, int64_t M, int32_t prec, const void *q_dev,
+                          void *dist_dev, void *grad_dev, void *hip_stream);
 
 /* Layered-graph search (Sec. III-B): node (t, k) is candidate k at waypoint
  * t; B_0(k) = pen_0(k), B_t(k) = min_k' max(B_{t-1}(k'), e_t(k',k) +

@@ -398,8 +398,12 @@ static void point_grad(const double z[][3], const double o[][3], int lnk, const 
  * radii); +inf where nothing is checked.  grad (optional, [2][n]): the
  * gradient of each minimum with respect to q through its closest points
  * (the points move with their links; derivative of a minimum over the QP's
- * variables taken at the optimum), zero where the closest points coincide.
+ * variables taken at the optimum), zero where the closest points are less
+ * than OR_CONTACT_EPS apart (cores touching or crossing: the distance is at
+ * its floor minus the radii and the direction between the points is only
+ * rounding).
  */
+#define OR_CONTACT_EPS 1e-9
 static void coll_eval(const or_robot *rb, const double *q, double dmin[2], double *grad) {
     const int n = rb->n;
     const or_coll *c = rb->coll;
@@ -431,7 +435,7 @@ static void coll_eval(const or_robot *rb, const double *q, double dmin[2], doubl
             nrm += u[k] * u[k];
         }
         nrm = sqrt(nrm);
-        if (nrm > 0.0) {
+        if (nrm > OR_CONTACT_EPS) {
             for (int k = 0; k < 3; ++k) u[k] /= nrm;
             point_grad(z, o, bi, pa, u, 1.0, grad);
             point_grad(z, o, bj, pb, u, -1.0, grad);
@@ -468,7 +472,7 @@ static void coll_eval(const or_robot *rb, const double *q, double dmin[2], doubl
             nrm += u[k] * u[k];
         }
         nrm = sqrt(nrm);
-        if (nrm > 0.0) {
+        if (nrm > OR_CONTACT_EPS) {
             for (int k = 0; k < 3; ++k) u[k] /= nrm;
             point_grad(z, o, li, pa, u, 1.0, grad + n);
         }

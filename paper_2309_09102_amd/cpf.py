@@ -9,6 +9,7 @@ built this module raises at import; there is no fallback.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 
 import numpy as np
@@ -41,12 +42,12 @@ class CpfError(RuntimeError):
 
 class cpf_robot(C.Structure):
     _fields_ = [("dof", C.c_int32), ("a", _dp), ("d", _dp), ("alpha", _dp),
-                ("theta_off", _dp), ("q_lo", _dp), ("q_hi", _dp)]
+                ("theta_off", _dp), ("q_lo", _dp), ("q_hi", _dp), ("capsules", _dp)]
 
 
 class cpf_problem(C.Structure):
     _fields_ = [("T", C.c_int32), ("K", C.c_int32), ("targets", _dp), ("cand", _dp),
-                ("node_pen", _dp)]
+                ("node_pen", _dp), ("n_obstacles", C.c_int32), ("obstacles", _dp)]
 
 
 class cpf_opts(C.Structure):
@@ -55,7 +56,8 @@ class cpf_opts(C.Structure):
                 ("limit_margin", C.c_double), ("limit_penalty", C.c_double),
                 ("iters", C.c_int32), ("prec", C.c_int32), ("refine_steps", C.c_int32),
                 ("schedule", C.c_int32), ("valid_pos_m", C.c_double),
-                ("valid_rot_rad", C.c_double), ("valid_step_rad", C.c_double)]
+                ("valid_rot_rad", C.c_double), ("valid_step_rad", C.c_double),
+                ("coll_margin", C.c_double), ("w_coll", C.c_double), ("coll_penalty", C.c_double)]
 
 
 class cpf_lm_report(C.Structure):
@@ -64,7 +66,8 @@ class cpf_lm_report(C.Structure):
                 ("max_pos_err_m", C.c_double), ("max_rot_err_rad", C.c_double),
                 ("mjac", C.c_double), ("n_valid", C.c_int32), ("first_valid", C.c_int32),
                 ("pose_steps", C.c_int32), ("diff_steps", C.c_int32),
-                ("valid_length", C.c_double)]
+                ("valid_length", C.c_double), ("min_self_dist_m", C.c_double),
+                ("min_env_dist_m", C.c_double)]
 
 
 class cpf_result(C.Structure):
@@ -89,6 +92,8 @@ _lib.cpf_dp_search.argtypes = [_vp, _ip, _dp, _dp]
 _lib.cpf_lm_refine.argtypes = [_vp, C.c_int32, _dp, C.POINTER(cpf_lm_report)]
 _lib.cpf_lm_latest_valid.argtypes = [_vp, _dp]
 _lib.cpf_plan_append.argtypes = [_vp, C.c_int32, _dp, _dp]
+_lib.cpf_coll_batch.argtypes = [_vp, C.POINTER(cpf_robot), C.c_int32, _vp, C.c_int64, C.c_int32, _vp, _vp,
+                                _vp, _vp]
 _lib.cpf_solve_batch.argtypes = [_vp, C.c_int32, C.POINTER(cpf_robot), C.POINTER(cpf_problem),
                                  C.POINTER(cpf_opts), C.POINTER(cpf_result)]
 _lib.cpf_batchopt.argtypes = [_vp, C.POINTER(cpf_robot), C.POINTER(cpf_problem), C.POINTER(cpf_opts),
@@ -101,13 +106,13 @@ _lib.cpf_ctx_profile.argtypes = [_vp, C.c_int32]
 _lib.cpf_ctx_kernel_stats.argtypes = [_vp, C.c_char_p, C.POINTER(C.c_double),
                                       C.POINTER(C.c_int64)]
 for _f in ("cpf_ctx_create", "cpf_plan_init", "cpf_fk_batch", "cpf_dp_search", "cpf_lm_refine",
-           "cpf_lm_latest_valid", "cpf_plan_append",
+           "cpf_lm_latest_valid", "cpf_plan_append", "cpf_coll_batch",
            "cpf_solve_batch", "cpf_batchopt", "cpf_submit", "cpf_poll", "cpf_ctx_profile",
            "cpf_ctx_kernel_stats", "cpf_ctx_config"):
     getattr(_lib, _f).restype = C.c_int
 
 EXPORTS = ("cpf_opts_default", "cpf_last_error", "cpf_ctx_create", "cpf_ctx_destroy",
-           "cpf_ctx_bytes_in_use", "cpf_plan_init", "cpf_plan_free", "cpf_fk_batch",
+           "cpf_ctx_bytes_in_use", "cpf_plan_init", "cpf_plan_free", "cpf_fk_batch", "cpf_coll_batch",
            "cpf_dp_search", "cpf_plan_append", "cpf_lm_refine", "cpf_lm_latest_valid", "cpf_solve_batch",
            "cpf_batchopt", "cpf_submit",
            "cpf_poll", "cpf_ctx_profile", "cpf_ctx_kernel_stats", "cpf_ctx_config")
@@ -139,20 +144,41 @@ class _Keep:
         self.arrays = arrays
 
 
-def make_robot(robot) -> _Keep:
+def make_robot(robot, coll=None) -> _Keep:
+    """coll: collision description (dict with capsules [dof][7], obstacles
+    [n][18], margin, w_coll, penalty) or None."""
     arrs = [_f64(robot.a), _f64(robot.d), _f64(robot.alpha), _f64(robot.theta_off),
             _f64(robot.q_lo), _f64(robot.q_hi)]
-    s = cpf_robot(int(arrs[0].shape[0]), *[_ptr(a) for a in arrs])
-    return _Keep(s, arrs)
+    caps = None if coll is None else _f64(coll["capsules"])
+    s = cpf_robot(int(arrs[0].shape[0]), *[_ptr(a) for a in arrs], _ptr(caps))
+    return _Keep(s, arrs + [caps])
 
 
-def make_problem(targets, cand, node_pen=None) -> _Keep:
+def _obstacles(coll):
+    if coll is None or coll.get("obstacles") is None:
+        return None
+    ob = _f64(coll["obstacles"]).reshape(-1, 18)
+    return ob if ob.shape[0] else None
+
+
+def make_problem(targets, cand, node_pen=None, coll=None) -> _Keep:
     tg = _f64(targets)
     cd = _f64(cand)
     K, T = int(cd.shape[0]), int(cd.shape[1])
     npen = None if node_pen is None else _f64(node_pen)
-    s = cpf_problem(T, K, _ptr(tg), _ptr(cd), _ptr(npen))
-    return _Keep(s, [tg, cd, npen])
+    ob = _obstacles(coll)
+    s = cpf_problem(T, K, _ptr(tg), _ptr(cd), _ptr(npen), 0 if ob is None else int(ob.shape[0]), _ptr(ob))
+    return _Keep(s, [tg, cd, npen, ob])
+
+
+def _with_coll(opts, coll):
+    """opts with the collision margin, weight and penalty of coll."""
+    o = cpf_opts.from_buffer_copy(opts if opts is not None else opts_default())
+    if coll is not None:
+        o.coll_margin = float(coll.get("margin", o.coll_margin))
+        o.w_coll = float(coll.get("w_coll", o.w_coll))
+        o.coll_penalty = float(coll.get("penalty", o.coll_penalty))
+    return o
 
 
 def opts_default() -> cpf_opts:
@@ -170,12 +196,18 @@ def make_opts(**kw) -> cpf_opts:
     return o
 
 
+def _finite_or_none(v):
+    return v if math.isfinite(v) else None
+
+
 def _report(r: cpf_lm_report) -> dict:
     return dict(cost0=r.cost0, cost=r.cost, lam=r.lambda_, grad_inf=r.grad_inf,
                 n_accepted=r.n_accepted, iters_done=r.iters_done,
                 max_pos_err_m=r.max_pos_err_m, max_rot_err_rad=r.max_rot_err_rad, mjac=r.mjac,
                 n_valid=r.n_valid, first_valid=r.first_valid, pose_steps=r.pose_steps,
-                diff_steps=r.diff_steps, valid_length=r.valid_length)
+                diff_steps=r.diff_steps, valid_length=r.valid_length,
+                min_self_dist_m=_finite_or_none(r.min_self_dist_m),
+                min_env_dist_m=_finite_or_none(r.min_env_dist_m))
 
 
 # ---- functions with the C ABI's names ---------------------------------------
@@ -210,10 +242,10 @@ def ctx_kernel_stats(ctx, kernel: str):
     return ms.value, int(n.value)
 
 
-def plan_init(ctx, robot, targets, cand, node_pen=None, opts=None):
-    rb = make_robot(robot)
-    pb = make_problem(targets, cand, node_pen)
-    o = opts if opts is not None else opts_default()
+def plan_init(ctx, robot, targets, cand, node_pen=None, opts=None, coll=None):
+    rb = make_robot(robot, coll)
+    pb = make_problem(targets, cand, node_pen, coll)
+    o = _with_coll(opts, coll)
     h = _vp()
     _check(_lib.cpf_plan_init(ctx, C.byref(rb.struct), C.byref(pb.struct), C.byref(o), C.byref(h)))
     return h
@@ -229,6 +261,15 @@ def fk_batch(ctx, robot, M, prec, q_ptr, pose_ptr, jac_ptr=None, stream=None):
     _check(_lib.cpf_fk_batch(ctx, C.byref(rb.struct), int(M), int(prec), _vp(q_ptr),
                              _vp(pose_ptr), _vp(jac_ptr) if jac_ptr else None,
                              _vp(stream) if stream else None))
+
+
+def coll_batch(ctx, robot, coll, M, prec, q_ptr, dist_ptr, grad_ptr=None, obstacles_ptr=None, n_obstacles=0,
+               stream=None):
+    """Device pointers (ints) in the SoA layout of include/cpf.h."""
+    rb = make_robot(robot, coll)
+    _check(_lib.cpf_coll_batch(ctx, C.byref(rb.struct), int(n_obstacles), _vp(obstacles_ptr) if obstacles_ptr else None,
+                               int(M), int(prec), _vp(q_ptr), _vp(dist_ptr), _vp(grad_ptr) if grad_ptr else None,
+                               _vp(stream) if stream else None))
 
 
 def dp_search(plan, T: int):
@@ -268,14 +309,18 @@ def lm_latest_valid(plan, T: int):
 
 
 def solve_batch(ctx, problems, opts=None):
-    """problems: list of (robot, targets, cand[, node_pen]).  Returns list of dicts."""
+    """problems: list of (robot, targets, cand[, node_pen[, coll]]); the
+    collision margin, weight and penalty of the first coll apply to the whole
+    batch.  Returns list of dicts."""
     n = len(problems)
     keeps, robots, probs = [], (cpf_robot * n)(), (cpf_problem * n)()
     results = (cpf_result * n)()
     outs = []
+    first_coll = next((pr[4] for pr in problems if len(pr) > 4 and pr[4] is not None), None)
     for i, pr in enumerate(problems):
-        rb = make_robot(pr[0])
-        pb = make_problem(pr[1], pr[2], pr[3] if len(pr) > 3 else None)
+        coll = pr[4] if len(pr) > 4 else None
+        rb = make_robot(pr[0], coll)
+        pb = make_problem(pr[1], pr[2], pr[3] if len(pr) > 3 else None, coll)
         keeps += [rb, pb]
         robots[i] = rb.struct
         probs[i] = pb.struct
@@ -287,16 +332,16 @@ def solve_batch(ctx, problems, opts=None):
         results[i].xi = _ptr(xi)
         results[i].path = path.ctypes.data_as(_ip)
         results[i].xi_valid = _ptr(xv)
-    o = opts if opts is not None else opts_default()
+    o = _with_coll(opts, first_coll)
     _check(_lib.cpf_solve_batch(ctx, n, robots, probs, C.byref(o), results))
     return [_result(results[i], *outs[i]) for i in range(n)]
 
 
-def batchopt(ctx, robot, targets, cand, M: int, opts=None, node_pen=None):
+def batchopt(ctx, robot, targets, cand, M: int, opts=None, node_pen=None, coll=None):
     """The M smoothest candidates optimised directly.  Returns (indices,
     list of result dicts), in ascending candidate mjac."""
-    rb = make_robot(robot)
-    pb = make_problem(targets, cand, node_pen)
+    rb = make_robot(robot, coll)
+    pb = make_problem(targets, cand, node_pen, coll)
     T = pb.struct.T
     idx = np.empty(max(M, 0), dtype=np.int32)
     results = (cpf_result * max(M, 1))()
@@ -309,7 +354,7 @@ def batchopt(ctx, robot, targets, cand, M: int, opts=None, node_pen=None):
         results[i].xi = _ptr(xi)
         results[i].path = path.ctypes.data_as(_ip)
         results[i].xi_valid = _ptr(xv)
-    o = opts if opts is not None else opts_default()
+    o = _with_coll(opts, coll)
     _check(_lib.cpf_batchopt(ctx, C.byref(rb.struct), C.byref(pb.struct), C.byref(o), M,
                              idx.ctypes.data_as(_ip), results))
     return [int(k) for k in idx], [_result(results[i], *outs[i]) for i in range(M)]
@@ -324,10 +369,10 @@ def _result(r: cpf_result, xi, path, xv=None) -> dict:
                 t_search_done_ns=r.t_search_done_ns, t_done_ns=r.t_done_ns)
 
 
-def submit(ctx, robot, targets, cand, opts=None, node_pen=None) -> int:
-    rb = make_robot(robot)
-    pb = make_problem(targets, cand, node_pen)
-    o = opts if opts is not None else opts_default()
+def submit(ctx, robot, targets, cand, opts=None, node_pen=None, coll=None) -> int:
+    rb = make_robot(robot, coll)
+    pb = make_problem(targets, cand, node_pen, coll)
+    o = _with_coll(opts, coll)
     t = C.c_uint64()
     _check(_lib.cpf_submit(ctx, C.byref(rb.struct), C.byref(pb.struct), C.byref(o), C.byref(t)))
     return int(t.value)
@@ -377,9 +422,31 @@ class Context:
     def kernel_stats(self, kernel: str):
         return ctx_kernel_stats(self.h, kernel)
 
-    def plan(self, robot, targets, cand, node_pen=None, opts=None) -> "Plan":
-        return Plan(self, plan_init(self.h, robot, targets, cand, node_pen, opts),
+    def plan(self, robot, targets, cand, node_pen=None, opts=None, coll=None) -> "Plan":
+        return Plan(self, plan_init(self.h, robot, targets, cand, node_pen, opts, coll),
                     int(np.shape(cand)[1]))
+
+    def coll_batch(self, robot, coll, q: "torch.Tensor", want_grad: bool = False, stream=None):
+        """q: device tensor [7][M] -> (dist [2][M], grad [14][M] | None): the
+        smallest self and environment capsule distances of each configuration."""
+        assert q.is_cuda and q.dim() == 2 and q.shape[0] == 7 and q.is_contiguous()
+        prec = F64 if q.dtype == torch.float64 else F32
+        M = q.shape[1]
+        ob = _obstacles(coll)
+        obt = None if ob is None else torch.tensor(ob, dtype=torch.float64, device=q.device)
+        dist = torch.empty((2, M), dtype=q.dtype, device=q.device)
+        grad = torch.empty((14, M), dtype=q.dtype, device=q.device) if want_grad else None
+        s = stream if stream is not None else torch.cuda.current_stream(q.device).cuda_stream
+        if obt is not None and stream is not None:
+            torch.cuda.current_stream(q.device).synchronize()   # the obstacle upload is on torch's stream
+        coll_batch(self.h, robot, coll, M, prec, q.data_ptr(), dist.data_ptr(),
+                   grad.data_ptr() if grad is not None else None,
+                   obt.data_ptr() if obt is not None else None, 0 if ob is None else ob.shape[0], s)
+        if obt is not None and stream is not None:
+            # the obstacle copy is freed by torch's allocator in the order of
+            # its own stream; tell it about the kernel's stream
+            obt.record_stream(torch.cuda.ExternalStream(stream))
+        return dist, grad
 
     def fk_batch(self, robot, q: "torch.Tensor", want_jac: bool = False, stream=None):
         """q: device tensor [7][M] (float32 or float64) -> (pose [12][M], J [42][M] | None)."""
@@ -396,11 +463,11 @@ class Context:
     def solve_batch(self, problems, opts=None):
         return solve_batch(self.h, problems, opts)
 
-    def batchopt(self, robot, targets, cand, M: int, opts=None, node_pen=None):
-        return batchopt(self.h, robot, targets, cand, M, opts, node_pen)
+    def batchopt(self, robot, targets, cand, M: int, opts=None, node_pen=None, coll=None):
+        return batchopt(self.h, robot, targets, cand, M, opts, node_pen, coll)
 
-    def submit(self, robot, targets, cand, opts=None, node_pen=None) -> int:
-        return submit(self.h, robot, targets, cand, opts, node_pen)
+    def submit(self, robot, targets, cand, opts=None, node_pen=None, coll=None) -> int:
+        return submit(self.h, robot, targets, cand, opts, node_pen, coll)
 
     def poll(self, ticket: int, T: int, timeout_ms: int = -1):
         return poll(self.h, ticket, T, timeout_ms)

@@ -39,7 +39,7 @@ int64_t now_ns() {
         .count();
 }
 
-Layout make_layout(int T, int K, bool extra) {
+Layout make_layout(int T, int K, bool extra, int n_obs, bool coll) {
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -68,16 +68,18 @@ Layout make_layout(int T, int K, bool extra) {
     L.st = take(sizeof(LMState));
     L.report = take(8 * sizeof(double));
     L.xv = take(NJ * t * sizeof(double));
+    L.obs = take((size_t)n_obs * 18 * sizeof(double));
+    L.cpen = take(coll ? t * k * sizeof(double) : 0);
     L.total = off;
     return L;
 }
 
-uint64_t plan_bytes(int T, int K, bool extra) {
-    return make_layout(T, K, extra).total + align256(sizeof(DevPlan));
+uint64_t plan_bytes(int T, int K, bool extra, int n_obs, bool coll) {
+    return make_layout(T, K, extra, n_obs, coll).total + align256(sizeof(DevPlan));
 }
 
-uint64_t plan_class_bytes(int T, int K, bool extra) {
-    const uint64_t b = plan_bytes(T, K, extra);
+uint64_t plan_class_bytes(int T, int K, bool extra, int n_obs, bool coll) {
+    const uint64_t b = plan_bytes(T, K, extra, n_obs, coll);
     uint64_t c = (uint64_t)1 << 20;
     while (c < b) c <<= 1;
     return c;
@@ -208,6 +210,25 @@ cpf_status check_robot(const cpf_robot *r, HostRobot *out) {
         out->lo[i] = r->q_lo[i];
         out->hi[i] = r->q_hi[i];
     }
+    out->has_caps = r->capsules != nullptr;
+    if (r->capsules) {
+        if (!all_finite(r->capsules, (size_t)NJ * 7)) return fail(CPF_E_ARG, "capsules not finite");
+        for (int i = 0; i < NJ; ++i) {
+            if (!(r->capsules[7 * i + 6] >= 0.0)) return fail(CPF_E_ARG, "capsule %d: negative radius", i);
+            for (int c = 0; c < 7; ++c) out->cap[i][c] = r->capsules[7 * i + c];
+        }
+    }
+    return CPF_OK;
+}
+
+cpf_status check_obstacles(int32_t n, const double *obs) {
+    if (n < 0 || n > MAX_OBS) return fail(CPF_E_ARG, "n_obstacles=%d must be in [0, %d]", n, MAX_OBS);
+    if (n > 0 && !obs) return fail(CPF_E_ARG, "obstacles is NULL");
+    if (n > 0 && !all_finite(obs, (size_t)n * 18)) return fail(CPF_E_ARG, "obstacles not finite");
+    for (int m = 0; m < n; ++m)
+        for (int k = 0; k < 3; ++k)
+            if (!(obs[18 * m + 12 + k] <= obs[18 * m + 15 + k]))
+                return fail(CPF_E_ARG, "obstacle %d: p_min > p_max", m);
     return CPF_OK;
 }
 
@@ -224,7 +245,7 @@ cpf_status check_problem(const cpf_problem *p) {
             if (!(std::fabs(p->node_pen[i]) <= 1e30))
                 return fail(CPF_E_ARG, "node_pen must be finite with |value| <= 1e30");
     }
-    return CPF_OK;
+    return check_obstacles(p->n_obstacles, p->obstacles);
 }
 
 cpf_status check_opts(const cpf_opts *o) {
@@ -244,6 +265,9 @@ cpf_status check_opts(const cpf_opts *o) {
     const double tv[3] = {o->valid_pos_m, o->valid_rot_rad, o->valid_step_rad};
     if (!all_finite(tv, 3) || tv[0] < 0 || tv[1] < 0 || tv[2] < 0)
         return fail(CPF_E_ARG, "validity thresholds must be finite and >= 0");
+    const double cv[3] = {o->coll_margin, o->w_coll, o->coll_penalty};
+    if (!all_finite(cv, 3) || cv[0] < 0 || cv[1] < 0 || !(std::fabs(cv[2]) <= 1e30))
+        return fail(CPF_E_ARG, "collision options out of range");
     return CPF_OK;
 }
 
@@ -267,6 +291,16 @@ static void fill_desc(cpf_plan *p, bool has_extra) {
     D.vtol[0] = p->opts.valid_pos_m;
     D.vtol[1] = p->opts.valid_rot_rad;
     D.vtol[2] = p->opts.valid_step_rad;
+    D.has_coll = p->robot.has_caps ? 1 : 0;
+    D.n_obs = p->n_obs;
+    D.coll_margin = p->opts.coll_margin;
+    D.w_coll = p->opts.w_coll;
+    D.coll_penalty = p->opts.coll_penalty;
+    for (int i = 0; i < NJ; ++i)
+        for (int c = 0; c < 7; ++c) {
+            D.cap[i][c] = p->robot.cap[i][c];
+            D.capf[i][c] = (float)p->robot.cap[i][c];
+        }
     const HostRobot &r = p->robot;
     for (int i = 0; i < NJ; ++i) {
         D.a[i] = r.a[i]; D.d[i] = r.d[i]; D.ca[i] = r.ca[i]; D.sa[i] = r.sa[i]; D.off[i] = r.off[i];
@@ -295,13 +329,15 @@ static void fill_desc(cpf_plan *p, bool has_extra) {
     set_dev_ptr(D.st, b + L.st);
     set_dev_ptr(D.report, b + L.report);
     set_dev_ptr(D.xv, b + L.xv);
+    set_dev_ptr(D.obs, b + L.obs);
+    set_dev_ptr(D.cpen, b + L.cpen);
 }
 
 // A plan of T waypoints and K candidates with an arena from the pool, its
 // descriptor and initial LM state uploaded on s; no problem data yet.
-cpf_status plan_alloc(cpf_ctx *ctx, const HostRobot &hr, int T, int K, bool has_extra, const cpf_opts *opts,
-                      int32_t iters_target, hipStream_t s, cpf_plan **out) {
-    const uint64_t cls = plan_class_bytes(T, K, has_extra);
+cpf_status plan_alloc(cpf_ctx *ctx, const HostRobot &hr, int T, int K, bool has_extra, int n_obs,
+                      const cpf_opts *opts, int32_t iters_target, hipStream_t s, cpf_plan **out) {
+    const uint64_t cls = plan_class_bytes(T, K, has_extra, n_obs, hr.has_caps);
     void *mem = nullptr;
     cpf_status st = arena_get(ctx, cls, &mem);
     if (st != CPF_OK) return st;
@@ -309,10 +345,11 @@ cpf_status plan_alloc(cpf_ctx *ctx, const HostRobot &hr, int T, int K, bool has_
     p->ctx = ctx;
     p->T = T;
     p->K = K;
+    p->n_obs = n_obs;
     p->robot = hr;
     p->opts = *opts;
     p->bytes = cls;
-    p->L = make_layout(T, K, has_extra);
+    p->L = make_layout(T, K, has_extra, n_obs, hr.has_caps);
     p->arena = (char *)mem;
     p->d_desc = (DevPlan *)(p->arena + p->L.total);
     fill_desc(p.get(), has_extra);
@@ -334,7 +371,7 @@ cpf_status plan_create(cpf_ctx *ctx, const HostRobot &hr, const cpf_problem *pro
                        const cpf_opts *opts, int32_t iters_target, hipStream_t s, cpf_plan **out) {
     const bool has_extra = prob->node_pen != nullptr;
     cpf_plan *p = nullptr;
-    cpf_status st = plan_alloc(ctx, hr, prob->T, prob->K, has_extra, opts, iters_target, s, &p);
+    cpf_status st = plan_alloc(ctx, hr, prob->T, prob->K, has_extra, prob->n_obstacles, opts, iters_target, s, &p);
     if (st != CPF_OK) return st;
 
     // The caller's arrays go up as they are; a kernel converts them into the
@@ -350,6 +387,9 @@ cpf_status plan_create(cpf_ctx *ctx, const HostRobot &hr, const cpf_problem *pro
         e = stage_launch(raw, T, K, (float *)(p->arena + p->L.cand), (double *)(p->arena + p->L.targets), s);
     if (e == hipSuccess && has_extra)
         e = hipMemcpyAsync(p->arena + p->L.extra, prob->node_pen, (size_t)T * K * sizeof(double),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && prob->n_obstacles > 0)
+        e = hipMemcpyAsync(p->arena + p->L.obs, prob->obstacles, (size_t)prob->n_obstacles * 18 * sizeof(double),
                            hipMemcpyHostToDevice, s);
     if (e != hipSuccess) {
         HIP_IGNORE(hipStreamSynchronize(s));
@@ -414,6 +454,8 @@ void report_from(const LMState &ls, const double *report, cpf_lm_report *rep) {
     rep->pose_steps = ls.pose_steps;
     rep->diff_steps = ls.diff_steps;
     rep->valid_length = ls.valid_length;
+    rep->min_self_dist_m = report[3];
+    rep->min_env_dist_m = report[4];
 }
 
 void fill_report(const PlanReadback &rb, cpf_lm_report *rep) { report_from(rb.st, rb.report, rep); }
@@ -444,6 +486,9 @@ void cpf_opts_default(cpf_opts *o) {
     o->valid_pos_m = 1e-4;
     o->valid_rot_rad = 0.1 * 3.14159265358979323846 / 180.0;
     o->valid_step_rad = 7.0 * 3.14159265358979323846 / 180.0;
+    o->coll_margin = 0.02;
+    o->w_coll = 1.0;
+    o->coll_penalty = 100.0;
 }
 
 const char *cpf_last_error(void) { return cpf::g_err.c_str(); }
@@ -522,12 +567,40 @@ cpf_status cpf_fk_batch(cpf_ctx *ctx, const cpf_robot *robot, int64_t M, int32_t
     return CPF_OK;
 }
 
+cpf_status cpf_coll_batch(cpf_ctx *ctx, const cpf_robot *robot, int32_t n_obstacles, const double *obstacles_dev,
+                          int64_t M, int32_t prec, const void *q_dev, void *dist_dev, void *grad_dev,
+                          void *hip_stream) {
+    if (!ctx) return fail(CPF_E_ARG, "ctx is NULL");
+    HostRobot hr;
+    cpf_status st;
+    if ((st = check_robot(robot, &hr)) != CPF_OK) return st;
+    if (!hr.has_caps) return fail(CPF_E_ARG, "robot has no capsules");
+    if (n_obstacles < 0 || n_obstacles > MAX_OBS)
+        return fail(CPF_E_ARG, "n_obstacles=%d must be in [0, %d]", n_obstacles, MAX_OBS);
+    if (n_obstacles > 0 && !obstacles_dev) return fail(CPF_E_ARG, "obstacles_dev is NULL");
+    if (M < 0) return fail(CPF_E_ARG, "M=%lld", (long long)M);
+    if (prec != CPF_F32 && prec != CPF_F64) return fail(CPF_E_ARG, "prec %d", prec);
+    if (M > 0 && (!q_dev || !dist_dev)) return fail(CPF_E_ARG, "q / dist pointer is NULL");
+    if ((uint64_t)M > ((uint64_t)1 << 38)) return fail(CPF_E_ARG, "M too large");
+    HIP_TRY(hipSetDevice(ctx->device));
+    HostCaps caps;
+    memcpy(caps.v, hr.cap, sizeof(caps.v));
+    hipStream_t s = (hipStream_t)hip_stream;
+    HIP_TRY(timed(ctx, KIND_FK, s, [&] {
+        return coll_batch_launch(hr, caps, n_obstacles, obstacles_dev, M, prec, q_dev, dist_dev, grad_dev, s);
+    }));
+    return CPF_OK;
+}
+
 cpf_status cpf_dp_search(cpf_plan *plan, int32_t *path_out, double *best_out, double *mjac_out) {
     if (!plan) return fail(CPF_E_ARG, "plan is NULL");
     cpf_ctx *ctx = plan->ctx;
     HIP_TRY(hipSetDevice(ctx->device));
     HIP_TRY(timed(ctx, KIND_DP, ctx->stream,
-                  [&] { return dp_launch(plan->d_desc, 1, plan->K, plan->T, plan->lists_valid, ctx->stream); }));
+                  [&] {
+                      return dp_launch(plan->d_desc, 1, plan->K, plan->T, plan->lists_valid, plan->robot.has_caps,
+                                       ctx->stream);
+                  }));
     PlanReadback rb;
     cpf_status st = read_plan(plan, ctx->stream, nullptr, &rb, nullptr, path_out, nullptr);
     if (st != CPF_OK) return st;
@@ -557,7 +630,8 @@ cpf_status cpf_plan_append(cpf_plan *plan, int32_t K_add, const double *cand_add
     // otherwise the next search computes them for all candidates.
     const bool merge = plan->lists_valid;
     cpf_plan *np = nullptr;
-    cpf_status st = plan_alloc(ctx, plan->robot, T, K2, has_extra, &plan->opts, plan->init.iters_target, s, &np);
+    cpf_status st = plan_alloc(ctx, plan->robot, T, K2, has_extra, plan->n_obs, &plan->opts, plan->init.iters_target,
+                               s, &np);
     if (st != CPF_OK) return st;
     char *a2 = np->arena;
     const char *a1 = plan->arena;
@@ -580,6 +654,7 @@ cpf_status cpf_plan_append(cpf_plan *plan, int32_t K_add, const double *cand_add
         cols(L2.pen, L1.pen, sizeof(double), T);
         cols(L2.topk, L1.topk, TOPM * sizeof(uint16_t), T);
         cols(L2.topc, L1.topc, TOPM * sizeof(double), T);
+        if (plan->robot.has_caps) cols(L2.cpen, L1.cpen, sizeof(double), T);
     }
     if (has_extra) {
         if (old_extra) cols(L2.extra, L1.extra, sizeof(double), T);
@@ -596,9 +671,12 @@ cpf_status cpf_plan_append(cpf_plan *plan, int32_t K_add, const double *cand_add
     if (e == hipSuccess)
         e = hipMemcpyAsync(a2 + L2.targets, a1 + L1.targets, (size_t)12 * T * sizeof(double),
                            hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && plan->n_obs > 0)
+        e = hipMemcpyAsync(a2 + L2.obs, a1 + L1.obs, (size_t)plan->n_obs * 18 * sizeof(double),
+                           hipMemcpyDeviceToDevice, s);
     // 3. penalties and lists of the new nodes; the old nodes' lists merged
     if (e == hipSuccess && merge)
-        e = timed(ctx, KIND_DP, s, [&] { return dp_append_launch(np->d_desc, K0, K2, T, s); });
+        e = timed(ctx, KIND_DP, s, [&] { return dp_append_launch(np->d_desc, K0, K2, T, plan->robot.has_caps, s); });
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         HIP_IGNORE(hipStreamSynchronize(s));
@@ -625,9 +703,12 @@ cpf_status cpf_lm_refine(cpf_plan *plan, int32_t iters, double *xi_out, cpf_lm_r
     cpf_ctx *ctx = plan->ctx;
     HIP_TRY(hipSetDevice(ctx->device));
     HIP_TRY(timed(ctx, KIND_LM, ctx->stream,
-                  [&] { return lm_launch(plan->d_desc, 1, plan->opts.prec, plan->opts.schedule, iters, ctx->stream); }));
+                  [&] {
+                      return lm_launch(plan->d_desc, 1, plan->opts.prec, plan->opts.schedule, plan->robot.has_caps,
+                                       iters, ctx->stream);
+                  }));
     HIP_TRY(timed(ctx, KIND_EVAL, ctx->stream,
-                  [&] { return eval_launch(plan->d_desc, 1, 0, ctx->stream); }));
+                  [&] { return eval_launch(plan->d_desc, 1, 0, plan->robot.has_caps, ctx->stream); }));
     PlanReadback rb;
     cpf_status st = read_plan(plan, ctx->stream, nullptr, &rb, xi_out, nullptr, nullptr);
     if (st != CPF_OK) return st;
@@ -673,7 +754,9 @@ cpf_status cpf_solve_batch(cpf_ctx *ctx, int32_t nplans, const cpf_robot *robots
         for (auto *p : plans) plan_destroy(p);
     };
     int maxK = 0, maxT = 0;
+    bool kinds[2] = {false, false};   // plans without / with collision geometry
     for (int i = 0; i < nplans; ++i) {
+        kinds[hrs[i].has_caps ? 1 : 0] = true;
         cpf_plan *p = nullptr;
         if ((st = plan_create(ctx, hrs[i], &probs[i], &o, 0, ctx->stream, &p)) != CPF_OK) {
             cleanup();
@@ -693,13 +776,23 @@ cpf_status cpf_solve_batch(cpf_ctx *ctx, int32_t nplans, const cpf_robot *robots
     const int64_t t0 = now_ns();
     if (e == hipSuccess)
         e = timed(ctx, KIND_DP, ctx->stream,
-                  [&] { return dp_launch(d_descs, nplans, maxK, maxT, false, ctx->stream); });
+                  [&] { return dp_launch(d_descs, nplans, maxK, maxT, false, kinds[1], ctx->stream); });
     if (e == hipSuccess)
         e = timed(ctx, KIND_LM, ctx->stream,
-                  [&] { return lm_launch(d_descs, nplans, o.prec, o.schedule, o.iters, ctx->stream); });
+                  [&] {
+                      hipError_t r = hipSuccess;
+                      for (int c = 0; c < 2 && r == hipSuccess; ++c)
+                          if (kinds[c]) r = lm_launch(d_descs, nplans, o.prec, o.schedule, c, o.iters, ctx->stream);
+                      return r;
+                  });
     if (e == hipSuccess)
         e = timed(ctx, KIND_EVAL, ctx->stream,
-                  [&] { return eval_launch(d_descs, nplans, 0, ctx->stream); });
+                  [&] {
+                      hipError_t r = hipSuccess;
+                      for (int c = 0; c < 2 && r == hipSuccess; ++c)
+                          if (kinds[c]) r = eval_launch(d_descs, nplans, 0, c, ctx->stream);
+                      return r;
+                  });
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     const int64_t t1 = now_ns();
     if (e != hipSuccess) {
@@ -766,7 +859,8 @@ cpf_status cpf_batchopt(cpf_ctx *ctx, const cpf_robot *robot, const cpf_problem 
     for (int i = 0; i < M; ++i) {
         const int k = order[i];
         idx_out[i] = k;
-        probs[i] = cpf_problem{T, 1, prob->targets, prob->cand + (size_t)k * T * NJ, nullptr};
+        probs[i] = cpf_problem{T, 1, prob->targets, prob->cand + (size_t)k * T * NJ, nullptr, prob->n_obstacles,
+                               prob->obstacles};
         if (prob->node_pen) {
             pens[i].resize(T);
             for (int t = 0; t < T; ++t) pens[i][t] = prob->node_pen[(size_t)t * K + k];

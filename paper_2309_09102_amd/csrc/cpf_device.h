@@ -45,6 +45,7 @@ constexpr int NJ = 7;         // joints
 constexpr int NTRI = 28;      // packed lower triangle of a 7x7 block
 constexpr int NBLK = 49;      // full 7x7 block
 constexpr int MAX_K = 1024;   // search kernel limit (one lane per destination)
+constexpr int MAX_OBS = 64;   // cuboid obstacles per problem
 constexpr int CPF_STATUS_NUMERIC = -6;
 constexpr int TOPM = 16;      // nearest predecessors kept per search node
 
@@ -81,11 +82,22 @@ struct DevPlan {
     CPF_GLOBAL double *targets;
     CPF_GLOBAL double *xi, *xt, *A, *g, *cr, *dx, *rb;
     CPF_GLOBAL LMState *st;
-    CPF_GLOBAL double *report;    // [0] max pos err, [1] max rot err, [2] mjac
+    CPF_GLOBAL double *report;    // [0] max pos err, [1] max rot err, [2] mjac, [3] min self
+                                  // distance, [4] min environment distance
     // schedule mode: validity thresholds (position m, rotation rad, joint
     // step rad) and the latest valid trajectory [dof][T]
     double vtol[3], pad3;
     CPF_GLOBAL double *xv;
+    // collision geometry (has_coll): capsule of each link (endpoints in the
+    // frame after the link, radius) in double and float, obstacles [n_obs][18]
+    // (frame origin, rotation row-major, p_min, p_max), residual margin,
+    // weight and search penalty
+    int32_t has_coll, n_obs;
+    double coll_margin, w_coll, coll_penalty;
+    double cap[NJ][7];
+    float capf[NJ][7];
+    CPF_GLOBAL const double *obs;
+    CPF_GLOBAL double *cpen;      // [T][K] collision penalty of each search node
 };
 
 template <typename S>
@@ -126,34 +138,45 @@ __device__ __forceinline__ void dev_sincos(double x, double *s, double *c) { sin
 // which is the product with Rz(q) Tz(d) Tx(a) Rx(alpha) written per column.
 // With FRAMES the axis Z and origin p of joint i (before link i) are kept
 // for the geometric Jacobian.
-template <typename S, bool FRAMES>
-__device__ __forceinline__ void chain(const RobotT<S> &rb, const S *q, S X[3], S Y[3], S Z[3],
-                                      S p[3], S Zs[NJ][3], S Os[NJ][3]) {
+template <typename S>
+__device__ __forceinline__ void chain_start(S X[3], S Y[3], S Z[3], S p[3]) {
     X[0] = 1; X[1] = 0; X[2] = 0;
     Y[0] = 0; Y[1] = 1; Y[2] = 0;
     Z[0] = 0; Z[1] = 0; Z[2] = 1;
     p[0] = 0; p[1] = 0; p[2] = 0;
+}
+
+// Link i of the chain: the frame before it becomes the frame after it.
+template <typename S>
+__device__ __forceinline__ void dh_step(const RobotT<S> &rb, int i, S qi, S X[3], S Y[3], S Z[3], S p[3]) {
+    S s, c;
+    dev_sincos(qi + rb.off[i], &s, &c);
+    S nx[3], w[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        nx[r] = c * X[r] + s * Y[r];
+        w[r] = c * Y[r] - s * X[r];
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        p[r] = p[r] + rb.a[i] * nx[r] + rb.d[i] * Z[r];
+        Y[r] = rb.ca[i] * w[r] + rb.sa[i] * Z[r];
+        Z[r] = rb.ca[i] * Z[r] - rb.sa[i] * w[r];
+        X[r] = nx[r];
+    }
+}
+
+template <typename S, bool FRAMES>
+__device__ __forceinline__ void chain(const RobotT<S> &rb, const S *q, S X[3], S Y[3], S Z[3],
+                                      S p[3], S Zs[NJ][3], S Os[NJ][3]) {
+    chain_start(X, Y, Z, p);
 #pragma unroll
     for (int i = 0; i < NJ; ++i) {
         if (FRAMES) {
 #pragma unroll
             for (int r = 0; r < 3; ++r) { Zs[i][r] = Z[r]; Os[i][r] = p[r]; }
         }
-        S s, c;
-        dev_sincos(q[i] + rb.off[i], &s, &c);
-        S nx[3], w[3];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            nx[r] = c * X[r] + s * Y[r];
-            w[r] = c * Y[r] - s * X[r];
-        }
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            p[r] = p[r] + rb.a[i] * nx[r] + rb.d[i] * Z[r];
-            Y[r] = rb.ca[i] * w[r] + rb.sa[i] * Z[r];
-            Z[r] = rb.ca[i] * Z[r] - rb.sa[i] * w[r];
-            X[r] = nx[r];
-        }
+        dh_step(rb, i, q[i], X, Y, Z, p);
     }
 }
 

@@ -12,11 +12,22 @@ namespace cpf {
 // once in double.
 struct HostRobot {
     double a[NJ], d[NJ], alpha[NJ], ca[NJ], sa[NJ], off[NJ], lo[NJ], hi[NJ];
+    bool has_caps;
+    double cap[NJ][7];   // capsule of each link: p0, p1 (frame after the link), radius
+};
+
+// Capsules passed to a kernel by value.
+struct HostCaps {
+    double v[NJ][7];
 };
 
 // Kernel launchers (asynchronous on stream s).
 hipError_t fk_batch_launch(const HostRobot &hr, int64_t M, int prec, const void *q, void *pose,
                            void *J, hipStream_t s);
+// Collision distances (self, environment) of M configurations q [7][M] into
+// dist [2][M], optionally gradients [14][M]; obs: device [n_obs][18].
+hipError_t coll_batch_launch(const HostRobot &hr, const HostCaps &caps, int n_obs, const double *obs, int64_t M,
+                             int prec, const void *q, void *dist, void *grad, hipStream_t s);
 // Convert the uploaded caller arrays of one plan (candidates [K][T][7] and
 // targets [T][12], doubles) into the device layout (cand float [T][7][K],
 // targets [12][T]).
@@ -29,18 +40,20 @@ hipError_t stage_append_launch(const double *raw, int T, int K_add, int K, int k
 // between consecutive waypoints), cand float [T][7][K] -> out double [K].
 hipError_t cand_mjac_launch(const float *cand, int T, int K, double *out, hipStream_t s);
 // Search + seed gather for nplans plans: the predecessor lists over the
-// whole GPU (unless lists_ready: the plans' lists are current), then one
-// workgroup per plan for the stages.
-hipError_t dp_launch(const DevPlan *d_plans, int nplans, int maxK, int maxT, bool lists_ready, hipStream_t s);
+// whole GPU (unless lists_ready: the plans' lists are current; with coll,
+// after the nodes' collision penalties), then one workgroup per plan for the
+// stages.
+hipError_t dp_launch(const DevPlan *d_plans, int nplans, int maxK, int maxT, bool lists_ready, bool coll,
+                     hipStream_t s);
 // Penalties and predecessor lists of one plan after candidates K_old..K-1
 // were appended (the old nodes' penalties and lists already copied in).
-hipError_t dp_append_launch(const DevPlan *d_plan, int K_old, int K, int T, hipStream_t s);
+hipError_t dp_append_launch(const DevPlan *d_plan, int K_old, int K, int T, bool coll, hipStream_t s);
 // Up to `iters` LM iterations for each plan of precision prec (0 = mixed,
 // 1 = FP64); empty slots (T = 0) and plans of the other precision are skipped.
-hipError_t lm_launch(const DevPlan *d_plans, int nplans, int prec, int sched, int iters, hipStream_t s);
+hipError_t lm_launch(const DevPlan *d_plans, int nplans, int prec, int sched, int coll, int iters, hipStream_t s);
 // Pose error vs targets and mjac of the current trajectory (FP64 FK).  With
 // only_finished, only plans that reached their iteration target (or failed)
 // and have not been reported yet.
-hipError_t eval_launch(const DevPlan *d_plans, int nplans, int only_finished, hipStream_t s);
+hipError_t eval_launch(const DevPlan *d_plans, int nplans, int only_finished, int coll, hipStream_t s);
 
 }  // namespace cpf

@@ -36,6 +36,7 @@
 //     loaded ahead.
 #include <float.h>
 
+#include "coll_device.h"
 #include "cpf_device.h"
 #include "cpf_internal.h"
 
@@ -53,14 +54,45 @@ __device__ __forceinline__ double edge(const double qk[NJ], const Q *pq, long st
 }
 
 // Node penalty: limit_penalty if any joint is within the margin of a limit,
-// plus the caller's cost of the node.
+// plus the caller's cost of the node, plus (collision geometry) the node's
+// collision penalty from node_coll_kernel.
 __device__ __forceinline__ double node_penalty(const DevPlan &P, const double q[NJ], int t, int k) {
     bool near = false;
 #pragma unroll
     for (int j = 0; j < NJ; ++j)
         near = near || (q[j] <= P.lo[j] + P.margin) || (q[j] >= P.hi[j] - P.margin);
     const double ex = P.has_extra ? P.extra[(size_t)t * P.K + k] : 0.0;
-    return (near ? P.penalty : 0.0) + ex;
+    double pen = (near ? P.penalty : 0.0) + ex;
+    if (P.has_coll) pen += P.cpen[(size_t)t * P.K + k];
+    return pen;
+}
+
+// The collision checker of the search (Sec. III-B): coll_penalty for every
+// node (t, k >= k_begin) whose configuration has a capsule distance below
+// zero (FP64 kinematics on the float32 candidates), else 0.  One lane per
+// node; its own kernel so that the list kernels keep their registers.
+// Grid: x = tile (stage t, block of TOPM_BS nodes from k_begin), y = plan.
+__global__ __launch_bounds__(TOPM_BS) void node_coll_kernel(const DevPlan *__restrict__ plans, int k_begin) {
+    const DevPlan &P = plans[blockIdx.y];
+    const int T = P.T, K = P.K;
+    if (T <= 0 || K <= k_begin || !P.has_coll) return;
+    const int nkb = (K - k_begin + TOPM_BS - 1) / TOPM_BS;
+    const int t = blockIdx.x / nkb, k = k_begin + (blockIdx.x % nkb) * TOPM_BS + threadIdx.x;
+    if (t >= T || k >= K) return;
+    double q[NJ], dm[2], g[2][NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) q[j] = (double)P.cand[((size_t)t * NJ + j) * K + k];
+    coll_distances<double, false>(load_robot<double>(P), P.cap, P.n_obs, P.obs, q, dm, g);
+    P.cpen[(size_t)t * K + k] = (dm[0] < 0.0 || dm[1] < 0.0) ? P.coll_penalty : 0.0;
+}
+
+static hipError_t node_coll_launch(const DevPlan *d_plans, int nplans, int maxK, int maxT, int k_begin,
+                                   hipStream_t s) {
+    const int nkb = (maxK - k_begin + TOPM_BS - 1) / TOPM_BS;
+    if (nkb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(node_coll_kernel, dim3((unsigned)(maxT * nkb), (unsigned)nplans), dim3(TOPM_BS), 0, s,
+                       d_plans, k_begin);
+    return hipGetLastError();
 }
 
 // Sorted insertion into a TOPM list ordered by (e, k').  Callers offer k' in
@@ -433,10 +465,15 @@ __global__ __launch_bounds__(BS) void dp_kernel(const DevPlan *__restrict__ plan
     }
 }
 
-hipError_t dp_launch(const DevPlan *d_plans, int nplans, int maxK, int maxT, bool lists_ready, hipStream_t s) {
+hipError_t dp_launch(const DevPlan *d_plans, int nplans, int maxK, int maxT, bool lists_ready, bool coll,
+                     hipStream_t s) {
     if (nplans <= 0 || maxT <= 0 || maxK <= 0) return hipSuccess;
     if (maxK > MAX_K) return hipErrorInvalidValue;
     if (!lists_ready) {
+        if (coll) {
+            const hipError_t e = node_coll_launch(d_plans, nplans, maxK, maxT, 0, s);
+            if (e != hipSuccess) return e;
+        }
         const int nkb = (maxK + TOPM_BS - 1) / TOPM_BS;
         const dim3 grid((unsigned)(maxT * nkb), (unsigned)nplans);
         hipLaunchKernelGGL(dp_topm_kernel, grid, dim3(TOPM_BS), (size_t)maxK * NJ * sizeof(float), s, d_plans);
@@ -453,9 +490,13 @@ hipError_t dp_launch(const DevPlan *d_plans, int nplans, int maxK, int maxT, boo
     return hipGetLastError();
 }
 
-hipError_t dp_append_launch(const DevPlan *d_plan, int K_old, int K, int T, hipStream_t s) {
+hipError_t dp_append_launch(const DevPlan *d_plan, int K_old, int K, int T, bool coll, hipStream_t s) {
     if (T <= 0 || K <= 0) return hipSuccess;
     if (K > MAX_K || K_old < 0 || K_old > K) return hipErrorInvalidValue;
+    if (coll) {   // the new nodes' collision penalties (the old ones are kept)
+        const hipError_t e = node_coll_launch(d_plan, 1, K, T, K_old, s);
+        if (e != hipSuccess) return e;
+    }
     const int nkb = (K + TOPM_BS - 1) / TOPM_BS;
     hipLaunchKernelGGL(dp_topm_append_kernel, dim3((unsigned)(T * nkb), 1), dim3(TOPM_BS),
                        (size_t)K * NJ * sizeof(float), s, d_plan, K_old);

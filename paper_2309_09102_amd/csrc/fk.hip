@@ -2,6 +2,7 @@
 // kinematic Jacobian of Sec. III-C).  One lane per configuration; the chain
 // lives in registers; q, pose and J are SoA so every load and store of a
 // wavefront is one contiguous 256-byte (float) or 512-byte (double) run.
+#include "coll_device.h"
 #include "cpf_device.h"
 #include "cpf_internal.h"
 
@@ -64,6 +65,63 @@ hipError_t fk_batch_launch(const HostRobot &hr, int64_t M, int prec, const void 
         rb.sa[i] = (float)hr.sa[i]; rb.off[i] = (float)hr.off[i];
     }
     return launch_fk<float>(rb, M, q, pose, J, s);
+}
+
+// Collision distances of M configurations (the checker of Sec. III-B and the
+// distances of Sec. III-C): dist [2][M] (self, environment), optionally the
+// gradients grad [2 * 7][M] (row h * 7 + k).  One lane per configuration.
+template <typename S, bool GRAD>
+__global__ __launch_bounds__(256) void coll_batch_kernel(RobotT<S> rb, HostCaps caps, int n_obs,
+                                                         const double *__restrict__ obs, int64_t M,
+                                                         const S *__restrict__ q, S *__restrict__ dist,
+                                                         S *__restrict__ grad) {
+    const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (m >= M) return;
+    S qq[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) qq[j] = q[(int64_t)j * M + m];
+    S dm[2], g[2][NJ];
+    coll_distances<S, GRAD>(rb, caps.v, n_obs, (const CPF_GLOBAL double *)obs, qq, dm, g);
+    dist[m] = dm[0];
+    dist[M + m] = dm[1];
+    if (GRAD) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int k = 0; k < NJ; ++k) grad[((int64_t)h * NJ + k) * M + m] = g[h][k];
+    }
+}
+
+template <typename S>
+static hipError_t launch_coll(const RobotT<S> &rb, const HostCaps &caps, int n_obs, const double *obs, int64_t M,
+                              const void *q, void *dist, void *grad, hipStream_t s) {
+    if (M == 0) return hipSuccess;
+    const dim3 grid((unsigned)((M + 255) / 256));
+    if (grad)
+        hipLaunchKernelGGL((coll_batch_kernel<S, true>), grid, dim3(256), 0, s, rb, caps, n_obs, obs, M,
+                           (const S *)q, (S *)dist, (S *)grad);
+    else
+        hipLaunchKernelGGL((coll_batch_kernel<S, false>), grid, dim3(256), 0, s, rb, caps, n_obs, obs, M,
+                           (const S *)q, (S *)dist, (S *)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t coll_batch_launch(const HostRobot &hr, const HostCaps &caps, int n_obs, const double *obs, int64_t M,
+                             int prec, const void *q, void *dist, void *grad, hipStream_t s) {
+    if (prec == 1) {
+        RobotT<double> rb;
+        for (int i = 0; i < NJ; ++i) {
+            rb.a[i] = hr.a[i]; rb.d[i] = hr.d[i]; rb.ca[i] = hr.ca[i]; rb.sa[i] = hr.sa[i];
+            rb.off[i] = hr.off[i];
+        }
+        return launch_coll<double>(rb, caps, n_obs, obs, M, q, dist, grad, s);
+    }
+    RobotT<float> rb;
+    for (int i = 0; i < NJ; ++i) {
+        rb.a[i] = (float)hr.a[i]; rb.d[i] = (float)hr.d[i]; rb.ca[i] = (float)hr.ca[i];
+        rb.sa[i] = (float)hr.sa[i]; rb.off[i] = (float)hr.off[i];
+    }
+    return launch_coll<float>(rb, caps, n_obs, obs, M, q, dist, grad, s);
 }
 
 // One thread per (waypoint, candidate) pair, candidates fastest, so the

@@ -19,6 +19,7 @@
 // same H reusing the stored factors.
 #include <float.h>
 
+#include "coll_device.h"
 #include "cpf_device.h"
 #include "cpf_internal.h"
 
@@ -78,11 +79,38 @@ __device__ __forceinline__ double pose_sq(const DevPlan &P, const RobotT<S> &rb,
     return (double)s;
 }
 
-// Cost of trajectory X: pose part and smoothness part, block-reduced.
+// The plan's capsules in the kinematics precision.
+template <typename S> struct CapsOf;
+template <> struct CapsOf<double> {
+    static __device__ __forceinline__ const double (*get(const DevPlan &P))[7] { return P.cap; }
+};
+template <> struct CapsOf<float> {
+    static __device__ __forceinline__ const float (*get(const DevPlan &P))[7] { return P.capf; }
+};
+
+// The two collision residuals max(0, margin - d) of waypoint t of X and,
+// with GRAD, their Jacobians (minus the distance gradients where positive).
+template <typename S, bool GRAD>
+__device__ __forceinline__ void coll_residuals(const DevPlan &P, const RobotT<S> &rb, const S q[NJ], double rc[2],
+                                               double Jc[2][NJ]) {
+    S dm[2], g[2][NJ];
+    coll_distances<S, GRAD>(rb, CapsOf<S>::get(P), P.n_obs, P.obs, q, dm, g);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const double r = P.coll_margin - (double)dm[h];
+        rc[h] = r > 0.0 ? r : 0.0;
+        if (GRAD)
+#pragma unroll
+            for (int k = 0; k < NJ; ++k) Jc[h][k] = r > 0.0 ? -(double)g[h][k] : 0.0;
+    }
+}
+
+// Cost of trajectory X: pose, smoothness and (wc != 0) collision parts,
+// block-reduced.
 template <typename S>
 __device__ __forceinline__ double plan_cost(const DevPlan &P, const RobotT<S> &rb, const CPF_GLOBAL double *X,
-                                            int T, double *red, double wp, double ws) {
-    double ps = 0.0, ss = 0.0;
+                                            int T, double *red, double wp, double ws, double wc) {
+    double ps = 0.0, ss = 0.0, cs = 0.0;
     for (int t = threadIdx.x; t < T; t += LM_BS) {
         ps += pose_sq<S>(P, rb, X, T, t);
         if (t + 1 < T) {
@@ -92,15 +120,25 @@ __device__ __forceinline__ double plan_cost(const DevPlan &P, const RobotT<S> &r
                 ss += d * d;
             }
         }
+        if (wc != 0.0) {
+            S q[NJ];
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) q[j] = (S)X[(size_t)j * T + t];
+            double rc[2], Jc[2][NJ];
+            coll_residuals<S, false>(P, rb, q, rc, Jc);
+            cs += rc[0] * rc[0] + rc[1] * rc[1];
+        }
     }
     const double pose_sum = block_sum(ps, red);
     const double diff_sum = block_sum(ss, red);
-    return 0.5 * wp * pose_sum + 0.5 * ws * diff_sum;
+    const double coll_sum = wc != 0.0 ? block_sum(cs, red) : 0.0;
+    return 0.5 * wp * pose_sum + 0.5 * ws * diff_sum + 0.5 * wc * coll_sum;
 }
 
 // Linearise at xi: A_t = w_p J^T J (packed lower), g_t; returns max |g|.
 template <typename S>
-__device__ __forceinline__ double linearise(const DevPlan &P, const RobotT<S> &rb, int T, double w_p, double w_s) {
+__device__ __forceinline__ double linearise(const DevPlan &P, const RobotT<S> &rb, int T, double w_p, double w_s,
+                                            double w_c) {
     double gmax = 0.0;
     for (int t = threadIdx.x; t < T; t += LM_BS) {
         double xq[NJ];
@@ -158,6 +196,28 @@ __device__ __forceinline__ double linearise(const DevPlan &P, const RobotT<S> &r
             gi += w_s * sm;
             P.g[(size_t)i * T + t] = gi;
             gmax = fmax(gmax, fabs(gi));
+        }
+    }
+    // Collision residuals (w_c != 0): w_c sum_h J_h J_h^T and w_c sum_h
+    // J_h r_h added to the waypoint's block and gradient (a second pass, so
+    // the pose pass keeps its registers).
+    if (w_c != 0.0) {
+        gmax = 0.0;
+        for (int t = threadIdx.x; t < T; t += LM_BS) {
+            S q[NJ];
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) q[j] = (S)P.xi[(size_t)j * T + t];
+            double rc[2], Jc[2][NJ];
+            coll_residuals<S, true>(P, rb, q, rc, Jc);
+#pragma unroll
+            for (int i = 0; i < NJ; ++i) {
+#pragma unroll
+                for (int j = 0; j < NJ; ++j)
+                    P.A[(size_t)t * NBLK + i * NJ + j] += w_c * (Jc[0][i] * Jc[0][j] + Jc[1][i] * Jc[1][j]);
+                const double gi = P.g[(size_t)i * T + t] + w_c * (Jc[0][i] * rc[0] + Jc[1][i] * rc[1]);
+                P.g[(size_t)i * T + t] = gi;
+                gmax = fmax(gmax, fabs(gi));
+            }
         }
     }
     return gmax;
@@ -823,18 +883,28 @@ __device__ __forceinline__ void pose_err_fp64(const DevPlan &P, const RobotT<dou
 
 // Validity check of the alternating schedule (Sec. III-C's anytime result
 // under the Sec. II thresholds), FP64 kinematics: every waypoint within the
-// position and rotation thresholds and no joint step above the step
-// threshold.  A trajectory that passes is copied to xv and counted.  Returns
+// position and rotation thresholds, no joint step above the step threshold
+// and, with collision geometry, no capsule distance below zero (Sec. II
+// collision avoidance).  A trajectory that passes is copied to xv and
+// counted.  Returns
 // the next step's objective to all lanes: 1 (differencing) when the pose
 // thresholds hold, else 0 (pose).
+template <bool COLL>
 __device__ int schedule_check(const DevPlan &P, LMState *st, int T, double *red) {
     const RobotT<double> rb = load_robot<double>(P);
-    double ep = 0.0, er = 0.0, mj = 0.0, len = 0.0;
+    double ep = 0.0, er = 0.0, mj = 0.0, len = 0.0, pen = 0.0;
     for (int t = threadIdx.x; t < T; t += LM_BS) {
         double a, b;
         pose_err_fp64(P, rb, P.xi, T, t, &a, &b);
         ep = fmax(ep, a);
         er = fmax(er, b);
+        if (COLL) {   // deepest penetration, as a positive number
+            double q[NJ], dm[2], g[2][NJ];
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) q[j] = P.xi[(size_t)j * T + t];
+            coll_distances<double, false>(rb, P.cap, P.n_obs, P.obs, q, dm, g);
+            pen = fmax(pen, fmax(-dm[0], -dm[1]));
+        }
         if (t + 1 < T)
 #pragma unroll
             for (int j = 0; j < NJ; ++j) {
@@ -847,8 +917,9 @@ __device__ int schedule_check(const DevPlan &P, LMState *st, int T, double *red)
     er = block_max(er, red);
     mj = block_max(mj, red);
     len = block_sum(len, red);
+    if (COLL) pen = block_max(pen, red);
     const bool pose_ok = ep <= P.vtol[0] && er <= P.vtol[1];
-    if (pose_ok && mj <= P.vtol[2]) {
+    if (pose_ok && mj <= P.vtol[2] && pen <= 0.0) {
         for (int e = threadIdx.x; e < NJ * T; e += LM_BS) P.xv[e] = P.xi[e];
         if (threadIdx.x == 0) {
             st->n_valid += 1;
@@ -859,16 +930,17 @@ __device__ int schedule_check(const DevPlan &P, LMState *st, int T, double *red)
     return pose_ok ? 1 : 0;
 }
 
-// One instance per precision and objective kind (the weighted sum, or the
-// alternating schedule), so that the schedule's extra state does not add
-// register pressure to the plain iteration.
-template <typename S, bool SCHED>
+// One instance per precision, objective kind (the weighted sum, or the
+// alternating schedule) and collision geometry (with or without), so that
+// the schedule's state and the collision terms add no register pressure to
+// the plain iteration.
+template <typename S, bool SCHED, bool COLL>
 __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ plans, int iters) {
     constexpr int PREC = sizeof(S) == sizeof(double) ? 1 : 0;
     const DevPlan &P = plans[blockIdx.x];
     const int T = P.T;
-    // empty slot, or a plan of the other precision or objective kind
-    if (T <= 0 || P.prec != PREC || (P.schedule != 0) != SCHED) return;
+    // empty slot, or a plan of another precision, objective kind or geometry
+    if (T <= 0 || P.prec != PREC || (P.schedule != 0) != SCHED || (P.has_coll != 0) != COLL) return;
     {
         const LMState *s0 = P.st;
         if (s0->seeded && s0->iters_target > 0 && s0->iters_done >= s0->iters_target) return;
@@ -880,6 +952,7 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
     const int tid = threadIdx.x;
     constexpr bool sched = SCHED;
     LMState *st = P.st;
+    const double wc_all = COLL ? P.w_coll : 0.0;   // weight of the collision residuals
 
     if (tid == 0) sh_flags[2] = st->seeded;
     __syncthreads();
@@ -893,7 +966,7 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
                 P.xi[(size_t)j * T + t] = v;
             }
         __syncthreads();
-        const double c0 = plan_cost<S>(P, load_robot<S>(P), P.xi, T, red, P.w_p, P.w_s);
+        const double c0 = plan_cost<S>(P, load_robot<S>(P), P.xi, T, red, P.w_p, P.w_s, wc_all);
         if (tid == 0) {
             st->nu = 2.0;
             st->cost = c0;
@@ -959,10 +1032,10 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
         // objective is quadratic, so the gain-ratio rule would only drive
         // lambda to its floor and one step would then flatten the path.
         int m = 0;
-        double wp = P.w_p, ws = P.w_s;
+        double wp = P.w_p, ws = P.w_s, wc = wc_all;
         if (sched) {
             if (!sh_sched[0]) {
-                const int nm = schedule_check(P, st, T, red);
+                const int nm = schedule_check<COLL>(P, st, T, red);
                 if (tid == 0) {
                     sh_sched[0] = 1;
                     sh_sched[1] = nm;
@@ -972,10 +1045,11 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
             m = sh_sched[1];
             wp = m ? 0.0 : P.w_p;
             ws = m ? P.w_s : 0.0;
+            wc = m ? wc_all : 0.0;
             if (m != sh_sched[2]) {   // new objective: its cost and linearisation
                 // (the barriers inside plan_cost order every lane's read of
                 // sh_sched[2] before lane 0 rewrites it)
-                const double c = plan_cost<S>(P, load_robot<S>(P), P.xi, T, red, wp, ws);
+                const double c = plan_cost<S>(P, load_robot<S>(P), P.xi, T, red, wp, ws, wc);
                 if (tid == 0) {
                     sh_cost = c;
                     sh_flags[0] = 1;
@@ -986,7 +1060,7 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
         }
         const double lam = m ? P.lam0 : sh_lam;
         if (sh_flags[0]) {
-            const double gm = linearise<S>(P, load_robot<S>(P), T, wp, ws);
+            const double gm = linearise<S>(P, load_robot<S>(P), T, wp, ws, wc);
             const double gmax = block_max(gm, red);
             if (tid == 0) st->grad_inf = gmax;
         }
@@ -1039,7 +1113,7 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
                 pr += dl * (lam * dl - P.g[e]);
             }
         __syncthreads();
-        const double cn = plan_cost<S>(P, load_robot<S>(P), P.xt, T, red, wp, ws);
+        const double cn = plan_cost<S>(P, load_robot<S>(P), P.xt, T, red, wp, ws, wc);
         const double pred = 0.5 * block_sum(pr, red);
         PHASE_MARK(5);
         if (tid == 0) {
@@ -1113,7 +1187,7 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
     // The check after the last step of the call (the next call's first step
     // then reuses its decision).
     if (sched && sh_flags[1] == 0 && !sh_sched[0]) {
-        const int nm = schedule_check(P, st, T, red);
+        const int nm = schedule_check<COLL>(P, st, T, red);
         if (tid == 0) {
             sh_sched[0] = 1;
             sh_sched[1] = nm;
@@ -1132,12 +1206,15 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
     }
 }
 
-// Report: FP64 pose error of xi vs the targets and mjac (Sec. II metrics).
+// Report: FP64 pose error of xi vs the targets and mjac (Sec. II metrics)
+// and, with collision geometry, the smallest self and environment distances
+// along xi (+inf without).
+template <bool COLL>
 __global__ __launch_bounds__(LM_BS) void eval_kernel(const DevPlan *__restrict__ plans,
                                                      int only_finished) {
     const DevPlan &P = plans[blockIdx.x];
     const int T = P.T;
-    if (T <= 0) return;
+    if (T <= 0 || (P.has_coll != 0) != COLL) return;
     if (only_finished) {
         const LMState *s0 = P.st;
         const bool finished = s0->status != 0 ||
@@ -1146,7 +1223,7 @@ __global__ __launch_bounds__(LM_BS) void eval_kernel(const DevPlan *__restrict__
     }
     __shared__ double red[LM_BS];
     const RobotT<double> rb = load_robot<double>(P);
-    double ep = 0.0, er = 0.0, mj = 0.0;
+    double ep = 0.0, er = 0.0, mj = 0.0, ns = -__builtin_inf(), ne = -__builtin_inf();
     for (int t = threadIdx.x; t < T; t += LM_BS) {
         double a, b;
         pose_err_fp64(P, rb, P.xi, T, t, &a, &b);
@@ -1156,35 +1233,60 @@ __global__ __launch_bounds__(LM_BS) void eval_kernel(const DevPlan *__restrict__
 #pragma unroll
             for (int j = 0; j < NJ; ++j)
                 mj = fmax(mj, fabs(P.xi[(size_t)j * T + t + 1] - P.xi[(size_t)j * T + t]));
+        if (COLL) {
+            double q[NJ], dm[2], g[2][NJ];
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) q[j] = P.xi[(size_t)j * T + t];
+            coll_distances<double, false>(rb, P.cap, P.n_obs, P.obs, q, dm, g);
+            ns = fmax(ns, -dm[0]);
+            ne = fmax(ne, -dm[1]);
+        }
     }
     ep = block_max(ep, red);
     er = block_max(er, red);
     mj = block_max(mj, red);
+    if (COLL) {
+        ns = block_max(ns, red);
+        ne = block_max(ne, red);
+    }
     if (threadIdx.x == 0) {
         P.report[0] = ep;
         P.report[1] = er;
         P.report[2] = mj;
+        P.report[3] = -ns;
+        P.report[4] = -ne;
         if (only_finished) P.st->reported = 1;
     }
 }
 
-hipError_t lm_launch(const DevPlan *d_plans, int nplans, int prec, int sched, int iters, hipStream_t s) {
-    if (nplans <= 0) return hipSuccess;
+template <typename S, bool SCHED>
+static void lm_launch_coll(const DevPlan *d_plans, int nplans, int coll, int iters, hipStream_t s) {
     const dim3 g(nplans), b(LM_BS);
-    if (prec == 1 && sched)
-        hipLaunchKernelGGL((lm_kernel<double, true>), g, b, 0, s, d_plans, iters);
-    else if (prec == 1)
-        hipLaunchKernelGGL((lm_kernel<double, false>), g, b, 0, s, d_plans, iters);
-    else if (sched)
-        hipLaunchKernelGGL((lm_kernel<float, true>), g, b, 0, s, d_plans, iters);
+    if (coll)
+        hipLaunchKernelGGL((lm_kernel<S, SCHED, true>), g, b, 0, s, d_plans, iters);
     else
-        hipLaunchKernelGGL((lm_kernel<float, false>), g, b, 0, s, d_plans, iters);
+        hipLaunchKernelGGL((lm_kernel<S, SCHED, false>), g, b, 0, s, d_plans, iters);
+}
+
+hipError_t lm_launch(const DevPlan *d_plans, int nplans, int prec, int sched, int coll, int iters, hipStream_t s) {
+    if (nplans <= 0) return hipSuccess;
+    if (prec == 1 && sched)
+        lm_launch_coll<double, true>(d_plans, nplans, coll, iters, s);
+    else if (prec == 1)
+        lm_launch_coll<double, false>(d_plans, nplans, coll, iters, s);
+    else if (sched)
+        lm_launch_coll<float, true>(d_plans, nplans, coll, iters, s);
+    else
+        lm_launch_coll<float, false>(d_plans, nplans, coll, iters, s);
     return hipGetLastError();
 }
 
-hipError_t eval_launch(const DevPlan *d_plans, int nplans, int only_finished, hipStream_t s) {
+hipError_t eval_launch(const DevPlan *d_plans, int nplans, int only_finished, int coll, hipStream_t s) {
     if (nplans <= 0) return hipSuccess;
-    hipLaunchKernelGGL(eval_kernel, dim3(nplans), dim3(LM_BS), 0, s, d_plans, only_finished);
+    if (coll)
+        hipLaunchKernelGGL((eval_kernel<true>), dim3(nplans), dim3(LM_BS), 0, s, d_plans, only_finished);
+    else
+        hipLaunchKernelGGL((eval_kernel<false>), dim3(nplans), dim3(LM_BS), 0, s, d_plans, only_finished);
     return hipGetLastError();
 }
 

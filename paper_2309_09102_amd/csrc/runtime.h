@@ -40,13 +40,13 @@ inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 // region is shared with the search lists (topc), which are written later.
 struct Layout {
     size_t cand, extra, pen, bp, topk, topc, raw, path, dp_out, targets, xi, xt, A, g, cr, dx, rb, st,
-        report, xv, total;
+        report, xv, obs, cpen, total;
 };
-Layout make_layout(int T, int K, bool extra);
-uint64_t plan_bytes(int T, int K, bool extra);
+Layout make_layout(int T, int K, bool extra, int n_obs, bool coll);
+uint64_t plan_bytes(int T, int K, bool extra, int n_obs, bool coll);
 // Device bytes a plan takes from the budget: its arena rounded up to a
 // power of two (at least 1 MiB), the unit the arena pool recycles.
-uint64_t plan_class_bytes(int T, int K, bool extra);
+uint64_t plan_class_bytes(int T, int K, bool extra, int n_obs, bool coll);
 
 cpf_status check_robot(const cpf_robot *r, HostRobot *out);
 cpf_status check_problem(const cpf_problem *p);
@@ -101,7 +101,7 @@ struct cpf_ctx {
 
 struct cpf_plan {
     cpf_ctx *ctx = nullptr;
-    int T = 0, K = 0;
+    int T = 0, K = 0, n_obs = 0;
     cpf::HostRobot robot{};
     cpf_opts opts{};
     cpf::Layout L{};
@@ -149,8 +149,8 @@ void copy_parallel(void *dst, const void *src, size_t bytes);
 // Take an arena and upload one plan on stream s (asynchronous: the caller's
 // arrays in `prob` must stay alive until s is synchronised).  iters_target =
 // 0 lets each lm_refine call run the iterations it asks for.
-cpf_status plan_alloc(cpf_ctx *ctx, const HostRobot &hr, int T, int K, bool has_extra, const cpf_opts *opts,
-                      int32_t iters_target, hipStream_t s, cpf_plan **out);
+cpf_status plan_alloc(cpf_ctx *ctx, const HostRobot &hr, int T, int K, bool has_extra, int n_obs,
+                      const cpf_opts *opts, int32_t iters_target, hipStream_t s, cpf_plan **out);
 cpf_status plan_create(cpf_ctx *ctx, const HostRobot &hr, const cpf_problem *prob,
                        const cpf_opts *opts, int32_t iters_target, hipStream_t s, cpf_plan **out);
 void plan_destroy(cpf_plan *p);

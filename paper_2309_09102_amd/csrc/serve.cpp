@@ -37,7 +37,8 @@ struct Request {
     int T = 0, K = 0;
     // copies of the caller's arrays: candidates, targets, node costs, one
     // buffer (pinned when the pinned pool allows, else pageable)
-    double *cand = nullptr, *targets = nullptr, *node_pen = nullptr;
+    double *cand = nullptr, *targets = nullptr, *node_pen = nullptr, *obstacles = nullptr;
+    int n_obs = 0;
     void *stage = nullptr;
     uint64_t stage_cls = 0;
     std::vector<double> stage_vec;
@@ -93,14 +94,15 @@ cpf_status server_init(cpf_ctx *ctx, Server *sv) {
     HIP_TRY(hipMemcpyAsync(sv->d_states, sv->h_states.data(), sizeof(LMState) * sv->cap,
                            hipMemcpyHostToDevice, sv->s_lm));
     HIP_TRY(hipStreamSynchronize(sv->s_lm));
-    // Capture the LM tick: both precisions and both objective kinds over
-    // every slot (each instance skips the slots of the others), then the
-    // report for plans that finished in this tick.
+    // Capture the LM tick: both precisions, both objective kinds, with and
+    // without collision geometry, over every slot (each instance skips the
+    // slots of the others), then the report for plans that finished in this
+    // tick.
     HIP_TRY(hipStreamBeginCapture(sv->s_lm, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int k = 0; k < 4 && e == hipSuccess; ++k)
-        e = lm_launch(sv->d_work, sv->cap, k & 1, k >> 1, sv->ipt, sv->s_lm);
-    if (e == hipSuccess) e = eval_launch(sv->d_work, sv->cap, 1, sv->s_lm);
+    for (int k = 0; k < 8 && e == hipSuccess; ++k)
+        e = lm_launch(sv->d_work, sv->cap, k & 1, (k >> 1) & 1, k >> 2, sv->ipt, sv->s_lm);
+    for (int c = 0; c < 2 && e == hipSuccess; ++c) e = eval_launch(sv->d_work, sv->cap, 1, c, sv->s_lm);
     hipError_t e2 = hipStreamEndCapture(sv->s_lm, &sv->graph);
     if (e != hipSuccess) return fail(CPF_E_DEVICE, "tick capture: %s", hipGetErrorString(e));
     if (e2 != hipSuccess) return fail(CPF_E_DEVICE, "tick capture end: %s", hipGetErrorString(e2));
@@ -125,7 +127,7 @@ void release_stage(cpf_ctx *ctx, Request *r) {
     if (r->stage) pinned_put(ctx, r->stage, r->stage_cls);
     r->stage = nullptr;
     std::vector<double>().swap(r->stage_vec);
-    r->cand = r->targets = r->node_pen = nullptr;
+    r->cand = r->targets = r->node_pen = r->obstacles = nullptr;
 }
 
 // Release a request's slot, plan and inputs and wake its pollers.  The slot's
@@ -209,6 +211,7 @@ void retire(cpf_ctx *ctx, Server *sv, const std::vector<Request *> &fin, cpf_sta
 int admit(cpf_ctx *ctx, Server *sv, int free_slots) {
     std::vector<Request *> batch;
     int maxK = 0, maxT = 0;
+    bool any_coll = false;
     while (free_slots > 0) {
         Request *r = nullptr;
         {
@@ -217,7 +220,7 @@ int admit(cpf_ctx *ctx, Server *sv, int free_slots) {
             r = ctx->pending.front();
             ctx->pending.pop_front();
         }
-        cpf_problem pb{r->T, r->K, r->targets, r->cand, r->node_pen};
+        cpf_problem pb{r->T, r->K, r->targets, r->cand, r->node_pen, r->n_obs, r->obstacles};
         r->t_admit = now_ns();
         cpf_status st = plan_create(ctx, r->robot, &pb, &r->opts, r->opts.iters, sv->s_up, &r->plan);
         if (st == CPF_E_NOMEM) {   // wait for arenas to come back
@@ -247,13 +250,14 @@ int admit(cpf_ctx *ctx, Server *sv, int free_slots) {
         batch.push_back(r);
         maxK = std::max(maxK, r->K);
         maxT = std::max(maxT, r->T);
+        any_coll = any_coll || r->robot.has_caps;
         --free_slots;
     }
     if (batch.empty()) return 0;
     hipError_t e = hipMemcpyAsync(sv->d_new, sv->h_new.data(), sizeof(DevPlan) * batch.size(),
                                   hipMemcpyHostToDevice, sv->s_up);
     if (e == hipSuccess)
-        e = timed(ctx, KIND_DP, sv->s_up, [&] { return dp_launch(sv->d_new, (int)batch.size(), maxK, maxT, false, sv->s_up); });
+        e = timed(ctx, KIND_DP, sv->s_up, [&] { return dp_launch(sv->d_new, (int)batch.size(), maxK, maxT, false, any_coll, sv->s_up); });
     if (e == hipSuccess) e = hipEventRecord(sv->searched, sv->s_up);
     if (e != hipSuccess) {
         HIP_IGNORE(hipStreamSynchronize(sv->s_up));
@@ -391,7 +395,7 @@ extern "C" cpf_status cpf_submit(cpf_ctx *ctx, const cpf_robot *robot, const cpf
     cpf_opts_default(&o);
     if (opts) o = *opts;
     if ((st = check_opts(&o)) != CPF_OK) return st;
-    const uint64_t bytes = plan_class_bytes(prob->T, prob->K, prob->node_pen != nullptr);
+    const uint64_t bytes = plan_class_bytes(prob->T, prob->K, prob->node_pen != nullptr, prob->n_obstacles, hr.has_caps);
     if (bytes > ctx->budget)
         return fail(CPF_E_NOMEM, "request needs %llu bytes, budget is %llu",
                     (unsigned long long)bytes, (unsigned long long)ctx->budget);
@@ -402,7 +406,8 @@ extern "C" cpf_status cpf_submit(cpf_ctx *ctx, const cpf_robot *robot, const cpf
     r->K = prob->K;
     const size_t n_cand = (size_t)prob->K * prob->T * NJ, n_tg = (size_t)prob->T * 12;
     const size_t n_pen = prob->node_pen ? (size_t)prob->T * prob->K : 0;
-    const size_t n_all = n_cand + n_tg + n_pen;
+    const size_t n_ob = (size_t)prob->n_obstacles * 18;
+    const size_t n_all = n_cand + n_tg + n_pen + n_ob;
     r->stage = pinned_get(ctx, n_all * sizeof(double), &r->stage_cls);
     double *buf = (double *)r->stage;
     if (!buf) {
@@ -412,9 +417,12 @@ extern "C" cpf_status cpf_submit(cpf_ctx *ctx, const cpf_robot *robot, const cpf
     r->cand = buf;
     r->targets = buf + n_cand;
     r->node_pen = n_pen ? buf + n_cand + n_tg : nullptr;
+    r->n_obs = prob->n_obstacles;
+    r->obstacles = n_ob ? buf + n_cand + n_tg + n_pen : nullptr;
     copy_parallel(r->cand, prob->cand, n_cand * sizeof(double));
     memcpy(r->targets, prob->targets, n_tg * sizeof(double));
     if (n_pen) copy_parallel(r->node_pen, prob->node_pen, n_pen * sizeof(double));
+    if (n_ob) memcpy(r->obstacles, prob->obstacles, n_ob * sizeof(double));
     r->bytes = bytes;
     r->t_submit = now_ns();
     {
