@@ -13,6 +13,10 @@
              beside the weighted objective.
   research   the T=300, K=256 request searched, 256 more candidates appended
              and the search repeated, against a fresh plan over all 512.
+  collision  the T=300, K=256 request with link capsules and six cuboid
+             obstacles: the collision checker over all candidates, the search
+             with the collision penalty and the LM with collision residuals,
+             beside the request without geometry.
   serve      Poisson arrivals (200 requests/s) of requests with T ~ U{50..2000},
              K in {128, 256, 512}, sigma ~ U[0.02, 0.15], offset fraction
              ~ U[0, 0.3] and 30 LM iterations, served by cpf_submit/cpf_poll
@@ -206,6 +210,50 @@ def run_research(K_add=256, reps=5):
     return out
 
 
+def run_collision(iters=50, n_obs=6, obstacle_seed=4):
+    """The T=300, K=256 request with a capsule on every link and six cuboid
+    obstacles: the collision checker over all K x T candidates, the search
+    with the collision penalty, and 50 LM iterations with the collision
+    residuals, both precisions, beside the same request without geometry."""
+    import torch
+    from paper_2309_09102_amd import cpf, synth
+    dev = torch.device("cuda:0")
+    ctx = cpf.Context(0)
+    p = _targets(ctx, synth.config2(), torch, dev)
+    coll = synth.collision_model(p.robot, synth.make_obstacles(obstacle_seed, n_obs))
+    out = {"mode": "collision", "T": p.T, "K": p.K, "n_obstacles": n_obs, "lm_iters": iters, "arms": {}}
+    q = p.cand.reshape(-1, 7)
+    for name, dt in (("checker_fp32", torch.float32), ("checker_fp64", torch.float64)):
+        qd = torch.tensor(q.T.copy(), dtype=dt, device=dev)
+        ctx.coll_batch(p.robot, coll, qd)                      # warm-up
+        ctx.profile(True)
+        dist, _ = ctx.coll_batch(p.robot, coll, qd)
+        torch.cuda.synchronize()
+        ms = ctx.kernel_stats("fk")[0]
+        ctx.profile(False)
+        out[name] = {"configs": q.shape[0], "kernel_ms": ms, "configs_per_s": q.shape[0] / (ms * 1e-3),
+                     "colliding_frac": float((dist < 0).any(dim=0).float().mean())}
+    for arm, prec, c in (("coll_mixed", "mixed", coll), ("coll_fp64", "fp64", coll), ("plain_mixed", "mixed", None)):
+        o = cpf.make_opts(prec=prec)
+        with ctx.plan(p.robot, p.targets, p.cand, opts=o, coll=c) as plan:
+            plan.dp_search()
+            plan.lm_refine(1)                                  # warm-up
+        with ctx.plan(p.robot, p.targets, p.cand, opts=o, coll=c) as plan:
+            ctx.profile(True)
+            t0 = time.perf_counter()
+            _, best, mj = plan.dp_search()
+            _, rep = plan.lm_refine(iters, want_xi=False)
+            t1 = time.perf_counter()
+            st = {k: ctx.kernel_stats(k)[0] for k in ("dp", "lm")}
+            ctx.profile(False)
+        out["arms"][arm] = {"latency_ms": (t1 - t0) * 1e3, "kernels_ms": st, "search_best": best,
+                            "seed_mjac": mj, "waypoint_lm_iters_per_s": p.T * iters / (st["lm"] * 1e-3),
+                            "pose_err_vs_targets": [rep["max_pos_err_m"], rep["max_rot_err_rad"]],
+                            "min_self_dist_m": rep["min_self_dist_m"], "min_env_dist_m": rep["min_env_dist_m"]}
+    ctx.close()
+    return out
+
+
 def _pct(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if xs else None
 
@@ -314,7 +362,8 @@ def run_serve(duration_s=10.0, rate_hz=200.0, pool=48, iters=30, slots=256, ipt=
 if __name__ == "__main__":
     import argparse
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["batch64", "T1000_K512", "batchopt", "schedule", "research", "serve"])
+    ap.add_argument("mode", choices=["batch64", "T1000_K512", "batchopt", "schedule", "research", "collision",
+                                     "serve"])
     ap.add_argument("--duration", type=float, default=10.0)
     a = ap.parse_args()
     if a.mode == "batch64":
@@ -327,5 +376,7 @@ if __name__ == "__main__":
         print(json.dumps(run_schedule()))
     elif a.mode == "research":
         print(json.dumps(run_research()))
+    elif a.mode == "collision":
+        print(json.dumps(run_collision()))
     else:
         print(json.dumps(run_serve(duration_s=a.duration)))
