@@ -26,6 +26,15 @@ template <typename S> __device__ __forceinline__ S contact_eps();
 template <> __device__ __forceinline__ double contact_eps<double>() { return 1e-9; }
 template <> __device__ __forceinline__ float contact_eps<float>() { return 1e-6f; }
 
+// A pair is skipped when a lower bound on its distance (bounding spheres of
+// the segments and of the cuboid) exceeds the smallest distance found so far
+// by more than this slack, which covers the bound's rounding: a skipped pair
+// is strictly farther than the minimum, so the minimum and its pair are those
+// of the full enumeration.
+template <typename S> __device__ __forceinline__ S cull_slack();
+template <> __device__ __forceinline__ double cull_slack<double>() { return 1e-9; }
+template <> __device__ __forceinline__ float cull_slack<float>() { return 1e-5f; }
+
 template <typename S>
 __device__ __forceinline__ S clamp01(S v) {
     return v < S(0) ? S(0) : (v > S(1) ? S(1) : v);
@@ -193,13 +202,33 @@ __device__ __forceinline__ void point_gradient(const S Zs[NJ][3], const S Os[NJ]
 }
 
 // Self and environment distances of configuration q (+inf where nothing is
-// checked) and, with GRAD, their gradients.
+// checked) and, with GRAD, their gradients.  With a finite `beyond`, pairs
+// provably farther than it are skipped as well: a minimum above `beyond` is
+// then reported as +inf (the residuals, which vanish beyond their margin,
+// need no more).
 template <typename S, bool GRAD, typename C>
 __device__ __forceinline__ void coll_distances(const RobotT<S> &rb, const C cap[NJ][7], int n_obs,
                                                const CPF_GLOBAL double *__restrict__ obs, const S *q, S dmin[2],
-                                               S grad[2][NJ]) {
+                                               S grad[2][NJ], S beyond = __builtin_inf()) {
     S Zs[NJ][3], Os[NJ][3], P0[NJ][3], P1[NJ][3];
     capsule_chain(rb, cap, q, Zs, Os, P0, P1);
+    // bounding sphere of each capsule: centre and radius (half length + r)
+    S cc[NJ][3], cr[NJ];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+        S h2 = S(0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            cc[i][k] = S(0.5) * (P0[i][k] + P1[i][k]);
+            const S h = S(0.5) * (P1[i][k] - P0[i][k]);
+            h2 += h * h;
+        }
+        cr[i] = sqrt(h2) + (S)cap[i][6];
+    }
+    auto gap = [&](const S a[3], const S b[3]) {
+        const S x = a[0] - b[0], y = a[1] - b[1], z = a[2] - b[2];
+        return sqrt(x * x + y * y + z * z);
+    };
     dmin[0] = __builtin_inf();
     dmin[1] = __builtin_inf();
     int bi = -1, bj = 0;
@@ -208,6 +237,7 @@ __device__ __forceinline__ void coll_distances(const RobotT<S> &rb, const C cap[
     for (int i = 0; i < NJ; ++i)
 #pragma unroll
         for (int j = i + 3; j < NJ; ++j) {
+            if (gap(cc[i], cc[j]) - cr[i] - cr[j] > fmin(dmin[0], beyond) + cull_slack<S>()) continue;
             S s, t;
             const S d = sqrt(seg_seg_d2(P0[i], P1[i], P0[j], P1[j], s, t)) - (S)cap[i][6] - (S)cap[j][6];
             if (d < dmin[0]) {
@@ -231,8 +261,23 @@ __device__ __forceinline__ void coll_distances(const RobotT<S> &rb, const C cap[
         }
 #pragma unroll
         for (int k = 0; k < 9; ++k) R[k] = (S)B[3 + k];
+        // the cuboid's bounding sphere: world centre and half diagonal
+        S bc[3], bh2 = S(0);
+        {
+            S m[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                m[k] = S(0.5) * (lo[k] + hi[k]);
+                const S h = S(0.5) * (hi[k] - lo[k]);
+                bh2 += h * h;
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) bc[k] = o[k] + R[3 * k] * m[0] + R[3 * k + 1] * m[1] + R[3 * k + 2] * m[2];
+        }
+        const S br = sqrt(bh2);
 #pragma unroll
         for (int i = 0; i < NJ; ++i) {
+            if (gap(cc[i], bc) - cr[i] - br > fmin(dmin[1], beyond) + cull_slack<S>()) continue;
             S A[3], D[3];
 #pragma unroll
             for (int r = 0; r < 3; ++r) {   // R^T (P0 - o), R^T (P1 - P0)

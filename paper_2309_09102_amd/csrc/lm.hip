@@ -94,7 +94,7 @@ template <typename S, bool GRAD>
 __device__ __forceinline__ void coll_residuals(const DevPlan &P, const RobotT<S> &rb, const S q[NJ], double rc[2],
                                                double Jc[2][NJ]) {
     S dm[2], g[2][NJ];
-    coll_distances<S, GRAD>(rb, CapsOf<S>::get(P), P.n_obs, P.obs, q, dm, g);
+    coll_distances<S, GRAD>(rb, CapsOf<S>::get(P), P.n_obs, P.obs, q, dm, g, (S)P.coll_margin);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const double r = P.coll_margin - (double)dm[h];
