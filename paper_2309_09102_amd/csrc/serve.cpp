@@ -7,11 +7,12 @@
 //      memory budget, take an arena from the pool and upload the request on
 //      the upload stream; the admitted requests are searched in one launch
 //      there (one workgroup per request), while
-//   2. the LM stream replays the tick graph over the work list:
-//      lm_kernel<float> and lm_kernel<double> over every slot (each skips
-//      empty slots and the other precision), every plan advancing up to
-//      `iters_per_tick` iterations, then the report kernel for plans that
-//      just finished;
+//   2. the LM stream replays a tick graph over the work list: the LM kernel
+//      instances of both precisions, for the kinds of plan in the table
+//      (weighted objective or schedule, with or without collision
+//      geometry), over every slot (each instance skips empty slots and the
+//      other instances' plans), every plan advancing up to `iters_per_tick`
+//      iterations, then the report kernel for plans that just finished;
 //   3. a searched batch joins the work list at the next tick (its
 //      descriptors are written into their slots on the LM stream);
 //   4. after each tick all slot states come back in one copy, and the
@@ -19,9 +20,11 @@
 //      go back to the pool).
 // Requests submitted while the GPU is busy join at the next tick, so their
 // search and iterations overlap on the device with the requests in flight.
-// The graph is captured once per context: its kernels read the work list
-// from device memory, so admissions and retirements only rewrite descriptor
-// slots between replays.
+// A graph is captured once per context and combination of plan kinds (at
+// its first use): its kernels read the work list from device memory, so
+// admissions and retirements only rewrite descriptor slots between replays,
+// and a table of plain plans never launches the other kinds' instances
+// (whose larger scratch needs slow every dispatch).
 #include <algorithm>
 #include <cstring>
 #include <memory>
@@ -68,8 +71,9 @@ struct Server {
     std::vector<LMState> h_states, h_init;
     std::vector<Request *> slot_req;
     std::vector<Request *> searching;   // the batch in flight on s_up
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    // tick graphs by kinds present: bit 0 schedule, bit 1 collision geometry
+    hipGraph_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipGraphExec_t exec[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
 namespace {
@@ -94,27 +98,38 @@ cpf_status server_init(cpf_ctx *ctx, Server *sv) {
     HIP_TRY(hipMemcpyAsync(sv->d_states, sv->h_states.data(), sizeof(LMState) * sv->cap,
                            hipMemcpyHostToDevice, sv->s_lm));
     HIP_TRY(hipStreamSynchronize(sv->s_lm));
-    // Capture the LM tick: both precisions, both objective kinds, with and
-    // without collision geometry, over every slot (each instance skips the
-    // slots of the others), then the report for plans that finished in this
-    // tick.
-    HIP_TRY(hipStreamBeginCapture(sv->s_lm, hipStreamCaptureModeThreadLocal));
-    hipError_t e = hipSuccess;
-    for (int k = 0; k < 8 && e == hipSuccess; ++k)
-        e = lm_launch(sv->d_work, sv->cap, k & 1, (k >> 1) & 1, k >> 2, sv->ipt, sv->s_lm);
-    for (int c = 0; c < 2 && e == hipSuccess; ++c) e = eval_launch(sv->d_work, sv->cap, 1, c, sv->s_lm);
-    hipError_t e2 = hipStreamEndCapture(sv->s_lm, &sv->graph);
-    if (e != hipSuccess) return fail(CPF_E_DEVICE, "tick capture: %s", hipGetErrorString(e));
-    if (e2 != hipSuccess) return fail(CPF_E_DEVICE, "tick capture end: %s", hipGetErrorString(e2));
-    HIP_TRY(hipGraphInstantiate(&sv->exec, sv->graph, nullptr, nullptr, 0));
+    return CPF_OK;
+}
+
+// The tick graph for the plan kinds in `kinds` (bit 0 schedule, bit 1
+// collision geometry), captured at its first use: the LM instances of both
+// precisions for those kinds and the plain ones, then the report kernels.
+cpf_status tick_graph(Server *sv, int kinds, hipGraphExec_t *out) {
+    if (!sv->exec[kinds]) {
+        HIP_TRY(hipStreamBeginCapture(sv->s_lm, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipSuccess;
+        for (int coll = 0; coll <= ((kinds >> 1) & 1); ++coll)
+            for (int sched = 0; sched <= (kinds & 1); ++sched)
+                for (int prec = 0; prec < 2 && e == hipSuccess; ++prec)
+                    e = lm_launch(sv->d_work, sv->cap, prec, sched, coll, sv->ipt, sv->s_lm);
+        for (int coll = 0; coll <= ((kinds >> 1) & 1) && e == hipSuccess; ++coll)
+            e = eval_launch(sv->d_work, sv->cap, 1, coll, sv->s_lm);
+        hipError_t e2 = hipStreamEndCapture(sv->s_lm, &sv->graph[kinds]);
+        if (e != hipSuccess) return fail(CPF_E_DEVICE, "tick capture: %s", hipGetErrorString(e));
+        if (e2 != hipSuccess) return fail(CPF_E_DEVICE, "tick capture end: %s", hipGetErrorString(e2));
+        HIP_TRY(hipGraphInstantiate(&sv->exec[kinds], sv->graph[kinds], nullptr, nullptr, 0));
+    }
+    *out = sv->exec[kinds];
     return CPF_OK;
 }
 
 void server_free(Server *sv) {
     if (sv->s_up) HIP_IGNORE(hipStreamSynchronize(sv->s_up));
     if (sv->s_lm) HIP_IGNORE(hipStreamSynchronize(sv->s_lm));
-    if (sv->exec) HIP_IGNORE(hipGraphExecDestroy(sv->exec));
-    if (sv->graph) HIP_IGNORE(hipGraphDestroy(sv->graph));
+    for (int g = 0; g < 4; ++g) {
+        if (sv->exec[g]) HIP_IGNORE(hipGraphExecDestroy(sv->exec[g]));
+        if (sv->graph[g]) HIP_IGNORE(hipGraphDestroy(sv->graph[g]));
+    }
     if (sv->searched) HIP_IGNORE(hipEventDestroy(sv->searched));
     if (sv->d_work) HIP_IGNORE(hipFree(sv->d_work));
     if (sv->d_states) HIP_IGNORE(hipFree(sv->d_states));
@@ -332,13 +347,17 @@ void server_main(cpf_ctx *ctx) {
         }
         if (active.empty()) continue;
         // 3. one LM tick over every slot, then all slot states in one copy
-        cpf_status dev = CPF_OK;
-        hipError_t e = timed(ctx, KIND_LM, sv->s_lm, [&] { return hipGraphLaunch(sv->exec, sv->s_lm); });
+        int kinds = 0;
+        for (Request *r : active) kinds |= (r->opts.schedule ? 1 : 0) | (r->robot.has_caps ? 2 : 0);
+        hipGraphExec_t exec = nullptr;
+        cpf_status dev = tick_graph(sv.get(), kinds, &exec);
+        hipError_t e = dev == CPF_OK ? hipSuccess : hipErrorUnknown;
+        if (e == hipSuccess) e = timed(ctx, KIND_LM, sv->s_lm, [&] { return hipGraphLaunch(exec, sv->s_lm); });
         if (e == hipSuccess)
             e = hipMemcpyAsync(sv->h_states.data(), sv->d_states, sizeof(LMState) * sv->cap,
                                hipMemcpyDeviceToHost, sv->s_lm);
         if (e == hipSuccess) e = hipStreamSynchronize(sv->s_lm);
-        if (e != hipSuccess) dev = fail(CPF_E_DEVICE, "LM tick: %s", hipGetErrorString(e));
+        if (dev == CPF_OK && e != hipSuccess) dev = fail(CPF_E_DEVICE, "LM tick: %s", hipGetErrorString(e));
         // 4. retire finished (or failed) requests together
         std::vector<Request *> still, fin;
         for (Request *r : active) {
