@@ -72,3 +72,33 @@ def test_batch64_sampled_vs_oracle_and_alone(ctx):
             plan.dp_search()
             xi, _ = plan.lm_refine(30)
         assert np.array_equal(xi, res[i]["xi"])
+
+
+def test_search_at_the_candidate_limit(ctx):
+    """K = 1024 (the search's limit) at T = 300: index-identical to the oracle."""
+    p = H.with_targets(synth.make_problem(synth.make_robot(0), seed=31, T=300, K=1024, sigma=0.1,
+                                          branch_frac=0.25))
+    path_ref, best_ref, _, _ = oracle.dp(p.cand, p.robot)
+    with ctx.plan(p.robot, p.targets, p.cand) as plan:
+        path, best, _ = plan.dp_search()
+    assert np.array_equal(path, path_ref) and best == best_ref
+
+
+def test_longest_served_path_vs_oracle(ctx):
+    """T = 2000 (the longest request of the serving stream), K = 128: search
+    index-identical, and after 150 LM iterations both arms within the
+    refinement tolerances.  Over 2000 waypoints the differencing term's
+    slowest modes (eigenvalues near w_s (pi / T)^2) are still moving after
+    20 or 50 iterations, and there the mixed arm's cost differs by 6e-6 and
+    1.1e-6 mid-descent."""
+    p = H.with_targets(synth.make_problem(synth.make_robot(0), seed=32, T=2000, K=128, sigma=0.08,
+                                          branch_frac=0.25))
+    path_ref, best_ref, _, _ = oracle.dp(p.cand, p.robot)
+    ref = oracle.lm(p.robot, H.seed_of(p, path_ref), p.targets, 150)
+    for prec in ("fp64", "mixed"):
+        with ctx.plan(p.robot, p.targets, p.cand, opts=cpf.make_opts(prec=prec)) as plan:
+            path, best, _ = plan.dp_search()
+            xi, rep = plan.lm_refine(150)
+        assert np.array_equal(path, path_ref) and best == best_ref
+        ep, er, ec = H.parity_metrics(p, xi, ref["xi"])
+        assert ep <= 1e-5 and er <= 1e-5 and ec <= 1e-6, (prec, ep, er, ec)
