@@ -159,8 +159,9 @@ def main():
 
         def step():
             ctx.fk_batch(prob.robot, cand_soa)          # batched FK over the K x T candidates
-            plan.dp_search()                             # search, back-track, seed
-            return plan.lm_refine(iters, want_xi=False)  # LM iterations + report
+            # search, back-track, seed, LM iterations and report in one stream
+            _, _, xi, rep = plan.solve(want_xi=False)
+            return xi, rep
 
         for _ in range(args.warmup):
             step()

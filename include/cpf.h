@@ -257,6 +257,14 @@ cpf_status cpf_plan_append(cpf_plan *plan, int32_t K_add, const double *cand_add
  * Sec. III-C.  Synchronous. */
 cpf_status cpf_lm_refine(cpf_plan *plan, int32_t iters, double *xi_out, cpf_lm_report *rep);
 
+/* The whole refinement of one plan (Sec. III-B then III-C): the search, then
+ * opts.iters LM iterations from its seed (restarting the LM state) and the
+ * report, queued in one stream with a single synchronisation at the end.
+ * path_out [T], best_out, xi_out [T][dof], rep: each may be NULL.
+ * Synchronous; CPF_E_NUMERIC as cpf_lm_refine. */
+cpf_status cpf_plan_solve(cpf_plan *plan, int32_t *path_out, double *best_out, double *xi_out,
+                          cpf_lm_report *rep);
+
 /* Latest valid trajectory of a plan refined with opts.schedule = 1 (the
  * anytime result of Sec. III-C's alternating objective), written to xi_out
  * [T][dof] (caller-owned, not NULL).  CPF_E_STATE if the plan does not use

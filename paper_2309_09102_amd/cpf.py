@@ -91,6 +91,7 @@ _lib.cpf_fk_batch.argtypes = [_vp, C.POINTER(cpf_robot), C.c_int64, C.c_int32, _
 _lib.cpf_dp_search.argtypes = [_vp, _ip, _dp, _dp]
 _lib.cpf_lm_refine.argtypes = [_vp, C.c_int32, _dp, C.POINTER(cpf_lm_report)]
 _lib.cpf_lm_latest_valid.argtypes = [_vp, _dp]
+_lib.cpf_plan_solve.argtypes = [_vp, _ip, _dp, _dp, C.POINTER(cpf_lm_report)]
 _lib.cpf_plan_append.argtypes = [_vp, C.c_int32, _dp, _dp]
 _lib.cpf_coll_batch.argtypes = [_vp, C.POINTER(cpf_robot), C.c_int32, _vp, C.c_int64, C.c_int32, _vp, _vp,
                                 _vp, _vp]
@@ -106,16 +107,16 @@ _lib.cpf_ctx_profile.argtypes = [_vp, C.c_int32]
 _lib.cpf_ctx_kernel_stats.argtypes = [_vp, C.c_char_p, C.POINTER(C.c_double),
                                       C.POINTER(C.c_int64)]
 for _f in ("cpf_ctx_create", "cpf_plan_init", "cpf_fk_batch", "cpf_dp_search", "cpf_lm_refine",
-           "cpf_lm_latest_valid", "cpf_plan_append", "cpf_coll_batch",
+           "cpf_lm_latest_valid", "cpf_plan_append", "cpf_coll_batch", "cpf_plan_solve",
            "cpf_solve_batch", "cpf_batchopt", "cpf_submit", "cpf_poll", "cpf_ctx_profile",
            "cpf_ctx_kernel_stats", "cpf_ctx_config"):
     getattr(_lib, _f).restype = C.c_int
 
 EXPORTS = ("cpf_opts_default", "cpf_last_error", "cpf_ctx_create", "cpf_ctx_destroy",
            "cpf_ctx_bytes_in_use", "cpf_plan_init", "cpf_plan_free", "cpf_fk_batch", "cpf_coll_batch",
-           "cpf_dp_search", "cpf_plan_append", "cpf_lm_refine", "cpf_lm_latest_valid", "cpf_solve_batch",
-           "cpf_batchopt", "cpf_submit",
-           "cpf_poll", "cpf_ctx_profile", "cpf_ctx_kernel_stats", "cpf_ctx_config")
+           "cpf_dp_search", "cpf_plan_append", "cpf_lm_refine", "cpf_plan_solve", "cpf_lm_latest_valid",
+           "cpf_solve_batch", "cpf_batchopt", "cpf_submit", "cpf_poll", "cpf_ctx_profile",
+           "cpf_ctx_kernel_stats", "cpf_ctx_config")
 
 
 def last_error() -> str:
@@ -298,6 +299,18 @@ def plan_append(plan, T: int, cand_add, node_pen_add=None):
     if npen is not None and npen.shape != (T, cd.shape[0]):
         raise ValueError(f"node_pen_add must be [{T}][{cd.shape[0]}], got {npen.shape}")
     _check(_lib.cpf_plan_append(plan, int(cd.shape[0]), _ptr(cd), _ptr(npen)))
+
+
+def plan_solve(plan, T: int, want_xi: bool = True):
+    """Search + opts.iters LM iterations + report -> (path, B*, xi | None, report)."""
+    path = np.empty(T, dtype=np.int32)
+    best = C.c_double()
+    xi = np.empty((T, 7)) if want_xi else None
+    rep = cpf_lm_report()
+    st = _lib.cpf_plan_solve(plan, path.ctypes.data_as(_ip), C.byref(best), _ptr(xi), C.byref(rep))
+    if st != OK:
+        raise CpfError(st, last_error())
+    return path, best.value, xi, _report(rep)
 
 
 def lm_latest_valid(plan, T: int):
@@ -485,6 +498,9 @@ class Plan:
 
     def latest_valid(self):
         return lm_latest_valid(self.h, self.T)
+
+    def solve(self, want_xi: bool = True):
+        return plan_solve(self.h, self.T, want_xi)
 
     def append(self, cand_add, node_pen_add=None):
         plan_append(self.h, self.T, cand_add, node_pen_add)

@@ -717,6 +717,29 @@ cpf_status cpf_lm_refine(cpf_plan *plan, int32_t iters, double *xi_out, cpf_lm_r
     return CPF_OK;
 }
 
+cpf_status cpf_plan_solve(cpf_plan *plan, int32_t *path_out, double *best_out, double *xi_out,
+                          cpf_lm_report *rep) {
+    if (!plan) return fail(CPF_E_ARG, "plan is NULL");
+    cpf_ctx *ctx = plan->ctx;
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const bool coll = plan->robot.has_caps;
+    HIP_TRY(timed(ctx, KIND_DP, s, [&] { return dp_launch(plan->d_desc, 1, plan->K, plan->T, plan->lists_valid, coll, s); }));
+    plan->lists_valid = true;
+    HIP_TRY(timed(ctx, KIND_LM, s, [&] {
+        return lm_launch(plan->d_desc, 1, plan->opts.prec, plan->opts.schedule, coll, plan->opts.iters, s);
+    }));
+    HIP_TRY(timed(ctx, KIND_EVAL, s, [&] { return eval_launch(plan->d_desc, 1, 0, coll, s); }));
+    PlanReadback rb;
+    cpf_status st = read_plan(plan, s, nullptr, &rb, xi_out, path_out, nullptr);
+    if (st != CPF_OK) return st;
+    plan->searched = true;
+    if (best_out) *best_out = rb.dp_out[0];
+    if (rep) fill_report(rb, rep);
+    if (rb.st.status != 0) return fail(CPF_E_NUMERIC, "non-positive pivot in the block solve");
+    return CPF_OK;
+}
+
 cpf_status cpf_lm_latest_valid(cpf_plan *plan, double *xi_out) {
     if (!plan || !xi_out) return fail(CPF_E_ARG, "plan / xi_out is NULL");
     if (!plan->opts.schedule) return fail(CPF_E_STATE, "plan was not created with opts.schedule = 1");

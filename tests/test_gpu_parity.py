@@ -195,6 +195,19 @@ def test_lm_resumable_bitwise(ctx):
     assert np.array_equal(xa, xb) and ra["cost"] == rb["cost"] and rb["iters_done"] == 30
 
 
+def test_plan_solve_equals_search_then_refine(ctx):
+    p = H.small_problem(seed=53, T=120, K=40)
+    opts = cpf.make_opts(iters=25)
+    with ctx.plan(p.robot, p.targets, p.cand, opts=opts) as a, ctx.plan(p.robot, p.targets, p.cand, opts=opts) as b:
+        pa, ba, xa, ra = a.solve()
+        pb, bb, _ = b.dp_search()
+        xb, rb = b.lm_refine(25)
+        pa2, ba2, xa2, ra2 = a.solve()            # a second solve restarts from the search
+    assert np.array_equal(pa, pb) and ba == bb
+    assert np.array_equal(xa, xb) and ra["cost"] == rb["cost"] and ra["iters_done"] == 25
+    assert np.array_equal(pa2, pa) and np.array_equal(xa2, xa) and ra2["iters_done"] == 25
+
+
 def test_lm_before_search_is_state_error(ctx):
     p = H.small_problem(seed=51, T=10, K=4)
     with ctx.plan(p.robot, p.targets, p.cand) as plan:
