@@ -221,6 +221,22 @@ cpf_status check_robot(const cpf_robot *r, HostRobot *out) {
     return CPF_OK;
 }
 
+hipError_t event_pair(cpf_ctx *ctx, hipEvent_t *a, hipEvent_t *b) {
+    {
+        std::lock_guard<std::mutex> lk(ctx->prof_mu);
+        if (ctx->ev_free.size() >= 2) {
+            *a = ctx->ev_free.back();
+            ctx->ev_free.pop_back();
+            *b = ctx->ev_free.back();
+            ctx->ev_free.pop_back();
+            return hipSuccess;
+        }
+    }
+    hipError_t e = hipEventCreate(a);
+    if (e == hipSuccess) e = hipEventCreate(b);
+    return e;
+}
+
 cpf_status check_obstacles(int32_t n, const double *obs) {
     if (n < 0 || n > MAX_OBS) return fail(CPF_E_ARG, "n_obstacles=%d must be in [0, %d]", n, MAX_OBS);
     if (n > 0 && !obs) return fail(CPF_E_ARG, "obstacles is NULL");
@@ -512,6 +528,8 @@ void cpf_ctx_destroy(cpf_ctx *ctx) {
     server_stop_and_join(ctx);
     HIP_IGNORE(hipSetDevice(ctx->device));
     cpf_ctx_profile(ctx, 0);
+    for (hipEvent_t ev : ctx->ev_free) HIP_IGNORE(hipEventDestroy(ev));
+    ctx->ev_free.clear();
     if (ctx->stream) HIP_IGNORE(hipStreamSynchronize(ctx->stream));
     pool_clear(ctx);
     if (ctx->stream) HIP_IGNORE(hipStreamDestroy(ctx->stream));
@@ -898,8 +916,8 @@ cpf_status cpf_ctx_profile(cpf_ctx *ctx, int32_t enable) {
     std::lock_guard<std::mutex> lk(ctx->prof_mu);
     for (auto &ev : ctx->events) {
         HIP_IGNORE(hipEventSynchronize(ev.b));
-        HIP_IGNORE(hipEventDestroy(ev.a));
-        HIP_IGNORE(hipEventDestroy(ev.b));
+        ctx->ev_free.push_back(ev.a);
+        ctx->ev_free.push_back(ev.b);
     }
     ctx->events.clear();
     for (int i = 0; i < 4; ++i) {
@@ -925,8 +943,8 @@ cpf_status cpf_ctx_kernel_stats(cpf_ctx *ctx, const char *kernel, double *total_
         HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
         ctx->prof_ms[ev.kind] += ms;
         ctx->prof_n[ev.kind] += 1;
-        HIP_IGNORE(hipEventDestroy(ev.a));
-        HIP_IGNORE(hipEventDestroy(ev.b));
+        ctx->ev_free.push_back(ev.a);
+        ctx->ev_free.push_back(ev.b);
     }
     ctx->events.clear();
     if (total_ms) *total_ms = ctx->prof_ms[kind];

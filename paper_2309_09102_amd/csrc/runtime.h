@@ -94,6 +94,7 @@ struct cpf_ctx {
         hipEvent_t a, b;
     };
     std::vector<Ev> events;
+    std::vector<hipEvent_t> ev_free;   // created events ready for reuse (no create in a timed launch)
     double prof_ms[4] = {0, 0, 0, 0};
     int64_t prof_n[4] = {0, 0, 0, 0};
 
@@ -116,13 +117,15 @@ struct cpf_plan {
 
 namespace cpf {
 
+// A pair of events from the context's pool (created when it is empty).
+hipError_t event_pair(cpf_ctx *ctx, hipEvent_t *a, hipEvent_t *b);
+
 // Launch through `launch`; with profiling on, bracket it with events on s.
 template <class F>
 hipError_t timed(cpf_ctx *ctx, int kind, hipStream_t s, F &&launch) {
     if (!ctx->prof.load()) return launch();
     hipEvent_t a = nullptr, b = nullptr;
-    hipError_t e = hipEventCreate(&a);
-    if (e == hipSuccess) e = hipEventCreate(&b);
+    hipError_t e = event_pair(ctx, &a, &b);
     if (e == hipSuccess) e = hipEventRecord(a, s);
     if (e != hipSuccess) return e;
     e = launch();
