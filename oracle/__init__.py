@@ -7,7 +7,8 @@ the HIP path and imports nothing from it.
 The arithmetic lives in ``cpf_oracle.c`` (plain C, IEEE double,
 ``-ffp-contract=off``); this module builds it with gcc and wraps it with
 ctypes.  Robots are duck-typed objects with float64 arrays ``a, d, alpha,
-theta_off, q_lo, q_hi``.
+theta_off, q_lo, q_hi`` and optionally ``joint_type`` (0 revolute, 1
+prismatic).
 
 Parity status per function (what pins it, in tests/test_oracle_pins.py):
   fk / jacobian   closed forms at q = 0, single-axis and planar chains;
@@ -31,13 +32,17 @@ Parity status per function (what pins it, in tests/test_oracle_pins.py):
   coll_eval       capsule endpoints vs FK of the truncated chains, distances vs
                   scipy, gradients vs central differences; adjacent links
                   never checked; the search penalty vs brute force
+  prismatic       FK translation along the closed-form axis; pure translation
+  joints          anywhere; Jacobian, LM gradient and collision gradients vs
+                  central differences; 3 cm limit margin and 2 cm validity
+                  step by constructed cases; seed steps split by joint type
 """
-from .oracle import (build, lib_path, fk, log_so3, cost, dp, mjac, btd_solve,
+from .oracle import (build, lib_path, fk, log_so3, cost, dp, mjac, seed_steps, joint_types, btd_solve,
                      lm_step, lm, lm_schedule, plan, batchopt, pose_compare,
                      seg_seg, seg_box, coll_eval, coll_spec,
                      DEFAULT_LM, VALID_TOL, COLL_MARGIN, COLL_WEIGHT, COLL_PENALTY)
 
-__all__ = ["build", "lib_path", "fk", "log_so3", "cost", "dp", "mjac",
+__all__ = ["build", "lib_path", "fk", "log_so3", "cost", "dp", "mjac", "seed_steps", "joint_types",
            "btd_solve", "lm_step", "lm", "lm_schedule", "plan", "batchopt", "pose_compare",
            "seg_seg", "seg_box", "coll_eval", "coll_spec",
            "DEFAULT_LM", "VALID_TOL", "COLL_MARGIN", "COLL_WEIGHT", "COLL_PENALTY"]

@@ -11,7 +11,8 @@
  *
  * Contents and the passages they follow:
  *   or_fk          forward kinematics FK(q) : R^n -> SE(3)          Sec. II
- *                  (standard distal Denavit-Hartenberg chain)
+ *                  (standard distal Denavit-Hartenberg chain of revolute
+ *                  and prismatic joints, Sec. IV's Fetch.Full torso lift)
  *                  and the geometric (kinematic) Jacobian J_fk      Sec. III-C
  *   or_log_so3     rotation vector of a rotation matrix; its norm is the
  *                  geodesic rotation error used as the validity metric Sec. II
@@ -86,18 +87,33 @@ static void tf_mul(const double A[12], const double B[12], double C[12]) {
 /*
  * pose[12] = (x, y, z, R00, R01, R02, R10, ..., R22) of the end effector.
  * J (optional) is 6 x n row-major: rows vx, vy, vz, wx, wy, wz; column i is
- * z_{i-1} x (p - o_{i-1}) over z_{i-1}, the axis and origin of joint i.
+ * z_{i-1} x (p - o_{i-1}) over z_{i-1}, the axis and origin of joint i, for
+ * a revolute joint and z_{i-1} over 0 for a prismatic one.
+ * jtype (optional, NULL = all revolute): 1 marks a prismatic joint, whose
+ * value is added to the link's offset d while its angle stays at theta_off;
+ * a revolute joint's value is added to theta_off.
  */
+static int prismatic(const int32_t *jtype, int i) { return jtype && jtype[i] == 1; }
+
+/* DH angle and offset of link i at joint value qi. */
+static void joint_dh(const int32_t *jtype, const double *d, const double *theta_off, int i, double qi,
+                     double *th, double *di) {
+    double off = theta_off ? theta_off[i] : 0.0;
+    if (prismatic(jtype, i)) { *th = off; *di = d[i] + qi; }
+    else { *th = qi + off; *di = d[i]; }
+}
+
 void or_fk(int n, const double *a, const double *d, const double *alpha,
-           const double *theta_off, const double *q, double *pose, double *J) {
+           const double *theta_off, const int32_t *jtype, const double *q, double *pose, double *J) {
     double M[12], A[12];
     double z[OR_MAXN][3], o[OR_MAXN][3];
     tf_identity(M);
     for (int i = 0; i < n; ++i) {
         z[i][0] = M[2]; z[i][1] = M[6]; z[i][2] = M[10];
         o[i][0] = M[3]; o[i][1] = M[7]; o[i][2] = M[11];
-        double th = q[i] + (theta_off ? theta_off[i] : 0.0);
-        dh_link(th, d[i], a[i], alpha[i], A);
+        double th, di;
+        joint_dh(jtype, d, theta_off, i, q[i], &th, &di);
+        dh_link(th, di, a[i], alpha[i], A);
         tf_mul(M, A, M);
     }
     pose[0] = M[3]; pose[1] = M[7]; pose[2] = M[11];
@@ -106,6 +122,15 @@ void or_fk(int n, const double *a, const double *d, const double *alpha,
     pose[9] = M[8]; pose[10] = M[9]; pose[11] = M[10];
     if (J) {
         for (int i = 0; i < n; ++i) {
+            if (prismatic(jtype, i)) {
+                J[0 * n + i] = z[i][0];
+                J[1 * n + i] = z[i][1];
+                J[2 * n + i] = z[i][2];
+                J[3 * n + i] = 0.0;
+                J[4 * n + i] = 0.0;
+                J[5 * n + i] = 0.0;
+                continue;
+            }
             double dx = pose[0] - o[i][0], dy = pose[1] - o[i][1], dz = pose[2] - o[i][2];
             J[0 * n + i] = z[i][1] * dz - z[i][2] * dy;
             J[1 * n + i] = z[i][2] * dx - z[i][0] * dz;
@@ -211,7 +236,9 @@ static void coll_parse(int n, const double *spec, or_coll *c) {
 
 typedef struct {
     int n;
-    const double *a, *d, *alpha, *theta_off, *lo, *hi;
+    const double *a, *d, *alpha, *theta_off;
+    const int32_t *jtype;  /* NULL: all revolute */
+    const double *lo, *hi;
     const or_coll *coll;   /* NULL: no collision geometry */
 } or_robot;
 
@@ -219,7 +246,7 @@ typedef struct {
 static void pose_residual(const or_robot *rb, const double *q, const double *target,
                           double *r, double *J6) {
     double pose[12];
-    or_fk(rb->n, rb->a, rb->d, rb->alpha, rb->theta_off, q, pose, J6);
+    or_fk(rb->n, rb->a, rb->d, rb->alpha, rb->theta_off, rb->jtype, q, pose, J6);
     r[0] = pose[0] - target[0];
     r[1] = pose[1] - target[1];
     r[2] = pose[2] - target[2];
@@ -362,8 +389,9 @@ static void link_frames(const or_robot *rb, const double *q, double z[][3], doub
     for (int i = 0; i < rb->n; ++i) {
         z[i][0] = M[2]; z[i][1] = M[6]; z[i][2] = M[10];
         o[i][0] = M[3]; o[i][1] = M[7]; o[i][2] = M[11];
-        double th = q[i] + (rb->theta_off ? rb->theta_off[i] : 0.0);
-        dh_link(th, rb->d[i], rb->a[i], rb->alpha[i], A);
+        double th, di;
+        joint_dh(rb->jtype, rb->d, rb->theta_off, i, q[i], &th, &di);
+        dh_link(th, di, rb->a[i], rb->alpha[i], A);
         tf_mul(M, A, M);
         memcpy(F[i], M, sizeof(M));
     }
@@ -375,10 +403,16 @@ static void frame_point(const double F[12], const double p[3], double w[3]) {
 }
 
 /* Gradient contribution of moving the point w, carried by link `lnk`:
- * g[k] += sgn * u . (z_k x (w - o_k)) for the joints k <= lnk. */
-static void point_grad(const double z[][3], const double o[][3], int lnk, const double w[3], const double u[3],
-                       double sgn, double *g) {
+ * g[k] += sgn * u . (z_k x (w - o_k)) for the revolute joints k <= lnk and
+ * sgn * u . z_k for the prismatic ones (the point's velocity per unit of
+ * joint k). */
+static void point_grad(const int32_t *jtype, const double z[][3], const double o[][3], int lnk, const double w[3],
+                       const double u[3], double sgn, double *g) {
     for (int k = 0; k <= lnk; ++k) {
+        if (prismatic(jtype, k)) {
+            g[k] += sgn * (u[0] * z[k][0] + u[1] * z[k][1] + u[2] * z[k][2]);
+            continue;
+        }
         double v[3] = {w[0] - o[k][0], w[1] - o[k][1], w[2] - o[k][2]};
         double c0 = z[k][1] * v[2] - z[k][2] * v[1];
         double c1 = z[k][2] * v[0] - z[k][0] * v[2];
@@ -437,8 +471,8 @@ static void coll_eval(const or_robot *rb, const double *q, double dmin[2], doubl
         nrm = sqrt(nrm);
         if (nrm > OR_CONTACT_EPS) {
             for (int k = 0; k < 3; ++k) u[k] /= nrm;
-            point_grad(z, o, bi, pa, u, 1.0, grad);
-            point_grad(z, o, bj, pb, u, -1.0, grad);
+            point_grad(rb->jtype, z, o, bi, pa, u, 1.0, grad);
+            point_grad(rb->jtype, z, o, bj, pb, u, -1.0, grad);
         }
     }
     int li = -1, ob = -1;
@@ -474,7 +508,7 @@ static void coll_eval(const or_robot *rb, const double *q, double dmin[2], doubl
         nrm = sqrt(nrm);
         if (nrm > OR_CONTACT_EPS) {
             for (int k = 0; k < 3; ++k) u[k] /= nrm;
-            point_grad(z, o, li, pa, u, 1.0, grad + n);
+            point_grad(rb->jtype, z, o, li, pa, u, 1.0, grad + n);
         }
     }
 }
@@ -520,10 +554,10 @@ static double cost_of(const or_robot *rb, int T, const double *xi, const double 
 }
 
 double or_cost(int n, const double *a, const double *d, const double *alpha,
-               const double *theta_off, int T, const double *xi, const double *targets,
+               const double *theta_off, const int32_t *jtype, int T, const double *xi, const double *targets,
                double w_p, double w_s, const double *coll) {
     or_coll cg;
-    or_robot rb = {n, a, d, alpha, theta_off, NULL, NULL, NULL};
+    or_robot rb = {n, a, d, alpha, theta_off, jtype, NULL, NULL, NULL};
     if (coll) { coll_parse(n, coll, &cg); rb.coll = &cg; }
     return cost_of(&rb, T, xi, targets, w_p, w_s, rb.coll ? cg.w_c : 0.0);
 }
@@ -531,11 +565,11 @@ double or_cost(int n, const double *a, const double *d, const double *alpha,
 /* Collision distances of M configurations q[M][n]: out[M][2] (self, env)
  * and optionally their gradients grad[M][2][n] (see coll_eval). */
 void or_coll_eval(int n, const double *a, const double *d, const double *alpha,
-                  const double *theta_off, const double *coll, long M, const double *q, double *out,
-                  double *grad) {
+                  const double *theta_off, const int32_t *jtype, const double *coll, long M, const double *q,
+                  double *out, double *grad) {
     or_coll cg;
     coll_parse(n, coll, &cg);
-    or_robot rb = {n, a, d, alpha, theta_off, NULL, NULL, &cg};
+    or_robot rb = {n, a, d, alpha, theta_off, jtype, NULL, NULL, &cg};
     for (long m = 0; m < M; ++m)
         coll_eval(&rb, q + (size_t)m * n, out + 2 * m, grad ? grad + (size_t)2 * n * m : NULL);
 }
@@ -544,12 +578,15 @@ void or_coll_eval(int n, const double *a, const double *d, const double *alpha,
 /* Global discrete search (Sec. III-B)                                       */
 /* ------------------------------------------------------------------------ */
 
-/* Penalty of candidate k at waypoint t: joint-limit margin plus caller extra. */
-static double node_penalty(int n, const double *q, const double *lo, const double *hi,
-                           double margin, double penalty, double extra) {
+/* Penalty of candidate k at waypoint t: joint-limit margin (margin for a
+ * revolute joint, margin_m for a prismatic one) plus caller extra. */
+static double node_penalty(int n, const int32_t *jtype, const double *q, const double *lo, const double *hi,
+                           double margin, double margin_m, double penalty, double extra) {
     int near = 0;
-    for (int j = 0; j < n; ++j)
-        if (q[j] <= lo[j] + margin || q[j] >= hi[j] - margin) near = 1;
+    for (int j = 0; j < n; ++j) {
+        double m = prismatic(jtype, j) ? margin_m : margin;
+        if (q[j] <= lo[j] + m || q[j] >= hi[j] - m) near = 1;
+    }
     return (near ? penalty : 0.0) + extra;
 }
 
@@ -569,12 +606,12 @@ static double coll_pen(const or_robot *rb, const double *q) {
  * Returns 0, or -1 on bad arguments / allocation failure.
  */
 int or_dp(int T, int K, int n, const double *cand, const double *lo, const double *hi,
-          double margin, double penalty, const double *extra, int32_t *path,
+          double margin, double margin_m, double penalty, const double *extra, int32_t *path,
           double *best_out, double *B_all, int32_t *bp_all, const double *a, const double *d,
-          const double *alpha, const double *theta_off, const double *coll) {
+          const double *alpha, const double *theta_off, const int32_t *jtype, const double *coll) {
     if (T < 1 || K < 1 || n < 1 || n > OR_MAXN) return -1;
     or_coll cg;
-    or_robot rb = {n, a, d, alpha, theta_off, lo, hi, NULL};
+    or_robot rb = {n, a, d, alpha, theta_off, jtype, lo, hi, NULL};
     if (coll) { coll_parse(n, coll, &cg); rb.coll = &cg; }
     /* a configuration in collision (some distance below zero) costs the
      * collision penalty on top (Sec. III-B) */
@@ -585,7 +622,7 @@ int or_dp(int T, int K, int n, const double *cand, const double *lo, const doubl
     if (!Bp || !Bc || !bp) { free(Bp); free(Bc); free(bp); return -1; }
 #define CAND(k, t) (cand + ((size_t)(k) * T + (t)) * n)
     for (int k = 0; k < K; ++k) {
-        Bp[k] = node_penalty(n, CAND(k, 0), lo, hi, margin, penalty, extra ? extra[k] : 0.0) +
+        Bp[k] = node_penalty(n, jtype, CAND(k, 0), lo, hi, margin, margin_m, penalty, extra ? extra[k] : 0.0) +
                 COLL_PEN(CAND(k, 0));
         bp[k] = -1;
     }
@@ -593,7 +630,7 @@ int or_dp(int T, int K, int n, const double *cand, const double *lo, const doubl
     for (int t = 1; t < T; ++t) {
         for (int k = 0; k < K; ++k) {
             const double *qk = CAND(k, t);
-            double pen = node_penalty(n, qk, lo, hi, margin, penalty,
+            double pen = node_penalty(n, jtype, qk, lo, hi, margin, margin_m, penalty,
                                       extra ? extra[(size_t)t * K + k] : 0.0) +
                          COLL_PEN(qk);
             double bv = INFINITY, be = INFINITY;
@@ -803,11 +840,11 @@ static int lm_solve(int T, int n, const double *A, const double *g, double w_s,
  * solve's error code.
  */
 int or_lm_step(int n, const double *a, const double *d, const double *alpha,
-               const double *theta_off, int T, const double *xi, const double *targets,
+               const double *theta_off, const int32_t *jtype, int T, const double *xi, const double *targets,
                double w_p, double w_s, double lambda, double *delta, double *g_out,
                const double *coll, double w_c) {
     or_coll cg;
-    or_robot rb = {n, a, d, alpha, theta_off, NULL, NULL, NULL};
+    or_robot rb = {n, a, d, alpha, theta_off, jtype, NULL, NULL, NULL};
     if (coll) { coll_parse(n, coll, &cg); rb.coll = &cg; }
     size_t nn = (size_t)n * n;
     double *A = (double *)malloc(sizeof(double) * nn * T);
@@ -842,12 +879,12 @@ typedef struct {
  * at the last accepted iterate), -2 (allocation).
  */
 int or_lm(int n, const double *a, const double *d, const double *alpha,
-          const double *theta_off, const double *lo, const double *hi, int T,
+          const double *theta_off, const int32_t *jtype, const double *lo, const double *hi, int T,
           double *xi, const double *targets, const double *opts5, int iters,
           double *cost_hist, double *lambda_hist, int32_t *acc_hist, double *cost0_out,
           const double *coll) {
     or_coll cg;
-    or_robot rb = {n, a, d, alpha, theta_off, lo, hi, NULL};
+    or_robot rb = {n, a, d, alpha, theta_off, jtype, lo, hi, NULL};
     if (coll) { coll_parse(n, coll, &cg); rb.coll = &cg; }
     const double w_c = rb.coll ? cg.w_c : 0.0;
     or_lm_opts o = {opts5[0], opts5[1], opts5[2], opts5[3], opts5[4]};
@@ -922,19 +959,19 @@ done:
  * candidates, then `iters` LM iterations.  Returns 0 or a negative code.
  */
 int or_plan(int n, const double *a, const double *d, const double *alpha,
-            const double *theta_off, const double *lo, const double *hi, int T, int K,
+            const double *theta_off, const int32_t *jtype, const double *lo, const double *hi, int T, int K,
             const double *cand, const double *targets, const double *extra, double margin,
-            double penalty, const double *opts5, int iters, int32_t *path, double *best,
+            double margin_m, double penalty, const double *opts5, int iters, int32_t *path, double *best,
             double *xi_out, double *cost_out, const double *coll) {
-    int rc = or_dp(T, K, n, cand, lo, hi, margin, penalty, extra, path, best, NULL, NULL, a, d, alpha,
-                   theta_off, coll);
+    int rc = or_dp(T, K, n, cand, lo, hi, margin, margin_m, penalty, extra, path, best, NULL, NULL, a, d, alpha,
+                   theta_off, jtype, coll);
     if (rc) return rc;
     for (int t = 0; t < T; ++t)
         memcpy(xi_out + (size_t)t * n, cand + ((size_t)path[t] * T + t) * n, sizeof(double) * n);
     double *hist = (double *)malloc(sizeof(double) * (iters > 0 ? iters : 1));
     if (!hist) return -2;
     double c0 = 0.0;
-    rc = or_lm(n, a, d, alpha, theta_off, lo, hi, T, xi_out, targets, opts5, iters, hist, NULL,
+    rc = or_lm(n, a, d, alpha, theta_off, jtype, lo, hi, T, xi_out, targets, opts5, iters, hist, NULL,
                NULL, &c0, coll);
     if (cost_out) *cost_out = iters > 0 ? hist[iters - 1] : c0;
     free(hist);
@@ -947,12 +984,12 @@ int or_plan(int n, const double *a, const double *d, const double *alpha,
  * With xi_b == NULL the second pose comes from targets[T][12] instead.
  */
 void or_pose_compare(int n, const double *a, const double *d, const double *alpha,
-                     const double *theta_off, int T, const double *xi_a, const double *xi_b,
+                     const double *theta_off, const int32_t *jtype, int T, const double *xi_a, const double *xi_b,
                      const double *targets, double *out) {
     double pa[12], pb[12], mp = 0.0, mr = 0.0;
     for (int t = 0; t < T; ++t) {
-        or_fk(n, a, d, alpha, theta_off, xi_a + (size_t)t * n, pa, NULL);
-        if (xi_b) or_fk(n, a, d, alpha, theta_off, xi_b + (size_t)t * n, pb, NULL);
+        or_fk(n, a, d, alpha, theta_off, jtype, xi_a + (size_t)t * n, pa, NULL);
+        if (xi_b) or_fk(n, a, d, alpha, theta_off, jtype, xi_b + (size_t)t * n, pb, NULL);
         else memcpy(pb, targets + (size_t)t * 12, sizeof(pb));
         double dx = pa[0] - pb[0], dy = pa[1] - pb[1], dz = pa[2] - pb[2];
         double ep = sqrt(dx * dx + dy * dy + dz * dz);
@@ -969,8 +1006,9 @@ void or_pose_compare(int n, const double *a, const double *d, const double *alph
  * and keeps the latest valid solution; validity thresholds of Sec. II).
  * Before every iteration, and once after the last, the current trajectory is
  * checked: position error <= tol[0] (m) and geodesic rotation error <=
- * tol[1] (rad) at every waypoint, and no joint changing by more than tol[2]
- * (rad) between consecutive waypoints (joint limits hold by clamping), and
+ * tol[1] (rad) at every waypoint, and no revolute joint changing by more
+ * than tol[2] (rad) and no prismatic joint by more than tol[3] (m) between
+ * consecutive waypoints (joint limits hold by clamping), and
  * with collision geometry no capsule distance below zero (Sec. II collision
  * avoidance).  A trajectory that passes is kept in xi_valid.  A trajectory
  * whose pose errors are within the thresholds then takes one LM step on the
@@ -988,11 +1026,11 @@ void or_pose_compare(int n, const double *a, const double *d, const double *alph
  * pose steps taken, info[4] = differencing steps taken.
  */
 int or_lm_schedule(int n, const double *a, const double *d, const double *alpha,
-                   const double *theta_off, const double *lo, const double *hi, int T, double *xi,
-                   const double *targets, const double *opts5, const double *tol, int iters,
+                   const double *theta_off, const int32_t *jtype, const double *lo, const double *hi, int T,
+                   double *xi, const double *targets, const double *opts5, const double *tol, int iters,
                    double *xi_valid, double *info, const double *coll) {
     or_coll cg;
-    or_robot rb = {n, a, d, alpha, theta_off, lo, hi, NULL};
+    or_robot rb = {n, a, d, alpha, theta_off, jtype, lo, hi, NULL};
     if (coll) { coll_parse(n, coll, &cg); rb.coll = &cg; }
     or_lm_opts o = {opts5[0], opts5[1], opts5[2], opts5[3], opts5[4]};
     size_t nn = (size_t)n * n, nT = (size_t)n * T;
@@ -1013,9 +1051,13 @@ int or_lm_schedule(int n, const double *a, const double *d, const double *alpha,
     double lam = o.lambda0, nu = 2.0;   /* pose objective */
     for (int it = 0; it <= iters; ++it) {
         double err[2];
-        or_pose_compare(n, a, d, alpha, theta_off, T, xi, NULL, targets, err);
+        or_pose_compare(n, a, d, alpha, theta_off, jtype, T, xi, NULL, targets, err);
         int pose_ok = err[0] <= tol[0] && err[1] <= tol[1];
-        int steps_ok = or_mjac(T, n, xi) <= tol[2];
+        int steps_ok = 1;
+        for (int t = 0; t + 1 < T; ++t)
+            for (int j = 0; j < n; ++j)
+                if (fabs(xi[(size_t)(t + 1) * n + j] - xi[(size_t)t * n + j]) > tol[prismatic(jtype, j) ? 3 : 2])
+                    steps_ok = 0;
         int coll_ok = 1;
         if (rb.coll)
             for (int t = 0; t < T; ++t) {
@@ -1077,8 +1119,8 @@ done:
 
 /* FK of M configurations q[M][n] -> pose[M][12] (and J[M][6][n] if non-NULL). */
 void or_fk_many(int n, const double *a, const double *d, const double *alpha,
-                const double *theta_off, long M, const double *q, double *pose, double *J) {
+                const double *theta_off, const int32_t *jtype, long M, const double *q, double *pose, double *J) {
     for (long m = 0; m < M; ++m)
-        or_fk(n, a, d, alpha, theta_off, q + (size_t)m * n, pose + (size_t)m * 12,
+        or_fk(n, a, d, alpha, theta_off, jtype, q + (size_t)m * n, pose + (size_t)m * 12,
               J ? J + (size_t)m * 6 * n : NULL);
 }

@@ -15,11 +15,17 @@ stand in for them.
 Draw order (fixed; changing it changes every workload):
   robot   rng = default_rng([seed, 0]):  a ~ U[0, 0.1] (n), d ~ U[0, 0.4] (n),
           alpha sign bit ~ U{0, 1} (n)  -> alpha = -pi/2 or +pi/2
+  prismatic robot: the robot of the same seed with joint 0 prismatic,
+          travel [0, 0.4] m (no draws)
   problem rng = default_rng([seed, 1]):  centre c ~ U[-1, 1] (n),
           amplitude A ~ U[0, 0.5/3] (n, 3), frequency f ~ U[0.25, 1.5] (n, 3)
           cycles per path, phase ~ U[0, 2 pi) (n, 3); then the candidate noise
           N(0, sigma) (K, T, n); then a permutation of K (the first nb get a
           branch offset); then one sign per (offset candidate, joint 2/4/6).
+A prismatic joint's path, noise and branch offset are drawn in the same
+units as a revolute joint's and then mapped affinely onto its travel: the
+revolute limit range [-2.8, 2.8] onto [q_lo, q_hi] (scale (q_hi - q_lo) / 5.6
+about the middle of the travel).
 Every value handed to either implementation is rounded to the nearest float32
 and stored as float64, so both sides see bit-identical inputs.
 """
@@ -42,17 +48,34 @@ def _f32(x):
 
 @dataclasses.dataclass
 class Robot:
-    """Standard (distal) DH chain: one revolute joint per row."""
+    """Standard (distal) DH chain: one joint per row, revolute unless
+    joint_type marks it prismatic (1)."""
     a: np.ndarray
     d: np.ndarray
     alpha: np.ndarray
     theta_off: np.ndarray
     q_lo: np.ndarray
     q_hi: np.ndarray
+    joint_type: np.ndarray | None = None
 
     @property
     def dof(self) -> int:
         return int(self.a.shape[0])
+
+    def prismatic(self) -> np.ndarray:
+        """bool [n]: which joints are prismatic."""
+        if self.joint_type is None:
+            return np.zeros(self.dof, dtype=bool)
+        return np.asarray(self.joint_type) == 1
+
+
+def _joint_map(robot: Robot):
+    """(centre, scale) per joint: identity for revolute joints; for a
+    prismatic joint the map of [-Q_LIMIT, Q_LIMIT] onto its travel."""
+    pr = robot.prismatic()
+    ctr = np.where(pr, 0.5 * (robot.q_lo + robot.q_hi), 0.0)
+    sc = np.where(pr, (robot.q_hi - robot.q_lo) / (2.0 * Q_LIMIT), 1.0)
+    return ctr, sc
 
 
 @dataclasses.dataclass
@@ -91,6 +114,18 @@ def make_robot(seed: int, n: int = N_JOINTS) -> Robot:
                  q_hi=np.full(n, Q_LIMIT))
 
 
+def make_robot_prismatic(seed: int, joint: int = 0, travel: float = 0.4) -> Robot:
+    """The robot of make_robot(seed) with one prismatic joint (a torso lift
+    like the Fetch.Full chain's, Sec. IV) of travel [0, travel] m; its DH
+    offset d is the link's length at zero extension."""
+    rb = make_robot(seed)
+    jt = np.zeros(rb.dof, dtype=np.int32)
+    jt[joint] = 1
+    lo, hi = rb.q_lo.copy(), rb.q_hi.copy()
+    lo[joint], hi[joint] = 0.0, float(np.float32(travel))
+    return dataclasses.replace(rb, q_lo=lo, q_hi=hi, joint_type=jt)
+
+
 def make_problem(robot: Robot, seed: int, T: int, K: int, sigma: float,
                  branch_frac: float = 0.0, n_branch: int | None = None,
                  mode: str = "iid") -> Problem:
@@ -111,7 +146,8 @@ def make_problem(robot: Robot, seed: int, T: int, K: int, sigma: float,
     s = np.arange(T, dtype=np.float64) / max(T - 1, 1)
     arg = 2 * math.pi * f[None, :, :] * s[:, None, None] + ph[None, :, :]
     q_star = c[None, :] + np.sum(A[None, :, :] * np.sin(arg), axis=2)
-    q_star = np.clip(_f32(q_star), robot.q_lo, robot.q_hi)
+    ctr, sc = _joint_map(robot)
+    q_star = np.clip(_f32(ctr + sc * q_star), robot.q_lo, robot.q_hi)
 
     if mode == "iid":
         noise = rng.normal(0.0, sigma, (K, T, n))
@@ -119,7 +155,7 @@ def make_problem(robot: Robot, seed: int, T: int, K: int, sigma: float,
         noise = np.broadcast_to(rng.normal(0.0, sigma, (K, 1, n)), (K, T, n))
     else:
         raise ValueError(f"unknown candidate mode {mode!r}")
-    cand = q_star[None, :, :] + noise
+    cand = q_star[None, :, :] + sc * noise
     nb = int(round(branch_frac * K)) if n_branch is None else int(n_branch)
     nb = max(0, min(nb, K))
     perm = rng.permutation(K)
@@ -128,7 +164,7 @@ def make_problem(robot: Robot, seed: int, T: int, K: int, sigma: float,
     joints = [j for j in BRANCH_JOINTS if j < n]
     for r, k in enumerate(sel):
         for c_i, j in enumerate(joints):
-            cand[k, :, j] += signs[r, c_i] * (math.pi / 2)
+            cand[k, :, j] += signs[r, c_i] * (math.pi / 2) * sc[j]
     cand = np.clip(_f32(cand), robot.q_lo[None, None, :], robot.q_hi[None, None, :])
     return Problem(robot=robot, q_star=q_star, cand=np.ascontiguousarray(cand),
                    targets=None, seed=seed, sigma=float(sigma),
@@ -145,14 +181,15 @@ def more_candidates(prob: Problem, K_add: int, batch: int = 1) -> np.ndarray:
     rb = prob.robot
     n = rb.dof
     rng = np.random.default_rng([prob.seed, 2, batch])
-    cand = prob.q_star[None, :, :] + rng.normal(0.0, prob.sigma, (K_add, prob.T, n))
+    _, sc = _joint_map(rb)
+    cand = prob.q_star[None, :, :] + sc * rng.normal(0.0, prob.sigma, (K_add, prob.T, n))
     nb = int(round(prob.branch_frac * K_add))
     sel = rng.permutation(K_add)[:nb]
     signs = rng.choice(np.array([-1.0, 1.0]), (nb, len(BRANCH_JOINTS)))
     joints = [j for j in BRANCH_JOINTS if j < n]
     for r, k in enumerate(sel):
         for c_i, j in enumerate(joints):
-            cand[k, :, j] += signs[r, c_i] * (math.pi / 2)
+            cand[k, :, j] += signs[r, c_i] * (math.pi / 2) * sc[j]
     return np.ascontiguousarray(np.clip(_f32(cand), rb.q_lo[None, None, :], rb.q_hi[None, None, :]))
 
 
@@ -163,7 +200,8 @@ def make_capsules(robot: Robot, trim: float = 0.15, radius_frac: float = 0.2,
     joint that remains after cutting `trim` of its length off both ends, with
     radius min(r_max, radius_frac x length).  In the frame after link i of a
     standard DH chain the joint of link i sits at (-a_i, -d_i sin alpha_i,
-    -d_i cos alpha_i) and the next joint at the origin."""
+    -d_i cos alpha_i) and the next joint at the origin (a prismatic link: at
+    zero extension)."""
     a, d, al = robot.a, robot.d, robot.alpha
     out = np.zeros((robot.dof, 7))
     for i in range(robot.dof):
@@ -262,7 +300,12 @@ def config5_arrivals(rate_hz: float = 200.0, duration_s: float = 60.0,
 
 
 def random_configs(seed: int, M: int, robot: Robot, spread: float = math.pi) -> np.ndarray:
-    """M joint configurations ([M][n]) uniform in [-spread, spread], float32-exact."""
+    """M joint configurations ([M][n]) uniform in [-spread, spread] (a
+    prismatic joint: uniform over its travel), float32-exact."""
     rng = np.random.default_rng([seed, 4])
     q = rng.uniform(-spread, spread, (M, robot.dof))
+    pr = robot.prismatic()
+    if pr.any():
+        u = (q + spread) / (2.0 * spread)
+        q = np.where(pr, robot.q_lo + (robot.q_hi - robot.q_lo) * u, q)
     return _f32(q)

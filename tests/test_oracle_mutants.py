@@ -42,13 +42,14 @@ MUTANTS = {
     "lm_no_clamp": ("if (v > hi[j]) v = hi[j];\n                trial[e] = v;",
                     "trial[e] = v;"),
     "sched_modes_swapped": ("const int m = pose_ok ? 1 : 0;", "const int m = pose_ok ? 0 : 1;"),
-    "sched_step_check_dropped": ("int steps_ok = or_mjac(T, n, xi) <= tol[2];", "int steps_ok = 1;"),
+    "sched_step_check_dropped": ("steps_ok = 0;", "steps_ok = 1;"),
     "sched_diff_damping_adapts": ("const double l = m ? o.lambda0 : lam;", "const double l = lam;"),
     "sched_reject_keeps_damping": ("lam *= nu;\n                nu *= 2.0;\n            }\n            if (lam < o.lambda_min)",
                                    "nu *= 2.0;\n            }\n            if (lam < o.lambda_min)"),
     "coll_radius_dropped": ("double d = sqrt(d2) - c->caps[7 * i + 6] - c->caps[7 * j + 6];",
                             "double d = sqrt(d2) - c->caps[7 * i + 6];"),
-    "coll_grad_sign": ("point_grad(z, o, bj, pb, u, -1.0, grad);", "point_grad(z, o, bj, pb, u, 1.0, grad);"),
+    "coll_grad_sign": ("point_grad(rb->jtype, z, o, bj, pb, u, -1.0, grad);",
+                       "point_grad(rb->jtype, z, o, bj, pb, u, 1.0, grad);"),
     "seg_seg_edge_sign": ("double s = side, t = e > 0.0 ? (b * s + f) / e : 0.0;",
                           "double s = side, t = e > 0.0 ? (b * s - f) / e : 0.0;"),
     "seg_box_upper_gap": ("if (x > hi) return (x - hi) * (x - hi);", "if (x > hi) return (x - lo) * (x - lo);"),
@@ -61,6 +62,13 @@ MUTANTS = {
     "sched_collision_ignored": ("if (dmin[0] < 0.0 || dmin[1] < 0.0) coll_ok = 0;", "if (0) coll_ok = 0;"),
     "sched_length_signed": ("len += fabs(xi[(size_t)(t + 1) * n + j] - xi[(size_t)t * n + j]);",
                             "len += xi[(size_t)(t + 1) * n + j] - xi[(size_t)t * n + j];"),
+    "prism_moves_as_revolute": ("if (prismatic(jtype, i)) { *th = off; *di = d[i] + qi; }",
+                                "if (0) { *th = off; *di = d[i] + qi; }"),
+    "prism_jac_angular_kept": ("J[3 * n + i] = 0.0;", "J[3 * n + i] = z[i][0];"),
+    "prism_jac_linear_index": ("J[0 * n + i] = z[i][0];", "J[0 * n + i] = z[i][1];"),
+    "prism_margin_revolute": ("double m = prismatic(jtype, j) ? margin_m : margin;", "double m = margin;"),
+    "prism_step_threshold_revolute": ("tol[prismatic(jtype, j) ? 3 : 2]", "tol[2]"),
+    "prism_point_grad_revolute": ("if (prismatic(jtype, k)) {", "if (0) {"),
 }
 
 
@@ -98,6 +106,12 @@ def battery():
         lambda: P.test_p16_search_penalises_colliding_nodes_brute_force(),
         lambda: P.test_p16_lm_gradient_with_collision_matches_cost_differences(),
         lambda: P.test_p16_schedule_rejects_a_colliding_pose_valid_trajectory(),
+        lambda: P.test_p17_prismatic_joint_translates_along_its_axis(2, 0.3),
+        lambda: P.test_p17_jacobian_with_prismatic_joint_finite_differences(1),
+        lambda: P.test_p17_lm_gradient_with_prismatic_joint_matches_cost_differences(),
+        lambda: P.test_p17_limit_margin_is_three_cm_for_a_prismatic_joint(),
+        lambda: P.test_p17_schedule_step_threshold_is_two_cm_for_a_prismatic_joint(),
+        lambda: P.test_p17_collision_gradient_with_prismatic_joint(0),
     ]
 
 

@@ -813,3 +813,145 @@ def test_p16_schedule_rejects_a_colliding_pose_valid_trajectory():
     assert r["n_valid"] == 0
     r = oracle.lm_schedule(rb, q, tg, 0, coll=cm)
     assert r["n_valid"] == 1
+
+
+# ---- P17: prismatic joints (Sec. IV's Fetch.Full torso lift) ----------------
+
+def _prismatic_exact(seed=0, joint=2):
+    rb = exact_robot(seed)
+    jt = np.zeros(7, dtype=np.int32)
+    jt[joint] = 1
+    rb.joint_type = jt
+    rb.q_lo[joint], rb.q_hi[joint] = 0.0, 0.4
+    return rb
+
+
+@pytest.mark.parametrize("joint", [0, 2, 6])
+@pytest.mark.parametrize("s", [0.05, 0.3])
+def test_p17_prismatic_joint_translates_along_its_axis(joint, s):
+    """At q = 0 the axis of joint i is (0, -sin A_i, cos A_i) with A_i the sum
+    of the twists before it (the closed form of P1): extending a prismatic
+    joint by s moves the end effector by s times that axis and leaves the
+    rotation alone."""
+    rb = _prismatic_exact(1, joint)
+    p0, R0, A = zero_pose_closed_form(rb)
+    axis = np.array([0.0, -math.sin(A[joint]), math.cos(A[joint])])
+    q = np.zeros(7)
+    q[joint] = s
+    p, R = split(oracle.fk(rb, q))
+    np.testing.assert_allclose(p, p0 + s * axis, atol=1e-15)
+    np.testing.assert_allclose(R, R0, atol=1e-15)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_p17_prismatic_motion_is_a_pure_translation_anywhere(seed):
+    """At any configuration the end effector moves linearly in the joint's
+    value along a unit direction, without rotating."""
+    rb = synth.make_robot_prismatic(seed, joint=seed % 3)
+    j = seed % 3
+    q = synth.random_configs(seed, 1, rb)[0]
+    q[j] = 0.1
+    base_p, base_R = split(oracle.fk(rb, q))
+    dirs = []
+    for s in (0.05, 0.2):
+        q2 = q.copy()
+        q2[j] += s
+        p, R = split(oracle.fk(rb, q2))
+        np.testing.assert_allclose(R, base_R, atol=1e-15)
+        dirs.append((p - base_p) / s)
+    np.testing.assert_allclose(dirs[0], dirs[1], atol=1e-13)
+    assert np.linalg.norm(dirs[0]) == pytest.approx(1.0, abs=1e-13)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_p17_jacobian_with_prismatic_joint_finite_differences(seed):
+    rb = synth.make_robot_prismatic(seed, joint=seed % 7)
+    q = synth.random_configs(100 + seed, 1, rb)[0]
+    _, J = oracle.fk(rb, q, jacobian=True)
+    h = 1e-6
+    for i in range(7):
+        e = np.zeros(7)
+        e[i] = h
+        pp, Rp = split(oracle.fk(rb, q + e))
+        pm, Rm = split(oracle.fk(rb, q - e))
+        np.testing.assert_allclose(J[:3, i], (pp - pm) / (2 * h), atol=1e-8)
+        w = Rotation.from_matrix(Rp @ Rm.T).as_rotvec() / (2 * h)
+        np.testing.assert_allclose(J[3:, i], w, atol=1e-8)
+
+
+def test_p17_lm_gradient_with_prismatic_joint_matches_cost_differences():
+    rb = synth.make_robot_prismatic(3)
+    prob = synth.make_problem(rb, seed=3, T=6, K=1, sigma=0.3)
+    tg = oracle.fk(rb, prob.q_star)
+    xi = prob.cand[0]
+    _, g = oracle.lm_step(rb, xi, tg, 1.0, 0.1, 1.0)
+    h = 1e-6
+    for t in range(6):
+        for j in range(7):
+            e = np.zeros_like(xi)
+            e[t, j] = h
+            fd = (oracle.cost(rb, xi + e, tg) - oracle.cost(rb, xi - e, tg)) / (2 * h)
+            assert g[t, j] == pytest.approx(fd, abs=1e-7, rel=1e-6)
+
+
+def test_p17_limit_margin_is_three_cm_for_a_prismatic_joint():
+    """Sec. III-B: the penalty applies within 1.5 degrees of a revolute
+    joint's limit and within 3 cm of a prismatic joint's.  0.028 m is inside
+    3 cm but outside 1.5 degrees (0.0262) read as a number."""
+    rb = synth.make_robot_prismatic(0)
+    cand = np.zeros((4, 1, 7))
+    cand[:, 0, 0] = [0.028, 0.2, 0.032, 0.372]   # joint 0 travels [0, 0.4]
+    extra = np.array([[0.0, 0.5, 0.7, 0.0]])
+    path, best, _, _ = oracle.dp(cand, rb, extra=extra)
+    assert path[0] == 1 and best == 0.5          # 0 and 3 lie within 3 cm of a limit
+    cand[1, 0, 0] = 0.2 + 1e-3
+    extra[0, 1] = 0.8
+    path, best, _, _ = oracle.dp(cand, rb, extra=extra)
+    assert path[0] == 2 and best == 0.7
+
+
+def test_p17_seed_steps_split_by_joint_type():
+    rb = synth.make_robot_prismatic(1)
+    prob = synth.make_problem(rb, seed=2, T=40, K=1, sigma=0.1)
+    xi = prob.cand[0]
+    rev, pri = oracle.seed_steps(xi, rb)
+    st = np.abs(np.diff(xi, axis=0))
+    assert pri == st[:, 0].max() and rev == st[:, 1:].max()
+    assert max(rev, pri) == oracle.mjac(xi)
+    rb0 = synth.make_robot(1)
+    assert oracle.seed_steps(xi, rb0) == (oracle.mjac(xi), 0.0)
+
+
+def test_p17_schedule_step_threshold_is_two_cm_for_a_prismatic_joint():
+    """Sec. II: at most 7 degrees per revolute joint and 2 cm per prismatic
+    joint between waypoints.  A pose-exact trajectory whose prismatic joint
+    steps by 2.5 cm (well under 7 degrees read as a number) is not valid; the
+    same with a 1.5 cm step is."""
+    rb = synth.make_robot_prismatic(2)
+    prob = synth.make_problem(rb, seed=5, T=20, K=1, sigma=0.0)
+    for step, valid in [(0.025, 0), (0.015, 1)]:
+        q = prob.q_star.copy()
+        q[:, 0] = 0.1
+        q[10:, 0] += step
+        assert np.abs(np.diff(q[:, 1:], axis=0)).max() <= oracle.VALID_TOL[2]
+        tg = oracle.fk(rb, q)
+        r = oracle.lm_schedule(rb, q, tg, 0)
+        assert r["n_valid"] == valid, step
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_p17_collision_gradient_with_prismatic_joint(seed):
+    rb = synth.make_robot_prismatic(seed + 1)
+    cm = synth.collision_model(rb, synth.make_obstacles(seed + 1, 6))
+    q = synth.random_configs(70 + seed, 1, rb, spread=2.0)[0]
+    d, g = oracle.coll_eval(rb, cm, q, gradient=True)
+    h = 1e-6
+    for k in range(7):
+        e = np.zeros(7)
+        e[k] = h
+        fd = (oracle.coll_eval(rb, cm, q + e) - oracle.coll_eval(rb, cm, q - e)) / (2 * h)
+        np.testing.assert_allclose(g[:, k], fd, atol=2e-6)
+    # the prismatic joint moves every capsule after it rigidly along its
+    # axis: the self-distance gradient of joint 0 vanishes (links 1.. move
+    # together; link 0's capsule rides on the joint too)
+    assert g[0, 0] == pytest.approx(0.0, abs=1e-12)
