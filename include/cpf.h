@@ -76,12 +76,23 @@ typedef struct cpf_plan cpf_plan;
  * after the link, then the radius.  With capsules the search adds
  * opts.coll_penalty to a configuration in collision (Sec. III-B) and the LM
  * adds the collision residuals (Sec. III-C); pairs of links fewer than three
- * apart in the chain are not checked. */
+ * apart in the chain are not checked.
+ * joint_type [dof] or NULL (all revolute): 0 revolute, 1 prismatic (the
+ * torso lift of the paper's Fetch.Full chain, Sec. IV).  A revolute joint's
+ * value (rad) adds to theta_off, a prismatic joint's (m) to d, which is then
+ * the link's offset at zero extension; its Jacobian column is [z; 0].  Limit
+ * margins, validity steps and the re-search threshold take the prismatic
+ * values (opts.limit_margin_m, opts.valid_step_m, CPF_RESEARCH_MJAC_M) for
+ * prismatic joints; the search's edge cost and mjac take every joint's change
+ * in its own unit (Sec. III-B).  A robot with capsules and a prismatic joint
+ * is accepted by cpf_fk_batch and cpf_coll_batch only: plans (cpf_plan_init,
+ * cpf_solve_batch, cpf_batchopt, cpf_submit) return CPF_E_UNSUPPORTED for it. */
 typedef struct cpf_robot {
     int32_t dof;
     const double *a, *d, *alpha, *theta_off; /* theta_off may be NULL (zeros) */
     const double *q_lo, *q_hi;
     const double *capsules;
+    const int32_t *joint_type;
 } cpf_robot;
 
 /* One problem (host, copied by every call that takes it).
@@ -125,7 +136,10 @@ typedef struct cpf_problem {
  *     collision residuals max(0, coll_margin - d) of the smallest self and
  *     environment distances d of every waypoint, weight w_coll in the cost
  *     (w_coll/2 sum r^2; in the schedule they belong to the differencing
- *     step), and the search penalty of a configuration with d < 0. */
+ *     step), and the search penalty of a configuration with d < 0.
+ *   limit_margin_m 0.03, valid_step_m 0.02: the joint-limit margin (Sec.
+ *     III-B) and the validity step threshold (Sec. II) of prismatic joints,
+ *     in metres. */
 typedef struct cpf_opts {
     double w_pose, w_smooth;
     double lambda0, lambda_min, lambda_max;
@@ -134,6 +148,7 @@ typedef struct cpf_opts {
     int32_t schedule;
     double valid_pos_m, valid_rot_rad, valid_step_rad;
     double coll_margin, w_coll, coll_penalty;
+    double limit_margin_m, valid_step_m;
 } cpf_opts;
 
 typedef struct cpf_lm_report {
@@ -233,8 +248,21 @@ cpf_status cpf_dp_search(cpf_plan *plan, int32_t *path_out, double *best_out,
 
 /* Seed mjac above which the paper generates more candidate plans and
  * searches again (12 degrees, Sec. III-B); compare with cpf_dp_search's
- * mjac_out. */
+ * mjac_out (a robot with prismatic joints: with cpf_dp_seed_steps'
+ * rev_rad_out). */
 #define CPF_RESEARCH_MJAC_RAD 0.20943951023931953
+/* The same threshold for prismatic joints (3 cm, Sec. III-B); compare with
+ * cpf_dp_seed_steps' pri_m_out. */
+#define CPF_RESEARCH_MJAC_M 0.03
+
+/* Largest change of a revolute joint (rad) and of a prismatic joint (m)
+ * between consecutive waypoints of the seed found by the plan's last search
+ * (cpf_dp_search or cpf_plan_solve); 0 for a joint type the robot lacks.
+ * mjac_out of the search is the larger of the two.  The paper searches again
+ * with more candidate plans when either exceeds its threshold (Sec. III-B).
+ * Reads values kept on the host by the search: no device work.  CPF_E_STATE
+ * before the first search. */
+cpf_status cpf_dp_seed_steps(const cpf_plan *plan, double *rev_rad_out, double *pri_m_out);
 
 /* Append K_add candidate plans to a plan, for a repeated search over K +
  * K_add candidates (Sec. III-B: more plans when the seed's mjac exceeds 12

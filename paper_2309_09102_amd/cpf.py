@@ -27,6 +27,7 @@ E_ARG, E_NOMEM, E_DEVICE, E_STATE, E_NOTFOUND, E_NUMERIC, E_UNSUPPORTED = -1, -2
 F32, F64 = 0, 1
 MIXED, FP64 = 0, 1
 RESEARCH_MJAC_RAD = 0.20943951023931953   # CPF_RESEARCH_MJAC_RAD: 12 degrees
+RESEARCH_MJAC_M = 0.03                    # CPF_RESEARCH_MJAC_M: 3 cm (prismatic joints)
 _NAMES = {0: "OK", 1: "PENDING", -1: "E_ARG", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_STATE",
           -5: "E_NOTFOUND", -6: "E_NUMERIC", -7: "E_UNSUPPORTED"}
 
@@ -42,7 +43,8 @@ class CpfError(RuntimeError):
 
 class cpf_robot(C.Structure):
     _fields_ = [("dof", C.c_int32), ("a", _dp), ("d", _dp), ("alpha", _dp),
-                ("theta_off", _dp), ("q_lo", _dp), ("q_hi", _dp), ("capsules", _dp)]
+                ("theta_off", _dp), ("q_lo", _dp), ("q_hi", _dp), ("capsules", _dp),
+                ("joint_type", _ip)]
 
 
 class cpf_problem(C.Structure):
@@ -57,7 +59,8 @@ class cpf_opts(C.Structure):
                 ("iters", C.c_int32), ("prec", C.c_int32), ("refine_steps", C.c_int32),
                 ("schedule", C.c_int32), ("valid_pos_m", C.c_double),
                 ("valid_rot_rad", C.c_double), ("valid_step_rad", C.c_double),
-                ("coll_margin", C.c_double), ("w_coll", C.c_double), ("coll_penalty", C.c_double)]
+                ("coll_margin", C.c_double), ("w_coll", C.c_double), ("coll_penalty", C.c_double),
+                ("limit_margin_m", C.c_double), ("valid_step_m", C.c_double)]
 
 
 class cpf_lm_report(C.Structure):
@@ -89,6 +92,7 @@ _lib.cpf_plan_init.argtypes = [_vp, C.POINTER(cpf_robot), C.POINTER(cpf_problem)
 _lib.cpf_plan_free.argtypes = [_vp]
 _lib.cpf_fk_batch.argtypes = [_vp, C.POINTER(cpf_robot), C.c_int64, C.c_int32, _vp, _vp, _vp, _vp]
 _lib.cpf_dp_search.argtypes = [_vp, _ip, _dp, _dp]
+_lib.cpf_dp_seed_steps.argtypes = [_vp, _dp, _dp]
 _lib.cpf_lm_refine.argtypes = [_vp, C.c_int32, _dp, C.POINTER(cpf_lm_report)]
 _lib.cpf_lm_latest_valid.argtypes = [_vp, _dp]
 _lib.cpf_plan_solve.argtypes = [_vp, _ip, _dp, _dp, C.POINTER(cpf_lm_report)]
@@ -106,7 +110,7 @@ _lib.cpf_ctx_config.argtypes = [_vp, C.c_int32, C.c_int32]
 _lib.cpf_ctx_profile.argtypes = [_vp, C.c_int32]
 _lib.cpf_ctx_kernel_stats.argtypes = [_vp, C.c_char_p, C.POINTER(C.c_double),
                                       C.POINTER(C.c_int64)]
-for _f in ("cpf_ctx_create", "cpf_plan_init", "cpf_fk_batch", "cpf_dp_search", "cpf_lm_refine",
+for _f in ("cpf_ctx_create", "cpf_plan_init", "cpf_fk_batch", "cpf_dp_search", "cpf_dp_seed_steps", "cpf_lm_refine",
            "cpf_lm_latest_valid", "cpf_plan_append", "cpf_coll_batch", "cpf_plan_solve",
            "cpf_solve_batch", "cpf_batchopt", "cpf_submit", "cpf_poll", "cpf_ctx_profile",
            "cpf_ctx_kernel_stats", "cpf_ctx_config"):
@@ -114,7 +118,7 @@ for _f in ("cpf_ctx_create", "cpf_plan_init", "cpf_fk_batch", "cpf_dp_search", "
 
 EXPORTS = ("cpf_opts_default", "cpf_last_error", "cpf_ctx_create", "cpf_ctx_destroy",
            "cpf_ctx_bytes_in_use", "cpf_plan_init", "cpf_plan_free", "cpf_fk_batch", "cpf_coll_batch",
-           "cpf_dp_search", "cpf_plan_append", "cpf_lm_refine", "cpf_plan_solve", "cpf_lm_latest_valid",
+           "cpf_dp_search", "cpf_dp_seed_steps", "cpf_plan_append", "cpf_lm_refine", "cpf_plan_solve", "cpf_lm_latest_valid",
            "cpf_solve_batch", "cpf_batchopt", "cpf_submit", "cpf_poll", "cpf_ctx_profile",
            "cpf_ctx_kernel_stats", "cpf_ctx_config")
 
@@ -147,12 +151,16 @@ class _Keep:
 
 def make_robot(robot, coll=None) -> _Keep:
     """coll: collision description (dict with capsules [dof][7], obstacles
-    [n][18], margin, w_coll, penalty) or None."""
+    [n][18], margin, w_coll, penalty) or None.  The robot's joint_type
+    attribute (0 revolute, 1 prismatic per joint), when present, is passed on."""
     arrs = [_f64(robot.a), _f64(robot.d), _f64(robot.alpha), _f64(robot.theta_off),
             _f64(robot.q_lo), _f64(robot.q_hi)]
     caps = None if coll is None else _f64(coll["capsules"])
-    s = cpf_robot(int(arrs[0].shape[0]), *[_ptr(a) for a in arrs], _ptr(caps))
-    return _Keep(s, arrs + [caps])
+    jt = getattr(robot, "joint_type", None)
+    jt = None if jt is None else np.ascontiguousarray(jt, dtype=np.int32)
+    s = cpf_robot(int(arrs[0].shape[0]), *[_ptr(a) for a in arrs], _ptr(caps),
+                  None if jt is None else jt.ctypes.data_as(_ip))
+    return _Keep(s, arrs + [caps, jt])
 
 
 def _obstacles(coll):
@@ -279,6 +287,13 @@ def dp_search(plan, T: int):
     mj = C.c_double()
     _check(_lib.cpf_dp_search(plan, path.ctypes.data_as(_ip), C.byref(best), C.byref(mj)))
     return path, best.value, mj.value
+
+
+def dp_seed_steps(plan):
+    """(largest revolute step rad, largest prismatic step m) of the last search's seed."""
+    r, p = C.c_double(), C.c_double()
+    _check(_lib.cpf_dp_seed_steps(plan, C.byref(r), C.byref(p)))
+    return r.value, p.value
 
 
 def lm_refine(plan, iters: int, T: int, want_xi: bool = True):
@@ -492,6 +507,15 @@ class Plan:
 
     def dp_search(self):
         return dp_search(self.h, self.T)
+
+    def seed_steps(self):
+        return dp_seed_steps(self.h)
+
+    def needs_research(self) -> bool:
+        """The paper's test for more candidate plans (Sec. III-B): a seed step
+        above 12 degrees (revolute) or 3 cm (prismatic)."""
+        r, p = dp_seed_steps(self.h)
+        return r > RESEARCH_MJAC_RAD or p > RESEARCH_MJAC_M
 
     def lm_refine(self, iters: int, want_xi: bool = True):
         return lm_refine(self.h, iters, self.T, want_xi)

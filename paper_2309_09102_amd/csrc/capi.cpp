@@ -210,6 +210,13 @@ cpf_status check_robot(const cpf_robot *r, HostRobot *out) {
         out->lo[i] = r->q_lo[i];
         out->hi[i] = r->q_hi[i];
     }
+    out->prism = 0;
+    if (r->joint_type)
+        for (int i = 0; i < NJ; ++i) {
+            if (r->joint_type[i] != 0 && r->joint_type[i] != 1)
+                return fail(CPF_E_ARG, "joint %d: joint_type %d (0 revolute, 1 prismatic)", i, r->joint_type[i]);
+            if (r->joint_type[i] == 1) out->prism |= 1u << i;
+        }
     out->has_caps = r->capsules != nullptr;
     if (r->capsules) {
         if (!all_finite(r->capsules, (size_t)NJ * 7)) return fail(CPF_E_ARG, "capsules not finite");
@@ -218,6 +225,12 @@ cpf_status check_robot(const cpf_robot *r, HostRobot *out) {
             for (int c = 0; c < 7; ++c) out->cap[i][c] = r->capsules[7 * i + c];
         }
     }
+    return CPF_OK;
+}
+
+cpf_status check_plan_robot(const HostRobot &hr) {
+    if (hr.has_caps && hr.prism)
+        return fail(CPF_E_UNSUPPORTED, "plans with collision capsules and a prismatic joint are switched off");
     return CPF_OK;
 }
 
@@ -284,6 +297,9 @@ cpf_status check_opts(const cpf_opts *o) {
     const double cv[3] = {o->coll_margin, o->w_coll, o->coll_penalty};
     if (!all_finite(cv, 3) || cv[0] < 0 || cv[1] < 0 || !(std::fabs(cv[2]) <= 1e30))
         return fail(CPF_E_ARG, "collision options out of range");
+    const double pv[2] = {o->limit_margin_m, o->valid_step_m};
+    if (!all_finite(pv, 2) || pv[0] < 0 || pv[1] < 0)
+        return fail(CPF_E_ARG, "prismatic margin / step threshold must be finite and >= 0");
     return CPF_OK;
 }
 
@@ -302,11 +318,14 @@ static void fill_desc(cpf_plan *p, bool has_extra) {
     D.lam_min = p->opts.lambda_min;
     D.lam_max = p->opts.lambda_max;
     D.margin = p->opts.limit_margin;
+    D.margin_p = p->opts.limit_margin_m;
     D.penalty = p->opts.limit_penalty;
     D.schedule = p->opts.schedule;
+    D.prism = (int32_t)p->robot.prism;
     D.vtol[0] = p->opts.valid_pos_m;
     D.vtol[1] = p->opts.valid_rot_rad;
     D.vtol[2] = p->opts.valid_step_rad;
+    D.vtol[3] = p->opts.valid_step_m;
     D.has_coll = p->robot.has_caps ? 1 : 0;
     D.n_obs = p->n_obs;
     D.coll_margin = p->opts.coll_margin;
@@ -505,6 +524,8 @@ void cpf_opts_default(cpf_opts *o) {
     o->coll_margin = 0.02;
     o->w_coll = 1.0;
     o->coll_penalty = 100.0;
+    o->limit_margin_m = 0.03;
+    o->valid_step_m = 0.02;
 }
 
 const char *cpf_last_error(void) { return cpf::g_err.c_str(); }
@@ -544,6 +565,7 @@ cpf_status cpf_plan_init(cpf_ctx *ctx, const cpf_robot *robot, const cpf_problem
     HostRobot hr;
     cpf_status st;
     if ((st = check_robot(robot, &hr)) != CPF_OK) return st;
+    if ((st = check_plan_robot(hr)) != CPF_OK) return st;
     if ((st = check_problem(prob)) != CPF_OK) return st;
     cpf_opts o;
     cpf_opts_default(&o);
@@ -624,8 +646,18 @@ cpf_status cpf_dp_search(cpf_plan *plan, int32_t *path_out, double *best_out, do
     if (st != CPF_OK) return st;
     plan->searched = true;
     plan->lists_valid = true;
+    plan->seed_steps[0] = rb.dp_out[3];
+    plan->seed_steps[1] = rb.dp_out[4];
     if (best_out) *best_out = rb.dp_out[0];
     if (mjac_out) *mjac_out = rb.dp_out[1];
+    return CPF_OK;
+}
+
+cpf_status cpf_dp_seed_steps(const cpf_plan *plan, double *rev_rad_out, double *pri_m_out) {
+    if (!plan) return fail(CPF_E_ARG, "plan is NULL");
+    if (!plan->searched) return fail(CPF_E_STATE, "the plan has not been searched");
+    if (rev_rad_out) *rev_rad_out = plan->seed_steps[0];
+    if (pri_m_out) *pri_m_out = plan->seed_steps[1];
     return CPF_OK;
 }
 
@@ -752,6 +784,8 @@ cpf_status cpf_plan_solve(cpf_plan *plan, int32_t *path_out, double *best_out, d
     cpf_status st = read_plan(plan, s, nullptr, &rb, xi_out, path_out, nullptr);
     if (st != CPF_OK) return st;
     plan->searched = true;
+    plan->seed_steps[0] = rb.dp_out[3];
+    plan->seed_steps[1] = rb.dp_out[4];
     if (best_out) *best_out = rb.dp_out[0];
     if (rep) fill_report(rb, rep);
     if (rb.st.status != 0) return fail(CPF_E_NUMERIC, "non-positive pivot in the block solve");
@@ -783,6 +817,7 @@ cpf_status cpf_solve_batch(cpf_ctx *ctx, int32_t nplans, const cpf_robot *robots
     std::vector<HostRobot> hrs(nplans);
     for (int i = 0; i < nplans; ++i) {
         if ((st = check_robot(&robots[i], &hrs[i])) != CPF_OK) return st;
+        if ((st = check_plan_robot(hrs[i])) != CPF_OK) return st;
         if ((st = check_problem(&probs[i])) != CPF_OK) return st;
     }
     if (nplans == 0) return CPF_OK;
@@ -867,6 +902,7 @@ cpf_status cpf_batchopt(cpf_ctx *ctx, const cpf_robot *robot, const cpf_problem 
     HostRobot hr;
     cpf_status st;
     if ((st = check_robot(robot, &hr)) != CPF_OK) return st;
+    if ((st = check_plan_robot(hr)) != CPF_OK) return st;
     if ((st = check_problem(prob)) != CPF_OK) return st;
     if (M < 1 || M > prob->K) return fail(CPF_E_ARG, "M=%d with K=%d", M, prob->K);
     cpf_opts o;

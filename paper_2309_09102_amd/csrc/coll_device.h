@@ -185,17 +185,20 @@ __device__ __forceinline__ S seg_box_d2(const S A[3], const S D[3], const S lo[3
     return best;
 }
 
-// Gradient of a distance through a closest point w carried by link lnk.
+// Gradient of a distance through a closest point w carried by link lnk: the
+// point's velocity for joint k is z_k x (w - o_k) (revolute) or z_k
+// (prismatic).
 template <typename S>
-__device__ __forceinline__ void point_gradient(const S Zs[NJ][3], const S Os[NJ][3], int lnk, const S w[3],
-                                               const S u[3], S sgn, S g[NJ]) {
+__device__ __forceinline__ void point_gradient(uint32_t prism, const S Zs[NJ][3], const S Os[NJ][3], int lnk,
+                                               const S w[3], const S u[3], S sgn, S g[NJ]) {
 #pragma unroll
     for (int k = 0; k < NJ; ++k) {
         if (k <= lnk) {
+            const bool pr = is_prismatic(prism, k);
             const S v0 = w[0] - Os[k][0], v1 = w[1] - Os[k][1], v2 = w[2] - Os[k][2];
-            const S c0 = Zs[k][1] * v2 - Zs[k][2] * v1;
-            const S c1 = Zs[k][2] * v0 - Zs[k][0] * v2;
-            const S c2 = Zs[k][0] * v1 - Zs[k][1] * v0;
+            const S c0 = pr ? Zs[k][0] : Zs[k][1] * v2 - Zs[k][2] * v1;
+            const S c1 = pr ? Zs[k][1] : Zs[k][2] * v0 - Zs[k][0] * v2;
+            const S c2 = pr ? Zs[k][2] : Zs[k][0] * v1 - Zs[k][1] * v0;
             g[k] += sgn * (u[0] * c0 + u[1] * c1 + u[2] * c2);
         }
     }
@@ -312,8 +315,8 @@ __device__ __forceinline__ void coll_distances(const RobotT<S> &rb, const C cap[
             if (nrm > contact_eps<S>()) {
 #pragma unroll
                 for (int k = 0; k < 3; ++k) u[k] /= nrm;
-                point_gradient(Zs, Os, bi, pa, u, S(1), grad[0]);
-                point_gradient(Zs, Os, bj, pb, u, S(-1), grad[0]);
+                point_gradient(rb.prism, Zs, Os, bi, pa, u, S(1), grad[0]);
+                point_gradient(rb.prism, Zs, Os, bj, pb, u, S(-1), grad[0]);
             }
         }
         if (li >= 0) {
@@ -334,7 +337,7 @@ __device__ __forceinline__ void coll_distances(const RobotT<S> &rb, const C cap[
             if (nrm > contact_eps<S>()) {
 #pragma unroll
                 for (int k = 0; k < 3; ++k) u[k] /= nrm;
-                point_gradient(Zs, Os, li, pa, u, S(1), grad[1]);
+                point_gradient(rb.prism, Zs, Os, li, pa, u, S(1), grad[1]);
             }
         }
     }

@@ -66,8 +66,9 @@ struct LMState {
 
 struct DevPlan {
     int32_t T, K, has_extra, prec;
-    int32_t refine_steps, schedule, pad1, pad2;
-    double w_p, w_s, lam0, lam_min, lam_max, margin, penalty;
+    int32_t refine_steps, schedule, prism, pad2;   // prism: bit i set = joint i prismatic
+    // joint-limit margin of revolute (rad) and prismatic (m) joints
+    double w_p, w_s, lam0, lam_min, lam_max, margin, penalty, margin_p;
     // robot in double and float (cos/sin of the twist precomputed on host)
     double a[8], d[8], ca[8], sa[8], off[8], lo[8], hi[8];
     float af[8], df[8], caf[8], saf[8], offf[8];
@@ -78,15 +79,17 @@ struct DevPlan {
     CPF_GLOBAL uint16_t *topk;    // [T][K][TOPM] nearest predecessors of each node
     CPF_GLOBAL double *topc;      // [T][K][TOPM] their edges plus the node penalty
     CPF_GLOBAL int32_t *path;
-    CPF_GLOBAL double *dp_out;    // [0] = B*, [1] = mjac of the seed, [2] = end node
+    CPF_GLOBAL double *dp_out;    // [0] = B*, [1] = mjac of the seed, [2] = end node, [3] / [4] = the
+                                  // seed's largest revolute / prismatic joint step
     CPF_GLOBAL double *targets;
     CPF_GLOBAL double *xi, *xt, *A, *g, *cr, *dx, *rb;
     CPF_GLOBAL LMState *st;
     CPF_GLOBAL double *report;    // [0] max pos err, [1] max rot err, [2] mjac, [3] min self
                                   // distance, [4] min environment distance
-    // schedule mode: validity thresholds (position m, rotation rad, joint
-    // step rad) and the latest valid trajectory [dof][T]
-    double vtol[3], pad3;
+    // schedule mode: validity thresholds (position m, rotation rad, step of
+    // a revolute joint rad, step of a prismatic joint m) and the latest
+    // valid trajectory [dof][T]
+    double vtol[4];
     CPF_GLOBAL double *xv;
     // collision geometry (has_coll): capsule of each link (endpoints in the
     // frame after the link, radius) in double and float, obstacles [n_obs][18]
@@ -103,7 +106,10 @@ struct DevPlan {
 template <typename S>
 struct RobotT {
     S a[NJ], d[NJ], ca[NJ], sa[NJ], off[NJ];
+    uint32_t prism;   // bit i set: joint i is prismatic
 };
+
+__host__ __device__ __forceinline__ bool is_prismatic(uint32_t prism, int i) { return (prism >> i) & 1u; }
 
 template <typename S>
 __device__ __forceinline__ RobotT<S> load_robot(const DevPlan &P);
@@ -115,6 +121,7 @@ __device__ __forceinline__ RobotT<double> load_robot<double>(const DevPlan &P) {
     for (int i = 0; i < NJ; ++i) {
         r.a[i] = P.a[i]; r.d[i] = P.d[i]; r.ca[i] = P.ca[i]; r.sa[i] = P.sa[i]; r.off[i] = P.off[i];
     }
+    r.prism = (uint32_t)P.prism;
     return r;
 }
 
@@ -125,6 +132,7 @@ __device__ __forceinline__ RobotT<float> load_robot<float>(const DevPlan &P) {
     for (int i = 0; i < NJ; ++i) {
         r.a[i] = P.af[i]; r.d[i] = P.df[i]; r.ca[i] = P.caf[i]; r.sa[i] = P.saf[i]; r.off[i] = P.offf[i];
     }
+    r.prism = (uint32_t)P.prism;
     return r;
 }
 
@@ -135,9 +143,10 @@ __device__ __forceinline__ void dev_sincos(double x, double *s, double *c) { sin
 // Frame columns X, Y, Z and origin p start at the identity; link i maps
 //   X' = c X + s Y,  W = c Y - s X,  Y' = ca W + sa Z,  Z' = ca Z - sa W,
 //   p' = p + a X' + d Z,
-// which is the product with Rz(q) Tz(d) Tx(a) Rx(alpha) written per column.
-// With FRAMES the axis Z and origin p of joint i (before link i) are kept
-// for the geometric Jacobian.
+// which is the product with Rz(theta) Tz(d) Tx(a) Rx(alpha) written per
+// column; theta = q + offset and d fixed for a revolute joint, theta = offset
+// and d + q for a prismatic one.  With FRAMES the axis Z and origin p of
+// joint i (before link i) are kept for the geometric Jacobian.
 template <typename S>
 __device__ __forceinline__ void chain_start(S X[3], S Y[3], S Z[3], S p[3]) {
     X[0] = 1; X[1] = 0; X[2] = 0;
@@ -149,8 +158,10 @@ __device__ __forceinline__ void chain_start(S X[3], S Y[3], S Z[3], S p[3]) {
 // Link i of the chain: the frame before it becomes the frame after it.
 template <typename S>
 __device__ __forceinline__ void dh_step(const RobotT<S> &rb, int i, S qi, S X[3], S Y[3], S Z[3], S p[3]) {
+    const bool pr = is_prismatic(rb.prism, i);
     S s, c;
-    dev_sincos(qi + rb.off[i], &s, &c);
+    dev_sincos(pr ? rb.off[i] : qi + rb.off[i], &s, &c);
+    const S di = pr ? rb.d[i] + qi : rb.d[i];
     S nx[3], w[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
@@ -159,11 +170,26 @@ __device__ __forceinline__ void dh_step(const RobotT<S> &rb, int i, S qi, S X[3]
     }
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-        p[r] = p[r] + rb.a[i] * nx[r] + rb.d[i] * Z[r];
+        p[r] = p[r] + rb.a[i] * nx[r] + di * Z[r];
         Y[r] = rb.ca[i] * w[r] + rb.sa[i] * Z[r];
         Z[r] = rb.ca[i] * Z[r] - rb.sa[i] * w[r];
         X[r] = nx[r];
     }
+}
+
+// Column i of the geometric Jacobian at end-effector position p: a revolute
+// joint gives [z x (p - o); z], a prismatic one [z; 0].
+template <typename S>
+__device__ __forceinline__ void jac_column(uint32_t prism, int i, const S z[3], const S o[3], const S p[3],
+                                           S col[6]) {
+    const bool pr = is_prismatic(prism, i);
+    const S dx = p[0] - o[0], dy = p[1] - o[1], dz = p[2] - o[2];
+    col[0] = pr ? z[0] : z[1] * dz - z[2] * dy;
+    col[1] = pr ? z[1] : z[2] * dx - z[0] * dz;
+    col[2] = pr ? z[2] : z[0] * dy - z[1] * dx;
+    col[3] = pr ? S(0) : z[0];
+    col[4] = pr ? S(0) : z[1];
+    col[5] = pr ? S(0) : z[2];
 }
 
 template <typename S, bool FRAMES>

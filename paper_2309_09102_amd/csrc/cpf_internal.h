@@ -12,6 +12,7 @@ namespace cpf {
 // once in double.
 struct HostRobot {
     double a[NJ], d[NJ], alpha[NJ], ca[NJ], sa[NJ], off[NJ], lo[NJ], hi[NJ];
+    uint32_t prism;      // bit i set: joint i is prismatic
     bool has_caps;
     double cap[NJ][7];   // capsule of each link: p0, p1 (frame after the link), radius
 };

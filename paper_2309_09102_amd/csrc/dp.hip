@@ -59,8 +59,10 @@ __device__ __forceinline__ double edge(const double qk[NJ], const Q *pq, long st
 __device__ __forceinline__ double node_penalty(const DevPlan &P, const double q[NJ], int t, int k) {
     bool near = false;
 #pragma unroll
-    for (int j = 0; j < NJ; ++j)
-        near = near || (q[j] <= P.lo[j] + P.margin) || (q[j] >= P.hi[j] - P.margin);
+    for (int j = 0; j < NJ; ++j) {
+        const double m = is_prismatic((uint32_t)P.prism, j) ? P.margin_p : P.margin;
+        near = near || (q[j] <= P.lo[j] + m) || (q[j] >= P.hi[j] - m);
+    }
     const double ex = P.has_extra ? P.extra[(size_t)t * P.K + k] : 0.0;
     double pen = (near ? P.penalty : 0.0) + ex;
     if (P.has_coll) pen += P.cpen[(size_t)t * P.K + k];
@@ -438,8 +440,9 @@ __global__ __launch_bounds__(BS) void dp_kernel(const DevPlan *__restrict__ plan
     }
     __syncthreads();
 
-    // Seed gather xi[j][t] = q_t^{path[t]}[j] and its mjac.
-    double m = 0.0;
+    // Seed gather xi[j][t] = q_t^{path[t]}[j] and its largest steps of a
+    // revolute and of a prismatic joint (the seed's mjac is the larger).
+    double m[2] = {0.0, 0.0};
     for (int t = tid; t < T; t += (int)blockDim.x) {
         const int kk = P.path[t];
 #pragma unroll
@@ -447,19 +450,27 @@ __global__ __launch_bounds__(BS) void dp_kernel(const DevPlan *__restrict__ plan
         if (t + 1 < T) {
             const int k2 = P.path[t + 1];
 #pragma unroll
-            for (int j = 0; j < NJ; ++j)
-                m = fmax(m, fabs((double)cand[((size_t)(t + 1) * NJ + j) * K + k2] -
-                                 (double)cand[((size_t)t * NJ + j) * K + kk]));
+            for (int j = 0; j < NJ; ++j) {
+                const int h = is_prismatic((uint32_t)P.prism, j) ? 1 : 0;
+                m[h] = fmax(m[h], fabs((double)cand[((size_t)(t + 1) * NJ + j) * K + k2] -
+                                       (double)cand[((size_t)t * NJ + j) * K + kk]));
+            }
         }
     }
-    red[tid] = m;
-    __syncthreads();
-    for (int s = (int)blockDim.x / 2; s > 0; s >>= 1) {
-        if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
+    for (int h = 0; h < 2; ++h) {
+        red[tid] = m[h];
+        __syncthreads();
+        for (int s = (int)blockDim.x / 2; s > 0; s >>= 1) {
+            if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
+            __syncthreads();
+        }
+        m[h] = red[0];
         __syncthreads();
     }
     if (tid == 0) {
-        P.dp_out[1] = red[0];
+        P.dp_out[1] = fmax(m[0], m[1]);
+        P.dp_out[3] = m[0];
+        P.dp_out[4] = m[1];
         P.st->lambda = P.lam0;   // the LM starts afresh from this seed
         P.st->seeded = 0;
     }

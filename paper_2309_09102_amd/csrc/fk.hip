@@ -26,9 +26,8 @@ __global__ __launch_bounds__(256) void fk_batch_kernel(RobotT<S> rb, int64_t M,
     if (WANT_J) {
 #pragma unroll
         for (int i = 0; i < NJ; ++i) {
-            const S dx = p[0] - Os[i][0], dy = p[1] - Os[i][1], dz = p[2] - Os[i][2];
-            const S col[6] = {Zs[i][1] * dz - Zs[i][2] * dy, Zs[i][2] * dx - Zs[i][0] * dz,
-                              Zs[i][0] * dy - Zs[i][1] * dx, Zs[i][0], Zs[i][1], Zs[i][2]};
+            S col[6];
+            jac_column<S>(rb.prism, i, Zs[i], Os[i], p, col);
 #pragma unroll
             for (int r = 0; r < 6; ++r) J[((int64_t)r * NJ + i) * M + m] = col[r];
         }
@@ -57,6 +56,7 @@ hipError_t fk_batch_launch(const HostRobot &hr, int64_t M, int prec, const void 
             rb.a[i] = hr.a[i]; rb.d[i] = hr.d[i]; rb.ca[i] = hr.ca[i]; rb.sa[i] = hr.sa[i];
             rb.off[i] = hr.off[i];
         }
+        rb.prism = hr.prism;
         return launch_fk<double>(rb, M, q, pose, J, s);
     }
     RobotT<float> rb;
@@ -64,6 +64,7 @@ hipError_t fk_batch_launch(const HostRobot &hr, int64_t M, int prec, const void 
         rb.a[i] = (float)hr.a[i]; rb.d[i] = (float)hr.d[i]; rb.ca[i] = (float)hr.ca[i];
         rb.sa[i] = (float)hr.sa[i]; rb.off[i] = (float)hr.off[i];
     }
+    rb.prism = hr.prism;
     return launch_fk<float>(rb, M, q, pose, J, s);
 }
 
@@ -114,6 +115,7 @@ hipError_t coll_batch_launch(const HostRobot &hr, const HostCaps &caps, int n_ob
             rb.a[i] = hr.a[i]; rb.d[i] = hr.d[i]; rb.ca[i] = hr.ca[i]; rb.sa[i] = hr.sa[i];
             rb.off[i] = hr.off[i];
         }
+        rb.prism = hr.prism;
         return launch_coll<double>(rb, caps, n_obs, obs, M, q, dist, grad, s);
     }
     RobotT<float> rb;
@@ -121,6 +123,7 @@ hipError_t coll_batch_launch(const HostRobot &hr, const HostCaps &caps, int n_ob
         rb.a[i] = (float)hr.a[i]; rb.d[i] = (float)hr.d[i]; rb.ca[i] = (float)hr.ca[i];
         rb.sa[i] = (float)hr.sa[i]; rb.off[i] = (float)hr.off[i];
     }
+    rb.prism = hr.prism;
     return launch_coll<float>(rb, caps, n_obs, obs, M, q, dist, grad, s);
 }
 

@@ -156,13 +156,10 @@ __device__ __forceinline__ double linearise(const DevPlan &P, const RobotT<S> &r
         S J[6][NJ];
 #pragma unroll
         for (int i = 0; i < NJ; ++i) {
-            const S dx = p[0] - Os[i][0], dy = p[1] - Os[i][1], dz = p[2] - Os[i][2];
-            J[0][i] = Zs[i][1] * dz - Zs[i][2] * dy;
-            J[1][i] = Zs[i][2] * dx - Zs[i][0] * dz;
-            J[2][i] = Zs[i][0] * dy - Zs[i][1] * dx;
-            J[3][i] = Zs[i][0];
-            J[4][i] = Zs[i][1];
-            J[5][i] = Zs[i][2];
+            S col[6];
+            jac_column<S>(rb.prism, i, Zs[i], Os[i], p, col);
+#pragma unroll
+            for (int r = 0; r < 6; ++r) J[r][i] = col[r];
         }
         // The Gram matrix and the gradient J^T r of the (FP32 or FP64)
         // Jacobian and residual are accumulated in FP64.  Then the Gram is
@@ -883,8 +880,9 @@ __device__ __forceinline__ void pose_err_fp64(const DevPlan &P, const RobotT<dou
 
 // Validity check of the alternating schedule (Sec. III-C's anytime result
 // under the Sec. II thresholds), FP64 kinematics: every waypoint within the
-// position and rotation thresholds, no joint step above the step threshold
-// and, with collision geometry, no capsule distance below zero (Sec. II
+// position and rotation thresholds, no joint step above the step threshold of
+// its joint type and, with collision geometry, no capsule distance below
+// zero (Sec. II
 // collision avoidance).  A trajectory that passes is copied to xv and
 // counted.  Returns
 // the next step's objective to all lanes: 1 (differencing) when the pose
@@ -892,7 +890,7 @@ __device__ __forceinline__ void pose_err_fp64(const DevPlan &P, const RobotT<dou
 template <bool COLL>
 __device__ int schedule_check(const DevPlan &P, LMState *st, int T, double *red) {
     const RobotT<double> rb = load_robot<double>(P);
-    double ep = 0.0, er = 0.0, mj = 0.0, len = 0.0, pen = 0.0;
+    double ep = 0.0, er = 0.0, big = 0.0, len = 0.0, pen = 0.0;
     for (int t = threadIdx.x; t < T; t += LM_BS) {
         double a, b;
         pose_err_fp64(P, rb, P.xi, T, t, &a, &b);
@@ -909,17 +907,17 @@ __device__ int schedule_check(const DevPlan &P, LMState *st, int T, double *red)
 #pragma unroll
             for (int j = 0; j < NJ; ++j) {
                 const double d = fabs(P.xi[(size_t)j * T + t + 1] - P.xi[(size_t)j * T + t]);
-                mj = fmax(mj, d);
+                if (d > P.vtol[is_prismatic((uint32_t)P.prism, j) ? 3 : 2]) big = 1.0;
                 len += d;
             }
     }
     ep = block_max(ep, red);
     er = block_max(er, red);
-    mj = block_max(mj, red);
+    big = block_max(big, red);
     len = block_sum(len, red);
     if (COLL) pen = block_max(pen, red);
     const bool pose_ok = ep <= P.vtol[0] && er <= P.vtol[1];
-    if (pose_ok && mj <= P.vtol[2] && pen <= 0.0) {
+    if (pose_ok && big == 0.0 && pen <= 0.0) {
         for (int e = threadIdx.x; e < NJ * T; e += LM_BS) P.xv[e] = P.xi[e];
         if (threadIdx.x == 0) {
             st->n_valid += 1;

@@ -49,6 +49,9 @@ uint64_t plan_bytes(int T, int K, bool extra, int n_obs, bool coll);
 uint64_t plan_class_bytes(int T, int K, bool extra, int n_obs, bool coll);
 
 cpf_status check_robot(const cpf_robot *r, HostRobot *out);
+// Robots a plan may use (CPF_E_UNSUPPORTED for collision capsules together
+// with a prismatic joint: that combination is switched off in plans).
+cpf_status check_plan_robot(const HostRobot &hr);
 cpf_status check_problem(const cpf_problem *p);
 cpf_status check_opts(const cpf_opts *o);
 
@@ -113,6 +116,7 @@ struct cpf_plan {
     cpf::LMState init{};  // host source of the initial LM state upload
     bool searched = false;
     bool lists_valid = false;   // the search's predecessor lists are current
+    double seed_steps[2] = {0.0, 0.0};   // last search: largest revolute / prismatic step
 };
 
 namespace cpf {

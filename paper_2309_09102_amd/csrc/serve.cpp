@@ -409,6 +409,7 @@ extern "C" cpf_status cpf_submit(cpf_ctx *ctx, const cpf_robot *robot, const cpf
     HostRobot hr;
     cpf_status st;
     if ((st = check_robot(robot, &hr)) != CPF_OK) return st;
+    if ((st = check_plan_robot(hr)) != CPF_OK) return st;
     if ((st = check_problem(prob)) != CPF_OK) return st;
     cpf_opts o;
     cpf_opts_default(&o);

@@ -1,0 +1,226 @@
+"""GPU parity of robots with a prismatic joint (the torso lift of the
+paper's Fetch.Full chain, Sec. IV) against the oracle: FK and Jacobian,
+collision distances and gradients, the search with the 3 cm limit margin
+(Sec. III-B) and the seed's step split by joint type (the 12 degree / 3 cm
+re-search test), the LM in both precisions, and the schedule's 2 cm validity
+step (Sec. II).
+
+Tolerances are those of the revolute-only tests: FK 1e-12 (FP64) / 2e-6
+(FP32); distances 1e-12 m and gradients 1e-9 (FP64); the search
+index-identical with bit-identical B*; the LM 1e-5 m, 1e-5 rad and 1e-6
+relative cost; the schedule's counts exact.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2309_09102_amd import synth
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2309_09102_amd import cpf  # noqa: E402
+
+POS_TOL, ROT_TOL, COST_TOL = 1e-5, 1e-5, 1e-6
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = cpf.Context(0, 8 << 30)
+    yield c
+    c.close()
+
+
+def _problem(seed, T, K, robot_seed=1, joint=0, sigma=0.1, frac=0.25):
+    rb = synth.make_robot_prismatic(robot_seed, joint=joint)
+    return H.with_targets(synth.make_problem(rb, seed=seed, T=T, K=K, sigma=sigma, branch_frac=frac))
+
+
+@pytest.mark.parametrize("joint", [0, 3, 6])
+@pytest.mark.parametrize("M", [1, 4097])
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 2e-6)])
+def test_fk_batch_prismatic_matches_oracle(ctx, joint, M, dtype, tol):
+    rb = synth.make_robot_prismatic(3, joint=joint)
+    q = synth.random_configs(M + joint, M, rb)
+    qd = torch.tensor(q.T.copy(), dtype=dtype, device="cuda")
+    pose, jac = ctx.fk_batch(rb, qd, want_jac=True)
+    torch.cuda.synchronize()
+    pose = pose.double().cpu().numpy().T
+    jac = jac.double().cpu().numpy().T.reshape(M, 6, 7)
+    pr, Jr = oracle.fk(rb, q, jacobian=True)
+    np.testing.assert_allclose(pose, pr, atol=tol, rtol=0)
+    np.testing.assert_allclose(jac, Jr, atol=tol, rtol=0)
+    assert np.all(jac[:, 3:, joint] == 0.0)
+
+
+def test_coll_batch_prismatic_matches_oracle(ctx):
+    rb = synth.make_robot_prismatic(2)
+    cm = synth.collision_model(rb, synth.make_obstacles(2, 6))
+    M = 3000
+    q = synth.random_configs(41, M, rb)
+    qd = torch.tensor(q.T.copy(), dtype=torch.float64, device="cuda")
+    dist, grad = ctx.coll_batch(rb, cm, qd, want_grad=True)
+    torch.cuda.synchronize()
+    dist = dist.cpu().numpy().T
+    grad = grad.cpu().numpy().T.reshape(M, 2, 7)
+    dref, gref = oracle.coll_eval(rb, cm, q, gradient=True)
+    np.testing.assert_allclose(dist, dref, atol=1e-12, rtol=0)
+    np.testing.assert_allclose(grad, gref, atol=1e-9, rtol=0)
+
+
+@pytest.mark.parametrize("seed,T,K,sigma", [(1, 40, 24, 0.1), (2, 7, 5, 0.6), (3, 1, 9, 0.6),
+                                            (4, 300, 256, 0.4)])
+def test_search_prismatic_matches_oracle(ctx, seed, T, K, sigma):
+    p = _problem(seed, T, K, sigma=sigma)
+    if K >= 256:   # wide noise reaches the travel's ends: the 3 cm margin is exercised
+        x = p.cand[..., 0]
+        assert ((x <= 0.03) | (x >= 0.37)).any()
+    path_ref, best_ref, _, _ = oracle.dp(p.cand, p.robot)
+    with ctx.plan(p.robot, p.targets, p.cand) as plan:
+        path, best, mj = plan.dp_search()
+        rev, pri = plan.seed_steps()
+        research = plan.needs_research()
+    assert np.array_equal(path, path_ref) and best == best_ref
+    seed_xi = H.seed_of(p, path_ref)
+    rev_ref, pri_ref = oracle.seed_steps(seed_xi, p.robot)
+    assert (rev, pri) == (rev_ref, pri_ref) and mj == oracle.mjac(seed_xi)
+    assert research == (rev_ref > cpf.RESEARCH_MJAC_RAD or pri_ref > cpf.RESEARCH_MJAC_M)
+
+
+def test_search_prismatic_limit_margin_is_three_cm(ctx):
+    """The constructed case of the oracle's pin: 0.028 m from a limit is
+    penalised for a prismatic joint (outside 1.5 degrees read as a number)."""
+    rb = synth.make_robot_prismatic(0)
+    cand = np.zeros((4, 1, 7))
+    cand[:, 0, 0] = [0.028, 0.2, 0.032, 0.372]
+    extra = np.array([[0.0, 0.5, 0.7, 0.0]])
+    tg = oracle.fk(rb, cand[:, 0][:1])
+    path_ref, best_ref, _, _ = oracle.dp(cand, rb, extra=extra)
+    assert path_ref[0] == 1 and best_ref == 0.5
+    with ctx.plan(rb, tg, cand, node_pen=extra) as plan:
+        path, best, _ = plan.dp_search()
+    assert path[0] == 1 and best == 0.5
+
+
+def test_seed_steps_before_search_is_state_error(ctx):
+    p = _problem(5, 10, 4)
+    with ctx.plan(p.robot, p.targets, p.cand) as plan:
+        with pytest.raises(cpf.CpfError) as ei:
+            plan.seed_steps()
+        assert ei.value.status == cpf.E_STATE
+
+
+def test_bad_joint_type_rejected(ctx):
+    p = _problem(6, 10, 4)
+    bad = synth.make_robot_prismatic(1)
+    bad.joint_type = np.array([0, 0, 2, 0, 0, 0, 0], dtype=np.int32)
+    with pytest.raises(cpf.CpfError) as ei:
+        ctx.plan(bad, p.targets, p.cand)
+    assert ei.value.status == cpf.E_ARG
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("joint", [0, 4])
+def test_lm_prismatic_matches_oracle(ctx, prec, joint):
+    p = _problem(7 + joint, 120, 32, joint=joint)
+    path_ref, _, _, _ = oracle.dp(p.cand, p.robot)
+    ref = oracle.lm(p.robot, H.seed_of(p, path_ref), p.targets, 40)
+    with ctx.plan(p.robot, p.targets, p.cand, opts=cpf.make_opts(prec=prec)) as plan:
+        path, _, _ = plan.dp_search()
+        xi, rep = plan.lm_refine(40)
+    assert np.array_equal(path, path_ref)
+    ep, er, ec = H.parity_metrics(p, xi, ref["xi"])
+    assert ep <= POS_TOL and er <= ROT_TOL and ec <= COST_TOL, (ep, er, ec)
+    lo, hi = p.robot.q_lo, p.robot.q_hi
+    assert np.all(xi >= lo) and np.all(xi <= hi)
+
+
+@pytest.mark.parametrize("step,first", [(0.025, None), (0.015, 0)])
+def test_schedule_prismatic_step_threshold(ctx, step, first):
+    """A pose-exact seed whose prismatic joint steps by 2.5 cm fails the
+    first check (2 cm limit, Sec. II); with 1.5 cm it passes."""
+    rb = synth.make_robot_prismatic(2)
+    prob = synth.make_problem(rb, seed=5, T=20, K=1, sigma=0.0)
+    q = prob.q_star.copy()
+    q[:, 0] = 0.1
+    q[10:, 0] += step
+    tg = oracle.fk(rb, q)
+    ref = oracle.lm_schedule(rb, q, tg, 3)
+    with ctx.plan(rb, tg, q[None], opts=cpf.make_opts(prec="fp64", schedule=1)) as plan:
+        plan.dp_search()
+        xi, rep = plan.lm_refine(3)
+    for k in ("n_valid", "first_valid", "pose_steps", "diff_steps"):
+        assert rep[k] == ref[k], (k, rep[k], ref[k])
+    if first is None:
+        assert rep["first_valid"] != 0
+    else:
+        assert rep["first_valid"] == first
+    ep, er = oracle.pose_compare(rb, xi, ref["xi"])
+    assert ep <= POS_TOL and er <= ROT_TOL
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_schedule_prismatic_matches_oracle(ctx, prec):
+    p = _problem(11, 60, 16, sigma=0.08)
+    path_ref, _, _, _ = oracle.dp(p.cand, p.robot)
+    ref = oracle.lm_schedule(p.robot, H.seed_of(p, path_ref), p.targets, 30)
+    with ctx.plan(p.robot, p.targets, p.cand, opts=cpf.make_opts(prec=prec, schedule=1)) as plan:
+        plan.dp_search()
+        xi, rep = plan.lm_refine(30)
+    if prec == "fp64":
+        for k in ("n_valid", "first_valid", "pose_steps", "diff_steps"):
+            assert rep[k] == ref[k], (k, rep[k], ref[k])
+        ep, er = oracle.pose_compare(p.robot, xi, ref["xi"])
+        assert ep <= POS_TOL and er <= ROT_TOL
+    assert rep["n_valid"] >= 1
+
+
+def test_plans_with_capsules_and_prismatic_joint_are_switched_off(ctx):
+    """The combination is rejected before any device work (see the skipped
+    test below)."""
+    rb = synth.make_robot_prismatic(3)
+    cm = synth.collision_model(rb, synth.make_obstacles(3, 2))
+    p = H.with_targets(synth.make_problem(rb, seed=8, T=10, K=4, sigma=0.1))
+    with pytest.raises(cpf.CpfError) as ei:
+        ctx.plan(rb, p.targets, p.cand, coll=cm)
+    assert ei.value.status == cpf.E_UNSUPPORTED
+    with pytest.raises(cpf.CpfError) as ei:
+        ctx.submit(rb, p.targets, p.cand, cpf.make_opts(iters=2), coll=cm)
+    assert ei.value.status == cpf.E_UNSUPPORTED
+
+
+@pytest.mark.skip(reason="plans with collision capsules and a prismatic joint are switched off: the one GPU "
+                         "run of this case ended with the GPU faulted and no cause has been shown yet")
+def test_lm_with_collision_prismatic_matches_oracle(ctx):
+    rb = synth.make_robot_prismatic(3)
+    cm = synth.collision_model(rb, synth.make_obstacles(3, 6), margin=0.12)
+    p = H.with_targets(synth.make_problem(rb, seed=8, T=80, K=24, sigma=0.15, branch_frac=0.25))
+    path_ref, _, _, _ = oracle.dp(p.cand, rb, coll=cm)
+    ref = oracle.lm(rb, H.seed_of(p, path_ref), p.targets, 30, coll=cm)
+    with ctx.plan(rb, p.targets, p.cand, opts=cpf.make_opts(prec="fp64"), coll=cm) as plan:
+        path, _, _ = plan.dp_search()
+        xi, rep = plan.lm_refine(30)
+    assert np.array_equal(path, path_ref)
+    ep, er = oracle.pose_compare(rb, xi, ref["xi"])
+    c, cr = oracle.cost(rb, xi, p.targets, coll=cm), oracle.cost(rb, ref["xi"], p.targets, coll=cm)
+    assert ep <= POS_TOL and er <= ROT_TOL and abs(c - cr) / max(cr, 1e-12) <= COST_TOL
+
+
+def test_prismatic_batch_and_serving_equal_alone(ctx):
+    probs = [_problem(20 + i, 30 + 11 * i, 10 + 6 * i, robot_seed=i + 1) for i in range(3)]
+    opts = cpf.make_opts(iters=10)
+    batch = ctx.solve_batch([(p.robot, p.targets, p.cand) for p in probs], opts)
+    tickets = [ctx.submit(p.robot, p.targets, p.cand, opts) for p in probs]
+    served = [ctx.poll(t, p.T, timeout_ms=60000) for t, p in zip(tickets, probs)]
+    for p, b, s in zip(probs, batch, served):
+        with ctx.plan(p.robot, p.targets, p.cand, opts=opts) as plan:
+            path, best, _ = plan.dp_search()
+            xi, _ = plan.lm_refine(10)
+        for r in (b, s):
+            assert r is not None and r["status"] == 0
+            assert np.array_equal(r["path"], path) and r["search_best"] == best
+            assert np.array_equal(r["xi"], xi)
