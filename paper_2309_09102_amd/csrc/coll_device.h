@@ -42,7 +42,7 @@ __device__ __forceinline__ S clamp01(S v) {
 
 // Chain with the capsules: world endpoints P0[i], P1[i] of capsule i and the
 // axis Zs[i] and origin Os[i] of joint i (before link i).
-template <typename S, typename C>
+template <typename S, typename C, bool PRISM = true>
 __device__ __forceinline__ void capsule_chain(const RobotT<S> &rb, const C cap[NJ][7], const S *q,
                                               S Zs[NJ][3], S Os[NJ][3], S P0[NJ][3], S P1[NJ][3]) {
     S X[3], Y[3], Z[3], p[3];
@@ -51,7 +51,7 @@ __device__ __forceinline__ void capsule_chain(const RobotT<S> &rb, const C cap[N
     for (int i = 0; i < NJ; ++i) {
 #pragma unroll
         for (int r = 0; r < 3; ++r) { Zs[i][r] = Z[r]; Os[i][r] = p[r]; }
-        dh_step(rb, i, q[i], X, Y, Z, p);
+        dh_step<S, PRISM>(rb, i, q[i], X, Y, Z, p);
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             P0[i][r] = p[r] + X[r] * (S)cap[i][0] + Y[r] * (S)cap[i][1] + Z[r] * (S)cap[i][2];
@@ -187,10 +187,23 @@ __device__ __forceinline__ S seg_box_d2(const S A[3], const S D[3], const S lo[3
 
 // Gradient of a distance through a closest point w carried by link lnk: the
 // point's velocity for joint k is z_k x (w - o_k) (revolute) or z_k
-// (prismatic).
-template <typename S>
+// (prismatic).  PRISM false: every joint revolute (prism is not read).
+template <typename S, bool PRISM = true>
 __device__ __forceinline__ void point_gradient(uint32_t prism, const S Zs[NJ][3], const S Os[NJ][3], int lnk,
                                                const S w[3], const S u[3], S sgn, S g[NJ]) {
+    if constexpr (!PRISM) {
+#pragma unroll
+        for (int k = 0; k < NJ; ++k) {
+            if (k <= lnk) {
+                const S v0 = w[0] - Os[k][0], v1 = w[1] - Os[k][1], v2 = w[2] - Os[k][2];
+                const S c0 = Zs[k][1] * v2 - Zs[k][2] * v1;
+                const S c1 = Zs[k][2] * v0 - Zs[k][0] * v2;
+                const S c2 = Zs[k][0] * v1 - Zs[k][1] * v0;
+                g[k] += sgn * (u[0] * c0 + u[1] * c1 + u[2] * c2);
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < NJ; ++k) {
         if (k <= lnk) {
@@ -209,12 +222,12 @@ __device__ __forceinline__ void point_gradient(uint32_t prism, const S Zs[NJ][3]
 // provably farther than it are skipped as well: a minimum above `beyond` is
 // then reported as +inf (the residuals, which vanish beyond their margin,
 // need no more).
-template <typename S, bool GRAD, typename C>
+template <typename S, bool GRAD, typename C, bool PRISM = true>
 __device__ __forceinline__ void coll_distances(const RobotT<S> &rb, const C cap[NJ][7], int n_obs,
                                                const CPF_GLOBAL double *__restrict__ obs, const S *q, S dmin[2],
                                                S grad[2][NJ], S beyond = __builtin_inf()) {
     S Zs[NJ][3], Os[NJ][3], P0[NJ][3], P1[NJ][3];
-    capsule_chain(rb, cap, q, Zs, Os, P0, P1);
+    capsule_chain<S, C, PRISM>(rb, cap, q, Zs, Os, P0, P1);
     // bounding sphere of each capsule: centre and radius (half length + r)
     S cc[NJ][3], cr[NJ];
 #pragma unroll
@@ -315,8 +328,8 @@ __device__ __forceinline__ void coll_distances(const RobotT<S> &rb, const C cap[
             if (nrm > contact_eps<S>()) {
 #pragma unroll
                 for (int k = 0; k < 3; ++k) u[k] /= nrm;
-                point_gradient(rb.prism, Zs, Os, bi, pa, u, S(1), grad[0]);
-                point_gradient(rb.prism, Zs, Os, bj, pb, u, S(-1), grad[0]);
+                point_gradient<S, PRISM>(PRISM ? rb.prism : 0u, Zs, Os, bi, pa, u, S(1), grad[0]);
+                point_gradient<S, PRISM>(PRISM ? rb.prism : 0u, Zs, Os, bj, pb, u, S(-1), grad[0]);
             }
         }
         if (li >= 0) {
@@ -337,7 +350,7 @@ __device__ __forceinline__ void coll_distances(const RobotT<S> &rb, const C cap[
             if (nrm > contact_eps<S>()) {
 #pragma unroll
                 for (int k = 0; k < 3; ++k) u[k] /= nrm;
-                point_gradient(rb.prism, Zs, Os, li, pa, u, S(1), grad[1]);
+                point_gradient<S, PRISM>(PRISM ? rb.prism : 0u, Zs, Os, li, pa, u, S(1), grad[1]);
             }
         }
     }

@@ -67,10 +67,11 @@ struct LMState {
 struct DevPlan {
     int32_t T, K, has_extra, prec;
     int32_t refine_steps, schedule, prism, pad2;   // prism: bit i set = joint i prismatic
-    // joint-limit margin of revolute (rad) and prismatic (m) joints
-    double w_p, w_s, lam0, lam_min, lam_max, margin, penalty, margin_p;
-    // robot in double and float (cos/sin of the twist precomputed on host)
-    double a[8], d[8], ca[8], sa[8], off[8], lo[8], hi[8];
+    double w_p, w_s, lam0, lam_min, lam_max, margin, penalty;
+    // robot in double and float (cos/sin of the twist precomputed on host);
+    // margin_p, the joint-limit margin of prismatic joints (m), takes the
+    // eighth slot after the seven link lengths a
+    double a[NJ], margin_p, d[8], ca[8], sa[8], off[8], lo[8], hi[8];
     float af[8], df[8], caf[8], saf[8], offf[8];
     CPF_GLOBAL const float *cand;
     CPF_GLOBAL const double *extra;
@@ -111,28 +112,33 @@ struct RobotT {
 
 __host__ __device__ __forceinline__ bool is_prismatic(uint32_t prism, int i) { return (prism >> i) & 1u; }
 
-template <typename S>
-__device__ __forceinline__ RobotT<S> load_robot(const DevPlan &P);
-
-template <>
-__device__ __forceinline__ RobotT<double> load_robot<double>(const DevPlan &P) {
-    RobotT<double> r;
+// The plan's robot in precision S.  PRISM false: a chain known to be all
+// revolute (the plans with collision capsules, which cannot hold a
+// prismatic joint); the joint-type mask is then neither loaded nor used, and
+// the chain functions below compile their revolute-only form.
+template <typename S> struct RobotRows;
+template <> struct RobotRows<double> {
+    static __device__ __forceinline__ void get(const DevPlan &P, RobotT<double> &r) {
 #pragma unroll
-    for (int i = 0; i < NJ; ++i) {
-        r.a[i] = P.a[i]; r.d[i] = P.d[i]; r.ca[i] = P.ca[i]; r.sa[i] = P.sa[i]; r.off[i] = P.off[i];
+        for (int i = 0; i < NJ; ++i) {
+            r.a[i] = P.a[i]; r.d[i] = P.d[i]; r.ca[i] = P.ca[i]; r.sa[i] = P.sa[i]; r.off[i] = P.off[i];
+        }
     }
-    r.prism = (uint32_t)P.prism;
-    return r;
-}
-
-template <>
-__device__ __forceinline__ RobotT<float> load_robot<float>(const DevPlan &P) {
-    RobotT<float> r;
+};
+template <> struct RobotRows<float> {
+    static __device__ __forceinline__ void get(const DevPlan &P, RobotT<float> &r) {
 #pragma unroll
-    for (int i = 0; i < NJ; ++i) {
-        r.a[i] = P.af[i]; r.d[i] = P.df[i]; r.ca[i] = P.caf[i]; r.sa[i] = P.saf[i]; r.off[i] = P.offf[i];
+        for (int i = 0; i < NJ; ++i) {
+            r.a[i] = P.af[i]; r.d[i] = P.df[i]; r.ca[i] = P.caf[i]; r.sa[i] = P.saf[i]; r.off[i] = P.offf[i];
+        }
     }
-    r.prism = (uint32_t)P.prism;
+};
+
+template <typename S, bool PRISM = true>
+__device__ __forceinline__ RobotT<S> load_robot(const DevPlan &P) {
+    RobotT<S> r;
+    RobotRows<S>::get(P, r);
+    if constexpr (PRISM) r.prism = (uint32_t)P.prism;
     return r;
 }
 
@@ -156,8 +162,27 @@ __device__ __forceinline__ void chain_start(S X[3], S Y[3], S Z[3], S p[3]) {
 }
 
 // Link i of the chain: the frame before it becomes the frame after it.
-template <typename S>
+// PRISM false: every joint revolute (the mask is not read).
+template <typename S, bool PRISM = true>
 __device__ __forceinline__ void dh_step(const RobotT<S> &rb, int i, S qi, S X[3], S Y[3], S Z[3], S p[3]) {
+    if constexpr (!PRISM) {
+        S s, c;
+        dev_sincos(qi + rb.off[i], &s, &c);
+        S nx[3], w[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            nx[r] = c * X[r] + s * Y[r];
+            w[r] = c * Y[r] - s * X[r];
+        }
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            p[r] = p[r] + rb.a[i] * nx[r] + rb.d[i] * Z[r];
+            Y[r] = rb.ca[i] * w[r] + rb.sa[i] * Z[r];
+            Z[r] = rb.ca[i] * Z[r] - rb.sa[i] * w[r];
+            X[r] = nx[r];
+        }
+        return;
+    }
     const bool pr = is_prismatic(rb.prism, i);
     S s, c;
     dev_sincos(pr ? rb.off[i] : qi + rb.off[i], &s, &c);
@@ -192,7 +217,7 @@ __device__ __forceinline__ void jac_column(uint32_t prism, int i, const S z[3], 
     col[5] = pr ? S(0) : z[2];
 }
 
-template <typename S, bool FRAMES>
+template <typename S, bool FRAMES, bool PRISM = true>
 __device__ __forceinline__ void chain(const RobotT<S> &rb, const S *q, S X[3], S Y[3], S Z[3],
                                       S p[3], S Zs[NJ][3], S Os[NJ][3]) {
     chain_start(X, Y, Z, p);
@@ -202,7 +227,7 @@ __device__ __forceinline__ void chain(const RobotT<S> &rb, const S *q, S X[3], S
 #pragma unroll
             for (int r = 0; r < 3; ++r) { Zs[i][r] = Z[r]; Os[i][r] = p[r]; }
         }
-        dh_step(rb, i, q[i], X, Y, Z, p);
+        dh_step<S, PRISM>(rb, i, q[i], X, Y, Z, p);
     }
 }
 

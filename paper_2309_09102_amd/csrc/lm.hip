@@ -61,15 +61,17 @@ __device__ __forceinline__ void load_target(const DevPlan &P, int T, int t, S tg
     for (int e = 0; e < 12; ++e) tg[e] = (S)P.targets[(size_t)e * T + t];
 }
 
-// Squared pose residual of trajectory X ([7][T]) at waypoint t.
-template <typename S>
+// Squared pose residual of trajectory X ([7][T]) at waypoint t.  PR false
+// throughout this file: a chain known to be all revolute (plans with
+// collision capsules).
+template <typename S, bool PR>
 __device__ __forceinline__ double pose_sq(const DevPlan &P, const RobotT<S> &rb, const CPF_GLOBAL double *X,
                                           int T, int t) {
     S q[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) q[j] = (S)X[(size_t)j * T + t];
     S Xc[3], Yc[3], Zc[3], p[3], Zs[NJ][3], Os[NJ][3];
-    chain<S, false>(rb, q, Xc, Yc, Zc, p, Zs, Os);
+    chain<S, false, PR>(rb, q, Xc, Yc, Zc, p, Zs, Os);
     S tg[12], r[6];
     load_target<S>(P, T, t, tg);
     pose_residual<S>(Xc, Yc, Zc, p, tg, r);
@@ -90,11 +92,11 @@ template <> struct CapsOf<float> {
 
 // The two collision residuals max(0, margin - d) of waypoint t of X and,
 // with GRAD, their Jacobians (minus the distance gradients where positive).
-template <typename S, bool GRAD>
+template <typename S, bool GRAD, bool PR>
 __device__ __forceinline__ void coll_residuals(const DevPlan &P, const RobotT<S> &rb, const S q[NJ], double rc[2],
                                                double Jc[2][NJ]) {
     S dm[2], g[2][NJ];
-    coll_distances<S, GRAD>(rb, CapsOf<S>::get(P), P.n_obs, P.obs, q, dm, g, (S)P.coll_margin);
+    coll_distances<S, GRAD, S, PR>(rb, CapsOf<S>::get(P), P.n_obs, P.obs, q, dm, g, (S)P.coll_margin);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const double r = P.coll_margin - (double)dm[h];
@@ -107,12 +109,12 @@ __device__ __forceinline__ void coll_residuals(const DevPlan &P, const RobotT<S>
 
 // Cost of trajectory X: pose, smoothness and (wc != 0) collision parts,
 // block-reduced.
-template <typename S>
+template <typename S, bool PR>
 __device__ __forceinline__ double plan_cost(const DevPlan &P, const RobotT<S> &rb, const CPF_GLOBAL double *X,
                                             int T, double *red, double wp, double ws, double wc) {
     double ps = 0.0, ss = 0.0, cs = 0.0;
     for (int t = threadIdx.x; t < T; t += LM_BS) {
-        ps += pose_sq<S>(P, rb, X, T, t);
+        ps += pose_sq<S, PR>(P, rb, X, T, t);
         if (t + 1 < T) {
 #pragma unroll
             for (int j = 0; j < NJ; ++j) {
@@ -125,7 +127,7 @@ __device__ __forceinline__ double plan_cost(const DevPlan &P, const RobotT<S> &r
 #pragma unroll
             for (int j = 0; j < NJ; ++j) q[j] = (S)X[(size_t)j * T + t];
             double rc[2], Jc[2][NJ];
-            coll_residuals<S, false>(P, rb, q, rc, Jc);
+            coll_residuals<S, false, PR>(P, rb, q, rc, Jc);
             cs += rc[0] * rc[0] + rc[1] * rc[1];
         }
     }
@@ -136,7 +138,7 @@ __device__ __forceinline__ double plan_cost(const DevPlan &P, const RobotT<S> &r
 }
 
 // Linearise at xi: A_t = w_p J^T J (packed lower), g_t; returns max |g|.
-template <typename S>
+template <typename S, bool PR>
 __device__ __forceinline__ double linearise(const DevPlan &P, const RobotT<S> &rb, int T, double w_p, double w_s,
                                             double w_c) {
     double gmax = 0.0;
@@ -149,17 +151,30 @@ __device__ __forceinline__ double linearise(const DevPlan &P, const RobotT<S> &r
             q[j] = (S)xq[j];
         }
         S Xc[3], Yc[3], Zc[3], p[3], Zs[NJ][3], Os[NJ][3];
-        chain<S, true>(rb, q, Xc, Yc, Zc, p, Zs, Os);
+        chain<S, true, PR>(rb, q, Xc, Yc, Zc, p, Zs, Os);
         S tg[12], r[6];
         load_target<S>(P, T, t, tg);
         pose_residual<S>(Xc, Yc, Zc, p, tg, r);
         S J[6][NJ];
+        if constexpr (PR) {
 #pragma unroll
-        for (int i = 0; i < NJ; ++i) {
-            S col[6];
-            jac_column<S>(rb.prism, i, Zs[i], Os[i], p, col);
+            for (int i = 0; i < NJ; ++i) {
+                S col[6];
+                jac_column<S>(rb.prism, i, Zs[i], Os[i], p, col);
 #pragma unroll
-            for (int r = 0; r < 6; ++r) J[r][i] = col[r];
+                for (int r = 0; r < 6; ++r) J[r][i] = col[r];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < NJ; ++i) {
+                const S dx = p[0] - Os[i][0], dy = p[1] - Os[i][1], dz = p[2] - Os[i][2];
+                J[0][i] = Zs[i][1] * dz - Zs[i][2] * dy;
+                J[1][i] = Zs[i][2] * dx - Zs[i][0] * dz;
+                J[2][i] = Zs[i][0] * dy - Zs[i][1] * dx;
+                J[3][i] = Zs[i][0];
+                J[4][i] = Zs[i][1];
+                J[5][i] = Zs[i][2];
+            }
         }
         // The Gram matrix and the gradient J^T r of the (FP32 or FP64)
         // Jacobian and residual are accumulated in FP64.  Then the Gram is
@@ -205,7 +220,7 @@ __device__ __forceinline__ double linearise(const DevPlan &P, const RobotT<S> &r
 #pragma unroll
             for (int j = 0; j < NJ; ++j) q[j] = (S)P.xi[(size_t)j * T + t];
             double rc[2], Jc[2][NJ];
-            coll_residuals<S, true>(P, rb, q, rc, Jc);
+            coll_residuals<S, true, PR>(P, rb, q, rc, Jc);
 #pragma unroll
             for (int i = 0; i < NJ; ++i) {
 #pragma unroll
@@ -855,6 +870,7 @@ __device__ __forceinline__ void refine_residual(const DevPlan &P, int T, double 
 
 // FP64 pose errors of waypoint t of X against its target (the Sec. II
 // metrics): position distance and geodesic rotation angle.
+template <bool PR>
 __device__ __forceinline__ void pose_err_fp64(const DevPlan &P, const RobotT<double> &rb,
                                               const CPF_GLOBAL double *X, int T, int t, double *ep,
                                               double *er) {
@@ -862,7 +878,7 @@ __device__ __forceinline__ void pose_err_fp64(const DevPlan &P, const RobotT<dou
 #pragma unroll
     for (int j = 0; j < NJ; ++j) q[j] = X[(size_t)j * T + t];
     double Xc[3], Yc[3], Zc[3], p[3], Zs[NJ][3], Os[NJ][3];
-    chain<double, false>(rb, q, Xc, Yc, Zc, p, Zs, Os);
+    chain<double, false, PR>(rb, q, Xc, Yc, Zc, p, Zs, Os);
     double tg[12];
     load_target<double>(P, T, t, tg);
     const double dx = p[0] - tg[0], dy = p[1] - tg[1], dz = p[2] - tg[2];
@@ -889,40 +905,54 @@ __device__ __forceinline__ void pose_err_fp64(const DevPlan &P, const RobotT<dou
 // thresholds hold, else 0 (pose).
 template <bool COLL>
 __device__ int schedule_check(const DevPlan &P, LMState *st, int T, double *red) {
-    const RobotT<double> rb = load_robot<double>(P);
-    double ep = 0.0, er = 0.0, big = 0.0, len = 0.0, pen = 0.0;
+    const RobotT<double> rb = load_robot<double, !COLL>(P);
+    // mj: with capsules (all joints revolute) the largest step; otherwise 1
+    // when some joint steps beyond the threshold of its type, else 0
+    double ep = 0.0, er = 0.0, mj = 0.0, len = 0.0, pen = 0.0;
     for (int t = threadIdx.x; t < T; t += LM_BS) {
         double a, b;
-        pose_err_fp64(P, rb, P.xi, T, t, &a, &b);
+        pose_err_fp64<!COLL>(P, rb, P.xi, T, t, &a, &b);
         ep = fmax(ep, a);
         er = fmax(er, b);
         if (COLL) {   // deepest penetration, as a positive number
             double q[NJ], dm[2], g[2][NJ];
 #pragma unroll
             for (int j = 0; j < NJ; ++j) q[j] = P.xi[(size_t)j * T + t];
-            coll_distances<double, false>(rb, P.cap, P.n_obs, P.obs, q, dm, g);
+            coll_distances<double, false, double, !COLL>(rb, P.cap, P.n_obs, P.obs, q, dm, g);
             pen = fmax(pen, fmax(-dm[0], -dm[1]));
         }
         if (t + 1 < T)
 #pragma unroll
             for (int j = 0; j < NJ; ++j) {
                 const double d = fabs(P.xi[(size_t)j * T + t + 1] - P.xi[(size_t)j * T + t]);
-                if (d > P.vtol[is_prismatic((uint32_t)P.prism, j) ? 3 : 2]) big = 1.0;
+                if constexpr (COLL) mj = fmax(mj, d);
+                else if (d > P.vtol[is_prismatic(rb.prism, j) ? 3 : 2]) mj = 1.0;
                 len += d;
             }
     }
     ep = block_max(ep, red);
     er = block_max(er, red);
-    big = block_max(big, red);
+    mj = block_max(mj, red);
     len = block_sum(len, red);
     if (COLL) pen = block_max(pen, red);
     const bool pose_ok = ep <= P.vtol[0] && er <= P.vtol[1];
-    if (pose_ok && big == 0.0 && pen <= 0.0) {
-        for (int e = threadIdx.x; e < NJ * T; e += LM_BS) P.xv[e] = P.xi[e];
-        if (threadIdx.x == 0) {
-            st->n_valid += 1;
-            if (st->first_valid < 0) st->first_valid = st->iters_done;
-            st->valid_length = len;
+    if constexpr (COLL) {
+        if (pose_ok && mj <= P.vtol[2] && pen <= 0.0) {
+            for (int e = threadIdx.x; e < NJ * T; e += LM_BS) P.xv[e] = P.xi[e];
+            if (threadIdx.x == 0) {
+                st->n_valid += 1;
+                if (st->first_valid < 0) st->first_valid = st->iters_done;
+                st->valid_length = len;
+            }
+        }
+    } else {
+        if (pose_ok && mj == 0.0 && pen <= 0.0) {
+            for (int e = threadIdx.x; e < NJ * T; e += LM_BS) P.xv[e] = P.xi[e];
+            if (threadIdx.x == 0) {
+                st->n_valid += 1;
+                if (st->first_valid < 0) st->first_valid = st->iters_done;
+                st->valid_length = len;
+            }
         }
     }
     return pose_ok ? 1 : 0;
@@ -964,7 +994,7 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
                 P.xi[(size_t)j * T + t] = v;
             }
         __syncthreads();
-        const double c0 = plan_cost<S>(P, load_robot<S>(P), P.xi, T, red, P.w_p, P.w_s, wc_all);
+        const double c0 = plan_cost<S, !COLL>(P, load_robot<S, !COLL>(P), P.xi, T, red, P.w_p, P.w_s, wc_all);
         if (tid == 0) {
             st->nu = 2.0;
             st->cost = c0;
@@ -1047,7 +1077,7 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
             if (m != sh_sched[2]) {   // new objective: its cost and linearisation
                 // (the barriers inside plan_cost order every lane's read of
                 // sh_sched[2] before lane 0 rewrites it)
-                const double c = plan_cost<S>(P, load_robot<S>(P), P.xi, T, red, wp, ws, wc);
+                const double c = plan_cost<S, !COLL>(P, load_robot<S, !COLL>(P), P.xi, T, red, wp, ws, wc);
                 if (tid == 0) {
                     sh_cost = c;
                     sh_flags[0] = 1;
@@ -1058,7 +1088,7 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
         }
         const double lam = m ? P.lam0 : sh_lam;
         if (sh_flags[0]) {
-            const double gm = linearise<S>(P, load_robot<S>(P), T, wp, ws, wc);
+            const double gm = linearise<S, !COLL>(P, load_robot<S, !COLL>(P), T, wp, ws, wc);
             const double gmax = block_max(gm, red);
             if (tid == 0) st->grad_inf = gmax;
         }
@@ -1111,7 +1141,7 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
                 pr += dl * (lam * dl - P.g[e]);
             }
         __syncthreads();
-        const double cn = plan_cost<S>(P, load_robot<S>(P), P.xt, T, red, wp, ws, wc);
+        const double cn = plan_cost<S, !COLL>(P, load_robot<S, !COLL>(P), P.xt, T, red, wp, ws, wc);
         const double pred = 0.5 * block_sum(pr, red);
         PHASE_MARK(5);
         if (tid == 0) {
@@ -1220,11 +1250,11 @@ __global__ __launch_bounds__(LM_BS) void eval_kernel(const DevPlan *__restrict__
         if (!finished || s0->reported) return;
     }
     __shared__ double red[LM_BS];
-    const RobotT<double> rb = load_robot<double>(P);
+    const RobotT<double> rb = load_robot<double, !COLL>(P);
     double ep = 0.0, er = 0.0, mj = 0.0, ns = -__builtin_inf(), ne = -__builtin_inf();
     for (int t = threadIdx.x; t < T; t += LM_BS) {
         double a, b;
-        pose_err_fp64(P, rb, P.xi, T, t, &a, &b);
+        pose_err_fp64<!COLL>(P, rb, P.xi, T, t, &a, &b);
         ep = fmax(ep, a);
         er = fmax(er, b);
         if (t + 1 < T)
@@ -1235,7 +1265,7 @@ __global__ __launch_bounds__(LM_BS) void eval_kernel(const DevPlan *__restrict__
             double q[NJ], dm[2], g[2][NJ];
 #pragma unroll
             for (int j = 0; j < NJ; ++j) q[j] = P.xi[(size_t)j * T + t];
-            coll_distances<double, false>(rb, P.cap, P.n_obs, P.obs, q, dm, g);
+            coll_distances<double, false, double, !COLL>(rb, P.cap, P.n_obs, P.obs, q, dm, g);
             ns = fmax(ns, -dm[0]);
             ne = fmax(ne, -dm[1]);
         }
