@@ -193,7 +193,7 @@ def main():
     lm_flops = LM_FLOPS_PER_WAYPOINT_ITER * T * iters
     dp_flops = DP_OPS_PER_PAIR * (T - 1) * K * K
     if lm_ms >= dp_ms:
-        dom, dom_ms, dom_flops = "lm_kernel<float, false, false>", lm_ms, lm_flops
+        dom, dom_ms, dom_flops = "lm_kernel<float, false, false, false>", lm_ms, lm_flops
     else:
         dom, dom_ms, dom_flops = "dp_kernel", dp_ms, dp_flops
     achieved = dom_flops / (dom_ms * 1e-3) / 1e12

@@ -754,11 +754,11 @@ cpf_status cpf_lm_refine(cpf_plan *plan, int32_t iters, double *xi_out, cpf_lm_r
     HIP_TRY(hipSetDevice(ctx->device));
     HIP_TRY(timed(ctx, KIND_LM, ctx->stream,
                   [&] {
-                      return lm_launch(plan->d_desc, 1, plan->opts.prec, plan->opts.schedule, plan->robot.has_caps,
+                      return lm_launch(plan->d_desc, 1, plan->opts.prec, plan->opts.schedule, plan_geo(plan->robot),
                                        iters, ctx->stream);
                   }));
     HIP_TRY(timed(ctx, KIND_EVAL, ctx->stream,
-                  [&] { return eval_launch(plan->d_desc, 1, 0, plan->robot.has_caps, ctx->stream); }));
+                  [&] { return eval_launch(plan->d_desc, 1, 0, plan_geo(plan->robot), ctx->stream); }));
     PlanReadback rb;
     cpf_status st = read_plan(plan, ctx->stream, nullptr, &rb, xi_out, nullptr, nullptr);
     if (st != CPF_OK) return st;
@@ -777,9 +777,10 @@ cpf_status cpf_plan_solve(cpf_plan *plan, int32_t *path_out, double *best_out, d
     HIP_TRY(timed(ctx, KIND_DP, s, [&] { return dp_launch(plan->d_desc, 1, plan->K, plan->T, plan->lists_valid, coll, s); }));
     plan->lists_valid = true;
     HIP_TRY(timed(ctx, KIND_LM, s, [&] {
-        return lm_launch(plan->d_desc, 1, plan->opts.prec, plan->opts.schedule, coll, plan->opts.iters, s);
+        return lm_launch(plan->d_desc, 1, plan->opts.prec, plan->opts.schedule, plan_geo(plan->robot), plan->opts.iters,
+                         s);
     }));
-    HIP_TRY(timed(ctx, KIND_EVAL, s, [&] { return eval_launch(plan->d_desc, 1, 0, coll, s); }));
+    HIP_TRY(timed(ctx, KIND_EVAL, s, [&] { return eval_launch(plan->d_desc, 1, 0, plan_geo(plan->robot), s); }));
     PlanReadback rb;
     cpf_status st = read_plan(plan, s, nullptr, &rb, xi_out, path_out, nullptr);
     if (st != CPF_OK) return st;
@@ -830,9 +831,9 @@ cpf_status cpf_solve_batch(cpf_ctx *ctx, int32_t nplans, const cpf_robot *robots
         for (auto *p : plans) plan_destroy(p);
     };
     int maxK = 0, maxT = 0;
-    bool kinds[2] = {false, false};   // plans without / with collision geometry
+    bool kinds[GEO_KINDS] = {false, false, false};   // geometry kinds present
     for (int i = 0; i < nplans; ++i) {
-        kinds[hrs[i].has_caps ? 1 : 0] = true;
+        kinds[plan_geo(hrs[i])] = true;
         cpf_plan *p = nullptr;
         if ((st = plan_create(ctx, hrs[i], &probs[i], &o, 0, ctx->stream, &p)) != CPF_OK) {
             cleanup();
@@ -852,12 +853,12 @@ cpf_status cpf_solve_batch(cpf_ctx *ctx, int32_t nplans, const cpf_robot *robots
     const int64_t t0 = now_ns();
     if (e == hipSuccess)
         e = timed(ctx, KIND_DP, ctx->stream,
-                  [&] { return dp_launch(d_descs, nplans, maxK, maxT, false, kinds[1], ctx->stream); });
+                  [&] { return dp_launch(d_descs, nplans, maxK, maxT, false, kinds[GEO_COLL], ctx->stream); });
     if (e == hipSuccess)
         e = timed(ctx, KIND_LM, ctx->stream,
                   [&] {
                       hipError_t r = hipSuccess;
-                      for (int c = 0; c < 2 && r == hipSuccess; ++c)
+                      for (int c = 0; c < GEO_KINDS && r == hipSuccess; ++c)
                           if (kinds[c]) r = lm_launch(d_descs, nplans, o.prec, o.schedule, c, o.iters, ctx->stream);
                       return r;
                   });
@@ -865,7 +866,7 @@ cpf_status cpf_solve_batch(cpf_ctx *ctx, int32_t nplans, const cpf_robot *robots
         e = timed(ctx, KIND_EVAL, ctx->stream,
                   [&] {
                       hipError_t r = hipSuccess;
-                      for (int c = 0; c < 2 && r == hipSuccess; ++c)
+                      for (int c = 0; c < GEO_KINDS && r == hipSuccess; ++c)
                           if (kinds[c]) r = eval_launch(d_descs, nplans, 0, c, ctx->stream);
                       return r;
                   });

@@ -17,6 +17,12 @@ struct HostRobot {
     double cap[NJ][7];   // capsule of each link: p0, p1 (frame after the link), radius
 };
 
+// Plan geometry kinds, one LM and report kernel instance each: an
+// all-revolute chain, collision capsules (always all-revolute), a chain with
+// a prismatic joint.
+enum { GEO_PLAIN = 0, GEO_COLL = 1, GEO_PRISM = 2, GEO_KINDS = 3 };
+inline int plan_geo(const HostRobot &hr) { return hr.has_caps ? GEO_COLL : (hr.prism ? GEO_PRISM : GEO_PLAIN); }
+
 // Capsules passed to a kernel by value.
 struct HostCaps {
     double v[NJ][7];
@@ -50,11 +56,12 @@ hipError_t dp_launch(const DevPlan *d_plans, int nplans, int maxK, int maxT, boo
 // were appended (the old nodes' penalties and lists already copied in).
 hipError_t dp_append_launch(const DevPlan *d_plan, int K_old, int K, int T, bool coll, hipStream_t s);
 // Up to `iters` LM iterations for each plan of precision prec (0 = mixed,
-// 1 = FP64); empty slots (T = 0) and plans of the other precision are skipped.
-hipError_t lm_launch(const DevPlan *d_plans, int nplans, int prec, int sched, int coll, int iters, hipStream_t s);
+// 1 = FP64), objective kind sched and geometry kind geo (GEO_*); empty slots
+// (T = 0) and plans of another precision or kind are skipped.
+hipError_t lm_launch(const DevPlan *d_plans, int nplans, int prec, int sched, int geo, int iters, hipStream_t s);
 // Pose error vs targets and mjac of the current trajectory (FP64 FK).  With
 // only_finished, only plans that reached their iteration target (or failed)
 // and have not been reported yet.
-hipError_t eval_launch(const DevPlan *d_plans, int nplans, int only_finished, int coll, hipStream_t s);
+hipError_t eval_launch(const DevPlan *d_plans, int nplans, int only_finished, int geo, hipStream_t s);
 
 }  // namespace cpf

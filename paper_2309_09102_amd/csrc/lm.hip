@@ -903,29 +903,29 @@ __device__ __forceinline__ void pose_err_fp64(const DevPlan &P, const RobotT<dou
 // counted.  Returns
 // the next step's objective to all lanes: 1 (differencing) when the pose
 // thresholds hold, else 0 (pose).
-template <bool COLL>
+template <bool COLL, bool PR>
 __device__ int schedule_check(const DevPlan &P, LMState *st, int T, double *red) {
-    const RobotT<double> rb = load_robot<double, !COLL>(P);
-    // mj: with capsules (all joints revolute) the largest step; otherwise 1
-    // when some joint steps beyond the threshold of its type, else 0
+    const RobotT<double> rb = load_robot<double, PR>(P);
+    // mj: for an all-revolute chain the largest step; with a prismatic joint
+    // 1 when some joint steps beyond the threshold of its type, else 0
     double ep = 0.0, er = 0.0, mj = 0.0, len = 0.0, pen = 0.0;
     for (int t = threadIdx.x; t < T; t += LM_BS) {
         double a, b;
-        pose_err_fp64<!COLL>(P, rb, P.xi, T, t, &a, &b);
+        pose_err_fp64<PR>(P, rb, P.xi, T, t, &a, &b);
         ep = fmax(ep, a);
         er = fmax(er, b);
         if (COLL) {   // deepest penetration, as a positive number
             double q[NJ], dm[2], g[2][NJ];
 #pragma unroll
             for (int j = 0; j < NJ; ++j) q[j] = P.xi[(size_t)j * T + t];
-            coll_distances<double, false, double, !COLL>(rb, P.cap, P.n_obs, P.obs, q, dm, g);
+            coll_distances<double, false, double, PR>(rb, P.cap, P.n_obs, P.obs, q, dm, g);
             pen = fmax(pen, fmax(-dm[0], -dm[1]));
         }
         if (t + 1 < T)
 #pragma unroll
             for (int j = 0; j < NJ; ++j) {
                 const double d = fabs(P.xi[(size_t)j * T + t + 1] - P.xi[(size_t)j * T + t]);
-                if constexpr (COLL) mj = fmax(mj, d);
+                if constexpr (!PR) mj = fmax(mj, d);
                 else if (d > P.vtol[is_prismatic(rb.prism, j) ? 3 : 2]) mj = 1.0;
                 len += d;
             }
@@ -936,7 +936,7 @@ __device__ int schedule_check(const DevPlan &P, LMState *st, int T, double *red)
     len = block_sum(len, red);
     if (COLL) pen = block_max(pen, red);
     const bool pose_ok = ep <= P.vtol[0] && er <= P.vtol[1];
-    if constexpr (COLL) {
+    if constexpr (!PR) {
         if (pose_ok && mj <= P.vtol[2] && pen <= 0.0) {
             for (int e = threadIdx.x; e < NJ * T; e += LM_BS) P.xv[e] = P.xi[e];
             if (threadIdx.x == 0) {
@@ -959,16 +959,20 @@ __device__ int schedule_check(const DevPlan &P, LMState *st, int T, double *red)
 }
 
 // One instance per precision, objective kind (the weighted sum, or the
-// alternating schedule) and collision geometry (with or without), so that
-// the schedule's state and the collision terms add no register pressure to
-// the plain iteration.
-template <typename S, bool SCHED, bool COLL>
+// alternating schedule) and geometry (an all-revolute chain, collision
+// capsules, a chain with a prismatic joint), so that the schedule's state,
+// the collision terms and the joint-type selects add nothing to the plain
+// iteration.  Plans with capsules are all-revolute (COLL implies !PR).
+template <typename S, bool SCHED, bool COLL, bool PR>
 __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ plans, int iters) {
+    static_assert(!(COLL && PR), "plans with capsules are all-revolute");
     constexpr int PREC = sizeof(S) == sizeof(double) ? 1 : 0;
     const DevPlan &P = plans[blockIdx.x];
     const int T = P.T;
     // empty slot, or a plan of another precision, objective kind or geometry
-    if (T <= 0 || P.prec != PREC || (P.schedule != 0) != SCHED || (P.has_coll != 0) != COLL) return;
+    if (T <= 0 || P.prec != PREC || (P.schedule != 0) != SCHED || (P.has_coll != 0) != COLL ||
+        (!COLL && (P.prism != 0) != PR))
+        return;
     {
         const LMState *s0 = P.st;
         if (s0->seeded && s0->iters_target > 0 && s0->iters_done >= s0->iters_target) return;
@@ -994,7 +998,7 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
                 P.xi[(size_t)j * T + t] = v;
             }
         __syncthreads();
-        const double c0 = plan_cost<S, !COLL>(P, load_robot<S, !COLL>(P), P.xi, T, red, P.w_p, P.w_s, wc_all);
+        const double c0 = plan_cost<S, PR>(P, load_robot<S, PR>(P), P.xi, T, red, P.w_p, P.w_s, wc_all);
         if (tid == 0) {
             st->nu = 2.0;
             st->cost = c0;
@@ -1063,7 +1067,7 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
         double wp = P.w_p, ws = P.w_s, wc = wc_all;
         if (sched) {
             if (!sh_sched[0]) {
-                const int nm = schedule_check<COLL>(P, st, T, red);
+                const int nm = schedule_check<COLL, PR>(P, st, T, red);
                 if (tid == 0) {
                     sh_sched[0] = 1;
                     sh_sched[1] = nm;
@@ -1077,7 +1081,7 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
             if (m != sh_sched[2]) {   // new objective: its cost and linearisation
                 // (the barriers inside plan_cost order every lane's read of
                 // sh_sched[2] before lane 0 rewrites it)
-                const double c = plan_cost<S, !COLL>(P, load_robot<S, !COLL>(P), P.xi, T, red, wp, ws, wc);
+                const double c = plan_cost<S, PR>(P, load_robot<S, PR>(P), P.xi, T, red, wp, ws, wc);
                 if (tid == 0) {
                     sh_cost = c;
                     sh_flags[0] = 1;
@@ -1088,7 +1092,7 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
         }
         const double lam = m ? P.lam0 : sh_lam;
         if (sh_flags[0]) {
-            const double gm = linearise<S, !COLL>(P, load_robot<S, !COLL>(P), T, wp, ws, wc);
+            const double gm = linearise<S, PR>(P, load_robot<S, PR>(P), T, wp, ws, wc);
             const double gmax = block_max(gm, red);
             if (tid == 0) st->grad_inf = gmax;
         }
@@ -1141,7 +1145,7 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
                 pr += dl * (lam * dl - P.g[e]);
             }
         __syncthreads();
-        const double cn = plan_cost<S, !COLL>(P, load_robot<S, !COLL>(P), P.xt, T, red, wp, ws, wc);
+        const double cn = plan_cost<S, PR>(P, load_robot<S, PR>(P), P.xt, T, red, wp, ws, wc);
         const double pred = 0.5 * block_sum(pr, red);
         PHASE_MARK(5);
         if (tid == 0) {
@@ -1215,7 +1219,7 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
     // The check after the last step of the call (the next call's first step
     // then reuses its decision).
     if (sched && sh_flags[1] == 0 && !sh_sched[0]) {
-        const int nm = schedule_check<COLL>(P, st, T, red);
+        const int nm = schedule_check<COLL, PR>(P, st, T, red);
         if (tid == 0) {
             sh_sched[0] = 1;
             sh_sched[1] = nm;
@@ -1237,12 +1241,13 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
 // Report: FP64 pose error of xi vs the targets and mjac (Sec. II metrics)
 // and, with collision geometry, the smallest self and environment distances
 // along xi (+inf without).
-template <bool COLL>
+template <bool COLL, bool PR>
 __global__ __launch_bounds__(LM_BS) void eval_kernel(const DevPlan *__restrict__ plans,
                                                      int only_finished) {
+    static_assert(!(COLL && PR), "plans with capsules are all-revolute");
     const DevPlan &P = plans[blockIdx.x];
     const int T = P.T;
-    if (T <= 0 || (P.has_coll != 0) != COLL) return;
+    if (T <= 0 || (P.has_coll != 0) != COLL || (!COLL && (P.prism != 0) != PR)) return;
     if (only_finished) {
         const LMState *s0 = P.st;
         const bool finished = s0->status != 0 ||
@@ -1250,11 +1255,11 @@ __global__ __launch_bounds__(LM_BS) void eval_kernel(const DevPlan *__restrict__
         if (!finished || s0->reported) return;
     }
     __shared__ double red[LM_BS];
-    const RobotT<double> rb = load_robot<double, !COLL>(P);
+    const RobotT<double> rb = load_robot<double, PR>(P);
     double ep = 0.0, er = 0.0, mj = 0.0, ns = -__builtin_inf(), ne = -__builtin_inf();
     for (int t = threadIdx.x; t < T; t += LM_BS) {
         double a, b;
-        pose_err_fp64<!COLL>(P, rb, P.xi, T, t, &a, &b);
+        pose_err_fp64<PR>(P, rb, P.xi, T, t, &a, &b);
         ep = fmax(ep, a);
         er = fmax(er, b);
         if (t + 1 < T)
@@ -1265,7 +1270,7 @@ __global__ __launch_bounds__(LM_BS) void eval_kernel(const DevPlan *__restrict__
             double q[NJ], dm[2], g[2][NJ];
 #pragma unroll
             for (int j = 0; j < NJ; ++j) q[j] = P.xi[(size_t)j * T + t];
-            coll_distances<double, false, double, !COLL>(rb, P.cap, P.n_obs, P.obs, q, dm, g);
+            coll_distances<double, false, double, PR>(rb, P.cap, P.n_obs, P.obs, q, dm, g);
             ns = fmax(ns, -dm[0]);
             ne = fmax(ne, -dm[1]);
         }
@@ -1288,33 +1293,40 @@ __global__ __launch_bounds__(LM_BS) void eval_kernel(const DevPlan *__restrict__
 }
 
 template <typename S, bool SCHED>
-static void lm_launch_coll(const DevPlan *d_plans, int nplans, int coll, int iters, hipStream_t s) {
+static void lm_launch_geo(const DevPlan *d_plans, int nplans, int geo, int iters, hipStream_t s) {
     const dim3 g(nplans), b(LM_BS);
-    if (coll)
-        hipLaunchKernelGGL((lm_kernel<S, SCHED, true>), g, b, 0, s, d_plans, iters);
+    if (geo == GEO_COLL)
+        hipLaunchKernelGGL((lm_kernel<S, SCHED, true, false>), g, b, 0, s, d_plans, iters);
+    else if (geo == GEO_PRISM)
+        hipLaunchKernelGGL((lm_kernel<S, SCHED, false, true>), g, b, 0, s, d_plans, iters);
     else
-        hipLaunchKernelGGL((lm_kernel<S, SCHED, false>), g, b, 0, s, d_plans, iters);
+        hipLaunchKernelGGL((lm_kernel<S, SCHED, false, false>), g, b, 0, s, d_plans, iters);
 }
 
-hipError_t lm_launch(const DevPlan *d_plans, int nplans, int prec, int sched, int coll, int iters, hipStream_t s) {
+hipError_t lm_launch(const DevPlan *d_plans, int nplans, int prec, int sched, int geo, int iters, hipStream_t s) {
     if (nplans <= 0) return hipSuccess;
+    if (geo < 0 || geo >= GEO_KINDS) return hipErrorInvalidValue;
     if (prec == 1 && sched)
-        lm_launch_coll<double, true>(d_plans, nplans, coll, iters, s);
+        lm_launch_geo<double, true>(d_plans, nplans, geo, iters, s);
     else if (prec == 1)
-        lm_launch_coll<double, false>(d_plans, nplans, coll, iters, s);
+        lm_launch_geo<double, false>(d_plans, nplans, geo, iters, s);
     else if (sched)
-        lm_launch_coll<float, true>(d_plans, nplans, coll, iters, s);
+        lm_launch_geo<float, true>(d_plans, nplans, geo, iters, s);
     else
-        lm_launch_coll<float, false>(d_plans, nplans, coll, iters, s);
+        lm_launch_geo<float, false>(d_plans, nplans, geo, iters, s);
     return hipGetLastError();
 }
 
-hipError_t eval_launch(const DevPlan *d_plans, int nplans, int only_finished, int coll, hipStream_t s) {
+hipError_t eval_launch(const DevPlan *d_plans, int nplans, int only_finished, int geo, hipStream_t s) {
     if (nplans <= 0) return hipSuccess;
-    if (coll)
-        hipLaunchKernelGGL((eval_kernel<true>), dim3(nplans), dim3(LM_BS), 0, s, d_plans, only_finished);
+    if (geo < 0 || geo >= GEO_KINDS) return hipErrorInvalidValue;
+    const dim3 g(nplans), b(LM_BS);
+    if (geo == GEO_COLL)
+        hipLaunchKernelGGL((eval_kernel<true, false>), g, b, 0, s, d_plans, only_finished);
+    else if (geo == GEO_PRISM)
+        hipLaunchKernelGGL((eval_kernel<false, true>), g, b, 0, s, d_plans, only_finished);
     else
-        hipLaunchKernelGGL((eval_kernel<false>), dim3(nplans), dim3(LM_BS), 0, s, d_plans, only_finished);
+        hipLaunchKernelGGL((eval_kernel<false, false>), g, b, 0, s, d_plans, only_finished);
     return hipGetLastError();
 }
 

@@ -71,9 +71,10 @@ struct Server {
     std::vector<LMState> h_states, h_init;
     std::vector<Request *> slot_req;
     std::vector<Request *> searching;   // the batch in flight on s_up
-    // tick graphs by kinds present: bit 0 schedule, bit 1 collision geometry
-    hipGraph_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
-    hipGraphExec_t exec[4] = {nullptr, nullptr, nullptr, nullptr};
+    // tick graphs by kinds present: bit 0 schedule, bit 1 collision geometry,
+    // bit 2 a prismatic joint
+    hipGraph_t graph[8] = {};
+    hipGraphExec_t exec[8] = {};
 };
 
 namespace {
@@ -102,18 +103,20 @@ cpf_status server_init(cpf_ctx *ctx, Server *sv) {
 }
 
 // The tick graph for the plan kinds in `kinds` (bit 0 schedule, bit 1
-// collision geometry), captured at its first use: the LM instances of both
-// precisions for those kinds and the plain ones, then the report kernels.
+// collision geometry, bit 2 a prismatic joint), captured at its first use:
+// the LM instances of both precisions for those kinds and the plain ones,
+// then the report kernels.
 cpf_status tick_graph(Server *sv, int kinds, hipGraphExec_t *out) {
     if (!sv->exec[kinds]) {
         HIP_TRY(hipStreamBeginCapture(sv->s_lm, hipStreamCaptureModeThreadLocal));
         hipError_t e = hipSuccess;
-        for (int coll = 0; coll <= ((kinds >> 1) & 1); ++coll)
-            for (int sched = 0; sched <= (kinds & 1); ++sched)
+        const bool geos[GEO_KINDS] = {true, ((kinds >> 1) & 1) != 0, ((kinds >> 2) & 1) != 0};
+        for (int geo = 0; geo < GEO_KINDS; ++geo)
+            for (int sched = 0; sched <= (kinds & 1) && geos[geo]; ++sched)
                 for (int prec = 0; prec < 2 && e == hipSuccess; ++prec)
-                    e = lm_launch(sv->d_work, sv->cap, prec, sched, coll, sv->ipt, sv->s_lm);
-        for (int coll = 0; coll <= ((kinds >> 1) & 1) && e == hipSuccess; ++coll)
-            e = eval_launch(sv->d_work, sv->cap, 1, coll, sv->s_lm);
+                    e = lm_launch(sv->d_work, sv->cap, prec, sched, geo, sv->ipt, sv->s_lm);
+        for (int geo = 0; geo < GEO_KINDS && e == hipSuccess; ++geo)
+            if (geos[geo]) e = eval_launch(sv->d_work, sv->cap, 1, geo, sv->s_lm);
         hipError_t e2 = hipStreamEndCapture(sv->s_lm, &sv->graph[kinds]);
         if (e != hipSuccess) return fail(CPF_E_DEVICE, "tick capture: %s", hipGetErrorString(e));
         if (e2 != hipSuccess) return fail(CPF_E_DEVICE, "tick capture end: %s", hipGetErrorString(e2));
@@ -126,7 +129,7 @@ cpf_status tick_graph(Server *sv, int kinds, hipGraphExec_t *out) {
 void server_free(Server *sv) {
     if (sv->s_up) HIP_IGNORE(hipStreamSynchronize(sv->s_up));
     if (sv->s_lm) HIP_IGNORE(hipStreamSynchronize(sv->s_lm));
-    for (int g = 0; g < 4; ++g) {
+    for (int g = 0; g < 8; ++g) {
         if (sv->exec[g]) HIP_IGNORE(hipGraphExecDestroy(sv->exec[g]));
         if (sv->graph[g]) HIP_IGNORE(hipGraphDestroy(sv->graph[g]));
     }
@@ -348,7 +351,8 @@ void server_main(cpf_ctx *ctx) {
         if (active.empty()) continue;
         // 3. one LM tick over every slot, then all slot states in one copy
         int kinds = 0;
-        for (Request *r : active) kinds |= (r->opts.schedule ? 1 : 0) | (r->robot.has_caps ? 2 : 0);
+        for (Request *r : active)
+            kinds |= (r->opts.schedule ? 1 : 0) | (r->robot.has_caps ? 2 : 0) | (r->robot.prism ? 4 : 0);
         hipGraphExec_t exec = nullptr;
         cpf_status dev = tick_graph(sv.get(), kinds, &exec);
         hipError_t e = dev == CPF_OK ? hipSuccess : hipErrorUnknown;
