@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--iters", type=int, default=50)
     ap.add_argument("--workload", default="T300_K256",
                     choices=["T300_K256", "T1000_K512", "batch64", "batchopt", "schedule", "research",
-                             "collision", "serve"],
+                             "collision", "prismatic", "serve"],
                     help="T300_K256: the headline single-request line; the others are the "
                          "additional measured workloads in paper_2309_09102_amd/workloads.py")
     ap.add_argument("--duration", type=float, default=10.0, help="serve: stream length (s)")
@@ -132,6 +132,8 @@ def main():
             out = workloads.run_research()
         elif args.workload == "collision":
             out = workloads.run_collision()
+        elif args.workload == "prismatic":
+            out = workloads.run_prismatic()
         else:
             out = workloads.run_serve(duration_s=args.duration)
         print(json.dumps(out))

@@ -254,6 +254,48 @@ def run_collision(iters=50, n_obs=6, obstacle_seed=4):
     return out
 
 
+def run_prismatic(iters=50, robot_seed=0):
+    """The T=300, K=256 request (seed 2, sigma 0.1, a quarter of the
+    candidates branch-offset) on the robot of the same seed with a prismatic
+    first joint (travel 0-0.4 m): the search with the seed's steps split by
+    joint type and the re-search decision (12 deg / 3 cm), then 50 LM
+    iterations in both precisions and the alternating schedule with its 2 cm
+    step threshold, beside the all-revolute robot on the same request."""
+    import torch
+    from paper_2309_09102_amd import cpf, synth
+    dev = torch.device("cuda:0")
+    ctx = cpf.Context(0)
+    out = {"mode": "prismatic", "T": 300, "K": 256, "lm_iters": iters, "arms": {}}
+    robots = (("prismatic", synth.make_robot_prismatic(robot_seed)), ("revolute", synth.make_robot(robot_seed)))
+    for rname, rb in robots:
+        p = _targets(ctx, synth.make_problem(rb, seed=2, T=300, K=256, sigma=0.1, branch_frac=0.25), torch, dev)
+        arms = (("mixed", dict(prec="mixed")), ("fp64", dict(prec="fp64")),
+                ("schedule_mixed", dict(prec="mixed", schedule=1)))
+        for arm, kw in arms:
+            o = cpf.make_opts(**kw)
+            with ctx.plan(p.robot, p.targets, p.cand, opts=o) as plan:
+                plan.dp_search()
+                plan.lm_refine(1)                              # warm-up
+            with ctx.plan(p.robot, p.targets, p.cand, opts=o) as plan:
+                ctx.profile(True)
+                t0 = time.perf_counter()
+                _, best, mj = plan.dp_search()
+                rev, pri = plan.seed_steps()
+                _, rep = plan.lm_refine(iters, want_xi=False)
+                t1 = time.perf_counter()
+                st = {k: ctx.kernel_stats(k)[0] for k in ("dp", "lm")}
+                ctx.profile(False)
+                research = plan.needs_research()
+            out["arms"][f"{rname}_{arm}"] = {
+                "latency_ms": (t1 - t0) * 1e3, "kernels_ms": st, "search_best": best, "seed_mjac": mj,
+                "seed_step_revolute_rad": rev, "seed_step_prismatic_m": pri, "needs_research": research,
+                "waypoint_lm_iters_per_s": p.T * iters / (st["lm"] * 1e-3),
+                "pose_err_vs_targets": [rep["max_pos_err_m"], rep["max_rot_err_rad"]],
+                "n_valid": rep["n_valid"], "first_valid": rep["first_valid"]}
+    ctx.close()
+    return out
+
+
 def _pct(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if xs else None
 
@@ -363,7 +405,7 @@ if __name__ == "__main__":
     import argparse
     ap = argparse.ArgumentParser()
     ap.add_argument("mode", choices=["batch64", "T1000_K512", "batchopt", "schedule", "research", "collision",
-                                     "serve"])
+                                     "prismatic", "serve"])
     ap.add_argument("--duration", type=float, default=10.0)
     a = ap.parse_args()
     if a.mode == "batch64":
@@ -378,5 +420,7 @@ if __name__ == "__main__":
         print(json.dumps(run_research()))
     elif a.mode == "collision":
         print(json.dumps(run_collision()))
+    elif a.mode == "prismatic":
+        print(json.dumps(run_prismatic()))
     else:
         print(json.dumps(run_serve(duration_s=a.duration)))
