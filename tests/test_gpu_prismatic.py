@@ -210,17 +210,26 @@ def test_lm_with_collision_prismatic_matches_oracle(ctx):
     assert ep <= POS_TOL and er <= ROT_TOL and abs(c - cr) / max(cr, 1e-12) <= COST_TOL
 
 
-def test_prismatic_batch_and_serving_equal_alone(ctx):
-    probs = [_problem(20 + i, 30 + 11 * i, 10 + 6 * i, robot_seed=i + 1) for i in range(3)]
-    opts = cpf.make_opts(iters=10)
-    batch = ctx.solve_batch([(p.robot, p.targets, p.cand) for p in probs], opts)
-    tickets = [ctx.submit(p.robot, p.targets, p.cand, opts) for p in probs]
-    served = [ctx.poll(t, p.T, timeout_ms=60000) for t, p in zip(tickets, probs)]
-    for p, b, s in zip(probs, batch, served):
-        with ctx.plan(p.robot, p.targets, p.cand, opts=opts) as plan:
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_mixed_geometry_batch_and_serving_equal_alone(ctx, schedule):
+    """Prismatic plans beside all-revolute plans and plans with capsules in
+    one batch launch and one serving stream: each kind runs its own kernel
+    instance, and every result equals the plan run alone, bitwise."""
+    items = [(p, None) for p in (_problem(20 + i, 30 + 11 * i, 10 + 6 * i, robot_seed=i + 1) for i in range(3))]
+    items.append((H.small_problem(seed=27, T=25, K=8), None))
+    rb = synth.make_robot(3)
+    cm = synth.collision_model(rb, synth.make_obstacles(3, 4))
+    items.append((H.with_targets(synth.make_problem(rb, seed=28, T=35, K=12, sigma=0.1, branch_frac=0.25)), cm))
+    opts = cpf.make_opts(iters=10, schedule=schedule)
+    batch = ctx.solve_batch([(p.robot, p.targets, p.cand, None, c) for p, c in items], opts)
+    tickets = [ctx.submit(p.robot, p.targets, p.cand, opts, coll=c) for p, c in items]
+    served = [ctx.poll(t, p.T, timeout_ms=60000) for t, (p, _) in zip(tickets, items)]
+    for (p, c), b, s in zip(items, batch, served):
+        with ctx.plan(p.robot, p.targets, p.cand, opts=opts, coll=c) as plan:
             path, best, _ = plan.dp_search()
-            xi, _ = plan.lm_refine(10)
+            xi, rep = plan.lm_refine(10)
         for r in (b, s):
             assert r is not None and r["status"] == 0
             assert np.array_equal(r["path"], path) and r["search_best"] == best
             assert np.array_equal(r["xi"], xi)
+            assert r["report"]["n_valid"] == rep["n_valid"]
