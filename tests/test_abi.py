@@ -46,6 +46,37 @@ def test_opts_default_values():
     assert abs(o.limit_margin - 0.026179938779914945) < 1e-15
 
 
+STRUCTS = ("cpf_robot", "cpf_problem", "cpf_opts", "cpf_lm_report", "cpf_result")
+C_NAME = {"lambda_": "lambda"}   # Python keywords renamed in the binding
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libcpf.so not built")
+def test_binding_structs_match_the_header(tmp_path):
+    """Every ctypes mirror has the size and field offsets the C compiler gives
+    the header's struct (a small C program compiled here prints them)."""
+    import subprocess
+    from paper_2309_09102_amd import cpf
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "cpf.h"', "int main(void) {"]
+    for st in STRUCTS:
+        lines.append(f'  printf("{st} size %zu\\n", sizeof({st}));')
+        for name, _ in getattr(cpf, st)._fields_:
+            lines.append(f'  printf("{st} {name} %zu\\n", offsetof({st}, {C_NAME.get(name, name)}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        st, key, val = line.split()
+        got[(st, key)] = int(val)
+    for st in STRUCTS:
+        cls = getattr(cpf, st)
+        assert got[(st, "size")] == ctypes.sizeof(cls), st
+        for name, _ in cls._fields_:
+            assert got[(st, name)] == getattr(cls, name).offset, (st, name)
+
+
 def test_oracle_and_product_share_no_code():
     """The oracle neither includes nor imports the HIP path, and vice versa."""
     csrc = os.path.join(ROOT, "paper_2309_09102_amd", "csrc")
