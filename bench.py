@@ -58,6 +58,9 @@ def parse():
                          "additional measured workloads in paper_2309_09102_amd/workloads.py")
     ap.add_argument("--duration", type=float, default=10.0, help="serve: stream length (s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-full-chip", action="store_true",
+                    help="skip the leg that runs the same request 256 times in one batch launch "
+                         "(one plan per compute unit)")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the short serving comparison (continuous batching, mixed precision, "
                          "vs all-FP64 one request at a time) that the default line carries")
@@ -225,6 +228,29 @@ def main():
         "report": {"mixed": rep_mixed, "fp64": rep_fp64},
         "roofline": roofline,
     }
+
+    if not args.no_full_chip:
+        # The same request 256 times in one batch launch, one plan per
+        # compute unit: what the LM kernel does with the chip full, beside
+        # the single request of `value`, which leaves 255 compute units idle.
+        n_plans = 256
+        opts = cpf.make_opts(iters=iters)
+        items = [(prob.robot, prob.targets, prob.cand)] * n_plans
+        ctx.solve_batch(items[:8], opts)                          # warm-up
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        res = ctx.solve_batch(items, opts)
+        t1 = time.perf_counter()
+        lm_b = ctx.kernel_stats("lm")[0]
+        dp_b = ctx.kernel_stats("dp")[0]
+        ctx.profile(False)
+        ach_b = LM_FLOPS_PER_WAYPOINT_ITER * T * iters * n_plans / (lm_b * 1e-3) / 1e12
+        out["full_chip"] = {
+            "plans": n_plans, "lm_kernel_ms": lm_b, "search_ms": dp_b, "wall_ms": (t1 - t0) * 1e3,
+            "waypoint_lm_iters_per_s": T * iters * n_plans / (lm_b * 1e-3),
+            "lm_achieved_tflops": ach_b, "lm_frac": ach_b / PEAK_ALU_TFLOPS,
+            "results_identical": bool(all(np.array_equal(r["xi"], res[0]["xi"]) for r in res)),
+            "note": "wall_ms includes uploading the 256 requests from host memory"}
 
     if not args.no_serving:
         # The serving half of the metric: the same seeded request stream
