@@ -16,7 +16,9 @@ import numpy as np
 import torch  # noqa: F401  (loads the HIP runtime the library binds to)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libcpf.so")
+# CPF_LIB selects another build of the library (e.g. a diagnostic variant
+# built with paper_2309_09102_amd/build.py -D ...); the default is the in-tree one.
+LIB_PATH = os.environ.get("CPF_LIB") or os.path.join(_HERE, "libcpf.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() "
                       "(or python paper_2309_09102_amd/build.py) first")
