@@ -43,3 +43,27 @@ def test_targets_rounded():
     p = synth.config1()
     p2 = p.with_targets(np.full((p.T, 12), 0.1))
     assert np.all(p2.targets == np.float32(0.1))
+
+
+def test_prismatic_robot_and_its_inputs():
+    """The prismatic robot is the revolute robot of the same seed with one
+    joint marked prismatic over [0, 0.4] m; its path, candidates and random
+    configurations stay inside that travel and are float32-exact, and the
+    revolute joints' inputs are unchanged by the mapping."""
+    import math
+    rb0 = synth.make_robot(3)
+    rb = synth.make_robot_prismatic(3)
+    assert list(rb.joint_type) == [1, 0, 0, 0, 0, 0, 0] and rb0.joint_type is None
+    assert np.array_equal(rb.a, rb0.a) and np.array_equal(rb.d, rb0.d)
+    assert rb.q_lo[0] == 0.0 and rb.q_hi[0] == np.float32(0.4)
+    p = synth.make_problem(rb, seed=5, T=40, K=16, sigma=0.3, branch_frac=0.25)
+    p0 = synth.make_problem(rb0, seed=5, T=40, K=16, sigma=0.3, branch_frac=0.25)
+    for x in (p.q_star[:, 0], p.cand[..., 0]):
+        assert x.min() >= 0.0 and x.max() <= rb.q_hi[0]
+    assert np.array_equal(p.cand[..., 1:], p0.cand[..., 1:])
+    assert np.array_equal(p.cand.astype(np.float32).astype(np.float64), p.cand)
+    q = synth.random_configs(2, 500, rb)
+    assert q[:, 0].min() >= 0.0 and q[:, 0].max() <= rb.q_hi[0]
+    assert np.abs(q[:, 1:]).max() <= math.pi
+    extra = synth.more_candidates(p, 8)
+    assert extra[..., 0].min() >= 0.0 and extra[..., 0].max() <= rb.q_hi[0]
