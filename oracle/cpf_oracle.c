@@ -37,7 +37,10 @@
  *   - lambda schedule: Nielsen's gain-ratio rule (H.B. Nielsen, IMM-REP-1999-05;
  *     Madsen, Nielsen & Tingleff 2004, Sec. 3.2);
  *   - penalties enter the search on the edge into the penalised node; ties
- *     are broken by the key (value, edge change, predecessor index).
+ *     are broken by the key (value, edge change, predecessor index);
+ *   - a prismatic joint's value adds to its link's offset d and its Jacobian
+ *     column is [z; 0]; its limit margin is 3 cm and its validity step 2 cm,
+ *     while edge costs and mjac keep the printed formula over all joints.
  */
 #include <math.h>
 #include <stdint.h>
