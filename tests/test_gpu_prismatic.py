@@ -233,3 +233,32 @@ def test_mixed_geometry_batch_and_serving_equal_alone(ctx, schedule):
             assert np.array_equal(r["path"], path) and r["search_best"] == best
             assert np.array_equal(r["xi"], xi)
             assert r["report"]["n_valid"] == rep["n_valid"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_prismatic_full_size_matches_oracle(ctx, prec):
+    """T=300, K=256 (the benchmark's request on the robot with a prismatic
+    first joint): the search bitwise, the seed's steps, 50 LM iterations
+    within the parity tolerances, and the schedule's decisions (FP64)."""
+    rb = synth.make_robot_prismatic(0)
+    p = H.with_targets(synth.make_problem(rb, seed=2, T=300, K=256, sigma=0.1, branch_frac=0.25))
+    path_ref, best_ref, _, _ = oracle.dp(p.cand, rb)
+    seed = H.seed_of(p, path_ref)
+    ref = oracle.lm(rb, seed, p.targets, 50)
+    with ctx.plan(rb, p.targets, p.cand, opts=cpf.make_opts(prec=prec)) as plan:
+        path, best, _ = plan.dp_search()
+        steps = plan.seed_steps()
+        xi, rep = plan.lm_refine(50)
+    assert np.array_equal(path, path_ref) and best == best_ref
+    assert steps == oracle.seed_steps(seed, rb)
+    ep, er, ec = H.parity_metrics(p, xi, ref["xi"])
+    assert ep <= POS_TOL and er <= ROT_TOL and ec <= COST_TOL, (ep, er, ec)
+    if prec == "fp64":
+        sref = oracle.lm_schedule(rb, seed, p.targets, 50)
+        with ctx.plan(rb, p.targets, p.cand, opts=cpf.make_opts(prec=prec, schedule=1)) as plan:
+            plan.dp_search()
+            xs, srep = plan.lm_refine(50)
+        for k in ("n_valid", "first_valid", "pose_steps", "diff_steps"):
+            assert srep[k] == sref[k], (k, srep[k], sref[k])
+        ep, er = oracle.pose_compare(rb, xs, sref["xi"])
+        assert ep <= POS_TOL and er <= ROT_TOL
