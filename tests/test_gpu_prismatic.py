@@ -262,3 +262,24 @@ def test_prismatic_full_size_matches_oracle(ctx, prec):
             assert srep[k] == sref[k], (k, srep[k], sref[k])
         ep, er = oracle.pose_compare(rb, xs, sref["xi"])
         assert ep <= POS_TOL and er <= ROT_TOL
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batchopt_prismatic_matches_oracle(ctx, prec):
+    """BatchOpt on the robot with a prismatic first joint: the same least-mjac
+    candidates (mjac over all joints, each in its own unit), each refined to
+    the oracle's result.  The three least-mjac candidates are compared: each
+    has converged after 50 iterations (checked on the oracle below), while the
+    fourth is still descending a slow valley after hundreds of iterations,
+    where two correct runs part by their rounding."""
+    p = _problem(31, 60, 24)
+    idx, res = ctx.batchopt(p.robot, p.targets, p.cand, 3, opts=cpf.make_opts(iters=50, prec=prec))
+    idx_ref, ref = oracle.batchopt(p.robot, p.cand, p.targets, 3, 50)
+    for k, rr in zip(idx_ref, ref):
+        longer = oracle.plan(p.robot, p.cand[k:k + 1], p.targets, 100)
+        assert oracle.pose_compare(p.robot, rr["xi"], longer["xi"])[0] <= 1e-9
+    assert idx == idx_ref
+    for r, rr in zip(res, ref):
+        assert r["status"] == 0 and np.all(r["path"] == 0)
+        ep, er, ec = H.parity_metrics(p, r["xi"], rr["xi"])
+        assert ep <= POS_TOL and er <= ROT_TOL and ec <= COST_TOL, (ep, er, ec)
