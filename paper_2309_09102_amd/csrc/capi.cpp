@@ -48,6 +48,11 @@ Layout make_layout(int T, int K, bool extra, int n_obs, bool coll) {
         return o;
     };
     const size_t t = (size_t)T, k = (size_t)K;
+    // what a read-back needs lies together at the start: one copy
+    L.st = take(sizeof(LMState));
+    L.report = take(8 * sizeof(double));
+    L.dp_out = take(8 * sizeof(double));
+    L.path = take(t * sizeof(int32_t));
     L.cand = take(t * NJ * k * sizeof(float));
     L.extra = take(extra ? t * k * sizeof(double) : 0);
     L.pen = take(t * k * sizeof(double));
@@ -55,8 +60,6 @@ Layout make_layout(int T, int K, bool extra, int n_obs, bool coll) {
     L.topk = take(t * k * TOPM * sizeof(uint16_t));
     L.topc = take(std::max(t * k * TOPM * sizeof(double), (t * k * NJ + 12 * t) * sizeof(double)));
     L.raw = L.topc;
-    L.path = take(t * sizeof(int32_t));
-    L.dp_out = take(8 * sizeof(double));
     L.targets = take(12 * t * sizeof(double));
     L.xi = take(NJ * t * sizeof(double));
     L.xt = take(NJ * t * sizeof(double));
@@ -65,8 +68,6 @@ Layout make_layout(int T, int K, bool extra, int n_obs, bool coll) {
     L.cr = take(cr_doubles(T) * sizeof(double));
     L.dx = take(NJ * t * sizeof(double));
     L.rb = take(NJ * t * sizeof(double));
-    L.st = take(sizeof(LMState));
-    L.report = take(8 * sizeof(double));
     L.xv = take(NJ * t * sizeof(double));
     L.obs = take((size_t)n_obs * 18 * sizeof(double));
     L.cpen = take(coll ? t * k * sizeof(double) : 0);
@@ -444,26 +445,27 @@ void plan_destroy(cpf_plan *p) {
 cpf_status read_plan(cpf_plan *p, hipStream_t s, const LMState *state_dev, PlanReadback *rb,
                      double *xi_out, int32_t *path_out, double *xv_out) {
     std::vector<double> xs, vs;
-    const void *st_src = state_dev ? (const void *)state_dev : (const void *)(p->arena + p->L.st);
-    HIP_TRY(hipMemcpyAsync(&rb->st, st_src, sizeof(LMState), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(rb->report, p->arena + p->L.report, 8 * sizeof(double),
-                           hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(rb->dp_out, p->arena + p->L.dp_out, 8 * sizeof(double),
-                           hipMemcpyDeviceToHost, s));
+    // the LM state, report, search output and path lead the arena (make_layout)
+    const Layout &L = p->L;
+    const size_t head = L.path + (path_out ? (size_t)p->T * sizeof(int32_t) : 0);
+    std::vector<char> hb(head);
+    HIP_TRY(hipMemcpyAsync(hb.data(), p->arena, head, hipMemcpyDeviceToHost, s));
+    if (state_dev) HIP_TRY(hipMemcpyAsync(&rb->st, state_dev, sizeof(LMState), hipMemcpyDeviceToHost, s));
     if (xi_out) {
         xs.resize((size_t)NJ * p->T);
         HIP_TRY(hipMemcpyAsync(xs.data(), p->arena + p->L.xi, xs.size() * sizeof(double),
                                hipMemcpyDeviceToHost, s));
     }
-    if (path_out)
-        HIP_TRY(hipMemcpyAsync(path_out, p->arena + p->L.path, (size_t)p->T * sizeof(int32_t),
-                               hipMemcpyDeviceToHost, s));
     if (xv_out) {
         vs.resize((size_t)NJ * p->T);
         HIP_TRY(hipMemcpyAsync(vs.data(), p->arena + p->L.xv, vs.size() * sizeof(double),
                                hipMemcpyDeviceToHost, s));
     }
     HIP_TRY(hipStreamSynchronize(s));
+    if (!state_dev) memcpy(&rb->st, hb.data() + L.st, sizeof(LMState));
+    memcpy(rb->report, hb.data() + L.report, sizeof(rb->report));
+    memcpy(rb->dp_out, hb.data() + L.dp_out, sizeof(rb->dp_out));
+    if (path_out) memcpy(path_out, hb.data() + L.path, (size_t)p->T * sizeof(int32_t));
     if (xi_out) soa_to_rows(xs.data(), p->T, xi_out);
     if (xv_out && rb->st.n_valid > 0) soa_to_rows(vs.data(), p->T, xv_out);
     return CPF_OK;
