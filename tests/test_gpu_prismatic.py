@@ -283,3 +283,32 @@ def test_batchopt_prismatic_matches_oracle(ctx, prec):
         assert r["status"] == 0 and np.all(r["path"] == 0)
         ep, er, ec = H.parity_metrics(p, r["xi"], rr["xi"])
         assert ep <= POS_TOL and er <= ROT_TOL and ec <= COST_TOL, (ep, er, ec)
+
+
+def test_coll_batch_prismatic_fp32_distances(ctx):
+    rb = synth.make_robot_prismatic(4)
+    cm = synth.collision_model(rb, synth.make_obstacles(4, 6))
+    q = synth.random_configs(43, 20000, rb)
+    qd = torch.tensor(q.T.copy(), dtype=torch.float32, device="cuda")
+    dist, _ = ctx.coll_batch(rb, cm, qd)
+    torch.cuda.synchronize()
+    dref = oracle.coll_eval(rb, cm, q.astype(np.float32).astype(np.float64))
+    np.testing.assert_allclose(dist.double().cpu().numpy().T, dref, atol=2e-6, rtol=0)
+
+
+@pytest.mark.parametrize("T,K0,Kadd", [(60, 24, 40), (300, 256, 256)])
+def test_append_prismatic_matches_oracle(ctx, T, K0, Kadd):
+    """Re-search with appended candidates on the prismatic robot (the new
+    nodes' limit penalties take the 3 cm margin): equal to the oracle's search
+    over the concatenation, and the seed's steps by joint type."""
+    p = _problem(50 + T, T, K0, sigma=0.4)
+    extra = synth.more_candidates(p, Kadd)
+    allc = np.concatenate([p.cand, extra])
+    path_ref, best_ref, _, _ = oracle.dp(allc, p.robot)
+    with ctx.plan(p.robot, p.targets, p.cand) as plan:
+        plan.dp_search()
+        plan.append(extra)
+        path, best, _ = plan.dp_search()
+        steps = plan.seed_steps()
+    assert np.array_equal(path, path_ref) and best == best_ref
+    assert steps == oracle.seed_steps(allc[path_ref, np.arange(T)], p.robot)
