@@ -14,9 +14,15 @@
  * residuals, clamped to the joint limits (Sec. III-C).
  *
  * Conventions
- *   - n = dof = 7 revolute joints, standard (distal) Denavit-Hartenberg:
- *     A_i = Rz(q_i + theta_off_i) Tz(d_i) Tx(a_i) Rx(alpha_i), no base or
- *     tool transform.  Other dof values return CPF_E_UNSUPPORTED.
+ *   - n = dof = 7 joints, standard (distal) Denavit-Hartenberg:
+ *     A_i = Rz(q_i + theta_off_i) Tz(d_i) Tx(a_i) Rx(alpha_i) for a revolute
+ *     joint, Rz(theta_off_i) Tz(d_i + q_i) Tx(a_i) Rx(alpha_i) for a
+ *     prismatic one (cpf_robot.joint_type), no base or tool transform.
+ *     Other dof values return CPF_E_UNSUPPORTED.
+ *   - Threads: calls on one context may come from several threads (its
+ *     arena pool and profiling records are locked; plan calls queue on the
+ *     context's stream and so run one after another); a plan is used by one
+ *     thread at a time; cpf_submit / cpf_poll may be called from any thread.
  *   - A pose is 12 doubles: x, y, z, then the 3x3 rotation row-major.
  *   - Host arrays are C-contiguous float64 unless stated otherwise.
  *   - Every function is exception-free; a non-OK status leaves outputs
