@@ -90,3 +90,14 @@ def test_oracle_and_product_share_no_code():
         if f.endswith((".c", ".py")):
             text = open(os.path.join(ROOT, "oracle", f)).read()
             assert "paper_2309_09102_amd" not in text and "csrc" not in text, f
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU: with --gpus 2 it exits with a message before
+    touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr and r.stdout == ""
