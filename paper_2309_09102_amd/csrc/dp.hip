@@ -364,6 +364,23 @@ __global__ __launch_bounds__(BS) void dp_kernel(const DevPlan *__restrict__ plan
     // list AHEAD stages on (clamped to a valid node, so every lane loads and
     // no branch separates the loads from their use).
     const int kc = owner ? k : K - 1;
+#ifdef CPF_PHASE_CYCLES
+    // Diagnostic build only: shader-clock totals of the stage loop, thread 0
+    // of plan 0: list evaluation, publication (its barrier), full scans.
+    unsigned long long ph_gather = 0, ph_publish = 0, ph_scan = 0, n_scan = 0, ph_t = clock64();
+#define DP_MARK(acc)                                   \
+    do {                                               \
+        if (tid == 0 && blockIdx.x == 0) {             \
+            const unsigned long long now_ = clock64(); \
+            acc += now_ - ph_t;                        \
+            ph_t = now_;                               \
+        }                                              \
+    } while (0)
+#else
+#define DP_MARK(acc) \
+    do {             \
+    } while (0)
+#endif
     auto stage = [&](int t, StageList &L) {
         const int cur = t & 1, prv = cur ^ 1;
         double b[TOPM];
@@ -389,8 +406,16 @@ __global__ __launch_bounds__(BS) void dp_kernel(const DevPlan *__restrict__ plan
         }
         if (owner && exact) bp[(size_t)t * K + k] = (uint16_t)(bk >= 0 ? bk : 0);
         load_list(P, min(t + AHEAD, T - 1), kc, L);
+        DP_MARK(ph_gather);
         beta = publish(cur, bv);   // its barrier also publishes fmask[cur] and ftag[cur]
-        if (ftag[cur] == t) beta = full_scans(t, cur, prv);
+        DP_MARK(ph_publish);
+        if (ftag[cur] == t) {
+            beta = full_scans(t, cur, prv);
+#ifdef CPF_PHASE_CYCLES
+            ++n_scan;
+#endif
+            DP_MARK(ph_scan);
+        }
     };
 
     // lists of the next AHEAD stages, in flight; buffer a serves the stages
@@ -474,6 +499,12 @@ __global__ __launch_bounds__(BS) void dp_kernel(const DevPlan *__restrict__ plan
         P.st->lambda = P.lam0;   // the LM starts afresh from this seed
         P.st->seeded = 0;
     }
+#ifdef CPF_PHASE_CYCLES
+    if (tid == 0 && blockIdx.x == 0)
+        printf("dp stage cycles T=%d K=%d: lists %llu publish %llu scans %llu (stages with scans %llu)\n", T, K,
+               ph_gather, ph_publish, ph_scan, n_scan);
+#endif
+#undef DP_MARK
 }
 
 hipError_t dp_launch(const DevPlan *d_plans, int nplans, int maxK, int maxT, bool lists_ready, bool coll,
