@@ -304,8 +304,14 @@ __global__ __launch_bounds__(BS) void dp_kernel(const DevPlan *__restrict__ plan
         const double m = wave_min(owner ? b : __builtin_inf());
         if (lane == 0) wmin[buf][wave] = m;
         __syncthreads();
+        // all BS / 64 slots are read at once (in bounds; those past nwave
+        // are not used), in the same order as a loop over the nwave waves
         double r = wmin[buf][0];
-        for (int w = 1; w < nwave; ++w) r = fmin(r, wmin[buf][w]);
+#pragma unroll
+        for (int w = 1; w < BS / 64; ++w) {
+            const double x = wmin[buf][w];
+            r = w < nwave ? fmin(r, x) : r;
+        }
         return r;
     };
 
