@@ -95,10 +95,10 @@ def kernel_sources_sha(files):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or
+def measured_traffic(kernel, summary="hbm_traffic_T300_K256.json"):
+    """HBM bytes per launch of `kernel` from a committed counter summary, or
     None when the kernel's sources changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_T300_K256.json")
+    path = os.path.join(ROOT, "profiles", summary)
     try:
         with open(path) as fh:
             rec = json.load(fh)
@@ -245,10 +245,16 @@ def main():
         dp_b = ctx.kernel_stats("dp")[0]
         ctx.profile(False)
         ach_b = LM_FLOPS_PER_WAYPOINT_ITER * T * iters * n_plans / (lm_b * 1e-3) / 1e12
+        # bytes past the L2 for the 256-plan launch (FETCH_SIZE + WRITE_SIZE,
+        # scaled by a copy of known size), from the committed counter summary
+        tr_b = measured_traffic("lm_kernel<float, false, false, false>", "hbm_traffic_full_chip_T300_K256.json")
+        gbs_b = tr_b / (lm_b * 1e-3) / 1e9 if tr_b else None
         out["full_chip"] = {
             "plans": n_plans, "lm_kernel_ms": lm_b, "search_ms": dp_b, "wall_ms": (t1 - t0) * 1e3,
             "waypoint_lm_iters_per_s": T * iters * n_plans / (lm_b * 1e-3),
             "lm_achieved_tflops": ach_b, "lm_frac": ach_b / PEAK_ALU_TFLOPS,
+            "lm_traffic": tr_b, "lm_traffic_GBps": gbs_b,
+            "lm_traffic_frac": gbs_b / PEAK_HBM_GBS if gbs_b else None,
             "results_identical": bool(all(np.array_equal(r["xi"], res[0]["xi"]) for r in res)),
             "note": "wall_ms includes uploading the 256 requests from host memory"}
 
