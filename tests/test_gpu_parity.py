@@ -274,6 +274,25 @@ def test_solve_batch_equals_single(ctx):
         assert np.array_equal(r["xi"], xi) and r["report"]["cost"] == rep["cost"]
 
 
+def test_solve_batch_more_plans_than_compute_units(ctx):
+    """300 ragged plans in one launch (the chip has 256 compute units, so the
+    last workgroups start only as the first finish): each result, sampled on
+    both sides of the 256th plan, is the one it gets alone."""
+    n = 300
+    probs = [H.small_problem(seed=400 + i, T=12 + (i % 7) * 5, K=6 + (i % 5) * 3, robot_seed=i % 3)
+             for i in range(n)]
+    opts = cpf.make_opts(iters=8)
+    res = ctx.solve_batch([(p.robot, p.targets, p.cand) for p in probs], opts)
+    assert len(res) == n and all(r["status"] == 0 for r in res)
+    for i in sorted(set(range(0, n, 37)) | {255, 256, 257, n - 1}):
+        p, r = probs[i], res[i]
+        with ctx.plan(p.robot, p.targets, p.cand, opts=opts) as plan:
+            path, best, _ = plan.dp_search()
+            xi, rep = plan.lm_refine(8)
+        assert np.array_equal(r["path"], path) and r["search_best"] == best, i
+        assert np.array_equal(r["xi"], xi) and r["report"]["cost"] == rep["cost"], i
+
+
 def test_serving_results_equal_alone(ctx):
     probs = [H.small_problem(seed=70 + i, T=30 + 11 * i, K=12 + 5 * i) for i in range(6)]
     opts = cpf.make_opts(iters=12)
