@@ -308,3 +308,27 @@ def test_serving_results_equal_alone(ctx):
     with pytest.raises(cpf.CpfError) as ei:
         ctx.poll(tickets[0], probs[0].T, timeout_ms=0)
     assert ei.value.status == cpf.E_NOTFOUND
+
+
+def test_serving_few_slots_admits_as_slots_free():
+    """Continuous batching under slot pressure: a server with 3 slots and 2 LM
+    iterations per tick takes 24 ragged requests; later requests are admitted
+    only as earlier ones finish, and every result is the one it gets alone."""
+    n, iters = 24, 9
+    probs = [H.small_problem(seed=500 + i, T=10 + (i % 6) * 7, K=5 + (i % 4) * 4, robot_seed=i % 2)
+             for i in range(n)]
+    opts = cpf.make_opts(iters=iters)
+    with cpf.Context(0, 1 << 30) as c:
+        c.config(slots=3, iters_per_tick=2)
+        tickets = [c.submit(p.robot, p.targets, p.cand, opts) for p in probs]
+        outs = [c.poll(t, p.T, timeout_ms=60000) for t, p in zip(tickets, probs)]
+        assert all(r is not None and r["status"] == 0 for r in outs)
+        # admission waited for a slot: some request was admitted after another finished
+        first_done = min(r["t_done_ns"] for r in outs)
+        assert sum(r["t_admit_ns"] >= first_done for r in outs) >= n - 3
+        for p, r in zip(probs, outs):
+            with c.plan(p.robot, p.targets, p.cand, opts=opts) as plan:
+                plan.dp_search()
+                xi, rep = plan.lm_refine(iters)
+            assert np.array_equal(r["xi"], xi)
+            assert r["report"]["cost"] == rep["cost"]
