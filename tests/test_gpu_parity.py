@@ -332,3 +332,29 @@ def test_serving_few_slots_admits_as_slots_free():
                 xi, rep = plan.lm_refine(iters)
             assert np.array_equal(r["xi"], xi)
             assert r["report"]["cost"] == rep["cost"]
+
+
+def test_serving_memory_budget_admits_as_arenas_return():
+    """Continuous batching under memory pressure: with a budget of 2.5 plan
+    arenas, 10 equal-size requests run at most two at a time (a third waits
+    for an arena to come back), and every result is the one it gets alone."""
+    n, iters = 10, 6
+    probs = [H.small_problem(seed=600 + i, T=30, K=10, robot_seed=i % 2) for i in range(n)]
+    opts = cpf.make_opts(iters=iters)
+    with cpf.Context(0, 1 << 30) as probe:
+        with probe.plan(probs[0].robot, probs[0].targets, probs[0].cand, opts=opts):
+            arena = probe.bytes_in_use()
+    assert arena > 0
+    with cpf.Context(0, 2 * arena + arena // 2) as c:
+        tickets = [c.submit(p.robot, p.targets, p.cand, opts) for p in probs]
+        outs = [c.poll(t, p.T, timeout_ms=60000) for t, p in zip(tickets, probs)]
+        assert all(r is not None and r["status"] == 0 for r in outs)
+        first_done = min(r["t_done_ns"] for r in outs)
+        assert sum(r["t_admit_ns"] >= first_done for r in outs) >= n - 2
+        assert c.bytes_in_use() <= 2 * arena
+        for p, r in zip(probs, outs):
+            with c.plan(p.robot, p.targets, p.cand, opts=opts) as plan:
+                plan.dp_search()
+                xi, rep = plan.lm_refine(iters)
+            assert np.array_equal(r["xi"], xi)
+            assert r["report"]["cost"] == rep["cost"]
