@@ -39,6 +39,11 @@ MUTANTS = {
     "lm_diag_dropped": ("Dbuf[nn * t + (size_t)i * n + i] += w_s * ct + lambda;",
                         "Dbuf[nn * t + (size_t)i * n + i] += lambda;"),
     "lm_always_accept": ("int acc = Cn < C;", "int acc = 1;"),
+    "lm_damping_floor": ("if (f < 1.0 / 3.0) f = 1.0 / 3.0;\n            lambda *= f;",
+                         "if (f < 0.5) f = 0.5;\n            lambda *= f;"),
+    "lm_damping_square": ("double f = 1.0 - u * u * u;\n            if (f < 1.0 / 3.0) f = 1.0 / 3.0;\n            lambda *= f;",
+                          "double f = 1.0 - u * u;\n            if (f < 1.0 / 3.0) f = 1.0 / 3.0;\n            lambda *= f;"),
+    "lm_nu_not_doubled": ("lambda *= nu;\n            nu *= 2.0;", "lambda *= nu;\n            nu *= 1.0;"),
     "lm_no_clamp": ("if (v > hi[j]) v = hi[j];\n                trial[e] = v;",
                     "trial[e] = v;"),
     "sched_modes_swapped": ("const int m = pose_ok ? 1 : 0;", "const int m = pose_ok ? 0 : 1;"),
@@ -91,6 +96,8 @@ def battery():
         lambda: P.test_p12_dls_push_through_identity(1e-2),
         lambda: P.test_p13_lm_cost_monotone_and_rejects_keep_xi(0),
         lambda: P.test_p13_lm_clamps_to_limits(),
+        lambda: P.test_p13_lm_damping_follows_the_gain_ratio_rule(0, 30, 0.1, 25),
+        lambda: P.test_p13_lm_damping_follows_the_gain_ratio_rule(8, 20, 1.5, 20),
         lambda: P.test_p15_schedule_pose_step_is_lm_without_smoothness(),
         lambda: P.test_p15_schedule_valid_seed_takes_a_differencing_step(),
         lambda: P.test_p15_schedule_latest_valid_meets_the_thresholds(),

@@ -420,6 +420,66 @@ def test_p13_lm_cost_monotone_and_rejects_keep_xi(cfg_seed):
             break
 
 
+def _nielsen_replay(rb, x0, tg, iters, lam0=1e-3, w_p=1.0, w_s=0.1):
+    """LM written out from its definition, one damped step at a time (the
+    step itself from the oracle's single-step routine, the rest here): a
+    trial clip(x + delta) is accepted iff it lowers the cost; Nielsen's gain
+    ratio rule then scales the damping by max(1/3, 1 - (2 rho - 1)^3) and
+    resets nu to 2, where rho is the cost drop over the predicted drop
+    delta^T (lam delta - g) / 2; a rejected trial multiplies the damping by
+    nu and doubles nu; the damping stays in [1e-10, 1e10].  Returns the
+    damping each iteration used, the accept flags and the final iterate."""
+    x = np.clip(np.asarray(x0, dtype=float), rb.q_lo, rb.q_hi)
+    lam, nu = lam0, 2.0
+    lams, accs = [], []
+    for _ in range(iters):
+        d, g = oracle.lm_step(rb, x, tg, w_p, w_s, lam)
+        trial = np.clip(x + d, rb.q_lo, rb.q_hi)
+        c, cn = oracle.cost(rb, x, tg, w_p, w_s), oracle.cost(rb, trial, tg, w_p, w_s)
+        lams.append(lam)
+        accs.append(cn < c)
+        if cn < c:
+            rho = (c - cn) / (0.5 * float(np.sum(d * (lam * d - g))))
+            lam *= max(1.0 / 3.0, 1.0 - (2.0 * rho - 1.0) ** 3)
+            nu = 2.0
+            x = trial
+        else:
+            lam *= nu
+            nu *= 2.0
+        lam = min(max(lam, 1e-10), 1e10)
+    return np.array(lams), np.array(accs), x
+
+
+@pytest.mark.parametrize("seed,T,sigma,iters", [(0, 30, 0.1, 25), (8, 20, 1.5, 20)])
+def test_p13_lm_damping_follows_the_gain_ratio_rule(seed, T, sigma, iters):
+    """The damping history, accept flags and result of a whole LM run equal a
+    step-by-step replay of the Levenberg-Marquardt loop with Nielsen's rule
+    (the reading taken where the paper gives no damping schedule).  The
+    smooth case reaches the 1/3 floor (a gain ratio near 1) and takes the
+    cubic factor between the floor and 1; the rough case (1.5 rad noise)
+    raises the damping after a poor accepted step (rho < 1/2) and rejects
+    three trials in a row, so nu doubles twice."""
+    rb = synth.make_robot(seed)
+    prob = synth.make_problem(rb, seed=seed, T=T, K=1, sigma=sigma)
+    tg = oracle.fk(rb, prob.q_star)
+    out = oracle.lm(rb, prob.cand[0], tg, iters)
+    lams, accs, x = _nielsen_replay(rb, prob.cand[0], tg, iters)
+    np.testing.assert_array_equal(out["accepted"], accs)
+    np.testing.assert_allclose(out["lambda_hist"], lams, rtol=1e-13, atol=0)
+    np.testing.assert_allclose(out["xi"], x, rtol=0, atol=1e-12)
+    run = longest = 0
+    for a in accs:
+        run = 0 if a else run + 1
+        longest = max(longest, run)
+    ratios = lams[1:] / lams[:-1]
+    acc_ratios = ratios[accs[:-1]]
+    if sigma < 1.0:
+        assert np.any(np.isclose(acc_ratios, 1.0 / 3.0))
+        assert np.any((acc_ratios > 0.34) & (acc_ratios < 0.99))
+    else:
+        assert longest >= 3 and np.any(acc_ratios > 1.01)
+
+
 def test_p13_fixed_point_gives_zero_step():
     rb = synth.make_robot(2)
     q = np.random.default_rng(0).uniform(-1, 1, 7)
