@@ -65,11 +65,13 @@ typedef enum cpf_status {
     CPF_E_UNSUPPORTED = -7
 } cpf_status;
 
-/* Arithmetic of FK, Jacobians and residuals.  The linear solve is FP64 in
- * both: CPF_MIXED computes kinematics (FK, Jacobian, residuals, the cost's
- * pose terms) in FP32 and refines the FP64 solve, with the Gram J^T J, the
- * cross-waypoint sums and the validity checks in FP64; CPF_FP64 computes
- * everything in FP64.  (CPF_F32 / CPF_F64 select cpf_fk_batch's precision.) */
+/* Arithmetic of the LM iteration (Sec. III-C).  Residuals, the cost and its
+ * accept test, the gradient J^T r, the Gram J^T J, the block solve and its
+ * FP64 refinement, and the validity checks are FP64 in both; CPF_MIXED
+ * computes the kinematic Jacobian J from an FP32 chain, CPF_FP64 from an
+ * FP64 one.  (The Jacobian only shapes the step; the FP64 residual fixes the
+ * point the iteration converges to.)  CPF_F32 / CPF_F64 select
+ * cpf_fk_batch's precision. */
 enum { CPF_F32 = 0, CPF_F64 = 1 };
 enum { CPF_MIXED = 0, CPF_FP64 = 1 };
 
@@ -101,11 +103,31 @@ typedef struct cpf_robot {
     const int32_t *joint_type;
 } cpf_robot;
 
-/* One problem (host, copied by every call that takes it).
+/* One problem.
  *   targets  [T][12]   target poses Y (Sec. II)
- *   cand     [K][T][dof] candidate plans (Sec. III-A)
+ *   cand     [K][T][dof] candidate plans (Sec. III-A), float64
  *   node_pen [T][K] or NULL: extra per-node search cost added to the
- *            joint-limit penalty (the paper's collision cost, Sec. III-B) */
+ *            joint-limit penalty (the paper's collision cost, Sec. III-B)
+ *   cand_f32 [K][T][dof] float32 candidates, or NULL: used in place of cand
+ *            (which may then be NULL); half the bytes to copy, the same
+ *            search and refinement whenever the candidates are float32
+ *            values (the device keeps candidates as float32 either way)
+ *   mem      where targets and the candidates live:
+ *            CPF_MEM_HOST   host arrays, copied before the call returns;
+ *            CPF_MEM_DEVICE device pointers on the context's device, read
+ *                           in place with no host copy; the candidates must
+ *                           be cand_f32 (cand is ignored).  cpf_plan_init,
+ *                           cpf_solve_batch and cpf_batchopt read them
+ *                           before they return; cpf_submit reads them when
+ *                           the server admits the request, so the caller
+ *                           keeps them allocated and unchanged until
+ *                           cpf_poll has returned the result.  The host
+ *                           cannot check device values: a non-finite one is
+ *                           read as 0 and the call (cpf_plan_init), the
+ *                           plan's result (cpf_solve_batch, cpf_batchopt) or
+ *                           the request (cpf_submit) ends with CPF_E_ARG.
+ *            node_pen and obstacles are host arrays in both cases. */
+enum { CPF_MEM_HOST = 0, CPF_MEM_DEVICE = 1 };
 typedef struct cpf_problem {
     int32_t T, K;
     const double *targets;
@@ -116,6 +138,8 @@ typedef struct cpf_problem {
      * p_max xyz in that frame (Sec. III-C); n_obstacles <= 64 */
     int32_t n_obstacles;
     const double *obstacles;
+    const float *cand_f32;
+    int32_t mem;
 } cpf_problem;
 
 /* Options (cpf_opts_default fills the defaults shown).
@@ -261,6 +285,15 @@ cpf_status cpf_dp_search(cpf_plan *plan, int32_t *path_out, double *best_out,
  * cpf_dp_seed_steps' pri_m_out. */
 #define CPF_RESEARCH_MJAC_M 0.03
 
+/* The paper's test for more candidate plans after a search (Sec. III-B):
+ * *out = 1 when the seed of the plan's last search changes a revolute joint
+ * by more than CPF_RESEARCH_MJAC_RAD or a prismatic joint by more than
+ * CPF_RESEARCH_MJAC_M between consecutive waypoints, else 0.  The caller
+ * then appends candidates (cpf_plan_append) and searches again.  Reads
+ * values kept on the host by the search: no device work.  CPF_E_STATE before
+ * the first search. */
+cpf_status cpf_dp_needs_research(const cpf_plan *plan, int32_t *out);
+
 /* Largest change of a revolute joint (rad) and of a prismatic joint (m)
  * between consecutive waypoints of the seed found by the plan's last search
  * (cpf_dp_search or cpf_plan_solve); 0 for a joint type the robot lacks.
@@ -291,9 +324,11 @@ cpf_status cpf_plan_append(cpf_plan *plan, int32_t K_add, const double *cand_add
  * Sec. III-C.  Synchronous. */
 cpf_status cpf_lm_refine(cpf_plan *plan, int32_t iters, double *xi_out, cpf_lm_report *rep);
 
-/* The whole refinement of one plan (Sec. III-B then III-C): the search, then
- * opts.iters LM iterations from its seed (restarting the LM state) and the
- * report, queued in one stream with a single synchronisation at the end.
+/* The whole refinement of one plan (Sec. III-B then III-C): the complete
+ * search (node penalties and predecessor lists rebuilt from the candidates,
+ * then the stage recursion and back-tracking), then opts.iters LM iterations
+ * from its seed (restarting the LM state) and the report, queued in one
+ * stream with a single synchronisation at the end.
  * path_out [T], best_out, xi_out [T][dof], rep: each may be NULL.
  * Synchronous; CPF_E_NUMERIC as cpf_lm_refine. */
 cpf_status cpf_plan_solve(cpf_plan *plan, int32_t *path_out, double *best_out, double *xi_out,
@@ -330,11 +365,13 @@ cpf_status cpf_batchopt(cpf_ctx *ctx, const cpf_robot *robot, const cpf_problem 
  * CPF_E_STATE once the server runs. */
 cpf_status cpf_ctx_config(cpf_ctx *ctx, int32_t slots, int32_t iters_per_tick);
 
-/* Serving: copy the request, queue it, return a ticket at once.  The server
+/* Serving: copy the request (host inputs; device inputs stay where they
+ * are, see cpf_problem.mem), queue it, return a ticket at once.  The server
  * thread admits queued requests while their device bytes fit the budget,
  * runs their searches, and advances every admitted request by LM iterations
- * in shared launches until it reaches opts->iters.  A request larger than
- * the whole budget gives CPF_E_NOMEM. */
+ * in shared launches until it reaches opts->iters, which must be >= 1
+ * (CPF_E_ARG otherwise).  A request larger than the whole budget gives
+ * CPF_E_NOMEM. */
 cpf_status cpf_submit(cpf_ctx *ctx, const cpf_robot *robot, const cpf_problem *prob,
                       const cpf_opts *opts, uint64_t *ticket);
 

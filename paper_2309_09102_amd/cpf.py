@@ -28,6 +28,7 @@ OK, PENDING = 0, 1
 E_ARG, E_NOMEM, E_DEVICE, E_STATE, E_NOTFOUND, E_NUMERIC, E_UNSUPPORTED = -1, -2, -3, -4, -5, -6, -7
 F32, F64 = 0, 1
 MIXED, FP64 = 0, 1
+MEM_HOST, MEM_DEVICE = 0, 1
 RESEARCH_MJAC_RAD = 0.20943951023931953   # CPF_RESEARCH_MJAC_RAD: 12 degrees
 RESEARCH_MJAC_M = 0.03                    # CPF_RESEARCH_MJAC_M: 3 cm (prismatic joints)
 _NAMES = {0: "OK", 1: "PENDING", -1: "E_ARG", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_STATE",
@@ -51,7 +52,8 @@ class cpf_robot(C.Structure):
 
 class cpf_problem(C.Structure):
     _fields_ = [("T", C.c_int32), ("K", C.c_int32), ("targets", _dp), ("cand", _dp),
-                ("node_pen", _dp), ("n_obstacles", C.c_int32), ("obstacles", _dp)]
+                ("node_pen", _dp), ("n_obstacles", C.c_int32), ("obstacles", _dp),
+                ("cand_f32", C.POINTER(C.c_float)), ("mem", C.c_int32)]
 
 
 class cpf_opts(C.Structure):
@@ -95,6 +97,7 @@ _lib.cpf_plan_free.argtypes = [_vp]
 _lib.cpf_fk_batch.argtypes = [_vp, C.POINTER(cpf_robot), C.c_int64, C.c_int32, _vp, _vp, _vp, _vp]
 _lib.cpf_dp_search.argtypes = [_vp, _ip, _dp, _dp]
 _lib.cpf_dp_seed_steps.argtypes = [_vp, _dp, _dp]
+_lib.cpf_dp_needs_research.argtypes = [_vp, _ip]
 _lib.cpf_lm_refine.argtypes = [_vp, C.c_int32, _dp, C.POINTER(cpf_lm_report)]
 _lib.cpf_lm_latest_valid.argtypes = [_vp, _dp]
 _lib.cpf_plan_solve.argtypes = [_vp, _ip, _dp, _dp, C.POINTER(cpf_lm_report)]
@@ -112,7 +115,8 @@ _lib.cpf_ctx_config.argtypes = [_vp, C.c_int32, C.c_int32]
 _lib.cpf_ctx_profile.argtypes = [_vp, C.c_int32]
 _lib.cpf_ctx_kernel_stats.argtypes = [_vp, C.c_char_p, C.POINTER(C.c_double),
                                       C.POINTER(C.c_int64)]
-for _f in ("cpf_ctx_create", "cpf_plan_init", "cpf_fk_batch", "cpf_dp_search", "cpf_dp_seed_steps", "cpf_lm_refine",
+for _f in ("cpf_ctx_create", "cpf_plan_init", "cpf_fk_batch", "cpf_dp_search", "cpf_dp_seed_steps",
+           "cpf_dp_needs_research", "cpf_lm_refine",
            "cpf_lm_latest_valid", "cpf_plan_append", "cpf_coll_batch", "cpf_plan_solve",
            "cpf_solve_batch", "cpf_batchopt", "cpf_submit", "cpf_poll", "cpf_ctx_profile",
            "cpf_ctx_kernel_stats", "cpf_ctx_config"):
@@ -120,7 +124,7 @@ for _f in ("cpf_ctx_create", "cpf_plan_init", "cpf_fk_batch", "cpf_dp_search", "
 
 EXPORTS = ("cpf_opts_default", "cpf_last_error", "cpf_ctx_create", "cpf_ctx_destroy",
            "cpf_ctx_bytes_in_use", "cpf_plan_init", "cpf_plan_free", "cpf_fk_batch", "cpf_coll_batch",
-           "cpf_dp_search", "cpf_dp_seed_steps", "cpf_plan_append", "cpf_lm_refine", "cpf_plan_solve", "cpf_lm_latest_valid",
+           "cpf_dp_search", "cpf_dp_seed_steps", "cpf_dp_needs_research", "cpf_plan_append", "cpf_lm_refine", "cpf_plan_solve", "cpf_lm_latest_valid",
            "cpf_solve_batch", "cpf_batchopt", "cpf_submit", "cpf_poll", "cpf_ctx_profile",
            "cpf_ctx_kernel_stats", "cpf_ctx_config")
 
@@ -172,13 +176,38 @@ def _obstacles(coll):
     return ob if ob.shape[0] else None
 
 
+def _is_device_tensor(x) -> bool:
+    return isinstance(x, torch.Tensor) and x.is_cuda
+
+
 def make_problem(targets, cand, node_pen=None, coll=None) -> _Keep:
-    tg = _f64(targets)
-    cd = _f64(cand)
-    K, T = int(cd.shape[0]), int(cd.shape[1])
+    """cand: float64 [K][T][7] (host), float32 [K][T][7] (host, passed as
+    cand_f32), or a contiguous float32 device tensor [K][T][7] with targets a
+    contiguous float64 device tensor [T][12] (device-resident inputs, read in
+    place: keep both alive and unchanged until the call or request is done)."""
     npen = None if node_pen is None else _f64(node_pen)
     ob = _obstacles(coll)
-    s = cpf_problem(T, K, _ptr(tg), _ptr(cd), _ptr(npen), 0 if ob is None else int(ob.shape[0]), _ptr(ob))
+    n_ob = 0 if ob is None else int(ob.shape[0])
+    if _is_device_tensor(cand):
+        if not (cand.dtype == torch.float32 and cand.dim() == 3 and cand.shape[2] == 7 and cand.is_contiguous()):
+            raise ValueError("device candidates must be a contiguous float32 tensor [K][T][7]")
+        if not (_is_device_tensor(targets) and targets.dtype == torch.float64 and targets.is_contiguous()
+                and tuple(targets.shape) == (cand.shape[1], 12)):
+            raise ValueError("device targets must be a contiguous float64 tensor [T][12]")
+        K, T = int(cand.shape[0]), int(cand.shape[1])
+        s = cpf_problem(T, K, C.cast(C.c_void_p(targets.data_ptr()), _dp), None, _ptr(npen), n_ob, _ptr(ob),
+                        C.cast(C.c_void_p(cand.data_ptr()), C.POINTER(C.c_float)), MEM_DEVICE)
+        return _Keep(s, [targets, cand, npen, ob])
+    tg = _f64(targets)
+    if isinstance(cand, np.ndarray) and cand.dtype == np.float32:
+        cf = np.ascontiguousarray(cand)
+        K, T = int(cf.shape[0]), int(cf.shape[1])
+        s = cpf_problem(T, K, _ptr(tg), None, _ptr(npen), n_ob, _ptr(ob),
+                        cf.ctypes.data_as(C.POINTER(C.c_float)), MEM_HOST)
+        return _Keep(s, [tg, cf, npen, ob])
+    cd = _f64(cand)
+    K, T = int(cd.shape[0]), int(cd.shape[1])
+    s = cpf_problem(T, K, _ptr(tg), _ptr(cd), _ptr(npen), n_ob, _ptr(ob), None, MEM_HOST)
     return _Keep(s, [tg, cd, npen, ob])
 
 
@@ -289,6 +318,14 @@ def dp_search(plan, T: int):
     mj = C.c_double()
     _check(_lib.cpf_dp_search(plan, path.ctypes.data_as(_ip), C.byref(best), C.byref(mj)))
     return path, best.value, mj.value
+
+
+def dp_needs_research(plan) -> bool:
+    """The paper's test for more candidate plans after a search (Sec. III-B),
+    decided by the library (cpf_dp_needs_research)."""
+    v = C.c_int32()
+    _check(_lib.cpf_dp_needs_research(plan, C.byref(v)))
+    return bool(v.value)
 
 
 def dp_seed_steps(plan):
@@ -454,7 +491,7 @@ class Context:
 
     def plan(self, robot, targets, cand, node_pen=None, opts=None, coll=None) -> "Plan":
         return Plan(self, plan_init(self.h, robot, targets, cand, node_pen, opts, coll),
-                    int(np.shape(cand)[1]))
+                    int(cand.shape[1]))
 
     def coll_batch(self, robot, coll, q: "torch.Tensor", want_grad: bool = False, stream=None):
         """q: device tensor [7][M] -> (dist [2][M], grad [14][M] | None): the
@@ -516,8 +553,7 @@ class Plan:
     def needs_research(self) -> bool:
         """The paper's test for more candidate plans (Sec. III-B): a seed step
         above 12 degrees (revolute) or 3 cm (prismatic)."""
-        r, p = dp_seed_steps(self.h)
-        return r > RESEARCH_MJAC_RAD or p > RESEARCH_MJAC_M
+        return dp_needs_research(self.h)
 
     def lm_refine(self, iters: int, want_xi: bool = True):
         return lm_refine(self.h, iters, self.T, want_xi)

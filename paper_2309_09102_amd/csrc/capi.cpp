@@ -39,6 +39,13 @@ int64_t now_ns() {
         .count();
 }
 
+// Bytes of the upload region: the caller's candidates ([K][T][7], doubles or
+// floats), then its targets ([T][12] doubles) from the next 256-byte boundary.
+size_t raw_targets_offset(int T, int K, bool cand_f32) {
+    return align256((size_t)T * K * NJ * (cand_f32 ? sizeof(float) : sizeof(double)));
+}
+size_t raw_bytes(int T, int K, bool cand_f32) { return raw_targets_offset(T, K, cand_f32) + (size_t)12 * T * sizeof(double); }
+
 Layout make_layout(int T, int K, bool extra, int n_obs, bool coll) {
     Layout L{};
     size_t off = 0;
@@ -58,7 +65,7 @@ Layout make_layout(int T, int K, bool extra, int n_obs, bool coll) {
     L.pen = take(t * k * sizeof(double));
     L.bp = take(t * k * sizeof(uint16_t));
     L.topk = take(t * k * TOPM * sizeof(uint16_t));
-    L.topc = take(std::max(t * k * TOPM * sizeof(double), (t * k * NJ + 12 * t) * sizeof(double)));
+    L.topc = take(std::max(t * k * TOPM * sizeof(double), raw_bytes(T, K, false)));
     L.raw = L.topc;
     L.targets = take(12 * t * sizeof(double));
     L.xi = take(NJ * t * sizeof(double));
@@ -71,6 +78,8 @@ Layout make_layout(int T, int K, bool extra, int n_obs, bool coll) {
     L.xv = take(NJ * t * sizeof(double));
     L.obs = take((size_t)n_obs * 18 * sizeof(double));
     L.cpen = take(coll ? t * k * sizeof(double) : 0);
+    L.rr = take(RROWS * t * sizeof(double));
+    L.rt = take(RROWS * t * sizeof(double));
     L.total = off;
     return L;
 }
@@ -267,9 +276,20 @@ cpf_status check_problem(const cpf_problem *p) {
     if (p->T < 1 || p->K < 1) return fail(CPF_E_ARG, "T=%d K=%d must be >= 1", p->T, p->K);
     if (p->K > MAX_K) return fail(CPF_E_UNSUPPORTED, "K=%d exceeds %d", p->K, MAX_K);
     if (p->T > (1 << 24)) return fail(CPF_E_UNSUPPORTED, "T=%d too large", p->T);
-    if (!p->targets || !p->cand) return fail(CPF_E_ARG, "targets / cand is NULL");
-    if (!all_finite(p->targets, (size_t)p->T * 12)) return fail(CPF_E_ARG, "targets not finite");
-    if (!all_finite(p->cand, (size_t)p->K * p->T * NJ)) return fail(CPF_E_ARG, "cand not finite");
+    if (p->mem != CPF_MEM_HOST && p->mem != CPF_MEM_DEVICE) return fail(CPF_E_ARG, "mem %d", p->mem);
+    if (p->mem == CPF_MEM_DEVICE) {   // device values are checked on the device (stage_kernel)
+        if (!p->targets || !p->cand_f32) return fail(CPF_E_ARG, "device inputs need targets and cand_f32");
+    } else {
+        if (!p->targets || (!p->cand && !p->cand_f32)) return fail(CPF_E_ARG, "targets / cand is NULL");
+        if (!all_finite(p->targets, (size_t)p->T * 12)) return fail(CPF_E_ARG, "targets not finite");
+        const size_t n = (size_t)p->K * p->T * NJ;
+        if (p->cand_f32) {
+            for (size_t i = 0; i < n; ++i)
+                if (!std::isfinite(p->cand_f32[i])) return fail(CPF_E_ARG, "cand_f32 not finite");
+        } else if (!all_finite(p->cand, n)) {
+            return fail(CPF_E_ARG, "cand not finite");
+        }
+    }
     if (p->node_pen) {
         for (size_t i = 0; i < (size_t)p->T * p->K; ++i)
             if (!(std::fabs(p->node_pen[i]) <= 1e30))
@@ -367,6 +387,8 @@ static void fill_desc(cpf_plan *p, bool has_extra) {
     set_dev_ptr(D.xv, b + L.xv);
     set_dev_ptr(D.obs, b + L.obs);
     set_dev_ptr(D.cpen, b + L.cpen);
+    set_dev_ptr(D.rr, b + L.rr);
+    set_dev_ptr(D.rt, b + L.rt);
 }
 
 // A plan of T waypoints and K candidates with an arena from the pool, its
@@ -394,6 +416,7 @@ cpf_status plan_alloc(cpf_ctx *ctx, const HostRobot &hr, int T, int K, bool has_
     p->init.iters_target = iters_target;
     hipError_t e = hipMemcpyAsync(p->arena + p->L.st, &p->init, sizeof(LMState), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(p->d_desc, &p->desc, sizeof(DevPlan), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(input_flag(p.get()), 0, sizeof(int), s);
     if (e != hipSuccess) {
         HIP_IGNORE(hipStreamSynchronize(s));
         arena_put(ctx, mem, cls);
@@ -410,17 +433,33 @@ cpf_status plan_create(cpf_ctx *ctx, const HostRobot &hr, const cpf_problem *pro
     cpf_status st = plan_alloc(ctx, hr, prob->T, prob->K, has_extra, prob->n_obstacles, opts, iters_target, s, &p);
     if (st != CPF_OK) return st;
 
-    // The caller's arrays go up as they are; a kernel converts them into the
-    // device layout (candidates to float, joint-major; targets component-major).
+    // Host arrays go up as they are into the upload region; a kernel converts
+    // them (or device-resident ones in place) into the device layout
+    // (candidates to float, joint-major; targets component-major).
     const int T = p->T, K = p->K;
     const size_t n_cand = (size_t)T * K * NJ;
-    double *raw = (double *)(p->arena + p->L.raw);
-    hipError_t e = hipMemcpyAsync(raw, prob->cand, n_cand * sizeof(double), hipMemcpyHostToDevice, s);
+    const bool f32 = prob->mem == CPF_MEM_DEVICE || prob->cand_f32 != nullptr;
+    const void *cin = nullptr;
+    const double *tin = nullptr;
+    int *bad = nullptr;
+    hipError_t e = hipSuccess;
+    if (prob->mem == CPF_MEM_DEVICE) {   // checked on the device (the flag was cleared by plan_alloc)
+        cin = prob->cand_f32;
+        tin = prob->targets;
+        bad = input_flag(p);
+    } else {
+        char *raw = p->arena + p->L.raw;
+        const size_t toff = raw_targets_offset(T, K, f32);
+        e = hipMemcpyAsync(raw, f32 ? (const void *)prob->cand_f32 : (const void *)prob->cand,
+                           n_cand * (f32 ? sizeof(float) : sizeof(double)), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(raw + toff, prob->targets, (size_t)12 * T * sizeof(double), hipMemcpyHostToDevice, s);
+        cin = raw;
+        tin = (const double *)(raw + toff);
+    }
     if (e == hipSuccess)
-        e = hipMemcpyAsync(raw + n_cand, prob->targets, (size_t)12 * T * sizeof(double),
-                           hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = stage_launch(raw, T, K, (float *)(p->arena + p->L.cand), (double *)(p->arena + p->L.targets), s);
+        e = stage_launch(cin, f32, tin, T, K, (float *)(p->arena + p->L.cand), (double *)(p->arena + p->L.targets),
+                         bad, s);
     if (e == hipSuccess && has_extra)
         e = hipMemcpyAsync(p->arena + p->L.extra, prob->node_pen, (size_t)T * K * sizeof(double),
                            hipMemcpyHostToDevice, s);
@@ -434,6 +473,14 @@ cpf_status plan_create(cpf_ctx *ctx, const HostRobot &hr, const cpf_problem *pro
     }
     *out = p;
     return CPF_OK;
+}
+
+int *input_flag(cpf_plan *p) { return (int *)(p->arena + p->L.report + 7 * sizeof(double)); }
+
+bool input_flag_set(const double *report) {
+    int v;
+    memcpy(&v, &report[7], sizeof(int));
+    return v != 0;
 }
 
 void plan_destroy(cpf_plan *p) {
@@ -576,10 +623,18 @@ cpf_status cpf_plan_init(cpf_ctx *ctx, const cpf_robot *robot, const cpf_problem
     HIP_TRY(hipSetDevice(ctx->device));
     cpf_plan *p = nullptr;
     if ((st = plan_create(ctx, hr, prob, &o, 0, ctx->stream, &p)) != CPF_OK) return st;
-    hipError_t e = hipStreamSynchronize(ctx->stream);
+    int bad = 0;
+    hipError_t e = hipSuccess;
+    if (prob->mem == CPF_MEM_DEVICE)
+        e = hipMemcpyAsync(&bad, input_flag(p), sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
         plan_destroy(p);
         return fail(CPF_E_DEVICE, "plan upload: %s", hipGetErrorString(e));
+    }
+    if (bad) {
+        plan_destroy(p);
+        return fail(CPF_E_ARG, "a device-resident target or candidate value is not finite");
     }
     *out = p;
     return CPF_OK;
@@ -652,6 +707,13 @@ cpf_status cpf_dp_search(cpf_plan *plan, int32_t *path_out, double *best_out, do
     plan->seed_steps[1] = rb.dp_out[4];
     if (best_out) *best_out = rb.dp_out[0];
     if (mjac_out) *mjac_out = rb.dp_out[1];
+    return CPF_OK;
+}
+
+cpf_status cpf_dp_needs_research(const cpf_plan *plan, int32_t *out) {
+    if (!plan || !out) return fail(CPF_E_ARG, "plan / out is NULL");
+    if (!plan->searched) return fail(CPF_E_STATE, "the plan has not been searched");
+    *out = (plan->seed_steps[0] > CPF_RESEARCH_MJAC_RAD || plan->seed_steps[1] > CPF_RESEARCH_MJAC_M) ? 1 : 0;
     return CPF_OK;
 }
 
@@ -776,7 +838,7 @@ cpf_status cpf_plan_solve(cpf_plan *plan, int32_t *path_out, double *best_out, d
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
     const bool coll = plan->robot.has_caps;
-    HIP_TRY(timed(ctx, KIND_DP, s, [&] { return dp_launch(plan->d_desc, 1, plan->K, plan->T, plan->lists_valid, coll, s); }));
+    HIP_TRY(timed(ctx, KIND_DP, s, [&] { return dp_launch(plan->d_desc, 1, plan->K, plan->T, false, coll, s); }));
     plan->lists_valid = true;
     HIP_TRY(timed(ctx, KIND_LM, s, [&] {
         return lm_launch(plan->d_desc, 1, plan->opts.prec, plan->opts.schedule, plan_geo(plan->robot), plan->opts.iters,
@@ -889,7 +951,7 @@ cpf_status cpf_solve_batch(cpf_ctx *ctx, int32_t nplans, const cpf_robot *robots
         fill_report(rb, &results[i].report);
         results[i].search_best = rb.dp_out[0];
         results[i].search_mjac = rb.dp_out[1];
-        results[i].status = rb.st.status != 0 ? CPF_E_NUMERIC : CPF_OK;
+        results[i].status = input_flag_set(rb.report) ? CPF_E_ARG : (rb.st.status != 0 ? CPF_E_NUMERIC : CPF_OK);
         results[i].t_submit_ns = t0;
         results[i].t_admit_ns = t0;
         results[i].t_search_done_ns = t1;
@@ -939,8 +1001,10 @@ cpf_status cpf_batchopt(cpf_ctx *ctx, const cpf_robot *robot, const cpf_problem 
     for (int i = 0; i < M; ++i) {
         const int k = order[i];
         idx_out[i] = k;
-        probs[i] = cpf_problem{T, 1, prob->targets, prob->cand + (size_t)k * T * NJ, nullptr, prob->n_obstacles,
-                               prob->obstacles};
+        const size_t off = (size_t)k * T * NJ;
+        probs[i] = cpf_problem{T, 1, prob->targets, prob->cand ? prob->cand + off : nullptr, nullptr,
+                               prob->n_obstacles, prob->obstacles,
+                               prob->cand_f32 ? prob->cand_f32 + off : nullptr, prob->mem};
         if (prob->node_pen) {
             pens[i].resize(T);
             for (int t = 0; t < T; ++t) pens[i][t] = prob->node_pen[(size_t)t * K + k];

@@ -16,9 +16,11 @@
 //   g        double [7][T]      gradient of the cost
 //   cr       double             cyclic-reduction levels of the LM system (cr_doubles(T))
 //   dx, rb   double [7][T]      step, refinement residual
+//   rr, rt   double [8][T]      FP64 residual rows of xi and of the trial point
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 // Device code reaches the per-plan arrays through pointers stored in the plan
@@ -48,6 +50,7 @@ constexpr int MAX_K = 1024;   // search kernel limit (one lane per destination)
 constexpr int MAX_OBS = 64;   // cuboid obstacles per problem
 constexpr int CPF_STATUS_NUMERIC = -6;
 constexpr int TOPM = 16;      // nearest predecessors kept per search node
+constexpr int RROWS = 8;      // residual rows per waypoint: 6 pose, then self and environment collision
 
 struct LMState {
     double lambda, nu, cost, cost0, grad_inf;
@@ -102,7 +105,61 @@ struct DevPlan {
     float capf[NJ][7];
     CPF_GLOBAL const double *obs;
     CPF_GLOBAL double *cpen;      // [T][K] collision penalty of each search node
+    // FP64 residual rows [RROWS][T] of xi and of the trial point xt (kept by
+    // the mixed arm, whose linearisation takes them instead of recomputing
+    // the residual in FP32)
+    CPF_GLOBAL double *rr, *rt;
 };
+
+// The host fills descriptors and LM states that kernels read, so both
+// compilation passes (host and gfx950) must lay them out alike: each pass
+// checks every field offset against these figures.
+static_assert(offsetof(DevPlan, T) == 0, "DevPlan layout");
+static_assert(offsetof(DevPlan, refine_steps) == 16, "DevPlan layout");
+static_assert(offsetof(DevPlan, w_p) == 32, "DevPlan layout");
+static_assert(offsetof(DevPlan, a) == 88, "DevPlan layout");
+static_assert(offsetof(DevPlan, margin_p) == 144, "DevPlan layout");
+static_assert(offsetof(DevPlan, d) == 152, "DevPlan layout");
+static_assert(offsetof(DevPlan, ca) == 216, "DevPlan layout");
+static_assert(offsetof(DevPlan, sa) == 280, "DevPlan layout");
+static_assert(offsetof(DevPlan, off) == 344, "DevPlan layout");
+static_assert(offsetof(DevPlan, lo) == 408, "DevPlan layout");
+static_assert(offsetof(DevPlan, hi) == 472, "DevPlan layout");
+static_assert(offsetof(DevPlan, af) == 536, "DevPlan layout");
+static_assert(offsetof(DevPlan, df) == 568, "DevPlan layout");
+static_assert(offsetof(DevPlan, caf) == 600, "DevPlan layout");
+static_assert(offsetof(DevPlan, saf) == 632, "DevPlan layout");
+static_assert(offsetof(DevPlan, offf) == 664, "DevPlan layout");
+static_assert(offsetof(DevPlan, cand) == 696, "DevPlan layout");
+static_assert(offsetof(DevPlan, extra) == 704, "DevPlan layout");
+static_assert(offsetof(DevPlan, bp) == 712, "DevPlan layout");
+static_assert(offsetof(DevPlan, pen) == 720, "DevPlan layout");
+static_assert(offsetof(DevPlan, topk) == 728, "DevPlan layout");
+static_assert(offsetof(DevPlan, topc) == 736, "DevPlan layout");
+static_assert(offsetof(DevPlan, path) == 744, "DevPlan layout");
+static_assert(offsetof(DevPlan, dp_out) == 752, "DevPlan layout");
+static_assert(offsetof(DevPlan, targets) == 760, "DevPlan layout");
+static_assert(offsetof(DevPlan, xi) == 768, "DevPlan layout");
+static_assert(offsetof(DevPlan, xt) == 776, "DevPlan layout");
+static_assert(offsetof(DevPlan, A) == 784, "DevPlan layout");
+static_assert(offsetof(DevPlan, g) == 792, "DevPlan layout");
+static_assert(offsetof(DevPlan, cr) == 800, "DevPlan layout");
+static_assert(offsetof(DevPlan, dx) == 808, "DevPlan layout");
+static_assert(offsetof(DevPlan, rb) == 816, "DevPlan layout");
+static_assert(offsetof(DevPlan, st) == 824, "DevPlan layout");
+static_assert(offsetof(DevPlan, report) == 832, "DevPlan layout");
+static_assert(offsetof(DevPlan, vtol) == 840, "DevPlan layout");
+static_assert(offsetof(DevPlan, xv) == 872, "DevPlan layout");
+static_assert(offsetof(DevPlan, has_coll) == 880, "DevPlan layout");
+static_assert(offsetof(DevPlan, coll_margin) == 888, "DevPlan layout");
+static_assert(offsetof(DevPlan, cap) == 912, "DevPlan layout");
+static_assert(offsetof(DevPlan, capf) == 1304, "DevPlan layout");
+static_assert(offsetof(DevPlan, obs) == 1504, "DevPlan layout");
+static_assert(offsetof(DevPlan, cpen) == 1512, "DevPlan layout");
+static_assert(offsetof(DevPlan, rr) == 1520, "DevPlan layout");
+static_assert(offsetof(DevPlan, rt) == 1528, "DevPlan layout");
+static_assert(sizeof(DevPlan) == 1536, "DevPlan layout");
+static_assert(sizeof(LMState) == 128, "LMState layout");
 
 template <typename S>
 struct RobotT {

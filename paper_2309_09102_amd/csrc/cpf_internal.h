@@ -35,10 +35,12 @@ hipError_t fk_batch_launch(const HostRobot &hr, int64_t M, int prec, const void 
 // dist [2][M], optionally gradients [14][M]; obs: device [n_obs][18].
 hipError_t coll_batch_launch(const HostRobot &hr, const HostCaps &caps, int n_obs, const double *obs, int64_t M,
                              int prec, const void *q, void *dist, void *grad, hipStream_t s);
-// Convert the uploaded caller arrays of one plan (candidates [K][T][7] and
-// targets [T][12], doubles) into the device layout (cand float [T][7][K],
-// targets [12][T]).
-hipError_t stage_launch(const double *raw, int T, int K, float *cand, double *targets, hipStream_t s);
+// Convert the caller arrays of one plan (candidates [K][T][7], doubles or
+// floats, and targets [T][12] doubles, device-resident) into the device
+// layout (cand float [T][7][K], targets [12][T]).  bad non-null: inputs the
+// host has not checked; non-finite values are stored as 0 and set *bad.
+hipError_t stage_launch(const void *cand_in, bool cand_f32, const double *tg_in, int T, int K, float *cand,
+                        double *targets, int *bad, hipStream_t s);
 // Appended candidates raw [K_add][T][7] doubles into columns k_off .. of the
 // float [T][7][K] candidate array.
 hipError_t stage_append_launch(const double *raw, int T, int K_add, int K, int k_off, float *cand,

@@ -129,22 +129,42 @@ hipError_t coll_batch_launch(const HostRobot &hr, const HostCaps &caps, int n_ob
 
 // One thread per (waypoint, candidate) pair, candidates fastest, so the
 // float stores of a joint row are contiguous; the last T threads transpose
-// the targets.
-__global__ __launch_bounds__(256) void stage_kernel(const double *__restrict__ raw, int T, int K,
-                                                    float *__restrict__ cand, double *__restrict__ targets) {
+// the targets.  Candidates arrive as [K][T][7] doubles or floats.  With bad
+// non-null (inputs the host could not check), a value that is not finite
+// (also a double beyond the float range) is stored as 0 and sets *bad.
+template <typename C>
+__global__ __launch_bounds__(256) void stage_kernel(const C *__restrict__ cand_in, const double *__restrict__ tg_in,
+                                                    int T, int K, float *__restrict__ cand,
+                                                    double *__restrict__ targets, int *__restrict__ bad) {
     const long long n = (long long)T * K;
     const long long x = (long long)blockIdx.x * 256 + threadIdx.x;
+    bool ok = true;
     if (x < n) {
         const int t = (int)(x / K), k = (int)(x % K);
-        const double *q = raw + ((size_t)k * T + t) * NJ;
+        const C *q = cand_in + ((size_t)k * T + t) * NJ;
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) cand[((size_t)t * NJ + j) * K + k] = (float)q[j];
+        for (int j = 0; j < NJ; ++j) {
+            float v = (float)q[j];
+            if (bad && !isfinite(v)) {
+                v = 0.0f;
+                ok = false;
+            }
+            cand[((size_t)t * NJ + j) * K + k] = v;
+        }
     } else if (x < n + T) {
         const int t = (int)(x - n);
-        const double *tg = raw + (size_t)n * NJ + (size_t)t * 12;
+        const double *tg = tg_in + (size_t)t * 12;
 #pragma unroll
-        for (int c = 0; c < 12; ++c) targets[(size_t)c * T + t] = tg[c];
+        for (int c = 0; c < 12; ++c) {
+            double v = tg[c];
+            if (bad && !isfinite(v)) {
+                v = 0.0;
+                ok = false;
+            }
+            targets[(size_t)c * T + t] = v;
+        }
     }
+    if (!ok) atomicOr(bad, 1);
 }
 
 // Appended candidates: raw [K_add][T][7] doubles into columns
@@ -169,11 +189,16 @@ hipError_t stage_append_launch(const double *raw, int T, int K_add, int K, int k
     return hipGetLastError();
 }
 
-hipError_t stage_launch(const double *raw, int T, int K, float *cand, double *targets, hipStream_t s) {
+hipError_t stage_launch(const void *cand_in, bool cand_f32, const double *tg_in, int T, int K, float *cand,
+                        double *targets, int *bad, hipStream_t s) {
     const long long n = (long long)T * K + T;
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(stage_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, raw, T, K, cand,
-                       targets);
+    const dim3 g((unsigned)((n + 255) / 256)), b(256);
+    if (cand_f32)
+        hipLaunchKernelGGL(stage_kernel<float>, g, b, 0, s, (const float *)cand_in, tg_in, T, K, cand, targets, bad);
+    else
+        hipLaunchKernelGGL(stage_kernel<double>, g, b, 0, s, (const double *)cand_in, tg_in, T, K, cand, targets,
+                           bad);
     return hipGetLastError();
 }
 

@@ -11,9 +11,16 @@
 // the joint limits; lambda follows Nielsen's gain-ratio rule.
 //
 // One workgroup per plan runs all iterations without returning to the host.
-// Kinematics (FK, J, residuals, and the cost's pose terms) run in S = float
-// or double; the Gram J^T J, the assembly, the solve and every
-// cross-waypoint sum are FP64.  The solve is
+// The residuals r_t, the cost and every cross-waypoint sum are FP64 in both
+// arms; the arms differ in the Jacobian: S = float builds J_t from an FP32
+// chain (the mixed arm), S = double from an FP64 one.  The Gram J^T J and the
+// gradient J^T r accumulate in FP64.  This is the split of mixed-precision
+// iterative refinement: the matrix of the linearised system only sets how
+// fast the iteration converges, while the right-hand side (the residual and
+// the gradient formed from it) and the accept test set the point it
+// converges to, so those stay FP64.  The mixed arm keeps the FP64 residual
+// of its current trajectory from the trial evaluation that accepted it, so
+// each iteration still runs one chain per precision.  The solve is
 // block cyclic reduction (a Cholesky factor per eliminated block, one lane
 // per 7x7 block, log2 T levels), then FP64 iterative refinement against the
 // same H reusing the stored factors.
@@ -61,24 +68,24 @@ __device__ __forceinline__ void load_target(const DevPlan &P, int T, int t, S tg
     for (int e = 0; e < 12; ++e) tg[e] = (S)P.targets[(size_t)e * T + t];
 }
 
-// Squared pose residual of trajectory X ([7][T]) at waypoint t.  PR false
-// throughout this file: a chain known to be all revolute (plans with
-// collision capsules).
-template <typename S, bool PR>
-__device__ __forceinline__ double pose_sq(const DevPlan &P, const RobotT<S> &rb, const CPF_GLOBAL double *X,
-                                          int T, int t) {
-    S q[NJ];
+// Pose residual of trajectory X ([7][T]) at waypoint t in FP64 (written to
+// r) and its squared norm.  PR false throughout this file: a chain known to
+// be all revolute (plans with collision capsules).
+template <bool PR>
+__device__ __forceinline__ double pose_res64(const DevPlan &P, const RobotT<double> &rb, const CPF_GLOBAL double *X,
+                                             int T, int t, double r[6]) {
+    double q[NJ];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) q[j] = (S)X[(size_t)j * T + t];
-    S Xc[3], Yc[3], Zc[3], p[3], Zs[NJ][3], Os[NJ][3];
-    chain<S, false, PR>(rb, q, Xc, Yc, Zc, p, Zs, Os);
-    S tg[12], r[6];
-    load_target<S>(P, T, t, tg);
-    pose_residual<S>(Xc, Yc, Zc, p, tg, r);
-    S s = r[0] * r[0];
+    for (int j = 0; j < NJ; ++j) q[j] = X[(size_t)j * T + t];
+    double Xc[3], Yc[3], Zc[3], p[3], Zs[NJ][3], Os[NJ][3];
+    chain<double, false, PR>(rb, q, Xc, Yc, Zc, p, Zs, Os);
+    double tg[12];
+    load_target<double>(P, T, t, tg);
+    pose_residual<double>(Xc, Yc, Zc, p, tg, r);
+    double s = r[0] * r[0];
 #pragma unroll
     for (int i = 1; i < 6; ++i) s += r[i] * r[i];
-    return (double)s;
+    return s;
 }
 
 // The plan's capsules in the kinematics precision.
@@ -107,14 +114,21 @@ __device__ __forceinline__ void coll_residuals(const DevPlan &P, const RobotT<S>
     }
 }
 
-// Cost of trajectory X: pose, smoothness and (wc != 0) collision parts,
-// block-reduced.
-template <typename S, bool PR>
-__device__ __forceinline__ double plan_cost(const DevPlan &P, const RobotT<S> &rb, const CPF_GLOBAL double *X,
-                                            int T, double *red, double wp, double ws, double wc) {
+// Cost of trajectory X in FP64: pose, smoothness and (wc != 0) collision
+// parts, block-reduced.  With R non-null every waypoint's residual rows go
+// to R ([RROWS][T]; the collision rows only when wc != 0).
+template <bool PR>
+__device__ __forceinline__ double plan_cost(const DevPlan &P, const CPF_GLOBAL double *X, int T, double *red,
+                                            double wp, double ws, double wc, CPF_GLOBAL double *R) {
+    const RobotT<double> rb = load_robot<double, PR>(P);
     double ps = 0.0, ss = 0.0, cs = 0.0;
     for (int t = threadIdx.x; t < T; t += LM_BS) {
-        ps += pose_sq<S, PR>(P, rb, X, T, t);
+        double r[6];
+        ps += pose_res64<PR>(P, rb, X, T, t, r);
+        if (R) {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) R[(size_t)i * T + t] = r[i];
+        }
         if (t + 1 < T) {
 #pragma unroll
             for (int j = 0; j < NJ; ++j) {
@@ -123,12 +137,16 @@ __device__ __forceinline__ double plan_cost(const DevPlan &P, const RobotT<S> &r
             }
         }
         if (wc != 0.0) {
-            S q[NJ];
+            double q[NJ];
 #pragma unroll
-            for (int j = 0; j < NJ; ++j) q[j] = (S)X[(size_t)j * T + t];
+            for (int j = 0; j < NJ; ++j) q[j] = X[(size_t)j * T + t];
             double rc[2], Jc[2][NJ];
-            coll_residuals<S, false, PR>(P, rb, q, rc, Jc);
+            coll_residuals<double, false, PR>(P, rb, q, rc, Jc);
             cs += rc[0] * rc[0] + rc[1] * rc[1];
+            if (R) {
+                R[(size_t)6 * T + t] = rc[0];
+                R[(size_t)7 * T + t] = rc[1];
+            }
         }
     }
     const double pose_sum = block_sum(ps, red);
@@ -137,10 +155,14 @@ __device__ __forceinline__ double plan_cost(const DevPlan &P, const RobotT<S> &r
     return 0.5 * wp * pose_sum + 0.5 * ws * diff_sum + 0.5 * wc * coll_sum;
 }
 
-// Linearise at xi: A_t = w_p J^T J (packed lower), g_t; returns max |g|.
+// Linearise at xi: A_t = w_p J^T J (whole blocks), g_t; returns max |g|.
+// S = double: J and the residual from one FP64 chain.  S = float (the mixed
+// arm): J from an FP32 chain, the residual rows of xi in FP64 from P.rr,
+// where the cost evaluation that produced xi left them.
 template <typename S, bool PR>
 __device__ __forceinline__ double linearise(const DevPlan &P, const RobotT<S> &rb, int T, double w_p, double w_s,
                                             double w_c) {
+    constexpr bool F64 = sizeof(S) == sizeof(double);
     double gmax = 0.0;
     for (int t = threadIdx.x; t < T; t += LM_BS) {
         double xq[NJ];
@@ -150,11 +172,18 @@ __device__ __forceinline__ double linearise(const DevPlan &P, const RobotT<S> &r
             xq[j] = P.xi[(size_t)j * T + t];
             q[j] = (S)xq[j];
         }
+        double r[6];
+        if constexpr (!F64) {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) r[i] = P.rr[(size_t)i * T + t];
+        }
         S Xc[3], Yc[3], Zc[3], p[3], Zs[NJ][3], Os[NJ][3];
         chain<S, true, PR>(rb, q, Xc, Yc, Zc, p, Zs, Os);
-        S tg[12], r[6];
-        load_target<S>(P, T, t, tg);
-        pose_residual<S>(Xc, Yc, Zc, p, tg, r);
+        if constexpr (F64) {
+            double tg[12];
+            load_target<double>(P, T, t, tg);
+            pose_residual<double>(Xc, Yc, Zc, p, tg, r);
+        }
         S J[6][NJ];
         if constexpr (PR) {
 #pragma unroll
@@ -198,9 +227,9 @@ __device__ __forceinline__ double linearise(const DevPlan &P, const RobotT<S> &r
         }
 #pragma unroll
         for (int i = 0; i < NJ; ++i) {
-            double s = (double)J[0][i] * (double)r[0];
+            double s = (double)J[0][i] * r[0];
 #pragma unroll
-            for (int k = 1; k < 6; ++k) s += (double)J[k][i] * (double)r[k];
+            for (int k = 1; k < 6; ++k) s += (double)J[k][i] * r[k];
             double gi = w_p * s;
             double sm = 0.0;
             if (t > 0) sm += xq[i] - P.xi[(size_t)i * T + t - 1];
@@ -220,7 +249,18 @@ __device__ __forceinline__ double linearise(const DevPlan &P, const RobotT<S> &r
 #pragma unroll
             for (int j = 0; j < NJ; ++j) q[j] = (S)P.xi[(size_t)j * T + t];
             double rc[2], Jc[2][NJ];
-            coll_residuals<S, true, PR>(P, rb, q, rc, Jc);
+            if constexpr (F64) {
+                coll_residuals<S, true, PR>(P, rb, q, rc, Jc);
+            } else {   // FP32 distance gradients; the FP64 residuals decide which are active
+                S dm[2], gd[2][NJ];
+                coll_distances<S, true, S, PR>(rb, CapsOf<S>::get(P), P.n_obs, P.obs, q, dm, gd, (S)P.coll_margin);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    rc[h] = P.rr[(size_t)(6 + h) * T + t];
+#pragma unroll
+                    for (int k = 0; k < NJ; ++k) Jc[h][k] = rc[h] > 0.0 ? -(double)gd[h][k] : 0.0;
+                }
+            }
 #pragma unroll
             for (int i = 0; i < NJ; ++i) {
 #pragma unroll
@@ -985,6 +1025,8 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
     constexpr bool sched = SCHED;
     LMState *st = P.st;
     const double wc_all = COLL ? P.w_coll : 0.0;   // weight of the collision residuals
+    // the mixed arm keeps the FP64 residual rows of xi (and of the trial point)
+    constexpr bool keep_r = sizeof(S) != sizeof(double);
 
     if (tid == 0) sh_flags[2] = st->seeded;
     __syncthreads();
@@ -998,7 +1040,7 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
                 P.xi[(size_t)j * T + t] = v;
             }
         __syncthreads();
-        const double c0 = plan_cost<S, PR>(P, load_robot<S, PR>(P), P.xi, T, red, P.w_p, P.w_s, wc_all);
+        const double c0 = plan_cost<PR>(P, P.xi, T, red, P.w_p, P.w_s, wc_all, keep_r ? P.rr : nullptr);
         if (tid == 0) {
             st->nu = 2.0;
             st->cost = c0;
@@ -1081,7 +1123,7 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
             if (m != sh_sched[2]) {   // new objective: its cost and linearisation
                 // (the barriers inside plan_cost order every lane's read of
                 // sh_sched[2] before lane 0 rewrites it)
-                const double c = plan_cost<S, PR>(P, load_robot<S, PR>(P), P.xi, T, red, wp, ws, wc);
+                const double c = plan_cost<PR>(P, P.xi, T, red, wp, ws, wc, keep_r ? P.rr : nullptr);
                 if (tid == 0) {
                     sh_cost = c;
                     sh_flags[0] = 1;
@@ -1145,7 +1187,7 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
                 pr += dl * (lam * dl - P.g[e]);
             }
         __syncthreads();
-        const double cn = plan_cost<S, PR>(P, load_robot<S, PR>(P), P.xt, T, red, wp, ws, wc);
+        const double cn = plan_cost<PR>(P, P.xt, T, red, wp, ws, wc, keep_r ? P.rt : nullptr);
         const double pred = 0.5 * block_sum(pr, red);
         PHASE_MARK(5);
         if (tid == 0) {
@@ -1189,9 +1231,14 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
         }
         __syncthreads();
         if (sh_flags[2]) {
-            for (int t = tid; t < T; t += LM_BS)
+            for (int t = tid; t < T; t += LM_BS) {
 #pragma unroll
                 for (int j = 0; j < NJ; ++j) P.xi[(size_t)j * T + t] = P.xt[(size_t)j * T + t];
+                if (keep_r) {
+                    const int rows = wc != 0.0 ? RROWS : 6;
+                    for (int i = 0; i < rows; ++i) P.rr[(size_t)i * T + t] = P.rt[(size_t)i * T + t];
+                }
+            }
         }
         __syncthreads();
         PHASE_MARK(6);

@@ -40,7 +40,7 @@ inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 // region is shared with the search lists (topc), which are written later.
 struct Layout {
     size_t cand, extra, pen, bp, topk, topc, raw, path, dp_out, targets, xi, xt, A, g, cr, dx, rb, st,
-        report, xv, obs, cpen, total;
+        report, xv, obs, cpen, rr, rt, total;
 };
 Layout make_layout(int T, int K, bool extra, int n_obs, bool coll);
 uint64_t plan_bytes(int T, int K, bool extra, int n_obs, bool coll);
@@ -161,6 +161,11 @@ cpf_status plan_alloc(cpf_ctx *ctx, const HostRobot &hr, int T, int K, bool has_
 cpf_status plan_create(cpf_ctx *ctx, const HostRobot &hr, const cpf_problem *prob,
                        const cpf_opts *opts, int32_t iters_target, hipStream_t s, cpf_plan **out);
 void plan_destroy(cpf_plan *p);
+// Flag of a plan's device-resident inputs (an int in the report's last
+// slot): cleared when the arena is taken, set by the staging kernel when a
+// device input value is not finite.
+int *input_flag(cpf_plan *p);
+bool input_flag_set(const double *report);
 
 struct PlanReadback {
     LMState st;

@@ -38,9 +38,11 @@ struct Request {
     HostRobot robot{};
     cpf_opts opts{};
     int T = 0, K = 0;
-    // copies of the caller's arrays: candidates, targets, node costs, one
-    // buffer (pinned when the pinned pool allows, else pageable)
-    double *cand = nullptr, *targets = nullptr, *node_pen = nullptr, *obstacles = nullptr;
+    // copies of the caller's host arrays (candidates as given, double or
+    // float, targets, node costs, obstacles) in one buffer, pinned when the
+    // pinned pool allows, else pageable; device-resident candidates and
+    // targets are not copied (prob points at them)
+    cpf_problem prob{};
     int n_obs = 0;
     void *stage = nullptr;
     uint64_t stage_cls = 0;
@@ -145,7 +147,7 @@ void release_stage(cpf_ctx *ctx, Request *r) {
     if (r->stage) pinned_put(ctx, r->stage, r->stage_cls);
     r->stage = nullptr;
     std::vector<double>().swap(r->stage_vec);
-    r->cand = r->targets = r->node_pen = r->obstacles = nullptr;
+    r->prob = cpf_problem{};
 }
 
 // Release a request's slot, plan and inputs and wake its pollers.  The slot's
@@ -217,7 +219,7 @@ void retire(cpf_ctx *ctx, Server *sv, const std::vector<Request *> &fin, cpf_sta
             report_from(ls, r->report, &r->rep);
             r->best = r->dp_out[0];
             r->smjac = r->dp_out[1];
-            r->status = ls.status != 0 ? CPF_E_NUMERIC : CPF_OK;
+            r->status = input_flag_set(r->report) ? CPF_E_ARG : (ls.status != 0 ? CPF_E_NUMERIC : CPF_OK);
         }
         finish(ctx, sv, r);
     }
@@ -238,9 +240,8 @@ int admit(cpf_ctx *ctx, Server *sv, int free_slots) {
             r = ctx->pending.front();
             ctx->pending.pop_front();
         }
-        cpf_problem pb{r->T, r->K, r->targets, r->cand, r->node_pen, r->n_obs, r->obstacles};
         r->t_admit = now_ns();
-        cpf_status st = plan_create(ctx, r->robot, &pb, &r->opts, r->opts.iters, sv->s_up, &r->plan);
+        cpf_status st = plan_create(ctx, r->robot, &r->prob, &r->opts, r->opts.iters, sv->s_up, &r->plan);
         if (st == CPF_E_NOMEM) {   // wait for arenas to come back
             std::lock_guard<std::mutex> lk(ctx->mu);
             ctx->pending.push_front(r);
@@ -419,6 +420,7 @@ extern "C" cpf_status cpf_submit(cpf_ctx *ctx, const cpf_robot *robot, const cpf
     cpf_opts_default(&o);
     if (opts) o = *opts;
     if ((st = check_opts(&o)) != CPF_OK) return st;
+    if (o.iters < 1) return fail(CPF_E_ARG, "iters=%d: a served request runs at least one LM iteration", o.iters);
     const uint64_t bytes = plan_class_bytes(prob->T, prob->K, prob->node_pen != nullptr, prob->n_obstacles, hr.has_caps);
     if (bytes > ctx->budget)
         return fail(CPF_E_NOMEM, "request needs %llu bytes, budget is %llu",
@@ -428,25 +430,55 @@ extern "C" cpf_status cpf_submit(cpf_ctx *ctx, const cpf_robot *robot, const cpf
     r->opts = o;
     r->T = prob->T;
     r->K = prob->K;
+    // staging bytes: [candidates][targets][node costs][obstacles], each part
+    // starting on an 8-byte boundary; device-resident candidates and targets
+    // stay where they are
+    const bool dev = prob->mem == CPF_MEM_DEVICE;
+    const bool f32 = prob->cand_f32 != nullptr;
     const size_t n_cand = (size_t)prob->K * prob->T * NJ, n_tg = (size_t)prob->T * 12;
+    const size_t b_cand = dev ? 0 : ((n_cand * (f32 ? sizeof(float) : sizeof(double)) + 7) & ~size_t(7));
+    const size_t b_tg = dev ? 0 : n_tg * sizeof(double);
     const size_t n_pen = prob->node_pen ? (size_t)prob->T * prob->K : 0;
     const size_t n_ob = (size_t)prob->n_obstacles * 18;
-    const size_t n_all = n_cand + n_tg + n_pen + n_ob;
-    r->stage = pinned_get(ctx, n_all * sizeof(double), &r->stage_cls);
-    double *buf = (double *)r->stage;
-    if (!buf) {
-        r->stage_vec.resize(n_all);
-        buf = r->stage_vec.data();
+    const size_t b_all = b_cand + b_tg + (n_pen + n_ob) * sizeof(double);
+    char *buf = nullptr;
+    if (b_all > 0) {
+        r->stage = pinned_get(ctx, b_all, &r->stage_cls);
+        buf = (char *)r->stage;
+        if (!buf) {
+            r->stage_vec.resize((b_all + 7) / 8);
+            buf = (char *)r->stage_vec.data();
+        }
     }
-    r->cand = buf;
-    r->targets = buf + n_cand;
-    r->node_pen = n_pen ? buf + n_cand + n_tg : nullptr;
+    cpf_problem &pb = r->prob;
+    pb.T = prob->T;
+    pb.K = prob->K;
+    pb.mem = prob->mem;
+    if (dev) {
+        pb.cand_f32 = prob->cand_f32;
+        pb.targets = prob->targets;
+    } else {
+        if (f32) {
+            pb.cand_f32 = (const float *)buf;
+            copy_parallel(buf, prob->cand_f32, n_cand * sizeof(float));
+        } else {
+            pb.cand = (const double *)buf;
+            copy_parallel(buf, prob->cand, n_cand * sizeof(double));
+        }
+        pb.targets = (const double *)(buf + b_cand);
+        memcpy(buf + b_cand, prob->targets, b_tg);
+    }
+    double *tail = buf ? (double *)(buf + b_cand + b_tg) : nullptr;
+    if (n_pen) {
+        pb.node_pen = tail;
+        copy_parallel(tail, prob->node_pen, n_pen * sizeof(double));
+    }
     r->n_obs = prob->n_obstacles;
-    r->obstacles = n_ob ? buf + n_cand + n_tg + n_pen : nullptr;
-    copy_parallel(r->cand, prob->cand, n_cand * sizeof(double));
-    memcpy(r->targets, prob->targets, n_tg * sizeof(double));
-    if (n_pen) copy_parallel(r->node_pen, prob->node_pen, n_pen * sizeof(double));
-    if (n_ob) memcpy(r->obstacles, prob->obstacles, n_ob * sizeof(double));
+    pb.n_obstacles = prob->n_obstacles;
+    if (n_ob) {
+        pb.obstacles = tail + n_pen;
+        memcpy(tail + n_pen, prob->obstacles, n_ob * sizeof(double));
+    }
     r->bytes = bytes;
     r->t_submit = now_ns();
     {

@@ -32,6 +32,7 @@ and stored as float64, so both sides see bit-identical inputs.
 from __future__ import annotations
 
 import dataclasses
+import functools
 import math
 
 import numpy as np
@@ -126,6 +127,23 @@ def make_robot_prismatic(seed: int, joint: int = 0, travel: float = 0.4) -> Robo
     return dataclasses.replace(rb, q_lo=lo, q_hi=hi, joint_type=jt)
 
 
+def _path(robot: Robot, seed: int, T: int, rng=None) -> np.ndarray:
+    """Ground-truth joint path q* [T][n] (float32 values): the first draws of
+    default_rng([seed, 1]) (rng continues from there when given)."""
+    n = robot.dof
+    if rng is None:
+        rng = np.random.default_rng([seed, 1])
+    c = rng.uniform(-1.0, 1.0, n)
+    A = rng.uniform(0.0, 0.5 / 3.0, (n, 3))
+    f = rng.uniform(0.25, 1.5, (n, 3))
+    ph = rng.uniform(0.0, 2 * math.pi, (n, 3))
+    s = np.arange(T, dtype=np.float64) / max(T - 1, 1)
+    arg = 2 * math.pi * f[None, :, :] * s[:, None, None] + ph[None, :, :]
+    q_star = c[None, :] + np.sum(A[None, :, :] * np.sin(arg), axis=2)
+    ctr, sc = _joint_map(robot)
+    return np.clip(_f32(ctr + sc * q_star), robot.q_lo, robot.q_hi)
+
+
 def make_problem(robot: Robot, seed: int, T: int, K: int, sigma: float,
                  branch_frac: float = 0.0, n_branch: int | None = None,
                  mode: str = "iid") -> Problem:
@@ -139,15 +157,8 @@ def make_problem(robot: Robot, seed: int, T: int, K: int, sigma: float,
         raise ValueError("T and K must be >= 1")
     n = robot.dof
     rng = np.random.default_rng([seed, 1])
-    c = rng.uniform(-1.0, 1.0, n)
-    A = rng.uniform(0.0, 0.5 / 3.0, (n, 3))
-    f = rng.uniform(0.25, 1.5, (n, 3))
-    ph = rng.uniform(0.0, 2 * math.pi, (n, 3))
-    s = np.arange(T, dtype=np.float64) / max(T - 1, 1)
-    arg = 2 * math.pi * f[None, :, :] * s[:, None, None] + ph[None, :, :]
-    q_star = c[None, :] + np.sum(A[None, :, :] * np.sin(arg), axis=2)
-    ctr, sc = _joint_map(robot)
-    q_star = np.clip(_f32(ctr + sc * q_star), robot.q_lo, robot.q_hi)
+    q_star = _path(robot, seed, T, rng)
+    _, sc = _joint_map(robot)
 
     if mode == "iid":
         noise = rng.normal(0.0, sigma, (K, T, n))
@@ -273,16 +284,53 @@ def config4_problem(i: int, T_range=(100, 1000), K_range=(64, 512)) -> Problem:
                         branch_frac=0.25)
 
 
+# The serving stream draws its candidate noise from one pool of float32
+# standard normals (2^26 of them, 256 MB, drawn once per process): request i
+# takes a contiguous run of K*T*n values at a seeded offset, so each request
+# still sees i.i.d. N(0, sigma) noise, and a stream of thousands of distinct
+# requests costs a few passes over float32 arrays each instead of fresh
+# normal draws.
+NOISE_POOL = 1 << 26
+
+
+@functools.lru_cache(maxsize=1)
+def _noise_pool() -> np.ndarray:
+    return np.random.default_rng([5, 9]).standard_normal(NOISE_POOL, dtype=np.float32)
+
+
 def config5_request(i: int, T_range=(50, 2000), K_choices=(128, 256, 512)) -> Problem:
-    """Request i of the serving stream: seed-0 robot, per-request shape."""
+    """Request i of the serving stream: seed-0 robot, per-request shape,
+    noise level and branch fraction.  Draw order: rng = default_rng([5000 + i,
+    2]): T ~ U{T_range}, K from K_choices, sigma ~ U[0.02, 0.15], frac ~ U[0,
+    0.3], the pool offset ~ U{0 .. pool - K*T*n}, a permutation of K (the
+    first round(frac*K) get the branch offset), one sign per (offset
+    candidate, joint 2/4/6); the path q* as make_problem draws it (seed 5000 +
+    i).  Candidates are computed in float32 (q* + sigma * noise, offsets,
+    clamp) and returned as a float32 array [K][T][n]."""
     seed = 5000 + i
     rng = np.random.default_rng([seed, 2])
     T = int(rng.integers(T_range[0], T_range[1] + 1))
     K = int(rng.choice(np.array(K_choices)))
     sigma = float(rng.uniform(0.02, 0.15))
     frac = float(rng.uniform(0.0, 0.3))
-    return make_problem(make_robot(0), seed=seed, T=T, K=K, sigma=sigma,
-                        branch_frac=frac)
+    robot = make_robot(0)
+    n = robot.dof
+    q_star = _path(robot, seed, T)
+    pool = _noise_pool()
+    m = K * T * n
+    if m > pool.shape[0]:
+        raise ValueError("request larger than the noise pool")
+    off = int(rng.integers(0, pool.shape[0] - m + 1))
+    cand = pool[off:off + m].reshape(K, T, n) * np.float32(sigma)
+    cand += q_star.astype(np.float32)[None, :, :]
+    nb = int(round(frac * K))
+    sel = rng.permutation(K)[:nb]
+    signs = rng.choice(np.array([-1.0, 1.0]), (nb, len(BRANCH_JOINTS)))
+    for c_i, j in enumerate(BRANCH_JOINTS):
+        cand[sel, :, j] += (signs[:, c_i] * (math.pi / 2)).astype(np.float32)[:, None]
+    np.clip(cand, robot.q_lo.astype(np.float32), robot.q_hi.astype(np.float32), out=cand)
+    return Problem(robot=robot, q_star=q_star, cand=cand, targets=None, seed=seed, sigma=sigma,
+                   branch_frac=float(nb) / K)
 
 
 def config5_arrivals(rate_hz: float = 200.0, duration_s: float = 60.0,

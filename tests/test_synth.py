@@ -67,3 +67,26 @@ def test_prismatic_robot_and_its_inputs():
     assert np.abs(q[:, 1:]).max() <= math.pi
     extra = synth.more_candidates(p, 8)
     assert extra[..., 0].min() >= 0.0 and extra[..., 0].max() <= rb.q_hi[0]
+
+
+def test_serving_requests_distinct_and_distributed():
+    """Each request of the stream has its own shape, path and noise: the
+    candidates are float32 values inside the limits; the candidates without
+    a branch offset scatter around q* with the request's sigma; round(frac K)
+    candidates carry the +-pi/2 offset on joints 2, 4 and 6."""
+    reqs = [synth.config5_request(i) for i in range(6)]
+    assert len({(r.T, r.K, r.sigma) for r in reqs}) == 6
+    for r in reqs:
+        assert r.cand.dtype == np.float32 and r.cand.shape == (r.K, r.T, 7)
+        assert np.all(r.cand <= r.robot.q_hi) and np.all(r.cand >= r.robot.q_lo)
+        dev = r.cand.astype(np.float64) - r.q_star[None]
+        shifted = np.abs(dev[:, :, [1, 3, 5]]).mean(axis=(1, 2)) > 0.8
+        assert shifted.sum() == round(r.branch_frac * r.K)
+        plain = dev[~shifted]
+        inside = np.abs(r.q_star[None] + plain) < 2.8 - 1e-6   # not clamped
+        z = plain[inside]
+        assert abs(z.mean()) < 0.05 * r.sigma
+        assert abs(z.std() / r.sigma - 1.0) < 0.05
+    # requests are distinct (different paths and noise)
+    a, b = reqs[0], reqs[1]
+    assert not np.array_equal(a.q_star[:min(a.T, b.T)], b.q_star[:min(a.T, b.T)])
