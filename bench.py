@@ -1,29 +1,32 @@
 """Benchmark of the CppFlow refinement path on one MI355X.
 
-A step is one pass of the whole path over one request: batched FK over the
-K x T candidates, the layered-graph search with its back-tracking and seed
-gather, the LM iterations (linearise, FP64 block solve with refinement,
-trial, accept) and the pose-error report.  Inputs are resident in HBM before
-the timed region starts (the plan is uploaded once; every step restarts from
-the search).
+Headline (the metric's own workload): the serving stream.  Requests arrive
+as a Poisson stream at 200 per second; each has T ~ U{50..2000} waypoints,
+K in {128, 256, 512} candidate plans (sigma ~ U[0.02, 0.15], branch-offset
+fraction ~ U[0, 0.3]) on the seed-0 7-DOF DH robot and asks for the search
+plus 30 LM iterations.  Every request is distinct (seeded), and the inputs
+of all of them are resident in HBM before the stream starts.  A step is one
+second of the arrival stream (about 200 requests, each a whole pass of the
+path: staging, search with its lists and back-tracking, 30 LM iterations,
+report); --warmup W serves the first W seconds untimed, --steps K times the
+next K seconds.  `value` is waypoint-LM-iterations per second of the
+continuously batched mixed-precision server (FP32 Jacobian, FP64 residual,
+cost and solve) on that open-loop schedule (submit of the first timed
+request to completion of the last); p50/p99 latency is submit -> result.
+Beside it: the same requests all at once (saturation), the all-FP64 arm
+continuously batched, and the plain all-FP64 path one request at a time on
+the same schedule.
 
-Default workload: T=300 waypoints, K=256 candidates (sigma 0.1 rad, 25%
-branch-offset candidates), 50 LM iterations, seed-0 7-DOF DH robot.
-
-Prints one JSON line.  `value` is waypoint-LM-iterations per second of the
-mixed-precision path (FP32 kinematics, FP64 solve); the all-FP64 path on the
-same GPU is reported beside it.  The `serving` object is the other half of
-the metric: a short seeded request stream (Poisson arrivals at 200/s,
-T ~ U{50..2000}, K in {128, 256, 512}, 30 LM iterations) served by
-cpf_submit/cpf_poll (continuous batching, mixed precision) and by the
-all-FP64 path one request at a time, with p50/p99 latency, open loop and as
-a closed-loop burst.
+The line also carries the roofline of the kernel with the most device time
+in the timed stream, the oracle's throughput on the host's cores
+(cpu_baseline) with the served results' pose errors against it, and, as
+context, the single T=300/K=256 request, the same request 256 times in one
+launch (chip full) and the 64-problem ragged batch.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import platform
 import sys
@@ -37,10 +40,14 @@ sys.path.insert(0, ROOT)
 PEAK_ALU_TFLOPS = 78.6      # 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz, FP32 unpacked and FP64
 PEAK_HBM_GBS = 8000.0
 
-# Algorithmic flops of one LM waypoint-iteration (derivation in the design notes):
-# linearise 964 (FK + J + residual + J^T J + J^T r), trial 436 (FK + residual),
-# FP64 solve 1160, FP64 refinement 330, FP64 clamp / predicted reduction 42.
-LM_FLOPS_PER_WAYPOINT_ITER = 964 + 436 + 1160 + 330 + 42
+# Algorithmic operations of one LM waypoint-iteration.  The survey's count
+# of the method (FK, Jacobian and residual of the linearisation and of the
+# trial, 7x7 Cholesky, block elimination, sweeps and refinement) is about
+# 1.3k + 0.6k; this build's own tally of the same steps (derivation in the
+# design notes) is 2,932 because it counts the block solve's products in
+# full.  `frac` uses the smaller count; `frac_own_count` the larger.
+LM_OPS_SURVEY = 1900
+LM_OPS_OWN = 964 + 436 + 1160 + 330 + 42
 # One search pair (t, k', k): 7 sub + 7 abs-max + add + max + 2 compares.
 DP_OPS_PER_PAIR = 18
 
@@ -48,24 +55,24 @@ DP_OPS_PER_PAIR = 18
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--iters", type=int, default=50)
-    ap.add_argument("--workload", default="T300_K256",
-                    choices=["T300_K256", "T1000_K512", "batch64", "batchopt", "schedule", "research",
-                             "collision", "prismatic", "serve"],
-                    help="T300_K256: the headline single-request line; the others are the "
-                         "additional measured workloads in paper_2309_09102_amd/workloads.py")
-    ap.add_argument("--duration", type=float, default=10.0, help="serve: stream length (s)")
+    ap.add_argument("--steps", type=int, default=20,
+                    help="seconds of the arrival stream timed (about 200 requests each)")
+    ap.add_argument("--warmup", type=int, default=5, help="seconds of the arrival stream served untimed")
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--iters", type=int, default=30, help="LM iterations per request")
+    ap.add_argument("--workload", default="serve",
+                    choices=["serve", "T300_K256", "T1000_K512", "batch64", "batchopt", "schedule", "research",
+                             "collision", "prismatic"],
+                    help="serve: the headline line; the others print the additional measured workloads "
+                         "of paper_2309_09102_amd/workloads.py")
+    ap.add_argument("--fp64-budget", type=float, default=None,
+                    help="seconds after which the one-at-a-time FP64 arm starts no further request "
+                         "(default: the timed stream's length)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-full-chip", action="store_true",
-                    help="skip the leg that runs the same request 256 times in one batch launch "
-                         "(one plan per compute unit)")
-    ap.add_argument("--no-serving", action="store_true",
-                    help="skip the short serving comparison (continuous batching, mixed precision, "
-                         "vs all-FP64 one request at a time) that the default line carries")
-    ap.add_argument("--serving-seconds", type=float, default=5.0)
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-context-legs", action="store_true",
+                    help="skip the single-request, chip-full and 64-problem legs")
+    ap.add_argument("--cpu-seconds", type=float, default=30.0,
+                    help="wall budget of the oracle on the sampled stream requests (all host cores)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device copy three times: the known-size "
                          "reference that scales the FETCH_SIZE / WRITE_SIZE counters")
@@ -95,9 +102,10 @@ def kernel_sources_sha(files):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, summary="hbm_traffic_T300_K256.json"):
-    """HBM bytes per launch of `kernel` from a committed counter summary, or
-    None when the kernel's sources changed since the counters were taken."""
+def measured_traffic(kernel, summary):
+    """Record of `kernel` in a committed counter summary (HBM bytes per
+    launch and per unit of work), or None when the kernel's sources changed
+    since the counters were taken."""
     path = os.path.join(ROOT, "profiles", summary)
     try:
         with open(path) as fh:
@@ -107,7 +115,266 @@ def measured_traffic(kernel, summary="hbm_traffic_T300_K256.json"):
     k = rec.get("kernels", {}).get(kernel)
     if not k or k.get("sources_sha") != kernel_sources_sha(k["sources"]):
         return None
-    return k["bytes_per_launch"]
+    return k
+
+
+def cpu_info():
+    model = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return model, avail
+
+
+def oracle_threads():
+    """Host threads for the oracle: the cores this process may use, at most
+    16 (the GPU machine's share)."""
+    return max(1, min(16, cpu_info()[1]))
+
+
+# ---- the serving headline ----------------------------------------------------
+
+def roofline_of(summary, raw, iters):
+    """Roofline object of the kernel with the most device time in the timed
+    open-loop stream: algorithmic operations of all its launches over their
+    summed duration."""
+    ks = summary["mixed_open"]["kernels"]
+    timed = raw["timed"]
+    lm_units = sum(T for _, T, _ in timed) * iters
+    pairs = sum((T - 1) * K * K for _, T, K in timed)
+    cand = {"lm": ("lm_kernel<float, false, false, false> (tick graph)", lm_units * LM_OPS_SURVEY,
+                   lm_units * LM_OPS_OWN, f"{lm_units} waypoint-LM-iterations x {LM_OPS_SURVEY} ops"),
+            "dp_lists": ("dp_topm_kernel", pairs * DP_OPS_PER_PAIR, pairs * DP_OPS_PER_PAIR,
+                         f"{pairs} search pairs x {DP_OPS_PER_PAIR} FP64 ops"),
+            "dp": ("dp_kernel<512, 2>", None, None, "stage recursion (one workgroup per plan)")}
+    dom = max(("lm", "dp_lists", "dp"), key=lambda k: ks[k]["ms"])
+    name, flops, flops_own, unit = cand[dom]
+    ms, n = ks[dom]["ms"], ks[dom]["launches"]
+    roof = {"bound": "alu", "kernel": name, "unit": "TFLOP/s", "peak": PEAK_ALU_TFLOPS,
+            "launches": n, "avg_launch_ms": ms / max(n, 1), "work": unit,
+            "device_ms": {k: v["ms"] for k, v in ks.items()}}
+    if flops is not None:
+        ach = flops / (ms * 1e-3) / 1e12
+        roof.update({"achieved": ach, "frac": ach / PEAK_ALU_TFLOPS,
+                     "frac_own_count": flops_own / (ms * 1e-3) / 1e12 / PEAK_ALU_TFLOPS})
+    rec = measured_traffic("serving:" + dom, "hbm_traffic_serving.json")
+    if rec is not None:
+        per_unit = rec["bytes_per_unit"]
+        units = lm_units if dom == "lm" else pairs
+        roof["traffic"] = per_unit * units / max(n, 1)
+        roof["traffic_GBps"] = per_unit * units / (ms * 1e-3) / 1e9
+    else:
+        roof["traffic"] = None
+    return roof
+
+
+# ---- the oracle leg (cpu_baseline) -------------------------------------------
+
+def _parallel(fn, items, threads, deadline=None):
+    """fn over items on `threads` host threads (the C oracle runs outside the
+    interpreter lock); items not started before `deadline` are skipped.
+    Returns (results in item order, None where skipped), wall seconds."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def run(x):
+        if deadline is not None and time.perf_counter() > deadline:
+            return None
+        return fn(x)
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        res = list(ex.map(run, items))
+    return res, time.perf_counter() - t0
+
+
+def cpu_baseline_leg(args, summary, raw, ctx_results):
+    """The FP64 C oracle on the host: the sampled serving requests on all
+    cores (throughput, and the served results' errors against it), configs
+    1-3 on one core, the 64-problem batch on all cores."""
+    import oracle
+    from paper_2309_09102_amd import synth
+    model, avail = cpu_info()
+    threads = oracle_threads()
+    iters = args.iters
+    timed = raw["timed"]
+    # every 20th timed request and the 20 longest
+    idx = [timed[k][0] for k in range(0, len(timed), 20)]
+    longest = sorted(timed, key=lambda x: -x[1])[:20]
+    idx = sorted(set(idx) | {i for i, _, _ in longest})
+    served = raw["mixed_open"]["xi"]
+    fp64 = raw["fp64_one_at_a_time_open"]["xi"]
+    gpu_tg = raw.get("targets", {})
+
+    def solve(i):
+        p = synth.config5_request(i)
+        p = p.with_targets(oracle.fk(p.robot, p.q_star))
+        t0 = time.perf_counter()
+        ref = oracle.plan(p.robot, p.cand, p.targets, iters)
+        dt = time.perf_counter() - t0
+        rec = {"i": i, "T": p.T, "K": p.K, "sec": dt,
+               "targets_equal": bool(i in gpu_tg and np.array_equal(gpu_tg[i], p.targets))}
+        c_ref = oracle.cost(p.robot, ref["xi"], p.targets)
+        for arm, xs in (("mixed_served", served), ("fp64_one_at_a_time", fp64)):
+            if i in xs:
+                ep, er = oracle.pose_compare(p.robot, xs[i], ref["xi"])
+                c = oracle.cost(p.robot, xs[i], p.targets)
+                rec[arm] = [ep, er, abs(c - c_ref) / max(c_ref, 1e-12)]
+        return rec
+
+    deadline = time.perf_counter() + args.cpu_seconds
+    recs, wall = _parallel(solve, idx, threads, deadline)
+    done = [r for r in recs if r is not None]
+    work = sum(r["T"] for r in done) * iters
+
+    def dist(arm):
+        v = np.array([r[arm] for r in done if arm in r])
+        if not len(v):
+            return None
+        return {"n": int(len(v)), "pos_m": {"p50": float(np.median(v[:, 0])), "p99": float(np.percentile(v[:, 0], 99)),
+                                            "max": float(v[:, 0].max())},
+                "rot_rad": {"p50": float(np.median(v[:, 1])), "p99": float(np.percentile(v[:, 1], 99)),
+                            "max": float(v[:, 1].max())},
+                "rel_cost_gap": {"p50": float(np.median(v[:, 2])), "max": float(v[:, 2].max())},
+                "within_1e-5_m_rad": bool(v[:, 0].max() <= 1e-5 and v[:, 1].max() <= 1e-5),
+                "within_1e-6_cost": bool(v[:, 2].max() <= 1e-6)}
+
+    cb = {"value": work / wall, "unit": "waypoint-LM-iters/s", "cores": threads, "kind": "oracle",
+          "sample": (f"{len(done)} of {len(idx)} sampled serving-stream requests (every 20th timed request "
+                     f"and the 20 longest; search + {iters} LM iterations each), FP64 C oracle on "
+                     f"{threads} host threads, {wall:.1f} s wall"),
+          "cpu_model": model, "host_cores_available": avail}
+    pose = {"mixed_served": dist("mixed_served"), "fp64_one_at_a_time": dist("fp64_one_at_a_time"),
+            "sampled_requests": len(done),
+            "targets_bitwise_equal": int(sum(r["targets_equal"] for r in done)),
+            "note": "oracle targets from its own FP64 FK of q*, rounded to float32 like the GPU's"}
+
+    # configs 1-3 on one core (median of a few runs), config 4 on all cores
+    def one_core(p, it, reps):
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            oracle.plan(p.robot, p.cand, p.targets, it)
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    c1 = synth.config1()
+    c1 = c1.with_targets(oracle.fk(c1.robot, c1.q_star))
+    t1 = one_core(c1, 20, 5)
+    cfg = {"config1": {"T": 50, "K": 16, "lm_iters": 20, "cores": 1, "latency_ms": t1 * 1e3,
+                       "waypoint_lm_iters_per_s": 50 * 20 / t1}}
+    c2 = synth.config2()
+    c2 = c2.with_targets(oracle.fk(c2.robot, c2.q_star))
+    t2 = one_core(c2, 50, 3)
+    cfg["config2"] = {"T": 300, "K": 256, "lm_iters": 50, "cores": 1, "latency_ms": t2 * 1e3,
+                      "waypoint_lm_iters_per_s": 300 * 50 / t2}
+    c3 = synth.config3()
+    c3 = c3.with_targets(oracle.fk(c3.robot, c3.q_star))
+    t0 = time.perf_counter()
+    ref3 = oracle.plan(c3.robot, c3.cand, c3.targets, 50)
+    t3 = time.perf_counter() - t0
+    cfg["config3"] = {"T": 1000, "K": 512, "lm_iters": 50, "cores": 1, "latency_ms": t3 * 1e3,
+                      "waypoint_lm_iters_per_s": 1000 * 50 / t3}
+    if "config3_xi" in ctx_results:
+        cfg["config3"]["gpu_pose_err_vs_oracle"] = {
+            arm: list(oracle.pose_compare(c3.robot, xi, ref3["xi"])) for arm, xi in ctx_results["config3_xi"].items()}
+    if "batch64_probs" in ctx_results:
+        probs = [p.with_targets(oracle.fk(p.robot, p.q_star)) for p in ctx_results["batch64_probs"]]
+        _, w4 = _parallel(lambda p: oracle.plan(p.robot, p.cand, p.targets, 30), probs, threads)
+        cfg["config4"] = {"problems": len(probs), "lm_iters": 30, "cores": threads, "wall_s": w4,
+                          "waypoint_lm_iters_per_s": sum(p.T for p in probs) * 30 / w4}
+    cb["configs"] = cfg
+    return cb, pose
+
+
+# ---- context legs --------------------------------------------------------------
+
+def context_legs(args, out, ctx_results):
+    """The single T=300/K=256 request (mixed and FP64, each step a fresh full
+    search + 50 LM iterations + report on resident inputs), the same request
+    256 times in one launch, the T=1000/K=512 precision study and the
+    64-problem ragged batch."""
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_2309_09102_amd import cpf, synth, workloads
+    dev = torch.device("cuda:0")
+    ctx = cpf.Context(0)
+
+    def targets_of(p):
+        q = torch.tensor(p.q_star.T.copy(), dtype=torch.float64, device=dev)
+        pose, _ = ctx.fk_batch(p.robot, q)
+        torch.cuda.synchronize()
+        return p.with_targets(pose.cpu().numpy().T)
+
+    out["single_request"] = workloads.run_single(ctx=ctx, iters=50)
+    prob = targets_of(synth.config2())
+    T, iters = prob.T, 50
+
+    # the same request 256 times in one launch: one plan per compute unit
+    n_plans = 256
+    opts = cpf.make_opts(iters=iters)
+    items = [(prob.robot, prob.targets, prob.cand)] * n_plans
+    ctx.solve_batch(items[:8], opts)
+    ctx.profile(True)
+    res = ctx.solve_batch(items, opts)
+    lm_b = ctx.kernel_stats("lm")[0]
+    sr_b = ctx.kernel_stats("dp")[0] + ctx.kernel_stats("dp_lists")[0]
+    ctx.profile(False)
+    rec = measured_traffic("lm_kernel<float, false, false, false>", "hbm_traffic_full_chip_T300_K256.json")
+    tr = rec["bytes_per_launch"] if rec else None
+    out["full_chip"] = {"plans": n_plans, "lm_kernel_ms": lm_b, "search_ms": sr_b,
+                        "waypoint_lm_iters_per_s": T * iters * n_plans / (lm_b * 1e-3),
+                        "lm_frac": T * iters * n_plans * LM_OPS_SURVEY / (lm_b * 1e-3) / 1e12 / PEAK_ALU_TFLOPS,
+                        "lm_traffic": tr, "lm_traffic_GBps": tr / (lm_b * 1e-3) / 1e9 if tr else None,
+                        "results_identical": bool(all(np.array_equal(r["xi"], res[0]["xi"]) for r in res))}
+
+    # precision study T=1000, K=512 (pose errors against the oracle in the cpu_baseline leg)
+    p3 = targets_of(synth.config3())
+    xs = {}
+    prec_study = {}
+    for prec in ("mixed", "fp64"):
+        with ctx.plan(p3.robot, p3.targets, p3.cand, opts=cpf.make_opts(prec=prec, iters=50)) as plan:
+            plan.solve(want_xi=False)
+            t0 = time.perf_counter()
+            _, _, xi, rep = plan.solve(want_xi=True)
+            dt = time.perf_counter() - t0
+        xs[prec] = xi
+        prec_study[prec] = {"latency_ms": dt * 1e3, "waypoint_lm_iters_per_s": 1000 * 50 / dt}
+    out["precision_study_T1000_K512"] = prec_study
+    ctx_results["config3_xi"] = xs
+
+    # 64 ragged problems in one launch of each kernel
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        probs = list(ex.map(synth.config4_problem, range(64)))
+    ctx_results["batch64_probs"] = probs
+    probs_t = [targets_of(p) for p in probs]
+    o4 = cpf.make_opts(iters=30)
+    items = [(p.robot, p.targets, p.cand) for p in probs_t]
+    ctx.solve_batch(items[:2], o4)
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    ctx.solve_batch(items, o4)
+    t1 = time.perf_counter()
+    st = {k: ctx.kernel_stats(k)[0] for k in ("dp_lists", "dp", "lm", "eval")}
+    ctx.profile(False)
+    work = sum(p.T for p in probs_t) * 30
+    dev_ms = sum(st.values())
+    lm_frac = work * LM_OPS_SURVEY / (st["lm"] * 1e-3) / 1e12 / PEAK_ALU_TFLOPS
+    pairs = sum((p.T - 1) * p.K * p.K for p in probs_t)
+    out["batch64"] = {"problems": 64, "lm_iters": 30, "device_ms": dev_ms, "kernels_ms": st,
+                      "waypoint_lm_iters_per_s_device": work / (dev_ms * 1e-3),
+                      "waypoint_lm_iters_per_s_end_to_end": work / (t1 - t0),
+                      "lm_frac": lm_frac,
+                      "lists_frac": pairs * DP_OPS_PER_PAIR / (st["dp_lists"] * 1e-3) / 1e12 / PEAK_ALU_TFLOPS}
+    ctx.close()
 
 
 def main():
@@ -121,179 +388,63 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    if args.workload != "T300_K256":
+    if args.workload != "serve":
         from paper_2309_09102_amd import workloads
-        if args.workload == "T1000_K512":
-            out = workloads.run_precision(iters=args.iters)
-        elif args.workload == "batch64":
-            out = workloads.run_batch64(iters=30)
-        elif args.workload == "batchopt":
-            out = workloads.run_batchopt()
-        elif args.workload == "schedule":
-            out = workloads.run_schedule()
-        elif args.workload == "research":
-            out = workloads.run_research()
-        elif args.workload == "collision":
-            out = workloads.run_collision()
-        elif args.workload == "prismatic":
-            out = workloads.run_prismatic()
-        else:
-            out = workloads.run_serve(duration_s=args.duration)
-        print(json.dumps(out))
+        fn = {"T300_K256": workloads.run_single, "T1000_K512": workloads.run_precision,
+              "batch64": lambda: workloads.run_batch64(iters=30), "batchopt": workloads.run_batchopt,
+              "schedule": workloads.run_schedule, "research": workloads.run_research,
+              "collision": workloads.run_collision, "prismatic": workloads.run_prismatic}[args.workload]
+        print(json.dumps(fn()))
         return
 
-    import torch
-    from paper_2309_09102_amd import cpf, synth
+    import torch  # noqa: F401
+    from paper_2309_09102_amd import workloads
 
-    dev = torch.device("cuda:0")
-    prob = synth.config2()
-    T, K, iters = prob.T, prob.K, args.iters
-    ctx = cpf.Context(0)
-
-    # Targets FK(q*) by the library's FP64 FK on the device (input preparation).
-    q_star = torch.tensor(prob.q_star.T.copy(), dtype=torch.float64, device=dev)
-    pose, _ = ctx.fk_batch(prob.robot, q_star)
-    torch.cuda.synchronize()
-    prob = prob.with_targets(pose.cpu().numpy().T)
-
-    cand_soa = torch.tensor(prob.cand.reshape(-1, 7).T.copy(), dtype=torch.float32, device=dev)
-
-    def run_arm(prec):
-        opts = cpf.make_opts(prec=prec, iters=iters)
-        plan = ctx.plan(prob.robot, prob.targets, prob.cand, opts=opts)
-
-        def step():
-            ctx.fk_batch(prob.robot, cand_soa)          # batched FK over the K x T candidates
-            # search, back-track, seed, LM iterations and report in one stream
-            _, _, xi, rep = plan.solve(want_xi=False)
-            return xi, rep
-
-        for _ in range(args.warmup):
-            step()
-        torch.cuda.synchronize()
-        ctx.profile(True)
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            _, rep = step()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        stats = {k: ctx.kernel_stats(k) for k in ("fk", "dp", "lm", "eval")}
-        ctx.profile(False)
-        xi, _ = plan.lm_refine(0)
-        plan.free()
-        return (t1 - t0) / args.steps, stats, rep, xi
-
-    sec_mixed, st_mixed, rep_mixed, xi_mixed = run_arm("mixed")
-    sec_fp64, st_fp64, rep_fp64, xi_fp64 = run_arm("fp64")
-
-    work = T * iters
-    value = work / sec_mixed
-
-    def avg_ms(stats, k):
-        ms, n = stats[k]
-        return ms / max(n, 1)
-
-    lm_ms = avg_ms(st_mixed, "lm")
-    dp_ms = avg_ms(st_mixed, "dp")
-    lm_flops = LM_FLOPS_PER_WAYPOINT_ITER * T * iters
-    dp_flops = DP_OPS_PER_PAIR * (T - 1) * K * K
-    if lm_ms >= dp_ms:
-        dom, dom_ms, dom_flops = "lm_kernel<float, false, false, false>", lm_ms, lm_flops
-    else:
-        dom, dom_ms, dom_flops = "dp_kernel", dp_ms, dp_flops
-    achieved = dom_flops / (dom_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_ALU_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS, "traffic": measured_traffic(dom),
-                "avg_launch_ms": dom_ms}
-
+    summary, raw = workloads.run_serve(duration_s=float(args.steps), warmup_s=float(args.warmup),
+                                       rate_hz=args.rate, iters=args.iters, fp64_budget_s=args.fp64_budget,
+                                       keep_xi="sample")
+    mo = summary["mixed_open"]
     out = {
         "metric": "waypoint-LM-iters/sec",
-        "value": value,
+        "value": mo["throughput"],
         "unit": "waypoint-LM-iters/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": sec_mixed * 1e3,
+        "ms_per_step": mo["wall_s"] * 1e3 / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 kinematics + f64 solve",
-        "data": "synthetic (seeded DH robot, sum-of-sinusoid path, noisy candidate plans)",
-        "config": {"workload": f"single request T={T} K={K}, {iters} LM iterations",
-                   "T": T, "K": K, "lm_iters": iters, "parallelism": "single GPU"},
-        "fp64_path": {"value": work / sec_fp64, "ms_per_step": sec_fp64 * 1e3,
-                      "speedup_mixed_over_fp64": sec_fp64 / sec_mixed},
-        "kernels_ms": {"mixed": {k: avg_ms(st_mixed, k) for k in st_mixed},
-                       "fp64": {k: avg_ms(st_fp64, k) for k in st_fp64}},
-        "report": {"mixed": rep_mixed, "fp64": rep_fp64},
-        "roofline": roofline,
+        "dtype": "f64 residuals/cost/solve, f32 Jacobian",
+        "data": "synthetic (seeded DH robot, sum-of-sinusoid paths, noisy candidate plans; every request distinct)",
+        "config": {"workload": (f"serving stream: Poisson {args.rate:.0f} req/s for {args.steps} s "
+                                f"({summary['requests']} distinct requests, inputs resident in HBM), "
+                                f"T ~ U{{50..2000}}, K in {{128, 256, 512}}, {args.iters} LM iterations, "
+                                "continuous batching, mixed precision"),
+                   "rate_hz": args.rate, "duration_s": args.steps, "requests": summary["requests"],
+                   "lm_iters": args.iters, "slots": summary["slots"], "iters_per_tick": summary["iters_per_tick"],
+                   "parallelism": "single GPU"},
+        "latency_ms": {"p50": mo["p50_ms"], "p99": mo["p99_ms"], "max": mo["max_ms"]},
+        "offered_load": summary["offered_load"],
+        "saturation": summary["mixed_closed"],
+        "fp64_batched_closed": summary["fp64_closed"],
+        "fp64_one_at_a_time": summary["fp64_one_at_a_time_open"],
+        "speedup_vs_fp64_one_at_a_time": {"open_loop": summary["speedup_open"],
+                                          "saturation": summary["speedup_closed_vs_one_at_a_time"]},
+        "speedup_mixed_vs_fp64_batched": summary["speedup_mixed_vs_fp64_batched"],
+        "serving_kernels_ms": mo["kernels"],
+        "input_prep_s": summary["input_prep_s"],
+        "input_bytes_resident": summary["input_bytes_resident"],
     }
+    out["roofline"] = roofline_of(summary, raw, args.iters)
 
-    if not args.no_full_chip:
-        # The same request 256 times in one batch launch, one plan per
-        # compute unit: what the LM kernel does with the chip full, beside
-        # the single request of `value`, which leaves 255 compute units idle.
-        n_plans = 256
-        opts = cpf.make_opts(iters=iters)
-        items = [(prob.robot, prob.targets, prob.cand)] * n_plans
-        ctx.solve_batch(items[:8], opts)                          # warm-up
-        ctx.profile(True)
-        t0 = time.perf_counter()
-        res = ctx.solve_batch(items, opts)
-        t1 = time.perf_counter()
-        lm_b = ctx.kernel_stats("lm")[0]
-        dp_b = ctx.kernel_stats("dp")[0]
-        ctx.profile(False)
-        ach_b = LM_FLOPS_PER_WAYPOINT_ITER * T * iters * n_plans / (lm_b * 1e-3) / 1e12
-        # bytes past the L2 for the 256-plan launch (FETCH_SIZE + WRITE_SIZE,
-        # scaled by a copy of known size), from the committed counter summary
-        tr_b = measured_traffic("lm_kernel<float, false, false, false>", "hbm_traffic_full_chip_T300_K256.json")
-        gbs_b = tr_b / (lm_b * 1e-3) / 1e9 if tr_b else None
-        out["full_chip"] = {
-            "plans": n_plans, "lm_kernel_ms": lm_b, "search_ms": dp_b, "wall_ms": (t1 - t0) * 1e3,
-            "waypoint_lm_iters_per_s": T * iters * n_plans / (lm_b * 1e-3),
-            "lm_achieved_tflops": ach_b, "lm_frac": ach_b / PEAK_ALU_TFLOPS,
-            "lm_traffic": tr_b, "lm_traffic_GBps": gbs_b,
-            "lm_traffic_frac": gbs_b / PEAK_HBM_GBS if gbs_b else None,
-            "results_identical": bool(all(np.array_equal(r["xi"], res[0]["xi"]) for r in res)),
-            "note": "wall_ms includes uploading the 256 requests from host memory"}
-
-    if not args.no_serving:
-        # The serving half of the metric: the same seeded request stream
-        # (Poisson 200/s, T ~ U{50..2000}, K in {128, 256, 512}, 30 LM
-        # iterations) served by continuous batching in mixed precision and
-        # one request at a time by the all-FP64 path, open loop and as a
-        # closed-loop burst; latencies are submit -> result.
-        from paper_2309_09102_amd import workloads
-        sv = workloads.run_serve(duration_s=args.serving_seconds, burst=240,
-                                 fp64_budget_s=args.serving_seconds)
-        keep = ("throughput", "p50_ms", "p99_ms", "wall_s", "requests", "requests_served",
-                "requests_offered", "statuses")
-        out["serving"] = {k: ({kk: vv for kk, vv in v.items() if kk in keep} if isinstance(v, dict) else v)
-                          for k, v in sv.items()}
-
+    ctx_results = {}
+    if not args.no_context_legs:
+        context_legs(args, out, ctx_results)
     if not args.no_cpu_baseline:
-        import oracle
-        threads = 1
-        t0 = time.perf_counter()
-        n = 0
-        ref = None
-        while True:
-            ref = oracle.plan(prob.robot, prob.cand, prob.targets, iters)
-            n += 1
-            if time.perf_counter() - t0 >= args.cpu_seconds:
-                break
-        dt = (time.perf_counter() - t0) / n
-        out["cpu_baseline"] = {"value": work / dt, "unit": "waypoint-LM-iters/s", "cores": threads,
-                               "kind": "oracle",
-                               "sample": f"{n} full runs of the same request (search + {iters} LM "
-                                         f"iterations), FP64 C oracle, 1 thread, "
-                                         f"{platform.processor() or platform.machine()}"}
-        ep_m, er_m = oracle.pose_compare(prob.robot, xi_mixed, ref["xi"])
-        ep_d, er_d = oracle.pose_compare(prob.robot, xi_fp64, ref["xi"])
-        out["pose_err_vs_oracle"] = {"mixed": [ep_m, er_m], "fp64": [ep_d, er_d],
-                                     "unit": ["m", "rad"]}
-    ctx.close()
+        cb, pose = cpu_baseline_leg(args, summary, raw, ctx_results)
+        out["cpu_baseline"] = cb
+        out["pose_err_vs_oracle"] = pose
     print(json.dumps(out))
 
 

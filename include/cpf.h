@@ -385,8 +385,11 @@ cpf_status cpf_poll(cpf_ctx *ctx, uint64_t ticket, int32_t timeout_ms, cpf_resul
 /* Kernel timing (tracing aid for the benchmark): with profiling enabled the
  * context brackets each of its kernel launches with HIP events on the
  * stream the kernel runs on.  cpf_ctx_kernel_stats returns the summed
- * duration (ms) and launch count for kernel "fk", "dp", "lm" or "eval" since
- * profiling was enabled (it synchronises the context's streams). */
+ * duration (ms) and launch count since profiling was enabled (it
+ * synchronises the context's streams) for "fk" (cpf_fk_batch and
+ * cpf_coll_batch), "dp_lists" (the search's node penalties and predecessor
+ * lists), "dp" (its stage recursion, back-tracking and seed), "lm" (LM
+ * launches; in serving, each tick graph) or "eval" (the report). */
 cpf_status cpf_ctx_profile(cpf_ctx *ctx, int32_t enable);
 cpf_status cpf_ctx_kernel_stats(cpf_ctx *ctx, const char *kernel, double *total_ms,
                                 int64_t *launches);

@@ -275,7 +275,7 @@ def ctx_profile(ctx, enable: bool):
 
 
 def ctx_kernel_stats(ctx, kernel: str):
-    """(total ms, launches) of kernel 'fk' | 'dp' | 'lm' | 'eval' since profiling began."""
+    """(total ms, launches) of kernel 'fk' | 'dp_lists' | 'dp' | 'lm' | 'eval' since profiling began."""
     ms = C.c_double()
     n = C.c_int64()
     _check(_lib.cpf_ctx_kernel_stats(ctx, kernel.encode(), C.byref(ms), C.byref(n)))

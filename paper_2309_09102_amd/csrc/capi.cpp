@@ -244,6 +244,15 @@ cpf_status check_plan_robot(const HostRobot &hr) {
     return CPF_OK;
 }
 
+hipError_t search_launch(cpf_ctx *ctx, const DevPlan *d_plans, int nplans, int maxK, int maxT, bool lists_ready,
+                         bool coll, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    if (!lists_ready)
+        e = timed(ctx, KIND_DPL, s, [&] { return dp_lists_launch(d_plans, nplans, maxK, maxT, coll, s); });
+    if (e == hipSuccess) e = timed(ctx, KIND_DP, s, [&] { return dp_stages_launch(d_plans, nplans, maxK, s); });
+    return e;
+}
+
 hipError_t event_pair(cpf_ctx *ctx, hipEvent_t *a, hipEvent_t *b) {
     {
         std::lock_guard<std::mutex> lk(ctx->prof_mu);
@@ -693,11 +702,8 @@ cpf_status cpf_dp_search(cpf_plan *plan, int32_t *path_out, double *best_out, do
     if (!plan) return fail(CPF_E_ARG, "plan is NULL");
     cpf_ctx *ctx = plan->ctx;
     HIP_TRY(hipSetDevice(ctx->device));
-    HIP_TRY(timed(ctx, KIND_DP, ctx->stream,
-                  [&] {
-                      return dp_launch(plan->d_desc, 1, plan->K, plan->T, plan->lists_valid, plan->robot.has_caps,
-                                       ctx->stream);
-                  }));
+    HIP_TRY(search_launch(ctx, plan->d_desc, 1, plan->K, plan->T, plan->lists_valid, plan->robot.has_caps,
+                          ctx->stream));
     PlanReadback rb;
     cpf_status st = read_plan(plan, ctx->stream, nullptr, &rb, nullptr, path_out, nullptr);
     if (st != CPF_OK) return st;
@@ -790,7 +796,7 @@ cpf_status cpf_plan_append(cpf_plan *plan, int32_t K_add, const double *cand_add
                            hipMemcpyDeviceToDevice, s);
     // 3. penalties and lists of the new nodes; the old nodes' lists merged
     if (e == hipSuccess && merge)
-        e = timed(ctx, KIND_DP, s, [&] { return dp_append_launch(np->d_desc, K0, K2, T, plan->robot.has_caps, s); });
+        e = timed(ctx, KIND_DPL, s, [&] { return dp_append_launch(np->d_desc, K0, K2, T, plan->robot.has_caps, s); });
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         HIP_IGNORE(hipStreamSynchronize(s));
@@ -838,7 +844,7 @@ cpf_status cpf_plan_solve(cpf_plan *plan, int32_t *path_out, double *best_out, d
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
     const bool coll = plan->robot.has_caps;
-    HIP_TRY(timed(ctx, KIND_DP, s, [&] { return dp_launch(plan->d_desc, 1, plan->K, plan->T, false, coll, s); }));
+    HIP_TRY(search_launch(ctx, plan->d_desc, 1, plan->K, plan->T, false, coll, s));
     plan->lists_valid = true;
     HIP_TRY(timed(ctx, KIND_LM, s, [&] {
         return lm_launch(plan->d_desc, 1, plan->opts.prec, plan->opts.schedule, plan_geo(plan->robot), plan->opts.iters,
@@ -916,8 +922,7 @@ cpf_status cpf_solve_batch(cpf_ctx *ctx, int32_t nplans, const cpf_robot *robots
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     const int64_t t0 = now_ns();
     if (e == hipSuccess)
-        e = timed(ctx, KIND_DP, ctx->stream,
-                  [&] { return dp_launch(d_descs, nplans, maxK, maxT, false, kinds[GEO_COLL], ctx->stream); });
+        e = search_launch(ctx, d_descs, nplans, maxK, maxT, false, kinds[GEO_COLL], ctx->stream);
     if (e == hipSuccess)
         e = timed(ctx, KIND_LM, ctx->stream,
                   [&] {
@@ -1023,7 +1028,7 @@ cpf_status cpf_ctx_profile(cpf_ctx *ctx, int32_t enable) {
         ctx->ev_free.push_back(ev.b);
     }
     ctx->events.clear();
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < KIND_COUNT; ++i) {
         ctx->prof_ms[i] = 0;
         ctx->prof_n[i] = 0;
     }
@@ -1034,9 +1039,9 @@ cpf_status cpf_ctx_profile(cpf_ctx *ctx, int32_t enable) {
 cpf_status cpf_ctx_kernel_stats(cpf_ctx *ctx, const char *kernel, double *total_ms,
                                 int64_t *launches) {
     if (!ctx || !kernel) return fail(CPF_E_ARG, "ctx / kernel is NULL");
-    static const char *names[4] = {"fk", "dp", "lm", "eval"};
+    static const char *names[KIND_COUNT] = {"fk", "dp", "lm", "eval", "dp_lists"};
     int kind = -1;
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < KIND_COUNT; ++i)
         if (strcmp(kernel, names[i]) == 0) kind = i;
     if (kind < 0) return fail(CPF_E_ARG, "unknown kernel '%s'", kernel);
     std::lock_guard<std::mutex> lk(ctx->prof_mu);

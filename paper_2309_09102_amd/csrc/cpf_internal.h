@@ -48,12 +48,12 @@ hipError_t stage_append_launch(const double *raw, int T, int K_add, int K, int k
 // mjac of every candidate plan (max over steps and joints of the change
 // between consecutive waypoints), cand float [T][7][K] -> out double [K].
 hipError_t cand_mjac_launch(const float *cand, int T, int K, double *out, hipStream_t s);
-// Search + seed gather for nplans plans: the predecessor lists over the
-// whole GPU (unless lists_ready: the plans' lists are current; with coll,
-// after the nodes' collision penalties), then one workgroup per plan for the
-// stages.
-hipError_t dp_launch(const DevPlan *d_plans, int nplans, int maxK, int maxT, bool lists_ready, bool coll,
-                     hipStream_t s);
+// Search for nplans plans in two launches: the node penalties (with coll,
+// after the nodes' collision penalties) and predecessor lists over the whole
+// GPU, then the stage recursion, back-tracking and seed gather, one
+// workgroup per plan.
+hipError_t dp_lists_launch(const DevPlan *d_plans, int nplans, int maxK, int maxT, bool coll, hipStream_t s);
+hipError_t dp_stages_launch(const DevPlan *d_plans, int nplans, int maxK, hipStream_t s);
 // Penalties and predecessor lists of one plan after candidates K_old..K-1
 // were appended (the old nodes' penalties and lists already copied in).
 hipError_t dp_append_launch(const DevPlan *d_plan, int K_old, int K, int T, bool coll, hipStream_t s);

@@ -513,21 +513,22 @@ __global__ __launch_bounds__(BS) void dp_kernel(const DevPlan *__restrict__ plan
 #undef DP_MARK
 }
 
-hipError_t dp_launch(const DevPlan *d_plans, int nplans, int maxK, int maxT, bool lists_ready, bool coll,
-                     hipStream_t s) {
+hipError_t dp_lists_launch(const DevPlan *d_plans, int nplans, int maxK, int maxT, bool coll, hipStream_t s) {
     if (nplans <= 0 || maxT <= 0 || maxK <= 0) return hipSuccess;
     if (maxK > MAX_K) return hipErrorInvalidValue;
-    if (!lists_ready) {
-        if (coll) {
-            const hipError_t e = node_coll_launch(d_plans, nplans, maxK, maxT, 0, s);
-            if (e != hipSuccess) return e;
-        }
-        const int nkb = (maxK + TOPM_BS - 1) / TOPM_BS;
-        const dim3 grid((unsigned)(maxT * nkb), (unsigned)nplans);
-        hipLaunchKernelGGL(dp_topm_kernel, grid, dim3(TOPM_BS), (size_t)maxK * NJ * sizeof(float), s, d_plans);
-        const hipError_t e = hipGetLastError();
+    if (coll) {
+        const hipError_t e = node_coll_launch(d_plans, nplans, maxK, maxT, 0, s);
         if (e != hipSuccess) return e;
     }
+    const int nkb = (maxK + TOPM_BS - 1) / TOPM_BS;
+    const dim3 grid((unsigned)(maxT * nkb), (unsigned)nplans);
+    hipLaunchKernelGGL(dp_topm_kernel, grid, dim3(TOPM_BS), (size_t)maxK * NJ * sizeof(float), s, d_plans);
+    return hipGetLastError();
+}
+
+hipError_t dp_stages_launch(const DevPlan *d_plans, int nplans, int maxK, hipStream_t s) {
+    if (nplans <= 0 || maxK <= 0) return hipSuccess;
+    if (maxK > MAX_K) return hipErrorInvalidValue;
     // one lane per destination, whole wavefronts (the seed reduction needs a power of two)
     int bs = 64;
     while (bs < maxK) bs <<= 1;

@@ -55,7 +55,7 @@ cpf_status check_plan_robot(const HostRobot &hr);
 cpf_status check_problem(const cpf_problem *p);
 cpf_status check_opts(const cpf_opts *o);
 
-enum { KIND_FK = 0, KIND_DP = 1, KIND_LM = 2, KIND_EVAL = 3 };
+enum { KIND_FK = 0, KIND_DP = 1, KIND_LM = 2, KIND_EVAL = 3, KIND_DPL = 4, KIND_COUNT = 5 };
 
 struct Request;
 struct Server;
@@ -98,8 +98,8 @@ struct cpf_ctx {
     };
     std::vector<Ev> events;
     std::vector<hipEvent_t> ev_free;   // created events ready for reuse (no create in a timed launch)
-    double prof_ms[4] = {0, 0, 0, 0};
-    int64_t prof_n[4] = {0, 0, 0, 0};
+    double prof_ms[cpf::KIND_COUNT] = {};
+    int64_t prof_n[cpf::KIND_COUNT] = {};
 
 };
 
@@ -139,6 +139,12 @@ hipError_t timed(cpf_ctx *ctx, int kind, hipStream_t s, F &&launch) {
     ctx->events.push_back({kind, a, b});
     return e;
 }
+
+// The search of nplans plans on s, each launch timed: the lists (unless
+// lists_ready: the plans' lists are current) as "dp_lists", the stages as
+// "dp".
+hipError_t search_launch(cpf_ctx *ctx, const DevPlan *d_plans, int nplans, int maxK, int maxT, bool lists_ready,
+                         bool coll, hipStream_t s);
 
 // Arena of `cls` bytes from the pool (or a new allocation within the
 // budget); E_NOMEM when the budget does not allow it.

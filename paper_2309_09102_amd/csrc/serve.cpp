@@ -276,7 +276,7 @@ int admit(cpf_ctx *ctx, Server *sv, int free_slots) {
     hipError_t e = hipMemcpyAsync(sv->d_new, sv->h_new.data(), sizeof(DevPlan) * batch.size(),
                                   hipMemcpyHostToDevice, sv->s_up);
     if (e == hipSuccess)
-        e = timed(ctx, KIND_DP, sv->s_up, [&] { return dp_launch(sv->d_new, (int)batch.size(), maxK, maxT, false, any_coll, sv->s_up); });
+        e = search_launch(ctx, sv->d_new, (int)batch.size(), maxK, maxT, false, any_coll, sv->s_up);
     if (e == hipSuccess) e = hipEventRecord(sv->searched, sv->s_up);
     if (e != hipSuccess) {
         HIP_IGNORE(hipStreamSynchronize(sv->s_up));

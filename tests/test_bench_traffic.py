@@ -18,7 +18,7 @@ def test_summary_matches_recorded_bytes_or_is_stale(summary):
     assert k["bytes_per_launch"] > 0
     got = bench.measured_traffic(KERNEL, summary)
     if k["sources_sha"] == bench.kernel_sources_sha(k["sources"]):
-        assert got == k["bytes_per_launch"]
+        assert got is not None and got["bytes_per_launch"] == k["bytes_per_launch"]
     else:
         assert got is None
 
