@@ -334,6 +334,25 @@ cpf_status cpf_lm_refine(cpf_plan *plan, int32_t iters, double *xi_out, cpf_lm_r
 cpf_status cpf_plan_solve(cpf_plan *plan, int32_t *path_out, double *best_out, double *xi_out,
                           cpf_lm_report *rep);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the work
+ * of cpf_plan_init + cpf_plan_solve + cpf_plan_free in one call (the search,
+ * then opts->iters LM iterations and the report; inputs as cpf_problem
+ * describes, host or device) with every device buffer in a static array of
+ * 64 MiB that the library holds on each GPU it runs on until the process
+ * ends.  No hipMalloc, hipFree or other allocating call is made.  A problem
+ * whose working memory (the arena of a plan of that T and K: about
+ * 198 K + 4.4 KB bytes per waypoint, e.g. 16.5 MB for T = 300, K = 256, so
+ * up to T of about 1200 at K = 256) exceeds 64 MiB returns CPF_E_NOMEM with
+ * the sizes in the message.  path_out [T], best_out,
+ * xi_out [T][dof] (host) and rep may each be NULL.  Calls on one GPU share
+ * its array: the library runs them one after another (a per-device lock),
+ * and each call starts by clearing the state it needs, so nothing carries
+ * over from the previous one.  Synchronous, on the context's stream;
+ * statuses as cpf_plan_init and cpf_plan_solve. */
+cpf_status cpf_solve_static(cpf_ctx *ctx, const cpf_robot *robot, const cpf_problem *prob, const cpf_opts *opts,
+                            int32_t *path_out, double *best_out, double *xi_out, cpf_lm_report *rep);
+
 /* Latest valid trajectory of a plan refined with opts.schedule = 1 (the
  * anytime result of Sec. III-C's alternating objective), written to xi_out
  * [T][dof] (caller-owned, not NULL).  CPF_E_STATE if the plan does not use

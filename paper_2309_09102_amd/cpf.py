@@ -100,6 +100,8 @@ _lib.cpf_dp_seed_steps.argtypes = [_vp, _dp, _dp]
 _lib.cpf_dp_needs_research.argtypes = [_vp, _ip]
 _lib.cpf_lm_refine.argtypes = [_vp, C.c_int32, _dp, C.POINTER(cpf_lm_report)]
 _lib.cpf_lm_latest_valid.argtypes = [_vp, _dp]
+_lib.cpf_solve_static.argtypes = [_vp, C.POINTER(cpf_robot), C.POINTER(cpf_problem), C.POINTER(cpf_opts), _ip, _dp,
+                                  _dp, C.POINTER(cpf_lm_report)]
 _lib.cpf_plan_solve.argtypes = [_vp, _ip, _dp, _dp, C.POINTER(cpf_lm_report)]
 _lib.cpf_plan_append.argtypes = [_vp, C.c_int32, _dp, _dp]
 _lib.cpf_coll_batch.argtypes = [_vp, C.POINTER(cpf_robot), C.c_int32, _vp, C.c_int64, C.c_int32, _vp, _vp,
@@ -119,14 +121,14 @@ for _f in ("cpf_ctx_create", "cpf_plan_init", "cpf_fk_batch", "cpf_dp_search", "
            "cpf_dp_needs_research", "cpf_lm_refine",
            "cpf_lm_latest_valid", "cpf_plan_append", "cpf_coll_batch", "cpf_plan_solve",
            "cpf_solve_batch", "cpf_batchopt", "cpf_submit", "cpf_poll", "cpf_ctx_profile",
-           "cpf_ctx_kernel_stats", "cpf_ctx_config"):
+           "cpf_ctx_kernel_stats", "cpf_ctx_config", "cpf_solve_static"):
     getattr(_lib, _f).restype = C.c_int
 
 EXPORTS = ("cpf_opts_default", "cpf_last_error", "cpf_ctx_create", "cpf_ctx_destroy",
            "cpf_ctx_bytes_in_use", "cpf_plan_init", "cpf_plan_free", "cpf_fk_batch", "cpf_coll_batch",
            "cpf_dp_search", "cpf_dp_seed_steps", "cpf_dp_needs_research", "cpf_plan_append", "cpf_lm_refine", "cpf_plan_solve", "cpf_lm_latest_valid",
            "cpf_solve_batch", "cpf_batchopt", "cpf_submit", "cpf_poll", "cpf_ctx_profile",
-           "cpf_ctx_kernel_stats", "cpf_ctx_config")
+           "cpf_ctx_kernel_stats", "cpf_ctx_config", "cpf_solve_static")
 
 
 def last_error() -> str:
@@ -367,6 +369,25 @@ def plan_solve(plan, T: int, want_xi: bool = True):
     return path, best.value, xi, _report(rep)
 
 
+def solve_static(ctx, robot, targets, cand, opts=None, node_pen=None, coll=None):
+    """cpf_solve_static: search + opts.iters LM iterations + report in the
+    library's static device scratch (no device allocation) -> (path, B*, xi,
+    report)."""
+    rb = make_robot(robot, coll)
+    pb = make_problem(targets, cand, node_pen, coll)
+    o = _with_coll(opts, coll)
+    T = pb.struct.T
+    path = np.empty(T, dtype=np.int32)
+    best = C.c_double()
+    xi = np.empty((T, 7))
+    rep = cpf_lm_report()
+    st = _lib.cpf_solve_static(ctx, C.byref(rb.struct), C.byref(pb.struct), C.byref(o), path.ctypes.data_as(_ip),
+                               C.byref(best), _ptr(xi), C.byref(rep))
+    if st != OK:
+        raise CpfError(st, last_error())
+    return path, best.value, xi, _report(rep)
+
+
 def lm_latest_valid(plan, T: int):
     """Latest valid trajectory [T][7] of a plan refined under the schedule
     (raises CpfError E_STATE when there is none yet or no schedule)."""
@@ -532,6 +553,9 @@ class Context:
 
     def batchopt(self, robot, targets, cand, M: int, opts=None, node_pen=None, coll=None):
         return batchopt(self.h, robot, targets, cand, M, opts, node_pen, coll)
+
+    def solve_static(self, robot, targets, cand, opts=None, node_pen=None, coll=None):
+        return solve_static(self.h, robot, targets, cand, opts, node_pen, coll)
 
     def submit(self, robot, targets, cand, opts=None, node_pen=None, coll=None) -> int:
         return submit(self.h, robot, targets, cand, opts, node_pen, coll)

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <thread>
 
 #include "runtime.h"
@@ -21,6 +22,30 @@ namespace cpf {
 
 namespace {
 thread_local std::string g_err;
+}
+
+// Working memory of cpf_solve_static: one plan arena in a static device
+// array, so that the call needs no device allocation.  Host code reaches it
+// only through the address hipGetSymbolAddress returns for the current
+// device (set up by cpf_ctx_create; the array's name is a host stand-in).
+constexpr uint64_t SCRATCH_BYTES = (uint64_t)64 << 20;
+constexpr int MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+static void *g_scratch_ptr[MAX_DEVICES];
+static std::mutex g_scratch_mu[MAX_DEVICES];   // one call at a time per device
+
+// Address of this device's copy of the static scratch, looked up once per
+// device with that device current.
+static cpf_status scratch_setup(int device) {
+    if (device < 0 || device >= MAX_DEVICES) return fail(CPF_E_UNSUPPORTED, "device %d beyond %d", device, MAX_DEVICES);
+    std::lock_guard<std::mutex> lk(g_scratch_mu[device]);
+    if (g_scratch_ptr[device]) return CPF_OK;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(CPF_E_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
+    g_scratch_ptr[device] = ptr;
+    return CPF_OK;
 }
 
 cpf_status fail(cpf_status st, const char *fmt, ...) {
@@ -402,6 +427,30 @@ static void fill_desc(cpf_plan *p, bool has_extra) {
 
 // A plan of T waypoints and K candidates with an arena from the pool, its
 // descriptor and initial LM state uploaded on s; no problem data yet.
+// Fill a plan's host fields and descriptor for an arena already in p->arena
+// and queue the descriptor, the initial LM state and the cleared input flag
+// on s.
+static hipError_t plan_setup(cpf_plan *p, cpf_ctx *ctx, const HostRobot &hr, int T, int K, bool has_extra, int n_obs,
+                             const cpf_opts *opts, int32_t iters_target, hipStream_t s) {
+    p->ctx = ctx;
+    p->T = T;
+    p->K = K;
+    p->n_obs = n_obs;
+    p->robot = hr;
+    p->opts = *opts;
+    p->L = make_layout(T, K, has_extra, n_obs, hr.has_caps);
+    p->d_desc = (DevPlan *)(p->arena + p->L.total);
+    fill_desc(p, has_extra);
+    p->init = LMState{};
+    p->init.lambda = opts->lambda0;
+    p->init.nu = 2.0;
+    p->init.iters_target = iters_target;
+    hipError_t e = hipMemcpyAsync(p->arena + p->L.st, &p->init, sizeof(LMState), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(p->d_desc, &p->desc, sizeof(DevPlan), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(input_flag(p), 0, sizeof(int), s);
+    return e;
+}
+
 cpf_status plan_alloc(cpf_ctx *ctx, const HostRobot &hr, int T, int K, bool has_extra, int n_obs,
                       const cpf_opts *opts, int32_t iters_target, hipStream_t s, cpf_plan **out) {
     const uint64_t cls = plan_class_bytes(T, K, has_extra, n_obs, hr.has_caps);
@@ -409,23 +458,9 @@ cpf_status plan_alloc(cpf_ctx *ctx, const HostRobot &hr, int T, int K, bool has_
     cpf_status st = arena_get(ctx, cls, &mem);
     if (st != CPF_OK) return st;
     std::unique_ptr<cpf_plan> p(new cpf_plan());
-    p->ctx = ctx;
-    p->T = T;
-    p->K = K;
-    p->n_obs = n_obs;
-    p->robot = hr;
-    p->opts = *opts;
     p->bytes = cls;
-    p->L = make_layout(T, K, has_extra, n_obs, hr.has_caps);
     p->arena = (char *)mem;
-    p->d_desc = (DevPlan *)(p->arena + p->L.total);
-    fill_desc(p.get(), has_extra);
-    p->init.lambda = opts->lambda0;
-    p->init.nu = 2.0;
-    p->init.iters_target = iters_target;
-    hipError_t e = hipMemcpyAsync(p->arena + p->L.st, &p->init, sizeof(LMState), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(p->d_desc, &p->desc, sizeof(DevPlan), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemsetAsync(input_flag(p.get()), 0, sizeof(int), s);
+    const hipError_t e = plan_setup(p.get(), ctx, hr, T, K, has_extra, n_obs, opts, iters_target, s);
     if (e != hipSuccess) {
         HIP_IGNORE(hipStreamSynchronize(s));
         arena_put(ctx, mem, cls);
@@ -435,16 +470,12 @@ cpf_status plan_alloc(cpf_ctx *ctx, const HostRobot &hr, int T, int K, bool has_
     return CPF_OK;
 }
 
-cpf_status plan_create(cpf_ctx *ctx, const HostRobot &hr, const cpf_problem *prob,
-                       const cpf_opts *opts, int32_t iters_target, hipStream_t s, cpf_plan **out) {
-    const bool has_extra = prob->node_pen != nullptr;
-    cpf_plan *p = nullptr;
-    cpf_status st = plan_alloc(ctx, hr, prob->T, prob->K, has_extra, prob->n_obstacles, opts, iters_target, s, &p);
-    if (st != CPF_OK) return st;
-
-    // Host arrays go up as they are into the upload region; a kernel converts
-    // them (or device-resident ones in place) into the device layout
-    // (candidates to float, joint-major; targets component-major).
+// Queue the problem's inputs into a set-up plan on s: host arrays go up as
+// they are into the upload region and a kernel converts them (or
+// device-resident ones in place) into the device layout (candidates to
+// float, joint-major; targets component-major); node costs and obstacles
+// are copied.
+static hipError_t plan_upload(cpf_plan *p, const cpf_problem *prob, hipStream_t s) {
     const int T = p->T, K = p->K;
     const size_t n_cand = (size_t)T * K * NJ;
     const bool f32 = prob->mem == CPF_MEM_DEVICE || prob->cand_f32 != nullptr;
@@ -452,7 +483,7 @@ cpf_status plan_create(cpf_ctx *ctx, const HostRobot &hr, const cpf_problem *pro
     const double *tin = nullptr;
     int *bad = nullptr;
     hipError_t e = hipSuccess;
-    if (prob->mem == CPF_MEM_DEVICE) {   // checked on the device (the flag was cleared by plan_alloc)
+    if (prob->mem == CPF_MEM_DEVICE) {   // checked on the device (the flag was cleared by plan_setup)
         cin = prob->cand_f32;
         tin = prob->targets;
         bad = input_flag(p);
@@ -469,12 +500,22 @@ cpf_status plan_create(cpf_ctx *ctx, const HostRobot &hr, const cpf_problem *pro
     if (e == hipSuccess)
         e = stage_launch(cin, f32, tin, T, K, (float *)(p->arena + p->L.cand), (double *)(p->arena + p->L.targets),
                          bad, s);
-    if (e == hipSuccess && has_extra)
+    if (e == hipSuccess && prob->node_pen)
         e = hipMemcpyAsync(p->arena + p->L.extra, prob->node_pen, (size_t)T * K * sizeof(double),
                            hipMemcpyHostToDevice, s);
     if (e == hipSuccess && prob->n_obstacles > 0)
         e = hipMemcpyAsync(p->arena + p->L.obs, prob->obstacles, (size_t)prob->n_obstacles * 18 * sizeof(double),
                            hipMemcpyHostToDevice, s);
+    return e;
+}
+
+cpf_status plan_create(cpf_ctx *ctx, const HostRobot &hr, const cpf_problem *prob,
+                       const cpf_opts *opts, int32_t iters_target, hipStream_t s, cpf_plan **out) {
+    cpf_plan *p = nullptr;
+    cpf_status st = plan_alloc(ctx, hr, prob->T, prob->K, prob->node_pen != nullptr, prob->n_obstacles, opts,
+                               iters_target, s, &p);
+    if (st != CPF_OK) return st;
+    const hipError_t e = plan_upload(p, prob, s);
     if (e != hipSuccess) {
         HIP_IGNORE(hipStreamSynchronize(s));
         plan_destroy(p);
@@ -594,6 +635,8 @@ cpf_status cpf_ctx_create(int device, uint64_t mem_budget_bytes, cpf_ctx **out) 
     HIP_TRY(hipGetDeviceCount(&n));
     if (device < 0 || device >= n) return fail(CPF_E_ARG, "device %d of %d", device, n);
     HIP_TRY(hipSetDevice(device));
+    cpf_status st = scratch_setup(device);
+    if (st != CPF_OK) return st;
     std::unique_ptr<cpf_ctx> c(new cpf_ctx());
     c->device = device;
     c->budget = mem_budget_bytes ? mem_budget_bytes : (uint64_t)64 << 30;
@@ -860,6 +903,67 @@ cpf_status cpf_plan_solve(cpf_plan *plan, int32_t *path_out, double *best_out, d
     if (best_out) *best_out = rb.dp_out[0];
     if (rep) fill_report(rb, rep);
     if (rb.st.status != 0) return fail(CPF_E_NUMERIC, "non-positive pivot in the block solve");
+    return CPF_OK;
+}
+
+cpf_status cpf_solve_static(cpf_ctx *ctx, const cpf_robot *robot, const cpf_problem *prob, const cpf_opts *opts,
+                            int32_t *path_out, double *best_out, double *xi_out, cpf_lm_report *rep) {
+    if (!ctx) return fail(CPF_E_ARG, "ctx is NULL");
+    HostRobot hr;
+    cpf_status st;
+    if ((st = check_robot(robot, &hr)) != CPF_OK) return st;
+    if ((st = check_plan_robot(hr)) != CPF_OK) return st;
+    if ((st = check_problem(prob)) != CPF_OK) return st;
+    cpf_opts o;
+    cpf_opts_default(&o);
+    if (opts) o = *opts;
+    if ((st = check_opts(&o)) != CPF_OK) return st;
+    const int T = prob->T, K = prob->K;
+    const bool has_extra = prob->node_pen != nullptr;
+    const Layout L = make_layout(T, K, has_extra, prob->n_obstacles, hr.has_caps);
+    const uint64_t need = L.total + align256(sizeof(DevPlan));
+    if (need > SCRATCH_BYTES)
+        return fail(CPF_E_NOMEM, "T=%d K=%d needs %llu bytes of working memory; the static scratch holds %llu", T, K,
+                    (unsigned long long)need, (unsigned long long)SCRATCH_BYTES);
+    char head[1024];   // LM state, report, search output: the arena's first bytes
+    if (L.path > sizeof(head)) return fail(CPF_E_STATE, "arena head of %zu bytes", L.path);
+    HIP_TRY(hipSetDevice(ctx->device));
+    std::lock_guard<std::mutex> lk(g_scratch_mu[ctx->device]);
+    char *base = (char *)g_scratch_ptr[ctx->device];
+    if (!base) return fail(CPF_E_STATE, "no static scratch on device %d", ctx->device);
+    cpf_plan p;   // on the stack, its arena the device's scratch
+    p.arena = base;
+    hipStream_t s = ctx->stream;
+    const bool coll = hr.has_caps;
+    const int geo = plan_geo(hr);
+    hipError_t e = plan_setup(&p, ctx, hr, T, K, has_extra, prob->n_obstacles, &o, 0, s);
+    if (e == hipSuccess) e = plan_upload(&p, prob, s);
+    if (e == hipSuccess) e = dp_lists_launch(p.d_desc, 1, K, T, coll, s);
+    if (e == hipSuccess) e = dp_stages_launch(p.d_desc, 1, K, s);
+    if (e == hipSuccess) e = lm_launch(p.d_desc, 1, o.prec, o.schedule, geo, o.iters, s);
+    if (e == hipSuccess) e = eval_launch(p.d_desc, 1, 0, geo, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(head, base, L.path, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && path_out)
+        e = hipMemcpyAsync(path_out, base + L.path, (size_t)T * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && xi_out) {   // rows [T][7] into the trial-point area, then straight to the caller
+        e = soa_rows_launch((const double *)(base + L.xi), T, (double *)(base + L.xt), s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(xi_out, base + L.xt, (size_t)T * NJ * sizeof(double), hipMemcpyDeviceToHost, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        HIP_IGNORE(hipStreamSynchronize(s));
+        return fail(CPF_E_DEVICE, "static solve: %s", hipGetErrorString(e));
+    }
+    LMState ls;
+    double report[8], dp_out[8];
+    memcpy(&ls, head + L.st, sizeof(ls));
+    memcpy(report, head + L.report, sizeof(report));
+    memcpy(dp_out, head + L.dp_out, sizeof(dp_out));
+    if (input_flag_set(report)) return fail(CPF_E_ARG, "a device-resident target or candidate value is not finite");
+    if (best_out) *best_out = dp_out[0];
+    if (rep) report_from(ls, report, rep);
+    if (ls.status != 0) return fail(CPF_E_NUMERIC, "non-positive pivot in the block solve");
     return CPF_OK;
 }
 

@@ -66,4 +66,7 @@ hipError_t lm_launch(const DevPlan *d_plans, int nplans, int prec, int sched, in
 // and have not been reported yet.
 hipError_t eval_launch(const DevPlan *d_plans, int nplans, int only_finished, int geo, hipStream_t s);
 
+// Trajectory [7][T] (device) into rows [T][7] (device).
+hipError_t soa_rows_launch(const double *soa, int T, double *rows, hipStream_t s);
+
 }  // namespace cpf

@@ -202,4 +202,21 @@ hipError_t stage_launch(const void *cand_in, bool cand_f32, const double *tg_in,
     return hipGetLastError();
 }
 
+// A [7][T] trajectory (one row per joint) into [T][7] rows, one thread per
+// element of the output.
+__global__ __launch_bounds__(256) void soa_rows_kernel(const double *__restrict__ soa, int T,
+                                                       double *__restrict__ rows) {
+    const long long x = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (x >= (long long)T * NJ) return;
+    const int t = (int)(x / NJ), j = (int)(x % NJ);
+    rows[x] = soa[(size_t)j * T + t];
+}
+
+hipError_t soa_rows_launch(const double *soa, int T, double *rows, hipStream_t s) {
+    const long long n = (long long)T * NJ;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(soa_rows_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, soa, T, rows);
+    return hipGetLastError();
+}
+
 }  // namespace cpf
