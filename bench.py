@@ -68,6 +68,9 @@ def parse():
     ap.add_argument("--fp64-budget", type=float, default=None,
                     help="seconds after which the one-at-a-time FP64 arm starts no further request "
                          "(default: the timed stream's length)")
+    ap.add_argument("--open-loop-only", action="store_true",
+                    help="serve only the mixed open-loop stream (for counter runs: every search and LM "
+                         "dispatch then belongs to the warm-up and timed requests)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-context-legs", action="store_true",
                     help="skip the single-request, chip-full and 64-problem legs")
@@ -402,8 +405,11 @@ def main():
 
     summary, raw = workloads.run_serve(duration_s=float(args.steps), warmup_s=float(args.warmup),
                                        rate_hz=args.rate, iters=args.iters, fp64_budget_s=args.fp64_budget,
-                                       keep_xi="sample")
+                                       keep_xi="sample", open_loop_only=args.open_loop_only)
     mo = summary["mixed_open"]
+    if args.open_loop_only:
+        print(json.dumps({"open_loop_only": True, "summary": summary, "roofline": roofline_of(summary, raw, args.iters)}))
+        return
     out = {
         "metric": "waypoint-LM-iters/sec",
         "value": mo["throughput"],

@@ -427,6 +427,36 @@ static void fill_desc(cpf_plan *p, bool has_extra) {
 
 // A plan of T waypoints and K candidates with an arena from the pool, its
 // descriptor and initial LM state uploaded on s; no problem data yet.
+// Every array the descriptor points at lies inside the plan's arena, at its
+// layout offset, with the extent its shape needs (recomputed here from T, K,
+// the obstacle count and the flags, independently of make_layout's
+// arithmetic), and the descriptor itself sits after the last array.
+static bool desc_in_arena(const cpf_plan *p, bool has_extra) {
+    const char *a = p->arena;
+    const size_t end = p->L.total;
+    const size_t t = (size_t)p->T, k = (size_t)p->K, d = sizeof(double);
+    const DevPlan &D = p->desc;
+    struct Span { const void *ptr; size_t bytes; };
+    const Span spans[] = {
+        {(const void *)D.cand, t * k * NJ * sizeof(float)}, {(const void *)D.pen, t * k * d},
+        {(const void *)D.bp, t * k * sizeof(uint16_t)}, {(const void *)D.topk, t * k * TOPM * sizeof(uint16_t)},
+        {(const void *)D.topc, t * k * TOPM * d}, {(const void *)D.path, t * sizeof(int32_t)},
+        {(const void *)D.dp_out, 8 * d}, {(const void *)D.targets, 12 * t * d}, {(const void *)D.xi, NJ * t * d},
+        {(const void *)D.xt, NJ * t * d}, {(const void *)D.A, NBLK * t * d}, {(const void *)D.g, NJ * t * d},
+        {(const void *)D.cr, cr_doubles(p->T) * d}, {(const void *)D.dx, NJ * t * d},
+        {(const void *)D.rb, NJ * t * d}, {(const void *)D.st, sizeof(LMState)}, {(const void *)D.report, 8 * d},
+        {(const void *)D.xv, NJ * t * d}, {(const void *)D.rr, RROWS * t * d}, {(const void *)D.rt, RROWS * t * d},
+        {(const void *)D.obs, (size_t)p->n_obs * 18 * d},
+        {(const void *)D.cpen, p->robot.has_caps ? t * k * d : 0},
+        {(const void *)D.extra, has_extra ? t * k * d : 0}};
+    for (const Span &sp : spans) {
+        if (sp.bytes == 0) continue;
+        const char *q = (const char *)sp.ptr;
+        if (q < a || q + sp.bytes > a + end) return false;
+    }
+    return (const char *)p->d_desc >= a + end;
+}
+
 // Fill a plan's host fields and descriptor for an arena already in p->arena
 // and queue the descriptor, the initial LM state and the cleared input flag
 // on s.
@@ -441,6 +471,7 @@ static hipError_t plan_setup(cpf_plan *p, cpf_ctx *ctx, const HostRobot &hr, int
     p->L = make_layout(T, K, has_extra, n_obs, hr.has_caps);
     p->d_desc = (DevPlan *)(p->arena + p->L.total);
     fill_desc(p, has_extra);
+    if (!desc_in_arena(p, has_extra)) return hipErrorInvalidValue;   // a layout mistake, caught on the host
     p->init = LMState{};
     p->init.lambda = opts->lambda0;
     p->init.nu = 2.0;

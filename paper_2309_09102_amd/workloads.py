@@ -467,7 +467,7 @@ def _summary(res, reqs, iters):
 
 
 def run_serve(duration_s=10.0, warmup_s=2.0, rate_hz=200.0, iters=30, slots=256, ipt=10,
-              fp64_budget_s=None, keep_xi=(), stats=None):
+              fp64_budget_s=None, keep_xi=(), open_loop_only=False):
     """The serving comparison on distinct device-resident requests: the
     arrival schedule's first warmup_s seconds are served untimed, the next
     duration_s seconds are the timed stream.  Returns the summary and the raw
@@ -498,6 +498,9 @@ def run_serve(duration_s=10.0, warmup_s=2.0, rate_hz=200.0, iters=30, slots=256,
            "requests": len(timed), "warmup_requests": len(warm), "lm_iters": iters, "slots": slots,
            "iters_per_tick": ipt, "unit": "waypoint-LM-iters/s", "waypoint_lm_iters": work,
            "offered_load": work / duration_s, "input_prep_s": t_gen,
+           "warmup_waypoint_lm_iters": sum(r.T for r in warm) * iters,
+           "search_pairs": sum((r.T - 1) * r.K * r.K for r in timed),
+           "warmup_search_pairs": sum((r.T - 1) * r.K * r.K for r in warm),
            "input_bytes_resident": int(sum(r.cand.numel() * 4 + r.targets.numel() * 8 for r in reqs))}
 
     def kstats(ctx):
@@ -515,6 +518,10 @@ def run_serve(duration_s=10.0, warmup_s=2.0, rate_hz=200.0, iters=30, slots=256,
     out["mixed_open"] = _summary(res, timed, iters)
     out["mixed_open"]["kernels"] = {k: {"ms": v[0], "launches": v[1]} for k, v in ks.items()}
     raw["mixed_open"] = res
+    raw["timed"] = [(r.i, r.T, r.K) for r in timed]
+    if open_loop_only:
+        ctx.close()
+        return out, raw
     ctx.profile(True)
     res = serve_stream(ctx, timed, None, o_mix)
     ks = kstats(ctx)
@@ -557,7 +564,6 @@ def run_serve(duration_s=10.0, warmup_s=2.0, rate_hz=200.0, iters=30, slots=256,
     out["speedup_closed_vs_one_at_a_time"] = (out["mixed_closed"]["throughput"] /
                                               out["fp64_one_at_a_time_open"]["throughput"])
     out["speedup_mixed_vs_fp64_batched"] = out["mixed_closed"]["throughput"] / out["fp64_closed"]["throughput"]
-    raw["timed"] = [(r.i, r.T, r.K) for r in timed]
     del reqs, warm, timed
     torch.cuda.empty_cache()
     return out, raw

@@ -7,37 +7,41 @@ import pytest
 
 import bench
 
-SUMMARIES = ["hbm_traffic_T300_K256.json", "hbm_traffic_full_chip_T300_K256.json"]
-KERNEL = "lm_kernel<float, false, false, false>"
+SUMMARY = "hbm_traffic_serving.json"
+KEYS = ["serving:lm", "serving:dp_lists"]
 
 
-@pytest.mark.parametrize("summary", SUMMARIES)
-def test_summary_matches_recorded_bytes_or_is_stale(summary):
-    rec = json.load(open(os.path.join(bench.ROOT, "profiles", summary)))
-    k = rec["kernels"][KERNEL]
-    assert k["bytes_per_launch"] > 0
-    got = bench.measured_traffic(KERNEL, summary)
+@pytest.mark.parametrize("key", KEYS)
+def test_summary_matches_recorded_bytes_or_is_stale(key):
+    rec = json.load(open(os.path.join(bench.ROOT, "profiles", SUMMARY)))
+    k = rec["kernels"][key]
+    assert k["bytes_per_unit"] > 0 and k["units"] > 0
+    got = bench.measured_traffic(key, SUMMARY)
     if k["sources_sha"] == bench.kernel_sources_sha(k["sources"]):
-        assert got is not None and got["bytes_per_launch"] == k["bytes_per_launch"]
+        assert got is not None and got["bytes_per_unit"] == k["bytes_per_unit"]
     else:
         assert got is None
 
 
-@pytest.mark.parametrize("summary", SUMMARIES)
-def test_changed_sources_drop_the_figure(summary, monkeypatch):
+@pytest.mark.parametrize("key", KEYS)
+def test_changed_sources_drop_the_figure(key, monkeypatch):
     monkeypatch.setattr(bench, "kernel_sources_sha", lambda files: "0" * 16)
-    assert bench.measured_traffic(KERNEL, summary) is None
+    assert bench.measured_traffic(key, SUMMARY) is None
 
 
 def test_missing_summary_or_kernel_gives_none():
-    assert bench.measured_traffic(KERNEL, "no_such_summary.json") is None
-    assert bench.measured_traffic("no_such_kernel", SUMMARIES[0]) is None
+    assert bench.measured_traffic(KEYS[0], "no_such_summary.json") is None
+    assert bench.measured_traffic("no_such_kernel", SUMMARY) is None
 
 
-def test_full_chip_traffic_exceeds_single_plan():
-    # 256 plans cannot move fewer bytes than one; the counters gave about 70x
-    # more per plan once the factors no longer fit in the L2
-    one = json.load(open(os.path.join(bench.ROOT, "profiles", SUMMARIES[0])))["kernels"][KERNEL]
-    full = json.load(open(os.path.join(bench.ROOT, "profiles", SUMMARIES[1])))["kernels"][KERNEL]
-    assert full["plans"] == 256
-    assert full["bytes_per_launch"] / full["plans"] >= one["bytes_per_launch"]
+def test_recorded_bytes_follow_from_the_counters():
+    """bytes per unit = (FETCH_SIZE x fetch scale + WRITE_SIZE x write scale)
+    KiB x 1024 / units, with the scales from the copy calibration (a copy's
+    FETCH_SIZE reads half the bytes it moves)."""
+    rec = json.load(open(os.path.join(bench.ROOT, "profiles", SUMMARY)))
+    assert rec["fetch_scale"] == pytest.approx(2.0, rel=0.01)
+    assert rec["write_scale"] == pytest.approx(1.0, rel=0.01)
+    for key in KEYS:
+        k = rec["kernels"][key]
+        b = (k["fetch_kib"] * rec["fetch_scale"] + k["write_kib"] * rec["write_scale"]) * 1024
+        assert k["bytes_per_unit"] == pytest.approx(b / k["units"], rel=1e-12)
