@@ -128,7 +128,31 @@ __device__ __forceinline__ void store_list(const DevPlan &P, size_t node, const 
     for (int m = 0; m < TOPM / 2; ++m) cv[m] = make_double2(le[2 * m] + pen, le[2 * m + 1] + pen);
 }
 
+// Candidates buffered per lane between merges into its list.
+constexpr int LIST_BUF = 16;
+
+// Shared memory of dp_topm_kernel for K candidates: the previous stage's
+// candidates (float [7][K]) and the merge buffers (uint16 [LIST_BUF][TOPM_BS]).
+__host__ __device__ inline size_t topm_shared_bytes(int K) {
+    return (size_t)K * NJ * sizeof(float) + (size_t)LIST_BUF * TOPM_BS * sizeof(uint16_t);
+}
+
 // Grid: x = tile (stage t, block of TOPM_BS destinations), y = plan.
+//
+// One lane per destination k builds its list in three parts: the first TOPM
+// predecessors go straight into the sorted list; each later predecessor is
+// screened by an FP32 edge against the list's last edge tau, raised by a
+// relative 2^-21 (FP32 rounding moves each joint difference by at most
+// 2^-24 of itself, so no predecessor with e < tau fails the screen), and
+// the ones that pass are buffered by index; whenever some lane of the
+// wavefront has LIST_BUF of them, every lane merges its buffer into its list
+// in buffer order with the exact FP64 edges (and the same strict insertion),
+// and tau is taken again.  A predecessor that fails the screen has e >= the
+// list's last edge at that moment, so direct insertion would have rejected
+// it too; buffered ones are offered in ascending k', so the list is the one
+// the plain scan builds, bit for bit.  The merges are what diverge between
+// lanes; batching them lets a wavefront pay for one insertion where the
+// lanes' insertions coincide instead of one per predecessor.
 __global__ __launch_bounds__(TOPM_BS) void dp_topm_kernel(const DevPlan *__restrict__ plans) {
     const DevPlan &P = plans[blockIdx.y];
     const int T = P.T, K = P.K;
@@ -136,7 +160,8 @@ __global__ __launch_bounds__(TOPM_BS) void dp_topm_kernel(const DevPlan *__restr
     const int nkb = (K + TOPM_BS - 1) / TOPM_BS;
     const int t = blockIdx.x / nkb, kb = blockIdx.x % nkb;
     if (t >= T) return;
-    extern __shared__ float qprev[];   // [7][K]: candidates of stage t-1
+    extern __shared__ float qprev[];   // [7][K]: candidates of stage t-1, then the merge buffers
+    uint16_t *buf = (uint16_t *)(qprev + (size_t)NJ * K) + threadIdx.x;   // [LIST_BUF][TOPM_BS]
     const CPF_GLOBAL float *__restrict__ cand = P.cand;
     if (t > 0) {
         for (int x = threadIdx.x; x < NJ * K; x += TOPM_BS)
@@ -145,9 +170,13 @@ __global__ __launch_bounds__(TOPM_BS) void dp_topm_kernel(const DevPlan *__restr
     __syncthreads();
     const int k = kb * TOPM_BS + threadIdx.x;
     if (k >= K) return;
+    float qf[NJ];
     double qk[NJ];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) qk[j] = (double)cand[((size_t)t * NJ + j) * K + k];
+    for (int j = 0; j < NJ; ++j) {
+        qf[j] = cand[((size_t)t * NJ + j) * K + k];
+        qk[j] = (double)qf[j];
+    }
     const double pen = node_penalty(P, qk, t, k);
     P.pen[(size_t)t * K + k] = pen;
     if (t == 0) return;
@@ -158,7 +187,27 @@ __global__ __launch_bounds__(TOPM_BS) void dp_topm_kernel(const DevPlan *__restr
         le[m] = __builtin_inf();
         li[m] = 0;
     }
-    for (int kp = 0; kp < K; ++kp) list_insert(le, li, edge(qk, qprev + kp, K), kp);
+    const int n0 = K < TOPM ? K : TOPM;
+    for (int kp = 0; kp < n0; ++kp) list_insert(le, li, edge(qk, qprev + kp, K), kp);
+    float tau = (float)(le[TOPM - 1] * (1.0 + 0x1p-21));
+    int cnt = 0;
+    for (int kp = n0; kp < K; ++kp) {
+        float e = fabsf(qf[0] - qprev[kp]);
+#pragma unroll
+        for (int j = 1; j < NJ; ++j) e = fmaxf(e, fabsf(qf[j] - qprev[(size_t)j * K + kp]));
+        if (e < tau) {
+            buf[cnt * TOPM_BS] = (uint16_t)kp;
+            ++cnt;
+        }
+        if (__any(cnt == LIST_BUF) || kp == K - 1) {   // uniform: every lane reaches both
+            for (int i = 0; i < cnt; ++i) {
+                const int kq = buf[i * TOPM_BS];
+                list_insert(le, li, edge(qk, qprev + kq, K), kq);
+            }
+            cnt = 0;
+            tau = (float)(le[TOPM - 1] * (1.0 + 0x1p-21));
+        }
+    }
     // With K < TOPM the entries past K keep index 0 and an infinite edge;
     // the serial pass reads only the first min(K, TOPM).
     store_list(P, (size_t)t * K + k, le, li, pen);
@@ -522,7 +571,7 @@ hipError_t dp_lists_launch(const DevPlan *d_plans, int nplans, int maxK, int max
     }
     const int nkb = (maxK + TOPM_BS - 1) / TOPM_BS;
     const dim3 grid((unsigned)(maxT * nkb), (unsigned)nplans);
-    hipLaunchKernelGGL(dp_topm_kernel, grid, dim3(TOPM_BS), (size_t)maxK * NJ * sizeof(float), s, d_plans);
+    hipLaunchKernelGGL(dp_topm_kernel, grid, dim3(TOPM_BS), topm_shared_bytes(maxK), s, d_plans);
     return hipGetLastError();
 }
 
