@@ -429,6 +429,7 @@ def main():
                                 "continuous batching, mixed precision"),
                    "rate_hz": args.rate, "duration_s": args.steps, "requests": summary["requests"],
                    "lm_iters": args.iters, "slots": summary["slots"], "iters_per_tick": summary["iters_per_tick"],
+                   "tick_budget": summary["tick_budget"],
                    "parallelism": "single GPU"},
         "latency_ms": {"p50": mo["p50_ms"], "p99": mo["p99_ms"], "max": mo["max_ms"]},
         "offered_load": summary["offered_load"],

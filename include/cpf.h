@@ -380,9 +380,15 @@ cpf_status cpf_batchopt(cpf_ctx *ctx, const cpf_robot *robot, const cpf_problem 
                         const cpf_opts *opts, int32_t M, int32_t *idx_out, cpf_result *results);
 
 /* Server shape, before the first cpf_submit: `slots` requests resident on the
- * device at once (default 256) and LM iterations per tick (default 10).
- * CPF_E_STATE once the server runs. */
-cpf_status cpf_ctx_config(cpf_ctx *ctx, int32_t slots, int32_t iters_per_tick);
+ * device at once (default 256); per tick (one replay of the LM graph) every
+ * resident request advances at most iters_per_tick LM iterations (default
+ * 30) and, when tick_budget > 0 (default 6000), at most about
+ * tick_budget / (T + 330) of them (at least one) for a request of T
+ * waypoints, so that a tick lasts about as long for short and long requests
+ * and short ones are not held back by long ones; tick_budget = 0 gives every
+ * request iters_per_tick.  CPF_E_ARG for values out of range, CPF_E_STATE
+ * once the server runs. */
+cpf_status cpf_ctx_config(cpf_ctx *ctx, int32_t slots, int32_t iters_per_tick, int32_t tick_budget);
 
 /* Serving: copy the request (host inputs; device inputs stay where they
  * are, see cpf_problem.mem), queue it, return a ticket at once.  The server

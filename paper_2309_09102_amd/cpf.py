@@ -113,7 +113,7 @@ _lib.cpf_batchopt.argtypes = [_vp, C.POINTER(cpf_robot), C.POINTER(cpf_problem),
 _lib.cpf_submit.argtypes = [_vp, C.POINTER(cpf_robot), C.POINTER(cpf_problem),
                             C.POINTER(cpf_opts), C.POINTER(C.c_uint64)]
 _lib.cpf_poll.argtypes = [_vp, C.c_uint64, C.c_int32, C.POINTER(cpf_result)]
-_lib.cpf_ctx_config.argtypes = [_vp, C.c_int32, C.c_int32]
+_lib.cpf_ctx_config.argtypes = [_vp, C.c_int32, C.c_int32, C.c_int32]
 _lib.cpf_ctx_profile.argtypes = [_vp, C.c_int32]
 _lib.cpf_ctx_kernel_stats.argtypes = [_vp, C.c_char_p, C.POINTER(C.c_double),
                                       C.POINTER(C.c_int64)]
@@ -268,8 +268,8 @@ def ctx_bytes_in_use(ctx) -> int:
     return int(_lib.cpf_ctx_bytes_in_use(ctx))
 
 
-def ctx_config(ctx, slots: int, iters_per_tick: int):
-    _check(_lib.cpf_ctx_config(ctx, int(slots), int(iters_per_tick)))
+def ctx_config(ctx, slots: int, iters_per_tick: int, tick_budget: int = 6000):
+    _check(_lib.cpf_ctx_config(ctx, int(slots), int(iters_per_tick), int(tick_budget)))
 
 
 def ctx_profile(ctx, enable: bool):
@@ -501,8 +501,8 @@ class Context:
     def bytes_in_use(self) -> int:
         return ctx_bytes_in_use(self.h)
 
-    def config(self, slots: int = 256, iters_per_tick: int = 10):
-        ctx_config(self.h, slots, iters_per_tick)
+    def config(self, slots: int = 256, iters_per_tick: int = 30, tick_budget: int = 6000):
+        ctx_config(self.h, slots, iters_per_tick, tick_budget)
 
     def profile(self, enable: bool = True):
         ctx_profile(self.h, enable)

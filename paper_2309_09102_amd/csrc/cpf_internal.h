@@ -59,8 +59,11 @@ hipError_t dp_stages_launch(const DevPlan *d_plans, int nplans, int maxK, hipStr
 hipError_t dp_append_launch(const DevPlan *d_plan, int K_old, int K, int T, bool coll, hipStream_t s);
 // Up to `iters` LM iterations for each plan of precision prec (0 = mixed,
 // 1 = FP64), objective kind sched and geometry kind geo (GEO_*); empty slots
-// (T = 0) and plans of another precision or kind are skipped.
-hipError_t lm_launch(const DevPlan *d_plans, int nplans, int prec, int sched, int geo, int iters, hipStream_t s);
+// (T = 0) and plans of another precision or kind are skipped.  tick_budget
+// > 0 (serving ticks) caps a plan of T waypoints at about
+// tick_budget / (T + 330) iterations per launch (at least one).
+hipError_t lm_launch(const DevPlan *d_plans, int nplans, int prec, int sched, int geo, int iters, hipStream_t s,
+                     int tick_budget = 0);
 // Pose error vs targets and mjac of the current trajectory (FP64 FK).  With
 // only_finished, only plans that reached their iteration target (or failed)
 // and have not been reported yet.

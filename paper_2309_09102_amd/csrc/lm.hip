@@ -33,6 +33,12 @@
 namespace cpf {
 
 constexpr int LM_BS = 512;
+// Fixed cost of an LM iteration in waypoints: an iteration of a plan of T
+// waypoints takes about as long as T + LM_ITER_FIXED waypoints' worth of
+// the per-waypoint work (the reduction rounds of the solve cost the same
+// for any level size), measured on the one-workgroup kernel at T = 300 to
+// 2000.
+constexpr int LM_ITER_FIXED = 330;
 
 __device__ __forceinline__ double block_sum(double v, double *red) {
     const int tid = threadIdx.x;
@@ -1004,7 +1010,7 @@ __device__ int schedule_check(const DevPlan &P, LMState *st, int T, double *red)
 // the collision terms and the joint-type selects add nothing to the plain
 // iteration.  Plans with capsules are all-revolute (COLL implies !PR).
 template <typename S, bool SCHED, bool COLL, bool PR>
-__global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ plans, int iters) {
+__global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ plans, int iters, int tick_budget) {
     static_assert(!(COLL && PR), "plans with capsules are all-revolute");
     constexpr int PREC = sizeof(S) == sizeof(double) ? 1 : 0;
     const DevPlan &P = plans[blockIdx.x];
@@ -1071,9 +1077,17 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
         sh_sched[2] = st->last_mode;
         sh_flags[0] = st->need_lin;
         sh_flags[1] = st->status;
-        // iterations this launch: at most what the plan still has to do
+        // iterations this launch: at most what the plan still has to do and,
+        // with a tick budget (serving), about tick_budget / (T + LM_ITER_FIXED)
+        // (at least one): a serving tick then takes about as long for a plan
+        // of any length, so short plans are not held back by long ones
         const int left = st->iters_target > 0 ? st->iters_target - st->iters_done : iters;
-        sh_flags[2] = left < iters ? (left > 0 ? left : 0) : iters;
+        int n = left < iters ? (left > 0 ? left : 0) : iters;
+        if (tick_budget > 0) {
+            const int cap = tick_budget / (T + LM_ITER_FIXED);
+            n = n < (cap > 1 ? cap : 1) ? n : (cap > 1 ? cap : 1);
+        }
+        sh_flags[2] = n;
     }
     __syncthreads();
     const int n_it = sh_flags[2];
@@ -1340,27 +1354,28 @@ __global__ __launch_bounds__(LM_BS) void eval_kernel(const DevPlan *__restrict__
 }
 
 template <typename S, bool SCHED>
-static void lm_launch_geo(const DevPlan *d_plans, int nplans, int geo, int iters, hipStream_t s) {
+static void lm_launch_geo(const DevPlan *d_plans, int nplans, int geo, int iters, int budget, hipStream_t s) {
     const dim3 g(nplans), b(LM_BS);
     if (geo == GEO_COLL)
-        hipLaunchKernelGGL((lm_kernel<S, SCHED, true, false>), g, b, 0, s, d_plans, iters);
+        hipLaunchKernelGGL((lm_kernel<S, SCHED, true, false>), g, b, 0, s, d_plans, iters, budget);
     else if (geo == GEO_PRISM)
-        hipLaunchKernelGGL((lm_kernel<S, SCHED, false, true>), g, b, 0, s, d_plans, iters);
+        hipLaunchKernelGGL((lm_kernel<S, SCHED, false, true>), g, b, 0, s, d_plans, iters, budget);
     else
-        hipLaunchKernelGGL((lm_kernel<S, SCHED, false, false>), g, b, 0, s, d_plans, iters);
+        hipLaunchKernelGGL((lm_kernel<S, SCHED, false, false>), g, b, 0, s, d_plans, iters, budget);
 }
 
-hipError_t lm_launch(const DevPlan *d_plans, int nplans, int prec, int sched, int geo, int iters, hipStream_t s) {
+hipError_t lm_launch(const DevPlan *d_plans, int nplans, int prec, int sched, int geo, int iters, hipStream_t s,
+                     int tick_budget) {
     if (nplans <= 0) return hipSuccess;
     if (geo < 0 || geo >= GEO_KINDS) return hipErrorInvalidValue;
     if (prec == 1 && sched)
-        lm_launch_geo<double, true>(d_plans, nplans, geo, iters, s);
+        lm_launch_geo<double, true>(d_plans, nplans, geo, iters, tick_budget, s);
     else if (prec == 1)
-        lm_launch_geo<double, false>(d_plans, nplans, geo, iters, s);
+        lm_launch_geo<double, false>(d_plans, nplans, geo, iters, tick_budget, s);
     else if (sched)
-        lm_launch_geo<float, true>(d_plans, nplans, geo, iters, s);
+        lm_launch_geo<float, true>(d_plans, nplans, geo, iters, tick_budget, s);
     else
-        lm_launch_geo<float, false>(d_plans, nplans, geo, iters, s);
+        lm_launch_geo<float, false>(d_plans, nplans, geo, iters, tick_budget, s);
     return hipGetLastError();
 }
 

@@ -88,7 +88,8 @@ struct cpf_ctx {
     cpf::Server *server = nullptr;
     std::thread server_thread;
     int32_t slots = 256;           // concurrent requests on the device
-    int32_t iters_per_tick = 10;   // LM iterations per graph replay
+    int32_t iters_per_tick = 30;   // LM iterations per graph replay, at most
+    int32_t tick_budget = 6000;    // and about tick_budget / (T + 330) of them for a plan of T waypoints
     // kernel timing
     std::mutex prof_mu;
     std::atomic<bool> prof{false};

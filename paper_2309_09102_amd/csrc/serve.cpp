@@ -63,6 +63,7 @@ struct Request {
 struct Server {
     int cap = 0;
     int ipt = 0;
+    int budget = 0;   // waypoint-iterations per plan and tick (0: iters_per_tick for every plan)
     hipStream_t s_lm = nullptr;    // tick graph, work-list updates, read-back
     hipStream_t s_up = nullptr;    // uploads and searches
     hipEvent_t searched = nullptr;
@@ -84,6 +85,7 @@ namespace {
 cpf_status server_init(cpf_ctx *ctx, Server *sv) {
     sv->cap = ctx->slots;
     sv->ipt = ctx->iters_per_tick;
+    sv->budget = ctx->tick_budget;
     HIP_TRY(hipSetDevice(ctx->device));
     HIP_TRY(hipStreamCreateWithFlags(&sv->s_lm, hipStreamNonBlocking));
     HIP_TRY(hipStreamCreateWithFlags(&sv->s_up, hipStreamNonBlocking));
@@ -116,7 +118,7 @@ cpf_status tick_graph(Server *sv, int kinds, hipGraphExec_t *out) {
         for (int geo = 0; geo < GEO_KINDS; ++geo)
             for (int sched = 0; sched <= (kinds & 1) && geos[geo]; ++sched)
                 for (int prec = 0; prec < 2 && e == hipSuccess; ++prec)
-                    e = lm_launch(sv->d_work, sv->cap, prec, sched, geo, sv->ipt, sv->s_lm);
+                    e = lm_launch(sv->d_work, sv->cap, prec, sched, geo, sv->ipt, sv->s_lm, sv->budget);
         for (int geo = 0; geo < GEO_KINDS && e == hipSuccess; ++geo)
             if (geos[geo]) e = eval_launch(sv->d_work, sv->cap, 1, geo, sv->s_lm);
         hipError_t e2 = hipStreamEndCapture(sv->s_lm, &sv->graph[kinds]);
@@ -397,14 +399,16 @@ void server_stop_and_join(cpf_ctx *ctx) {
 
 using namespace cpf;
 
-extern "C" cpf_status cpf_ctx_config(cpf_ctx *ctx, int32_t slots, int32_t iters_per_tick) {
+extern "C" cpf_status cpf_ctx_config(cpf_ctx *ctx, int32_t slots, int32_t iters_per_tick, int32_t tick_budget) {
     if (!ctx) return fail(CPF_E_ARG, "ctx is NULL");
     if (slots < 1 || slots > 65536 || iters_per_tick < 1 || iters_per_tick > 100000)
         return fail(CPF_E_ARG, "slots %d / iters_per_tick %d out of range", slots, iters_per_tick);
+    if (tick_budget < 0) return fail(CPF_E_ARG, "tick_budget %d < 0", tick_budget);
     std::lock_guard<std::mutex> lk(ctx->mu);
     if (ctx->server_thread.joinable()) return fail(CPF_E_STATE, "server already running");
     ctx->slots = slots;
     ctx->iters_per_tick = iters_per_tick;
+    ctx->tick_budget = tick_budget;
     return CPF_OK;
 }
 

@@ -466,7 +466,7 @@ def _summary(res, reqs, iters):
             "wall_s": res["wall_s"], "statuses": sorted(set(res["status"]))}
 
 
-def run_serve(duration_s=10.0, warmup_s=2.0, rate_hz=200.0, iters=30, slots=256, ipt=10,
+def run_serve(duration_s=10.0, warmup_s=2.0, rate_hz=200.0, iters=30, slots=256, ipt=30, tick_budget=6000,
               fp64_budget_s=None, keep_xi=(), open_loop_only=False):
     """The serving comparison on distinct device-resident requests: the
     arrival schedule's first warmup_s seconds are served untimed, the next
@@ -496,7 +496,8 @@ def run_serve(duration_s=10.0, warmup_s=2.0, rate_hz=200.0, iters=30, slots=256,
     o_64 = cpf.make_opts(iters=iters, prec="fp64")
     out = {"mode": "serve", "rate_hz": rate_hz, "duration_s": duration_s, "warmup_s": warmup_s,
            "requests": len(timed), "warmup_requests": len(warm), "lm_iters": iters, "slots": slots,
-           "iters_per_tick": ipt, "unit": "waypoint-LM-iters/s", "waypoint_lm_iters": work,
+           "iters_per_tick": ipt, "tick_budget": tick_budget, "unit": "waypoint-LM-iters/s",
+           "waypoint_lm_iters": work,
            "offered_load": work / duration_s, "input_prep_s": t_gen,
            "warmup_waypoint_lm_iters": sum(r.T for r in warm) * iters,
            "search_pairs": sum((r.T - 1) * r.K * r.K for r in timed),
@@ -508,7 +509,7 @@ def run_serve(duration_s=10.0, warmup_s=2.0, rate_hz=200.0, iters=30, slots=256,
 
     # --- mixed precision, continuous batching -------------------------------
     ctx = cpf.Context(0, 64 << 30)
-    ctx.config(slots=slots, iters_per_tick=ipt)
+    ctx.config(slots=slots, iters_per_tick=ipt, tick_budget=tick_budget)
     if warm:
         serve_stream(ctx, warm, None, o_mix)                     # warm-up: graphs, arena pool
     ctx.profile(True)
@@ -532,7 +533,7 @@ def run_serve(duration_s=10.0, warmup_s=2.0, rate_hz=200.0, iters=30, slots=256,
 
     # --- all FP64, continuous batching (the precision comparison at equal batching)
     ctx = cpf.Context(0, 64 << 30)
-    ctx.config(slots=slots, iters_per_tick=ipt)
+    ctx.config(slots=slots, iters_per_tick=ipt, tick_budget=tick_budget)
     if warm:
         serve_stream(ctx, warm[:64], None, o_64)
     ctx.profile(True)

@@ -112,3 +112,28 @@ def test_needs_research_is_decided_by_the_library(ctx):
             plan.dp_search()
             rev, pri = plan.seed_steps()
             assert plan.needs_research() == (rev > cpf.RESEARCH_MJAC_RAD or pri > cpf.RESEARCH_MJAC_M)
+
+
+def test_server_config_validation():
+    """cpf_ctx_config rejects a negative tick budget and any change once the
+    server runs; a budget of 0 (every request iters_per_tick per tick) serves
+    the same results as the default budget (bitwise)."""
+    probs = [H.small_problem(seed=72 + i, T=30 + 400 * i, K=8) for i in range(3)]
+    opts = cpf.make_opts(iters=12)
+    out = []
+    for budget in (0, 6000, 700):
+        with cpf.Context(0, 4 << 30) as c:
+            with pytest.raises(cpf.CpfError) as ei:
+                c.config(slots=8, iters_per_tick=5, tick_budget=-1)
+            assert ei.value.status == cpf.E_ARG
+            c.config(slots=8, iters_per_tick=5, tick_budget=budget)
+            tickets = [c.submit(p.robot, p.targets, p.cand, opts) for p in probs]
+            with pytest.raises(cpf.CpfError) as ei:
+                c.config(slots=8, iters_per_tick=5, tick_budget=budget)
+            assert ei.value.status == cpf.E_STATE
+            res = [c.poll(t, p.T, timeout_ms=60000) for t, p in zip(tickets, probs)]
+        assert all(r is not None and r["status"] == 0 and r["report"]["iters_done"] == 12 for r in res)
+        out.append([r["xi"] for r in res])
+    for other in out[1:]:
+        for a, b in zip(out[0], other):
+            assert np.array_equal(a, b)
