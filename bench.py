@@ -62,7 +62,7 @@ def parse():
     ap.add_argument("--iters", type=int, default=30, help="LM iterations per request")
     ap.add_argument("--workload", default="serve",
                     choices=["serve", "T300_K256", "T1000_K512", "batch64", "batchopt", "schedule", "research",
-                             "collision", "prismatic"],
+                             "collision", "prismatic", "lm_phases"],
                     help="serve: the headline line; the others print the additional measured workloads "
                          "of paper_2309_09102_amd/workloads.py")
     ap.add_argument("--fp64-budget", type=float, default=None,
@@ -396,7 +396,8 @@ def main():
         fn = {"T300_K256": workloads.run_single, "T1000_K512": workloads.run_precision,
               "batch64": lambda: workloads.run_batch64(iters=30), "batchopt": workloads.run_batchopt,
               "schedule": workloads.run_schedule, "research": workloads.run_research,
-              "collision": workloads.run_collision, "prismatic": workloads.run_prismatic}[args.workload]
+              "collision": workloads.run_collision, "prismatic": workloads.run_prismatic,
+              "lm_phases": workloads.run_lm_phases}[args.workload]
         print(json.dumps(fn()))
         return
 
@@ -434,6 +435,7 @@ def main():
         "latency_ms": {"p50": mo["p50_ms"], "p99": mo["p99_ms"], "max": mo["max_ms"]},
         "offered_load": summary["offered_load"],
         "saturation": summary["mixed_closed"],
+        "saturation_host_inputs": summary.get("mixed_closed_host_inputs"),
         "fp64_batched_closed": summary["fp64_closed"],
         "fp64_one_at_a_time": summary["fp64_one_at_a_time_open"],
         "speedup_vs_fp64_one_at_a_time": {"open_loop": summary["speedup_open"],

@@ -91,6 +91,36 @@ def run_single(ctx=None, iters=50, reps=10):
     return out
 
 
+def run_lm_phases(iters=10):
+    """One plan each at T = 300 (K = 256), 1000 and 2000 (K = 128), mixed
+    arm: a warm-up iteration, then `iters` LM iterations timed.  With the
+    diagnostic build of the library (built with -D CPF_PHASE_CYCLES and
+    loaded through CPF_LIB) the LM kernel also prints its per-phase and
+    per-round shader-clock totals for each launch."""
+    import sys
+    import torch
+    from paper_2309_09102_amd import cpf, synth
+    dev = torch.device("cuda:0")
+    ctx = cpf.Context(0)
+    out = {"mode": "lm_phases", "iters": iters, "plans": []}
+    for T, K in ((300, 256), (1000, 128), (2000, 128)):
+        p = _targets(ctx, synth.make_problem(synth.make_robot(0), seed=2, T=T, K=K, sigma=0.1, branch_frac=0.25),
+                     torch, dev)
+        with ctx.plan(p.robot, p.targets, p.cand, opts=cpf.make_opts(prec="mixed")) as plan:
+            plan.dp_search()
+            plan.lm_refine(1)
+            torch.cuda.synchronize()
+            print(f"=== T={T} K={K}: {iters} iterations", flush=True)
+            ctx.profile(True)
+            plan.lm_refine(iters, want_xi=False)
+            ms = ctx.kernel_stats("lm")[0]
+            ctx.profile(False)
+            sys.stdout.flush()
+        out["plans"].append({"T": T, "K": K, "lm_ms_per_iteration": ms / iters})
+    ctx.close()
+    return out
+
+
 def run_batch64(n=64, iters=30):
     import torch
     from paper_2309_09102_amd import cpf, synth
@@ -467,7 +497,7 @@ def _summary(res, reqs, iters):
 
 
 def run_serve(duration_s=10.0, warmup_s=2.0, rate_hz=200.0, iters=30, slots=256, ipt=30, tick_budget=6000,
-              fp64_budget_s=None, keep_xi=(), open_loop_only=False):
+              fp64_budget_s=None, keep_xi=(), open_loop_only=False, host_requests=256):
     """The serving comparison on distinct device-resident requests: the
     arrival schedule's first warmup_s seconds are served untimed, the next
     duration_s seconds are the timed stream.  Returns the summary and the raw
@@ -529,6 +559,20 @@ def run_serve(duration_s=10.0, warmup_s=2.0, rate_hz=200.0, iters=30, slots=256,
     ctx.profile(False)
     out["mixed_closed"] = _summary(res, timed, iters)
     out["mixed_closed"]["kernels"] = {k: {"ms": v[0], "launches": v[1]} for k, v in ks.items()}
+
+    # --- the same server fed host arrays (float32 candidates, copied by
+    # cpf_submit and sent over PCIe at admission): the first requests of the
+    # timed stream, all at once
+    n_host = min(len(timed), host_requests)
+    if n_host:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=8) as ex:
+            hp = list(ex.map(lambda r: synth.config5_request(r.i), timed[:n_host]))
+        host_reqs = [StreamRequest(r.i, r.T, r.K, p.cand, r.targets.cpu().numpy())
+                     for r, p in zip(timed[:n_host], hp)]
+        res = serve_stream(ctx, host_reqs, None, o_mix)
+        out["mixed_closed_host_inputs"] = _summary(res, host_reqs, iters)
+        del hp, host_reqs
     ctx.close()
 
     # --- all FP64, continuous batching (the precision comparison at equal batching)
@@ -574,7 +618,7 @@ if __name__ == "__main__":
     import argparse
     ap = argparse.ArgumentParser()
     ap.add_argument("mode", choices=["batch64", "T1000_K512", "batchopt", "schedule", "research", "collision",
-                                     "prismatic", "serve"])
+                                     "prismatic", "serve", "lm_phases"])
     ap.add_argument("--duration", type=float, default=10.0)
     a = ap.parse_args()
     if a.mode == "batch64":
@@ -591,5 +635,7 @@ if __name__ == "__main__":
         print(json.dumps(run_collision()))
     elif a.mode == "prismatic":
         print(json.dumps(run_prismatic()))
+    elif a.mode == "lm_phases":
+        print(json.dumps(run_lm_phases()))
     else:
         print(json.dumps(run_serve(duration_s=a.duration)[0]))
