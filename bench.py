@@ -279,6 +279,13 @@ def cpu_baseline_leg(args, summary, raw, ctx_results):
     t2 = one_core(c2, 50, 3)
     cfg["config2"] = {"T": 300, "K": 256, "lm_iters": 50, "cores": 1, "latency_ms": t2 * 1e3,
                       "waypoint_lm_iters_per_s": 300 * 50 / t2}
+    if ctx_results.get("config2_xi"):
+        ref2 = oracle.plan(c2.robot, c2.cand, c2.targets, 50)
+        c_ref = oracle.cost(c2.robot, ref2["xi"], c2.targets)
+        cfg["config2"]["gpu_err_vs_oracle"] = {
+            arm: list(oracle.pose_compare(c2.robot, xi, ref2["xi"])) +
+            [abs(oracle.cost(c2.robot, xi, c2.targets) - c_ref) / c_ref]
+            for arm, xi in ctx_results["config2_xi"].items()}
     c3 = synth.config3()
     c3 = c3.with_targets(oracle.fk(c3.robot, c3.q_star))
     t0 = time.perf_counter()
@@ -317,7 +324,8 @@ def context_legs(args, out, ctx_results):
         torch.cuda.synchronize()
         return p.with_targets(pose.cpu().numpy().T)
 
-    out["single_request"] = workloads.run_single(ctx=ctx, iters=50)
+    ctx_results["config2_xi"] = {}
+    out["single_request"] = workloads.run_single(ctx=ctx, iters=50, xi_out=ctx_results["config2_xi"])
     prob = targets_of(synth.config2())
     T, iters = prob.T, 50
 

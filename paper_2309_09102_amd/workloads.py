@@ -45,7 +45,7 @@ def _targets(ctx, prob, torch, dev):
     return prob.with_targets(pose.cpu().numpy().T)
 
 
-def run_single(ctx=None, iters=50, reps=10):
+def run_single(ctx=None, iters=50, reps=10, xi_out=None):
     """The single T=300, K=256 request, mixed and all-FP64: each step is
     batched FK over the K x T candidates plus cpf_plan_solve (the full
     search with its lists, back-tracking, `iters` LM iterations and the
@@ -79,6 +79,8 @@ def run_single(ctx=None, iters=50, reps=10):
         dt = (time.perf_counter() - t0) / reps
         st = {k: ctx.kernel_stats(k) for k in ("fk", "dp_lists", "dp", "lm", "eval")}
         ctx.profile(False)
+        if xi_out is not None:
+            xi_out[prec] = plan.solve(want_xi=True)[2]
         plan.free()
         lm_ms = st["lm"][0] / max(st["lm"][1], 1)
         out["arms"][prec] = {"ms_per_step": dt * 1e3, "waypoint_lm_iters_per_s": T * iters / dt,
