@@ -342,8 +342,8 @@ cpf_status cpf_plan_solve(cpf_plan *plan, int32_t *path_out, double *best_out, d
  * 64 MiB that the library holds on each GPU it runs on until the process
  * ends.  No hipMalloc, hipFree or other allocating call is made.  A problem
  * whose working memory (the arena of a plan of that T and K: about
- * 198 K + 4.4 KB bytes per waypoint, e.g. 16.5 MB for T = 300, K = 256, so
- * up to T of about 1200 at K = 256) exceeds 64 MiB returns CPF_E_NOMEM with
+ * 198 K + 3.6 KB bytes per waypoint, e.g. 15.5 MB for T = 300, K = 256, so
+ * up to T of about 1230 at K = 256) exceeds 64 MiB returns CPF_E_NOMEM with
  * the sizes in the message.  path_out [T], best_out,
  * xi_out [T][dof] (host) and rep may each be NULL.  Calls on one GPU share
  * its array: the library runs them one after another (a per-device lock),

@@ -95,7 +95,7 @@ Layout make_layout(int T, int K, bool extra, int n_obs, bool coll) {
     L.targets = take(12 * t * sizeof(double));
     L.xi = take(NJ * t * sizeof(double));
     L.xt = take(NJ * t * sizeof(double));
-    L.A = take(NBLK * t * sizeof(double));
+    L.A = take(NTRI * t * sizeof(double));
     L.g = take(NJ * t * sizeof(double));
     L.cr = take(cr_doubles(T) * sizeof(double));
     L.dx = take(NJ * t * sizeof(double));
@@ -442,7 +442,7 @@ static bool desc_in_arena(const cpf_plan *p, bool has_extra) {
         {(const void *)D.bp, t * k * sizeof(uint16_t)}, {(const void *)D.topk, t * k * TOPM * sizeof(uint16_t)},
         {(const void *)D.topc, t * k * TOPM * d}, {(const void *)D.path, t * sizeof(int32_t)},
         {(const void *)D.dp_out, 8 * d}, {(const void *)D.targets, 12 * t * d}, {(const void *)D.xi, NJ * t * d},
-        {(const void *)D.xt, NJ * t * d}, {(const void *)D.A, NBLK * t * d}, {(const void *)D.g, NJ * t * d},
+        {(const void *)D.xt, NJ * t * d}, {(const void *)D.A, NTRI * t * d}, {(const void *)D.g, NJ * t * d},
         {(const void *)D.cr, cr_doubles(p->T) * d}, {(const void *)D.dx, NJ * t * d},
         {(const void *)D.rb, NJ * t * d}, {(const void *)D.st, sizeof(LMState)}, {(const void *)D.report, 8 * d},
         {(const void *)D.xv, NJ * t * d}, {(const void *)D.rr, RROWS * t * d}, {(const void *)D.rt, RROWS * t * d},

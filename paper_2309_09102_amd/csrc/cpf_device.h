@@ -12,7 +12,7 @@
 //   path     int32  [T]
 //   targets  double [12][T]     target poses (Sec. II): x y z, R row-major
 //   xi, xt   double [7][T]      trajectory master copy and LM trial point
-//   A        double [T][49]     w_p J_t^T J_t, whole 7x7 blocks
+//   A        double [T][28]     w_p J_t^T J_t, packed lower triangles (row by row)
 //   g        double [7][T]      gradient of the cost
 //   cr       double             cyclic-reduction levels of the LM system (cr_doubles(T))
 //   dx, rb   double [7][T]      step, refinement residual
@@ -352,16 +352,17 @@ __device__ __forceinline__ void pose_residual(const S X[3], const S Y[3], const 
 __host__ __device__ constexpr int tri_index(int i, int j) { return i * (i + 1) / 2 + j; }  // i >= j
 
 // Storage of one cyclic-reduction level with n blocks (no = n / 2 odd
-// blocks, ne = n - no even ones), in doubles, every block whole (49) or a
-// whole vector (7): the sub-diagonal blocks E (49 n), the even blocks'
-// diagonal block and right-hand side (49 ne + 7 ne), the solution (7 n), and
-// per odd block the inverse Cholesky factor, the two coupling products, the
-// two Schur contributions (5 x 49), the transformed right-hand side and its
-// two contributions (3 x 7); the last level (n = 1) keeps its factor in the
-// first odd slot.
+// blocks, ne = n - no even ones), in doubles: a general 7x7 block whole (49,
+// row-major), a symmetric or triangular one as its packed lower triangle
+// (28), a vector whole (7).  The sub-diagonal blocks E (49 n), the even
+// blocks' diagonal block and right-hand side (28 ne + 7 ne), the solution
+// (7 n), and per odd block the inverse Cholesky factor (28), the two
+// coupling products (2 x 49), the two Schur contributions (2 x 28), the
+// transformed right-hand side and its two contributions (3 x 7); the last
+// level (n = 1) keeps its factor in the first odd slot.
 __host__ __device__ inline size_t cr_level_doubles(int n) {
     const size_t no = (size_t)(n / 2), ne = (size_t)n - no, nod = no > 0 ? no : 1;
-    return 56 * (size_t)n + 56 * ne + 266 * nod;
+    return 56 * (size_t)n + 35 * ne + 203 * nod;
 }
 
 // All levels of a path of T waypoints (n halves, rounding up, down to 1).

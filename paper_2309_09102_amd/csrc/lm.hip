@@ -226,9 +226,7 @@ __device__ __forceinline__ double linearise(const DevPlan &P, const RobotT<S> &r
                 double s = (double)J[0][i] * (double)J[0][j];
 #pragma unroll
                 for (int k = 1; k < 6; ++k) s += (double)J[k][i] * (double)J[k][j];
-                const double v = w_p * s;
-                P.A[(size_t)t * NBLK + i * NJ + j] = v;
-                if (i != j) P.A[(size_t)t * NBLK + j * NJ + i] = v;
+                P.A[(size_t)t * NTRI + tri_index(i, j)] = w_p * s;   // packed lower triangle
             }
         }
 #pragma unroll
@@ -270,8 +268,8 @@ __device__ __forceinline__ double linearise(const DevPlan &P, const RobotT<S> &r
 #pragma unroll
             for (int i = 0; i < NJ; ++i) {
 #pragma unroll
-                for (int j = 0; j < NJ; ++j)
-                    P.A[(size_t)t * NBLK + i * NJ + j] += w_c * (Jc[0][i] * Jc[0][j] + Jc[1][i] * Jc[1][j]);
+                for (int j = 0; j <= i; ++j)
+                    P.A[(size_t)t * NTRI + tri_index(i, j)] += w_c * (Jc[0][i] * Jc[0][j] + Jc[1][i] * Jc[1][j]);
                 const double gi = P.g[(size_t)i * T + t] + w_c * (Jc[0][i] * rc[0] + Jc[1][i] * rc[1]);
                 P.g[(size_t)i * T + t] = gi;
                 gmax = fmax(gmax, fabs(gi));
@@ -279,16 +277,6 @@ __device__ __forceinline__ double linearise(const DevPlan &P, const RobotT<S> &r
         }
     }
     return gmax;
-}
-
-// Element (i, j) of D_t = A_t + (w_s c_t + lambda) I.
-__device__ __forceinline__ double d_elem(const DevPlan &P, int T, int t, int i, int j, double lam, double ws) {
-    double v = P.A[(size_t)t * NBLK + i * NJ + j];
-    if (i == j) {
-        const int ct = (t > 0) + (t + 1 < T);
-        v += ws * ct + lam;
-    }
-    return v;
 }
 
 // ---------------------------------------------------------------------------
@@ -314,10 +302,13 @@ __device__ __forceinline__ double d_elem(const DevPlan &P, int T, int t, int i, 
 // (lane c owns column c of W, V and of the products) and exchange columns
 // through a per-group LDS area; LDS instructions of one wavefront complete
 // in order, so a wave barrier is the only synchronisation the exchange
-// needs.  Blocks are stored whole (7 x 7 row-major, 49 doubles, symmetric
-// ones in full and factors with zeros above the diagonal) one after another,
-// so a lane reaches every element of its block, row or column from one
-// per-lane address plus an instruction immediate.
+// needs.  Blocks are 7 x 7 row-major (49 doubles) one after another, so a
+// lane reaches every element of its block, row or column from one per-lane
+// address plus an instruction immediate.  Of the Gram blocks A_t, the
+// diagonal blocks kept for the next level, the level-0 Schur contributions
+// and the factors Li only the lower triangle is written: a reader takes a
+// symmetric block's element (i, j) at (max, min) and a factor's upper part
+// as zero, and the other readers use only the lower triangle.
 // ---------------------------------------------------------------------------
 
 constexpr int CR_GPW = 9;                          // 7-lane groups per wavefront (lane 63 idles)
@@ -327,18 +318,19 @@ constexpr int CR_EX = 2 * NBLK;                    // LDS doubles per group
 struct CRLevel {
     CPF_GLOBAL double *p;
     int n, no, ne, nod;
+    // whole blocks: E, W, V; packed lower triangles: DE, Li, Z1, Z2
     __device__ CPF_GLOBAL double *E() const { return p; }
-    __device__ CPF_GLOBAL double *DE() const { return p + 49 * (size_t)n; }
-    __device__ CPF_GLOBAL double *rE() const { return DE() + 49 * (size_t)ne; }
-    __device__ CPF_GLOBAL double *X() const { return rE() + 7 * (size_t)ne; }
-    __device__ CPF_GLOBAL double *Li() const { return X() + 7 * (size_t)n; }
-    __device__ CPF_GLOBAL double *W() const { return Li() + 49 * (size_t)nod; }
-    __device__ CPF_GLOBAL double *V() const { return W() + 49 * (size_t)nod; }
-    __device__ CPF_GLOBAL double *Z1() const { return V() + 49 * (size_t)nod; }
-    __device__ CPF_GLOBAL double *Z2() const { return Z1() + 49 * (size_t)nod; }
-    __device__ CPF_GLOBAL double *s() const { return Z2() + 49 * (size_t)nod; }
-    __device__ CPF_GLOBAL double *c1() const { return s() + 7 * (size_t)nod; }
-    __device__ CPF_GLOBAL double *c2() const { return c1() + 7 * (size_t)nod; }
+    __device__ CPF_GLOBAL double *DE() const { return p + NBLK * (size_t)n; }
+    __device__ CPF_GLOBAL double *rE() const { return DE() + NTRI * (size_t)ne; }
+    __device__ CPF_GLOBAL double *X() const { return rE() + NJ * (size_t)ne; }
+    __device__ CPF_GLOBAL double *Li() const { return X() + NJ * (size_t)n; }
+    __device__ CPF_GLOBAL double *W() const { return Li() + NTRI * (size_t)nod; }
+    __device__ CPF_GLOBAL double *V() const { return W() + NBLK * (size_t)nod; }
+    __device__ CPF_GLOBAL double *Z1() const { return V() + NBLK * (size_t)nod; }
+    __device__ CPF_GLOBAL double *Z2() const { return Z1() + NTRI * (size_t)nod; }
+    __device__ CPF_GLOBAL double *s() const { return Z2() + NTRI * (size_t)nod; }
+    __device__ CPF_GLOBAL double *c1() const { return s() + NJ * (size_t)nod; }
+    __device__ CPF_GLOBAL double *c2() const { return c1() + NJ * (size_t)nod; }
 };
 
 __device__ __forceinline__ CRLevel cr_level(CPF_GLOBAL double *base, int T, int lev) {
@@ -429,25 +421,22 @@ __device__ __forceinline__ void tri_tmv(const double M[NTRI], const double x[NJ]
     }
 }
 
-// Lower triangle of a whole block / a whole block from a lower triangle
-// (zeros above the diagonal, or mirrored when sym).
-__device__ __forceinline__ void ld_lower(const CPF_GLOBAL double *b, double m[NTRI]) {
+// A symmetric or lower-triangular 7 x 7 block kept as its packed lower
+// triangle (NTRI doubles, row by row): loaded, stored (scaled), and the
+// position of element (i, j) of a symmetric one.
+__device__ __forceinline__ void ld_packed(const CPF_GLOBAL double *b, double m[NTRI]) {
 #pragma unroll
-    for (int a = 0; a < NJ; ++a)
-#pragma unroll
-        for (int k = 0; k <= a; ++k) m[tri_index(a, k)] = b[a * NJ + k];
+    for (int q = 0; q < NTRI; ++q) m[q] = b[q];
 }
-__device__ __forceinline__ void st_full(CPF_GLOBAL double *b, const double m[NTRI], bool sym, double scale) {
+__device__ __forceinline__ void st_packed(CPF_GLOBAL double *b, const double m[NTRI], double scale) {
 #pragma unroll
-    for (int a = 0; a < NJ; ++a)
-#pragma unroll
-        for (int k = 0; k < NJ; ++k)
-            b[a * NJ + k] = k <= a ? scale * m[tri_index(a, k)] : (sym ? scale * m[tri_index(k, a)] : 0.0);
+    for (int q = 0; q < NTRI; ++q) b[q] = scale * m[q];
 }
+__device__ __forceinline__ int sym_index(int i, int j) { return i >= j ? tri_index(i, j) : tri_index(j, i); }
 
 // Level-0 diagonal block t (lower triangle): w_p J^T J + (w_s c_t + lambda) I.
 __device__ __forceinline__ void level0_D(const DevPlan &P, int T, double lam, double ws, int t, double D[NTRI]) {
-    ld_lower(blk(P.A, t, NBLK), D);
+    ld_packed(blk(P.A, t, NTRI), D);
     const double dg = ws * ((t > 0) + (t + 1 < T)) + lam;
 #pragma unroll
     for (int a = 0; a < NJ; ++a) D[tri_index(a, a)] += dg;
@@ -479,13 +468,13 @@ __device__ __forceinline__ void cr_form_lane(const DevPlan &P, int T, double lam
     const CPF_GLOBAL double *c2 = lev == 1 ? Lp.c1() : Lp.c2();
     if (factor) {
         if (lev == 1) level0_D(P, T, lam, ws, 2 * j, D);
-        else ld_lower(blk(Lp.DE(), j, NBLK), D);
-        const CPF_GLOBAL double *zr = blk(Lp.Z1(), q.jr, NBLK), *zl = blk(Z2, q.jl, NBLK);
+        else ld_packed(blk(Lp.DE(), j, NTRI), D);
+        const CPF_GLOBAL double *zr = blk(Lp.Z1(), q.jr, NTRI), *zl = blk(Z2, q.jl, NTRI);
 #pragma unroll
         for (int a = 0; a < NJ; ++a)
 #pragma unroll
             for (int k = 0; k <= a; ++k) {
-                const double vr = zr[a * NJ + k], vl = zl[a * NJ + k];
+                const double vr = zr[tri_index(a, k)], vl = zl[tri_index(a, k)];
                 D[tri_index(a, k)] = D[tri_index(a, k)] - (q.has_r ? vr : 0.0) - (q.has_l ? vl : 0.0);
             }
     }
@@ -509,14 +498,14 @@ __device__ __forceinline__ void cr_form_col(const DevPlan &P, int T, double lam,
     const CPF_GLOBAL double *c2 = lev == 1 ? Lp.c1() : Lp.c2();
     if (factor) {
         const int t = 2 * j;
-        const CPF_GLOBAL double *b0 = lev == 1 ? blk(P.A, t, NBLK) : blk(Lp.DE(), j, NBLK);
+        const CPF_GLOBAL double *b0 = lev == 1 ? blk(P.A, t, NTRI) : blk(Lp.DE(), j, NTRI);
         const double dg = lev == 1 ? ws * ((t > 0) + (t + 1 < T)) + lam : 0.0;
-        const CPF_GLOBAL double *zr = blk(Lp.Z1(), q.jr, NBLK) + c, *zl = blk(Z2, q.jl, NBLK) + c;
-        b0 += c;
+        const CPF_GLOBAL double *zr = blk(Lp.Z1(), q.jr, NTRI), *zl = blk(Z2, q.jl, NTRI);
 #pragma unroll
         for (int a = 0; a < NJ; ++a) {
-            const double v = b0[a * NJ] + (a == c ? dg : 0.0);
-            const double vr = zr[a * NJ], vl = zl[a * NJ];
+            const int e = sym_index(a, c);
+            const double v = b0[e] + (a == c ? dg : 0.0);
+            const double vr = zr[e], vl = zl[e];
             d[a] = v - (q.has_r ? vr : 0.0) - (q.has_l ? vl : 0.0);
         }
     }
@@ -525,18 +514,44 @@ __device__ __forceinline__ void cr_form_col(const DevPlan &P, int T, double lam,
     rc = r0 - (q.has_r ? vr : 0.0) - (q.has_l ? vl : 0.0);
 }
 
-// Odd block i = 2h+1 of level 0 (one lane): factor, Schur contribution and
-// coupling of level 1 (factor only), s and its contribution.
-__device__ __forceinline__ void cr_odd_level0(const DevPlan &P, int T, double lam, double ws, const CRLevel &L0,
-                                              const CRLevel &L1, int h, bool factor, const CPF_GLOBAL double *rhs,
-                                              double sgn, bool &ok) {
+// Column c of the coupling E_i of block i of level lev >= 1 (to block i-1)
+// and row c of E_{i+1} (zero without a right neighbour).  Level 1's
+// couplings are -Z1 of the odd blocks of level 0 between them: symmetric
+// packed blocks, so row c equals column c.
+__device__ __forceinline__ void cr_coupling_cols(const CRLevel &L, const CRLevel &Lp, int lev, int i, bool right, int c,
+                                                 double e[NJ], double f[NJ]) {
+    if (lev == 1) {
+        const CPF_GLOBAL double *Zl = blk(Lp.Z1(), i - 1, NTRI), *Zr = blk(Lp.Z1(), right ? i : i - 1, NTRI);
+#pragma unroll
+        for (int k = 0; k < NJ; ++k) {
+            const int q = sym_index(k, c);
+            e[k] = -1.0 * Zl[q];
+            const double fk = Zr[q];
+            f[k] = right ? -1.0 * fk : 0.0;
+        }
+    } else {
+        const CPF_GLOBAL double *Ei = blk(L.E(), i, NBLK) + c;
+        const CPF_GLOBAL double *Er = blk(L.E(), right ? i + 1 : i, NBLK) + c * NJ;
+#pragma unroll
+        for (int k = 0; k < NJ; ++k) {
+            e[k] = Ei[k * NJ];
+            const double fk = Er[k];
+            f[k] = right ? fk : 0.0;
+        }
+    }
+}
+
+// Odd block i = 2h+1 of level 0 (one lane): factor and Schur contribution
+// (factor only), s and its contribution.
+__device__ __forceinline__ void cr_odd_level0(const DevPlan &P, int T, double lam, double ws, const CRLevel &L0, int h,
+                                              bool factor, const CPF_GLOBAL double *rhs, double sgn, bool &ok) {
     const int i = 2 * h + 1;
     const double w = ws;
     double Li[NTRI];
     if (factor) {
         level0_D(P, T, lam, ws, i, Li);
         chol_inverse(Li, ok);
-        st_full(blk(L0.Li(), h, NBLK), Li, false, 1.0);
+        st_packed(blk(L0.Li(), h, NTRI), Li, 1.0);
         double Pm[NTRI];   // Li^T Li
 #pragma unroll
         for (int a = 0; a < NJ; ++a)
@@ -547,11 +562,11 @@ __device__ __forceinline__ void cr_odd_level0(const DevPlan &P, int T, double la
                 for (int k = a; k < NJ; ++k) s = fma(Li[tri_index(k, a)], Li[tri_index(k, b)], s);
                 Pm[tri_index(a, b)] = s;
             }
-        const double w2 = w * w;
-        st_full(blk(L0.Z1(), h, NBLK), Pm, true, w2);
-        if (i + 1 < L0.n) st_full(blk(L1.E(), (i + 1) / 2, NBLK), Pm, true, -w2);
+        // Z1 = Z2 = w^2 Pm; the coupling E' = -Z1 of level 1 is not stored:
+        // level 1 reads it from Z1
+        st_packed(blk(L0.Z1(), h, NTRI), Pm, w * w);
     } else {
-        ld_lower(blk(L0.Li(), h, NBLK), Li);
+        ld_packed(blk(L0.Li(), h, NTRI), Li);
     }
     double r[NJ], s[NJ], c[NJ];
 #pragma unroll
@@ -572,7 +587,7 @@ __device__ __forceinline__ void cr_even(const DevPlan &P, int T, double lam, dou
                                         int lev, int jj, bool factor, const CPF_GLOBAL double *rhs, double sgn) {
     double D[NTRI], r[NJ];
     cr_form_lane(P, T, lam, ws, Lp, lev, 2 * jj, factor, rhs, sgn, D, r);
-    if (factor) st_full(blk(L.DE(), jj, NBLK), D, true, 1.0);
+    if (factor) st_packed(blk(L.DE(), jj, NTRI), D, 1.0);
     CPF_GLOBAL double *ro = blk(L.rE(), jj, NJ);
 #pragma unroll
     for (int e = 0; e < NJ; ++e) ro[e] = r[e];
@@ -592,9 +607,9 @@ __device__ __forceinline__ void cr_top_solve(const DevPlan &P, int T, double lam
     }
     if (factor) {
         chol_inverse(Li, ok);
-        st_full(blk(L.Li(), 0, NBLK), Li, false, 1.0);
+        st_packed(blk(L.Li(), 0, NTRI), Li, 1.0);
     } else {
-        ld_lower(blk(L.Li(), 0, NBLK), Li);
+        ld_packed(blk(L.Li(), 0, NTRI), Li);
     }
     tri_mv(Li, r, s);
     tri_tmv(Li, s, x);
@@ -613,16 +628,10 @@ __device__ __forceinline__ void cr_odd_factor(const DevPlan &P, int T, double la
                                               const CPF_GLOBAL double *rhs, double sgn, double *ex, bool &ok) {
     const int i = 2 * h + 1;
     const bool right = i + 1 < L.n;
-    // column c of E_i and row c of E_{i+1}, loaded first (used after the factor)
-    const CPF_GLOBAL double *Ei = blk(L.E(), i, NBLK) + c;
-    const CPF_GLOBAL double *Er = blk(L.E(), right ? i + 1 : i, NBLK) + c * NJ;
+    // column c of E_i and row c of E_{i+1}, loaded first (used after the
+    // factor); on level 1, E_i = -Z1 of odd block i-1 of level 0 (symmetric)
     double e[NJ], f[NJ];
-#pragma unroll
-    for (int k = 0; k < NJ; ++k) {
-        e[k] = Ei[k * NJ];
-        const double fk = Er[k];
-        f[k] = right ? fk : 0.0;
-    }
+    cr_coupling_cols(L, Lp, lev, i, right, c, e, f);
     // the group forms D_i and r_i column by column and shares them
     {
         double d[NJ], rc;
@@ -659,19 +668,24 @@ __device__ __forceinline__ void cr_odd_factor(const DevPlan &P, int T, double la
     }
     blk(L.c1(), h, NJ)[c] = c1;
     blk(L.c2(), h, NJ)[c] = c2;
-    // Li (whole block, zeros above the diagonal) and s: element q by lane q % 7
-    CPF_GLOBAL double *Lo = blk(L.Li(), h, NBLK);
+    // Li (packed lower triangle) column c and s_c by lane c, picked out of
+    // the registers every lane of the group holds
+    CPF_GLOBAL double *Lo = blk(L.Li(), h, NTRI) + c;
 #pragma unroll
-    for (int a = 0; a < NJ; ++a)
+    for (int a = 0; a < NJ; ++a) {
+        double lv = Li[tri_index(a, 0)];
 #pragma unroll
-        for (int b = 0; b < NJ; ++b)
-            if (b == c) Lo[a * NJ + b] = b <= a ? Li[tri_index(a, b)] : 0.0;
+        for (int b = 1; b <= a; ++b) lv = c == b ? Li[tri_index(a, b)] : lv;
+        if (a >= c) Lo[tri_index(a, 0)] = lv;
+    }
+    double sc = s[0];
 #pragma unroll
-    for (int a = 0; a < NJ; ++a)
-        if (a == c) blk(L.s(), h, NJ)[a] = s[a];
+    for (int a = 1; a < NJ; ++a) sc = c == a ? s[a] : sc;
+    blk(L.s(), h, NJ)[c] = sc;
     group_sync();
-    // column c of W^T W, V^T V and -V^T W (the coupling of level lev+1)
-    CPF_GLOBAL double *Z1c = blk(L.Z1(), h, NBLK) + c, *Z2c = blk(L.Z2(), h, NBLK) + c;
+    // column c of W^T W, V^T V (symmetric: rows a >= c, packed) and -V^T W
+    // (the coupling of level lev+1, whole)
+    CPF_GLOBAL double *Z1c = blk(L.Z1(), h, NTRI) + c, *Z2c = blk(L.Z2(), h, NTRI) + c;
     CPF_GLOBAL double *Enc = blk(Ln.E(), right ? (i + 1) / 2 : 0, NBLK) + c;
 #pragma unroll
     for (int a = 0; a < NJ; ++a) {
@@ -683,8 +697,10 @@ __device__ __forceinline__ void cr_odd_factor(const DevPlan &P, int T, double la
             z2 = fma(va, v[k], z2);
             en = fma(va, w[k], en);
         }
-        Z1c[a * NJ] = z1;
-        Z2c[a * NJ] = z2;
+        if (a >= c) {
+            Z1c[tri_index(a, 0)] = z1;
+            Z2c[tri_index(a, 0)] = z2;
+        }
         if (right) Enc[a * NJ] = -en;
     }
     group_sync();   // ex is rewritten by the group's next block
@@ -696,12 +712,15 @@ __device__ __forceinline__ void cr_odd_rhs(const DevPlan &P, int T, const CRLeve
                                            int h, int c, const CPF_GLOBAL double *rhs, double sgn, double *ex) {
     const int i = 2 * h + 1;
     // row c of Li and column c of W and V, loaded with the right-hand side
-    const CPF_GLOBAL double *Lr = blk(L.Li(), h, NBLK) + c * NJ;
+    // (Li packed: its row c starts at tri_index(c, 0); the loads past the
+    // diagonal stay inside the block and are replaced by zero)
+    const CPF_GLOBAL double *Lr = blk(L.Li(), h, NTRI) + tri_index(c, 0);
     const CPF_GLOBAL double *Wc = blk(L.W(), h, NBLK) + c, *Vc = blk(L.V(), h, NBLK) + c;
     double lr[NJ], wc[NJ], vc[NJ];
 #pragma unroll
     for (int k = 0; k < NJ; ++k) {
-        lr[k] = Lr[k];
+        const double l = Lr[k];
+        lr[k] = k <= c ? l : 0.0;   // zero above the diagonal
         wc[k] = Wc[k * NJ];
         vc[k] = Vc[k * NJ];
     }
@@ -735,10 +754,15 @@ __device__ __forceinline__ void cr_back_group(const CRLevel &L, const CRLevel &L
     const bool right = i + 1 < L.n;
     const CPF_GLOBAL double *xl = blk(Ln.X(), (i - 1) / 2, NJ), *xr = blk(Ln.X(), right ? (i + 1) / 2 : 0, NJ);
     const CPF_GLOBAL double *Wr = blk(L.W(), h, NBLK) + c * NJ, *Vr = blk(L.V(), h, NBLK) + c * NJ;
-    const CPF_GLOBAL double *Lc = blk(L.Li(), h, NBLK) + c;   // column c of Li (zeros above)
+    // column c of Li (packed; the loads above the diagonal stay inside the
+    // block and are replaced by zero)
+    const CPF_GLOBAL double *Lc = blk(L.Li(), h, NTRI) + c;
     double lc[NJ];
 #pragma unroll
-    for (int a = 0; a < NJ; ++a) lc[a] = Lc[a * NJ];
+    for (int a = 0; a < NJ; ++a) {
+        const double l = Lc[tri_index(a, 0)];
+        lc[a] = a >= c ? l : 0.0;   // zero above the diagonal
+    }
     double acc = blk(L.s(), h, NJ)[c];
 #pragma unroll
     for (int k = 0; k < NJ; ++k) {
@@ -772,7 +796,7 @@ __device__ __forceinline__ void cr_back_lane(const DevPlan &P, int T, double ws,
             const double vr = xr[e];
             u[e] = xl[e] + (right ? vr : 0.0);
         }
-        ld_lower(blk(L.Li(), h, NBLK), Li);
+        ld_packed(blk(L.Li(), h, NTRI), Li);
         tri_mv(Li, u, v);
 #pragma unroll
         for (int e = 0; e < NJ; ++e) y[e] = fma(ws, v[e], so[e]);
@@ -787,6 +811,272 @@ __device__ __forceinline__ void cr_back_lane(const DevPlan &P, int T, double ws,
         if (lev == 0) out[(size_t)e * T + x] = xv[e];
         else blk(L.X(), x, NJ)[e] = xv[e];
     }
+}
+
+// ---------------------------------------------------------------------------
+// The small levels in one wavefront.
+//
+// From the first level of at most CR_TAIL_N = 2 CR_GPW + 1 blocks on (level
+// 1 at the earliest), every level's odd blocks fit the groups of a single
+// wavefront.  Wavefront 0 then runs all the remaining levels, forward and
+// back, with the blocks in LDS and wave barriers between the steps, while
+// the other wavefronts wait at the workgroup barrier after it.  The
+// arithmetic is that of the rounds above, operation for operation.  Blocks
+// are updated in place: block b of the k-th level of the tail lives in slot
+// b 2^k of the entry level's arrays, so an even block is already where the
+// next level looks for it, and the two Schur contributions to an even block
+// are subtracted in two steps (first from its right odd neighbour, then from
+// its left one, as the rounds above form it).  The factored blocks (Li, W,
+// V whole and s) stay in LDS for further right-hand sides; a level's x goes
+// back to global memory only at the entry level, for the rounds below.
+// ---------------------------------------------------------------------------
+
+constexpr int CR_TAIL_N = 2 * CR_GPW + 1;      // blocks of the entry level, at most
+constexpr int CR_TAIL_FB = 3 * NBLK + NJ;      // LDS doubles per factored block: Li, W, V, s
+constexpr int CR_TAIL_FS = CR_TAIL_N * CR_TAIL_FB;
+constexpr int CR_TAIL_WK = CR_TAIL_N * (2 * NBLK + 2 * NJ);   // D, E, r, x of the entry level
+
+// First level of the tail: the first with at most CR_TAIL_N blocks, and at
+// least 1 (level 0 has its own one-lane-per-block round).
+__device__ __forceinline__ int cr_tail_level(int T) {
+    int lev = 0;
+    for (int n = T; n > CR_TAIL_N; n = (n + 1) / 2) ++lev;
+    return lev > 0 ? lev : 1;
+}
+
+#ifdef CPF_PHASE_CYCLES
+// Diagnostic build only: shader-clock totals of the steps of the tail's
+// forward levels (thread 0, block 0): 0 block loads, 1 Cholesky and inverse,
+// 2 products with Li and the W, V stores, 3 Li and s stores, 4 Z columns,
+// 5 left update, 6 right update; 8 entry, 9 top, 10 back levels, 11 exit.
+__device__ unsigned long long cr_tail_cycles[2][12];
+#define CR_TAIL_MARK(kind, k)                                           \
+    do {                                                                \
+        if (threadIdx.x == 0 && blockIdx.x == 0) {                      \
+            const unsigned long long now_ = clock64();                  \
+            cr_tail_cycles[kind][k] += now_ - tl_last_;                 \
+            tl_last_ = now_;                                            \
+        }                                                               \
+    } while (0)
+#else
+#define CR_TAIL_MARK(kind, k) \
+    do {                      \
+    } while (0)
+#endif
+
+// Wavefront 0 only (lanes 0..62 in groups of 7; lane 63 idles).  Solves
+// levels lw..top of the system whose levels below lw are in `base`,
+// factoring them first (factor) or reusing the factored blocks in fs.
+__device__ void cr_tail(const DevPlan &P, int T, double lam, double ws, bool factor, const CPF_GLOBAL double *rhs,
+                        double sgn, CPF_GLOBAL double *base, int lw, double *fs, double *wk, bool &ok) {
+    const int lane = threadIdx.x & 63;
+    const int g = lane < 63 ? lane / NJ : CR_GPW;   // lane 63: a group of its own that never has a block
+    const int c = lane < 63 ? lane % NJ : 0;
+    double *D = wk, *E = D + CR_TAIL_N * NBLK, *R = E + CR_TAIL_N * NBLK, *X = R + CR_TAIL_N * NJ;
+    const CRLevel Lp = cr_level(base, T, lw - 1), L = cr_level(base, T, lw);
+    const int n = L.n;
+#ifdef CPF_PHASE_CYCLES
+    unsigned long long tl_last_ = clock64();
+    const int kd = factor ? 0 : 1;
+#endif
+
+    // Entry: the blocks of level lw formed from level lw-1 (column c by lane c).
+    if (g < CR_GPW) {
+        for (int j = g; j < n; j += CR_GPW) {
+            double d[NJ], rc;
+            cr_form_col(P, T, lam, ws, Lp, lw, j, c, factor, rhs, sgn, d, rc);
+            R[j * NJ + c] = rc;
+            if (factor) {
+#pragma unroll
+                for (int a = 0; a < NJ; ++a) D[j * NBLK + a * NJ + c] = d[a];
+                if (j >= 1) {   // E_j, column c
+                    double e[NJ], f[NJ];
+                    cr_coupling_cols(L, Lp, lw, j, false, c, e, f);
+#pragma unroll
+                    for (int k = 0; k < NJ; ++k) E[j * NBLK + k * NJ + c] = e[k];
+                }
+            }
+        }
+    }
+    group_sync();
+    CR_TAIL_MARK(kd, 8);
+
+    // Forward: level by level up to the single top block.
+    int nk = n, st = 1, fb = 0;
+    for (; nk > 1; fb += nk / 2, nk = (nk + 1) / 2, st *= 2) {
+        const int no = nk / 2;
+        const int i = 2 * g + 1;
+        const bool mine = g < no, right = i + 1 < nk;
+        const int pi = i * st, pl = (i - 1) * st, pr = right ? (i + 1) * st : pi;
+        double *F = fs + (size_t)(fb + (mine ? g : 0)) * CR_TAIL_FB;
+        double *Fl = F, *Fw = F + NBLK, *Fv = F + 2 * NBLK, *Fs = F + 3 * NBLK;
+        double z1[NJ], z2[NJ], en[NJ], c1 = 0.0, c2 = 0.0;
+        if (mine) {
+            if (factor) {
+                double Li[NTRI], rv[NJ], e[NJ], f[NJ], s[NJ], w[NJ], v[NJ];
+#pragma unroll
+                for (int a = 0; a < NJ; ++a) {
+#pragma unroll
+                    for (int b = 0; b <= a; ++b) Li[tri_index(a, b)] = D[pi * NBLK + a * NJ + b];
+                    rv[a] = R[pi * NJ + a];
+                }
+#pragma unroll
+                for (int k = 0; k < NJ; ++k) {
+                    e[k] = E[pi * NBLK + k * NJ + c];
+                    const double fk = E[pr * NBLK + c * NJ + k];
+                    f[k] = right ? fk : 0.0;
+                }
+                CR_TAIL_MARK(0, 0);
+                chol_inverse(Li, ok);
+                CR_TAIL_MARK(0, 1);
+                tri_mv(Li, rv, s);
+                tri_mv(Li, e, w);
+                tri_mv(Li, f, v);
+#pragma unroll
+                for (int k = 0; k < NJ; ++k) {
+                    c1 = fma(w[k], s[k], c1);
+                    c2 = fma(v[k], s[k], c2);
+                    Fw[k * NJ + c] = w[k];
+                    Fv[k * NJ + c] = v[k];
+                }
+                CR_TAIL_MARK(0, 2);
+                // the lower triangle of Li and s, the same values from every
+                // lane of the group
+#pragma unroll
+                for (int a = 0; a < NJ; ++a) {
+#pragma unroll
+                    for (int b = 0; b <= a; ++b) Fl[a * NJ + b] = Li[tri_index(a, b)];
+                    Fs[a] = s[a];
+                }
+                group_sync();
+                CR_TAIL_MARK(0, 3);
+                // column c of W^T W, V^T V and -V^T W
+#pragma unroll
+                for (int a = 0; a < NJ; ++a) {
+                    double x1 = 0.0, x2 = 0.0, x3 = 0.0;
+#pragma unroll
+                    for (int k = 0; k < NJ; ++k) {
+                        const double wa = Fw[k * NJ + a], va = Fv[k * NJ + a];
+                        x1 = fma(wa, w[k], x1);
+                        x2 = fma(va, v[k], x2);
+                        x3 = fma(va, w[k], x3);
+                    }
+                    z1[a] = x1;
+                    z2[a] = x2;
+                    en[a] = x3;
+                }
+                CR_TAIL_MARK(0, 4);
+            } else {
+                // s = Li r_i (row c of Li), shared through Fs, then W^T s and V^T s
+                double sc = 0.0;
+#pragma unroll
+                for (int k = 0; k < NJ; ++k) {
+                    const double l = Fl[c * NJ + k];
+                    sc = fma(k <= c ? l : 0.0, R[pi * NJ + k], sc);
+                }
+                group_sync();
+                Fs[c] = sc;
+                group_sync();
+#pragma unroll
+                for (int k = 0; k < NJ; ++k) {
+                    const double sk = Fs[k];
+                    c1 = fma(Fw[k * NJ + c], sk, c1);
+                    c2 = fma(Fv[k * NJ + c], sk, c2);
+                }
+            }
+            // left even neighbour: the contribution of its right odd neighbour
+            if (factor)
+#pragma unroll
+                for (int a = 0; a < NJ; ++a) D[pl * NBLK + a * NJ + c] -= z1[a];
+            R[pl * NJ + c] -= c1;
+        }
+        group_sync();
+        CR_TAIL_MARK(kd, 5);
+        if (mine && right) {   // right even neighbour: the contribution of its left odd neighbour
+            if (factor)
+#pragma unroll
+                for (int a = 0; a < NJ; ++a) {
+                    D[pr * NBLK + a * NJ + c] -= z2[a];
+                    E[pr * NBLK + a * NJ + c] = -en[a];   // coupling of level k+1 (slot of block i+1)
+                }
+            R[pr * NJ + c] -= c2;
+        }
+        group_sync();
+        CR_TAIL_MARK(kd, 6);
+    }
+
+    // Top block (slot 0): x = Li^T Li r, by group 0.
+    if (g == 0) {
+        double *Fl = fs + (size_t)fb * CR_TAIL_FB;
+        double Li[NTRI], rv[NJ], s[NJ], x[NJ];
+#pragma unroll
+        for (int a = 0; a < NJ; ++a) rv[a] = R[a];
+        if (factor) {
+#pragma unroll
+            for (int a = 0; a < NJ; ++a)
+#pragma unroll
+                for (int b = 0; b <= a; ++b) Li[tri_index(a, b)] = D[a * NJ + b];
+            chol_inverse(Li, ok);
+#pragma unroll
+            for (int a = 0; a < NJ; ++a)
+#pragma unroll
+                for (int b = 0; b <= a; ++b) Fl[a * NJ + b] = Li[tri_index(a, b)];
+        } else {
+#pragma unroll
+            for (int a = 0; a < NJ; ++a)
+#pragma unroll
+                for (int b = 0; b <= a; ++b) Li[tri_index(a, b)] = Fl[a * NJ + b];
+        }
+        tri_mv(Li, rv, s);
+        tri_tmv(Li, s, x);
+#pragma unroll
+        for (int a = 0; a < NJ; ++a) X[a] = x[a];
+    }
+    group_sync();
+    CR_TAIL_MARK(kd, 9);
+
+    // Back: x_i = Li^T (s_i - W x_{i-1} - V x_{i+1}) for the odd blocks, from
+    // the level below the top down to the entry level.
+    while (st > 1) {
+        st /= 2;
+        // the level with slot stride st: its block count and first factored block
+        int m = n, f0 = 0;
+        for (int s2 = 1; s2 < st; s2 *= 2) {
+            f0 += m / 2;
+            m = (m + 1) / 2;
+        }
+        const int i = 2 * g + 1;
+        if (g < m / 2) {
+            const bool right = i + 1 < m;
+            const int pi = i * st, pl = (i - 1) * st, pr = right ? (i + 1) * st : pl;
+            const double *F = fs + (size_t)(f0 + g) * CR_TAIL_FB;
+            const double *Fl = F, *Fw = F + NBLK, *Fv = F + 2 * NBLK, *Fs = F + 3 * NBLK;
+            double acc = Fs[c];
+#pragma unroll
+            for (int k = 0; k < NJ; ++k) {
+                const double xr = X[pr * NJ + k];
+                acc = fma(-Fw[c * NJ + k], X[pl * NJ + k], acc);
+                acc = fma(-Fv[c * NJ + k], right ? xr : 0.0, acc);
+            }
+            X[pi * NJ + c] = acc;
+            group_sync();
+            double x = 0.0;
+#pragma unroll
+            for (int a = 0; a < NJ; ++a) {
+                const double l = Fl[a * NJ + c];
+                x = fma(a >= c ? l : 0.0, X[pi * NJ + a], x);
+            }
+            group_sync();
+            X[pi * NJ + c] = x;
+        }
+        group_sync();
+        CR_TAIL_MARK(kd, 10);
+    }
+
+    // x of the entry level for the back-substitution rounds below it
+    if (g < CR_GPW)
+        for (int j = g; j < n; j += CR_GPW) blk(L.X(), j, NJ)[c] = X[j * NJ + c];
+    CR_TAIL_MARK(kd, 11);
 }
 
 #ifdef CPF_PHASE_CYCLES
@@ -810,16 +1100,21 @@ __device__ unsigned long long cr_round_cycles[2][64];
 // reusing the stored factors; x goes to out ([7][T], may alias rhs: the
 // right-hand side is read only in the first two forward rounds).  Returns
 // false on a pivot that is not positive.  All threads of the workgroup;
-// exch: CR_GROUPS x CR_EX doubles of LDS.
+// exch: CR_GROUPS x CR_EX doubles of LDS; tfs, twk: CR_TAIL_FS and
+// CR_TAIL_WK doubles of LDS for the small levels (tfs kept between the
+// factoring solve and the further right-hand sides).
 __device__ __forceinline__ bool cr_solve(const DevPlan &P, int T, double lam, double ws, bool factor,
                                          const CPF_GLOBAL double *rhs, double sgn, CPF_GLOBAL double *out,
-                                         int *bad, double *exch) {
+                                         int *bad, double *exch, double *tfs, double *twk) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int gid = lane < 63 ? (tid >> 6) * CR_GPW + lane / NJ : -1;
     const int gc = lane < 63 ? lane % NJ : 0;
     double *ex = exch + (size_t)(gid >= 0 ? gid : 0) * CR_EX;
     const int top = cr_top(T);
+    // levels below lw run as workgroup rounds, lw..top in wavefront 0
+    // (a single waypoint: level 0 is the top, solved by one lane)
+    const int lw = top >= 1 ? cr_tail_level(T) : 1;
     CPF_GLOBAL double *base = P.cr;
     bool ok = true;
     if (tid == 0) *bad = 0;
@@ -827,14 +1122,13 @@ __device__ __forceinline__ bool cr_solve(const DevPlan &P, int T, double lam, do
     unsigned long long cr_last_ = clock64();
 #endif
     // forward rounds
-    for (int lev = 0; lev <= top; ++lev) {
+    for (int lev = 0; lev < lw; ++lev) {
         const CRLevel L = cr_level(base, T, lev);
         const CRLevel Lp = cr_level(base, T, lev > 0 ? lev - 1 : 0);
         if (lev == top) {
             if (tid == 0) cr_top_solve(P, T, lam, ws, Lp, L, lev, factor, rhs, sgn, out, ok);
         } else if (lev == 0) {
-            const CRLevel L1 = cr_level(base, T, 1);
-            for (int h = tid; h < L.no; h += LM_BS) cr_odd_level0(P, T, lam, ws, L, L1, h, factor, rhs, sgn, ok);
+            for (int h = tid; h < L.no; h += LM_BS) cr_odd_level0(P, T, lam, ws, L, h, factor, rhs, sgn, ok);
         } else {
             const CRLevel Ln = cr_level(base, T, lev + 1);
             if (gid >= 0) {
@@ -850,9 +1144,14 @@ __device__ __forceinline__ bool cr_solve(const DevPlan &P, int T, double lam, do
         __syncthreads();
         CR_ROUND_MARK(factor ? 0 : 1, lev);
     }
+    if (top >= 1) {
+        if (tid < 64) cr_tail(P, T, lam, ws, factor, rhs, sgn, base, lw, tfs, twk, ok);
+        __syncthreads();
+        CR_ROUND_MARK(factor ? 0 : 1, 31);
+    }
     if (!ok) *bad = 1;
-    // back-substitution rounds
-    for (int lev = top - 1; lev >= 0; --lev) {
+    // back-substitution rounds below the tail
+    for (int lev = top >= 1 ? lw - 1 : -1; lev >= 0; --lev) {
         const CRLevel L = cr_level(base, T, lev);
         const CRLevel Ln = cr_level(base, T, lev + 1);
         if (lev == 0) {
@@ -899,14 +1198,20 @@ __device__ __forceinline__ bool diag_solve(const DevPlan &P, int T, double lam, 
 __device__ __forceinline__ void refine_residual(const DevPlan &P, int T, double lam, double ws) {
     const double w = ws;
     for (int t = threadIdx.x; t < T; t += LM_BS) {
-        double d[NJ];
+        double d[NJ], A[NTRI];
 #pragma unroll
         for (int c = 0; c < NJ; ++c) d[c] = P.dx[(size_t)c * T + t];
+        ld_packed(blk(P.A, t, NTRI), A);
+        const int ct = (t > 0) + (t + 1 < T);
 #pragma unroll
         for (int r = 0; r < NJ; ++r) {
             double h = 0.0;
 #pragma unroll
-            for (int c = 0; c < NJ; ++c) h += d_elem(P, T, t, r, c, lam, ws) * d[c];
+            for (int c = 0; c < NJ; ++c) {
+                double v = A[sym_index(r, c)];   // element (r, c) of D_t = A_t + (w_s c_t + lambda) I
+                if (r == c) v += ws * ct + lam;
+                h += v * d[c];
+            }
             if (t > 0) h -= w * P.dx[(size_t)r * T + t - 1];
             if (t + 1 < T) h -= w * P.dx[(size_t)r * T + t + 1];
             P.rb[(size_t)r * T + t] = -P.g[(size_t)r * T + t] - h;
@@ -1094,6 +1399,7 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
 
     __shared__ int sh_bad;
     __shared__ double exch[CR_GROUPS * CR_EX];
+    __shared__ double tail_fs[CR_TAIL_FS], tail_wk[CR_TAIL_WK];
 #ifdef CPF_PHASE_CYCLES
     // Diagnostic build only: per-phase shader-clock totals printed by thread 0.
     uint64_t ph[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -1168,7 +1474,7 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
                                 ? diag_solve(P, T, lam, first ? P.g : P.rb, first ? -1.0 : 1.0,
                                              first ? P.dx : P.rb, &sh_bad)
                                 : cr_solve(P, T, lam, ws, first, first ? P.g : P.rb, first ? -1.0 : 1.0,
-                                           first ? P.dx : P.rb, &sh_bad, exch);
+                                           first ? P.dx : P.rb, &sh_bad, exch, tail_fs, tail_wk);
             if (first) {
                 if (tid == 0) sh_flags[3] = ok ? 0 : 1;
                 PHASE_MARK(1);
@@ -1270,9 +1576,18 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
         for (int k = 0; k < 2; ++k) {
             printf("cr rounds %s:", k ? "rhs" : "factor");
             for (int r = 0; r < 64; ++r)
-                if (cr_round_cycles[k][r]) printf(" %s%d=%llu", r >= 32 ? "b" : "f", r & 31, cr_round_cycles[k][r]);
+                if (cr_round_cycles[k][r] && r == 31) printf(" tail=%llu", cr_round_cycles[k][r]);
+                else if (cr_round_cycles[k][r]) printf(" %s%d=%llu", r >= 32 ? "b" : "f", r & 31, cr_round_cycles[k][r]);
             printf("\n");
             for (int r = 0; r < 64; ++r) cr_round_cycles[k][r] = 0;
+        }
+        for (int k = 0; k < 2; ++k) {
+            printf("tail steps %s:", k ? "rhs" : "factor");
+            for (int r = 0; r < 12; ++r) {
+                if (cr_tail_cycles[k][r]) printf(" s%d=%llu", r, cr_tail_cycles[k][r]);
+                cr_tail_cycles[k][r] = 0;
+            }
+            printf("\n");
         }
     }
 #endif
