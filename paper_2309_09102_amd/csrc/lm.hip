@@ -40,33 +40,63 @@ constexpr int LM_BS = 512;
 // 2000.
 constexpr int LM_ITER_FIXED = 330;
 
-__device__ __forceinline__ double block_sum(double v, double *red) {
+// Workgroup sum and maximum of one value per thread, by a fixed tree
+// (v_t + v_{t+256}, then + v_{t+128}, ... down to + v_{t+1}), so that every
+// run adds in the same order: the three steps across wavefronts go through
+// LDS with a barrier each, the six inside wavefront 0 through lane shuffles.
+template <bool MAX>
+__device__ __forceinline__ double block_reduce(double v, double *red) {
+    static_assert(LM_BS == 512, "three steps across wavefronts, six inside one");
     const int tid = threadIdx.x;
     red[tid] = v;
     __syncthreads();
 #pragma unroll
-    for (int s = LM_BS / 2; s > 0; s >>= 1) {
-        if (tid < s) red[tid] += red[tid + s];
+    for (int s = LM_BS / 2; s >= 128; s >>= 1) {
+        if (tid < s) red[tid] = MAX ? fmax(red[tid], red[tid + s]) : red[tid] + red[tid + s];
         __syncthreads();
     }
+    if (tid < 64) {
+        double x = MAX ? fmax(red[tid], red[tid + 64]) : red[tid] + red[tid + 64];
+#pragma unroll
+        for (int s = 32; s > 0; s >>= 1) {
+            const double y = __shfl_down(x, s, 64);
+            x = MAX ? fmax(x, y) : x + y;
+        }
+        if (tid == 0) red[0] = x;
+    }
+    __syncthreads();
     const double r = red[0];
     __syncthreads();
     return r;
 }
+__device__ __forceinline__ double block_sum(double v, double *red) { return block_reduce<false>(v, red); }
+__device__ __forceinline__ double block_max(double v, double *red) { return block_reduce<true>(v, red); }
 
-__device__ __forceinline__ double block_max(double v, double *red) {
-    const int tid = threadIdx.x;
-    red[tid] = v;
-    __syncthreads();
-#pragma unroll
-    for (int s = LM_BS / 2; s > 0; s >>= 1) {
-        if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
-        __syncthreads();
-    }
-    const double r = red[0];
-    __syncthreads();
-    return r;
-}
+#ifdef CPF_PHASE_CYCLES
+// Diagnostic build only: shader-clock totals of the iteration's phases, the
+// solve's rounds and the steps of its one-wavefront levels, summed over a
+// launch by thread 0 of each workgroup; workgroup 0 prints them at its end.
+// All of it, the last clock readings included (one for the phases, one for
+// the rounds and steps inside a solve), lives in LDS, so the marks hold no
+// registers across the code they time.  Reading the clock waits for the
+// wavefront's outstanding LDS operations.
+__shared__ unsigned long long diag_last[2];
+__shared__ unsigned long long diag_phase[8];
+__shared__ unsigned long long diag_round[2][64];
+__shared__ unsigned long long diag_tail[2][12];
+#define DIAG_MARK(slot, clk)                           \
+    do {                                               \
+        if (threadIdx.x == 0) {                        \
+            const unsigned long long now_ = clock64(); \
+            (slot) += now_ - diag_last[clk];           \
+            diag_last[clk] = now_;                     \
+        }                                              \
+    } while (0)
+#else
+#define DIAG_MARK(slot, clk) \
+    do {                     \
+    } while (0)
+#endif
 
 template <typename S>
 __device__ __forceinline__ void load_target(const DevPlan &P, int T, int t, S tg[12]) {
@@ -844,23 +874,16 @@ __device__ __forceinline__ int cr_tail_level(int T) {
     return lev > 0 ? lev : 1;
 }
 
-#ifdef CPF_PHASE_CYCLES
-// Diagnostic build only: shader-clock totals of the steps of the tail's
-// forward levels (thread 0, block 0): 0 block loads, 1 Cholesky and inverse,
-// 2 products with Li and the W, V stores, 3 Li and s stores, 4 Z columns,
-// 5 left update, 6 right update; 8 entry, 9 top, 10 back levels, 11 exit.
-__device__ unsigned long long cr_tail_cycles[2][12];
-#define CR_TAIL_MARK(kind, k)                                           \
-    do {                                                                \
-        if (threadIdx.x == 0 && blockIdx.x == 0) {                      \
-            const unsigned long long now_ = clock64();                  \
-            cr_tail_cycles[kind][k] += now_ - tl_last_;                 \
-            tl_last_ = now_;                                            \
-        }                                                               \
-    } while (0)
+// Steps of the one-wavefront levels (diagnostic build with CPF_TAIL_STEPS as
+// well; the marks change how the compiler schedules these steps): 0 block
+// loads, 1 Cholesky and inverse, 2 products with Li and the W, V stores, 3
+// Li and s stores, 4 Z columns, 5 left update, 6 right update; 8 entry, 9
+// top, 10 back levels, 11 exit.
+#ifdef CPF_TAIL_STEPS
+#define CR_TAIL_MARK(k) DIAG_MARK(diag_tail[factor ? 0 : 1][k], 1)
 #else
-#define CR_TAIL_MARK(kind, k) \
-    do {                      \
+#define CR_TAIL_MARK(k) \
+    do {                \
     } while (0)
 #endif
 
@@ -875,10 +898,6 @@ __device__ void cr_tail(const DevPlan &P, int T, double lam, double ws, bool fac
     double *D = wk, *E = D + CR_TAIL_N * NBLK, *R = E + CR_TAIL_N * NBLK, *X = R + CR_TAIL_N * NJ;
     const CRLevel Lp = cr_level(base, T, lw - 1), L = cr_level(base, T, lw);
     const int n = L.n;
-#ifdef CPF_PHASE_CYCLES
-    unsigned long long tl_last_ = clock64();
-    const int kd = factor ? 0 : 1;
-#endif
 
     // Entry: the blocks of level lw formed from level lw-1 (column c by lane c).
     if (g < CR_GPW) {
@@ -899,7 +918,7 @@ __device__ void cr_tail(const DevPlan &P, int T, double lam, double ws, bool fac
         }
     }
     group_sync();
-    CR_TAIL_MARK(kd, 8);
+    CR_TAIL_MARK(8);
 
     // Forward: level by level up to the single top block.
     int nk = n, st = 1, fb = 0;
@@ -926,9 +945,9 @@ __device__ void cr_tail(const DevPlan &P, int T, double lam, double ws, bool fac
                     const double fk = E[pr * NBLK + c * NJ + k];
                     f[k] = right ? fk : 0.0;
                 }
-                CR_TAIL_MARK(0, 0);
+                CR_TAIL_MARK(0);
                 chol_inverse(Li, ok);
-                CR_TAIL_MARK(0, 1);
+                CR_TAIL_MARK(1);
                 tri_mv(Li, rv, s);
                 tri_mv(Li, e, w);
                 tri_mv(Li, f, v);
@@ -939,7 +958,7 @@ __device__ void cr_tail(const DevPlan &P, int T, double lam, double ws, bool fac
                     Fw[k * NJ + c] = w[k];
                     Fv[k * NJ + c] = v[k];
                 }
-                CR_TAIL_MARK(0, 2);
+                CR_TAIL_MARK(2);
                 // the lower triangle of Li and s, the same values from every
                 // lane of the group
 #pragma unroll
@@ -949,7 +968,7 @@ __device__ void cr_tail(const DevPlan &P, int T, double lam, double ws, bool fac
                     Fs[a] = s[a];
                 }
                 group_sync();
-                CR_TAIL_MARK(0, 3);
+                CR_TAIL_MARK(3);
                 // column c of W^T W, V^T V and -V^T W
 #pragma unroll
                 for (int a = 0; a < NJ; ++a) {
@@ -965,7 +984,7 @@ __device__ void cr_tail(const DevPlan &P, int T, double lam, double ws, bool fac
                     z2[a] = x2;
                     en[a] = x3;
                 }
-                CR_TAIL_MARK(0, 4);
+                CR_TAIL_MARK(4);
             } else {
                 // s = Li r_i (row c of Li), shared through Fs, then W^T s and V^T s
                 double sc = 0.0;
@@ -991,7 +1010,7 @@ __device__ void cr_tail(const DevPlan &P, int T, double lam, double ws, bool fac
             R[pl * NJ + c] -= c1;
         }
         group_sync();
-        CR_TAIL_MARK(kd, 5);
+        CR_TAIL_MARK(5);
         if (mine && right) {   // right even neighbour: the contribution of its left odd neighbour
             if (factor)
 #pragma unroll
@@ -1002,7 +1021,7 @@ __device__ void cr_tail(const DevPlan &P, int T, double lam, double ws, bool fac
             R[pr * NJ + c] -= c2;
         }
         group_sync();
-        CR_TAIL_MARK(kd, 6);
+        CR_TAIL_MARK(6);
     }
 
     // Top block (slot 0): x = Li^T Li r, by group 0.
@@ -1033,7 +1052,7 @@ __device__ void cr_tail(const DevPlan &P, int T, double lam, double ws, bool fac
         for (int a = 0; a < NJ; ++a) X[a] = x[a];
     }
     group_sync();
-    CR_TAIL_MARK(kd, 9);
+    CR_TAIL_MARK(9);
 
     // Back: x_i = Li^T (s_i - W x_{i-1} - V x_{i+1}) for the odd blocks, from
     // the level below the top down to the entry level.
@@ -1070,31 +1089,16 @@ __device__ void cr_tail(const DevPlan &P, int T, double lam, double ws, bool fac
             X[pi * NJ + c] = x;
         }
         group_sync();
-        CR_TAIL_MARK(kd, 10);
+        CR_TAIL_MARK(10);
     }
 
     // x of the entry level for the back-substitution rounds below it
     if (g < CR_GPW)
         for (int j = g; j < n; j += CR_GPW) blk(L.X(), j, NJ)[c] = X[j * NJ + c];
-    CR_TAIL_MARK(kd, 11);
+    CR_TAIL_MARK(11);
 }
 
-#ifdef CPF_PHASE_CYCLES
-// Diagnostic build only: shader-clock totals per solve round (block 0).
-__device__ unsigned long long cr_round_cycles[2][64];
-#define CR_ROUND_MARK(kind, r)                                                     \
-    do {                                                                           \
-        if (threadIdx.x == 0 && blockIdx.x == 0) {                                 \
-            const unsigned long long now_ = clock64();                             \
-            cr_round_cycles[kind][(r) & 63] += now_ - cr_last_;                     \
-            cr_last_ = now_;                                                       \
-        }                                                                          \
-    } while (0)
-#else
-#define CR_ROUND_MARK(kind, r) \
-    do {                       \
-    } while (0)
-#endif
+#define CR_ROUND_MARK(kind, r) DIAG_MARK(diag_round[kind][(r) & 63], 1)
 
 // Solve H x = sgn * rhs ([7][T]), factoring H first (factor = true) or
 // reusing the stored factors; x goes to out ([7][T], may alias rhs: the
@@ -1118,9 +1122,7 @@ __device__ __forceinline__ bool cr_solve(const DevPlan &P, int T, double lam, do
     CPF_GLOBAL double *base = P.cr;
     bool ok = true;
     if (tid == 0) *bad = 0;
-#ifdef CPF_PHASE_CYCLES
-    unsigned long long cr_last_ = clock64();
-#endif
+    DIAG_MARK(diag_phase[7], 1);   // (restarts the rounds' clock)
     // forward rounds
     for (int lev = 0; lev < lw; ++lev) {
         const CRLevel L = cr_level(base, T, lev);
@@ -1401,22 +1403,15 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
     __shared__ double exch[CR_GROUPS * CR_EX];
     __shared__ double tail_fs[CR_TAIL_FS], tail_wk[CR_TAIL_WK];
 #ifdef CPF_PHASE_CYCLES
-    // Diagnostic build only: per-phase shader-clock totals printed by thread 0.
-    uint64_t ph[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    uint64_t ph_last = clock64();
-#define PHASE_MARK(k)                                  \
-    do {                                               \
-        if (tid == 0) {                                \
-            const uint64_t now_ = clock64();           \
-            ph[k] += now_ - ph_last;                   \
-            ph_last = now_;                            \
-        }                                              \
-    } while (0)
-#else
-#define PHASE_MARK(k) \
-    do {              \
-    } while (0)
+    if (tid == 0) {
+        for (int r = 0; r < 64; ++r) diag_round[0][r] = diag_round[1][r] = 0;
+        for (int r = 0; r < 12; ++r) diag_tail[0][r] = diag_tail[1][r] = 0;
+        for (int r = 0; r < 8; ++r) diag_phase[r] = 0;
+        diag_last[0] = diag_last[1] = clock64();
+    }
+    __syncthreads();
 #endif
+#define PHASE_MARK(k) DIAG_MARK(diag_phase[k], 0)
     for (int it = 0; it < n_it; ++it) {
         if (sh_flags[1] != 0) break;
         // Objective of this step: the weighted sum, or under the schedule the
@@ -1567,26 +1562,22 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
     if (tid == 0 && blockIdx.x == 0)
         printf("lm phase cycles T=%d iters=%d: lin %llu factor %llu solve %llu refres %llu "
                "refsub %llu trial %llu accept %llu\n",
-               T, n_it, (unsigned long long)ph[0], (unsigned long long)ph[1],
-               (unsigned long long)ph[2], (unsigned long long)ph[3], (unsigned long long)ph[4],
-               (unsigned long long)ph[5], (unsigned long long)ph[6]);
+               T, n_it, diag_phase[0], diag_phase[1], diag_phase[2], diag_phase[3], diag_phase[4],
+               diag_phase[5], diag_phase[6]);
 #endif
 #ifdef CPF_PHASE_CYCLES
     if (tid == 0 && blockIdx.x == 0) {
         for (int k = 0; k < 2; ++k) {
             printf("cr rounds %s:", k ? "rhs" : "factor");
             for (int r = 0; r < 64; ++r)
-                if (cr_round_cycles[k][r] && r == 31) printf(" tail=%llu", cr_round_cycles[k][r]);
-                else if (cr_round_cycles[k][r]) printf(" %s%d=%llu", r >= 32 ? "b" : "f", r & 31, cr_round_cycles[k][r]);
+                if (diag_round[k][r] && r == 31) printf(" tail=%llu", diag_round[k][r]);
+                else if (diag_round[k][r]) printf(" %s%d=%llu", r >= 32 ? "b" : "f", r & 31, diag_round[k][r]);
             printf("\n");
-            for (int r = 0; r < 64; ++r) cr_round_cycles[k][r] = 0;
         }
         for (int k = 0; k < 2; ++k) {
             printf("tail steps %s:", k ? "rhs" : "factor");
-            for (int r = 0; r < 12; ++r) {
-                if (cr_tail_cycles[k][r]) printf(" s%d=%llu", r, cr_tail_cycles[k][r]);
-                cr_tail_cycles[k][r] = 0;
-            }
+            for (int r = 0; r < 12; ++r)
+                if (diag_tail[k][r]) printf(" s%d=%llu", r, diag_tail[k][r]);
             printf("\n");
         }
     }
