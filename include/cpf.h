@@ -14,7 +14,9 @@
  * residuals, clamped to the joint limits (Sec. III-C).
  *
  * Conventions
- *   - n = dof = 7 joints, standard (distal) Denavit-Hartenberg:
+ *   - n = dof = 7 or 8 joints (an 8-joint chain such as the Fetch.Full
+ *     robot's prismatic torso lift ahead of a 7-joint arm, Sec. IV),
+ *     standard (distal) Denavit-Hartenberg:
  *     A_i = Rz(q_i + theta_off_i) Tz(d_i) Tx(a_i) Rx(alpha_i) for a revolute
  *     joint, Rz(theta_off_i) Tz(d_i + q_i) Tx(a_i) Rx(alpha_i) for a
  *     prismatic one (cpf_robot.joint_type), no base or tool transform.
@@ -41,8 +43,8 @@
  *   CPF_E_STATE      call out of order (e.g. lm_refine before dp_search)
  *   CPF_E_NOTFOUND   unknown ticket
  *   CPF_E_NUMERIC    non-finite cost or a non-positive pivot in the solve
- *   CPF_E_UNSUPPORTED a shape the kernels are not built for (dof != 7,
- *                    K > 1024)
+ *   CPF_E_UNSUPPORTED a shape the kernels are not built for (dof other than
+ *                    7 or 8, K > 1024)
  */
 #ifndef CPF_H
 #define CPF_H

@@ -1,7 +1,10 @@
 """Build libcpf.so (HIP for gfx950) in-tree with hipcc.
 
-Every HIP source is compiled with packed FP32 instructions disabled; the host
-pass prints a harmless warning that it does not know that target feature.
+The kernel sources are compiled once per chain length the library serves
+(CPF_NJ = 7 and 8 joints, each into its own namespace); the host sources
+once.  Every HIP source is compiled with packed FP32 instructions disabled;
+the host pass prints a harmless warning that it does not know that target
+feature.
 """
 from __future__ import annotations
 
@@ -16,7 +19,9 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcpf.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["fk.hip", "dp.hip", "lm.hip", "capi.cpp", "serve.cpp"]
+KERNEL_SOURCES = ["fk.hip", "dp.hip", "lm.hip"]
+HOST_SOURCES = ["capi.cpp", "serve.cpp"]
+CHAIN_LENGTHS = (7, 8)
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -25,8 +30,11 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", CSRC, "-
           "-Wall", "-Wno-unused-result", "-Wno-unused-function"]
 
 
-def _compile(src: str, build_dir: str = BUILD, defines=()) -> str:
-    obj = os.path.join(build_dir, os.path.basename(src) + ".o")
+def _compile(src: str, build_dir: str = BUILD, defines=(), nj=None) -> str:
+    tag = "" if nj is None else ".nj%d" % nj
+    obj = os.path.join(build_dir, os.path.basename(src) + tag + ".o")
+    if nj is not None:
+        defines = tuple(defines) + ("CPF_NJ=%d" % nj,)
     cmd = ([HIPCC] + COMMON + [f"-D{d}" for d in defines] +
            ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj])
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -45,8 +53,9 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     variants (e.g. CPF_PHASE_CYCLES); those are built into their own folder."""
     build_dir = BUILD if not defines else os.path.join(BUILD, "_".join(defines))
     os.makedirs(build_dir, exist_ok=True)
+    jobs = [(s, nj) for s in KERNEL_SOURCES for nj in CHAIN_LENGTHS] + [(s, None) for s in HOST_SOURCES]
     with ThreadPoolExecutor(max_workers=4) as ex:
-        objs = list(ex.map(lambda s: _compile(s, build_dir, defines), SOURCES))
+        objs = list(ex.map(lambda j: _compile(j[0], build_dir, defines, j[1]), jobs))
     tmp = out + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs + ["-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)

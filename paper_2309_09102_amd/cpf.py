@@ -182,17 +182,24 @@ def _is_device_tensor(x) -> bool:
     return isinstance(x, torch.Tensor) and x.is_cuda
 
 
-def make_problem(targets, cand, node_pen=None, coll=None) -> _Keep:
-    """cand: float64 [K][T][7] (host), float32 [K][T][7] (host, passed as
-    cand_f32), or a contiguous float32 device tensor [K][T][7] with targets a
+def _dof(robot) -> int:
+    return int(np.asarray(robot.a).shape[0])
+
+
+def make_problem(targets, cand, node_pen=None, coll=None, dof=None) -> _Keep:
+    """cand: float64 [K][T][dof] (host), float32 [K][T][dof] (host, passed as
+    cand_f32), or a contiguous float32 device tensor [K][T][dof] with targets a
     contiguous float64 device tensor [T][12] (device-resident inputs, read in
-    place: keep both alive and unchanged until the call or request is done)."""
+    place: keep both alive and unchanged until the call or request is done).
+    dof: the robot's joint count, checked against the candidates' last axis."""
+    if dof is not None and (len(cand.shape) != 3 or int(cand.shape[2]) != dof):
+        raise ValueError(f"candidates must be [K][T][{dof}], got {tuple(cand.shape)}")
     npen = None if node_pen is None else _f64(node_pen)
     ob = _obstacles(coll)
     n_ob = 0 if ob is None else int(ob.shape[0])
     if _is_device_tensor(cand):
-        if not (cand.dtype == torch.float32 and cand.dim() == 3 and cand.shape[2] == 7 and cand.is_contiguous()):
-            raise ValueError("device candidates must be a contiguous float32 tensor [K][T][7]")
+        if not (cand.dtype == torch.float32 and cand.dim() == 3 and cand.is_contiguous()):
+            raise ValueError("device candidates must be a contiguous float32 tensor [K][T][dof]")
         if not (_is_device_tensor(targets) and targets.dtype == torch.float64 and targets.is_contiguous()
                 and tuple(targets.shape) == (cand.shape[1], 12)):
             raise ValueError("device targets must be a contiguous float64 tensor [T][12]")
@@ -286,7 +293,7 @@ def ctx_kernel_stats(ctx, kernel: str):
 
 def plan_init(ctx, robot, targets, cand, node_pen=None, opts=None, coll=None):
     rb = make_robot(robot, coll)
-    pb = make_problem(targets, cand, node_pen, coll)
+    pb = make_problem(targets, cand, node_pen, coll, _dof(robot))
     o = _with_coll(opts, coll)
     h = _vp()
     _check(_lib.cpf_plan_init(ctx, C.byref(rb.struct), C.byref(pb.struct), C.byref(o), C.byref(h)))
@@ -337,8 +344,8 @@ def dp_seed_steps(plan):
     return r.value, p.value
 
 
-def lm_refine(plan, iters: int, T: int, want_xi: bool = True):
-    xi = np.empty((T, 7)) if want_xi else None
+def lm_refine(plan, iters: int, T: int, want_xi: bool = True, dof: int = 7):
+    xi = np.empty((T, dof)) if want_xi else None
     rep = cpf_lm_report()
     st = _lib.cpf_lm_refine(plan, int(iters), _ptr(xi), C.byref(rep))
     if st != OK:
@@ -346,22 +353,22 @@ def lm_refine(plan, iters: int, T: int, want_xi: bool = True):
     return xi, _report(rep)
 
 
-def plan_append(plan, T: int, cand_add, node_pen_add=None):
-    """Append candidates [K_add][T][7] (and their node costs [T][K_add])."""
+def plan_append(plan, T: int, cand_add, node_pen_add=None, dof: int = 7):
+    """Append candidates [K_add][T][dof] (and their node costs [T][K_add])."""
     cd = _f64(cand_add)
-    if cd.ndim != 3 or cd.shape[1] != T or cd.shape[2] != 7:
-        raise ValueError(f"cand_add must be [K_add][{T}][7], got {cd.shape}")
+    if cd.ndim != 3 or cd.shape[1] != T or cd.shape[2] != dof:
+        raise ValueError(f"cand_add must be [K_add][{T}][{dof}], got {cd.shape}")
     npen = None if node_pen_add is None else _f64(node_pen_add)
     if npen is not None and npen.shape != (T, cd.shape[0]):
         raise ValueError(f"node_pen_add must be [{T}][{cd.shape[0]}], got {npen.shape}")
     _check(_lib.cpf_plan_append(plan, int(cd.shape[0]), _ptr(cd), _ptr(npen)))
 
 
-def plan_solve(plan, T: int, want_xi: bool = True):
+def plan_solve(plan, T: int, want_xi: bool = True, dof: int = 7):
     """Search + opts.iters LM iterations + report -> (path, B*, xi | None, report)."""
     path = np.empty(T, dtype=np.int32)
     best = C.c_double()
-    xi = np.empty((T, 7)) if want_xi else None
+    xi = np.empty((T, dof)) if want_xi else None
     rep = cpf_lm_report()
     st = _lib.cpf_plan_solve(plan, path.ctypes.data_as(_ip), C.byref(best), _ptr(xi), C.byref(rep))
     if st != OK:
@@ -374,12 +381,12 @@ def solve_static(ctx, robot, targets, cand, opts=None, node_pen=None, coll=None)
     library's static device scratch (no device allocation) -> (path, B*, xi,
     report)."""
     rb = make_robot(robot, coll)
-    pb = make_problem(targets, cand, node_pen, coll)
+    pb = make_problem(targets, cand, node_pen, coll, _dof(robot))
     o = _with_coll(opts, coll)
     T = pb.struct.T
     path = np.empty(T, dtype=np.int32)
     best = C.c_double()
-    xi = np.empty((T, 7))
+    xi = np.empty((T, _dof(robot)))
     rep = cpf_lm_report()
     st = _lib.cpf_solve_static(ctx, C.byref(rb.struct), C.byref(pb.struct), C.byref(o), path.ctypes.data_as(_ip),
                                C.byref(best), _ptr(xi), C.byref(rep))
@@ -388,10 +395,10 @@ def solve_static(ctx, robot, targets, cand, opts=None, node_pen=None, coll=None)
     return path, best.value, xi, _report(rep)
 
 
-def lm_latest_valid(plan, T: int):
-    """Latest valid trajectory [T][7] of a plan refined under the schedule
+def lm_latest_valid(plan, T: int, dof: int = 7):
+    """Latest valid trajectory [T][dof] of a plan refined under the schedule
     (raises CpfError E_STATE when there is none yet or no schedule)."""
-    xi = np.empty((T, 7))
+    xi = np.empty((T, dof))
     _check(_lib.cpf_lm_latest_valid(plan, _ptr(xi)))
     return xi
 
@@ -407,15 +414,16 @@ def solve_batch(ctx, problems, opts=None):
     first_coll = next((pr[4] for pr in problems if len(pr) > 4 and pr[4] is not None), None)
     for i, pr in enumerate(problems):
         coll = pr[4] if len(pr) > 4 else None
+        nj = _dof(pr[0])
         rb = make_robot(pr[0], coll)
-        pb = make_problem(pr[1], pr[2], pr[3] if len(pr) > 3 else None, coll)
+        pb = make_problem(pr[1], pr[2], pr[3] if len(pr) > 3 else None, coll, nj)
         keeps += [rb, pb]
         robots[i] = rb.struct
         probs[i] = pb.struct
         T = pb.struct.T
-        xi = np.empty((T, 7))
+        xi = np.empty((T, nj))
         path = np.empty(T, dtype=np.int32)
-        xv = np.empty((T, 7))
+        xv = np.empty((T, nj))
         outs.append((xi, path, xv))
         results[i].xi = _ptr(xi)
         results[i].path = path.ctypes.data_as(_ip)
@@ -428,16 +436,17 @@ def solve_batch(ctx, problems, opts=None):
 def batchopt(ctx, robot, targets, cand, M: int, opts=None, node_pen=None, coll=None):
     """The M smoothest candidates optimised directly.  Returns (indices,
     list of result dicts), in ascending candidate mjac."""
+    nj = _dof(robot)
     rb = make_robot(robot, coll)
-    pb = make_problem(targets, cand, node_pen, coll)
+    pb = make_problem(targets, cand, node_pen, coll, nj)
     T = pb.struct.T
     idx = np.empty(max(M, 0), dtype=np.int32)
     results = (cpf_result * max(M, 1))()
     outs = []
     for i in range(M):
-        xi = np.empty((T, 7))
+        xi = np.empty((T, nj))
         path = np.empty(T, dtype=np.int32)
-        xv = np.empty((T, 7))
+        xv = np.empty((T, nj))
         outs.append((xi, path, xv))
         results[i].xi = _ptr(xi)
         results[i].path = path.ctypes.data_as(_ip)
@@ -459,18 +468,18 @@ def _result(r: cpf_result, xi, path, xv=None) -> dict:
 
 def submit(ctx, robot, targets, cand, opts=None, node_pen=None, coll=None) -> int:
     rb = make_robot(robot, coll)
-    pb = make_problem(targets, cand, node_pen, coll)
+    pb = make_problem(targets, cand, node_pen, coll, _dof(robot))
     o = _with_coll(opts, coll)
     t = C.c_uint64()
     _check(_lib.cpf_submit(ctx, C.byref(rb.struct), C.byref(pb.struct), C.byref(o), C.byref(t)))
     return int(t.value)
 
 
-def poll(ctx, ticket: int, T: int, timeout_ms: int = -1):
+def poll(ctx, ticket: int, T: int, timeout_ms: int = -1, dof: int = 7):
     """Result dict, or None while the request is pending."""
-    xi = np.empty((T, 7))
+    xi = np.empty((T, dof))
     path = np.empty(T, dtype=np.int32)
-    xv = np.empty((T, 7))
+    xv = np.empty((T, dof))
     r = cpf_result()
     r.xi = _ptr(xi)
     r.path = path.ctypes.data_as(_ip)
@@ -512,18 +521,19 @@ class Context:
 
     def plan(self, robot, targets, cand, node_pen=None, opts=None, coll=None) -> "Plan":
         return Plan(self, plan_init(self.h, robot, targets, cand, node_pen, opts, coll),
-                    int(cand.shape[1]))
+                    int(cand.shape[1]), _dof(robot))
 
     def coll_batch(self, robot, coll, q: "torch.Tensor", want_grad: bool = False, stream=None):
-        """q: device tensor [7][M] -> (dist [2][M], grad [14][M] | None): the
+        """q: device tensor [dof][M] -> (dist [2][M], grad [2 dof][M] | None): the
         smallest self and environment capsule distances of each configuration."""
-        assert q.is_cuda and q.dim() == 2 and q.shape[0] == 7 and q.is_contiguous()
+        nj = _dof(robot)
+        assert q.is_cuda and q.dim() == 2 and q.shape[0] == nj and q.is_contiguous()
         prec = F64 if q.dtype == torch.float64 else F32
         M = q.shape[1]
         ob = _obstacles(coll)
         obt = None if ob is None else torch.tensor(ob, dtype=torch.float64, device=q.device)
         dist = torch.empty((2, M), dtype=q.dtype, device=q.device)
-        grad = torch.empty((14, M), dtype=q.dtype, device=q.device) if want_grad else None
+        grad = torch.empty((2 * nj, M), dtype=q.dtype, device=q.device) if want_grad else None
         s = stream if stream is not None else torch.cuda.current_stream(q.device).cuda_stream
         if obt is not None and stream is not None:
             torch.cuda.current_stream(q.device).synchronize()   # the obstacle upload is on torch's stream
@@ -537,12 +547,13 @@ class Context:
         return dist, grad
 
     def fk_batch(self, robot, q: "torch.Tensor", want_jac: bool = False, stream=None):
-        """q: device tensor [7][M] (float32 or float64) -> (pose [12][M], J [42][M] | None)."""
-        assert q.is_cuda and q.dim() == 2 and q.shape[0] == 7 and q.is_contiguous()
+        """q: device tensor [dof][M] (float32 or float64) -> (pose [12][M], J [6 dof][M] | None)."""
+        nj = _dof(robot)
+        assert q.is_cuda and q.dim() == 2 and q.shape[0] == nj and q.is_contiguous()
         prec = F64 if q.dtype == torch.float64 else F32
         M = q.shape[1]
         pose = torch.empty((12, M), dtype=q.dtype, device=q.device)
-        jac = torch.empty((42, M), dtype=q.dtype, device=q.device) if want_jac else None
+        jac = torch.empty((6 * nj, M), dtype=q.dtype, device=q.device) if want_jac else None
         s = stream if stream is not None else torch.cuda.current_stream(q.device).cuda_stream
         fk_batch(self.h, robot, M, prec, q.data_ptr(), pose.data_ptr(),
                  jac.data_ptr() if jac is not None else None, s)
@@ -560,13 +571,13 @@ class Context:
     def submit(self, robot, targets, cand, opts=None, node_pen=None, coll=None) -> int:
         return submit(self.h, robot, targets, cand, opts, node_pen, coll)
 
-    def poll(self, ticket: int, T: int, timeout_ms: int = -1):
-        return poll(self.h, ticket, T, timeout_ms)
+    def poll(self, ticket: int, T: int, timeout_ms: int = -1, dof: int = 7):
+        return poll(self.h, ticket, T, timeout_ms, dof)
 
 
 class Plan:
-    def __init__(self, ctx: Context, h, T: int):
-        self.ctx, self.h, self.T = ctx, h, T
+    def __init__(self, ctx: Context, h, T: int, dof: int = 7):
+        self.ctx, self.h, self.T, self.dof = ctx, h, T, dof
 
     def dp_search(self):
         return dp_search(self.h, self.T)
@@ -580,16 +591,16 @@ class Plan:
         return dp_needs_research(self.h)
 
     def lm_refine(self, iters: int, want_xi: bool = True):
-        return lm_refine(self.h, iters, self.T, want_xi)
+        return lm_refine(self.h, iters, self.T, want_xi, self.dof)
 
     def latest_valid(self):
-        return lm_latest_valid(self.h, self.T)
+        return lm_latest_valid(self.h, self.T, self.dof)
 
     def solve(self, want_xi: bool = True):
-        return plan_solve(self.h, self.T, want_xi)
+        return plan_solve(self.h, self.T, want_xi, self.dof)
 
     def append(self, cand_add, node_pen_add=None):
-        plan_append(self.h, self.T, cand_add, node_pen_add)
+        plan_append(self.h, self.T, cand_add, node_pen_add, self.dof)
 
     def free(self):
         if self.h:

@@ -64,14 +64,17 @@ int64_t now_ns() {
         .count();
 }
 
-// Bytes of the upload region: the caller's candidates ([K][T][7], doubles or
-// floats), then its targets ([T][12] doubles) from the next 256-byte boundary.
-size_t raw_targets_offset(int T, int K, bool cand_f32) {
-    return align256((size_t)T * K * NJ * (cand_f32 ? sizeof(float) : sizeof(double)));
+// Bytes of the upload region: the caller's candidates ([K][T][dof], doubles
+// or floats), then its targets ([T][12] doubles) from the next 256-byte
+// boundary.
+size_t raw_targets_offset(int T, int K, int dof, bool cand_f32) {
+    return align256((size_t)T * K * dof * (cand_f32 ? sizeof(float) : sizeof(double)));
 }
-size_t raw_bytes(int T, int K, bool cand_f32) { return raw_targets_offset(T, K, cand_f32) + (size_t)12 * T * sizeof(double); }
+size_t raw_bytes(int T, int K, int dof, bool cand_f32) {
+    return raw_targets_offset(T, K, dof, cand_f32) + (size_t)12 * T * sizeof(double);
+}
 
-Layout make_layout(int T, int K, bool extra, int n_obs, bool coll) {
+Layout make_layout(int T, int K, int dof, bool extra, int n_obs, bool coll) {
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -79,28 +82,28 @@ Layout make_layout(int T, int K, bool extra, int n_obs, bool coll) {
         off += align256(bytes);
         return o;
     };
-    const size_t t = (size_t)T, k = (size_t)K;
+    const size_t t = (size_t)T, k = (size_t)K, nj = (size_t)dof, ntri = nj * (nj + 1) / 2;
     // what a read-back needs lies together at the start: one copy
     L.st = take(sizeof(LMState));
     L.report = take(8 * sizeof(double));
     L.dp_out = take(8 * sizeof(double));
     L.path = take(t * sizeof(int32_t));
-    L.cand = take(t * NJ * k * sizeof(float));
+    L.cand = take(t * nj * k * sizeof(float));
     L.extra = take(extra ? t * k * sizeof(double) : 0);
     L.pen = take(t * k * sizeof(double));
     L.bp = take(t * k * sizeof(uint16_t));
     L.topk = take(t * k * TOPM * sizeof(uint16_t));
-    L.topc = take(std::max(t * k * TOPM * sizeof(double), raw_bytes(T, K, false)));
+    L.topc = take(std::max(t * k * TOPM * sizeof(double), raw_bytes(T, K, dof, false)));
     L.raw = L.topc;
     L.targets = take(12 * t * sizeof(double));
-    L.xi = take(NJ * t * sizeof(double));
-    L.xt = take(NJ * t * sizeof(double));
-    L.A = take(NTRI * t * sizeof(double));
-    L.g = take(NJ * t * sizeof(double));
-    L.cr = take(cr_doubles(T) * sizeof(double));
-    L.dx = take(NJ * t * sizeof(double));
-    L.rb = take(NJ * t * sizeof(double));
-    L.xv = take(NJ * t * sizeof(double));
+    L.xi = take(nj * t * sizeof(double));
+    L.xt = take(nj * t * sizeof(double));
+    L.A = take(ntri * t * sizeof(double));
+    L.g = take(nj * t * sizeof(double));
+    L.cr = take(cr_doubles(T, dof) * sizeof(double));
+    L.dx = take(nj * t * sizeof(double));
+    L.rb = take(nj * t * sizeof(double));
+    L.xv = take(nj * t * sizeof(double));
     L.obs = take((size_t)n_obs * 18 * sizeof(double));
     L.cpen = take(coll ? t * k * sizeof(double) : 0);
     L.rr = take(RROWS * t * sizeof(double));
@@ -109,12 +112,12 @@ Layout make_layout(int T, int K, bool extra, int n_obs, bool coll) {
     return L;
 }
 
-uint64_t plan_bytes(int T, int K, bool extra, int n_obs, bool coll) {
-    return make_layout(T, K, extra, n_obs, coll).total + align256(sizeof(DevPlan));
+uint64_t plan_bytes(int T, int K, int dof, bool extra, int n_obs, bool coll) {
+    return make_layout(T, K, dof, extra, n_obs, coll).total + align256(sizeof(DevPlan));
 }
 
-uint64_t plan_class_bytes(int T, int K, bool extra, int n_obs, bool coll) {
-    const uint64_t b = plan_bytes(T, K, extra, n_obs, coll);
+uint64_t plan_class_bytes(int T, int K, int dof, bool extra, int n_obs, bool coll) {
+    const uint64_t b = plan_bytes(T, K, dof, extra, n_obs, coll);
     uint64_t c = (uint64_t)1 << 20;
     while (c < b) c <<= 1;
     return c;
@@ -228,10 +231,13 @@ static bool all_finite(const double *p, size_t n) {
 
 cpf_status check_robot(const cpf_robot *r, HostRobot *out) {
     if (!r) return fail(CPF_E_ARG, "robot is NULL");
-    if (r->dof != NJ) return fail(CPF_E_UNSUPPORTED, "dof=%d: only 7-joint chains are built", r->dof);
+    if (!dof_supported(r->dof)) return fail(CPF_E_UNSUPPORTED, "dof=%d: chains of 7 or 8 joints are built", r->dof);
     if (!r->a || !r->d || !r->alpha || !r->q_lo || !r->q_hi)
         return fail(CPF_E_ARG, "robot array is NULL");
-    for (int i = 0; i < NJ; ++i) {
+    *out = HostRobot{};
+    out->dof = r->dof;
+    const int nj = r->dof;
+    for (int i = 0; i < nj; ++i) {
         const double off = r->theta_off ? r->theta_off[i] : 0.0;
         const double v[6] = {r->a[i], r->d[i], r->alpha[i], off, r->q_lo[i], r->q_hi[i]};
         if (!all_finite(v, 6)) return fail(CPF_E_ARG, "robot row %d is not finite", i);
@@ -247,15 +253,15 @@ cpf_status check_robot(const cpf_robot *r, HostRobot *out) {
     }
     out->prism = 0;
     if (r->joint_type)
-        for (int i = 0; i < NJ; ++i) {
+        for (int i = 0; i < nj; ++i) {
             if (r->joint_type[i] != 0 && r->joint_type[i] != 1)
                 return fail(CPF_E_ARG, "joint %d: joint_type %d (0 revolute, 1 prismatic)", i, r->joint_type[i]);
             if (r->joint_type[i] == 1) out->prism |= 1u << i;
         }
     out->has_caps = r->capsules != nullptr;
     if (r->capsules) {
-        if (!all_finite(r->capsules, (size_t)NJ * 7)) return fail(CPF_E_ARG, "capsules not finite");
-        for (int i = 0; i < NJ; ++i) {
+        if (!all_finite(r->capsules, (size_t)nj * 7)) return fail(CPF_E_ARG, "capsules not finite");
+        for (int i = 0; i < nj; ++i) {
             if (!(r->capsules[7 * i + 6] >= 0.0)) return fail(CPF_E_ARG, "capsule %d: negative radius", i);
             for (int c = 0; c < 7; ++c) out->cap[i][c] = r->capsules[7 * i + c];
         }
@@ -270,11 +276,16 @@ cpf_status check_plan_robot(const HostRobot &hr) {
 }
 
 hipError_t search_launch(cpf_ctx *ctx, const DevPlan *d_plans, int nplans, int maxK, int maxT, bool lists_ready,
-                         bool coll, hipStream_t s) {
+                         bool coll, int dofs, hipStream_t s) {
     hipError_t e = hipSuccess;
-    if (!lists_ready)
-        e = timed(ctx, KIND_DPL, s, [&] { return dp_lists_launch(d_plans, nplans, maxK, maxT, coll, s); });
-    if (e == hipSuccess) e = timed(ctx, KIND_DP, s, [&] { return dp_stages_launch(d_plans, nplans, maxK, s); });
+    for (int dof = 7; dof <= 8 && e == hipSuccess; ++dof) {
+        if (!(dofs & dof_bit(dof))) continue;
+        if (!lists_ready)
+            e = timed(ctx, KIND_DPL, s,
+                      [&] { return CPF_BY_DOF(dof, dp_lists_launch(d_plans, nplans, maxK, maxT, coll, s)); });
+        if (e == hipSuccess)
+            e = timed(ctx, KIND_DP, s, [&] { return CPF_BY_DOF(dof, dp_stages_launch(d_plans, nplans, maxK, s)); });
+    }
     return e;
 }
 
@@ -305,7 +316,7 @@ cpf_status check_obstacles(int32_t n, const double *obs) {
     return CPF_OK;
 }
 
-cpf_status check_problem(const cpf_problem *p) {
+cpf_status check_problem(const cpf_problem *p, int dof) {
     if (!p) return fail(CPF_E_ARG, "problem is NULL");
     if (p->T < 1 || p->K < 1) return fail(CPF_E_ARG, "T=%d K=%d must be >= 1", p->T, p->K);
     if (p->K > MAX_K) return fail(CPF_E_UNSUPPORTED, "K=%d exceeds %d", p->K, MAX_K);
@@ -316,7 +327,7 @@ cpf_status check_problem(const cpf_problem *p) {
     } else {
         if (!p->targets || (!p->cand && !p->cand_f32)) return fail(CPF_E_ARG, "targets / cand is NULL");
         if (!all_finite(p->targets, (size_t)p->T * 12)) return fail(CPF_E_ARG, "targets not finite");
-        const size_t n = (size_t)p->K * p->T * NJ;
+        const size_t n = (size_t)p->K * p->T * dof;
         if (p->cand_f32) {
             for (size_t i = 0; i < n; ++i)
                 if (!std::isfinite(p->cand_f32[i])) return fail(CPF_E_ARG, "cand_f32 not finite");
@@ -377,6 +388,7 @@ static void fill_desc(cpf_plan *p, bool has_extra) {
     D.penalty = p->opts.limit_penalty;
     D.schedule = p->opts.schedule;
     D.prism = (int32_t)p->robot.prism;
+    D.dof = p->robot.dof;
     D.vtol[0] = p->opts.valid_pos_m;
     D.vtol[1] = p->opts.valid_rot_rad;
     D.vtol[2] = p->opts.valid_step_rad;
@@ -386,13 +398,13 @@ static void fill_desc(cpf_plan *p, bool has_extra) {
     D.coll_margin = p->opts.coll_margin;
     D.w_coll = p->opts.w_coll;
     D.coll_penalty = p->opts.coll_penalty;
-    for (int i = 0; i < NJ; ++i)
-        for (int c = 0; c < 7; ++c) {
-            D.cap[i][c] = p->robot.cap[i][c];
-            D.capf[i][c] = (float)p->robot.cap[i][c];
-        }
     const HostRobot &r = p->robot;
-    for (int i = 0; i < NJ; ++i) {
+    for (int i = 0; i < r.dof; ++i)
+        for (int c = 0; c < 7; ++c) {
+            D.cap[i][c] = r.cap[i][c];
+            D.capf[i][c] = (float)r.cap[i][c];
+        }
+    for (int i = 0; i < r.dof; ++i) {
         D.a[i] = r.a[i]; D.d[i] = r.d[i]; D.ca[i] = r.ca[i]; D.sa[i] = r.sa[i]; D.off[i] = r.off[i];
         D.lo[i] = r.lo[i]; D.hi[i] = r.hi[i];
         D.af[i] = (float)r.a[i]; D.df[i] = (float)r.d[i]; D.caf[i] = (float)r.ca[i];
@@ -435,17 +447,18 @@ static bool desc_in_arena(const cpf_plan *p, bool has_extra) {
     const char *a = p->arena;
     const size_t end = p->L.total;
     const size_t t = (size_t)p->T, k = (size_t)p->K, d = sizeof(double);
+    const size_t nj = (size_t)p->robot.dof, ntri = nj * (nj + 1) / 2;
     const DevPlan &D = p->desc;
     struct Span { const void *ptr; size_t bytes; };
     const Span spans[] = {
-        {(const void *)D.cand, t * k * NJ * sizeof(float)}, {(const void *)D.pen, t * k * d},
+        {(const void *)D.cand, t * k * nj * sizeof(float)}, {(const void *)D.pen, t * k * d},
         {(const void *)D.bp, t * k * sizeof(uint16_t)}, {(const void *)D.topk, t * k * TOPM * sizeof(uint16_t)},
         {(const void *)D.topc, t * k * TOPM * d}, {(const void *)D.path, t * sizeof(int32_t)},
-        {(const void *)D.dp_out, 8 * d}, {(const void *)D.targets, 12 * t * d}, {(const void *)D.xi, NJ * t * d},
-        {(const void *)D.xt, NJ * t * d}, {(const void *)D.A, NTRI * t * d}, {(const void *)D.g, NJ * t * d},
-        {(const void *)D.cr, cr_doubles(p->T) * d}, {(const void *)D.dx, NJ * t * d},
-        {(const void *)D.rb, NJ * t * d}, {(const void *)D.st, sizeof(LMState)}, {(const void *)D.report, 8 * d},
-        {(const void *)D.xv, NJ * t * d}, {(const void *)D.rr, RROWS * t * d}, {(const void *)D.rt, RROWS * t * d},
+        {(const void *)D.dp_out, 8 * d}, {(const void *)D.targets, 12 * t * d}, {(const void *)D.xi, nj * t * d},
+        {(const void *)D.xt, nj * t * d}, {(const void *)D.A, ntri * t * d}, {(const void *)D.g, nj * t * d},
+        {(const void *)D.cr, cr_doubles(p->T, (int)nj) * d}, {(const void *)D.dx, nj * t * d},
+        {(const void *)D.rb, nj * t * d}, {(const void *)D.st, sizeof(LMState)}, {(const void *)D.report, 8 * d},
+        {(const void *)D.xv, nj * t * d}, {(const void *)D.rr, RROWS * t * d}, {(const void *)D.rt, RROWS * t * d},
         {(const void *)D.obs, (size_t)p->n_obs * 18 * d},
         {(const void *)D.cpen, p->robot.has_caps ? t * k * d : 0},
         {(const void *)D.extra, has_extra ? t * k * d : 0}};
@@ -468,7 +481,7 @@ static hipError_t plan_setup(cpf_plan *p, cpf_ctx *ctx, const HostRobot &hr, int
     p->n_obs = n_obs;
     p->robot = hr;
     p->opts = *opts;
-    p->L = make_layout(T, K, has_extra, n_obs, hr.has_caps);
+    p->L = make_layout(T, K, hr.dof, has_extra, n_obs, hr.has_caps);
     p->d_desc = (DevPlan *)(p->arena + p->L.total);
     fill_desc(p, has_extra);
     if (!desc_in_arena(p, has_extra)) return hipErrorInvalidValue;   // a layout mistake, caught on the host
@@ -484,7 +497,7 @@ static hipError_t plan_setup(cpf_plan *p, cpf_ctx *ctx, const HostRobot &hr, int
 
 cpf_status plan_alloc(cpf_ctx *ctx, const HostRobot &hr, int T, int K, bool has_extra, int n_obs,
                       const cpf_opts *opts, int32_t iters_target, hipStream_t s, cpf_plan **out) {
-    const uint64_t cls = plan_class_bytes(T, K, has_extra, n_obs, hr.has_caps);
+    const uint64_t cls = plan_class_bytes(T, K, hr.dof, has_extra, n_obs, hr.has_caps);
     void *mem = nullptr;
     cpf_status st = arena_get(ctx, cls, &mem);
     if (st != CPF_OK) return st;
@@ -507,8 +520,8 @@ cpf_status plan_alloc(cpf_ctx *ctx, const HostRobot &hr, int T, int K, bool has_
 // float, joint-major; targets component-major); node costs and obstacles
 // are copied.
 static hipError_t plan_upload(cpf_plan *p, const cpf_problem *prob, hipStream_t s) {
-    const int T = p->T, K = p->K;
-    const size_t n_cand = (size_t)T * K * NJ;
+    const int T = p->T, K = p->K, dof = p->robot.dof;
+    const size_t n_cand = (size_t)T * K * dof;
     const bool f32 = prob->mem == CPF_MEM_DEVICE || prob->cand_f32 != nullptr;
     const void *cin = nullptr;
     const double *tin = nullptr;
@@ -520,7 +533,7 @@ static hipError_t plan_upload(cpf_plan *p, const cpf_problem *prob, hipStream_t 
         bad = input_flag(p);
     } else {
         char *raw = p->arena + p->L.raw;
-        const size_t toff = raw_targets_offset(T, K, f32);
+        const size_t toff = raw_targets_offset(T, K, dof, f32);
         e = hipMemcpyAsync(raw, f32 ? (const void *)prob->cand_f32 : (const void *)prob->cand,
                            n_cand * (f32 ? sizeof(float) : sizeof(double)), hipMemcpyHostToDevice, s);
         if (e == hipSuccess)
@@ -529,8 +542,8 @@ static hipError_t plan_upload(cpf_plan *p, const cpf_problem *prob, hipStream_t 
         tin = (const double *)(raw + toff);
     }
     if (e == hipSuccess)
-        e = stage_launch(cin, f32, tin, T, K, (float *)(p->arena + p->L.cand), (double *)(p->arena + p->L.targets),
-                         bad, s);
+        e = CPF_BY_DOF(dof, stage_launch(cin, f32, tin, T, K, (float *)(p->arena + p->L.cand),
+                                         (double *)(p->arena + p->L.targets), bad, s));
     if (e == hipSuccess && prob->node_pen)
         e = hipMemcpyAsync(p->arena + p->L.extra, prob->node_pen, (size_t)T * K * sizeof(double),
                            hipMemcpyHostToDevice, s);
@@ -580,12 +593,12 @@ cpf_status read_plan(cpf_plan *p, hipStream_t s, const LMState *state_dev, PlanR
     HIP_TRY(hipMemcpyAsync(hb.data(), p->arena, head, hipMemcpyDeviceToHost, s));
     if (state_dev) HIP_TRY(hipMemcpyAsync(&rb->st, state_dev, sizeof(LMState), hipMemcpyDeviceToHost, s));
     if (xi_out) {
-        xs.resize((size_t)NJ * p->T);
+        xs.resize((size_t)p->robot.dof * p->T);
         HIP_TRY(hipMemcpyAsync(xs.data(), p->arena + p->L.xi, xs.size() * sizeof(double),
                                hipMemcpyDeviceToHost, s));
     }
     if (xv_out) {
-        vs.resize((size_t)NJ * p->T);
+        vs.resize((size_t)p->robot.dof * p->T);
         HIP_TRY(hipMemcpyAsync(vs.data(), p->arena + p->L.xv, vs.size() * sizeof(double),
                                hipMemcpyDeviceToHost, s));
     }
@@ -594,14 +607,14 @@ cpf_status read_plan(cpf_plan *p, hipStream_t s, const LMState *state_dev, PlanR
     memcpy(rb->report, hb.data() + L.report, sizeof(rb->report));
     memcpy(rb->dp_out, hb.data() + L.dp_out, sizeof(rb->dp_out));
     if (path_out) memcpy(path_out, hb.data() + L.path, (size_t)p->T * sizeof(int32_t));
-    if (xi_out) soa_to_rows(xs.data(), p->T, xi_out);
-    if (xv_out && rb->st.n_valid > 0) soa_to_rows(vs.data(), p->T, xv_out);
+    if (xi_out) soa_to_rows(xs.data(), p->T, p->robot.dof, xi_out);
+    if (xv_out && rb->st.n_valid > 0) soa_to_rows(vs.data(), p->T, p->robot.dof, xv_out);
     return CPF_OK;
 }
 
-void soa_to_rows(const double *soa, int T, double *rows) {
+void soa_to_rows(const double *soa, int T, int dof, double *rows) {
     for (int t = 0; t < T; ++t)
-        for (int j = 0; j < NJ; ++j) rows[(size_t)t * NJ + j] = soa[(size_t)j * T + t];
+        for (int j = 0; j < dof; ++j) rows[(size_t)t * dof + j] = soa[(size_t)j * T + t];
 }
 
 void report_from(const LMState &ls, const double *report, cpf_lm_report *rep) {
@@ -698,7 +711,7 @@ cpf_status cpf_plan_init(cpf_ctx *ctx, const cpf_robot *robot, const cpf_problem
     cpf_status st;
     if ((st = check_robot(robot, &hr)) != CPF_OK) return st;
     if ((st = check_plan_robot(hr)) != CPF_OK) return st;
-    if ((st = check_problem(prob)) != CPF_OK) return st;
+    if ((st = check_problem(prob, hr.dof)) != CPF_OK) return st;
     cpf_opts o;
     cpf_opts_default(&o);
     if (opts) o = *opts;
@@ -743,7 +756,7 @@ cpf_status cpf_fk_batch(cpf_ctx *ctx, const cpf_robot *robot, int64_t M, int32_t
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t s = (hipStream_t)hip_stream;
     HIP_TRY(timed(ctx, KIND_FK, s,
-                  [&] { return fk_batch_launch(hr, M, prec, q_dev, pose_dev, jac_dev, s); }));
+                  [&] { return CPF_BY_DOF(hr.dof, fk_batch_launch(hr, M, prec, q_dev, pose_dev, jac_dev, s)); }));
     return CPF_OK;
 }
 
@@ -767,7 +780,8 @@ cpf_status cpf_coll_batch(cpf_ctx *ctx, const cpf_robot *robot, int32_t n_obstac
     memcpy(caps.v, hr.cap, sizeof(caps.v));
     hipStream_t s = (hipStream_t)hip_stream;
     HIP_TRY(timed(ctx, KIND_FK, s, [&] {
-        return coll_batch_launch(hr, caps, n_obstacles, obstacles_dev, M, prec, q_dev, dist_dev, grad_dev, s);
+        return CPF_BY_DOF(hr.dof,
+                          coll_batch_launch(hr, caps, n_obstacles, obstacles_dev, M, prec, q_dev, dist_dev, grad_dev, s));
     }));
     return CPF_OK;
 }
@@ -777,7 +791,7 @@ cpf_status cpf_dp_search(cpf_plan *plan, int32_t *path_out, double *best_out, do
     cpf_ctx *ctx = plan->ctx;
     HIP_TRY(hipSetDevice(ctx->device));
     HIP_TRY(search_launch(ctx, plan->d_desc, 1, plan->K, plan->T, plan->lists_valid, plan->robot.has_caps,
-                          ctx->stream));
+                          dof_bit(plan->robot.dof), ctx->stream));
     PlanReadback rb;
     cpf_status st = read_plan(plan, ctx->stream, nullptr, &rb, nullptr, path_out, nullptr);
     if (st != CPF_OK) return st;
@@ -808,9 +822,9 @@ cpf_status cpf_dp_seed_steps(const cpf_plan *plan, double *rev_rad_out, double *
 cpf_status cpf_plan_append(cpf_plan *plan, int32_t K_add, const double *cand_add, const double *node_pen_add) {
     if (!plan || !cand_add) return fail(CPF_E_ARG, "plan / cand_add is NULL");
     if (K_add < 1) return fail(CPF_E_ARG, "K_add=%d must be >= 1", K_add);
-    const int T = plan->T, K0 = plan->K, K2 = K0 + K_add;
+    const int T = plan->T, K0 = plan->K, K2 = K0 + K_add, dof = plan->robot.dof;
     if (K2 > MAX_K) return fail(CPF_E_UNSUPPORTED, "K=%d + %d exceeds %d", K0, K_add, MAX_K);
-    if (!all_finite(cand_add, (size_t)K_add * T * NJ)) return fail(CPF_E_ARG, "cand_add not finite");
+    if (!all_finite(cand_add, (size_t)K_add * T * dof)) return fail(CPF_E_ARG, "cand_add not finite");
     if (node_pen_add)
         for (size_t i = 0; i < (size_t)T * K_add; ++i)
             if (!(std::fabs(node_pen_add[i]) <= 1e30))
@@ -832,10 +846,11 @@ cpf_status cpf_plan_append(cpf_plan *plan, int32_t K_add, const double *cand_add
     const Layout &L1 = plan->L, &L2 = np->L;
     // 1. the new candidates go up through the raw region and are converted
     //    into columns K0.. of the new candidate array
-    hipError_t e = hipMemcpyAsync(a2 + L2.raw, cand_add, (size_t)K_add * T * NJ * sizeof(double),
+    hipError_t e = hipMemcpyAsync(a2 + L2.raw, cand_add, (size_t)K_add * T * dof * sizeof(double),
                                   hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
-        e = stage_append_launch((const double *)(a2 + L2.raw), T, K_add, K2, K0, (float *)(a2 + L2.cand), s);
+        e = CPF_BY_DOF(dof, stage_append_launch((const double *)(a2 + L2.raw), T, K_add, K2, K0,
+                                                (float *)(a2 + L2.cand), s));
     // 2. kept on the device: candidates, node costs, penalties, predecessor
     //    lists and targets (the lists overwrite the raw region, in stream order)
     auto cols = [&](size_t off2, size_t off1, size_t elem, int rows) {
@@ -843,7 +858,7 @@ cpf_status cpf_plan_append(cpf_plan *plan, int32_t K_add, const double *cand_add
             e = hipMemcpy2DAsync(a2 + off2, (size_t)K2 * elem, a1 + off1, (size_t)K0 * elem, (size_t)K0 * elem,
                                  (size_t)rows, hipMemcpyDeviceToDevice, s);
     };
-    cols(L2.cand, L1.cand, sizeof(float), T * NJ);
+    cols(L2.cand, L1.cand, sizeof(float), T * dof);
     if (merge) {
         cols(L2.pen, L1.pen, sizeof(double), T);
         cols(L2.topk, L1.topk, TOPM * sizeof(uint16_t), T);
@@ -870,7 +885,9 @@ cpf_status cpf_plan_append(cpf_plan *plan, int32_t K_add, const double *cand_add
                            hipMemcpyDeviceToDevice, s);
     // 3. penalties and lists of the new nodes; the old nodes' lists merged
     if (e == hipSuccess && merge)
-        e = timed(ctx, KIND_DPL, s, [&] { return dp_append_launch(np->d_desc, K0, K2, T, plan->robot.has_caps, s); });
+        e = timed(ctx, KIND_DPL, s, [&] {
+            return CPF_BY_DOF(dof, dp_append_launch(np->d_desc, K0, K2, T, plan->robot.has_caps, s));
+        });
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         HIP_IGNORE(hipStreamSynchronize(s));
@@ -898,11 +915,12 @@ cpf_status cpf_lm_refine(cpf_plan *plan, int32_t iters, double *xi_out, cpf_lm_r
     HIP_TRY(hipSetDevice(ctx->device));
     HIP_TRY(timed(ctx, KIND_LM, ctx->stream,
                   [&] {
-                      return lm_launch(plan->d_desc, 1, plan->opts.prec, plan->opts.schedule, plan_geo(plan->robot),
-                                       iters, ctx->stream);
+                      return CPF_BY_DOF(plan->robot.dof, lm_launch(plan->d_desc, 1, plan->opts.prec, plan->opts.schedule,
+                                                                   plan_geo(plan->robot), iters, ctx->stream));
                   }));
-    HIP_TRY(timed(ctx, KIND_EVAL, ctx->stream,
-                  [&] { return eval_launch(plan->d_desc, 1, 0, plan_geo(plan->robot), ctx->stream); }));
+    HIP_TRY(timed(ctx, KIND_EVAL, ctx->stream, [&] {
+        return CPF_BY_DOF(plan->robot.dof, eval_launch(plan->d_desc, 1, 0, plan_geo(plan->robot), ctx->stream));
+    }));
     PlanReadback rb;
     cpf_status st = read_plan(plan, ctx->stream, nullptr, &rb, xi_out, nullptr, nullptr);
     if (st != CPF_OK) return st;
@@ -918,13 +936,15 @@ cpf_status cpf_plan_solve(cpf_plan *plan, int32_t *path_out, double *best_out, d
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
     const bool coll = plan->robot.has_caps;
-    HIP_TRY(search_launch(ctx, plan->d_desc, 1, plan->K, plan->T, false, coll, s));
+    const int dof = plan->robot.dof;
+    HIP_TRY(search_launch(ctx, plan->d_desc, 1, plan->K, plan->T, false, coll, dof_bit(dof), s));
     plan->lists_valid = true;
     HIP_TRY(timed(ctx, KIND_LM, s, [&] {
-        return lm_launch(plan->d_desc, 1, plan->opts.prec, plan->opts.schedule, plan_geo(plan->robot), plan->opts.iters,
-                         s);
+        return CPF_BY_DOF(dof, lm_launch(plan->d_desc, 1, plan->opts.prec, plan->opts.schedule, plan_geo(plan->robot),
+                                         plan->opts.iters, s));
     }));
-    HIP_TRY(timed(ctx, KIND_EVAL, s, [&] { return eval_launch(plan->d_desc, 1, 0, plan_geo(plan->robot), s); }));
+    HIP_TRY(timed(ctx, KIND_EVAL, s,
+                  [&] { return CPF_BY_DOF(dof, eval_launch(plan->d_desc, 1, 0, plan_geo(plan->robot), s)); }));
     PlanReadback rb;
     cpf_status st = read_plan(plan, s, nullptr, &rb, xi_out, path_out, nullptr);
     if (st != CPF_OK) return st;
@@ -944,14 +964,15 @@ cpf_status cpf_solve_static(cpf_ctx *ctx, const cpf_robot *robot, const cpf_prob
     cpf_status st;
     if ((st = check_robot(robot, &hr)) != CPF_OK) return st;
     if ((st = check_plan_robot(hr)) != CPF_OK) return st;
-    if ((st = check_problem(prob)) != CPF_OK) return st;
+    if ((st = check_problem(prob, hr.dof)) != CPF_OK) return st;
     cpf_opts o;
     cpf_opts_default(&o);
     if (opts) o = *opts;
     if ((st = check_opts(&o)) != CPF_OK) return st;
     const int T = prob->T, K = prob->K;
     const bool has_extra = prob->node_pen != nullptr;
-    const Layout L = make_layout(T, K, has_extra, prob->n_obstacles, hr.has_caps);
+    const int dof = hr.dof;
+    const Layout L = make_layout(T, K, dof, has_extra, prob->n_obstacles, hr.has_caps);
     const uint64_t need = L.total + align256(sizeof(DevPlan));
     if (need > SCRATCH_BYTES)
         return fail(CPF_E_NOMEM, "T=%d K=%d needs %llu bytes of working memory; the static scratch holds %llu", T, K,
@@ -969,17 +990,17 @@ cpf_status cpf_solve_static(cpf_ctx *ctx, const cpf_robot *robot, const cpf_prob
     const int geo = plan_geo(hr);
     hipError_t e = plan_setup(&p, ctx, hr, T, K, has_extra, prob->n_obstacles, &o, 0, s);
     if (e == hipSuccess) e = plan_upload(&p, prob, s);
-    if (e == hipSuccess) e = dp_lists_launch(p.d_desc, 1, K, T, coll, s);
-    if (e == hipSuccess) e = dp_stages_launch(p.d_desc, 1, K, s);
-    if (e == hipSuccess) e = lm_launch(p.d_desc, 1, o.prec, o.schedule, geo, o.iters, s);
-    if (e == hipSuccess) e = eval_launch(p.d_desc, 1, 0, geo, s);
+    if (e == hipSuccess) e = CPF_BY_DOF(dof, dp_lists_launch(p.d_desc, 1, K, T, coll, s));
+    if (e == hipSuccess) e = CPF_BY_DOF(dof, dp_stages_launch(p.d_desc, 1, K, s));
+    if (e == hipSuccess) e = CPF_BY_DOF(dof, lm_launch(p.d_desc, 1, o.prec, o.schedule, geo, o.iters, s));
+    if (e == hipSuccess) e = CPF_BY_DOF(dof, eval_launch(p.d_desc, 1, 0, geo, s));
     if (e == hipSuccess) e = hipMemcpyAsync(head, base, L.path, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess && path_out)
         e = hipMemcpyAsync(path_out, base + L.path, (size_t)T * sizeof(int32_t), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess && xi_out) {   // rows [T][7] into the trial-point area, then straight to the caller
-        e = soa_rows_launch((const double *)(base + L.xi), T, (double *)(base + L.xt), s);
+    if (e == hipSuccess && xi_out) {   // rows [T][dof] into the trial-point area, then straight to the caller
+        e = CPF_BY_DOF(dof, soa_rows_launch((const double *)(base + L.xi), T, (double *)(base + L.xt), s));
         if (e == hipSuccess)
-            e = hipMemcpyAsync(xi_out, base + L.xt, (size_t)T * NJ * sizeof(double), hipMemcpyDeviceToHost, s);
+            e = hipMemcpyAsync(xi_out, base + L.xt, (size_t)T * dof * sizeof(double), hipMemcpyDeviceToHost, s);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
@@ -1024,7 +1045,7 @@ cpf_status cpf_solve_batch(cpf_ctx *ctx, int32_t nplans, const cpf_robot *robots
     for (int i = 0; i < nplans; ++i) {
         if ((st = check_robot(&robots[i], &hrs[i])) != CPF_OK) return st;
         if ((st = check_plan_robot(hrs[i])) != CPF_OK) return st;
-        if ((st = check_problem(&probs[i])) != CPF_OK) return st;
+        if ((st = check_problem(&probs[i], hrs[i].dof)) != CPF_OK) return st;
     }
     if (nplans == 0) return CPF_OK;
     HIP_TRY(hipSetDevice(ctx->device));
@@ -1035,10 +1056,11 @@ cpf_status cpf_solve_batch(cpf_ctx *ctx, int32_t nplans, const cpf_robot *robots
         if (d_descs) HIP_IGNORE(hipFree(d_descs));
         for (auto *p : plans) plan_destroy(p);
     };
-    int maxK = 0, maxT = 0;
+    int maxK = 0, maxT = 0, dofs = 0;
     bool kinds[GEO_KINDS] = {false, false, false};   // geometry kinds present
     for (int i = 0; i < nplans; ++i) {
         kinds[plan_geo(hrs[i])] = true;
+        dofs |= dof_bit(hrs[i].dof);
         cpf_plan *p = nullptr;
         if ((st = plan_create(ctx, hrs[i], &probs[i], &o, 0, ctx->stream, &p)) != CPF_OK) {
             cleanup();
@@ -1057,21 +1079,26 @@ cpf_status cpf_solve_batch(cpf_ctx *ctx, int32_t nplans, const cpf_robot *robots
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     const int64_t t0 = now_ns();
     if (e == hipSuccess)
-        e = search_launch(ctx, d_descs, nplans, maxK, maxT, false, kinds[GEO_COLL], ctx->stream);
+        e = search_launch(ctx, d_descs, nplans, maxK, maxT, false, kinds[GEO_COLL], dofs, ctx->stream);
     if (e == hipSuccess)
         e = timed(ctx, KIND_LM, ctx->stream,
                   [&] {
                       hipError_t r = hipSuccess;
-                      for (int c = 0; c < GEO_KINDS && r == hipSuccess; ++c)
-                          if (kinds[c]) r = lm_launch(d_descs, nplans, o.prec, o.schedule, c, o.iters, ctx->stream);
+                      for (int dof = 7; dof <= 8; ++dof)
+                          for (int c = 0; c < GEO_KINDS && r == hipSuccess; ++c)
+                              if (kinds[c] && (dofs & dof_bit(dof)))
+                                  r = CPF_BY_DOF(dof, lm_launch(d_descs, nplans, o.prec, o.schedule, c, o.iters,
+                                                                ctx->stream));
                       return r;
                   });
     if (e == hipSuccess)
         e = timed(ctx, KIND_EVAL, ctx->stream,
                   [&] {
                       hipError_t r = hipSuccess;
-                      for (int c = 0; c < GEO_KINDS && r == hipSuccess; ++c)
-                          if (kinds[c]) r = eval_launch(d_descs, nplans, 0, c, ctx->stream);
+                      for (int dof = 7; dof <= 8; ++dof)
+                          for (int c = 0; c < GEO_KINDS && r == hipSuccess; ++c)
+                              if (kinds[c] && (dofs & dof_bit(dof)))
+                                  r = CPF_BY_DOF(dof, eval_launch(d_descs, nplans, 0, c, ctx->stream));
                       return r;
                   });
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
@@ -1108,7 +1135,7 @@ cpf_status cpf_batchopt(cpf_ctx *ctx, const cpf_robot *robot, const cpf_problem 
     cpf_status st;
     if ((st = check_robot(robot, &hr)) != CPF_OK) return st;
     if ((st = check_plan_robot(hr)) != CPF_OK) return st;
-    if ((st = check_problem(prob)) != CPF_OK) return st;
+    if ((st = check_problem(prob, hr.dof)) != CPF_OK) return st;
     if (M < 1 || M > prob->K) return fail(CPF_E_ARG, "M=%d with K=%d", M, prob->K);
     cpf_opts o;
     cpf_opts_default(&o);
@@ -1121,8 +1148,8 @@ cpf_status cpf_batchopt(cpf_ctx *ctx, const cpf_robot *robot, const cpf_problem 
     cpf_plan *p = nullptr;
     if ((st = plan_create(ctx, hr, prob, &o, 0, ctx->stream, &p)) != CPF_OK) return st;
     std::vector<double> m(K);
-    hipError_t e = cand_mjac_launch((const float *)(p->arena + p->L.cand), T, K, (double *)(p->arena + p->L.pen),
-                                    ctx->stream);
+    hipError_t e = CPF_BY_DOF(hr.dof, cand_mjac_launch((const float *)(p->arena + p->L.cand), T, K,
+                                                       (double *)(p->arena + p->L.pen), ctx->stream));
     if (e == hipSuccess)
         e = hipMemcpyAsync(m.data(), p->arena + p->L.pen, (size_t)K * sizeof(double), hipMemcpyDeviceToHost,
                            ctx->stream);
@@ -1141,7 +1168,7 @@ cpf_status cpf_batchopt(cpf_ctx *ctx, const cpf_robot *robot, const cpf_problem 
     for (int i = 0; i < M; ++i) {
         const int k = order[i];
         idx_out[i] = k;
-        const size_t off = (size_t)k * T * NJ;
+        const size_t off = (size_t)k * T * hr.dof;
         probs[i] = cpf_problem{T, 1, prob->targets, prob->cand ? prob->cand + off : nullptr, nullptr,
                                prob->n_obstacles, prob->obstacles,
                                prob->cand_f32 ? prob->cand_f32 + off : nullptr, prob->mem};

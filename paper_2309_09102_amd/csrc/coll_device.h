@@ -21,6 +21,7 @@
 #include "cpf_device.h"
 
 namespace cpf {
+namespace CPF_JNS {
 
 template <typename S> __device__ __forceinline__ S contact_eps();
 template <> __device__ __forceinline__ double contact_eps<double>() { return 1e-9; }
@@ -356,4 +357,5 @@ __device__ __forceinline__ void coll_distances(const RobotT<S> &rb, const C cap[
     }
 }
 
+}  // namespace CPF_JNS
 }  // namespace cpf

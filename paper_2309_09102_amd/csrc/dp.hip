@@ -41,10 +41,11 @@
 #include "cpf_internal.h"
 
 namespace cpf {
+namespace CPF_JNS {
 
 constexpr int TOPM_BS = 256;       // list kernel: one lane per node of a stage tile
 
-// Edge change between a destination (registers) and a predecessor (7 values).
+// Edge change between a destination (registers) and a predecessor (NJ values).
 template <typename Q>
 __device__ __forceinline__ double edge(const double qk[NJ], const Q *pq, long stride) {
     double e = fabs(qk[0] - (double)pq[0]);
@@ -77,7 +78,7 @@ __device__ __forceinline__ double node_penalty(const DevPlan &P, const double q[
 __global__ __launch_bounds__(TOPM_BS) void node_coll_kernel(const DevPlan *__restrict__ plans, int k_begin) {
     const DevPlan &P = plans[blockIdx.y];
     const int T = P.T, K = P.K;
-    if (T <= 0 || K <= k_begin || !P.has_coll) return;
+    if (T <= 0 || K <= k_begin || !P.has_coll || P.dof != NJ) return;
     const int nkb = (K - k_begin + TOPM_BS - 1) / TOPM_BS;
     const int t = blockIdx.x / nkb, k = k_begin + (blockIdx.x % nkb) * TOPM_BS + threadIdx.x;
     if (t >= T || k >= K) return;
@@ -132,7 +133,7 @@ __device__ __forceinline__ void store_list(const DevPlan &P, size_t node, const 
 constexpr int LIST_BUF = 16;
 
 // Shared memory of dp_topm_kernel for K candidates: the previous stage's
-// candidates (float [7][K]) and the merge buffers (uint16 [LIST_BUF][TOPM_BS]).
+// candidates (float [NJ][K]) and the merge buffers (uint16 [LIST_BUF][TOPM_BS]).
 __host__ __device__ inline size_t topm_shared_bytes(int K) {
     return (size_t)K * NJ * sizeof(float) + (size_t)LIST_BUF * TOPM_BS * sizeof(uint16_t);
 }
@@ -156,11 +157,11 @@ __host__ __device__ inline size_t topm_shared_bytes(int K) {
 __global__ __launch_bounds__(TOPM_BS) void dp_topm_kernel(const DevPlan *__restrict__ plans) {
     const DevPlan &P = plans[blockIdx.y];
     const int T = P.T, K = P.K;
-    if (T <= 0 || K <= 0) return;
+    if (T <= 0 || K <= 0 || P.dof != NJ) return;   // empty slot, or a chain of another length
     const int nkb = (K + TOPM_BS - 1) / TOPM_BS;
     const int t = blockIdx.x / nkb, kb = blockIdx.x % nkb;
     if (t >= T) return;
-    extern __shared__ float qprev[];   // [7][K]: candidates of stage t-1, then the merge buffers
+    extern __shared__ float qprev[];   // [NJ][K]: candidates of stage t-1, then the merge buffers
     uint16_t *buf = (uint16_t *)(qprev + (size_t)NJ * K) + threadIdx.x;   // [LIST_BUF][TOPM_BS]
     const CPF_GLOBAL float *__restrict__ cand = P.cand;
     if (t > 0) {
@@ -225,11 +226,11 @@ __global__ __launch_bounds__(TOPM_BS) void dp_topm_kernel(const DevPlan *__restr
 __global__ __launch_bounds__(TOPM_BS) void dp_topm_append_kernel(const DevPlan *__restrict__ plans, int K_old) {
     const DevPlan &P = plans[blockIdx.y];
     const int T = P.T, K = P.K;
-    if (T <= 0 || K <= 0) return;
+    if (T <= 0 || K <= 0 || P.dof != NJ) return;
     const int nkb = (K + TOPM_BS - 1) / TOPM_BS;
     const int t = blockIdx.x / nkb, kb = blockIdx.x % nkb;
     if (t >= T) return;
-    extern __shared__ float qprev[];   // [7][K]: candidates of stage t-1
+    extern __shared__ float qprev[];   // [NJ][K]: candidates of stage t-1
     const CPF_GLOBAL float *__restrict__ cand = P.cand;
     if (t > 0) {
         for (int x = threadIdx.x; x < NJ * K; x += TOPM_BS)
@@ -332,7 +333,7 @@ template <int BS, int AHEAD>
 __global__ __launch_bounds__(BS) void dp_kernel(const DevPlan *__restrict__ plans) {
     const DevPlan &P = plans[blockIdx.x];
     const int T = P.T, K = P.K;
-    if (T <= 0 || K <= 0) return;
+    if (T <= 0 || K <= 0 || P.dof != NJ) return;
     __shared__ double Bb[2][MAX_K];          // B_{t-1} and B_t (ping-pong)
     __shared__ double wmin[2][BS / 64];   // per-wave minima of each buffer
     __shared__ unsigned long long fmask[2][BS / 64];   // lanes whose list proved nothing
@@ -622,4 +623,5 @@ hipError_t cand_mjac_launch(const float *cand, int T, int K, double *out, hipStr
     return hipGetLastError();
 }
 
+}  // namespace CPF_JNS
 }  // namespace cpf

@@ -7,6 +7,7 @@
 #include "cpf_internal.h"
 
 namespace cpf {
+namespace CPF_JNS {
 
 template <typename S, bool WANT_J>
 __global__ __launch_bounds__(256) void fk_batch_kernel(RobotT<S> rb, int64_t M,
@@ -70,7 +71,7 @@ hipError_t fk_batch_launch(const HostRobot &hr, int64_t M, int prec, const void 
 
 // Collision distances of M configurations (the checker of Sec. III-B and the
 // distances of Sec. III-C): dist [2][M] (self, environment), optionally the
-// gradients grad [2 * 7][M] (row h * 7 + k).  One lane per configuration.
+// gradients grad [2 * NJ][M] (row h * NJ + k).  One lane per configuration.
 template <typename S, bool GRAD>
 __global__ __launch_bounds__(256) void coll_batch_kernel(RobotT<S> rb, HostCaps caps, int n_obs,
                                                          const double *__restrict__ obs, int64_t M,
@@ -129,7 +130,7 @@ hipError_t coll_batch_launch(const HostRobot &hr, const HostCaps &caps, int n_ob
 
 // One thread per (waypoint, candidate) pair, candidates fastest, so the
 // float stores of a joint row are contiguous; the last T threads transpose
-// the targets.  Candidates arrive as [K][T][7] doubles or floats.  With bad
+// the targets.  Candidates arrive as [K][T][NJ] doubles or floats.  With bad
 // non-null (inputs the host could not check), a value that is not finite
 // (also a double beyond the float range) is stored as 0 and sets *bad.
 template <typename C>
@@ -167,8 +168,8 @@ __global__ __launch_bounds__(256) void stage_kernel(const C *__restrict__ cand_i
     if (!ok) atomicOr(bad, 1);
 }
 
-// Appended candidates: raw [K_add][T][7] doubles into columns
-// k_off .. k_off + K_add - 1 of the float [T][7][K] candidate array.
+// Appended candidates: raw [K_add][T][NJ] doubles into columns
+// k_off .. k_off + K_add - 1 of the float [T][NJ][K] candidate array.
 __global__ __launch_bounds__(256) void stage_append_kernel(const double *__restrict__ raw, int T, int K_add,
                                                            int K, int k_off, float *__restrict__ cand) {
     const long long x = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -202,7 +203,7 @@ hipError_t stage_launch(const void *cand_in, bool cand_f32, const double *tg_in,
     return hipGetLastError();
 }
 
-// A [7][T] trajectory (one row per joint) into [T][7] rows, one thread per
+// A [NJ][T] trajectory (one row per joint) into [T][NJ] rows, one thread per
 // element of the output.
 __global__ __launch_bounds__(256) void soa_rows_kernel(const double *__restrict__ soa, int T,
                                                        double *__restrict__ rows) {
@@ -219,4 +220,5 @@ hipError_t soa_rows_launch(const double *soa, int T, double *rows, hipStream_t s
     return hipGetLastError();
 }
 
+}  // namespace CPF_JNS
 }  // namespace cpf

@@ -22,7 +22,7 @@
 // of its current trajectory from the trial evaluation that accepted it, so
 // each iteration still runs one chain per precision.  The solve is
 // block cyclic reduction (a Cholesky factor per eliminated block, one lane
-// per 7x7 block, log2 T levels), then FP64 iterative refinement against the
+// per NJ x NJ block, log2 T levels), then FP64 iterative refinement against the
 // same H reusing the stored factors.
 #include <float.h>
 
@@ -31,6 +31,7 @@
 #include "cpf_internal.h"
 
 namespace cpf {
+namespace CPF_JNS {
 
 constexpr int LM_BS = 512;
 // Fixed cost of an LM iteration in waypoints: an iteration of a plan of T
@@ -104,7 +105,7 @@ __device__ __forceinline__ void load_target(const DevPlan &P, int T, int t, S tg
     for (int e = 0; e < 12; ++e) tg[e] = (S)P.targets[(size_t)e * T + t];
 }
 
-// Pose residual of trajectory X ([7][T]) at waypoint t in FP64 (written to
+// Pose residual of trajectory X ([NJ][T]) at waypoint t in FP64 (written to
 // r) and its squared norm.  PR false throughout this file: a chain known to
 // be all revolute (plans with collision capsules).
 template <bool PR>
@@ -328,11 +329,11 @@ __device__ __forceinline__ double linearise(const DevPlan &P, const RobotT<S> &r
 // refinement) costs only the right-hand-side and back-substitution rounds.
 //
 // Each round is one pass over a level followed by one workgroup barrier.
-// Level 0 runs one lane per block.  Above it, 7 lanes share an odd block
+// Level 0 runs one lane per block.  Above it, NJ lanes share an odd block
 // (lane c owns column c of W, V and of the products) and exchange columns
 // through a per-group LDS area; LDS instructions of one wavefront complete
 // in order, so a wave barrier is the only synchronisation the exchange
-// needs.  Blocks are 7 x 7 row-major (49 doubles) one after another, so a
+// needs.  Blocks are NJ x NJ row-major (NBLK doubles) one after another, so a
 // lane reaches every element of its block, row or column from one per-lane
 // address plus an instruction immediate.  Of the Gram blocks A_t, the
 // diagonal blocks kept for the next level, the level-0 Schur contributions
@@ -341,7 +342,8 @@ __device__ __forceinline__ double linearise(const DevPlan &P, const RobotT<S> &r
 // as zero, and the other readers use only the lower triangle.
 // ---------------------------------------------------------------------------
 
-constexpr int CR_GPW = 9;                          // 7-lane groups per wavefront (lane 63 idles)
+constexpr int CR_GPW = 64 / NJ;                    // NJ-lane groups per wavefront
+constexpr int CR_GL = CR_GPW * NJ;                 // lanes in groups (7 joints: lane 63 idles)
 constexpr int CR_GROUPS = (LM_BS / 64) * CR_GPW;   // groups per workgroup
 constexpr int CR_EX = 2 * NBLK;                    // LDS doubles per group
 
@@ -367,7 +369,7 @@ __device__ __forceinline__ CRLevel cr_level(CPF_GLOBAL double *base, int T, int 
     int n = T;
     size_t off = 0;
     for (int l = 0; l < lev; ++l) {
-        off += cr_level_doubles(n);
+        off += cr_level_doubles(n, NJ);
         n = (n + 1) / 2;
     }
     CRLevel L;
@@ -451,7 +453,7 @@ __device__ __forceinline__ void tri_tmv(const double M[NTRI], const double x[NJ]
     }
 }
 
-// A symmetric or lower-triangular 7 x 7 block kept as its packed lower
+// A symmetric or lower-triangular NJ x NJ block kept as its packed lower
 // triangle (NTRI doubles, row by row): loaded, stored (scaled), and the
 // position of element (i, j) of a symmetric one.
 __device__ __forceinline__ void ld_packed(const CPF_GLOBAL double *b, double m[NTRI]) {
@@ -887,14 +889,14 @@ __device__ __forceinline__ int cr_tail_level(int T) {
     } while (0)
 #endif
 
-// Wavefront 0 only (lanes 0..62 in groups of 7; lane 63 idles).  Solves
+// Wavefront 0 only (lanes in groups of NJ; with 7 joints lane 63 idles).  Solves
 // levels lw..top of the system whose levels below lw are in `base`,
 // factoring them first (factor) or reusing the factored blocks in fs.
 __device__ void cr_tail(const DevPlan &P, int T, double lam, double ws, bool factor, const CPF_GLOBAL double *rhs,
                         double sgn, CPF_GLOBAL double *base, int lw, double *fs, double *wk, bool &ok) {
     const int lane = threadIdx.x & 63;
-    const int g = lane < 63 ? lane / NJ : CR_GPW;   // lane 63: a group of its own that never has a block
-    const int c = lane < 63 ? lane % NJ : 0;
+    const int g = lane < CR_GL ? lane / NJ : CR_GPW;   // an idle lane: a group that never has a block
+    const int c = lane < CR_GL ? lane % NJ : 0;
     double *D = wk, *E = D + CR_TAIL_N * NBLK, *R = E + CR_TAIL_N * NBLK, *X = R + CR_TAIL_N * NJ;
     const CRLevel Lp = cr_level(base, T, lw - 1), L = cr_level(base, T, lw);
     const int n = L.n;
@@ -1100,8 +1102,8 @@ __device__ void cr_tail(const DevPlan &P, int T, double lam, double ws, bool fac
 
 #define CR_ROUND_MARK(kind, r) DIAG_MARK(diag_round[kind][(r) & 63], 1)
 
-// Solve H x = sgn * rhs ([7][T]), factoring H first (factor = true) or
-// reusing the stored factors; x goes to out ([7][T], may alias rhs: the
+// Solve H x = sgn * rhs ([NJ][T]), factoring H first (factor = true) or
+// reusing the stored factors; x goes to out ([NJ][T], may alias rhs: the
 // right-hand side is read only in the first two forward rounds).  Returns
 // false on a pivot that is not positive.  All threads of the workgroup;
 // exch: CR_GROUPS x CR_EX doubles of LDS; tfs, twk: CR_TAIL_FS and
@@ -1112,8 +1114,8 @@ __device__ __forceinline__ bool cr_solve(const DevPlan &P, int T, double lam, do
                                          int *bad, double *exch, double *tfs, double *twk) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int gid = lane < 63 ? (tid >> 6) * CR_GPW + lane / NJ : -1;
-    const int gc = lane < 63 ? lane % NJ : 0;
+    const int gid = lane < CR_GL ? (tid >> 6) * CR_GPW + lane / NJ : -1;
+    const int gc = lane < CR_GL ? lane % NJ : 0;
     double *ex = exch + (size_t)(gid >= 0 ? gid : 0) * CR_EX;
     const int top = cr_top(T);
     // levels below lw run as workgroup rounds, lw..top in wavefront 0
@@ -1172,7 +1174,7 @@ __device__ __forceinline__ bool cr_solve(const DevPlan &P, int T, double lam, do
 
 // Block-diagonal case (no differencing term, w_s = 0: the schedule's pose
 // step, Sec. III-C): each waypoint solves D_t x_t = sgn rhs_t on its own,
-// one lane per waypoint, refactoring for every right-hand side (a 7 x 7
+// one lane per waypoint, refactoring for every right-hand side (an NJ x NJ
 // Cholesky is cheaper than storing and reloading it).  out may alias rhs.
 // Returns false on a pivot that is not positive.  All threads.
 __device__ __forceinline__ bool diag_solve(const DevPlan &P, int T, double lam, const CPF_GLOBAL double *rhs,
@@ -1322,9 +1324,10 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
     constexpr int PREC = sizeof(S) == sizeof(double) ? 1 : 0;
     const DevPlan &P = plans[blockIdx.x];
     const int T = P.T;
-    // empty slot, or a plan of another precision, objective kind or geometry
+    // empty slot, or a plan of another precision, objective kind, geometry or
+    // chain length
     if (T <= 0 || P.prec != PREC || (P.schedule != 0) != SCHED || (P.has_coll != 0) != COLL ||
-        (!COLL && (P.prism != 0) != PR))
+        (!COLL && (P.prism != 0) != PR) || P.dof != NJ)
         return;
     {
         const LMState *s0 = P.st;
@@ -1614,7 +1617,7 @@ __global__ __launch_bounds__(LM_BS) void eval_kernel(const DevPlan *__restrict__
     static_assert(!(COLL && PR), "plans with capsules are all-revolute");
     const DevPlan &P = plans[blockIdx.x];
     const int T = P.T;
-    if (T <= 0 || (P.has_coll != 0) != COLL || (!COLL && (P.prism != 0) != PR)) return;
+    if (T <= 0 || (P.has_coll != 0) != COLL || (!COLL && (P.prism != 0) != PR) || P.dof != NJ) return;
     if (only_finished) {
         const LMState *s0 = P.st;
         const bool finished = s0->status != 0 ||
@@ -1698,4 +1701,5 @@ hipError_t eval_launch(const DevPlan *d_plans, int nplans, int only_finished, in
     return hipGetLastError();
 }
 
+}  // namespace CPF_JNS
 }  // namespace cpf

@@ -15,7 +15,7 @@
 #include <vector>
 
 #include "../../include/cpf.h"
-#include "cpf_device.h"
+#include "cpf_plan.h"
 #include "cpf_internal.h"
 
 // Best-effort cleanup calls whose status cannot be reported.
@@ -35,24 +35,25 @@ int64_t now_ns();
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Byte offsets of one plan's buffers inside its arena.  `raw` receives the
-// caller's candidates ([K][T][7] doubles) and targets ([T][12]) as uploaded;
+// caller's candidates ([K][T][dof] doubles or floats) and targets ([T][12])
+// as uploaded;
 // a kernel converts them into the device layout before the search, so the
 // region is shared with the search lists (topc), which are written later.
 struct Layout {
     size_t cand, extra, pen, bp, topk, topc, raw, path, dp_out, targets, xi, xt, A, g, cr, dx, rb, st,
         report, xv, obs, cpen, rr, rt, total;
 };
-Layout make_layout(int T, int K, bool extra, int n_obs, bool coll);
-uint64_t plan_bytes(int T, int K, bool extra, int n_obs, bool coll);
+Layout make_layout(int T, int K, int dof, bool extra, int n_obs, bool coll);
+uint64_t plan_bytes(int T, int K, int dof, bool extra, int n_obs, bool coll);
 // Device bytes a plan takes from the budget: its arena rounded up to a
 // power of two (at least 1 MiB), the unit the arena pool recycles.
-uint64_t plan_class_bytes(int T, int K, bool extra, int n_obs, bool coll);
+uint64_t plan_class_bytes(int T, int K, int dof, bool extra, int n_obs, bool coll);
 
 cpf_status check_robot(const cpf_robot *r, HostRobot *out);
 // Robots a plan may use (CPF_E_UNSUPPORTED for collision capsules together
 // with a prismatic joint: that combination is switched off in plans).
 cpf_status check_plan_robot(const HostRobot &hr);
-cpf_status check_problem(const cpf_problem *p);
+cpf_status check_problem(const cpf_problem *p, int dof);
 cpf_status check_opts(const cpf_opts *o);
 
 enum { KIND_FK = 0, KIND_DP = 1, KIND_LM = 2, KIND_EVAL = 3, KIND_DPL = 4, KIND_COUNT = 5 };
@@ -143,9 +144,10 @@ hipError_t timed(cpf_ctx *ctx, int kind, hipStream_t s, F &&launch) {
 
 // The search of nplans plans on s, each launch timed: the lists (unless
 // lists_ready: the plans' lists are current) as "dp_lists", the stages as
-// "dp".
+// "dp"; dofs: the chain lengths among the plans (dof_bit), one set of
+// launches each.
 hipError_t search_launch(cpf_ctx *ctx, const DevPlan *d_plans, int nplans, int maxK, int maxT, bool lists_ready,
-                         bool coll, hipStream_t s);
+                         bool coll, int dofs, hipStream_t s);
 
 // Arena of `cls` bytes from the pool (or a new allocation within the
 // budget); E_NOMEM when the budget does not allow it.
@@ -179,12 +181,12 @@ struct PlanReadback {
     double report[8];
     double dp_out[8];
 };
-// Read state / report / search output and optionally xi ([T][7]), path and
-// the latest valid trajectory ([T][7], written only when one exists).
+// Read state / report / search output and optionally xi ([T][dof]), path and
+// the latest valid trajectory ([T][dof], written only when one exists).
 cpf_status read_plan(cpf_plan *p, hipStream_t s, const LMState *state_dev, PlanReadback *rb,
                      double *xi_out, int32_t *path_out, double *xv_out);
-// Device [7][T] to caller [T][7].
-void soa_to_rows(const double *soa, int T, double *rows);
+// Device [dof][T] to caller [T][dof].
+void soa_to_rows(const double *soa, int T, int dof, double *rows);
 void report_from(const LMState &ls, const double *report, cpf_lm_report *rep);
 void fill_report(const PlanReadback &rb, cpf_lm_report *rep);
 

@@ -75,9 +75,9 @@ struct Server {
     std::vector<Request *> slot_req;
     std::vector<Request *> searching;   // the batch in flight on s_up
     // tick graphs by kinds present: bit 0 schedule, bit 1 collision geometry,
-    // bit 2 a prismatic joint
-    hipGraph_t graph[8] = {};
-    hipGraphExec_t exec[8] = {};
+    // bit 2 a prismatic joint, bit 3 an 8-joint chain
+    hipGraph_t graph[16] = {};
+    hipGraphExec_t exec[16] = {};
 };
 
 namespace {
@@ -107,20 +107,25 @@ cpf_status server_init(cpf_ctx *ctx, Server *sv) {
 }
 
 // The tick graph for the plan kinds in `kinds` (bit 0 schedule, bit 1
-// collision geometry, bit 2 a prismatic joint), captured at its first use:
-// the LM instances of both precisions for those kinds and the plain ones,
-// then the report kernels.
+// collision geometry, bit 2 a prismatic joint, bit 3 an 8-joint chain),
+// captured at its first use: the LM instances of both precisions for those
+// kinds and the plain ones, then the report kernels; those of 7-joint chains
+// always, those of 8-joint chains with bit 3.
 cpf_status tick_graph(Server *sv, int kinds, hipGraphExec_t *out) {
     if (!sv->exec[kinds]) {
         HIP_TRY(hipStreamBeginCapture(sv->s_lm, hipStreamCaptureModeThreadLocal));
         hipError_t e = hipSuccess;
         const bool geos[GEO_KINDS] = {true, ((kinds >> 1) & 1) != 0, ((kinds >> 2) & 1) != 0};
-        for (int geo = 0; geo < GEO_KINDS; ++geo)
-            for (int sched = 0; sched <= (kinds & 1) && geos[geo]; ++sched)
-                for (int prec = 0; prec < 2 && e == hipSuccess; ++prec)
-                    e = lm_launch(sv->d_work, sv->cap, prec, sched, geo, sv->ipt, sv->s_lm, sv->budget);
-        for (int geo = 0; geo < GEO_KINDS && e == hipSuccess; ++geo)
-            if (geos[geo]) e = eval_launch(sv->d_work, sv->cap, 1, geo, sv->s_lm);
+        const int top_dof = (kinds >> 3) & 1 ? 8 : 7;
+        for (int dof = 7; dof <= top_dof; ++dof) {
+            for (int geo = 0; geo < GEO_KINDS; ++geo)
+                for (int sched = 0; sched <= (kinds & 1) && geos[geo]; ++sched)
+                    for (int prec = 0; prec < 2 && e == hipSuccess; ++prec)
+                        e = CPF_BY_DOF(dof, lm_launch(sv->d_work, sv->cap, prec, sched, geo, sv->ipt, sv->s_lm,
+                                                      sv->budget));
+            for (int geo = 0; geo < GEO_KINDS && e == hipSuccess; ++geo)
+                if (geos[geo]) e = CPF_BY_DOF(dof, eval_launch(sv->d_work, sv->cap, 1, geo, sv->s_lm));
+        }
         hipError_t e2 = hipStreamEndCapture(sv->s_lm, &sv->graph[kinds]);
         if (e != hipSuccess) return fail(CPF_E_DEVICE, "tick capture: %s", hipGetErrorString(e));
         if (e2 != hipSuccess) return fail(CPF_E_DEVICE, "tick capture end: %s", hipGetErrorString(e2));
@@ -185,7 +190,7 @@ void retire(cpf_ctx *ctx, Server *sv, const std::vector<Request *> &fin, cpf_sta
             if (!r->plan) continue;
             const Layout &L = r->plan->L;
             const char *a = r->plan->arena;
-            r->xi_soa.resize((size_t)NJ * r->T);
+            r->xi_soa.resize((size_t)r->robot.dof * r->T);
             r->path.resize(r->T);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(r->xi_soa.data(), a + L.xi, r->xi_soa.size() * sizeof(double),
@@ -198,7 +203,7 @@ void retire(cpf_ctx *ctx, Server *sv, const std::vector<Request *> &fin, cpf_sta
             if (e == hipSuccess)
                 e = hipMemcpyAsync(r->dp_out, a + L.dp_out, sizeof(r->dp_out), hipMemcpyDeviceToHost, sv->s_lm);
             if (r->opts.schedule && sv->h_states[r->slot].n_valid > 0) {
-                r->xv_soa.resize((size_t)NJ * r->T);
+                r->xv_soa.resize((size_t)r->robot.dof * r->T);
                 if (e == hipSuccess)
                     e = hipMemcpyAsync(r->xv_soa.data(), a + L.xv, r->xv_soa.size() * sizeof(double),
                                        hipMemcpyDeviceToHost, sv->s_lm);
@@ -212,11 +217,12 @@ void retire(cpf_ctx *ctx, Server *sv, const std::vector<Request *> &fin, cpf_sta
             if (r->status == CPF_OK) r->status = dev;
         } else {
             const LMState &ls = sv->h_states[r->slot];
-            r->xi.resize((size_t)r->T * NJ);
-            soa_to_rows(r->xi_soa.data(), r->T, r->xi.data());
+            const int dof = r->robot.dof;
+            r->xi.resize((size_t)r->T * dof);
+            soa_to_rows(r->xi_soa.data(), r->T, dof, r->xi.data());
             if (!r->xv_soa.empty()) {
-                r->xv.resize((size_t)r->T * NJ);
-                soa_to_rows(r->xv_soa.data(), r->T, r->xv.data());
+                r->xv.resize((size_t)r->T * dof);
+                soa_to_rows(r->xv_soa.data(), r->T, dof, r->xv.data());
             }
             report_from(ls, r->report, &r->rep);
             r->best = r->dp_out[0];
@@ -232,7 +238,7 @@ void retire(cpf_ctx *ctx, Server *sv, const std::vector<Request *> &fin, cpf_sta
 // admitted; requests that fail to upload are retired with their status.
 int admit(cpf_ctx *ctx, Server *sv, int free_slots) {
     std::vector<Request *> batch;
-    int maxK = 0, maxT = 0;
+    int maxK = 0, maxT = 0, dofs = 0;
     bool any_coll = false;
     while (free_slots > 0) {
         Request *r = nullptr;
@@ -272,13 +278,14 @@ int admit(cpf_ctx *ctx, Server *sv, int free_slots) {
         maxK = std::max(maxK, r->K);
         maxT = std::max(maxT, r->T);
         any_coll = any_coll || r->robot.has_caps;
+        dofs |= dof_bit(r->robot.dof);
         --free_slots;
     }
     if (batch.empty()) return 0;
     hipError_t e = hipMemcpyAsync(sv->d_new, sv->h_new.data(), sizeof(DevPlan) * batch.size(),
                                   hipMemcpyHostToDevice, sv->s_up);
     if (e == hipSuccess)
-        e = search_launch(ctx, sv->d_new, (int)batch.size(), maxK, maxT, false, any_coll, sv->s_up);
+        e = search_launch(ctx, sv->d_new, (int)batch.size(), maxK, maxT, false, any_coll, dofs, sv->s_up);
     if (e == hipSuccess) e = hipEventRecord(sv->searched, sv->s_up);
     if (e != hipSuccess) {
         HIP_IGNORE(hipStreamSynchronize(sv->s_up));
@@ -355,7 +362,8 @@ void server_main(cpf_ctx *ctx) {
         // 3. one LM tick over every slot, then all slot states in one copy
         int kinds = 0;
         for (Request *r : active)
-            kinds |= (r->opts.schedule ? 1 : 0) | (r->robot.has_caps ? 2 : 0) | (r->robot.prism ? 4 : 0);
+            kinds |= (r->opts.schedule ? 1 : 0) | (r->robot.has_caps ? 2 : 0) | (r->robot.prism ? 4 : 0) |
+                     (r->robot.dof == 8 ? 8 : 0);
         hipGraphExec_t exec = nullptr;
         cpf_status dev = tick_graph(sv.get(), kinds, &exec);
         hipError_t e = dev == CPF_OK ? hipSuccess : hipErrorUnknown;
@@ -419,13 +427,14 @@ extern "C" cpf_status cpf_submit(cpf_ctx *ctx, const cpf_robot *robot, const cpf
     cpf_status st;
     if ((st = check_robot(robot, &hr)) != CPF_OK) return st;
     if ((st = check_plan_robot(hr)) != CPF_OK) return st;
-    if ((st = check_problem(prob)) != CPF_OK) return st;
+    if ((st = check_problem(prob, hr.dof)) != CPF_OK) return st;
     cpf_opts o;
     cpf_opts_default(&o);
     if (opts) o = *opts;
     if ((st = check_opts(&o)) != CPF_OK) return st;
     if (o.iters < 1) return fail(CPF_E_ARG, "iters=%d: a served request runs at least one LM iteration", o.iters);
-    const uint64_t bytes = plan_class_bytes(prob->T, prob->K, prob->node_pen != nullptr, prob->n_obstacles, hr.has_caps);
+    const uint64_t bytes =
+        plan_class_bytes(prob->T, prob->K, hr.dof, prob->node_pen != nullptr, prob->n_obstacles, hr.has_caps);
     if (bytes > ctx->budget)
         return fail(CPF_E_NOMEM, "request needs %llu bytes, budget is %llu",
                     (unsigned long long)bytes, (unsigned long long)ctx->budget);
@@ -439,7 +448,7 @@ extern "C" cpf_status cpf_submit(cpf_ctx *ctx, const cpf_robot *robot, const cpf
     // stay where they are
     const bool dev = prob->mem == CPF_MEM_DEVICE;
     const bool f32 = prob->cand_f32 != nullptr;
-    const size_t n_cand = (size_t)prob->K * prob->T * NJ, n_tg = (size_t)prob->T * 12;
+    const size_t n_cand = (size_t)prob->K * prob->T * hr.dof, n_tg = (size_t)prob->T * 12;
     const size_t b_cand = dev ? 0 : ((n_cand * (f32 ? sizeof(float) : sizeof(double)) + 7) & ~size_t(7));
     const size_t b_tg = dev ? 0 : n_tg * sizeof(double);
     const size_t n_pen = prob->node_pen ? (size_t)prob->T * prob->K : 0;

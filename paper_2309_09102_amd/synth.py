@@ -127,6 +127,19 @@ def make_robot_prismatic(seed: int, joint: int = 0, travel: float = 0.4) -> Robo
     return dataclasses.replace(rb, q_lo=lo, q_hi=hi, joint_type=jt)
 
 
+def make_robot_torso_arm(seed: int, travel: float = 0.4) -> Robot:
+    """An 8-joint chain standing in for the Fetch.Full robot of the
+    experiments (Sec. IV): a prismatic torso lift of travel [0, travel] m
+    (joint 0; its DH offset d is the link's length at zero extension) ahead
+    of a 7-joint revolute arm, all rows drawn as make_robot's are."""
+    rb = make_robot(seed, N_JOINTS + 1)
+    jt = np.zeros(rb.dof, dtype=np.int32)
+    jt[0] = 1
+    lo, hi = rb.q_lo.copy(), rb.q_hi.copy()
+    lo[0], hi[0] = 0.0, float(np.float32(travel))
+    return dataclasses.replace(rb, q_lo=lo, q_hi=hi, joint_type=jt)
+
+
 def _path(robot: Robot, seed: int, T: int, rng=None) -> np.ndarray:
     """Ground-truth joint path q* [T][n] (float32 values): the first draws of
     default_rng([seed, 1]) (rng continues from there when given)."""
