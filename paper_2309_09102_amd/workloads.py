@@ -339,13 +339,16 @@ def run_prismatic(iters=50, robot_seed=0):
     first joint (travel 0-0.4 m): the search with the seed's steps split by
     joint type and the re-search decision (12 deg / 3 cm), then 50 LM
     iterations in both precisions and the alternating schedule with its 2 cm
-    step threshold, beside the all-revolute robot on the same request."""
+    step threshold, beside the all-revolute robot on the same request and
+    the 8-joint chain of the same seed (a torso lift ahead of a 7-joint arm,
+    the Fetch.Full stand-in)."""
     import torch
     from paper_2309_09102_amd import cpf, synth
     dev = torch.device("cuda:0")
     ctx = cpf.Context(0)
     out = {"mode": "prismatic", "T": 300, "K": 256, "lm_iters": iters, "arms": {}}
-    robots = (("prismatic", synth.make_robot_prismatic(robot_seed)), ("revolute", synth.make_robot(robot_seed)))
+    robots = (("prismatic", synth.make_robot_prismatic(robot_seed)), ("revolute", synth.make_robot(robot_seed)),
+              ("torso_arm_8", synth.make_robot_torso_arm(robot_seed)))
     for rname, rb in robots:
         p = _targets(ctx, synth.make_problem(rb, seed=2, T=300, K=256, sigma=0.1, branch_frac=0.25), torch, dev)
         arms = (("mixed", dict(prec="mixed")), ("fp64", dict(prec="fp64")),
