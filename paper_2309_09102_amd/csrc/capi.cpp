@@ -861,8 +861,8 @@ cpf_status cpf_plan_append(cpf_plan *plan, int32_t K_add, const double *cand_add
     cols(L2.cand, L1.cand, sizeof(float), T * dof);
     if (merge) {
         cols(L2.pen, L1.pen, sizeof(double), T);
-        cols(L2.topk, L1.topk, TOPM * sizeof(uint16_t), T);
-        cols(L2.topc, L1.topc, TOPM * sizeof(double), T);
+        cols(L2.topk, L1.topk, sizeof(uint32_t), T * TOPM / 2);   // [T][TOPM / 2][K] index pairs
+        cols(L2.topc, L1.topc, sizeof(double), T * TOPM);         // [T][TOPM][K] values
         if (plan->robot.has_caps) cols(L2.cpen, L1.cpen, sizeof(double), T);
     }
     if (has_extra) {

@@ -8,8 +8,8 @@
 //   extra    double [T][K]      optional caller search cost (Sec. III-B)
 //   bp       uint16 [T][K]      search back-pointers
 //   pen      double [T][K]      search node penalties
-//   topk     uint16 [T][K][16]  nearest predecessors of each search node
-//   topc     double [T][K][16]  their edges plus the node's penalty
+//   topk     uint32 [T][8][K]   nearest predecessors of each search node (16, in pairs)
+//   topc     double [T][16][K]  their edges plus the node's penalty
 //   path     int32  [T]
 //   targets  double [12][T]     target poses (Sec. II): x y z, R row-major
 //   xi, xt   double [n][T]      trajectory master copy and LM trial point
@@ -78,8 +78,8 @@ struct DevPlan {
     CPF_GLOBAL const double *extra;
     CPF_GLOBAL uint16_t *bp;
     CPF_GLOBAL double *pen;       // [T][K] node penalties
-    CPF_GLOBAL uint16_t *topk;    // [T][K][TOPM] nearest predecessors of each node
-    CPF_GLOBAL double *topc;      // [T][K][TOPM] their edges plus the node penalty
+    CPF_GLOBAL uint16_t *topk;    // [T][TOPM / 2][K] nearest predecessors of each node, in pairs per 32-bit word
+    CPF_GLOBAL double *topc;      // [T][TOPM][K] their edges plus the node penalty
     CPF_GLOBAL int32_t *path;
     CPF_GLOBAL double *dp_out;    // [0] = B*, [1] = mjac of the seed, [2] = end node, [3] / [4] = the
                                   // seed's largest revolute / prismatic joint step

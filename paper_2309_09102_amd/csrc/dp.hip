@@ -116,17 +116,30 @@ __device__ __forceinline__ void list_insert(double le[TOPM], int li[TOPM], doubl
     }
 }
 
-__device__ __forceinline__ void store_list(const DevPlan &P, size_t node, const double le[TOPM],
+// The lists of stage t are element-major, so that the lanes of a wavefront
+// (consecutive k) read and write contiguous runs: the indices as pairs
+// packed in 32-bit words, [T][TOPM / 2][K], the values as [T][TOPM][K].
+__device__ __forceinline__ CPF_GLOBAL uint32_t *list_words(const DevPlan &P, int t, int k, int K) {
+    return (CPF_GLOBAL uint32_t *)P.topk + (size_t)t * (TOPM / 2) * K + k;
+}
+__device__ __forceinline__ CPF_GLOBAL double *list_values(const DevPlan &P, int t, int k, int K) {
+    return P.topc + (size_t)t * TOPM * K + k;
+}
+
+// Entry m of the stored list of node (t, k).
+__device__ __forceinline__ int list_entry(const DevPlan &P, int t, int k, int K, int m) {
+    const uint32_t w = list_words(P, t, k, K)[(size_t)(m >> 1) * K];
+    return (int)((w >> ((m & 1) * 16)) & 0xffffu);
+}
+
+__device__ __forceinline__ void store_list(const DevPlan &P, int t, int k, int K, const double le[TOPM],
                                            const int li[TOPM], double pen) {
-    CPF_GLOBAL uint4 *ix = (CPF_GLOBAL uint4 *)(P.topk + node * TOPM);
-    uint32_t pk[TOPM / 2];
+    CPF_GLOBAL uint32_t *ix = list_words(P, t, k, K);
 #pragma unroll
-    for (int m = 0; m < TOPM / 2; ++m) pk[m] = (uint32_t)li[2 * m] | ((uint32_t)li[2 * m + 1] << 16);
-    ix[0] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
-    ix[1] = make_uint4(pk[4], pk[5], pk[6], pk[7]);
-    CPF_GLOBAL double2 *cv = (CPF_GLOBAL double2 *)(P.topc + node * TOPM);
+    for (int m = 0; m < TOPM / 2; ++m) ix[(size_t)m * K] = (uint32_t)li[2 * m] | ((uint32_t)li[2 * m + 1] << 16);
+    CPF_GLOBAL double *cv = list_values(P, t, k, K);
 #pragma unroll
-    for (int m = 0; m < TOPM / 2; ++m) cv[m] = make_double2(le[2 * m] + pen, le[2 * m + 1] + pen);
+    for (int m = 0; m < TOPM; ++m) cv[(size_t)m * K] = le[m] + pen;
 }
 
 // Candidates buffered per lane between merges into its list.
@@ -211,7 +224,7 @@ __global__ __launch_bounds__(TOPM_BS) void dp_topm_kernel(const DevPlan *__restr
     }
     // With K < TOPM the entries past K keep index 0 and an infinite edge;
     // the serial pass reads only the first min(K, TOPM).
-    store_list(P, (size_t)t * K + k, le, li, pen);
+    store_list(P, t, k, K, le, li, pen);
 }
 
 // After candidates K_old..K-1 were appended to a plan (Sec. III-B's
@@ -263,13 +276,13 @@ __global__ __launch_bounds__(TOPM_BS) void dp_topm_append_kernel(const DevPlan *
     if (old) {
         const int n_old = K_old < TOPM ? K_old : TOPM;
         for (int m = 0; m < n_old; ++m) {
-            const int kp = P.topk[node * TOPM + m];
+            const int kp = list_entry(P, t, k, K, m);
             list_insert(le, li, edge(qk, qprev + kp, K), kp);
         }
         kp0 = K_old;
     }
     for (int kp = kp0; kp < K; ++kp) list_insert(le, li, edge(qk, qprev + kp, K), kp);
-    store_list(P, node, le, li, pen);
+    store_list(P, t, k, K, le, li, pen);
 }
 
 // One stage's list of a destination, in registers.
@@ -280,17 +293,12 @@ struct StageList {
 
 __device__ __forceinline__ void load_list(const DevPlan &P, int t, int k, StageList &L) {
     const int K = P.K;
-    const size_t node = (size_t)t * K + k;
-    const CPF_GLOBAL uint4 *ix = (const CPF_GLOBAL uint4 *)(P.topk + node * TOPM);
-    L.ix0 = ix[0];
-    L.ix1 = ix[1];
-    const CPF_GLOBAL double2 *cv = (const CPF_GLOBAL double2 *)(P.topc + node * TOPM);
+    const CPF_GLOBAL uint32_t *ix = list_words(P, t, k, K);
+    L.ix0 = make_uint4(ix[0], ix[(size_t)K], ix[(size_t)2 * K], ix[(size_t)3 * K]);
+    L.ix1 = make_uint4(ix[(size_t)4 * K], ix[(size_t)5 * K], ix[(size_t)6 * K], ix[(size_t)7 * K]);
+    const CPF_GLOBAL double *cv = list_values(P, t, k, K);
 #pragma unroll
-    for (int m = 0; m < TOPM / 2; ++m) {
-        const double2 v = cv[m];
-        L.c[2 * m] = v.x;
-        L.c[2 * m + 1] = v.y;
-    }
+    for (int m = 0; m < TOPM; ++m) L.c[m] = cv[(size_t)m * K];
 }
 
 // Lane-to-lane move of a double by a DPP control (ALU only, no LDS); rows
