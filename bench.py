@@ -346,6 +346,15 @@ def context_legs(args, out, ctx_results):
                         "lm_frac": T * iters * n_plans * LM_OPS_SURVEY / (lm_b * 1e-3) / 1e12 / PEAK_ALU_TFLOPS,
                         "lm_traffic": tr, "lm_traffic_GBps": tr / (lm_b * 1e-3) / 1e9 if tr else None,
                         "results_identical": bool(all(np.array_equal(r["xi"], res[0]["xi"]) for r in res))}
+    # the all-FP64 arm of the same 256 plans (the precision comparison at full chip)
+    o64 = cpf.make_opts(iters=iters, prec="fp64")
+    ctx.solve_batch(items[:8], o64)
+    ctx.profile(True)
+    res64 = ctx.solve_batch(items, o64)
+    lm64 = ctx.kernel_stats("lm")[0]
+    ctx.profile(False)
+    out["full_chip"]["fp64"] = {"lm_kernel_ms": lm64, "waypoint_lm_iters_per_s": T * iters * n_plans / (lm64 * 1e-3),
+                                "results_identical": bool(all(np.array_equal(r["xi"], res64[0]["xi"]) for r in res64))}
 
     # precision study T=1000, K=512 (pose errors against the oracle in the cpu_baseline leg)
     p3 = targets_of(synth.config3())
