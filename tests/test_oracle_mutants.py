@@ -21,6 +21,8 @@ MUTANTS = {
     "fk_sign": ("A[1] = -st * ca;", "A[1] = st * ca;"),
     "fk_param": ("A[11] = d;", "A[11] = a;"),
     "fk_translation_dropped": ("if (c == 3) s += A[r * 4 + 3];", "if (c == 3) s += 0.0;"),
+    "fk_chain_stops_at_seven": ("    for (int i = 0; i < n; ++i) {\n        z[i][0] = M[2];",
+                                "    for (int i = 0; i < n && i < 7; ++i) {\n        z[i][0] = M[2];"),
     "jac_cross_sign": ("J[0 * n + i] = z[i][1] * dz - z[i][2] * dy;",
                        "J[0 * n + i] = z[i][2] * dy - z[i][1] * dz;"),
     "log_vee_sign": ("double v0 = 0.5 * (R[7] - R[5]);", "double v0 = 0.5 * (R[5] - R[7]);"),
@@ -119,6 +121,10 @@ def battery():
         lambda: P.test_p17_limit_margin_is_three_cm_for_a_prismatic_joint(),
         lambda: P.test_p17_schedule_step_threshold_is_two_cm_for_a_prismatic_joint(),
         lambda: P.test_p17_collision_gradient_with_prismatic_joint(0),
+        lambda: P.test_p18_fk_zero_configuration_eight_joints(0),
+        lambda: P.test_p18_torso_lift_is_a_translation_along_the_base_axis(0),
+        lambda: P.test_p18_jacobian_torso_arm_finite_differences(0),
+        lambda: P.test_p18_lm_gradient_eight_joints_matches_cost_differences(),
     ]
 
 

@@ -1015,3 +1015,93 @@ def test_p17_collision_gradient_with_prismatic_joint(seed):
     # axis: the self-distance gradient of joint 0 vanishes (links 1.. move
     # together; link 0's capsule rides on the joint too)
     assert g[0, 0] == pytest.approx(0.0, abs=1e-12)
+
+
+# ---- P18: chains of 8 joints (Sec. IV's Fetch.Full: torso lift + 7-joint arm) --
+
+@pytest.mark.parametrize("seed", range(3))
+def test_p18_fk_zero_configuration_eight_joints(seed):
+    rb = exact_robot(seed, n=8)
+    p, R = split(oracle.fk(rb, np.zeros(8)))
+    p_ref, R_ref, _ = zero_pose_closed_form(rb)
+    np.testing.assert_allclose(p, p_ref, atol=1e-15)
+    np.testing.assert_allclose(R, R_ref, atol=1e-15)
+
+
+@pytest.mark.parametrize("theta", [1.0, -HALF_PI, 2.5])
+def test_p18_fk_single_axis_eight_joints(theta):
+    """Turning joint i alone rotates everything after it about joint i's axis
+    through its origin (both from the zero configuration's closed form)."""
+    rb = exact_robot(4, n=8)
+    p0, R0, A = zero_pose_closed_form(rb)
+    for i in range(8):
+        axis = np.array([0.0, -math.sin(A[i]), math.cos(A[i])])
+        origin = np.zeros(3)
+        for k in range(i):
+            origin += np.array([rb.a[k], -rb.d[k] * math.sin(A[k]), rb.d[k] * math.cos(A[k])])
+        Rot = Rotation.from_rotvec(theta * axis).as_matrix()
+        q = np.zeros(8)
+        q[i] = theta
+        p, R = split(oracle.fk(rb, q))
+        np.testing.assert_allclose(p, origin + Rot @ (p0 - origin), atol=1e-14)
+        np.testing.assert_allclose(R, Rot @ R0, atol=1e-14)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_p18_torso_lift_is_a_translation_along_the_base_axis(seed):
+    """The first joint of the torso-arm chain is prismatic along the base z
+    axis: extending it by s moves the end effector by s along z and leaves
+    its orientation, at any arm configuration."""
+    rb = synth.make_robot_torso_arm(seed)
+    q = synth.random_configs(200 + seed, 1, rb)[0]
+    q2 = q.copy()
+    q2[0] = q[0] + 0.05 if q[0] < 0.3 else q[0] - 0.05
+    p, R = split(oracle.fk(rb, q))
+    p2, R2 = split(oracle.fk(rb, q2))
+    np.testing.assert_allclose(p2 - p, [0.0, 0.0, q2[0] - q[0]], atol=1e-14)
+    np.testing.assert_allclose(R2, R, atol=1e-15)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_p18_jacobian_torso_arm_finite_differences(seed):
+    rb = synth.make_robot_torso_arm(seed)
+    q = synth.random_configs(300 + seed, 1, rb)[0]
+    _, J = oracle.fk(rb, q, jacobian=True)
+    assert J.shape == (6, 8)
+    h = 1e-6
+    for i in range(8):
+        e = np.zeros(8)
+        e[i] = h
+        pp, Rp = split(oracle.fk(rb, q + e))
+        pm, Rm = split(oracle.fk(rb, q - e))
+        np.testing.assert_allclose(J[:3, i], (pp - pm) / (2 * h), atol=1e-8)
+        w = Rotation.from_matrix(Rp @ Rm.T).as_rotvec() / (2 * h)
+        np.testing.assert_allclose(J[3:, i], w, atol=1e-8)
+    np.testing.assert_allclose(J[:, 0], [0, 0, 1, 0, 0, 0], atol=1e-15)
+
+
+@given(st.integers(1, 3), st.integers(1, 5), st.integers(0, 2**31 - 1))
+@settings(max_examples=40, deadline=None)
+def test_p18_dp_matches_brute_force_eight_joints(K, T, seed):
+    rng = np.random.default_rng(seed)
+    rb = synth.make_robot(2, 8)
+    cand = np.clip(rng.uniform(-2.8, 2.8, (K, T, 8)), rb.q_lo, rb.q_hi)
+    path, best, B_all, _ = oracle.dp(cand, rb, want_tables=True)
+    B_ref, value = brute_force_tables(cand, rb)
+    assert np.array_equal(B_all, B_ref)
+    assert best == B_ref[-1].min() and value(tuple(path)) == best
+
+
+def test_p18_lm_gradient_eight_joints_matches_cost_differences():
+    rb = synth.make_robot_torso_arm(3)
+    prob = synth.make_problem(rb, seed=3, T=5, K=1, sigma=0.3)
+    tg = oracle.fk(rb, prob.q_star)
+    xi = prob.cand[0]
+    _, g = oracle.lm_step(rb, xi, tg, 1.0, 0.1, 1.0)
+    h = 1e-6
+    for t in range(5):
+        for j in range(8):
+            e = np.zeros_like(xi)
+            e[t, j] = h
+            fd = (oracle.cost(rb, xi + e, tg) - oracle.cost(rb, xi - e, tg)) / (2 * h)
+            assert g[t, j] == pytest.approx(fd, abs=1e-7, rel=1e-6)
