@@ -305,6 +305,22 @@ cpf_status cpf_dp_needs_research(const cpf_plan *plan, int32_t *out);
  * before the first search. */
 cpf_status cpf_dp_seed_steps(const cpf_plan *plan, double *rev_rad_out, double *pri_m_out);
 
+/* The pruned predecessor lists the search decides its stages with
+ * (Sec. III-B's recursion, exact by construction): for node (t, k), the
+ * CPF_TOPM predecessors k' with the smallest (e_t(k', k), k') in that order,
+ * e_t as in cpf_dp_search (exact FP64), each with c = e_t(k', k) + pen_t(k).
+ * Copies the lists of waypoints t0 .. t0 + nt - 1 (1 <= t0, t0 + nt <= T)
+ * to caller host buffers, node-major:
+ *   idx_out [nt][K][CPF_TOPM] predecessor indices (or NULL)
+ *   c_out   [nt][K][CPF_TOPM] their c values (or NULL)
+ * With K < CPF_TOPM the entries past K hold index 0 and c = +inf.
+ * Synchronous.  CPF_E_STATE when the plan has no current lists (before its
+ * first search, or after cpf_plan_append to a plan never searched: an
+ * append to a searched plan merges its lists with the new predecessors);
+ * CPF_E_ARG for a range outside [1, T) or two NULL outputs. */
+#define CPF_TOPM 16
+cpf_status cpf_dp_lists(const cpf_plan *plan, int32_t t0, int32_t nt, uint16_t *idx_out, double *c_out);
+
 /* Append K_add candidate plans to a plan, for a repeated search over K +
  * K_add candidates (Sec. III-B: more plans when the seed's mjac exceeds 12
  * degrees; Sec. III-C: when refinement finds no valid trajectory).

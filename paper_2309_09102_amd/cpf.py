@@ -98,6 +98,7 @@ _lib.cpf_fk_batch.argtypes = [_vp, C.POINTER(cpf_robot), C.c_int64, C.c_int32, _
 _lib.cpf_dp_search.argtypes = [_vp, _ip, _dp, _dp]
 _lib.cpf_dp_seed_steps.argtypes = [_vp, _dp, _dp]
 _lib.cpf_dp_needs_research.argtypes = [_vp, _ip]
+_lib.cpf_dp_lists.argtypes = [_vp, C.c_int32, C.c_int32, _vp, _dp]
 _lib.cpf_lm_refine.argtypes = [_vp, C.c_int32, _dp, C.POINTER(cpf_lm_report)]
 _lib.cpf_lm_latest_valid.argtypes = [_vp, _dp]
 _lib.cpf_solve_static.argtypes = [_vp, C.POINTER(cpf_robot), C.POINTER(cpf_problem), C.POINTER(cpf_opts), _ip, _dp,
@@ -118,7 +119,7 @@ _lib.cpf_ctx_profile.argtypes = [_vp, C.c_int32]
 _lib.cpf_ctx_kernel_stats.argtypes = [_vp, C.c_char_p, C.POINTER(C.c_double),
                                       C.POINTER(C.c_int64)]
 for _f in ("cpf_ctx_create", "cpf_plan_init", "cpf_fk_batch", "cpf_dp_search", "cpf_dp_seed_steps",
-           "cpf_dp_needs_research", "cpf_lm_refine",
+           "cpf_dp_needs_research", "cpf_dp_lists", "cpf_lm_refine",
            "cpf_lm_latest_valid", "cpf_plan_append", "cpf_coll_batch", "cpf_plan_solve",
            "cpf_solve_batch", "cpf_batchopt", "cpf_submit", "cpf_poll", "cpf_ctx_profile",
            "cpf_ctx_kernel_stats", "cpf_ctx_config", "cpf_solve_static"):
@@ -126,7 +127,7 @@ for _f in ("cpf_ctx_create", "cpf_plan_init", "cpf_fk_batch", "cpf_dp_search", "
 
 EXPORTS = ("cpf_opts_default", "cpf_last_error", "cpf_ctx_create", "cpf_ctx_destroy",
            "cpf_ctx_bytes_in_use", "cpf_plan_init", "cpf_plan_free", "cpf_fk_batch", "cpf_coll_batch",
-           "cpf_dp_search", "cpf_dp_seed_steps", "cpf_dp_needs_research", "cpf_plan_append", "cpf_lm_refine", "cpf_plan_solve", "cpf_lm_latest_valid",
+           "cpf_dp_search", "cpf_dp_seed_steps", "cpf_dp_needs_research", "cpf_dp_lists", "cpf_plan_append", "cpf_lm_refine", "cpf_plan_solve", "cpf_lm_latest_valid",
            "cpf_solve_batch", "cpf_batchopt", "cpf_submit", "cpf_poll", "cpf_ctx_profile",
            "cpf_ctx_kernel_stats", "cpf_ctx_config", "cpf_solve_static")
 
@@ -344,6 +345,19 @@ def dp_seed_steps(plan):
     return r.value, p.value
 
 
+TOPM = 16
+
+
+def dp_lists(plan, K: int, t0: int, nt: int):
+    """The search's predecessor lists of waypoints t0 .. t0 + nt - 1
+    (cpf_dp_lists): indices [nt][K][TOPM] (uint16) and c = edge + node
+    penalty [nt][K][TOPM]."""
+    idx = np.empty((nt, K, TOPM), dtype=np.uint16)
+    c = np.empty((nt, K, TOPM))
+    _check(_lib.cpf_dp_lists(plan, int(t0), int(nt), idx.ctypes.data_as(_vp), _ptr(c)))
+    return idx, c
+
+
 def lm_refine(plan, iters: int, T: int, want_xi: bool = True, dof: int = 7):
     xi = np.empty((T, dof)) if want_xi else None
     rep = cpf_lm_report()
@@ -521,7 +535,7 @@ class Context:
 
     def plan(self, robot, targets, cand, node_pen=None, opts=None, coll=None) -> "Plan":
         return Plan(self, plan_init(self.h, robot, targets, cand, node_pen, opts, coll),
-                    int(cand.shape[1]), _dof(robot))
+                    int(cand.shape[1]), _dof(robot), int(cand.shape[0]))
 
     def coll_batch(self, robot, coll, q: "torch.Tensor", want_grad: bool = False, stream=None):
         """q: device tensor [dof][M] -> (dist [2][M], grad [2 dof][M] | None): the
@@ -576,14 +590,19 @@ class Context:
 
 
 class Plan:
-    def __init__(self, ctx: Context, h, T: int, dof: int = 7):
-        self.ctx, self.h, self.T, self.dof = ctx, h, T, dof
+    def __init__(self, ctx: Context, h, T: int, dof: int = 7, K: int = 0):
+        self.ctx, self.h, self.T, self.dof, self.K = ctx, h, T, dof, K
 
     def dp_search(self):
         return dp_search(self.h, self.T)
 
     def seed_steps(self):
         return dp_seed_steps(self.h)
+
+    def lists(self, t0: int = 1, nt: int | None = None):
+        """Predecessor lists of waypoints t0 .. t0 + nt - 1 (default: to the end)."""
+        nt = self.T - t0 if nt is None else nt
+        return dp_lists(self.h, self.K, t0, nt)
 
     def needs_research(self) -> bool:
         """The paper's test for more candidate plans (Sec. III-B): a seed step
@@ -601,6 +620,7 @@ class Plan:
 
     def append(self, cand_add, node_pen_add=None):
         plan_append(self.h, self.T, cand_add, node_pen_add, self.dof)
+        self.K += int(np.shape(cand_add)[0])
 
     def free(self):
         if self.h:

@@ -819,6 +819,35 @@ cpf_status cpf_dp_seed_steps(const cpf_plan *plan, double *rev_rad_out, double *
     return CPF_OK;
 }
 
+static_assert(TOPM == CPF_TOPM, "list length of the ABI and the kernels");
+
+cpf_status cpf_dp_lists(const cpf_plan *plan, int32_t t0, int32_t nt, uint16_t *idx_out, double *c_out) {
+    if (!plan || (!idx_out && !c_out)) return fail(CPF_E_ARG, "plan / both outputs NULL");
+    if (!plan->lists_valid) return fail(CPF_E_STATE, "the plan has no current search lists");
+    const int T = plan->T, K = plan->K;
+    if (t0 < 1 || nt < 0 || (int64_t)t0 + nt > T) return fail(CPF_E_ARG, "waypoints %d + %d outside [1, %d)", t0, nt, T);
+    if (nt == 0) return CPF_OK;
+    cpf_ctx *ctx = plan->ctx;
+    HIP_TRY(hipSetDevice(ctx->device));
+    // device layout: indices as pairs in 32-bit words [T][TOPM / 2][K], values [T][TOPM][K]
+    std::vector<uint32_t> w((size_t)nt * (TOPM / 2) * K);
+    std::vector<double> c((size_t)nt * TOPM * K);
+    hipStream_t s = ctx->stream;
+    HIP_TRY(hipMemcpyAsync(w.data(), plan->arena + plan->L.topk + (size_t)t0 * (TOPM / 2) * K * sizeof(uint32_t),
+                           w.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(c.data(), plan->arena + plan->L.topc + (size_t)t0 * TOPM * K * sizeof(double),
+                           c.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int t = 0; t < nt; ++t)
+        for (int k = 0; k < K; ++k)
+            for (int m = 0; m < TOPM; ++m) {
+                const size_t o = ((size_t)t * K + k) * TOPM + m;
+                if (idx_out) idx_out[o] = (uint16_t)(w[((size_t)t * (TOPM / 2) + m / 2) * K + k] >> (16 * (m & 1)));
+                if (c_out) c_out[o] = c[((size_t)t * TOPM + m) * K + k];
+            }
+    return CPF_OK;
+}
+
 cpf_status cpf_plan_append(cpf_plan *plan, int32_t K_add, const double *cand_add, const double *node_pen_add) {
     if (!plan || !cand_add) return fail(CPF_E_ARG, "plan / cand_add is NULL");
     if (K_add < 1) return fail(CPF_E_ARG, "K_add=%d must be >= 1", K_add);

@@ -142,31 +142,89 @@ __device__ __forceinline__ void store_list(const DevPlan &P, int t, int k, int K
     for (int m = 0; m < TOPM; ++m) cv[(size_t)m * K] = le[m] + pen;
 }
 
-// Candidates buffered per lane between merges into its list.
+// Candidates buffered per lane between merges into its list (exact scan).
 constexpr int LIST_BUF = 16;
 
+// The previous stage's candidates in shared memory, in groups of four
+// predecessors: group g holds joint j of predecessors 4g..4g+3 as one float4
+// at (g * NJ + j) * 4, so a group is NJ consecutive float4s.  K is rounded up
+// to whole groups (the padding holds +inf).
+__host__ __device__ inline int topm_row(int K) { return (K + 3) & ~3; }
+__device__ __forceinline__ int qidx(int j, int kp) { return ((kp >> 2) * NJ + j) * 4 + (kp & 3); }
+
 // Shared memory of dp_topm_kernel for K candidates: the previous stage's
-// candidates (float [NJ][K]) and the merge buffers (uint16 [LIST_BUF][TOPM_BS]).
+// candidates (float, NJ * topm_row(K)) and the merge buffers (uint16
+// [LIST_BUF][TOPM_BS]).
 __host__ __device__ inline size_t topm_shared_bytes(int K) {
-    return (size_t)K * NJ * sizeof(float) + (size_t)LIST_BUF * TOPM_BS * sizeof(uint16_t);
+    return (size_t)topm_row(K) * NJ * sizeof(float) + (size_t)LIST_BUF * TOPM_BS * sizeof(uint16_t);
+}
+
+// Selection keys.  The bit pattern of a non-negative float orders like its
+// value.  Clamped to [2^-24, 2^8) and less the clamp's low end it fits in 28
+// bits; shifted up by 4, with its low b bits replaced by the predecessor's
+// index (b = max(4, ceil(log2 K)), so an index fits), it gives a 32-bit key
+// that orders predecessors by FP32 edge, coarsened to buckets of 2^(b-4)
+// consecutive floats, then by index.  Keys are distinct, and a bucket's
+// edges are bounded by bucket_lower / bucket_upper.
+constexpr uint32_t KEY_LO = 103u << 23;          // 2^-24
+constexpr uint32_t KEY_HI = (135u << 23) - 1u;   // the largest float below 2^8
+
+__device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+__device__ __forceinline__ uint32_t edge_key(float e, uint32_t kmask, uint32_t kp) {
+    const uint32_t x = min(max(__float_as_uint(e), KEY_LO), KEY_HI);
+    return (((x - KEY_LO) << 4) & kmask) | kp;
+}
+
+// Bounds of the FP32 edges whose keys carry the bucket bits cb (a key with
+// its index bits cleared): every such edge e has lower <= e < upper.  The
+// lowest bucket takes every edge below the clamp, the highest every edge
+// above it.
+__device__ __forceinline__ double bucket_lower(uint32_t cb) {
+    return cb == 0 ? 0.0 : (double)__uint_as_float((cb >> 4) + KEY_LO);
+}
+__device__ __forceinline__ double bucket_upper(uint32_t cb, uint32_t kmask, int b) {
+    const uint32_t top = ((KEY_HI - KEY_LO) << 4) & kmask;
+    return cb == top ? __builtin_inf() : (double)__uint_as_float((cb >> 4) + KEY_LO + (1u << (b - 4)));
+}
+
+// (e, k') order of two list entries.
+__device__ __forceinline__ bool entry_before(double ea, int ia, double eb, int ib) {
+    return ea < eb || (ea == eb && ia < ib);
 }
 
 // Grid: x = tile (stage t, block of TOPM_BS destinations), y = plan.
 //
-// One lane per destination k builds its list in three parts: the first TOPM
-// predecessors go straight into the sorted list; each later predecessor is
-// screened by an FP32 edge against the list's last edge tau, raised by a
-// relative 2^-21 (FP32 rounding moves each joint difference by at most
-// 2^-24 of itself, so no predecessor with e < tau fails the screen), and
-// the ones that pass are buffered by index; whenever some lane of the
-// wavefront has LIST_BUF of them, every lane merges its buffer into its list
-// in buffer order with the exact FP64 edges (and the same strict insertion),
-// and tau is taken again.  A predecessor that fails the screen has e >= the
-// list's last edge at that moment, so direct insertion would have rejected
-// it too; buffered ones are offered in ascending k', so the list is the one
-// the plain scan builds, bit for bit.  The merges are what diverge between
-// lanes; batching them lets a wavefront pay for one insertion where the
-// lanes' insertions coincide instead of one per predecessor.
+// One lane per destination k.  Its list is the TOPM predecessors with the
+// smallest (e_t(k', k), k') under the exact FP64 edge e.  The FP32 edge ef
+// of the float32 inputs is the FP32 rounding of the exact edge and the FP64
+// edge its FP64 rounding, so ef orders predecessors like e up to a relative
+// 2^-21 (twice FP32's rounding, with room to spare): e_a <= e_b implies
+// ef_a <= ef_b (1 + 2^-21), and ef_a >= ef_b (1 + 2^-21) implies e_a > e_b.
+//
+//  1. Selection: every predecessor's 32-bit key (FP32 edge bucket, index)
+//     goes through a sorted register list of the TOPM + 1 smallest keys,
+//     branch-free: inserting x moves entry m to median(L[m-1], L[m], x).
+//  2. When K <= TOPM the list holds every predecessor.  Otherwise, if the
+//     (TOPM+1)-th key's bucket starts at or above the TOPM-th key's bucket
+//     end times (1 + 2^-21), each of the first TOPM has a smaller exact edge
+//     than every predecessor left out, so they are the list's members.
+//     Their FP64 edges are computed and, should the key order differ from
+//     the (e, k') order (equal buckets), they are sorted.
+//  3. Otherwise (near-equal edges at the list's end) the lane rebuilds its
+//     list exactly: each predecessor whose FP32 edge is below the TOPM-th
+//     bucket's end times (1 + 2^-21) -- a set holding the whole list -- is
+//     buffered, and the buffers are merged into a sorted FP64 list with
+//     strict insertion in ascending k' (whenever some lane of the wavefront
+//     has LIST_BUF of them), the screen tightening to the list's last edge
+//     times (1 + 2^-21) as it fills.
+// Each path yields the list the plain scan in ascending k' builds, bit for
+// bit; with K < TOPM the entries past K keep index 0 and an infinite edge
+// (the serial pass reads only the first min(K, TOPM)).
 __global__ __launch_bounds__(TOPM_BS) void dp_topm_kernel(const DevPlan *__restrict__ plans) {
     const DevPlan &P = plans[blockIdx.y];
     const int T = P.T, K = P.K;
@@ -174,12 +232,15 @@ __global__ __launch_bounds__(TOPM_BS) void dp_topm_kernel(const DevPlan *__restr
     const int nkb = (K + TOPM_BS - 1) / TOPM_BS;
     const int t = blockIdx.x / nkb, kb = blockIdx.x % nkb;
     if (t >= T) return;
-    extern __shared__ float qprev[];   // [NJ][K]: candidates of stage t-1, then the merge buffers
-    uint16_t *buf = (uint16_t *)(qprev + (size_t)NJ * K) + threadIdx.x;   // [LIST_BUF][TOPM_BS]
+    const int Kr = topm_row(K);
+    extern __shared__ float qprev[];   // candidates of stage t-1 (qidx), then the merge buffers
+    uint16_t *buf = (uint16_t *)(qprev + (size_t)NJ * Kr) + threadIdx.x;   // [LIST_BUF][TOPM_BS]
     const CPF_GLOBAL float *__restrict__ cand = P.cand;
     if (t > 0) {
-        for (int x = threadIdx.x; x < NJ * K; x += TOPM_BS)
-            qprev[x] = cand[(size_t)(t - 1) * NJ * K + x];
+        for (int x = threadIdx.x; x < NJ * Kr; x += TOPM_BS) {
+            const int j = x / Kr, kp = x - j * Kr;
+            qprev[qidx(j, kp)] = kp < K ? cand[((size_t)(t - 1) * NJ + j) * K + kp] : __builtin_inff();
+        }
     }
     __syncthreads();
     const int k = kb * TOPM_BS + threadIdx.x;
@@ -194,36 +255,94 @@ __global__ __launch_bounds__(TOPM_BS) void dp_topm_kernel(const DevPlan *__restr
     const double pen = node_penalty(P, qk, t, k);
     P.pen[(size_t)t * K + k] = pen;
     if (t == 0) return;
+
+    // 1. the TOPM + 1 smallest keys
+    const int b = K <= 16 ? 4 : 32 - __clz(K - 1);
+    const uint32_t kmask = ~((1u << b) - 1u);
+    uint32_t L[TOPM + 1];
+#pragma unroll
+    for (int m = 0; m <= TOPM; ++m) L[m] = 0xffffffffu;
+    const float4 *rows = (const float4 *)qprev;
+    for (int k4 = 0; k4 < Kr / 4; ++k4) {
+        float4 p[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) p[j] = rows[k4 * NJ + j];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            auto pu = [&](int j) { return u == 0 ? p[j].x : (u == 1 ? p[j].y : (u == 2 ? p[j].z : p[j].w)); };
+            float e = fabsf(qf[0] - pu(0));
+#pragma unroll
+            for (int j = 1; j < NJ; ++j) e = fmaxf(e, fabsf(qf[j] - pu(j)));
+            const uint32_t key = edge_key(e, kmask, (uint32_t)(4 * k4 + u));
+#pragma unroll
+            for (int m = TOPM; m > 0; --m) L[m] = umed3(L[m - 1], L[m], key);
+            L[0] = min(L[0], key);
+        }
+    }
+
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) qk[j] = (double)qf[j];   // (not kept live through the selection)
     double le[TOPM];
     int li[TOPM];
-#pragma unroll
-    for (int m = 0; m < TOPM; ++m) {
-        le[m] = __builtin_inf();
-        li[m] = 0;
+    const int n = K < TOPM ? K : TOPM;
+    bool exact_scan = false;
+    if (K > TOPM) {
+        const uint32_t c15 = L[TOPM - 1] & kmask, c16 = L[TOPM] & kmask;
+        exact_scan = !(bucket_lower(c16) >= bucket_upper(c15, kmask, b) * (1.0 + 0x1p-21));
     }
-    const int n0 = K < TOPM ? K : TOPM;
-    for (int kp = 0; kp < n0; ++kp) list_insert(le, li, edge(qk, qprev + kp, K), kp);
-    float tau = (float)(le[TOPM - 1] * (1.0 + 0x1p-21));
-    int cnt = 0;
-    for (int kp = n0; kp < K; ++kp) {
-        float e = fabsf(qf[0] - qprev[kp]);
+    if (!exact_scan) {
+        // 2. the first n keys are the list; FP64 edges, then the (e, k') order
+        bool unsorted = false;
 #pragma unroll
-        for (int j = 1; j < NJ; ++j) e = fmaxf(e, fabsf(qf[j] - qprev[(size_t)j * K + kp]));
-        if (e < tau) {
-            buf[cnt * TOPM_BS] = (uint16_t)kp;
-            ++cnt;
+        for (int m = 0; m < TOPM; ++m) {
+            li[m] = m < n ? (int)(L[m] & ~kmask) : 0;
+            le[m] = m < n ? edge(qk, qprev + qidx(0, li[m]), 4) : __builtin_inf();
+            if (m > 0) unsorted = unsorted || (m < n && entry_before(le[m], li[m], le[m - 1], li[m - 1]));
         }
-        if (__any(cnt == LIST_BUF) || kp == K - 1) {   // uniform: every lane reaches both
-            for (int i = 0; i < cnt; ++i) {
-                const int kq = buf[i * TOPM_BS];
-                list_insert(le, li, edge(qk, qprev + kq, K), kq);
+        if (unsorted) {   // odd-even transposition sort of the first n entries
+#pragma unroll
+            for (int r = 0; r < TOPM; ++r) {
+#pragma unroll
+                for (int m = (r & 1) + 1; m < TOPM; m += 2) {
+                    const bool sw = m < n && entry_before(le[m], li[m], le[m - 1], li[m - 1]);
+                    const double ea = le[m - 1], eb = le[m];
+                    const int ia = li[m - 1], ib = li[m];
+                    le[m - 1] = sw ? eb : ea;
+                    le[m] = sw ? ea : eb;
+                    li[m - 1] = sw ? ib : ia;
+                    li[m] = sw ? ia : ib;
+                }
             }
-            cnt = 0;
-            tau = (float)(le[TOPM - 1] * (1.0 + 0x1p-21));
+        }
+    } else {
+        // 3. exact rebuild from the predecessors below the screen
+        const double thr = bucket_upper(L[TOPM - 1] & kmask, kmask, b) * (1.0 + 0x1p-21);
+#pragma unroll
+        for (int m = 0; m < TOPM; ++m) {
+            le[m] = __builtin_inf();
+            li[m] = 0;
+        }
+        double tau = thr;
+        int cnt = 0;
+        for (int kp = 0; kp < K; ++kp) {
+            const float *pq = qprev + qidx(0, kp);
+            float e = fabsf(qf[0] - pq[0]);
+#pragma unroll
+            for (int j = 1; j < NJ; ++j) e = fmaxf(e, fabsf(qf[j] - pq[4 * j]));
+            if ((double)e < tau) {
+                buf[cnt * TOPM_BS] = (uint16_t)kp;
+                ++cnt;
+            }
+            if (__any(cnt == LIST_BUF) || kp == K - 1) {   // uniform over the lanes in this branch
+                for (int i = 0; i < cnt; ++i) {
+                    const int kq = buf[i * TOPM_BS];
+                    list_insert(le, li, edge(qk, qprev + qidx(0, kq), 4), kq);
+                }
+                cnt = 0;
+                tau = fmin(thr, le[TOPM - 1] * (1.0 + 0x1p-21));
+            }
         }
     }
-    // With K < TOPM the entries past K keep index 0 and an infinite edge;
-    // the serial pass reads only the first min(K, TOPM).
     store_list(P, t, k, K, le, li, pen);
 }
 

@@ -5,8 +5,12 @@
 // and their LM states in one contiguous array.  One server thread loops:
 //   1. admission: while a slot is free and the request's arena fits the
 //      memory budget, take an arena from the pool and upload the request on
-//      the upload stream; the admitted requests are searched in one launch
-//      there (one workgroup per request), while
+//      a search lane's stream; the admitted requests are searched in one
+//      launch there (one workgroup per request).  SEARCH_LANES batches can
+//      be in flight at once on their own streams, so a batch admitted while
+//      another is searched does not wait for it (a batch's stage recursion
+//      lasts as long as its longest request, however few requests it has),
+//      while
 //   2. the LM stream replays a tick graph over the work list: the LM kernel
 //      instances of both precisions, for the kinds of plan in the table
 //      (weighted objective or schedule, with or without collision
@@ -26,8 +30,10 @@
 // and a table of plain plans never launches the other kinds' instances
 // (whose larger scratch needs slow every dispatch).
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 #include <memory>
+#include <thread>
 
 #include "runtime.h"
 
@@ -60,20 +66,28 @@ struct Request {
     int64_t t_submit = 0, t_admit = 0, t_search = 0, t_done = 0;
 };
 
+// A search lane: one admitted batch at a time, uploaded and searched on the
+// lane's stream.
+struct SearchLane {
+    hipStream_t s = nullptr;
+    hipEvent_t searched = nullptr;
+    DevPlan *d_new = nullptr;           // [cap] descriptors of the batch
+    std::vector<DevPlan> h_new;
+    std::vector<Request *> searching;   // the batch in flight (empty: lane free)
+};
+constexpr int SEARCH_LANES = 2;
+
 struct Server {
     int cap = 0;
     int ipt = 0;
     int budget = 0;   // waypoint-iterations per plan and tick (0: iters_per_tick for every plan)
     hipStream_t s_lm = nullptr;    // tick graph, work-list updates, read-back
-    hipStream_t s_up = nullptr;    // uploads and searches
-    hipEvent_t searched = nullptr;
+    SearchLane lane[SEARCH_LANES];
     DevPlan *d_work = nullptr;     // [cap]
     LMState *d_states = nullptr;   // [cap]
-    DevPlan *d_new = nullptr;      // [cap] descriptors of the batch being searched
-    std::vector<DevPlan> h_work, h_new;
+    std::vector<DevPlan> h_work;
     std::vector<LMState> h_states, h_init;
     std::vector<Request *> slot_req;
-    std::vector<Request *> searching;   // the batch in flight on s_up
     // tick graphs by kinds present: bit 0 schedule, bit 1 collision geometry,
     // bit 2 a prismatic joint, bit 3 an 8-joint chain
     hipGraph_t graph[16] = {};
@@ -88,13 +102,15 @@ cpf_status server_init(cpf_ctx *ctx, Server *sv) {
     sv->budget = ctx->tick_budget;
     HIP_TRY(hipSetDevice(ctx->device));
     HIP_TRY(hipStreamCreateWithFlags(&sv->s_lm, hipStreamNonBlocking));
-    HIP_TRY(hipStreamCreateWithFlags(&sv->s_up, hipStreamNonBlocking));
-    HIP_TRY(hipEventCreateWithFlags(&sv->searched, hipEventDisableTiming));
+    for (SearchLane &ln : sv->lane) {
+        HIP_TRY(hipStreamCreateWithFlags(&ln.s, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&ln.searched, hipEventDisableTiming));
+        HIP_TRY(hipMalloc((void **)&ln.d_new, sizeof(DevPlan) * sv->cap));
+        ln.h_new.assign(sv->cap, DevPlan{});
+    }
     HIP_TRY(hipMalloc((void **)&sv->d_work, sizeof(DevPlan) * sv->cap));
     HIP_TRY(hipMalloc((void **)&sv->d_states, sizeof(LMState) * sv->cap));
-    HIP_TRY(hipMalloc((void **)&sv->d_new, sizeof(DevPlan) * sv->cap));
     sv->h_work.assign(sv->cap, DevPlan{});     // T = 0: empty slot
-    sv->h_new.assign(sv->cap, DevPlan{});
     sv->h_states.assign(sv->cap, LMState{});
     sv->h_init.assign(sv->cap, LMState{});
     sv->slot_req.assign(sv->cap, nullptr);
@@ -136,17 +152,20 @@ cpf_status tick_graph(Server *sv, int kinds, hipGraphExec_t *out) {
 }
 
 void server_free(Server *sv) {
-    if (sv->s_up) HIP_IGNORE(hipStreamSynchronize(sv->s_up));
+    for (SearchLane &ln : sv->lane)
+        if (ln.s) HIP_IGNORE(hipStreamSynchronize(ln.s));
     if (sv->s_lm) HIP_IGNORE(hipStreamSynchronize(sv->s_lm));
-    for (int g = 0; g < 8; ++g) {
+    for (int g = 0; g < 16; ++g) {
         if (sv->exec[g]) HIP_IGNORE(hipGraphExecDestroy(sv->exec[g]));
         if (sv->graph[g]) HIP_IGNORE(hipGraphDestroy(sv->graph[g]));
     }
-    if (sv->searched) HIP_IGNORE(hipEventDestroy(sv->searched));
     if (sv->d_work) HIP_IGNORE(hipFree(sv->d_work));
     if (sv->d_states) HIP_IGNORE(hipFree(sv->d_states));
-    if (sv->d_new) HIP_IGNORE(hipFree(sv->d_new));
-    if (sv->s_up) HIP_IGNORE(hipStreamDestroy(sv->s_up));
+    for (SearchLane &ln : sv->lane) {
+        if (ln.searched) HIP_IGNORE(hipEventDestroy(ln.searched));
+        if (ln.d_new) HIP_IGNORE(hipFree(ln.d_new));
+        if (ln.s) HIP_IGNORE(hipStreamDestroy(ln.s));
+    }
     if (sv->s_lm) HIP_IGNORE(hipStreamDestroy(sv->s_lm));
 }
 
@@ -234,9 +253,10 @@ void retire(cpf_ctx *ctx, Server *sv, const std::vector<Request *> &fin, cpf_sta
 }
 
 // Admit queued requests into free slots while their arenas fit the budget,
-// upload them on s_up and launch their search there.  Returns the number
-// admitted; requests that fail to upload are retired with their status.
-int admit(cpf_ctx *ctx, Server *sv, int free_slots) {
+// upload them on a free search lane's stream and launch their search there.
+// Returns the number admitted; requests that fail to upload are retired with
+// their status.
+int admit(cpf_ctx *ctx, Server *sv, SearchLane &ln, int free_slots) {
     std::vector<Request *> batch;
     int maxK = 0, maxT = 0, dofs = 0;
     bool any_coll = false;
@@ -249,7 +269,7 @@ int admit(cpf_ctx *ctx, Server *sv, int free_slots) {
             ctx->pending.pop_front();
         }
         r->t_admit = now_ns();
-        cpf_status st = plan_create(ctx, r->robot, &r->prob, &r->opts, r->opts.iters, sv->s_up, &r->plan);
+        cpf_status st = plan_create(ctx, r->robot, &r->prob, &r->opts, r->opts.iters, ln.s, &r->plan);
         if (st == CPF_E_NOMEM) {   // wait for arenas to come back
             std::lock_guard<std::mutex> lk(ctx->mu);
             ctx->pending.push_front(r);
@@ -270,10 +290,10 @@ int admit(cpf_ctx *ctx, Server *sv, int free_slots) {
         ls.lambda = r->opts.lambda0;
         ls.nu = 2.0;
         ls.iters_target = r->opts.iters;
-        HIP_IGNORE(hipMemcpyAsync(sv->d_states + slot, &ls, sizeof(LMState), hipMemcpyHostToDevice, sv->s_up));
+        HIP_IGNORE(hipMemcpyAsync(sv->d_states + slot, &ls, sizeof(LMState), hipMemcpyHostToDevice, ln.s));
         DevPlan d = r->plan->desc;
         set_dev_ptr(d.st, sv->d_states + slot);
-        sv->h_new[batch.size()] = d;
+        ln.h_new[batch.size()] = d;
         batch.push_back(r);
         maxK = std::max(maxK, r->K);
         maxT = std::max(maxT, r->T);
@@ -282,27 +302,27 @@ int admit(cpf_ctx *ctx, Server *sv, int free_slots) {
         --free_slots;
     }
     if (batch.empty()) return 0;
-    hipError_t e = hipMemcpyAsync(sv->d_new, sv->h_new.data(), sizeof(DevPlan) * batch.size(),
-                                  hipMemcpyHostToDevice, sv->s_up);
+    hipError_t e = hipMemcpyAsync(ln.d_new, ln.h_new.data(), sizeof(DevPlan) * batch.size(),
+                                  hipMemcpyHostToDevice, ln.s);
     if (e == hipSuccess)
-        e = search_launch(ctx, sv->d_new, (int)batch.size(), maxK, maxT, false, any_coll, dofs, sv->s_up);
-    if (e == hipSuccess) e = hipEventRecord(sv->searched, sv->s_up);
+        e = search_launch(ctx, ln.d_new, (int)batch.size(), maxK, maxT, false, any_coll, dofs, ln.s);
+    if (e == hipSuccess) e = hipEventRecord(ln.searched, ln.s);
     if (e != hipSuccess) {
-        HIP_IGNORE(hipStreamSynchronize(sv->s_up));
+        HIP_IGNORE(hipStreamSynchronize(ln.s));
         const cpf_status dev = fail(CPF_E_DEVICE, "search launch: %s", hipGetErrorString(e));
         for (Request *r : batch) r->status = dev;
         retire(ctx, sv, batch, dev);
         return 0;
     }
-    sv->searching = batch;
+    ln.searching = batch;
     return (int)batch.size();
 }
 
 // A searched batch joins the work list (descriptors written on s_lm, so the
 // next tick sees them).
-void activate(cpf_ctx *ctx, Server *sv) {
+void activate(cpf_ctx *ctx, Server *sv, SearchLane &ln) {
     const int64_t ts = now_ns();
-    for (Request *r : sv->searching) {
+    for (Request *r : ln.searching) {
         DevPlan d = r->plan->desc;
         set_dev_ptr(d.st, sv->d_states + r->slot);
         sv->h_work[r->slot] = d;
@@ -311,7 +331,7 @@ void activate(cpf_ctx *ctx, Server *sv) {
         r->t_search = ts;
         release_stage(ctx, r);   // the inputs are on the device now
     }
-    sv->searching.clear();
+    ln.searching.clear();
 }
 
 void server_main(cpf_ctx *ctx) {
@@ -319,7 +339,9 @@ void server_main(cpf_ctx *ctx) {
     const cpf_status init = server_init(ctx, sv.get());
     std::vector<Request *> active;   // in the work list
     while (true) {
-        const bool busy = !active.empty() || !sv->searching.empty();
+        bool searching = false;
+        for (const SearchLane &ln : sv->lane) searching = searching || !ln.searching.empty();
+        const bool busy = !active.empty() || searching;
         {
             std::unique_lock<std::mutex> lk(ctx->mu);
             if (!busy)
@@ -339,26 +361,37 @@ void server_main(cpf_ctx *ctx) {
             }
             continue;
         }
-        // 1. admit and search a new batch when none is in flight
-        if (sv->searching.empty()) {
+        // 1. admit and search a new batch on a free lane
+        for (SearchLane &ln : sv->lane) {
+            if (!ln.searching.empty()) continue;
             int used = 0;
             for (Request *r : sv->slot_req) used += r != nullptr;
-            admit(ctx, sv.get(), sv->cap - used);
+            admit(ctx, sv.get(), ln, sv->cap - used);
+            break;
         }
-        // 2. a finished search joins the work list before the next tick
-        if (!sv->searching.empty()) {
-            const hipError_t q = active.empty() ? hipEventSynchronize(sv->searched) : hipEventQuery(sv->searched);
+        // 2. finished searches join the work list before the next tick
+        bool pending_search = false;
+        for (SearchLane &ln : sv->lane) {
+            if (ln.searching.empty()) continue;
+            const hipError_t q = hipEventQuery(ln.searched);
             if (q == hipSuccess) {
-                for (Request *r : sv->searching) active.push_back(r);
-                activate(ctx, sv.get());
-            } else if (q != hipErrorNotReady) {
+                for (Request *r : ln.searching) active.push_back(r);
+                activate(ctx, sv.get(), ln);
+            } else if (q == hipErrorNotReady) {
+                pending_search = true;
+            } else {
                 const cpf_status dev = fail(CPF_E_DEVICE, "search: %s", hipGetErrorString(q));
-                std::vector<Request *> b = sv->searching;
-                sv->searching.clear();
+                std::vector<Request *> b = ln.searching;
+                ln.searching.clear();
                 retire(ctx, sv.get(), b, dev);
             }
         }
-        if (active.empty()) continue;
+        if (active.empty()) {
+            // nothing to tick yet: poll the searches (and admit new requests
+            // to a free lane meanwhile)
+            if (pending_search) std::this_thread::sleep_for(std::chrono::microseconds(50));
+            continue;
+        }
         // 3. one LM tick over every slot, then all slot states in one copy
         int kinds = 0;
         for (Request *r : active)
