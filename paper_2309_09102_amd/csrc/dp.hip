@@ -471,7 +471,6 @@ __global__ __launch_bounds__(BS) void dp_kernel(const DevPlan *__restrict__ plan
     const int nwave = (int)(blockDim.x >> 6);
     const int k = tid;
     const bool owner = k < K;
-    const int meff = K < TOPM ? K : TOPM;
     const CPF_GLOBAL float *__restrict__ cand = P.cand;
     CPF_GLOBAL uint16_t *__restrict__ bp = P.bp;
 
@@ -487,7 +486,7 @@ __global__ __launch_bounds__(BS) void dp_kernel(const DevPlan *__restrict__ plan
 #pragma unroll
         for (int w = 1; w < BS / 64; ++w) {
             const double x = wmin[buf][w];
-            r = w < nwave ? fmin(r, x) : r;
+            r = (w < nwave && x < r) ? x : r;   // values are never NaN
         }
         return r;
     };
@@ -569,19 +568,17 @@ __global__ __launch_bounds__(BS) void dp_kernel(const DevPlan *__restrict__ plan
         double b[TOPM];
 #pragma unroll
         for (int m = 0; m < TOPM; ++m) b[m] = Bb[prv][list_index(L, m)];
+        // entries past K (K < TOPM) carry c = +inf and are never taken
         double bv = __builtin_inf();
         int bk = -1;
 #pragma unroll
         for (int m = 0; m < TOPM; ++m) {
             const double v = fmax(b[m], L.c[m]);
-            const bool take = (m < meff) && (v < bv);
+            const bool take = v < bv;
             bv = take ? v : bv;
             bk = take ? list_index(L, m) : bk;
         }
-        double cM = L.c[0];
-#pragma unroll
-        for (int m = 1; m < TOPM; ++m) cM = m < meff ? L.c[m] : cM;
-        const bool exact = (meff == K) || (fmax(beta, cM) >= bv);
+        const bool exact = (K <= TOPM) || (fmax(beta, L.c[TOPM - 1]) >= bv);
         const unsigned long long need = __ballot(owner && !exact);
         if (lane == 0) {
             fmask[cur][wave] = need;
