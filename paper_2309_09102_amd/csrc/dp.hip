@@ -550,6 +550,7 @@ __global__ __launch_bounds__(BS) void dp_kernel(const DevPlan *__restrict__ plan
     // Diagnostic build only: shader-clock totals of the stage loop, thread 0
     // of plan 0: list evaluation, publication (its barrier), full scans.
     unsigned long long ph_gather = 0, ph_publish = 0, ph_scan = 0, n_scan = 0, ph_t = clock64();
+    unsigned long long ph_read = 0, ph_eval = 0;
 #define DP_MARK(acc)                                   \
     do {                                               \
         if (tid == 0 && blockIdx.x == 0) {             \
@@ -568,23 +569,48 @@ __global__ __launch_bounds__(BS) void dp_kernel(const DevPlan *__restrict__ plan
         double b[TOPM];
 #pragma unroll
         for (int m = 0; m < TOPM; ++m) b[m] = Bb[prv][list_index(L, m)];
-        // entries past K (K < TOPM) carry c = +inf and are never taken
-        double bv = __builtin_inf();
-        int bk = -1;
+#ifdef CPF_PHASE_CYCLES
+        {   // diagnostic build: wait for the gathered values here
+            double sb = b[0];
+#pragma unroll
+            for (int m = 1; m < TOPM; ++m) sb += b[m];
+            if (sb == -1.0) bp[0] = 0;
+        }
+#endif
+        DP_MARK(ph_read);
+        // The first entry of least value, by a pairwise tree (a right half
+        // replaces its left half only when strictly smaller, so ties keep
+        // the earlier entry, as a scan in list order would).  Entries past K
+        // (K < TOPM) carry c = +inf and never win; the first entry's value is
+        // finite, so bk is always a list index.
+        double tv[TOPM];
+        int tk[TOPM];
 #pragma unroll
         for (int m = 0; m < TOPM; ++m) {
-            const double v = fmax(b[m], L.c[m]);
-            const bool take = v < bv;
-            bv = take ? v : bv;
-            bk = take ? list_index(L, m) : bk;
+            tv[m] = fmax(b[m], L.c[m]);
+            tk[m] = list_index(L, m);
         }
+#pragma unroll
+        for (int w = 1; w < TOPM; w *= 2)
+#pragma unroll
+            for (int m = 0; m < TOPM; m += 2 * w) {
+                const bool right = tv[m + w] < tv[m];
+                tv[m] = right ? tv[m + w] : tv[m];
+                tk[m] = right ? tk[m + w] : tk[m];
+            }
+        const double bv = tv[0];
+        const int bk = tk[0];
         const bool exact = (K <= TOPM) || (fmax(beta, L.c[TOPM - 1]) >= bv);
+#ifdef CPF_PHASE_CYCLES
+        if (bv == -1.0) bp[0] = 0;   // diagnostic build: the evaluation is complete here
+#endif
+        DP_MARK(ph_eval);
         const unsigned long long need = __ballot(owner && !exact);
         if (lane == 0) {
             fmask[cur][wave] = need;
             if (need) ftag[cur] = t;
         }
-        if (owner && exact) bp[(size_t)t * K + k] = (uint16_t)(bk >= 0 ? bk : 0);
+        if (owner && exact) bp[(size_t)t * K + k] = (uint16_t)bk;
         load_list(P, min(t + AHEAD, T - 1), kc, L);
         DP_MARK(ph_gather);
         beta = publish(cur, bv);   // its barrier also publishes fmask[cur] and ftag[cur]
@@ -681,8 +707,8 @@ __global__ __launch_bounds__(BS) void dp_kernel(const DevPlan *__restrict__ plan
     }
 #ifdef CPF_PHASE_CYCLES
     if (tid == 0 && blockIdx.x == 0)
-        printf("dp stage cycles T=%d K=%d: lists %llu publish %llu scans %llu (stages with scans %llu)\n", T, K,
-               ph_gather, ph_publish, ph_scan, n_scan);
+        printf("dp stage cycles T=%d K=%d: read %llu eval %llu lists %llu publish %llu scans %llu (stages with scans "
+               "%llu)\n", T, K, ph_read, ph_eval, ph_gather, ph_publish, ph_scan, n_scan);
 #endif
 #undef DP_MARK
 }
