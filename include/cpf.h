@@ -414,7 +414,11 @@ cpf_status cpf_ctx_config(cpf_ctx *ctx, int32_t slots, int32_t iters_per_tick, i
  * runs their searches, and advances every admitted request by LM iterations
  * in shared launches until it reaches opts->iters, which must be >= 1
  * (CPF_E_ARG otherwise).  A request larger than the whole budget gives
- * CPF_E_NOMEM. */
+ * CPF_E_NOMEM.  The server keeps three streams busy at once (LM ticks and
+ * two search lanes); HIP maps a process's streams onto a pool of hardware
+ * queues (GPU_MAX_HW_QUEUES, 4 unless set before HIP starts), where streams
+ * sharing a queue serialise, so a process that holds other streams should
+ * start with a pool of 8 or more. */
 cpf_status cpf_submit(cpf_ctx *ctx, const cpf_robot *robot, const cpf_problem *prob,
                       const cpf_opts *opts, uint64_t *ticket);
 
