@@ -541,11 +541,7 @@ __global__ __launch_bounds__(BS) void dp_kernel(const DevPlan *__restrict__ plan
         return publish(cur, owner ? Bb[cur][k] : 0.0);
     };
 
-    // One stage: the best of the list in `L`, the exactness check and, when
-    // it fails anywhere, the cooperative full scans; `L` is refilled with the
-    // list AHEAD stages on (clamped to a valid node, so every lane loads and
-    // no branch separates the loads from their use).
-    const int kc = owner ? k : K - 1;
+    const int kc = owner ? k : K - 1;   // the node whose lists a lane loads
 #ifdef CPF_PHASE_CYCLES
     // Diagnostic build only: shader-clock totals of the stage loop, thread 0
     // of plan 0: list evaluation, publication (its barrier), full scans.
@@ -564,42 +560,67 @@ __global__ __launch_bounds__(BS) void dp_kernel(const DevPlan *__restrict__ plan
     do {             \
     } while (0)
 #endif
-    auto stage = [&](int t, StageList &L) {
-        const int cur = t & 1, prv = cur ^ 1;
-        double b[TOPM];
+    // The first entry of least value among list entries m0 .. m0 + TOPM/2 - 1,
+    // by a pairwise tree: a right half replaces its left half only when
+    // strictly smaller, so ties keep the earlier entry, as a scan in list
+    // order would.  Entries past K (K < TOPM) carry c = +inf and never win.
+    auto half_best = [&](const StageList &L, int prv, int m0, double &bv, int &bk) {
+        constexpr int H = TOPM / 2;
+        double tv[H];
+        int tk[H];
 #pragma unroll
-        for (int m = 0; m < TOPM; ++m) b[m] = Bb[prv][list_index(L, m)];
+        for (int m = 0; m < H; ++m) {
+            tk[m] = list_index(L, m0 + m);
+            tv[m] = Bb[prv][tk[m]];
+        }
 #ifdef CPF_PHASE_CYCLES
         {   // diagnostic build: wait for the gathered values here
-            double sb = b[0];
+            double sb = tv[0];
 #pragma unroll
-            for (int m = 1; m < TOPM; ++m) sb += b[m];
+            for (int m = 1; m < H; ++m) sb += tv[m];
             if (sb == -1.0) bp[0] = 0;
         }
-#endif
         DP_MARK(ph_read);
-        // The first entry of least value, by a pairwise tree (a right half
-        // replaces its left half only when strictly smaller, so ties keep
-        // the earlier entry, as a scan in list order would).  Entries past K
-        // (K < TOPM) carry c = +inf and never win; the first entry's value is
-        // finite, so bk is always a list index.
-        double tv[TOPM];
-        int tk[TOPM];
+#endif
 #pragma unroll
-        for (int m = 0; m < TOPM; ++m) {
-            tv[m] = fmax(b[m], L.c[m]);
-            tk[m] = list_index(L, m);
-        }
+        for (int m = 0; m < H; ++m) tv[m] = fmax(tv[m], L.c[m0 + m]);
 #pragma unroll
-        for (int w = 1; w < TOPM; w *= 2)
+        for (int w = 1; w < H; w *= 2)
 #pragma unroll
-            for (int m = 0; m < TOPM; m += 2 * w) {
+            for (int m = 0; m < H; m += 2 * w) {
                 const bool right = tv[m + w] < tv[m];
                 tv[m] = right ? tv[m + w] : tv[m];
                 tk[m] = right ? tk[m + w] : tk[m];
             }
-        const double bv = tv[0];
-        const int bk = tk[0];
+        bv = tv[0];
+        bk = tk[0];
+    };
+
+    // One stage: the best of the list in `L`, the exactness check and, when
+    // it fails anywhere, the cooperative full scans; `L` is refilled with the
+    // list AHEAD stages on (clamped to a valid node, so every lane loads and
+    // no branch separates the loads from their use).
+    //
+    // The list is evaluated in two halves.  Every entry m of the second half
+    // has value max(B, c_m) >= c_m >= c_{TOPM/2}, and a later entry of equal
+    // value loses the tie, so once the first half's best is at most
+    // c_{TOPM/2} the second half cannot change the result; only when some
+    // lane of the wavefront needs it does the wavefront gather the second
+    // half (about one wavefront-stage in a hundred on the serving stream's
+    // inputs).
+    auto stage = [&](int t, StageList &L) {
+        const int cur = t & 1, prv = cur ^ 1;
+        double bv;
+        int bk;
+        half_best(L, prv, 0, bv, bk);
+        if (__any(!(bv <= L.c[TOPM / 2]))) {   // uniform: the wavefront's lanes together
+            double bv2;
+            int bk2;
+            half_best(L, prv, TOPM / 2, bv2, bk2);
+            const bool right = bv2 < bv;
+            bv = right ? bv2 : bv;
+            bk = right ? bk2 : bk;
+        }
         const bool exact = (K <= TOPM) || (fmax(beta, L.c[TOPM - 1]) >= bv);
 #ifdef CPF_PHASE_CYCLES
         if (bv == -1.0) bp[0] = 0;   // diagnostic build: the evaluation is complete here
