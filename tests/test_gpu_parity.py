@@ -128,6 +128,39 @@ def test_dp_search_list_fallback(ctx):
     assert best < 50.0 and not np.any(path < 20)
 
 
+def test_dp_search_best_in_second_half_of_lists(ctx):
+    """Eight candidates sit on the ground truth and cost 5 at even waypoints;
+    eight more are offset by 0.05 rad on joint 0 and cost nothing.  A node
+    of the first group at an odd waypoint then has the costly candidates as
+    its 8 nearest predecessors and finds its best among entries 8-15 of its
+    list, so the stage pass must evaluate the second half (checked here on
+    the oracle's tables: more than a thousand nodes need it)."""
+    p = H.small_problem(seed=13, T=200, K=64, sigma=0.3, frac=0.0)
+    cand = p.cand.copy()
+    cand[:8] = p.q_star[None]
+    cand[8:16] = p.q_star[None]
+    cand[8:16, :, 0] += 0.05
+    cand = cand.astype(np.float32).astype(np.float64)
+    extra = np.zeros((p.T, p.K))
+    extra[0::2, :8] = 5.0
+    path_ref, best_ref, B, _ = oracle.dp(cand, p.robot, extra=extra, want_tables=True)
+    lo, hi = p.robot.q_lo, p.robot.q_hi
+    m = oracle.oracle.LIMIT_MARGIN
+    need = 0
+    for t in range(1, p.T):
+        e = np.max(np.abs(cand[:, t, None, :] - cand[None, :, t - 1, :]), axis=2)
+        q = cand[:, t, :]
+        pen = np.where(np.any((q <= lo + m) | (q >= hi - m), axis=1), oracle.oracle.LIMIT_PENALTY, 0.0) + extra[t]
+        order = np.argsort(e, axis=1, kind="stable")[:, :16]
+        c = np.take_along_axis(e, order, axis=1) + pen[:, None]
+        v = np.maximum(B[t - 1][order], c)
+        need += int(np.sum(v[:, :8].min(axis=1) > c[:, 8]))
+    assert need > 1000
+    with ctx.plan(p.robot, p.targets, cand, node_pen=extra) as plan:
+        path, best, _ = plan.dp_search()
+    assert np.array_equal(path, path_ref) and best == best_ref
+
+
 def test_dp_search_config2_full_size(ctx):
     p = H.with_targets(synth.config2())
     path_ref, best_ref, _, _ = oracle.dp(p.cand, p.robot)
