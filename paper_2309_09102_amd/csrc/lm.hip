@@ -41,34 +41,41 @@ constexpr int LM_BS = 512;
 // 2000.
 constexpr int LM_ITER_FIXED = 330;
 
-// Workgroup sum and maximum of one value per thread, by a fixed tree
-// (v_t + v_{t+256}, then + v_{t+128}, ... down to + v_{t+1}), so that every
-// run adds in the same order: the three steps across wavefronts go through
-// LDS with a barrier each, the six inside wavefront 0 through lane shuffles.
-template <bool MAX>
-__device__ __forceinline__ double block_reduce(double v, double *red) {
-    static_assert(LM_BS == 512, "three steps across wavefronts, six inside one");
-    const int tid = threadIdx.x;
-    red[tid] = v;
-    __syncthreads();
+// Workgroup sums (or maxima) of N values per thread, by a fixed tree: inside
+// each wavefront by lane shuffles (offsets 32, 16, ..., 1, into lane 0),
+// then the wavefronts' partial results in wavefront order, so that every run
+// adds in the same order.  Two barriers for any N: after the partials are
+// written, and before `red` may be written again.  `red` holds at least
+// N * LM_BS / 64 doubles.
+template <int N, bool MAX>
+__device__ __forceinline__ void block_reduce_n(double v[N], double *red) {
+    constexpr int NW = LM_BS / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int s = LM_BS / 2; s >= 128; s >>= 1) {
-        if (tid < s) red[tid] = MAX ? fmax(red[tid], red[tid + s]) : red[tid] + red[tid + s];
-        __syncthreads();
-    }
-    if (tid < 64) {
-        double x = MAX ? fmax(red[tid], red[tid + 64]) : red[tid] + red[tid + 64];
+    for (int i = 0; i < N; ++i) {
+        double x = v[i];
 #pragma unroll
         for (int s = 32; s > 0; s >>= 1) {
             const double y = __shfl_down(x, s, 64);
             x = MAX ? fmax(x, y) : x + y;
         }
-        if (tid == 0) red[0] = x;
+        if (lane == 0) red[wave * N + i] = x;
     }
     __syncthreads();
-    const double r = red[0];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        double r = red[i];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) r = MAX ? fmax(r, red[w * N + i]) : r + red[w * N + i];
+        v[i] = r;
+    }
     __syncthreads();
-    return r;
+}
+template <bool MAX>
+__device__ __forceinline__ double block_reduce(double v, double *red) {
+    double a[1] = {v};
+    block_reduce_n<1, MAX>(a, red);
+    return a[0];
 }
 __device__ __forceinline__ double block_sum(double v, double *red) { return block_reduce<false>(v, red); }
 __device__ __forceinline__ double block_max(double v, double *red) { return block_reduce<true>(v, red); }
@@ -156,7 +163,8 @@ __device__ __forceinline__ void coll_residuals(const DevPlan &P, const RobotT<S>
 // to R ([RROWS][T]; the collision rows only when wc != 0).
 template <bool PR>
 __device__ __forceinline__ double plan_cost(const DevPlan &P, const CPF_GLOBAL double *X, int T, double *red,
-                                            double wp, double ws, double wc, CPF_GLOBAL double *R) {
+                                            double wp, double ws, double wc, CPF_GLOBAL double *R,
+                                            double *extra_sum = nullptr, double extra = 0.0) {
     const RobotT<double> rb = load_robot<double, PR>(P);
     double ps = 0.0, ss = 0.0, cs = 0.0;
     for (int t = threadIdx.x; t < T; t += LM_BS) {
@@ -186,10 +194,13 @@ __device__ __forceinline__ double plan_cost(const DevPlan &P, const CPF_GLOBAL d
             }
         }
     }
-    const double pose_sum = block_sum(ps, red);
-    const double diff_sum = block_sum(ss, red);
-    const double coll_sum = wc != 0.0 ? block_sum(cs, red) : 0.0;
-    return 0.5 * wp * pose_sum + 0.5 * ws * diff_sum + 0.5 * wc * coll_sum;
+    // one reduction for the three terms and the caller's extra per-thread
+    // value (the trial's predicted reduction)
+    double sums[4] = {ps, ss, cs, extra};
+    block_reduce_n<4, false>(sums, red);
+    if (extra_sum) *extra_sum = sums[3];
+    const double coll_sum = wc != 0.0 ? sums[2] : 0.0;
+    return 0.5 * wp * sums[0] + 0.5 * ws * sums[1] + 0.5 * wc * coll_sum;
 }
 
 // Linearise at xi: A_t = w_p J^T J (whole blocks), g_t; returns max |g|.
@@ -1285,11 +1296,13 @@ __device__ int schedule_check(const DevPlan &P, LMState *st, int T, double *red)
                 len += d;
             }
     }
-    ep = block_max(ep, red);
-    er = block_max(er, red);
-    mj = block_max(mj, red);
+    double mx[4] = {ep, er, mj, pen};
+    block_reduce_n<4, true>(mx, red);
+    ep = mx[0];
+    er = mx[1];
+    mj = mx[2];
+    if (COLL) pen = mx[3];
     len = block_sum(len, red);
-    if (COLL) pen = block_max(pen, red);
     const bool pose_ok = ep <= P.vtol[0] && er <= P.vtol[1];
     if constexpr (!PR) {
         if (pose_ok && mj <= P.vtol[2] && pen <= 0.0) {
@@ -1505,8 +1518,9 @@ __global__ __launch_bounds__(LM_BS) void lm_kernel(const DevPlan *__restrict__ p
                 pr += dl * (lam * dl - P.g[e]);
             }
         __syncthreads();
-        const double cn = plan_cost<PR>(P, P.xt, T, red, wp, ws, wc, keep_r ? P.rt : nullptr);
-        const double pred = 0.5 * block_sum(pr, red);
+        double pr_sum;
+        const double cn = plan_cost<PR>(P, P.xt, T, red, wp, ws, wc, keep_r ? P.rt : nullptr, &pr_sum, pr);
+        const double pred = 0.5 * pr_sum;
         PHASE_MARK(5);
         if (tid == 0) {
             const double c = sh_cost;
@@ -1645,12 +1659,14 @@ __global__ __launch_bounds__(LM_BS) void eval_kernel(const DevPlan *__restrict__
             ne = fmax(ne, -dm[1]);
         }
     }
-    ep = block_max(ep, red);
-    er = block_max(er, red);
-    mj = block_max(mj, red);
+    double mx[5] = {ep, er, mj, ns, ne};
+    block_reduce_n<5, true>(mx, red);
+    ep = mx[0];
+    er = mx[1];
+    mj = mx[2];
     if (COLL) {
-        ns = block_max(ns, red);
-        ne = block_max(ne, red);
+        ns = mx[3];
+        ne = mx[4];
     }
     if (threadIdx.x == 0) {
         P.report[0] = ep;
