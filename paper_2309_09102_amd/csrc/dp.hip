@@ -237,10 +237,10 @@ __global__ __launch_bounds__(TOPM_BS) void dp_topm_kernel(const DevPlan *__restr
     uint16_t *buf = (uint16_t *)(qprev + (size_t)NJ * Kr) + threadIdx.x;   // [LIST_BUF][TOPM_BS]
     const CPF_GLOBAL float *__restrict__ cand = P.cand;
     if (t > 0) {
-        for (int x = threadIdx.x; x < NJ * Kr; x += TOPM_BS) {
-            const int j = x / Kr, kp = x - j * Kr;
-            qprev[qidx(j, kp)] = kp < K ? cand[((size_t)(t - 1) * NJ + j) * K + kp] : __builtin_inff();
-        }
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+            for (int kp = threadIdx.x; kp < Kr; kp += TOPM_BS)
+                qprev[qidx(j, kp)] = kp < K ? cand[((size_t)(t - 1) * NJ + j) * K + kp] : __builtin_inff();
     }
     __syncthreads();
     const int k = kb * TOPM_BS + threadIdx.x;
