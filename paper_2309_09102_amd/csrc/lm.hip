@@ -900,36 +900,46 @@ __device__ __forceinline__ int cr_tail_level(int T) {
     } while (0)
 #endif
 
+// The entry level of the tail: the blocks of level lw formed from level
+// lw-1 (column c by lane c of a group) into the tail's LDS arrays, by all
+// the workgroup's groups at once (a level of at most CR_TAIL_N blocks is one
+// round of them); the caller's barrier then hands the arrays to wavefront 0.
+__device__ void cr_tail_entry(const DevPlan &P, int T, double lam, double ws, bool factor,
+                              const CPF_GLOBAL double *rhs, double sgn, CPF_GLOBAL double *base, int lw, int gid,
+                              int c, double *wk) {
+    double *D = wk, *E = D + CR_TAIL_N * NBLK, *R = E + CR_TAIL_N * NBLK;
+    const CRLevel Lp = cr_level(base, T, lw - 1), L = cr_level(base, T, lw);
+    if (gid < 0) return;
+    for (int j = gid; j < L.n; j += CR_GROUPS) {
+        double d[NJ], rc;
+        cr_form_col(P, T, lam, ws, Lp, lw, j, c, factor, rhs, sgn, d, rc);
+        R[j * NJ + c] = rc;
+        if (factor) {
+#pragma unroll
+            for (int a = 0; a < NJ; ++a) D[j * NBLK + a * NJ + c] = d[a];
+            if (j >= 1) {   // E_j, column c
+                double e[NJ], f[NJ];
+                cr_coupling_cols(L, Lp, lw, j, false, c, e, f);
+#pragma unroll
+                for (int k = 0; k < NJ; ++k) E[j * NBLK + k * NJ + c] = e[k];
+            }
+        }
+    }
+}
+
 // Wavefront 0 only (lanes in groups of NJ; with 7 joints lane 63 idles).  Solves
 // levels lw..top of the system whose levels below lw are in `base`,
-// factoring them first (factor) or reusing the factored blocks in fs.
+// factoring them first (factor) or reusing the factored blocks in fs; the
+// entry level's blocks are in wk already (cr_tail_entry).
 __device__ void cr_tail(const DevPlan &P, int T, double lam, double ws, bool factor, const CPF_GLOBAL double *rhs,
                         double sgn, CPF_GLOBAL double *base, int lw, double *fs, double *wk, bool &ok) {
     const int lane = threadIdx.x & 63;
     const int g = lane < CR_GL ? lane / NJ : CR_GPW;   // an idle lane: a group that never has a block
     const int c = lane < CR_GL ? lane % NJ : 0;
     double *D = wk, *E = D + CR_TAIL_N * NBLK, *R = E + CR_TAIL_N * NBLK, *X = R + CR_TAIL_N * NJ;
-    const CRLevel Lp = cr_level(base, T, lw - 1), L = cr_level(base, T, lw);
+    const CRLevel L = cr_level(base, T, lw);
     const int n = L.n;
 
-    // Entry: the blocks of level lw formed from level lw-1 (column c by lane c).
-    if (g < CR_GPW) {
-        for (int j = g; j < n; j += CR_GPW) {
-            double d[NJ], rc;
-            cr_form_col(P, T, lam, ws, Lp, lw, j, c, factor, rhs, sgn, d, rc);
-            R[j * NJ + c] = rc;
-            if (factor) {
-#pragma unroll
-                for (int a = 0; a < NJ; ++a) D[j * NBLK + a * NJ + c] = d[a];
-                if (j >= 1) {   // E_j, column c
-                    double e[NJ], f[NJ];
-                    cr_coupling_cols(L, Lp, lw, j, false, c, e, f);
-#pragma unroll
-                    for (int k = 0; k < NJ; ++k) E[j * NBLK + k * NJ + c] = e[k];
-                }
-            }
-        }
-    }
     group_sync();
     CR_TAIL_MARK(8);
 
@@ -1160,6 +1170,8 @@ __device__ __forceinline__ bool cr_solve(const DevPlan &P, int T, double lam, do
         CR_ROUND_MARK(factor ? 0 : 1, lev);
     }
     if (top >= 1) {
+        cr_tail_entry(P, T, lam, ws, factor, rhs, sgn, base, lw, gid, gc, twk);
+        __syncthreads();
         if (tid < 64) cr_tail(P, T, lam, ws, factor, rhs, sgn, base, lw, tfs, twk, ok);
         __syncthreads();
         CR_ROUND_MARK(factor ? 0 : 1, 31);
