@@ -31,9 +31,10 @@
 //     K predecessors, done by a whole wavefront (the nodes needing one are
 //     shared out among the wavefronts after the stage's barrier).  Either
 //     way the answer equals the exhaustive minimum, bit for bit.  A stage
-//     costs one LDS gather of TOPM values per lane and one workgroup barrier
-//     (two more when a full scan is needed); the lists of later stages are
-//     loaded ahead.
+//     costs an LDS gather of TOPM / 2 values per lane (the list's second
+//     half only where the first half cannot settle the node) and one
+//     workgroup barrier (two more when a full scan is needed); the lists of
+//     later stages are loaded ahead.
 #include <float.h>
 
 #include "coll_device.h"
