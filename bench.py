@@ -44,7 +44,14 @@ sys.path.insert(0, ROOT)
 # on one queue (measured: open-loop p50 16.1 ms and p99 36 ms against 12.4
 # and 24 ms with eight).  The pool size is read when HIP starts, so it is
 # raised here, before anything imports torch.
-if int(os.environ.get("GPU_MAX_HW_QUEUES", "0") or 0) < 8:
+def _hw_queues() -> int:
+    try:
+        return int(os.environ.get("GPU_MAX_HW_QUEUES", "0"))
+    except ValueError:
+        return 0
+
+
+if _hw_queues() < 8:
     os.environ["GPU_MAX_HW_QUEUES"] = "8"
 
 PEAK_ALU_TFLOPS = 78.6      # 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz, FP32 unpacked and FP64
